@@ -1,0 +1,351 @@
+"""FP64 CPU oracle for the spectral-element PCG solve (ctypes binding).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the
+cpu_baseline leg of the benchmark may import this package; the product path
+never does.  The C source (``oracle.c``) shares no code with the HIP library.
+
+Every function here only marshals numpy arrays into the C library; the
+arithmetic lives in ``oracle.c``, each step citing the passage it follows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+CONVERGED, MAXITER, STAGNATED, BREAKDOWN = 1, 2, 3, 4
+PC_IDENTITY, PC_JACOBI, PC_NN = 0, 1, 2
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc into liboracle.so (plain FP64, no contraction)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
+               "-fPIC", "-shared", "-Wall", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build()
+    lib = C.CDLL(_LIB)
+    dp = C.POINTER(C.c_double)
+    vp = C.c_void_p
+    lib.orc_gll.argtypes = [C.c_int, dp, dp]
+    lib.orc_deriv.argtypes = [C.c_int, dp, dp]
+    lib.orc_mesh_create.argtypes = [C.c_int, C.c_int, vp, vp, vp, vp, C.c_double,
+                                    C.POINTER(vp)]
+    lib.orc_mesh_destroy.argtypes = [vp]
+    lib.orc_mesh_nloc.argtypes = [vp]
+    lib.orc_mesh_nloc.restype = C.c_int64
+    lib.orc_mesh_ngroups.argtypes = [vp]
+    lib.orc_mesh_ngroups.restype = C.c_int64
+    lib.orc_mesh_mindet.argtypes = [vp]
+    lib.orc_mesh_mindet.restype = C.c_double
+    lib.orc_mesh_get.argtypes = [vp, C.c_int, vp]
+    for f in ("orc_ax_local", "orc_apply", "orc_rhs"):
+        getattr(lib, f).argtypes = [vp, vp, vp]
+    for f in ("orc_gs", "orc_mask", "orc_diag"):
+        getattr(lib, f).argtypes = [vp, vp]
+    lib.orc_dot.argtypes = [vp, vp, vp]
+    lib.orc_dot.restype = C.c_double
+    lib.orc_pcg.argtypes = [vp, C.c_int, vp, vp, vp, C.c_int, C.c_double, C.c_int, vp,
+                            vp]
+    lib.orc_fcg.argtypes = [vp, C.c_int, vp, vp, vp, C.c_double, C.c_int, vp, vp]
+    lib.orc_ir.argtypes = [vp, C.c_int, vp, vp, C.c_double, C.c_double, C.c_int, C.c_int,
+                           vp, vp]
+    lib.orc_nn_create.argtypes = [C.c_int, C.c_int, vp, vp, C.POINTER(vp)]
+    lib.orc_nn_destroy.argtypes = [vp]
+    lib.orc_nn_set.argtypes = [vp, vp, vp]
+    lib.orc_nn_local.argtypes = [vp, vp, vp, vp, vp]
+    lib.orc_nn_apply.argtypes = [vp, vp, vp, vp]
+    lib.orc_nn_loss_grad.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp, vp]
+    lib.orc_adam.argtypes = [C.c_int, vp, vp, vp, vp, C.c_int, C.c_double, C.c_double,
+                             C.c_double, C.c_double]
+    _lib = lib
+    return lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class _Stats(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("reason", C.c_int), ("outer", C.c_int),
+                ("fallback", C.c_int), ("rel_res_recursive", C.c_double),
+                ("rel_res_true", C.c_double)]
+
+
+@dataclass
+class SolveStats:
+    iterations: int
+    reason: int
+    outer: int
+    fallback: int
+    rel_res_recursive: float
+    rel_res_true: float
+
+
+def gll(N: int):
+    """GLL nodes and weights on [-1, 1] (ascending)."""
+    lib = _load()
+    xi = np.zeros(N + 1)
+    w = np.zeros(N + 1)
+    rc = lib.orc_gll(N, xi.ctypes.data_as(C.POINTER(C.c_double)),
+                     w.ctypes.data_as(C.POINTER(C.c_double)))
+    if rc != 0:
+        raise ValueError(f"orc_gll({N}) failed: {rc}")
+    return xi, w
+
+
+def deriv(N: int) -> np.ndarray:
+    """Nodal derivative matrix D[i, j] = l_j'(xi_i)."""
+    lib = _load()
+    xi, _ = gll(N)
+    D = np.zeros((N + 1, N + 1))
+    rc = lib.orc_deriv(N, xi.ctypes.data_as(C.POINTER(C.c_double)),
+                       D.ctypes.data_as(C.POINTER(C.c_double)))
+    if rc != 0:
+        raise ValueError(rc)
+    return D
+
+
+class Mesh:
+    """Oracle mesh: FP64 geometric factors, gather-scatter groups, mask, dinv."""
+
+    def __init__(self, E: int, N: int, xyz, glo, bnd, kcoef=None, helm_h: float = 0.0):
+        lib = _load()
+        self.E, self.N, self.n = int(E), int(N), int(N) + 1
+        self.nloc = self.E * self.n ** 3
+        xyz = _f64(xyz)
+        glo = np.ascontiguousarray(glo, dtype=np.int64)
+        bnd = np.ascontiguousarray(bnd, dtype=np.uint8)
+        assert xyz.size == 3 * self.nloc and glo.size == self.nloc and bnd.size == self.nloc
+        kk = None if kcoef is None else _f64(kcoef)
+        if kk is not None:
+            assert kk.size == self.nloc
+        h = C.c_void_p()
+        rc = lib.orc_mesh_create(self.E, self.N, _p(xyz), _p(glo), _p(bnd),
+                                 None if kk is None else _p(kk), float(helm_h), C.byref(h))
+        if rc != 0:
+            raise ValueError(f"orc_mesh_create failed with code {rc}")
+        self._h = h
+        self.helm_h = float(helm_h)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.orc_mesh_destroy(h)
+            self._h = None
+
+    # --- data accessors ---------------------------------------------------
+    def _get(self, what: int, size: int) -> np.ndarray:
+        out = np.zeros(size)
+        _lib.orc_mesh_get(self._h, what, _p(out))
+        return out
+
+    @property
+    def G(self):
+        return self._get(0, 6 * self.nloc).reshape(self.E, 6, self.n ** 3)
+
+    @property
+    def B(self):
+        return self._get(1, self.nloc)
+
+    @property
+    def mult(self):
+        return self._get(2, self.nloc)
+
+    @property
+    def c(self):
+        return self._get(3, self.nloc)
+
+    @property
+    def dinv(self):
+        return self._get(4, self.nloc)
+
+    @property
+    def D(self):
+        return self._get(5, self.n * self.n).reshape(self.n, self.n)
+
+    @property
+    def mask(self):
+        return self._get(6, self.nloc).astype(bool)
+
+    @property
+    def ngroups(self) -> int:
+        return int(_lib.orc_mesh_ngroups(self._h))
+
+    @property
+    def mindet(self) -> float:
+        return float(_lib.orc_mesh_mindet(self._h))
+
+    # --- operators ---------------------------------------------------------
+    def _unary(self, fn, u):
+        u = _f64(u).reshape(-1)
+        assert u.size == self.nloc
+        w = np.zeros(self.nloc)
+        fn(self._h, _p(u), _p(w))
+        return w
+
+    def ax_local(self, u):
+        return self._unary(_lib.orc_ax_local, u)
+
+    def apply(self, u):
+        return self._unary(_lib.orc_apply, u)
+
+    def rhs(self, f):
+        return self._unary(_lib.orc_rhs, f)
+
+    def gs(self, v):
+        v = _f64(v).reshape(-1).copy()
+        _lib.orc_gs(self._h, _p(v))
+        return v
+
+    def mask_apply(self, v):
+        v = _f64(v).reshape(-1).copy()
+        _lib.orc_mask(self._h, _p(v))
+        return v
+
+    def diag(self):
+        d = np.zeros(self.nloc)
+        _lib.orc_diag(self._h, _p(d))
+        return d
+
+    def dot(self, a, b) -> float:
+        a = _f64(a).reshape(-1)
+        b = _f64(b).reshape(-1)
+        return float(_lib.orc_dot(self._h, _p(a), _p(b)))
+
+    # --- solvers -----------------------------------------------------------
+    def pcg(self, b, pc=PC_JACOBI, tol=1e-10, maxit=1000, x0=None, history=False, nn=None):
+        b = _f64(b).reshape(-1)
+        x = np.zeros(self.nloc) if x0 is None else _f64(x0).reshape(-1).copy()
+        hist = np.zeros(maxit + 1) if history else None
+        st = _Stats()
+        rc = _lib.orc_pcg(self._h, pc, None if nn is None else nn._h, _p(b), _p(x),
+                          0 if x0 is None else 1, tol, maxit,
+                          None if hist is None else _p(hist), C.byref(st))
+        if rc != 0:
+            raise RuntimeError(rc)
+        s = _stats(st)
+        if history:
+            return x, s, hist[: s.iterations + 1]
+        return x, s
+
+    def fcg(self, b, nn=None, pc=None, tol=1e-10, maxit=1000, history=False):
+        b = _f64(b).reshape(-1)
+        x = np.zeros(self.nloc)
+        hist = np.zeros(maxit + 1) if history else None
+        st = _Stats()
+        if pc is None:
+            pc = PC_NN if nn is not None else PC_JACOBI
+        rc = _lib.orc_fcg(self._h, pc, None if nn is None else nn._h, _p(b), _p(x), tol,
+                          maxit, None if hist is None else _p(hist), C.byref(st))
+        if rc != 0:
+            raise RuntimeError(rc)
+        s = _stats(st)
+        if history:
+            return x, s, hist[: s.iterations + 1]
+        return x, s
+
+    def ir(self, b, tol=1e-10, tau_in=1e-4, max_outer=10, inner_maxit=10000, pc=PC_JACOBI):
+        b = _f64(b).reshape(-1)
+        x = np.zeros(self.nloc)
+        outer = np.zeros(max_outer + 1)
+        st = _Stats()
+        rc = _lib.orc_ir(self._h, pc, _p(b), _p(x), tol, tau_in, max_outer, inner_maxit,
+                         _p(outer), C.byref(st))
+        if rc != 0:
+            raise RuntimeError(rc)
+        s = _stats(st)
+        return x, s, outer[: s.outer + 1]
+
+
+def _stats(st: _Stats) -> SolveStats:
+    return SolveStats(st.iterations, st.reason, st.outer, st.fallback,
+                      st.rel_res_recursive, st.rel_res_true)
+
+
+class NN:
+    """Oracle copy of the per-element convolutional correction (FP64)."""
+
+    def __init__(self, W1, W2, cin: int = 2):
+        lib = _load()
+        W1 = _f64(W1)
+        W2 = _f64(W2)
+        self.ch = W2.size // 27
+        self.cin = cin
+        assert W1.size == self.ch * cin * 27
+        h = C.c_void_p()
+        rc = lib.orc_nn_create(cin, self.ch, _p(W1), _p(W2), C.byref(h))
+        if rc != 0:
+            raise ValueError(rc)
+        self._h = h
+        self.W1 = W1.reshape(self.ch, cin, 27).copy()
+        self.W2 = W2.reshape(self.ch, 27).copy()
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.orc_nn_destroy(h)
+            self._h = None
+
+    def set(self, W1, W2):
+        W1 = _f64(W1)
+        W2 = _f64(W2)
+        _lib.orc_nn_set(self._h, _p(W1), _p(W2))
+        self.W1 = W1.reshape(self.ch, self.cin, 27).copy()
+        self.W2 = W2.reshape(self.ch, 27).copy()
+
+    def local(self, mesh: Mesh, r):
+        r = _f64(r).reshape(-1)
+        zL = np.zeros(mesh.nloc)
+        y = np.zeros(mesh.nloc)
+        _lib.orc_nn_local(mesh._h, self._h, _p(r), _p(zL), _p(y))
+        return zL, y
+
+    def apply(self, mesh: Mesh, r):
+        r = _f64(r).reshape(-1)
+        z = np.zeros(mesh.nloc)
+        _lib.orc_nn_apply(mesh._h, self._h, _p(r), _p(z))
+        return z
+
+    def loss_grad(self, mesh: Mesh, R, Eerr):
+        R = _f64(R)
+        Eerr = _f64(Eerr)
+        ns = R.size // mesh.nloc
+        assert R.size == ns * mesh.nloc and Eerr.size == R.size
+        loss = np.zeros(1)
+        g1 = np.zeros(self.ch * self.cin * 27)
+        g2 = np.zeros(self.ch * 27)
+        rc = _lib.orc_nn_loss_grad(mesh._h, self._h, ns, _p(R), _p(Eerr), _p(loss), _p(g1),
+                                   _p(g2))
+        if rc != 0:
+            raise RuntimeError(rc)
+        return float(loss[0]), g1.reshape(self.ch, self.cin, 27), g2.reshape(self.ch, 27)
+
+
+def adam(theta, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """In-place Adam step on float64 arrays."""
+    for a in (theta, g, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    _load().orc_adam(theta.size, _p(theta), _p(g), _p(m), _p(v), t, lr, b1, b2, eps)
