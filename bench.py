@@ -1,0 +1,197 @@
+"""Benchmark: GDOF*iter/s of the spectral-element PCG solve on one MI355X.
+
+One step = one complete solve, from x = 0 to relative residual 1e-10, of
+the synthetic workload in the mixed-precision refinement mode (FP32 inner
+Jacobi-PCG with FP64 gather-scatter sums and dots, FP64 residuals in the
+refinement loop).  value = local dofs x (inner + outer iterations) per
+second over the timed steps.  Inputs are resident in HBM before timing.
+
+Beside it: the FP64 solve on the same GPU, time-to-1e-8 for both, the
+roofline of the dominant kernel (the fused operator kernel of the inner
+loop, timed with HIP events around its graph node on the solve's stream),
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="box32_N7_deformed")
+    ap.add_argument("--mode", default="mixed_ir", choices=["mixed_ir", "mixed_ir_bf16g", "fp64",
+                                                           "mixed"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-iters", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharded design is described, not built); run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2503_02134_amd import mxsem as mx
+    from paper_2503_02134_amd import workloads as W
+
+    mx.lib()
+    wl = W.WORKLOADS[args.workload]
+    modes = {"mixed_ir": mx.MODE_MIXED_IR, "mixed_ir_bf16g": mx.MODE_MIXED_IR_BF16G,
+             "fp64": mx.MODE_FP64, "mixed": mx.MODE_MIXED}
+    mode = modes[args.mode]
+    ctx = mx.Context(0)
+    t0 = time.perf_counter()
+    xi, _ = mx.mxsem_gll(wl.N)
+    bm = W.box_mesh(wl.ne, wl.N, xi, seed=wl.deform_seed)
+    kf = W.lognormal_k(bm, wl.k_seed) if wl.k_seed is not None else None
+    if wl.rhs == "manufactured":
+        f, _ = W.manufactured(bm)
+    else:
+        f = W.random_smooth_rhs(bm, wl.rhs_seed)
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    mesh = mx.Mesh(ctx, bm.E, wl.N, bm.xyz, bm.glo, bm.bnd, kcoef=kf, helm_h=wl.helm_h)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    nloc = mesh.nloc
+    log(f"workload {wl.name}: E={bm.E} N={wl.N} nloc={nloc} gen {t_gen:.1f}s setup {t_setup:.2f}s")
+    b = mesh.mass_rhs(torch.as_tensor(f, device="cuda"))
+    x = torch.zeros_like(b)
+    opts = dict(mode=mode, tol=wl.tol, max_iter=20000, graph_chunk=16)
+
+    for i in range(args.warmup):
+        x.zero_()
+        _, st = mesh.solve(b, x, **opts)
+        log(f"warmup {i}: it={st.iterations} outer={st.outer} res={st.rel_res:.2e} "
+            f"{st.ms:.1f} ms")
+    torch.cuda.synchronize()
+    iters = 0
+    ax_ms = []
+    stats = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        x.zero_()
+        _, st = mesh.solve(b, x, **opts)
+        iters += st.iterations + st.outer
+        ax_ms.append((st.ax_ms, st.ax_samples))
+        stats.append(st)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for i, st in enumerate(stats):
+        log(f"step {i}: it={st.iterations} outer={st.outer} reason={st.reason} "
+            f"res={st.rel_res:.2e} {st.ms:.1f} ms ax={st.ax_ms * 1e3:.1f} us")
+    value = nloc * iters / elapsed / 1e9
+    x_mixed = x.clone()
+
+    # dominant kernel: fused operator kernel of the inner loop
+    tot = sum(s for _, s in ax_ms)
+    ax_avg_ms = sum(a * s for a, s in ax_ms) / max(tot, 1)
+    vec_bytes = 8 if mode == mx.MODE_FP64 else 4
+    g_bytes = 6 * (8 if mode == mx.MODE_FP64 else 2 if mode == mx.MODE_MIXED_IR_BF16G else 4)
+    hb = 0 if wl.helm_h == 0 else g_bytes // 6
+    bytes_per_dof = 5 * vec_bytes + g_bytes + hb  # z, p_old in; p, w out; G (and h*B) in
+    traffic_bytes = nloc * bytes_per_dof
+    achieved = traffic_bytes / (ax_avg_ms * 1e-3) / 1e9 if ax_avg_ms > 0 else 0.0
+
+    # FP64 solve and time-to-1e-8
+    extra = {}
+    x64 = torch.zeros_like(b)
+    _, s64 = mesh.solve(b, x64, mode=mx.MODE_FP64, tol=wl.tol, max_iter=20000, graph_chunk=16)
+    extra["fp64"] = {"iterations": s64.iterations, "ms": round(s64.ms, 3),
+                     "gdof_iter_s": round(nloc * s64.iterations / (s64.ms * 1e-3) / 1e9, 3),
+                     "rel_res": s64.rel_res, "ax_us": round(s64.ax_ms * 1e3, 2)}
+    mstep = stats[-1]
+    extra["time_to_solution_ms"] = {"fp64": round(s64.ms, 3), args.mode: round(mstep.ms, 3),
+                                    "gain": round(s64.ms / mstep.ms, 3)}
+    d = (x_mixed - x64).double()
+    extra["rel_diff_vs_fp64_solution"] = float(torch.linalg.vector_norm(d)
+                                               / torch.linalg.vector_norm(x64))
+    tt = {}
+    for name, md in (("fp64", mx.MODE_FP64), (args.mode, mode)):
+        xt = torch.zeros_like(b)
+        _, st8 = mesh.solve(b, xt, mode=md, tol=1e-8, max_iter=20000, graph_chunk=16)
+        tt[name] = {"ms": round(st8.ms, 3), "iterations": st8.iterations, "outer": st8.outer,
+                    "rel_res": st8.rel_res}
+    extra["time_to_1e-8"] = tt
+    log(f"fp64: {extra['fp64']}; tt1e-8: {tt}")
+
+    out = {
+        "metric": "GDOF*iter/s (local dofs x iterations / s) of the SEM PCG solve",
+        "value": round(value, 4),
+        "unit": "GDOF*iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (f64 gather-scatter sums, dots, refinement residuals)"
+        if mode != mx.MODE_FP64 else "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "E": bm.E, "N": wl.N, "nloc": nloc,
+                   "mode": args.mode, "pc": "jacobi", "tol": wl.tol,
+                   "iterations_per_step": iters / args.steps},
+        "roofline": {"bound": "hbm", "kernel": "ax_kernel (fused p-update + local operator)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": traffic_bytes, "avg_launch_us": round(ax_avg_ms * 1e3, 2),
+                     "launches_timed": tot},
+        "setup_s": round(t_setup, 3),
+        **extra,
+    }
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_iters)
+    print(json.dumps(out), flush=True)
+    mesh.close()
+    ctx.close()
+
+
+def cpu_baseline(wl, iters):
+    """FP64 oracle Jacobi-PCG on the same workload, a bounded number of
+    iterations (tol 0), GDOF*iter/s of the iteration loop only."""
+    import numpy as np
+
+    import oracle
+    from paper_2503_02134_amd import workloads as W
+    xo, _ = oracle.gll(wl.N)
+    bm = W.box_mesh(wl.ne, wl.N, xo, seed=wl.deform_seed)
+    kf = W.lognormal_k(bm, wl.k_seed) if wl.k_seed is not None else None
+    f = W.manufactured(bm)[0] if wl.rhs == "manufactured" else W.random_smooth_rhs(bm, wl.rhs_seed)
+    om = oracle.Mesh(bm.E, wl.N, bm.xyz, bm.glo, bm.bnd, kcoef=kf, helm_h=wl.helm_h)
+    b = om.rhs(f)
+    t0 = time.perf_counter()
+    _, st = om.pcg(b, tol=0.0, maxit=iters)
+    el = time.perf_counter() - t0
+    # the call also does one true-residual apply at exit: count it as an iteration
+    value = om.nloc * (st.iterations + 1) / el / 1e9
+    log(f"cpu oracle: {st.iterations} iterations in {el:.1f}s")
+    return {"value": round(value, 5), "unit": "GDOF*iter/s", "cores": oracle.max_threads(),
+            "kind": "oracle",
+            "sample": f"{st.iterations} FP64 Jacobi-PCG iterations of {wl.name} "
+                      f"(plain C oracle, OpenMP over elements), {el:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

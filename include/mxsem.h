@@ -1,0 +1,284 @@
+/*
+ * mxsem: matrix-free spectral-element Poisson/Helmholtz (P)CG on one
+ * MI355X (gfx950), in FP64, in the paper's mixed FP32/FP64 recipe, inside
+ * FP64 iterative refinement, batched over many uneven problems, and with a
+ * learned flexible-CG preconditioner.
+ *
+ * Paper: Y. Chen et al., "Enabling mixed-precision in spectral element
+ * codes" (arXiv 2503.02134).  The calls follow the paper's statement of the
+ * problem: set up a mesh of E hexahedral elements of order N (Sec. 4,
+ * Nekbone solves a Poisson problem on high-order elements; Sec. 5, Neko on
+ * hexahedra), apply the matrix-free operator A (Sec. 4.1, CG-loop profiling
+ * table, the "ax" line), gather-scatter / direct stiffness summation QQ^T
+ * (Sec. 4.2.1), the weighted dot glsc3 (same table, lines 3, 6, 9), the
+ * Jacobi preconditioner 1/diag(A) (Sec. 5.2) and the (P)CG solve with a
+ * stopping tolerance (Sec. 6).  The mixed modes keep the gather-scatter sums
+ * and the dot products in FP64 while the loop body runs in FP32 (Sec. 4.2.1
+ * conclusion, Sec. 5.2, Sec. 6.1.1).
+ *
+ * Conventions for every call:
+ *  - A local vector holds E*(N+1)^3 entries, entry ((e*n+k)*n+j)*n+i for
+ *    node (i,j,k) of element e, n = N+1 (i fastest).
+ *  - "device" pointers are HIP device memory owned by the caller (for
+ *    example torch tensors); they must stay valid until the work queued on
+ *    the context stream has finished.  FP64 vectors must be 8-byte aligned,
+ *    FP32 vectors 4-byte aligned; 256-byte alignment is best.
+ *  - "host" pointers are read or written only during the call.
+ *  - Handles own the device memory the library allocates for them (operator
+ *    data, gather-scatter plan, solver work vectors); destroy frees it and
+ *    never frees caller memory.
+ *  - Every call returns 0 (MXSEM_OK) or a negative status; no C++ exception
+ *    crosses this boundary and nothing calls exit.  mxsem_last_error()
+ *    returns a message for the most recent failure on the calling thread.
+ *  - A context (and everything created from it) must be used by one host
+ *    thread at a time.
+ *  - Calls marked "async" only enqueue work on the context stream.
+ */
+#ifndef MXSEM_H
+#define MXSEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define MXSEM_OK 0
+#define MXSEM_EINVAL (-1)     /* bad argument: null pointer, size, alignment */
+#define MXSEM_ENOTSUP (-2)    /* unsupported order, view or combination      */
+#define MXSEM_EHIP (-3)       /* HIP runtime failure (message in last_error) */
+#define MXSEM_EBREAKDOWN (-4) /* (p,Ap) <= 0 or non-finite, no fallback left */
+#define MXSEM_EINTERNAL (-5)
+#define MXSEM_ENOMEM (-6)     /* device or host allocation failed            */
+#define MXSEM_EMESH (-7)      /* mesh rejected: |J| <= 0, inconsistent mask,
+                                 shared or masked element-interior node      */
+
+/* ---- precisions of vectors and operator data --------------------------- */
+typedef enum {
+  MXSEM_F64 = 0,       /* FP64 vectors, FP64 geometric factors            */
+  MXSEM_F32 = 1,       /* FP32 vectors, FP32 geometric factors            */
+  MXSEM_BF16G_F32 = 2  /* FP32 vectors, BF16 geometric factors (and h*B),
+                          FP32 accumulation                                */
+} mxsem_prec;
+
+/* ---- preconditioners ---------------------------------------------------- */
+typedef enum {
+  MXSEM_PC_IDENTITY = 0, /* z = r (Sec. 5, identity-preconditioned CG)      */
+  MXSEM_PC_JACOBI = 1,   /* z = dinv * r, dinv = 1/diag(A) built in FP64 (Sec. 5.2) */
+  MXSEM_PC_LEARNED = 2   /* z = M QQ^T(c*(dinv*r + s_e NN(r))), needs an
+                            attached network and method FCG                */
+} mxsem_pc;
+
+/* ---- solve modes -------------------------------------------------------- */
+typedef enum {
+  MXSEM_MODE_FP64 = 0,           /* everything FP64                          */
+  MXSEM_MODE_MIXED = 1,          /* the paper's recipe: FP32 loop body and
+                                    preconditioner, FP64 gather-scatter sums
+                                    and dot products, no refinement        */
+  MXSEM_MODE_MIXED_IR = 2,       /* MIXED inner PCG inside FP64 iterative
+                                    refinement with FP64 residuals           */
+  MXSEM_MODE_MIXED_IR_BF16G = 3, /* as MIXED_IR, inner operator reads BF16 G */
+  MXSEM_MODE_FP32_ALL = 4        /* ablation: FP32 gather-scatter sums and FP32
+                                    dot accumulation (the configuration the
+                                    paper finds to stagnate)                 */
+} mxsem_mode;
+
+typedef enum { MXSEM_METHOD_PCG = 0, MXSEM_METHOD_FCG = 1 } mxsem_method;
+
+/* termination reasons */
+#define MXSEM_CONVERGED 1
+#define MXSEM_MAX_ITER 2
+#define MXSEM_STAGNATED 3
+#define MXSEM_BREAKDOWN 4
+
+/* apply / gather-scatter flags */
+#define MXSEM_LOCAL_ONLY 1u /* apply: w = A_L u only (no QQ^T, no mask)      */
+#define MXSEM_MASK 2u       /* gather_scatter: also zero Dirichlet entries   */
+
+/* mesh views (bitmask): which operator copies to keep on the device */
+#define MXSEM_VIEW_F64 1u
+#define MXSEM_VIEW_F32 2u
+#define MXSEM_VIEW_BF16 4u
+
+typedef struct mxsem_ctx mxsem_ctx;
+typedef struct mxsem_mesh mxsem_mesh;
+typedef struct mxsem_batch mxsem_batch;
+typedef struct mxsem_nn mxsem_nn;
+
+/* ---- context ------------------------------------------------------------- */
+/* One device and one stream.  hip_stream: a hipStream_t (for example
+ * torch.cuda.current_stream().cuda_stream) or NULL for the null stream.
+ * Makes hip_device current on the calling thread. */
+int mxsem_ctx_create(int hip_device, void *hip_stream, mxsem_ctx **out);
+int mxsem_ctx_destroy(mxsem_ctx *ctx);
+/* Replace the stream used by later calls (same device). */
+int mxsem_ctx_set_stream(mxsem_ctx *ctx, void *hip_stream);
+
+/* ---- reference element --------------------------------------------------- */
+/* Gauss-Lobatto-Legendre nodes (ascending, -1..1) and weights for order N,
+ * 1 <= N <= 15; host arrays of N+1 entries.  Input generators use the nodes
+ * to place mesh points. */
+int mxsem_gll(int N, double *xi_host, double *w_host);
+
+/* ---- mesh ---------------------------------------------------------------- */
+typedef struct {
+  int E;                 /* number of hexahedra, >= 1                       */
+  int N;                 /* polynomial order, 1..15                         */
+  const double *xyz;     /* host [E][3][n^3] node coordinates               */
+  const int64_t *glo;    /* host [E][n^3] global node ids (>= 0)            */
+  const uint8_t *bnd;    /* host [E][n^3], nonzero on Dirichlet nodes       */
+  const double *kcoef;   /* host [E][n^3] diffusion coefficient, or NULL = 1 */
+  double helm_h;         /* Helmholtz coefficient h >= 0 (0: Poisson)       */
+  unsigned views;        /* MXSEM_VIEW_* bitmask; F64 is always kept        */
+} mxsem_mesh_desc;
+
+/* Builds, in FP64 on the device, the geometric factors G (6 per node,
+ * times k), the mass B, the multiplicity weight c = 1/m, the gather-scatter
+ * plan (host sort of glo), the Dirichlet list and the Jacobi inverse
+ * diagonal dinv (0 on Dirichlet nodes); then the FP32 / BF16 copies asked
+ * for in views.  Synchronous.  Rejects (MXSEM_EMESH) a non-positive
+ * Jacobian, copies of one node that disagree on bnd, and element-interior
+ * nodes that are shared or Dirichlet. */
+int mxsem_mesh_create(mxsem_ctx *ctx, const mxsem_mesh_desc *desc, mxsem_mesh **out);
+int mxsem_mesh_destroy(mxsem_mesh *mesh);
+
+/* Sizes: local entries, gather-scatter groups (shared nodes and free
+ * element-face nodes), Dirichlet entries, minimum |J|. */
+int mxsem_mesh_info(const mxsem_mesh *mesh, int64_t *nloc, int64_t *ngroups,
+                    int64_t *nmasked, double *min_detj);
+
+/* Copy operator data to host arrays (FP64): what = 0 G [E][6][n^3],
+ * 1 B [E][n^3], 2 c [E][n^3], 3 dinv [E][n^3], 4 mask [E][n^3] (0/1),
+ * 5 D [n][n].  Synchronous. */
+int mxsem_mesh_get(const mxsem_mesh *mesh, int what, double *out_host);
+
+/* ---- operator pieces (async) ----------------------------------------------- */
+/* w = M QQ^T A_L u (assembled apply, Dirichlet rows zeroed), or with
+ * MXSEM_LOCAL_ONLY w = A_L u.  A_L u = sum_ab D_a^T diag(G_ab) D_b u + h B u
+ * (tensor-product local_grad3, geometric-factor multiply, local_grad3_t).
+ * io selects the vector type and the G copy (the view must exist).  With
+ * QQ^T the shared-node sums are accumulated in FP64 for every io. */
+int mxsem_apply(mxsem_mesh *mesh, mxsem_prec io, const void *u, void *w, unsigned flags);
+
+/* In place v <- QQ^T v: each shared node's copies are summed in ascending
+ * local-index order in acc precision (MXSEM_F64 or MXSEM_F32), rounded once
+ * to io and written to every copy.  MXSEM_MASK also zeroes Dirichlet
+ * entries.  io: MXSEM_F64 or MXSEM_F32. */
+int mxsem_gather_scatter(mxsem_mesh *mesh, mxsem_prec io, mxsem_prec acc, void *v,
+                         unsigned flags);
+
+/* *out_dev (device FP64 scalar) = sum_i a_i c_i b_i, c = 1/multiplicity,
+ * products and accumulation in FP64 (glsc3).  io: MXSEM_F64 or MXSEM_F32. */
+int mxsem_dot(mxsem_mesh *mesh, mxsem_prec io, const void *a, const void *b,
+              double *out_dev);
+
+/* z = M^-1 r for pc = identity or Jacobi (io MXSEM_F64 / MXSEM_F32), or the
+ * learned map (MXSEM_F32, network attached). */
+int mxsem_precond(mxsem_mesh *mesh, mxsem_pc pc, mxsem_prec io, const void *r, void *z);
+
+/* b = M QQ^T (B f) for a nodal source f (device FP64 vectors). */
+int mxsem_mass_rhs(mxsem_mesh *mesh, const double *f, double *b);
+
+/* ---- solve ----------------------------------------------------------------- */
+typedef struct {
+  int method;         /* mxsem_method                                      */
+  int pc;             /* mxsem_pc                                          */
+  int mode;           /* mxsem_mode                                        */
+  double tol;         /* stop when ||r||_c <= tol ||b||_c                  */
+  int max_iter;       /* cap on (inner) iterations in total               */
+  double inner_tol;   /* IR modes: relative tolerance of each inner solve  */
+  int max_outer;      /* IR modes: cap on refinement steps                 */
+  int graph_chunk;    /* iterations per captured HIP graph (>= 1)          */
+  int x0_given;       /* 1: start from x (FP64 modes); 0: x = 0            */
+  double *history;    /* nullable device FP64 [max_iter+1]: relative
+                         recursive residual per iteration                   */
+} mxsem_solve_opts;
+
+typedef struct {
+  int iterations;     /* inner (P)CG iterations in total                   */
+  int outer;          /* refinement steps (IR modes)                       */
+  int reason;         /* MXSEM_CONVERGED / MAX_ITER / STAGNATED / BREAKDOWN */
+  int fallback_used;  /* learned PC replaced by Jacobi (steps), or IR fell
+                         back to FP64 PCG (1)                              */
+  double rel_res;     /* true ||b - A x||_c / ||b||_c in FP64 at exit      */
+  double rel_res_recursive; /* last recursive residual of the inner loop   */
+  double ms;          /* wall time of the solve on the stream (hipEvents)  */
+  double ax_ms;       /* mean duration of the operator kernel of the first
+                         iteration of each graph launch (hipEvents around
+                         that kernel node), inner loop only               */
+  int ax_samples;     /* number of such timed launches                     */
+  int pad_;
+} mxsem_solve_stats;
+
+/* Solve A x = b.  b, x: device FP64 local vectors (b continuous and masked,
+ * e.g. from mxsem_mass_rhs).  Stops at tol, max_iter, stagnation (the best
+ * residual has not improved by 10% in 50 iterations) or breakdown.
+ * Synchronous on the context stream; fills st. */
+int mxsem_solve(mxsem_mesh *mesh, const mxsem_solve_opts *opts, const double *b, double *x,
+                mxsem_solve_stats *st);
+void mxsem_solve_opts_default(mxsem_solve_opts *opts);
+
+/* ---- batch of independent problems --------------------------------------- */
+typedef struct {
+  int epb[16];        /* elements per workgroup of the operator kernel per N
+                         (0 = library default)                              */
+} mxsem_tuning;
+
+/* P meshes on one context solved together: every captured graph chunk
+ * launches each stage once per order class over a tile table that spans
+ * all problems; problems that have converged become no-ops.  tune_cache:
+ * JSON file path for autotuned tiles (nullable = defaults, or the
+ * MXSEM_TUNE_CACHE environment variable). */
+int mxsem_batch_create(mxsem_ctx *ctx, int P, mxsem_mesh *const *meshes,
+                       const char *tune_cache, mxsem_batch **out);
+int mxsem_batch_destroy(mxsem_batch *batch);
+/* b[p], x[p]: device FP64 vectors per problem; st: host array of P. */
+int mxsem_batch_solve(mxsem_batch *batch, const mxsem_solve_opts *opts,
+                      const double *const *b, double *const *x, mxsem_solve_stats *st);
+/* Time the candidate tiles of the operator kernel for one (N, E, prec) on
+ * the context's device and return the fastest (epb[N]). */
+int mxsem_autotune(mxsem_ctx *ctx, int N, int E, mxsem_prec prec, mxsem_tuning *out);
+/* Tiles the library will use for a mesh (after any tuning). */
+int mxsem_mesh_set_tuning(mxsem_mesh *mesh, const mxsem_tuning *t);
+
+/* ---- learned preconditioner ------------------------------------------------ */
+typedef struct {
+  int cin;            /* input channels, must be 2: [r, dinv r] / s_e      */
+  int ch;             /* hidden channels (32)                              */
+} mxsem_nn_desc;
+
+/* Network z_L = dinv r + s_e * conv2(relu(conv1([r, dinv r]/s_e))), 3x3x3
+ * kernels with zero padding at element borders, no bias, s_e = ||dinv r||
+ * per element; weights W1 [ch][cin][27], W2 [ch][27] (offset o = (di+1) +
+ * 3(dj+1) + 9(dk+1)); BF16 inputs and weights, FP32 accumulation. */
+int mxsem_nn_create(mxsem_mesh *mesh, const mxsem_nn_desc *desc, mxsem_nn **out);
+int mxsem_nn_destroy(mxsem_nn *nn);
+int mxsem_nn_set_params(mxsem_nn *nn, const float *W1_host, const float *W2_host);
+int mxsem_nn_get_params(mxsem_nn *nn, float *W1_host, float *W2_host);
+/* z = M QQ^T (c * zL(r)) for a device FP32 residual r. Async. */
+int mxsem_nn_forward(mxsem_nn *nn, const float *r, float *z);
+/* Mean over nsamp pairs of ||z(r_s) - e_s||_A^2 / ||e_s||_A^2 and its
+ * gradient (device FP32 grad [ch*cin*27 + ch*27], W1 part first); r, e:
+ * device FP32 [nsamp][nloc]; loss_dev: device FP64 scalar. Async. */
+int mxsem_nn_loss_grad(mxsem_nn *nn, const float *r, const float *e, int nsamp,
+                       double *loss_dev, float *grad_dev);
+typedef struct {
+  double lr, beta1, beta2, eps;
+  int step;           /* 1-based step count                                */
+} mxsem_adam;
+/* Adam on the FP32 master weights with the gradient last computed by
+ * mxsem_nn_loss_grad. Async. */
+int mxsem_nn_adam_step(mxsem_nn *nn, const mxsem_adam *opt);
+int mxsem_mesh_attach_nn(mxsem_mesh *mesh, mxsem_nn *nn);
+
+/* ---- diagnostics ------------------------------------------------------------ */
+const char *mxsem_status_str(int status);
+const char *mxsem_last_error(void);
+int mxsem_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MXSEM_H */

@@ -52,6 +52,8 @@ def _load():
     lib.orc_mesh_destroy.argtypes = [vp]
     lib.orc_mesh_nloc.argtypes = [vp]
     lib.orc_mesh_nloc.restype = C.c_int64
+    lib.orc_max_threads.argtypes = []
+    lib.orc_max_threads.restype = C.c_int
     lib.orc_mesh_ngroups.argtypes = [vp]
     lib.orc_mesh_ngroups.restype = C.c_int64
     lib.orc_mesh_mindet.argtypes = [vp]
@@ -102,6 +104,11 @@ class SolveStats:
     fallback: int
     rel_res_recursive: float
     rel_res_true: float
+
+
+def max_threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(_load().orc_max_threads())
 
 
 def gll(N: int):

@@ -31,6 +31,7 @@
  * xyz is [E][3][n^3]; G is [E][6][n^3] with components rr,rs,rt,ss,st,tt.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -488,6 +489,7 @@ int orc_mesh_create(int E, int N, const double *xyz, const int64_t *glo,
 }
 
 int64_t orc_mesh_nloc(const orc_mesh *m) { return m->nloc; }
+int orc_max_threads(void) { return omp_get_max_threads(); }
 int64_t orc_mesh_ngroups(const orc_mesh *m) { return m->ngroups; }
 double orc_mesh_mindet(const orc_mesh *m) { return m->mindet; }
 

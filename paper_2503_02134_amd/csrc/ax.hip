@@ -1,0 +1,222 @@
+// Local spectral-element operator  w_L = sum_ab D_a^T diag(G_ab) D_b u_L + h B u_L
+// on hexahedra of order N (the "ax" kernel of the CG loop: local_grad3, the
+// geometric-factor multiply and local_grad3_t, Sec. 4.1, CG-loop profiling
+// table and its footnote on mxm and accumulations).
+//
+// Mapping for gfx950: one thread per (i,j) column of an element, n^2
+// threads per element, several elements per workgroup (tile size epb),
+// workgroup rounded up to whole wave64s.  Each thread keeps its u column
+// and the w accumulator column (length n) in registers; the t-direction
+// derivative and its transpose therefore never touch LDS.  For each k the
+// (i,j) slab of u is staged in LDS for the r/s derivatives, and the slabs
+// of G-multiplied r/s components are staged for the transposed sums.
+// Global traffic per local dof: u in, six G values in, w out (plus, in the
+// solver variant, z in and p in/out for the fused p update) - each a fully
+// coalesced n^2-wide stream per k.
+#include "common.hpp"
+
+namespace mx {
+
+struct AxApplyArgs {
+  const void* u;
+  void* w;
+  const void* G;
+  const void* hB;
+  const void* D;
+  int E;
+};
+
+// Solver variant: p = z + beta p_old (beta from the device state, p
+// written back), w = A_L p, and the partial sum of p.w over element-interior
+// nodes (never shared, never Dirichlet, so c = 1 and w is already final).
+template <int N, typename T, typename TG, bool SOLVER>
+__global__ void ax_kernel(const Tile* __restrict__ tiles, const ProbDev* __restrict__ probs,
+                          AxApplyArgs apply, int epb) {
+  constexpr int n = N + 1, n2 = n * n, n3 = n2 * n;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sD = reinterpret_cast<T*>(smem_raw);
+  T* slab = sD + n2;
+  __shared__ double sred[16];
+
+  const T* __restrict__ Dg;
+  const TG* __restrict__ G;
+  const TG* __restrict__ hB;
+  const T* __restrict__ U;
+  T* __restrict__ Wout;
+  const T* __restrict__ Z = nullptr;
+  int E, first;
+  const ProbDev* P = nullptr;
+  if constexpr (SOLVER) {
+    const Tile t = tiles[blockIdx.x];
+    P = &probs[t.prob];
+    if (P->st->done) return;  // uniform across the workgroup
+    Dg = (const T*)P->D;
+    G = (const TG*)P->G;
+    hB = (const TG*)P->hB;
+    U = (const T*)P->p;
+    Wout = (T*)P->w;
+    Z = (const T*)P->z;
+    E = P->E;
+    first = t.first;
+  } else {
+    Dg = (const T*)apply.D;
+    G = (const TG*)apply.G;
+    hB = (const TG*)apply.hB;
+    U = (const T*)apply.u;
+    Wout = (T*)apply.w;
+    E = apply.E;
+    first = blockIdx.x * epb;
+  }
+
+  const int tid = threadIdx.x;
+  for (int q = tid; q < n2; q += blockDim.x) sD[q] = Dg[q];
+  const int le = tid / n2;
+  const int ij = tid - le * n2;
+  const int i = ij % n, j = ij / n;
+  const int e = first + le;
+  const bool active = (le < epb) && (e < E);
+  T* su = slab + le * 3 * n2;
+  T* sr = su + n2;
+  T* ss = sr + n2;
+  __syncthreads();
+
+  T u[n], w[n], Di[n], Dj[n], DiT[n], DjT[n];
+#pragma unroll
+  for (int l = 0; l < n; ++l) {
+    Di[l] = sD[i * n + l];
+    Dj[l] = sD[j * n + l];
+    DiT[l] = sD[l * n + i];
+    DjT[l] = sD[l * n + j];
+    w[l] = T(0);
+  }
+  const int64_t base = (int64_t)e * n3 + ij;
+  if (active) {
+    if constexpr (SOLVER) {
+      const T beta = (T)P->st->beta;
+      T* __restrict__ Pw = (T*)P->p;
+#pragma unroll
+      for (int k = 0; k < n; ++k) {
+        T pv = Z[base + k * n2] + beta * U[base + k * n2];
+        Pw[base + k * n2] = pv;
+        u[k] = pv;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < n; ++k) u[k] = U[base + k * n2];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < n; ++k) u[k] = T(0);
+  }
+
+  const TG* __restrict__ Ge = G + (int64_t)e * 6 * n3 + ij;
+#pragma unroll
+  for (int k = 0; k < n; ++k) {
+    if (active) su[ij] = u[k];
+    __syncthreads();
+    if (active) {
+      T ur = T(0), us = T(0), ut = T(0);
+#pragma unroll
+      for (int l = 0; l < n; ++l) {
+        ur += Di[l] * su[j * n + l];
+        us += Dj[l] * su[l * n + i];
+        ut += sD[k * n + l] * u[l];
+      }
+      const int off = k * n2;
+      const T g0 = cvt<T>(Ge[0 * n3 + off]);
+      const T g1 = cvt<T>(Ge[1 * n3 + off]);
+      const T g2 = cvt<T>(Ge[2 * n3 + off]);
+      const T g3 = cvt<T>(Ge[3 * n3 + off]);
+      const T g4 = cvt<T>(Ge[4 * n3 + off]);
+      const T g5 = cvt<T>(Ge[5 * n3 + off]);
+      const T wr = g0 * ur + g1 * us + g2 * ut;
+      const T ws = g1 * ur + g3 * us + g4 * ut;
+      const T wt = g2 * ur + g4 * us + g5 * ut;
+#pragma unroll
+      for (int m = 0; m < n; ++m) w[m] += sD[k * n + m] * wt;
+      sr[ij] = wr;
+      ss[ij] = ws;
+    }
+    __syncthreads();
+    if (active) {
+      T acc = T(0);
+#pragma unroll
+      for (int l = 0; l < n; ++l) acc += DiT[l] * sr[j * n + l] + DjT[l] * ss[l * n + i];
+      w[k] += acc;
+    }
+    __syncthreads();
+  }
+
+  double dot = 0.0;
+  if (active) {
+    const bool ij_interior = (i > 0) && (i < N) && (j > 0) && (j < N);
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+      T wv = w[k];
+      if (hB) wv += cvt<T>(hB[(int64_t)e * n3 + k * n2 + ij]) * u[k];
+      Wout[base + k * n2] = wv;
+      if constexpr (SOLVER) {
+        if (ij_interior && k > 0 && k < N) dot += (double)u[k] * (double)wv;
+      }
+    }
+  }
+  if constexpr (SOLVER) {
+    double s = block_sum(dot, sred);
+    if (tid == 0) P->part_ax[first / epb] = s;
+  }
+}
+
+template <int N, typename T, typename TG, bool SOLVER>
+static hipError_t launch_one(const Tile* tiles, const ProbDev* probs, const AxApplyArgs& a,
+                             int ntiles, int epb, hipStream_t s) {
+  constexpr int n = N + 1, n2 = n * n;
+  int threads = ((epb * n2 + 63) / 64) * 64;
+  size_t shm = sizeof(T) * (n2 + (size_t)epb * 3 * n2);
+  hipLaunchKernelGGL((ax_kernel<N, T, TG, SOLVER>), dim3(ntiles), dim3(threads), shm, s, tiles,
+                     probs, a, epb);
+  return hipGetLastError();
+}
+
+template <typename T, typename TG, bool SOLVER>
+static hipError_t dispatch(int N, const Tile* tiles, const ProbDev* probs, const AxApplyArgs& a,
+                           int ntiles, int epb, hipStream_t s) {
+  switch (N) {
+#define MX_CASE(NN) \
+  case NN:          \
+    return launch_one<NN, T, TG, SOLVER>(tiles, probs, a, ntiles, epb, s);
+    MX_CASE(1) MX_CASE(2) MX_CASE(3) MX_CASE(4) MX_CASE(5) MX_CASE(6) MX_CASE(7) MX_CASE(8)
+    MX_CASE(9) MX_CASE(10) MX_CASE(11) MX_CASE(12) MX_CASE(13) MX_CASE(14) MX_CASE(15)
+#undef MX_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+// prec: 0 FP64/FP64, 1 FP32/FP32, 2 FP32 vectors with BF16 G
+hipError_t launch_ax_apply(int prec, int N, int E, int epb, const void* u, void* w,
+                           const void* G, const void* hB, const void* D, hipStream_t s) {
+  AxApplyArgs a{u, w, G, hB, D, E};
+  int ntiles = (E + epb - 1) / epb;
+  switch (prec) {
+    case 0: return dispatch<double, double, false>(N, nullptr, nullptr, a, ntiles, epb, s);
+    case 1: return dispatch<float, float, false>(N, nullptr, nullptr, a, ntiles, epb, s);
+    case 2: return dispatch<float, bf16_t, false>(N, nullptr, nullptr, a, ntiles, epb, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_ax_solver(int prec, int N, const Tile* tiles, int ntiles, const ProbDev* probs,
+                            int epb, hipStream_t s) {
+  AxApplyArgs a{};
+  switch (prec) {
+    case 0: return dispatch<double, double, true>(N, tiles, probs, a, ntiles, epb, s);
+    case 1: return dispatch<float, float, true>(N, tiles, probs, a, ntiles, epb, s);
+    case 2: return dispatch<float, bf16_t, true>(N, tiles, probs, a, ntiles, epb, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// largest epb whose workgroup fits 1024 threads
+int max_epb(int N) { return 1024 / ((N + 1) * (N + 1)); }
+
+}  // namespace mx

@@ -1,0 +1,165 @@
+// Shared internal definitions of the mxsem HIP library (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/mxsem.h"
+
+namespace mx {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+const char* get_error();
+
+#define MX_HIP(call)                                                          \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess) {                                                   \
+      ::mx::set_error(std::string(#call) + ": " + hipGetErrorString(e_));     \
+      return MXSEM_EHIP;                                                      \
+    }                                                                         \
+  } while (0)
+
+#define MX_TRY(call)               \
+  do {                             \
+    int rc_ = (call);              \
+    if (rc_ != MXSEM_OK) return rc_; \
+  } while (0)
+
+#define MX_CHECK(cond, code, msg)  \
+  do {                             \
+    if (!(cond)) {                 \
+      ::mx::set_error(msg);        \
+      return code;                 \
+    }                              \
+  } while (0)
+
+// ---------------------------------------------------------------- bf16
+// Storage of the BF16 geometric factors: the upper 16 bits of an FP32.
+typedef uint16_t bf16_t;
+
+__host__ __device__ inline float bf16_to_float(bf16_t b) {
+  union {
+    uint32_t u;
+    float f;
+  } v;
+  v.u = ((uint32_t)b) << 16;
+  return v.f;
+}
+
+// round-to-nearest-even FP32 -> BF16 (finite inputs)
+__host__ __device__ inline bf16_t float_to_bf16(float f) {
+  union {
+    uint32_t u;
+    float f;
+  } v;
+  v.f = f;
+  uint32_t lsb = (v.u >> 16) & 1u;
+  v.u += 0x7FFFu + lsb;
+  return (bf16_t)(v.u >> 16);
+}
+
+template <typename T>
+__device__ inline T load_as(const T* p) {
+  return *p;
+}
+template <typename TD, typename TS>
+__device__ inline TD cvt(TS v) {
+  return (TD)v;
+}
+template <>
+__device__ inline float cvt<float, bf16_t>(bf16_t v) {
+  return bf16_to_float(v);
+}
+template <>
+__device__ inline double cvt<double, bf16_t>(bf16_t v) {
+  return (double)bf16_to_float(v);
+}
+
+// ---------------------------------------------------------------- solver state
+// Per-problem scalars of one (P)CG solve, resident in device memory.
+struct State {
+  double rho;    // (r, z)_c
+  double sigma;  // (p, A p)_c
+  double alpha, beta;
+  double rr;     // (r, r)_c
+  double bb;     // (b, b)_c of the (inner) right-hand side
+  double tol2;   // tol^2
+  double best;   // stagnation reference relative residual
+  double res;    // last relative recursive residual
+  double zw;     // (z, A p_old)_c (flexible CG)
+  double* history;  // nullable [maxit+1]
+  int iter, maxit;
+  int done;      // 1: this problem's kernels return at once
+  int reason;    // MXSEM_CONVERGED ...
+  int since;     // iterations since the last 10% improvement
+  int fallback;  // learned-PC steps replaced by Jacobi
+  int pc;        // mxsem_pc
+  int pad;
+};
+
+// A tile: a block of work of one problem (elements, groups or entries).
+struct Tile {
+  int prob;
+  int first;
+};
+
+// Device view of one problem for the iteration kernels.  Vector and
+// operator pointers are typed by the kernel instantiation.
+struct ProbDev {
+  int E, n3;
+  int64_t nloc;
+  // operator
+  const void* G;     // [E][6][n3] in the G type
+  const void* hB;    // [E][n3] h*B in the G type or null (Poisson)
+  const void* D;     // [n][n] in the vector type
+  const void* dinv;  // [nloc] vector type
+  const uint8_t* mult;  // [nloc] multiplicity m
+  // gather-scatter plan
+  const int* gs_off;  // [ngroups+1]
+  const int* gs_idx;
+  const int* mask_idx;
+  int ngroups, nmask;
+  // vectors (vector type)
+  void *x, *r, *z, *p, *w;
+  // FP64 right-hand side of the current (inner) solve and its scale
+  const double* rhs64;
+  double rhs_scale;  // r = rhs64 * rhs_scale
+  // partial sums
+  double* part_ax;   // sigma over element-interior nodes, per Ax tile
+  double* part_gs;   // sigma over gather-scatter items, per GS tile
+  double* part_u0;   // per update tile: (r,z)_c  (or rr for FCG)
+  double* part_u1;   // per update tile: (r,r)_c
+  double* part_u2;   // per tile: (z,w)_c (flexible CG)
+  int nblk_ax, nblk_gs, nblk_upd;
+  State* st;
+};
+
+constexpr int GS_CHUNK = 256;    // gather-scatter items per workgroup
+constexpr int UPD_THREADS = 256; // threads per vector-update workgroup
+constexpr int UPD_PER_THREAD = 8;
+constexpr int UPD_CHUNK = UPD_THREADS * UPD_PER_THREAD;
+constexpr int MAX_N = 15;
+
+// ---------------------------------------------------------------- reductions
+// Deterministic block sum of one double per thread (wave64 shuffles, then
+// LDS across waves).  Every thread of the block must call it.  Returns the
+// sum on thread 0.
+template <typename A>
+__device__ inline A block_sum(A v, A* sred) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) sred[wid] = v;
+  __syncthreads();
+  A s = 0;
+  if (threadIdx.x == 0)
+    for (int q = 0; q < nw; ++q) s += sred[q];
+  return s;
+}
+
+}  // namespace mx

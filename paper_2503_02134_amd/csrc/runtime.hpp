@@ -1,0 +1,129 @@
+// Host-side objects of the mxsem library (context, mesh, solver buffers).
+#pragma once
+
+#include <vector>
+
+#include "common.hpp"
+
+struct mxsem_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;   // caller's stream (may be null)
+  hipStream_t capture = nullptr;  // private stream used only for graph capture
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  int* pinned_flags = nullptr;    // host-pinned poll buffer
+};
+
+namespace mx {
+
+// launchers (defined in the .hip files)
+hipError_t launch_ax_apply(int prec, int N, int E, int epb, const void* u, void* w, const void* G,
+                           const void* hB, const void* D, hipStream_t s);
+hipError_t launch_ax_solver(int prec, int N, const Tile* tiles, int ntiles, const ProbDev* probs,
+                            int epb, hipStream_t s);
+int max_epb(int N);
+hipError_t launch_gs_apply2(int prec_io, int prec_acc, void* v, const int* off, const int* idx,
+                            int ngroups_all, int nfree, int nmask_entries, int mask_first,
+                            bool mask, hipStream_t s);
+hipError_t launch_gs_solver(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs,
+                            hipStream_t s);
+hipError_t launch_update(int vprec, int pc, const Tile* tiles, int ntiles, const ProbDev* probs,
+                         hipStream_t s);
+hipError_t launch_init(int vprec, int pc, const Tile* tiles, int ntiles, const ProbDev* probs,
+                       const double* x0, hipStream_t s);
+hipError_t launch_fin_sigma(const ProbDev* probs, int nprob, hipStream_t s);
+hipError_t launch_fin_rho(const ProbDev* probs, int nprob, int init, hipStream_t s);
+hipError_t launch_dot(int prec, const void* a, const void* b, const uint8_t* mult, int64_t n,
+                      double* part, double* out, hipStream_t s);
+hipError_t launch_precond(int prec, int pc, const void* r, void* z, const void* dinv, int64_t n,
+                          hipStream_t s);
+hipError_t launch_residual(const double* b, const double* w, double* r, const uint8_t* mult,
+                           int64_t n, double* part, double* out, hipStream_t s);
+hipError_t launch_axpy_cast(int vprec, double* x64, const void* xT, double sc, double keep,
+                            int64_t n, hipStream_t s);
+hipError_t launch_zero(double* x, int64_t n, hipStream_t s);
+hipError_t launch_mass(const double* B, const double* f, double* b, int64_t n, hipStream_t s);
+hipError_t launch_cast_f32(float* d, const double* src, int64_t n, hipStream_t s);
+hipError_t launch_cast_bf16(bf16_t* d, const double* src, int64_t n, hipStream_t s);
+hipError_t launch_geom(int E, int n, const double* xyz, const double* D, const double* wq,
+                       const double* kcoef, double* G, double* B, double* detmin, int* nblocks,
+                       hipStream_t s);
+hipError_t launch_diag(int E, int n, const double* G, const double* B, double h, const double* D,
+                       double* diag, hipStream_t s);
+hipError_t launch_invert(double* d, int64_t n, hipStream_t s);
+hipError_t launch_scale(double* d, const double* src, double h, int64_t n, hipStream_t s);
+
+// host reference-element routines (library's own)
+void gll_rule(int N, double* xi, double* w);
+void deriv_matrix(int N, const double* xi, double* D);
+
+// vector precision class of a solve
+enum VPrec { VP_F64 = 0, VP_F32 = 1, VP_F32ACC = 3 };
+
+// Device buffers and launch tables of one problem's iteration in one
+// vector precision (the same layout serves the batch, where several
+// problems share the launch tables).
+struct SolverBufs {
+  int vprec = 0;
+  void *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *w = nullptr;
+  double *part_ax = nullptr, *part_gs = nullptr, *part_u0 = nullptr, *part_u1 = nullptr,
+         *part_u2 = nullptr;
+  State* st = nullptr;
+  ProbDev* probs = nullptr;  // device copy (1 entry)
+  ProbDev host_prob{};
+  State host_state{};        // staging copy for host<->device transfers
+  Tile *tiles_ax = nullptr, *tiles_gs = nullptr, *tiles_upd = nullptr;
+  int nt_ax = 0, nt_gs = 0, nt_upd = 0, epb = 1;
+  // cached graph of K iterations
+  hipGraphExec_t graph = nullptr;
+  int graph_k = 0, graph_pc = -1, graph_gprec = -1;
+  // events around the operator kernel of the graph's first iteration
+  hipEvent_t evA = nullptr, evB = nullptr;
+  double ax_ms_sum = 0.0;
+  int ax_samples = 0;
+};
+
+}  // namespace mx
+
+struct mxsem_mesh {
+  mxsem_ctx* ctx = nullptr;
+  int E = 0, N = 0, n = 0, n3 = 0;
+  int64_t nloc = 0;
+  double helm_h = 0.0;
+  unsigned views = 0;
+  // device operator data
+  double* D64 = nullptr;
+  float* D32 = nullptr;
+  double* G64 = nullptr;
+  float* G32 = nullptr;
+  mx::bf16_t* G16 = nullptr;
+  double* B64 = nullptr;
+  double* hB64 = nullptr;
+  float* hB32 = nullptr;
+  mx::bf16_t* hB16 = nullptr;
+  double* dinv64 = nullptr;
+  float* dinv32 = nullptr;
+  uint8_t* mult = nullptr;
+  int* gs_off = nullptr;
+  int* gs_idx = nullptr;
+  int ngroups_all = 0, nfree = 0, nmask_entries = 0, mask_first = 0;
+  double min_det = 0.0;
+  // scratch
+  double* part = nullptr;    // [ceil(nloc / UPD_CHUNK)]
+  double* scal = nullptr;    // [8] device scalars
+  double* tmpa = nullptr;    // FP64 [nloc] work vectors (lazily)
+  double* tmpb = nullptr;
+  int epb[16] = {0};
+  mx::SolverBufs* bufs[4] = {nullptr, nullptr, nullptr, nullptr};
+  mxsem_nn* nn = nullptr;
+  std::vector<void*> allocs;
+};
+
+namespace mx {
+int mesh_alloc(mxsem_mesh* m, void** p, size_t bytes);
+int default_epb(int N);
+int ensure_bufs(mxsem_mesh* m, int vprec, SolverBufs** out);
+int ensure_tmp(mxsem_mesh* m);
+const void* G_ptr(const mxsem_mesh* m, int gprec);
+const void* hB_ptr(const mxsem_mesh* m, int gprec);
+int apply_impl(mxsem_mesh* m, int prec, const void* u, void* w, unsigned flags, hipStream_t s);
+}  // namespace mx

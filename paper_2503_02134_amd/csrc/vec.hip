@@ -1,0 +1,483 @@
+// Gather-scatter (direct stiffness summation QQ^T, Sec. 4.2.1), the
+// Dirichlet mask, the c-weighted dots (glsc3, Sec. 4.1 CG-loop profiling
+// table lines 3/6/9), the fused CG vector pass (add2s2 x2 + Jacobi
+// z = dinv r + two dots, lines 7-9 and the preconditioner line), the
+// device-side scalar updates of (P)CG, and the small casts of iterative
+// refinement.
+//
+// Gather-scatter plan: every element-face node belongs to a group (its
+// copies, ascending local index).  Groups of free nodes come first, sorted
+// by multiplicity, then groups of Dirichlet nodes, whose entries form the
+// mask list.  One thread per group: copies are summed in the accumulation
+// type (FP64 in every mode of the paper's recipe) in ascending local-index
+// order, rounded once to the storage type and written to every copy, so
+// the copies stay bitwise equal.  No atomics anywhere: every reduction is a
+// fixed tree (wave64 shuffles, LDS, per-tile partials, one final block).
+#include <math.h>
+
+#include "common.hpp"
+
+namespace mx {
+
+// ------------------------------------------------------------ gather-scatter
+template <typename T, typename ACC>
+__global__ void gs_apply_kernel(T* __restrict__ v, const int* __restrict__ off,
+                                const int* __restrict__ idx, int nsum, int nfree,
+                                int nmask_entries, int mask_first) {
+  const int item = blockIdx.x * blockDim.x + threadIdx.x;
+  if (item < nsum) {
+    const int a = off[item], b = off[item + 1];
+    ACC s = ACC(0);
+    for (int q = a; q < b; ++q) s += (ACC)v[idx[q]];
+    const T val = (T)s;
+    for (int q = a; q < b; ++q) v[idx[q]] = val;
+  } else if (item - nsum < nmask_entries) {
+    v[idx[mask_first + item - nsum]] = T(0);
+  }
+  (void)nfree;
+}
+
+// solver variant on w, with the partial (p, w)_c over the groups
+template <typename T, typename ACC>
+__global__ void gs_solver_kernel(const Tile* __restrict__ tiles,
+                                 const ProbDev* __restrict__ probs) {
+  __shared__ ACC sred[16];
+  const Tile t = tiles[blockIdx.x];
+  const ProbDev& P = probs[t.prob];
+  if (P.st->done) return;
+  T* __restrict__ w = (T*)P.w;
+  const T* __restrict__ p = (const T*)P.p;
+  const int* __restrict__ off = P.gs_off;
+  const int* __restrict__ idx = P.gs_idx;
+  const int item = t.first + threadIdx.x;
+  ACC dot = ACC(0);
+  if (item < P.ngroups) {
+    const int a = off[item], b = off[item + 1];
+    ACC s = ACC(0);
+    for (int q = a; q < b; ++q) s += (ACC)w[idx[q]];
+    const T val = (T)s;
+    for (int q = a; q < b; ++q) w[idx[q]] = val;
+    dot = (ACC)p[idx[a]] * (ACC)val;
+  } else if (item < P.ngroups + P.nmask) {
+    w[P.mask_idx[item - P.ngroups]] = T(0);
+  }
+  ACC s = block_sum(dot, sred);
+  if (threadIdx.x == 0) P.part_gs[t.first / GS_CHUNK] = (double)s;
+}
+
+// ------------------------------------------------------------ vector pass
+__device__ inline double cweight(uint8_t m) { return m == 1 ? 1.0 : 1.0 / (double)m; }
+
+// PC: 0 identity, 1 Jacobi, -1 none (z left alone; flexible CG computes it)
+// x += alpha p; r -= alpha w; z = M^-1 r; partials (r,z)_c and (r,r)_c.
+template <typename T, typename ACC, int PC>
+__global__ void update_kernel(const Tile* __restrict__ tiles, const ProbDev* __restrict__ probs) {
+  __shared__ ACC sred[16];
+  const Tile t = tiles[blockIdx.x];
+  const ProbDev& P = probs[t.prob];
+  if (P.st->done) return;
+  const T alpha = (T)P.st->alpha;
+  T* __restrict__ x = (T*)P.x;
+  T* __restrict__ r = (T*)P.r;
+  T* __restrict__ z = (T*)P.z;
+  const T* __restrict__ p = (const T*)P.p;
+  const T* __restrict__ w = (const T*)P.w;
+  const T* __restrict__ dinv = (const T*)P.dinv;
+  const uint8_t* __restrict__ mult = P.mult;
+  ACC rz = ACC(0), rr = ACC(0);
+#pragma unroll
+  for (int q = 0; q < UPD_PER_THREAD; ++q) {
+    const int64_t i = (int64_t)t.first + q * UPD_THREADS + threadIdx.x;
+    if (i < P.nloc) {
+      const T xv = x[i] + alpha * p[i];
+      const T rv = r[i] - alpha * w[i];
+      x[i] = xv;
+      r[i] = rv;
+      const ACC c = (ACC)cweight(mult[i]);
+      rr += (ACC)rv * c * (ACC)rv;
+      if constexpr (PC >= 0) {
+        const T zv = (PC == 1) ? dinv[i] * rv : rv;
+        z[i] = zv;
+        rz += (ACC)rv * c * (ACC)zv;
+      }
+    }
+  }
+  ACC s0 = block_sum(rz, sred);
+  ACC s1 = block_sum(rr, sred);
+  if (threadIdx.x == 0) {
+    const int b = t.first / UPD_CHUNK;
+    P.part_u0[b] = (double)s0;
+    P.part_u1[b] = (double)s1;
+  }
+}
+
+// start of a solve: r = rhs64 * scale (cast to T), x = x0 or 0, p = 0,
+// z = M^-1 r, partials (r,z)_c and (r,r)_c
+template <typename T, typename ACC, int PC>
+__global__ void init_kernel(const Tile* __restrict__ tiles, const ProbDev* __restrict__ probs,
+                            const double* __restrict__ x0) {
+  __shared__ ACC sred[16];
+  const Tile t = tiles[blockIdx.x];
+  const ProbDev& P = probs[t.prob];
+  if (P.st->done) return;
+  T* __restrict__ x = (T*)P.x;
+  T* __restrict__ r = (T*)P.r;
+  T* __restrict__ z = (T*)P.z;
+  T* __restrict__ p = (T*)P.p;
+  const T* __restrict__ dinv = (const T*)P.dinv;
+  const double scale = P.rhs_scale;
+  ACC rz = ACC(0), rr = ACC(0);
+#pragma unroll
+  for (int q = 0; q < UPD_PER_THREAD; ++q) {
+    const int64_t i = (int64_t)t.first + q * UPD_THREADS + threadIdx.x;
+    if (i < P.nloc) {
+      const T rv = (T)(P.rhs64[i] * scale);
+      r[i] = rv;
+      x[i] = x0 ? (T)x0[i] : T(0);
+      p[i] = T(0);
+      const ACC c = (ACC)cweight(P.mult[i]);
+      rr += (ACC)rv * c * (ACC)rv;
+      if constexpr (PC >= 0) {
+        const T zv = (PC == 1) ? dinv[i] * rv : rv;
+        z[i] = zv;
+        rz += (ACC)rv * c * (ACC)zv;
+      }
+    }
+  }
+  ACC s0 = block_sum(rz, sred);
+  ACC s1 = block_sum(rr, sred);
+  if (threadIdx.x == 0) {
+    const int b = t.first / UPD_CHUNK;
+    P.part_u0[b] = (double)s0;
+    P.part_u1[b] = (double)s1;
+  }
+}
+
+// ------------------------------------------------------------ scalar stages
+// sum of parts[0..n) in a fixed order by one workgroup (256 threads)
+__device__ inline double fixed_sum(const double* __restrict__ parts, int n, double* sred) {
+  double s = 0.0;
+  for (int q = threadIdx.x; q < n; q += blockDim.x) s += parts[q];
+  return block_sum(s, sred);
+}
+
+// sigma = (p, A p)_c; alpha = rho / sigma; breakdown if sigma <= 0 or not finite
+__global__ void fin_sigma_kernel(const ProbDev* __restrict__ probs) {
+  __shared__ double sred[16];
+  const ProbDev& P = probs[blockIdx.x];
+  State* st = P.st;
+  if (st->done) return;
+  double a = fixed_sum(P.part_ax, P.nblk_ax, sred);
+  double g = fixed_sum(P.part_gs, P.nblk_gs, sred);
+  if (threadIdx.x == 0) {
+    const double sigma = a + g;
+    st->sigma = sigma;
+    if (!(sigma > 0.0) || !isfinite(sigma)) {
+      st->done = 1;
+      st->reason = MXSEM_BREAKDOWN;
+    } else {
+      st->alpha = st->rho / sigma;
+    }
+  }
+}
+
+// after the vector pass: convergence / max-iteration / stagnation tests,
+// beta = rho_new / rho.  With init != 0: the start of a solve.
+__global__ void fin_rho_kernel(const ProbDev* __restrict__ probs, int init) {
+  __shared__ double sred[16];
+  const ProbDev& P = probs[blockIdx.x];
+  State* st = P.st;
+  if (st->done) return;
+  double rz = fixed_sum(P.part_u0, P.nblk_upd, sred);
+  double rr = fixed_sum(P.part_u1, P.nblk_upd, sred);
+  if (threadIdx.x != 0) return;
+  st->rr = rr;
+  if (init) {
+    st->bb = rr;
+    st->rho = rz;
+    st->beta = 0.0;
+    st->iter = 0;
+    st->since = 0;
+    st->best = 1.0;
+    st->res = rr > 0.0 ? 1.0 : 0.0;
+    if (st->history) st->history[0] = st->res;
+    if (!(rr > 0.0)) {
+      st->done = 1;
+      st->reason = MXSEM_CONVERGED;
+    }
+    return;
+  }
+  const int it = st->iter + 1;
+  st->iter = it;
+  const double res = sqrt(rr / st->bb);
+  st->res = res;
+  if (st->history) st->history[it] = res;
+  if (rr <= st->tol2 * st->bb) {
+    st->done = 1;
+    st->reason = MXSEM_CONVERGED;
+    return;
+  }
+  if (!isfinite(rr)) {
+    st->done = 1;
+    st->reason = MXSEM_BREAKDOWN;
+    return;
+  }
+  if (it >= st->maxit) {
+    st->done = 1;
+    st->reason = MXSEM_MAX_ITER;
+    return;
+  }
+  if (res < 0.9 * st->best) {
+    st->best = res;
+    st->since = 0;
+  } else if (++st->since >= 50) {
+    st->done = 1;
+    st->reason = MXSEM_STAGNATED;
+    return;
+  }
+  st->beta = rz / st->rho;
+  st->rho = rz;
+}
+
+// ------------------------------------------------------------ API kernels
+template <typename T>
+__global__ void dot_kernel(const T* __restrict__ a, const T* __restrict__ b,
+                           const uint8_t* __restrict__ mult, int64_t n, double* __restrict__ part) {
+  __shared__ double sred[16];
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < UPD_PER_THREAD; ++q) {
+    const int64_t i = (int64_t)blockIdx.x * UPD_CHUNK + q * UPD_THREADS + threadIdx.x;
+    if (i < n) s += (double)a[i] * cweight(mult[i]) * (double)b[i];
+  }
+  double t = block_sum(s, sred);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void final_sum_kernel(const double* __restrict__ part, int n, double* __restrict__ out) {
+  __shared__ double sred[16];
+  double s = fixed_sum(part, n, sred);
+  if (threadIdx.x == 0) *out = s;
+}
+
+template <typename T>
+__global__ void precond_kernel(const T* __restrict__ r, T* __restrict__ z,
+                               const T* __restrict__ dinv, const int* __restrict__ mask_idx,
+                               int64_t n, int pc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = pc == 1 ? dinv[i] * r[i] : r[i];
+  (void)mask_idx;
+}
+
+// r64 = b - w64, partial (r,r)_c
+__global__ void residual_kernel(const double* __restrict__ b, const double* __restrict__ w,
+                                double* __restrict__ r, const uint8_t* __restrict__ mult,
+                                int64_t n, double* __restrict__ part) {
+  __shared__ double sred[16];
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < UPD_PER_THREAD; ++q) {
+    const int64_t i = (int64_t)blockIdx.x * UPD_CHUNK + q * UPD_THREADS + threadIdx.x;
+    if (i < n) {
+      const double v = b[i] - w[i];
+      r[i] = v;
+      s += v * cweight(mult[i]) * v;
+    }
+  }
+  double t = block_sum(s, sred);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// x64 = x64 * keep + s * (double) xT
+template <typename T>
+__global__ void axpy_cast_kernel(double* __restrict__ x64, const T* __restrict__ xT, double s,
+                                 double keep, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x64[i] = (keep == 0.0 ? 0.0 : keep * x64[i]) + s * (double)xT[i];
+}
+
+__global__ void zero_kernel(double* __restrict__ x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0.0;
+}
+
+__global__ void mass_kernel(const double* __restrict__ B, const double* __restrict__ f,
+                            double* __restrict__ b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = B[i] * f[i];
+}
+
+template <typename TD, typename TS>
+__global__ void cast_kernel(TD* __restrict__ d, const TS* __restrict__ s, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = (TD)s[i];
+}
+
+__global__ void cast_bf16_kernel(bf16_t* __restrict__ d, const double* __restrict__ s, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = float_to_bf16((float)s[i]);
+}
+
+__global__ void fill_state_kernel(State* __restrict__ st, int nprob, const State* __restrict__ tmpl) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nprob) st[i] = tmpl[i];
+}
+
+// ------------------------------------------------------------ host launchers
+static inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+hipError_t launch_gs_apply2(int prec_io, int prec_acc, void* v, const int* off, const int* idx,
+                            int ngroups_all, int nfree, int nmask_entries, int mask_first,
+                            bool mask, hipStream_t s) {
+  const int nsum = mask ? nfree : ngroups_all;
+  const int nm = mask ? nmask_entries : 0;
+  const int items = nsum + nm;
+  if (items == 0) return hipSuccess;
+  dim3 g(nblk(items, 256)), b(256);
+  if (prec_io == MXSEM_F64 && prec_acc == MXSEM_F64)
+    hipLaunchKernelGGL((gs_apply_kernel<double, double>), g, b, 0, s, (double*)v, off, idx, nsum,
+                       nfree, nm, mask_first);
+  else if (prec_io == MXSEM_F64 && prec_acc == MXSEM_F32)
+    hipLaunchKernelGGL((gs_apply_kernel<double, float>), g, b, 0, s, (double*)v, off, idx, nsum,
+                       nfree, nm, mask_first);
+  else if (prec_io == MXSEM_F32 && prec_acc == MXSEM_F64)
+    hipLaunchKernelGGL((gs_apply_kernel<float, double>), g, b, 0, s, (float*)v, off, idx, nsum,
+                       nfree, nm, mask_first);
+  else if (prec_io == MXSEM_F32 && prec_acc == MXSEM_F32)
+    hipLaunchKernelGGL((gs_apply_kernel<float, float>), g, b, 0, s, (float*)v, off, idx, nsum,
+                       nfree, nm, mask_first);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// vector precision: 0 FP64, 1 FP32 (FP64 accumulation), 3 FP32 (FP32 accumulation)
+hipError_t launch_gs_solver(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs,
+                            hipStream_t s) {
+  if (ntiles == 0) return hipSuccess;
+  dim3 g(ntiles), b(GS_CHUNK);
+  if (vprec == 0)
+    hipLaunchKernelGGL((gs_solver_kernel<double, double>), g, b, 0, s, tiles, probs);
+  else if (vprec == 1)
+    hipLaunchKernelGGL((gs_solver_kernel<float, double>), g, b, 0, s, tiles, probs);
+  else
+    hipLaunchKernelGGL((gs_solver_kernel<float, float>), g, b, 0, s, tiles, probs);
+  return hipGetLastError();
+}
+
+template <typename T, typename ACC>
+static void upd_dispatch(int pc, dim3 g, dim3 b, hipStream_t s, const Tile* tiles,
+                         const ProbDev* probs) {
+  if (pc == MXSEM_PC_JACOBI)
+    hipLaunchKernelGGL((update_kernel<T, ACC, 1>), g, b, 0, s, tiles, probs);
+  else if (pc == MXSEM_PC_IDENTITY)
+    hipLaunchKernelGGL((update_kernel<T, ACC, 0>), g, b, 0, s, tiles, probs);
+  else
+    hipLaunchKernelGGL((update_kernel<T, ACC, -1>), g, b, 0, s, tiles, probs);
+}
+
+hipError_t launch_update(int vprec, int pc, const Tile* tiles, int ntiles, const ProbDev* probs,
+                         hipStream_t s) {
+  dim3 g(ntiles), b(UPD_THREADS);
+  if (vprec == 0) upd_dispatch<double, double>(pc, g, b, s, tiles, probs);
+  else if (vprec == 1) upd_dispatch<float, double>(pc, g, b, s, tiles, probs);
+  else upd_dispatch<float, float>(pc, g, b, s, tiles, probs);
+  return hipGetLastError();
+}
+
+template <typename T, typename ACC>
+static void init_dispatch(int pc, dim3 g, dim3 b, hipStream_t s, const Tile* tiles,
+                          const ProbDev* probs, const double* x0) {
+  if (pc == MXSEM_PC_JACOBI)
+    hipLaunchKernelGGL((init_kernel<T, ACC, 1>), g, b, 0, s, tiles, probs, x0);
+  else if (pc == MXSEM_PC_IDENTITY)
+    hipLaunchKernelGGL((init_kernel<T, ACC, 0>), g, b, 0, s, tiles, probs, x0);
+  else
+    hipLaunchKernelGGL((init_kernel<T, ACC, -1>), g, b, 0, s, tiles, probs, x0);
+}
+
+hipError_t launch_init(int vprec, int pc, const Tile* tiles, int ntiles, const ProbDev* probs,
+                       const double* x0, hipStream_t s) {
+  dim3 g(ntiles), b(UPD_THREADS);
+  if (vprec == 0) init_dispatch<double, double>(pc, g, b, s, tiles, probs, x0);
+  else if (vprec == 1) init_dispatch<float, double>(pc, g, b, s, tiles, probs, x0);
+  else init_dispatch<float, float>(pc, g, b, s, tiles, probs, x0);
+  return hipGetLastError();
+}
+
+hipError_t launch_fin_sigma(const ProbDev* probs, int nprob, hipStream_t s) {
+  hipLaunchKernelGGL(fin_sigma_kernel, dim3(nprob), dim3(256), 0, s, probs);
+  return hipGetLastError();
+}
+
+hipError_t launch_fin_rho(const ProbDev* probs, int nprob, int init, hipStream_t s) {
+  hipLaunchKernelGGL(fin_rho_kernel, dim3(nprob), dim3(256), 0, s, probs, init);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot(int prec, const void* a, const void* b, const uint8_t* mult, int64_t n,
+                      double* part, double* out, hipStream_t s) {
+  const unsigned nb = nblk(n, UPD_CHUNK);
+  if (prec == MXSEM_F64)
+    hipLaunchKernelGGL((dot_kernel<double>), dim3(nb), dim3(UPD_THREADS), 0, s, (const double*)a,
+                       (const double*)b, mult, n, part);
+  else
+    hipLaunchKernelGGL((dot_kernel<float>), dim3(nb), dim3(UPD_THREADS), 0, s, (const float*)a,
+                       (const float*)b, mult, n, part);
+  hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(256), 0, s, part, (int)nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_precond(int prec, int pc, const void* r, void* z, const void* dinv, int64_t n,
+                          hipStream_t s) {
+  const unsigned nb = nblk(n, 256);
+  if (prec == MXSEM_F64)
+    hipLaunchKernelGGL((precond_kernel<double>), dim3(nb), dim3(256), 0, s, (const double*)r,
+                       (double*)z, (const double*)dinv, nullptr, n, pc);
+  else
+    hipLaunchKernelGGL((precond_kernel<float>), dim3(nb), dim3(256), 0, s, (const float*)r,
+                       (float*)z, (const float*)dinv, nullptr, n, pc);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(const double* b, const double* w, double* r, const uint8_t* mult,
+                           int64_t n, double* part, double* out, hipStream_t s) {
+  const unsigned nb = nblk(n, UPD_CHUNK);
+  hipLaunchKernelGGL(residual_kernel, dim3(nb), dim3(UPD_THREADS), 0, s, b, w, r, mult, n, part);
+  hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(256), 0, s, part, (int)nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_cast(int vprec, double* x64, const void* xT, double sc, double keep,
+                            int64_t n, hipStream_t s) {
+  const unsigned nb = nblk(n, 256);
+  if (vprec == 0)
+    hipLaunchKernelGGL((axpy_cast_kernel<double>), dim3(nb), dim3(256), 0, s, x64,
+                       (const double*)xT, sc, keep, n);
+  else
+    hipLaunchKernelGGL((axpy_cast_kernel<float>), dim3(nb), dim3(256), 0, s, x64,
+                       (const float*)xT, sc, keep, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(double* x, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(zero_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, x, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_mass(const double* B, const double* f, double* b, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(mass_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, B, f, b, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_f32(float* d, const double* src, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL((cast_kernel<float, double>), dim3(nblk(n, 256)), dim3(256), 0, s, d, src, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_bf16(bf16_t* d, const double* src, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(cast_bf16_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, d, src, n);
+  return hipGetLastError();
+}
+
+}  // namespace mx

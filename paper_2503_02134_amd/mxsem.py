@@ -1,0 +1,422 @@
+"""ctypes binding of libmxsem.so (the C ABI in include/mxsem.h).
+
+Argument marshalling only: every numerical step runs in the HIP kernels of
+the library.  Device vectors are torch tensors on the context's device;
+their data pointers are passed through unchanged.  If the library is not
+built or cannot be loaded, every call raises: there is no CPU fallback.
+
+torch is imported before the library is loaded so that the library binds
+to the HIP runtime torch already holds (one runtime per process).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch  # noqa: F401  (must precede loading the HIP library)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmxsem.so")
+
+# status codes
+OK, EINVAL, ENOTSUP, EHIP, EBREAKDOWN, EINTERNAL, ENOMEM, EMESH = 0, -1, -2, -3, -4, -5, -6, -7
+# precisions
+F64, F32, BF16G_F32 = 0, 1, 2
+# preconditioners
+PC_IDENTITY, PC_JACOBI, PC_LEARNED = 0, 1, 2
+# modes
+MODE_FP64, MODE_MIXED, MODE_MIXED_IR, MODE_MIXED_IR_BF16G, MODE_FP32_ALL = 0, 1, 2, 3, 4
+METHOD_PCG, METHOD_FCG = 0, 1
+CONVERGED, MAX_ITER, STAGNATED, BREAKDOWN = 1, 2, 3, 4
+LOCAL_ONLY, MASK = 1, 2
+VIEW_F64, VIEW_F32, VIEW_BF16 = 1, 2, 4
+
+MODE_NAMES = {MODE_FP64: "fp64", MODE_MIXED: "mixed", MODE_MIXED_IR: "mixed_ir",
+              MODE_MIXED_IR_BF16G: "mixed_ir_bf16g", MODE_FP32_ALL: "fp32_all"}
+
+
+class MxsemError(RuntimeError):
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__(f"{fn} failed with status {code}: {msg}")
+        self.code = code
+
+
+class mxsem_mesh_desc(C.Structure):
+    _fields_ = [("E", C.c_int), ("N", C.c_int), ("xyz", C.c_void_p), ("glo", C.c_void_p),
+                ("bnd", C.c_void_p), ("kcoef", C.c_void_p), ("helm_h", C.c_double),
+                ("views", C.c_uint)]
+
+
+class mxsem_solve_opts(C.Structure):
+    _fields_ = [("method", C.c_int), ("pc", C.c_int), ("mode", C.c_int), ("tol", C.c_double),
+                ("max_iter", C.c_int), ("inner_tol", C.c_double), ("max_outer", C.c_int),
+                ("graph_chunk", C.c_int), ("x0_given", C.c_int), ("history", C.c_void_p)]
+
+
+class mxsem_solve_stats(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("outer", C.c_int), ("reason", C.c_int),
+                ("fallback_used", C.c_int), ("rel_res", C.c_double),
+                ("rel_res_recursive", C.c_double), ("ms", C.c_double), ("ax_ms", C.c_double),
+                ("ax_samples", C.c_int), ("pad_", C.c_int)]
+
+
+class mxsem_tuning(C.Structure):
+    _fields_ = [("epb", C.c_int * 16)]
+
+
+class mxsem_nn_desc(C.Structure):
+    _fields_ = [("cin", C.c_int), ("ch", C.c_int)]
+
+
+class mxsem_adam(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("eps", C.c_double), ("step", C.c_int)]
+
+
+_lib = None
+vp = C.c_void_p
+_SIGS = {
+    "mxsem_ctx_create": [C.c_int, vp, C.POINTER(vp)],
+    "mxsem_ctx_destroy": [vp],
+    "mxsem_ctx_set_stream": [vp, vp],
+    "mxsem_gll": [C.c_int, vp, vp],
+    "mxsem_mesh_create": [vp, C.POINTER(mxsem_mesh_desc), C.POINTER(vp)],
+    "mxsem_mesh_destroy": [vp],
+    "mxsem_mesh_info": [vp, vp, vp, vp, vp],
+    "mxsem_mesh_get": [vp, C.c_int, vp],
+    "mxsem_apply": [vp, C.c_int, vp, vp, C.c_uint],
+    "mxsem_gather_scatter": [vp, C.c_int, C.c_int, vp, C.c_uint],
+    "mxsem_dot": [vp, C.c_int, vp, vp, vp],
+    "mxsem_precond": [vp, C.c_int, C.c_int, vp, vp],
+    "mxsem_mass_rhs": [vp, vp, vp],
+    "mxsem_solve": [vp, C.POINTER(mxsem_solve_opts), vp, vp, C.POINTER(mxsem_solve_stats)],
+    "mxsem_batch_create": [vp, C.c_int, vp, C.c_char_p, C.POINTER(vp)],
+    "mxsem_batch_destroy": [vp],
+    "mxsem_batch_solve": [vp, C.POINTER(mxsem_solve_opts), vp, vp, vp],
+    "mxsem_autotune": [vp, C.c_int, C.c_int, C.c_int, C.POINTER(mxsem_tuning)],
+    "mxsem_mesh_set_tuning": [vp, C.POINTER(mxsem_tuning)],
+    "mxsem_nn_create": [vp, C.POINTER(mxsem_nn_desc), C.POINTER(vp)],
+    "mxsem_nn_destroy": [vp],
+    "mxsem_nn_set_params": [vp, vp, vp],
+    "mxsem_nn_get_params": [vp, vp, vp],
+    "mxsem_nn_forward": [vp, vp, vp],
+    "mxsem_nn_loss_grad": [vp, vp, vp, C.c_int, vp, vp],
+    "mxsem_nn_adam_step": [vp, C.POINTER(mxsem_adam)],
+    "mxsem_mesh_attach_nn": [vp, vp],
+    "mxsem_version": [],
+}
+
+
+def lib():
+    """Load libmxsem.so (raises if it is not built: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                           "python paper_2503_02134_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    for name, args in _SIGS.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    L.mxsem_status_str.argtypes = [C.c_int]
+    L.mxsem_status_str.restype = C.c_char_p
+    L.mxsem_last_error.argtypes = []
+    L.mxsem_last_error.restype = C.c_char_p
+    L.mxsem_solve_opts_default.argtypes = [C.POINTER(mxsem_solve_opts)]
+    L.mxsem_solve_opts_default.restype = None
+    _lib = L
+    return L
+
+
+def _check(fn: str, rc: int):
+    if rc != OK:
+        msg = lib().mxsem_last_error().decode(errors="replace")
+        raise MxsemError(fn, rc, msg)
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA/HIP tensors"
+        return t.data_ptr()
+    if isinstance(t, np.ndarray):
+        assert t.flags.c_contiguous
+        return t.ctypes.data
+    return int(t)
+
+
+# ---------------------------------------------------------------- C ABI, one to one
+def mxsem_ctx_create(device: int = 0, stream=None):
+    h = vp()
+    s = torch.cuda.current_stream(device).cuda_stream if stream is None else stream
+    _check("mxsem_ctx_create", lib().mxsem_ctx_create(device, s, C.byref(h)))
+    return h
+
+
+def mxsem_ctx_destroy(ctx):
+    _check("mxsem_ctx_destroy", lib().mxsem_ctx_destroy(ctx))
+
+
+def mxsem_gll(N: int):
+    xi = np.zeros(N + 1)
+    w = np.zeros(N + 1)
+    _check("mxsem_gll", lib().mxsem_gll(N, xi.ctypes.data, w.ctypes.data))
+    return xi, w
+
+
+def mxsem_mesh_create(ctx, E, N, xyz, glo, bnd, kcoef=None, helm_h=0.0,
+                      views=VIEW_F64 | VIEW_F32 | VIEW_BF16):
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    glo = np.ascontiguousarray(glo, dtype=np.int64)
+    bnd = np.ascontiguousarray(bnd, dtype=np.uint8)
+    kk = None if kcoef is None else np.ascontiguousarray(kcoef, dtype=np.float64)
+    n3 = (N + 1) ** 3
+    assert xyz.size == 3 * E * n3 and glo.size == E * n3 and bnd.size == E * n3
+    d = mxsem_mesh_desc(E, N, xyz.ctypes.data, glo.ctypes.data, bnd.ctypes.data,
+                        None if kk is None else kk.ctypes.data, float(helm_h), views)
+    h = vp()
+    _check("mxsem_mesh_create", lib().mxsem_mesh_create(ctx, C.byref(d), C.byref(h)))
+    return h
+
+
+def mxsem_mesh_destroy(mesh):
+    _check("mxsem_mesh_destroy", lib().mxsem_mesh_destroy(mesh))
+
+
+def mxsem_mesh_info(mesh):
+    a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+    d = C.c_double()
+    _check("mxsem_mesh_info", lib().mxsem_mesh_info(mesh, C.byref(a), C.byref(b), C.byref(c),
+                                                     C.byref(d)))
+    return a.value, b.value, c.value, d.value
+
+
+def mxsem_mesh_get(mesh, what: int, size: int) -> np.ndarray:
+    out = np.zeros(size)
+    _check("mxsem_mesh_get", lib().mxsem_mesh_get(mesh, what, out.ctypes.data))
+    return out
+
+
+def mxsem_apply(mesh, prec, u, w, flags=0):
+    _check("mxsem_apply", lib().mxsem_apply(mesh, prec, _ptr(u), _ptr(w), flags))
+
+
+def mxsem_gather_scatter(mesh, io, acc, v, flags=0):
+    _check("mxsem_gather_scatter", lib().mxsem_gather_scatter(mesh, io, acc, _ptr(v), flags))
+
+
+def mxsem_dot(mesh, io, a, b, out_dev):
+    _check("mxsem_dot", lib().mxsem_dot(mesh, io, _ptr(a), _ptr(b), _ptr(out_dev)))
+
+
+def mxsem_precond(mesh, pc, io, r, z):
+    _check("mxsem_precond", lib().mxsem_precond(mesh, pc, io, _ptr(r), _ptr(z)))
+
+
+def mxsem_mass_rhs(mesh, f, b):
+    _check("mxsem_mass_rhs", lib().mxsem_mass_rhs(mesh, _ptr(f), _ptr(b)))
+
+
+def solve_opts(**kw) -> mxsem_solve_opts:
+    o = mxsem_solve_opts()
+    lib().mxsem_solve_opts_default(C.byref(o))
+    for k, v in kw.items():
+        if k == "history":
+            v = _ptr(v)
+        setattr(o, k, v)
+    return o
+
+
+def mxsem_solve(mesh, opts: mxsem_solve_opts, b, x) -> mxsem_solve_stats:
+    st = mxsem_solve_stats()
+    rc = lib().mxsem_solve(mesh, C.byref(opts), _ptr(b), _ptr(x), C.byref(st))
+    if rc == EBREAKDOWN:
+        return st
+    _check("mxsem_solve", rc)
+    return st
+
+
+def mxsem_batch_create(ctx, meshes, tune_cache: str | None = None):
+    arr = (vp * len(meshes))(*[m.value if isinstance(m, vp) else m for m in meshes])
+    h = vp()
+    _check("mxsem_batch_create", lib().mxsem_batch_create(
+        ctx, len(meshes), C.cast(arr, vp), None if tune_cache is None else tune_cache.encode(),
+        C.byref(h)))
+    return h
+
+
+def mxsem_batch_destroy(batch):
+    _check("mxsem_batch_destroy", lib().mxsem_batch_destroy(batch))
+
+
+def mxsem_batch_solve(batch, opts, bs, xs):
+    P = len(bs)
+    barr = (vp * P)(*[_ptr(b) for b in bs])
+    xarr = (vp * P)(*[_ptr(x) for x in xs])
+    st = (mxsem_solve_stats * P)()
+    rc = lib().mxsem_batch_solve(batch, C.byref(opts), C.cast(barr, vp), C.cast(xarr, vp),
+                                 C.cast(st, vp))
+    if rc != EBREAKDOWN:
+        _check("mxsem_batch_solve", rc)
+    return list(st)
+
+
+def mxsem_autotune(ctx, N, E, prec) -> int:
+    t = mxsem_tuning()
+    _check("mxsem_autotune", lib().mxsem_autotune(ctx, N, E, prec, C.byref(t)))
+    return t.epb[N]
+
+
+def mxsem_mesh_set_tuning(mesh, epb_by_N: dict):
+    t = mxsem_tuning()
+    for N, e in epb_by_N.items():
+        t.epb[N] = e
+    _check("mxsem_mesh_set_tuning", lib().mxsem_mesh_set_tuning(mesh, C.byref(t)))
+
+
+def mxsem_nn_create(mesh, ch=32, cin=2):
+    d = mxsem_nn_desc(cin, ch)
+    h = vp()
+    _check("mxsem_nn_create", lib().mxsem_nn_create(mesh, C.byref(d), C.byref(h)))
+    return h
+
+
+def mxsem_nn_destroy(nn):
+    _check("mxsem_nn_destroy", lib().mxsem_nn_destroy(nn))
+
+
+def mxsem_nn_set_params(nn, W1, W2):
+    W1 = np.ascontiguousarray(W1, dtype=np.float32)
+    W2 = np.ascontiguousarray(W2, dtype=np.float32)
+    _check("mxsem_nn_set_params", lib().mxsem_nn_set_params(nn, W1.ctypes.data, W2.ctypes.data))
+
+
+def mxsem_nn_get_params(nn, ch=32, cin=2):
+    W1 = np.zeros((ch, cin, 27), dtype=np.float32)
+    W2 = np.zeros((ch, 27), dtype=np.float32)
+    _check("mxsem_nn_get_params", lib().mxsem_nn_get_params(nn, W1.ctypes.data, W2.ctypes.data))
+    return W1, W2
+
+
+def mxsem_nn_forward(nn, r, z):
+    _check("mxsem_nn_forward", lib().mxsem_nn_forward(nn, _ptr(r), _ptr(z)))
+
+
+def mxsem_nn_loss_grad(nn, r, e, nsamp, loss_dev, grad_dev):
+    _check("mxsem_nn_loss_grad", lib().mxsem_nn_loss_grad(nn, _ptr(r), _ptr(e), nsamp,
+                                                           _ptr(loss_dev), _ptr(grad_dev)))
+
+
+def mxsem_nn_adam_step(nn, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, step=1):
+    a = mxsem_adam(lr, beta1, beta2, eps, step)
+    _check("mxsem_nn_adam_step", lib().mxsem_nn_adam_step(nn, C.byref(a)))
+
+
+def mxsem_mesh_attach_nn(mesh, nn):
+    _check("mxsem_mesh_attach_nn", lib().mxsem_mesh_attach_nn(mesh, nn))
+
+
+# ---------------------------------------------------------------- convenience
+@dataclass
+class Stats:
+    iterations: int
+    outer: int
+    reason: int
+    fallback_used: int
+    rel_res: float
+    rel_res_recursive: float
+    ms: float
+    ax_ms: float
+    ax_samples: int
+
+    @staticmethod
+    def of(st: mxsem_solve_stats) -> "Stats":
+        return Stats(st.iterations, st.outer, st.reason, st.fallback_used, st.rel_res,
+                     st.rel_res_recursive, st.ms, st.ax_ms, st.ax_samples)
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self.device = device
+        self.h = mxsem_ctx_create(device)
+
+    def close(self):
+        if self.h is not None:
+            mxsem_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mesh:
+    """Device mesh built from host arrays (box-mesh generator output)."""
+
+    def __init__(self, ctx: Context, E, N, xyz, glo, bnd, kcoef=None, helm_h=0.0,
+                 views=VIEW_F64 | VIEW_F32 | VIEW_BF16):
+        self.ctx = ctx
+        self.E, self.N, self.n = int(E), int(N), int(N) + 1
+        self.nloc = self.E * self.n ** 3
+        self.h = mxsem_mesh_create(ctx.h, E, N, xyz, glo, bnd, kcoef, helm_h, views)
+        self.dev = torch.device("cuda", ctx.device)
+
+    def close(self):
+        if self.h is not None:
+            mxsem_mesh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        return mxsem_mesh_info(self.h)
+
+    def get(self, what: int):
+        size = {0: 6 * self.nloc, 5: self.n * self.n}.get(what, self.nloc)
+        return mxsem_mesh_get(self.h, what, size)
+
+    def vec(self, dtype=torch.float64):
+        return torch.zeros(self.nloc, dtype=dtype, device=self.dev)
+
+    def apply(self, u, prec=F64, local_only=False):
+        w = torch.empty_like(u)
+        mxsem_apply(self.h, prec, u, w, LOCAL_ONLY if local_only else 0)
+        return w
+
+    def gs(self, v, acc=F64, mask=False):
+        v = v.clone()
+        io = F64 if v.dtype == torch.float64 else F32
+        mxsem_gather_scatter(self.h, io, acc, v, MASK if mask else 0)
+        return v
+
+    def dot(self, a, b) -> float:
+        out = torch.zeros(1, dtype=torch.float64, device=self.dev)
+        mxsem_dot(self.h, F64 if a.dtype == torch.float64 else F32, a, b, out)
+        return float(out.item())
+
+    def precond(self, r, pc=PC_JACOBI):
+        z = torch.empty_like(r)
+        mxsem_precond(self.h, pc, F64 if r.dtype == torch.float64 else F32, r, z)
+        return z
+
+    def mass_rhs(self, f):
+        b = torch.empty_like(f)
+        mxsem_mass_rhs(self.h, f, b)
+        return b
+
+    def solve(self, b, x=None, **kw):
+        if x is None:
+            x = torch.zeros_like(b)
+        st = mxsem_solve(self.h, solve_opts(**kw), b, x)
+        return x, Stats.of(st)
