@@ -197,6 +197,7 @@ int mxsem_ctx_create(int hip_device, void* hip_stream, mxsem_ctx** out) {
 
 int mxsem_ctx_destroy(mxsem_ctx* c) {
   if (!c) return MXSEM_OK;
+  MX_CHECK(c->live == 0, MXSEM_EINVAL, "ctx_destroy: meshes or batches of this context are alive");
   hipSetDevice(c->device);
   if (c->stream) hipStreamSynchronize(c->stream);
   else hipDeviceSynchronize();
@@ -234,6 +235,7 @@ int mxsem_mesh_destroy(mxsem_mesh* m) {
       delete m->bufs[q];
     }
   for (void* p : m->allocs) hipFree(p);
+  if (m->counted) m->ctx->live -= 1;
   delete m;
   return MXSEM_OK;
 }
@@ -451,6 +453,8 @@ int mxsem_mesh_create(mxsem_ctx* ctx, const mxsem_mesh_desc* d, mxsem_mesh** out
     m->allocs.erase(std::find(m->allocs.begin(), m->allocs.end(), p));
   }
   for (int q = 0; q < 16; ++q) m->epb[q] = 0;
+  ctx->live += 1;
+  m->counted = true;
   *out = m;
   return MXSEM_OK;
 }

@@ -11,6 +11,7 @@ struct mxsem_ctx {
   hipStream_t capture = nullptr;  // private stream used only for graph capture
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int* pinned_flags = nullptr;    // host-pinned poll buffer
+  int live = 0;                   // meshes / batches created from this context
 };
 
 namespace mx {
@@ -116,6 +117,7 @@ struct mxsem_mesh {
   mx::SolverBufs* bufs[4] = {nullptr, nullptr, nullptr, nullptr};
   mxsem_nn* nn = nullptr;
   std::vector<void*> allocs;
+  bool counted = false;
 };
 
 namespace mx {

@@ -10,8 +10,10 @@ to the HIP runtime torch already holds (one runtime per process).
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -340,19 +342,46 @@ class Stats:
                      st.rel_res_recursive, st.ms, st.ax_ms, st.ax_samples)
 
 
+_live_contexts: "weakref.WeakSet[Context]" = weakref.WeakSet()
+
+
 class Context:
+    """One device + the torch stream current at creation.  Closing it first
+    closes every mesh / batch / network created from it."""
+
     def __init__(self, device: int = 0):
         self.device = device
         self.h = mxsem_ctx_create(device)
+        self.children: list = []
+        _live_contexts.add(self)
+
+    def _adopt(self, obj):
+        self.children.append(weakref.ref(obj))
 
     def close(self):
-        if self.h is not None:
-            mxsem_ctx_destroy(self.h)
-            self.h = None
+        if self.h is None:
+            return
+        for ref in reversed(self.children):
+            obj = ref()
+            if obj is not None:
+                obj.close()
+        self.children = []
+        torch.cuda.synchronize(self.device)
+        mxsem_ctx_destroy(self.h)
+        self.h = None
 
     def __del__(self):
         try:
             self.close()
+        except Exception:
+            pass
+
+
+@atexit.register
+def _close_all():
+    for c in list(_live_contexts):
+        try:
+            c.close()
         except Exception:
             pass
 
@@ -367,6 +396,7 @@ class Mesh:
         self.nloc = self.E * self.n ** 3
         self.h = mxsem_mesh_create(ctx.h, E, N, xyz, glo, bnd, kcoef, helm_h, views)
         self.dev = torch.device("cuda", ctx.device)
+        ctx._adopt(self)
 
     def close(self):
         if self.h is not None:

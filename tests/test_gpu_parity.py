@@ -46,7 +46,7 @@ def test_mesh_setup_matches_oracle(orc, mx, ctx, ne, N, seed, kseed, hh):
     np.testing.assert_array_equal(gm.get(2), om.c)
     np.testing.assert_allclose(gm.get(3), om.dinv, rtol=1e-11)
     np.testing.assert_array_equal(gm.get(4).astype(bool), om.mask)
-    np.testing.assert_allclose(gm.get(5), om.D, atol=1e-12 * N * N)
+    np.testing.assert_allclose(gm.get(5).reshape(N + 1, N + 1), om.D, atol=1e-12 * N * N)
     nloc, ngroups, nmasked, mindet = gm.info()
     assert nloc == om.nloc and mindet > 0 and abs(mindet - om.mindet) < 1e-12 * om.mindet
 
