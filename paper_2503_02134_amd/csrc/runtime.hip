@@ -278,6 +278,7 @@ int mxsem_mesh_create(mxsem_ctx* ctx, const mxsem_mesh_desc* d, mxsem_mesh** out
   MX_CHECK(nloc < (int64_t)INT32_MAX - UPD_CHUNK, MXSEM_ENOTSUP,
            "mesh_create: more than 2^31 local entries");
   MX_HIP(hipSetDevice(ctx->device));
+  (void)hipGetLastError();
   mxsem_mesh* m = new (std::nothrow) mxsem_mesh();
   MX_CHECK(m, MXSEM_ENOMEM, "mesh_create: host allocation failed");
   m->ctx = ctx;
@@ -473,6 +474,7 @@ int mxsem_mesh_get(const mxsem_mesh* m, int what, double* out) {
   MX_CHECK(m && out, MXSEM_EINVAL, "mesh_get: null argument");
   hipStream_t s = m->ctx->stream;
   MX_HIP(hipSetDevice(m->ctx->device));
+  (void)hipGetLastError();
   switch (what) {
     case 0: MX_HIP(hipMemcpyAsync(out, m->G64, sizeof(double) * 6 * m->nloc, hipMemcpyDeviceToHost, s)); break;
     case 1: MX_HIP(hipMemcpyAsync(out, m->B64, sizeof(double) * m->nloc, hipMemcpyDeviceToHost, s)); break;
@@ -513,6 +515,7 @@ int mxsem_apply(mxsem_mesh* m, mxsem_prec io, const void* u, void* w, unsigned f
   MX_CHECK(u != w, MXSEM_EINVAL, "apply: u and w must not alias");
   MX_TRY(check_prec_view(m, io));
   MX_HIP(hipSetDevice(m->ctx->device));
+  (void)hipGetLastError();
   return apply_impl(m, io, u, w, flags, m->ctx->stream);
 }
 
@@ -521,6 +524,7 @@ int mxsem_gather_scatter(mxsem_mesh* m, mxsem_prec io, mxsem_prec acc, void* v, 
   MX_CHECK(io == MXSEM_F64 || io == MXSEM_F32, MXSEM_EINVAL, "gather_scatter: io must be F64/F32");
   MX_CHECK(acc == MXSEM_F64 || acc == MXSEM_F32, MXSEM_EINVAL, "gather_scatter: acc must be F64/F32");
   MX_HIP(hipSetDevice(m->ctx->device));
+  (void)hipGetLastError();
   MX_HIP(launch_gs_apply2(io, acc, v, m->gs_off, m->gs_idx, m->ngroups_all, m->nfree,
                           m->nmask_entries, m->mask_first, (flags & MXSEM_MASK) != 0,
                           m->ctx->stream));
@@ -531,6 +535,7 @@ int mxsem_dot(mxsem_mesh* m, mxsem_prec io, const void* a, const void* b, double
   MX_CHECK(m && a && b && out_dev, MXSEM_EINVAL, "dot: null argument");
   MX_CHECK(io == MXSEM_F64 || io == MXSEM_F32, MXSEM_EINVAL, "dot: io must be F64/F32");
   MX_HIP(hipSetDevice(m->ctx->device));
+  (void)hipGetLastError();
   MX_HIP(launch_dot(io, a, b, m->mult, m->nloc, m->part, out_dev, m->ctx->stream));
   return MXSEM_OK;
 }
@@ -538,6 +543,7 @@ int mxsem_dot(mxsem_mesh* m, mxsem_prec io, const void* a, const void* b, double
 int mxsem_mass_rhs(mxsem_mesh* m, const double* f, double* b) {
   MX_CHECK(m && f && b, MXSEM_EINVAL, "mass_rhs: null argument");
   MX_HIP(hipSetDevice(m->ctx->device));
+  (void)hipGetLastError();
   hipStream_t s = m->ctx->stream;
   MX_HIP(launch_mass(m->B64, f, b, m->nloc, s));
   MX_HIP(launch_gs_apply2(MXSEM_F64, MXSEM_F64, b, m->gs_off, m->gs_idx, m->ngroups_all, m->nfree,

