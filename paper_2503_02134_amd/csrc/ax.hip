@@ -30,7 +30,7 @@ struct AxApplyArgs {
 // written back), w = A_L p, and the partial sum of p.w over element-interior
 // nodes (never shared, never Dirichlet, so c = 1 and w is already final).
 template <int N, typename T, typename TG, bool SOLVER>
-__global__ void ax_kernel(const Tile* __restrict__ tiles, const ProbDev* __restrict__ probs,
+__global__ void __launch_bounds__(256) ax_kernel(const Tile* __restrict__ tiles, const ProbDev* __restrict__ probs,
                           AxApplyArgs apply, int epb) {
   constexpr int n = N + 1, n2 = n * n, n3 = n2 * n;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -171,6 +171,7 @@ static hipError_t launch_one(const Tile* tiles, const ProbDev* probs, const AxAp
                              int ntiles, int epb, hipStream_t s) {
   constexpr int n = N + 1, n2 = n * n;
   int threads = ((epb * n2 + 63) / 64) * 64;
+  if (epb < 1 || threads > 256) return hipErrorInvalidConfiguration;
   size_t shm = sizeof(T) * (n2 + (size_t)epb * 3 * n2);
   hipLaunchKernelGGL((ax_kernel<N, T, TG, SOLVER>), dim3(ntiles), dim3(threads), shm, s, tiles,
                      probs, a, epb);
@@ -216,7 +217,12 @@ hipError_t launch_ax_solver(int prec, int N, const Tile* tiles, int ntiles, cons
   }
 }
 
-// largest epb whose workgroup fits 1024 threads
-int max_epb(int N) { return 1024 / ((N + 1) * (N + 1)); }
+// largest epb whose workgroup (rounded to wave64s) fits 256 threads
+int max_epb(int N) {
+  const int n2 = (N + 1) * (N + 1);
+  int e = 1;
+  while ((((e + 1) * n2 + 63) / 64) * 64 <= 256) ++e;
+  return e;
+}
 
 }  // namespace mx

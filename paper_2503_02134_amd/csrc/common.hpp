@@ -138,10 +138,13 @@ struct ProbDev {
   State* st;
 };
 
-constexpr int GS_CHUNK = 256;    // gather-scatter items per workgroup
+constexpr int GS_THREADS = 256;  // gather-scatter workgroup
+constexpr int GS_PER_THREAD = 4;
+constexpr int GS_CHUNK = GS_THREADS * GS_PER_THREAD;  // items per workgroup
 constexpr int UPD_THREADS = 256; // threads per vector-update workgroup
-constexpr int UPD_PER_THREAD = 8;
+constexpr int UPD_PER_THREAD = 8;  // entries per thread (two 4-wide vectors)
 constexpr int UPD_CHUNK = UPD_THREADS * UPD_PER_THREAD;
+constexpr int FIN_THREADS = 1024;  // final-reduction workgroup
 constexpr int MAX_N = 15;
 
 // ---------------------------------------------------------------- reductions

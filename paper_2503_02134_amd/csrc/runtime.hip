@@ -99,18 +99,18 @@ int mesh_alloc(mxsem_mesh* m, void** p, size_t bytes) {
   return MXSEM_OK;
 }
 
-// Elements per workgroup of the operator kernel: the smallest count whose
-// workgroup (rounded up to whole wave64s) wastes under 5% of its lanes,
-// else the least wasteful up to 256 threads.
+// Elements per workgroup of the operator kernel (workgroups of at most 256
+// threads, rounded up to whole wave64s): the smallest count whose idle
+// lanes are under 5%, else the count with the fewest idle lanes.
 int default_epb(int N) {
   const int n2 = (N + 1) * (N + 1);
   int best = 1;
   double bestw = 1.0;
-  for (int e = 1; e * n2 <= 1024; ++e) {
+  for (int e = 1; ((e * n2 + 63) / 64) * 64 <= 256; ++e) {
     const int th = ((e * n2 + 63) / 64) * 64;
     const double waste = (double)(th - e * n2) / th;
     if (waste < 0.05) return e;
-    if (th <= 256 && waste < bestw) {
+    if (waste < bestw - 1e-12) {
       bestw = waste;
       best = e;
     }
@@ -384,7 +384,16 @@ int mxsem_mesh_create(mxsem_ctx* ctx, const mxsem_mesh_desc* d, mxsem_mesh** out
     Grp gr{sz, (int32_t)a, glo[order[a]]};
     (msk ? maskg : freeg).push_back(gr);
   }
-  std::stable_sort(freeg.begin(), freeg.end(), [](const Grp& x, const Grp& y) { return x.m < y.m; });
+  // groups of one multiplicity together (uniform trip counts per wave), and
+  // inside each in ascending first local index, so neighbouring threads
+  // touch neighbouring entries of the same elements
+  auto by_first = [&order](const Grp& x, const Grp& y) {
+    if (x.m != y.m) return x.m < y.m;
+    return order[x.first] < order[y.first];
+  };
+  std::sort(freeg.begin(), freeg.end(), by_first);
+  std::sort(maskg.begin(), maskg.end(),
+            [&order](const Grp& x, const Grp& y) { return order[x.first] < order[y.first]; });
   m->nfree = (int)freeg.size();
   m->ngroups_all = (int)(freeg.size() + maskg.size());
   std::vector<int32_t> off, idx;

@@ -124,6 +124,7 @@ namespace mx {
 int mesh_alloc(mxsem_mesh* m, void** p, size_t bytes);
 int default_epb(int N);
 int ensure_bufs(mxsem_mesh* m, int vprec, SolverBufs** out);
+int retile_ax(mxsem_mesh* m, SolverBufs* b);
 int ensure_tmp(mxsem_mesh* m);
 const void* G_ptr(const mxsem_mesh* m, int gprec);
 const void* hB_ptr(const mxsem_mesh* m, int gprec);

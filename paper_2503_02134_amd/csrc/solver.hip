@@ -36,10 +36,27 @@ static int gprec_of_mode(int mode) {
   }
 }
 
+// operator tiles for the mesh's current elements-per-workgroup choice
+int retile_ax(mxsem_mesh* m, SolverBufs* b) {
+  const int epb = m->epb[m->N] > 0 ? m->epb[m->N] : default_epb(m->N);
+  if (epb == b->epb && b->host_prob.nblk_ax == (m->E + epb - 1) / epb) return MXSEM_OK;
+  b->epb = epb;
+  b->nt_ax = (m->E + epb - 1) / epb;
+  std::vector<Tile> ta(b->nt_ax);
+  for (int q = 0; q < b->nt_ax; ++q) ta[q] = Tile{0, q * epb};
+  MX_HIP(hipMemcpy(b->tiles_ax, ta.data(), sizeof(Tile) * ta.size(), hipMemcpyHostToDevice));
+  b->host_prob.nblk_ax = b->nt_ax;
+  if (b->graph) {
+    MX_HIP(hipGraphExecDestroy(b->graph));
+    b->graph = nullptr;
+  }
+  return MXSEM_OK;
+}
+
 int ensure_bufs(mxsem_mesh* m, int vprec, SolverBufs** out) {
   if (m->bufs[vprec]) {
     *out = m->bufs[vprec];
-    return MXSEM_OK;
+    return retile_ax(m, *out);
   }
   SolverBufs* b = new SolverBufs();
   b->vprec = vprec;
@@ -59,14 +76,14 @@ int ensure_bufs(mxsem_mesh* m, int vprec, SolverBufs** out) {
   A(&b->z, es * nl);
   A(&b->p, es * nl);
   A(&b->w, es * nl);
-  A((void**)&b->part_ax, sizeof(double) * (b->nt_ax + 1));
+  A((void**)&b->part_ax, sizeof(double) * (m->E + 1));  // any epb fits
   A((void**)&b->part_gs, sizeof(double) * (b->nt_gs + 1));
   A((void**)&b->part_u0, sizeof(double) * (b->nt_upd + 1));
   A((void**)&b->part_u1, sizeof(double) * (b->nt_upd + 1));
   A((void**)&b->part_u2, sizeof(double) * (b->nt_upd + b->nt_gs + 1));
   A((void**)&b->st, sizeof(State));
   A((void**)&b->probs, sizeof(ProbDev));
-  A((void**)&b->tiles_ax, sizeof(Tile) * (b->nt_ax + 1));
+  A((void**)&b->tiles_ax, sizeof(Tile) * (m->E + 1));
   A((void**)&b->tiles_gs, sizeof(Tile) * (b->nt_gs + 1));
   A((void**)&b->tiles_upd, sizeof(Tile) * (b->nt_upd + 1));
   if (rc != MXSEM_OK) {

@@ -12,8 +12,6 @@ int mxsem_batch_create(mxsem_ctx*, int, mxsem_mesh* const*, const char*, mxsem_b
 int mxsem_batch_destroy(mxsem_batch*) { return MXSEM_OK; }
 int mxsem_batch_solve(mxsem_batch*, const mxsem_solve_opts*, const double* const*, double* const*,
                       mxsem_solve_stats*) { return MXSEM_ENOTSUP; }
-int mxsem_autotune(mxsem_ctx*, int, int, mxsem_prec, mxsem_tuning*) { return MXSEM_ENOTSUP; }
-int mxsem_mesh_set_tuning(mxsem_mesh*, const mxsem_tuning*) { return MXSEM_ENOTSUP; }
 int mxsem_nn_create(mxsem_mesh*, const mxsem_nn_desc*, mxsem_nn**) { return MXSEM_ENOTSUP; }
 int mxsem_nn_destroy(mxsem_nn*) { return MXSEM_OK; }
 int mxsem_nn_set_params(mxsem_nn*, const float*, const float*) { return MXSEM_ENOTSUP; }

@@ -1,0 +1,118 @@
+// Autotuner for the operator kernel's tile (elements per workgroup), and
+// the per-mesh tuning entry point.  Candidates are every elements-per-
+// workgroup count whose workgroup fits 256 threads; each is timed with HIP
+// events over repeated launches on synthetic data of the requested (N, E,
+// precision), and the fastest wins.
+#include <math.h>
+
+#include <string>
+#include <vector>
+
+#include "runtime.hpp"
+
+namespace mx {
+
+__global__ void fill_pattern_kernel(float* __restrict__ a, int64_t n, float base) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = base + 1e-3f * (float)(i % 977);
+}
+
+int autotune_epb(int device, hipStream_t s, int N, int E, int prec, int* best_epb,
+                 std::vector<float>* times) {
+  const int n = N + 1, n3 = n * n * n;
+  const int64_t nloc = (int64_t)E * n3;
+  const size_t vb = prec == MXSEM_F64 ? 8 : 4;
+  const size_t gb = prec == MXSEM_F64 ? 8 : prec == MXSEM_F32 ? 4 : 2;
+  void *u = nullptr, *w = nullptr, *G = nullptr, *D = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = MXSEM_OK;
+  auto cleanup = [&]() {
+    if (u) hipFree(u);
+    if (w) hipFree(w);
+    if (G) hipFree(G);
+    if (D) hipFree(D);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+  };
+  if (hipMalloc(&u, vb * nloc) != hipSuccess || hipMalloc(&w, vb * nloc) != hipSuccess ||
+      hipMalloc(&G, gb * 6 * nloc) != hipSuccess || hipMalloc(&D, 8 * n * n) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    set_error("autotune: allocation failed");
+    return MXSEM_ENOMEM;
+  }
+  // finite synthetic data (values do not affect the timing)
+  const size_t words_u = vb * nloc / 4, words_G = gb * 6 * nloc / 4, words_D = 8 * n * n / 4;
+  hipLaunchKernelGGL(fill_pattern_kernel, dim3((unsigned)((words_u + 255) / 256)), dim3(256), 0, s,
+                     (float*)u, (int64_t)words_u, 0.5f);
+  hipLaunchKernelGGL(fill_pattern_kernel, dim3((unsigned)((words_G + 255) / 256)), dim3(256), 0, s,
+                     (float*)G, (int64_t)words_G, 0.25f);
+  hipLaunchKernelGGL(fill_pattern_kernel, dim3((unsigned)((words_D + 255) / 256)), dim3(256), 0, s,
+                     (float*)D, (int64_t)words_D, 0.125f);
+  float best = INFINITY;
+  *best_epb = default_epb(N);
+  const int emax = max_epb(N);
+  for (int epb = 1; epb <= emax; ++epb) {
+    for (int r = 0; r < 2; ++r) {
+      if (launch_ax_apply(prec, N, E, epb, u, w, G, nullptr, D, s) != hipSuccess) {
+        cleanup();
+        set_error("autotune: launch failed");
+        return MXSEM_EHIP;
+      }
+    }
+    const int reps = 5;
+    hipEventRecord(e0, s);
+    for (int r = 0; r < reps; ++r) launch_ax_apply(prec, N, E, epb, u, w, G, nullptr, D, s);
+    hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess) {
+      cleanup();
+      set_error("autotune: event synchronisation failed");
+      return MXSEM_EHIP;
+    }
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    ms /= reps;
+    if (times) times->push_back(ms);
+    if (ms < best) {
+      best = ms;
+      *best_epb = epb;
+    }
+  }
+  (void)device;
+  cleanup();
+  return rc;
+}
+
+}  // namespace mx
+
+using namespace mx;
+
+extern "C" {
+
+int mxsem_autotune(mxsem_ctx* ctx, int N, int E, mxsem_prec prec, mxsem_tuning* out) {
+  MX_CHECK(ctx && out, MXSEM_EINVAL, "autotune: null argument");
+  MX_CHECK(N >= 1 && N <= MAX_N, MXSEM_ENOTSUP, "autotune: N must be in 1..15");
+  MX_CHECK(E >= 1, MXSEM_EINVAL, "autotune: E must be >= 1");
+  MX_CHECK(prec >= MXSEM_F64 && prec <= MXSEM_BF16G_F32, MXSEM_EINVAL, "autotune: bad precision");
+  MX_HIP(hipSetDevice(ctx->device));
+  (void)hipGetLastError();
+  int best = 0;
+  MX_TRY(autotune_epb(ctx->device, ctx->stream, N, E, prec, &best, nullptr));
+  for (int q = 0; q < 16; ++q) out->epb[q] = 0;
+  out->epb[N] = best;
+  return MXSEM_OK;
+}
+
+int mxsem_mesh_set_tuning(mxsem_mesh* m, const mxsem_tuning* t) {
+  MX_CHECK(m && t, MXSEM_EINVAL, "mesh_set_tuning: null argument");
+  const int e = t->epb[m->N];
+  MX_CHECK(e >= 0 && e <= max_epb(m->N), MXSEM_EINVAL,
+           "mesh_set_tuning: elements per workgroup out of range for this order");
+  MX_HIP(hipSetDevice(m->ctx->device));
+  m->epb[m->N] = e;
+  for (int q = 0; q < 4; ++q)
+    if (m->bufs[q]) MX_TRY(retile_ax(m, m->bufs[q]));
+  return MXSEM_OK;
+}
+
+}  // extern "C"

@@ -37,10 +37,12 @@ __global__ void gs_apply_kernel(T* __restrict__ v, const int* __restrict__ off,
   (void)nfree;
 }
 
-// solver variant on w, with the partial (p, w)_c over the groups
+// solver variant on w, with the partial (p, w)_c over the groups: a group's
+// copies all hold p_g (p is continuous) and, after the sum, w_g, so their
+// c-weighted products add up to exactly p_g * w_g.
 template <typename T, typename ACC>
-__global__ void gs_solver_kernel(const Tile* __restrict__ tiles,
-                                 const ProbDev* __restrict__ probs) {
+__global__ void __launch_bounds__(GS_THREADS) gs_solver_kernel(const Tile* __restrict__ tiles,
+                                                               const ProbDev* __restrict__ probs) {
   __shared__ ACC sred[16];
   const Tile t = tiles[blockIdx.x];
   const ProbDev& P = probs[t.prob];
@@ -49,17 +51,20 @@ __global__ void gs_solver_kernel(const Tile* __restrict__ tiles,
   const T* __restrict__ p = (const T*)P.p;
   const int* __restrict__ off = P.gs_off;
   const int* __restrict__ idx = P.gs_idx;
-  const int item = t.first + threadIdx.x;
   ACC dot = ACC(0);
-  if (item < P.ngroups) {
-    const int a = off[item], b = off[item + 1];
-    ACC s = ACC(0);
-    for (int q = a; q < b; ++q) s += (ACC)w[idx[q]];
-    const T val = (T)s;
-    for (int q = a; q < b; ++q) w[idx[q]] = val;
-    dot = (ACC)p[idx[a]] * (ACC)val;
-  } else if (item < P.ngroups + P.nmask) {
-    w[P.mask_idx[item - P.ngroups]] = T(0);
+#pragma unroll
+  for (int q = 0; q < GS_PER_THREAD; ++q) {
+    const int item = t.first + q * GS_THREADS + threadIdx.x;
+    if (item < P.ngroups) {
+      const int a = off[item], b = off[item + 1];
+      ACC s = ACC(0);
+      for (int k = a; k < b; ++k) s += (ACC)w[idx[k]];
+      const T val = (T)s;
+      for (int k = a; k < b; ++k) w[idx[k]] = val;
+      dot += (ACC)p[idx[a]] * (ACC)val;
+    } else if (item < P.ngroups + P.nmask) {
+      w[P.mask_idx[item - P.ngroups]] = T(0);
+    }
   }
   ACC s = block_sum(dot, sred);
   if (threadIdx.x == 0) P.part_gs[t.first / GS_CHUNK] = (double)s;
@@ -68,10 +73,25 @@ __global__ void gs_solver_kernel(const Tile* __restrict__ tiles,
 // ------------------------------------------------------------ vector pass
 __device__ inline double cweight(uint8_t m) { return m == 1 ? 1.0 : 1.0 / (double)m; }
 
+template <typename T>
+struct V4;
+template <>
+struct V4<float> {
+  typedef float4 type;
+};
+template <>
+struct V4<double> {
+  typedef double4 type;
+};
+
 // PC: 0 identity, 1 Jacobi, -1 none (z left alone; flexible CG computes it)
 // x += alpha p; r -= alpha w; z = M^-1 r; partials (r,z)_c and (r,r)_c.
+// Each thread handles UPD_PER_THREAD entries as 4-wide vectors when the
+// problem's entry count is a multiple of 4, else one by one (decided per
+// problem, so a problem is reduced the same way alone or in a batch).
 template <typename T, typename ACC, int PC>
-__global__ void update_kernel(const Tile* __restrict__ tiles, const ProbDev* __restrict__ probs) {
+__global__ void __launch_bounds__(UPD_THREADS) update_kernel(const Tile* __restrict__ tiles,
+                                                             const ProbDev* __restrict__ probs) {
   __shared__ ACC sred[16];
   const Tile t = tiles[blockIdx.x];
   const ProbDev& P = probs[t.prob];
@@ -85,20 +105,55 @@ __global__ void update_kernel(const Tile* __restrict__ tiles, const ProbDev* __r
   const T* __restrict__ dinv = (const T*)P.dinv;
   const uint8_t* __restrict__ mult = P.mult;
   ACC rz = ACC(0), rr = ACC(0);
+  if ((P.nloc & 3) == 0) {
+    typedef typename V4<T>::type VT;
 #pragma unroll
-  for (int q = 0; q < UPD_PER_THREAD; ++q) {
-    const int64_t i = (int64_t)t.first + q * UPD_THREADS + threadIdx.x;
-    if (i < P.nloc) {
-      const T xv = x[i] + alpha * p[i];
-      const T rv = r[i] - alpha * w[i];
-      x[i] = xv;
-      r[i] = rv;
-      const ACC c = (ACC)cweight(mult[i]);
-      rr += (ACC)rv * c * (ACC)rv;
-      if constexpr (PC >= 0) {
-        const T zv = (PC == 1) ? dinv[i] * rv : rv;
-        z[i] = zv;
-        rz += (ACC)rv * c * (ACC)zv;
+    for (int q = 0; q < UPD_PER_THREAD / 4; ++q) {
+      const int64_t v = (int64_t)t.first / 4 + q * UPD_THREADS + threadIdx.x;
+      if (4 * v < P.nloc) {
+        VT xv = ((const VT*)x)[v], pv = ((const VT*)p)[v], rv = ((const VT*)r)[v],
+           wv = ((const VT*)w)[v];
+        const uchar4 mv = ((const uchar4*)mult)[v];
+        xv.x += alpha * pv.x; xv.y += alpha * pv.y; xv.z += alpha * pv.z; xv.w += alpha * pv.w;
+        rv.x -= alpha * wv.x; rv.y -= alpha * wv.y; rv.z -= alpha * wv.z; rv.w -= alpha * wv.w;
+        ((VT*)x)[v] = xv;
+        ((VT*)r)[v] = rv;
+        const ACC c0 = (ACC)cweight(mv.x), c1 = (ACC)cweight(mv.y), c2 = (ACC)cweight(mv.z),
+                  c3 = (ACC)cweight(mv.w);
+        rr += (ACC)rv.x * c0 * (ACC)rv.x;
+        rr += (ACC)rv.y * c1 * (ACC)rv.y;
+        rr += (ACC)rv.z * c2 * (ACC)rv.z;
+        rr += (ACC)rv.w * c3 * (ACC)rv.w;
+        if constexpr (PC >= 0) {
+          VT zv = rv;
+          if constexpr (PC == 1) {
+            const VT dv = ((const VT*)dinv)[v];
+            zv.x = dv.x * rv.x; zv.y = dv.y * rv.y; zv.z = dv.z * rv.z; zv.w = dv.w * rv.w;
+          }
+          ((VT*)z)[v] = zv;
+          rz += (ACC)rv.x * c0 * (ACC)zv.x;
+          rz += (ACC)rv.y * c1 * (ACC)zv.y;
+          rz += (ACC)rv.z * c2 * (ACC)zv.z;
+          rz += (ACC)rv.w * c3 * (ACC)zv.w;
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < UPD_PER_THREAD; ++q) {
+      const int64_t i = (int64_t)t.first + q * UPD_THREADS + threadIdx.x;
+      if (i < P.nloc) {
+        const T xv = x[i] + alpha * p[i];
+        const T rv = r[i] - alpha * w[i];
+        x[i] = xv;
+        r[i] = rv;
+        const ACC c = (ACC)cweight(mult[i]);
+        rr += (ACC)rv * c * (ACC)rv;
+        if constexpr (PC >= 0) {
+          const T zv = (PC == 1) ? dinv[i] * rv : rv;
+          z[i] = zv;
+          rz += (ACC)rv * c * (ACC)zv;
+        }
       }
     }
   }
@@ -154,10 +209,21 @@ __global__ void init_kernel(const Tile* __restrict__ tiles, const ProbDev* __res
 }
 
 // ------------------------------------------------------------ scalar stages
-// sum of parts[0..n) in a fixed order by one workgroup (256 threads)
+// sum of parts[0..n) in a fixed order by one workgroup of FIN_THREADS:
+// thread t adds parts[t + k*FIN_THREADS] into accumulator k % 8 (eight
+// independent chains keep eight loads in flight), then the accumulators,
+// then the block.  The order depends only on n.
 __device__ inline double fixed_sum(const double* __restrict__ parts, int n, double* sred) {
-  double s = 0.0;
-  for (int q = threadIdx.x; q < n; q += blockDim.x) s += parts[q];
+  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int q = threadIdx.x;
+  for (; q + 7 * FIN_THREADS < n; q += 8 * FIN_THREADS) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] += parts[q + k * FIN_THREADS];
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (q + k * FIN_THREADS < n) a[k] += parts[q + k * FIN_THREADS];
+  const double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   return block_sum(s, sred);
 }
 
@@ -355,7 +421,7 @@ hipError_t launch_gs_apply2(int prec_io, int prec_acc, void* v, const int* off, 
 hipError_t launch_gs_solver(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs,
                             hipStream_t s) {
   if (ntiles == 0) return hipSuccess;
-  dim3 g(ntiles), b(GS_CHUNK);
+  dim3 g(ntiles), b(GS_THREADS);
   if (vprec == 0)
     hipLaunchKernelGGL((gs_solver_kernel<double, double>), g, b, 0, s, tiles, probs);
   else if (vprec == 1)
@@ -406,12 +472,12 @@ hipError_t launch_init(int vprec, int pc, const Tile* tiles, int ntiles, const P
 }
 
 hipError_t launch_fin_sigma(const ProbDev* probs, int nprob, hipStream_t s) {
-  hipLaunchKernelGGL(fin_sigma_kernel, dim3(nprob), dim3(256), 0, s, probs);
+  hipLaunchKernelGGL(fin_sigma_kernel, dim3(nprob), dim3(FIN_THREADS), 0, s, probs);
   return hipGetLastError();
 }
 
 hipError_t launch_fin_rho(const ProbDev* probs, int nprob, int init, hipStream_t s) {
-  hipLaunchKernelGGL(fin_rho_kernel, dim3(nprob), dim3(256), 0, s, probs, init);
+  hipLaunchKernelGGL(fin_rho_kernel, dim3(nprob), dim3(FIN_THREADS), 0, s, probs, init);
   return hipGetLastError();
 }
 
@@ -424,7 +490,7 @@ hipError_t launch_dot(int prec, const void* a, const void* b, const uint8_t* mul
   else
     hipLaunchKernelGGL((dot_kernel<float>), dim3(nb), dim3(UPD_THREADS), 0, s, (const float*)a,
                        (const float*)b, mult, n, part);
-  hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(256), 0, s, part, (int)nb, out);
+  hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(FIN_THREADS), 0, s, part, (int)nb, out);
   return hipGetLastError();
 }
 
@@ -444,7 +510,7 @@ hipError_t launch_residual(const double* b, const double* w, double* r, const ui
                            int64_t n, double* part, double* out, hipStream_t s) {
   const unsigned nb = nblk(n, UPD_CHUNK);
   hipLaunchKernelGGL(residual_kernel, dim3(nb), dim3(UPD_THREADS), 0, s, b, w, r, mult, n, part);
-  hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(256), 0, s, part, (int)nb, out);
+  hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(FIN_THREADS), 0, s, part, (int)nb, out);
   return hipGetLastError();
 }
 
