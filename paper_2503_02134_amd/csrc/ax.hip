@@ -27,8 +27,7 @@ struct AxApplyArgs {
 };
 
 // Solver variant: p = z + beta p_old (beta from the device state, p
-// written back), w = A_L p, and the partial sum of p.w over element-interior
-// nodes (never shared, never Dirichlet, so c = 1 and w is already final).
+// written back), w = A_L p, and the workgroup's partial sum of p.w.
 template <int N, typename T, typename TG, bool SOLVER>
 __global__ void __launch_bounds__(256) ax_kernel(const Tile* __restrict__ tiles, const ProbDev* __restrict__ probs,
                           AxApplyArgs apply, int epb) {
@@ -109,7 +108,20 @@ __global__ void __launch_bounds__(256) ax_kernel(const Tile* __restrict__ tiles,
     for (int k = 0; k < n; ++k) u[k] = T(0);
   }
 
+  // Geometric factors of the whole column: loaded before the k loop when
+  // they fit in registers, so every load of the element is in flight at
+  // once (the workgroup barriers inside the loop would otherwise serialise
+  // one HBM round trip per k).
   const TG* __restrict__ Ge = G + (int64_t)e * 6 * n3 + ij;
+  constexpr bool PREFETCH = 6 * n * sizeof(T) <= 512;
+  T gpre[PREFETCH ? 6 * n : 1];
+  if constexpr (PREFETCH) {
+#pragma unroll
+    for (int k = 0; k < n; ++k)
+#pragma unroll
+      for (int q = 0; q < 6; ++q)
+        gpre[q * n + k] = active ? cvt<T>(Ge[q * n3 + k * n2]) : T(0);
+  }
 #pragma unroll
   for (int k = 0; k < n; ++k) {
     if (active) su[ij] = u[k];
@@ -123,12 +135,22 @@ __global__ void __launch_bounds__(256) ax_kernel(const Tile* __restrict__ tiles,
         ut += sD[k * n + l] * u[l];
       }
       const int off = k * n2;
-      const T g0 = cvt<T>(Ge[0 * n3 + off]);
-      const T g1 = cvt<T>(Ge[1 * n3 + off]);
-      const T g2 = cvt<T>(Ge[2 * n3 + off]);
-      const T g3 = cvt<T>(Ge[3 * n3 + off]);
-      const T g4 = cvt<T>(Ge[4 * n3 + off]);
-      const T g5 = cvt<T>(Ge[5 * n3 + off]);
+      T g0, g1, g2, g3, g4, g5;
+      if constexpr (PREFETCH) {
+        g0 = gpre[0 * n + k];
+        g1 = gpre[1 * n + k];
+        g2 = gpre[2 * n + k];
+        g3 = gpre[3 * n + k];
+        g4 = gpre[4 * n + k];
+        g5 = gpre[5 * n + k];
+      } else {
+        g0 = cvt<T>(Ge[0 * n3 + off]);
+        g1 = cvt<T>(Ge[1 * n3 + off]);
+        g2 = cvt<T>(Ge[2 * n3 + off]);
+        g3 = cvt<T>(Ge[3 * n3 + off]);
+        g4 = cvt<T>(Ge[4 * n3 + off]);
+        g5 = cvt<T>(Ge[5 * n3 + off]);
+      }
       const T wr = g0 * ur + g1 * us + g2 * ut;
       const T ws = g1 * ur + g3 * us + g4 * ut;
       const T wt = g2 * ur + g4 * us + g5 * ut;
@@ -147,17 +169,17 @@ __global__ void __launch_bounds__(256) ax_kernel(const Tile* __restrict__ tiles,
     __syncthreads();
   }
 
+  // (p, QQ^T A_L p)_c = sum_i p_i (A_L p)_i over all local entries, because
+  // p is continuous and zero on Dirichlet nodes: the solver takes sigma
+  // from the local result, before the gather-scatter.
   double dot = 0.0;
   if (active) {
-    const bool ij_interior = (i > 0) && (i < N) && (j > 0) && (j < N);
 #pragma unroll
     for (int k = 0; k < n; ++k) {
       T wv = w[k];
       if (hB) wv += cvt<T>(hB[(int64_t)e * n3 + k * n2 + ij]) * u[k];
       Wout[base + k * n2] = wv;
-      if constexpr (SOLVER) {
-        if (ij_interior && k > 0 && k < N) dot += (double)u[k] * (double)wv;
-      }
+      if constexpr (SOLVER) dot += (double)u[k] * (double)wv;
     }
   }
   if constexpr (SOLVER) {

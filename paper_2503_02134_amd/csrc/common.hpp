@@ -101,10 +101,34 @@ struct State {
   int pad;
 };
 
-// A tile: a block of work of one problem (elements, groups or entries).
+// A tile: a block of work of one problem (elements, groups or entries);
+// aux selects the gather-scatter bucket.
 struct Tile {
   int prob;
   int first;
+  int aux;
+  int pad;
+};
+
+// Gather-scatter plan.  Groups of m >= 2 copies of one node are stored in
+// buckets of equal m, m copies per group contiguous in idx (ascending local
+// index), groups of a bucket in ascending first local index.  Free buckets
+// come first (m = 8, 4, 2 at 16-byte aligned offsets, then any other m),
+// then buckets of Dirichlet groups, then one bucket with m = 0 that lists
+// every Dirichlet entry (one entry per "group") for the mask.
+constexpr int MAX_BUCKETS = 16;
+struct GsBucket {
+  int m;        // copies per group (0: mask list)
+  int ngroups;  // groups (entries for the mask list)
+  int off;      // first index in idx
+  int pad;
+};
+struct GsPlan {
+  const int* idx;
+  GsBucket bk[MAX_BUCKETS];
+  int nfree;    // buckets [0, nfree): free groups
+  int nall;     // buckets [nfree, nall): Dirichlet groups; bk[nall]: mask list
+  int pad0, pad1;
 };
 
 // Device view of one problem for the iteration kernels.  Vector and
@@ -119,18 +143,15 @@ struct ProbDev {
   const void* dinv;  // [nloc] vector type
   const uint8_t* mult;  // [nloc] multiplicity m
   // gather-scatter plan
-  const int* gs_off;  // [ngroups+1]
-  const int* gs_idx;
-  const int* mask_idx;
-  int ngroups, nmask;
+  GsPlan gs;
   // vectors (vector type)
   void *x, *r, *z, *p, *w;
   // FP64 right-hand side of the current (inner) solve and its scale
   const double* rhs64;
   double rhs_scale;  // r = rhs64 * rhs_scale
   // partial sums
-  double* part_ax;   // sigma over element-interior nodes, per Ax tile
-  double* part_gs;   // sigma over gather-scatter items, per GS tile
+  double* part_ax;   // sigma = sum_i p_i (A_L p)_i, per operator tile
+  double* part_gs;   // unused by PCG (kept for the flexible-CG dots)
   double* part_u0;   // per update tile: (r,z)_c  (or rr for FCG)
   double* part_u1;   // per update tile: (r,r)_c
   double* part_u2;   // per tile: (z,w)_c (flexible CG)

@@ -140,9 +140,8 @@ int apply_impl(mxsem_mesh* m, int prec, const void* u, void* w, unsigned flags, 
   MX_HIP(launch_ax_apply(prec, m->N, m->E, m->epb[m->N] > 0 ? m->epb[m->N] : default_epb(m->N),
                          u, w, G_ptr(m, gprec), hB_ptr(m, gprec), D, s));
   if (!(flags & MXSEM_LOCAL_ONLY)) {
-    MX_HIP(launch_gs_apply2(prec == MXSEM_F64 ? MXSEM_F64 : MXSEM_F32, MXSEM_F64, w, m->gs_off,
-                            m->gs_idx, m->ngroups_all, m->nfree, m->nmask_entries, m->mask_first,
-                            true, s));
+    MX_HIP(launch_gs_apply(prec == MXSEM_F64 ? MXSEM_F64 : MXSEM_F32, MXSEM_F64, w, m->plan, true,
+                           s));
   }
   return MXSEM_OK;
 }
@@ -357,62 +356,68 @@ int mxsem_mesh_create(mxsem_ctx* ctx, const mxsem_mesh_desc* d, mxsem_mesh** out
   const int64_t ng = (int64_t)gstart.size() - 1;
   std::vector<uint8_t> mult(nloc);
   struct Grp {
-    int32_t m, first;  // size, position in order
-    int64_t g;
+    int32_t m, first;  // size, position in `order`
   };
-  std::vector<Grp> freeg, maskg;
+  std::vector<std::vector<Grp>> freeb(256), maskb(256);
+  std::vector<int32_t> masklist;
   const uint8_t* bnd = d->bnd;
+  int64_t ngroups = 0;
   for (int64_t q = 0; q < ng; ++q) {
     const int64_t a = gstart[q], b = gstart[q + 1];
     const int32_t sz = (int32_t)(b - a);
     MX_MCHECK(sz <= 255, MXSEM_ENOTSUP, "mesh_create: a node shared by more than 255 elements");
     const bool msk = bnd[order[a]] != 0;
-    bool face = false;
     for (int64_t t = a; t < b; ++t) {
       const int32_t li = order[t];
       MX_MCHECK((bnd[li] != 0) == msk, MXSEM_EMESH,
                 "mesh_create: copies of a global node disagree on the Dirichlet flag");
       mult[li] = (uint8_t)sz;
-      const int p = li % n3;
-      const int i = p % n, j = (p / n) % n, k = p / (n * n);
-      const bool f = i == 0 || i == d->N || j == 0 || j == d->N || k == 0 || k == d->N;
-      face = face || f;
-      if (!f) MX_MCHECK(sz == 1 && !msk, MXSEM_EMESH,
-                        "mesh_create: an element-interior node is shared or Dirichlet");
+      if (msk) masklist.push_back(li);
     }
-    if (!face) continue;
-    Grp gr{sz, (int32_t)a, glo[order[a]]};
-    (msk ? maskg : freeg).push_back(gr);
+    if (sz >= 2) {
+      (msk ? maskb : freeb)[sz].push_back(Grp{sz, (int32_t)a});
+      ++ngroups;
+    }
   }
-  // groups of one multiplicity together (uniform trip counts per wave), and
-  // inside each in ascending first local index, so neighbouring threads
-  // touch neighbouring entries of the same elements
-  auto by_first = [&order](const Grp& x, const Grp& y) {
-    if (x.m != y.m) return x.m < y.m;
-    return order[x.first] < order[y.first];
-  };
-  std::sort(freeg.begin(), freeg.end(), by_first);
-  std::sort(maskg.begin(), maskg.end(),
-            [&order](const Grp& x, const Grp& y) { return order[x.first] < order[y.first]; });
-  m->nfree = (int)freeg.size();
-  m->ngroups_all = (int)(freeg.size() + maskg.size());
-  std::vector<int32_t> off, idx;
-  off.reserve(m->ngroups_all + 1);
-  off.push_back(0);
-  for (const auto* vec : {&freeg, &maskg})
-    for (const Grp& gr : *vec) {
-      for (int t = 0; t < gr.m; ++t) idx.push_back(order[gr.first + t]);
-      off.push_back((int32_t)idx.size());
+  std::sort(masklist.begin(), masklist.end());
+  // bucket order: 8, 4, 2 (vector index loads), then every other m descending
+  std::vector<int> morder = {8, 4, 2};
+  for (int mm = 255; mm >= 2; --mm)
+    if (mm != 8 && mm != 4 && mm != 2) morder.push_back(mm);
+  std::vector<int32_t> idx;
+  GsPlan plan{};
+  int nb = 0;
+  auto emit = [&](std::vector<std::vector<Grp>>& bks) -> bool {
+    for (int mm : morder) {
+      auto& gv = bks[mm];
+      if (gv.empty()) continue;
+      if (nb >= MAX_BUCKETS - 1) return false;
+      std::sort(gv.begin(), gv.end(),
+                [&order](const Grp& x, const Grp& y) { return order[x.first] < order[y.first]; });
+      while (idx.size() % 4) idx.push_back(0);  // 16-byte aligned bucket start
+      plan.bk[nb] = GsBucket{mm, (int)gv.size(), (int)idx.size(), 0};
+      for (const Grp& gr : gv)
+        for (int t = 0; t < gr.m; ++t) idx.push_back(order[gr.first + t]);
+      ++nb;
     }
-  m->mask_first = off[m->nfree];
-  m->nmask_entries = (int)idx.size() - m->mask_first;
-  MX_MTRY(mesh_alloc(m, (void**)&m->gs_off, sizeof(int) * off.size()));
-  MX_MTRY(mesh_alloc(m, (void**)&m->gs_idx, sizeof(int) * std::max<size_t>(idx.size(), 1)));
+    return true;
+  };
+  MX_MCHECK(emit(freeb), MXSEM_ENOTSUP, "mesh_create: too many distinct node multiplicities");
+  plan.nfree = nb;
+  MX_MCHECK(emit(maskb), MXSEM_ENOTSUP, "mesh_create: too many distinct node multiplicities");
+  plan.nall = nb;
+  while (idx.size() % 4) idx.push_back(0);
+  plan.bk[nb] = GsBucket{0, (int)masklist.size(), (int)idx.size(), 0};
+  idx.insert(idx.end(), masklist.begin(), masklist.end());
+  m->ngroups = ngroups;
+  m->nmask_entries = (int)masklist.size();
+  MX_MTRY(mesh_alloc(m, (void**)&m->gs_idx, sizeof(int) * std::max<size_t>(idx.size(), 4)));
   MX_MTRY(mesh_alloc(m, (void**)&m->mult, nloc));
-  MX_MHIP(hipMemcpyAsync(m->gs_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice, s));
   if (!idx.empty())
     MX_MHIP(hipMemcpyAsync(m->gs_idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice, s));
   MX_MHIP(hipMemcpyAsync(m->mult, mult.data(), nloc, hipMemcpyHostToDevice, s));
+  plan.idx = m->gs_idx;
+  m->plan = plan;
 
   // scratch
   const int64_t nbu = (nloc + UPD_CHUNK - 1) / UPD_CHUNK;
@@ -428,11 +433,13 @@ int mxsem_mesh_create(mxsem_ctx* ctx, const mxsem_mesh_desc* d, mxsem_mesh** out
   // Jacobi: assembled diagonal (FP64), inverse, zero on Dirichlet entries
   MX_MTRY(mesh_alloc(m, (void**)&m->dinv64, sizeof(double) * nloc));
   MX_MHIP(launch_diag(m->E, n, m->G64, m->B64, m->helm_h, m->D64, m->dinv64, s));
-  MX_MHIP(launch_gs_apply2(MXSEM_F64, MXSEM_F64, m->dinv64, m->gs_off, m->gs_idx, m->ngroups_all,
-                           m->nfree, m->nmask_entries, m->mask_first, false, s));
+  MX_MHIP(launch_gs_apply(MXSEM_F64, MXSEM_F64, m->dinv64, m->plan, false, s));
   MX_MHIP(launch_invert(m->dinv64, nloc, s));
-  MX_MHIP(launch_gs_apply2(MXSEM_F64, MXSEM_F64, m->dinv64, m->gs_off, m->gs_idx, m->ngroups_all,
-                           0, m->nmask_entries, m->mask_first, true, s));
+  {
+    GsPlan only_mask = m->plan;  // zero the Dirichlet entries only
+    only_mask.nfree = 0;
+    MX_MHIP(launch_gs_apply(MXSEM_F64, MXSEM_F64, m->dinv64, only_mask, true, s));
+  }
 
   // lower-precision views (one-time casts)
   if (m->views & (MXSEM_VIEW_F32 | MXSEM_VIEW_BF16)) {
@@ -473,7 +480,7 @@ int mxsem_mesh_info(const mxsem_mesh* m, int64_t* nloc, int64_t* ngroups, int64_
                     double* min_detj) {
   MX_CHECK(m, MXSEM_EINVAL, "mesh_info: null mesh");
   if (nloc) *nloc = m->nloc;
-  if (ngroups) *ngroups = m->ngroups_all;
+  if (ngroups) *ngroups = m->ngroups;
   if (nmasked) *nmasked = m->nmask_entries;
   if (min_detj) *min_detj = m->min_det;
   return MXSEM_OK;
@@ -497,8 +504,8 @@ int mxsem_mesh_get(const mxsem_mesh* m, int what, double* out) {
       } else {
         std::vector<int32_t> idx(m->nmask_entries);
         if (m->nmask_entries)
-          MX_HIP(hipMemcpy(idx.data(), m->gs_idx + m->mask_first, sizeof(int) * m->nmask_entries,
-                           hipMemcpyDeviceToHost));
+          MX_HIP(hipMemcpy(idx.data(), m->gs_idx + m->plan.bk[m->plan.nall].off,
+                           sizeof(int) * m->nmask_entries, hipMemcpyDeviceToHost));
         for (int64_t i = 0; i < m->nloc; ++i) out[i] = 0.0;
         for (int32_t i : idx) out[i] = 1.0;
       }
@@ -534,9 +541,7 @@ int mxsem_gather_scatter(mxsem_mesh* m, mxsem_prec io, mxsem_prec acc, void* v, 
   MX_CHECK(acc == MXSEM_F64 || acc == MXSEM_F32, MXSEM_EINVAL, "gather_scatter: acc must be F64/F32");
   MX_HIP(hipSetDevice(m->ctx->device));
   (void)hipGetLastError();
-  MX_HIP(launch_gs_apply2(io, acc, v, m->gs_off, m->gs_idx, m->ngroups_all, m->nfree,
-                          m->nmask_entries, m->mask_first, (flags & MXSEM_MASK) != 0,
-                          m->ctx->stream));
+  MX_HIP(launch_gs_apply(io, acc, v, m->plan, (flags & MXSEM_MASK) != 0, m->ctx->stream));
   return MXSEM_OK;
 }
 
@@ -555,8 +560,7 @@ int mxsem_mass_rhs(mxsem_mesh* m, const double* f, double* b) {
   (void)hipGetLastError();
   hipStream_t s = m->ctx->stream;
   MX_HIP(launch_mass(m->B64, f, b, m->nloc, s));
-  MX_HIP(launch_gs_apply2(MXSEM_F64, MXSEM_F64, b, m->gs_off, m->gs_idx, m->ngroups_all, m->nfree,
-                          m->nmask_entries, m->mask_first, true, s));
+  MX_HIP(launch_gs_apply(MXSEM_F64, MXSEM_F64, b, m->plan, true, s));
   return MXSEM_OK;
 }
 

@@ -22,9 +22,8 @@ hipError_t launch_ax_apply(int prec, int N, int E, int epb, const void* u, void*
 hipError_t launch_ax_solver(int prec, int N, const Tile* tiles, int ntiles, const ProbDev* probs,
                             int epb, hipStream_t s);
 int max_epb(int N);
-hipError_t launch_gs_apply2(int prec_io, int prec_acc, void* v, const int* off, const int* idx,
-                            int ngroups_all, int nfree, int nmask_entries, int mask_first,
-                            bool mask, hipStream_t s);
+hipError_t launch_gs_apply(int prec_io, int prec_acc, void* v, const GsPlan& plan, bool mask,
+                           hipStream_t s);
 hipError_t launch_gs_solver(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs,
                             hipStream_t s);
 hipError_t launch_update(int vprec, int pc, const Tile* tiles, int ntiles, const ProbDev* probs,
@@ -104,9 +103,10 @@ struct mxsem_mesh {
   double* dinv64 = nullptr;
   float* dinv32 = nullptr;
   uint8_t* mult = nullptr;
-  int* gs_off = nullptr;
   int* gs_idx = nullptr;
-  int ngroups_all = 0, nfree = 0, nmask_entries = 0, mask_first = 0;
+  mx::GsPlan plan{};          // device index array + bucket table
+  int64_t ngroups = 0;        // groups of >= 2 copies
+  int nmask_entries = 0;      // Dirichlet entries
   double min_det = 0.0;
   // scratch
   double* part = nullptr;    // [ceil(nloc / UPD_CHUNK)]

@@ -43,7 +43,7 @@ int retile_ax(mxsem_mesh* m, SolverBufs* b) {
   b->epb = epb;
   b->nt_ax = (m->E + epb - 1) / epb;
   std::vector<Tile> ta(b->nt_ax);
-  for (int q = 0; q < b->nt_ax; ++q) ta[q] = Tile{0, q * epb};
+  for (int q = 0; q < b->nt_ax; ++q) ta[q] = Tile{0, q * epb, 0, 0};
   MX_HIP(hipMemcpy(b->tiles_ax, ta.data(), sizeof(Tile) * ta.size(), hipMemcpyHostToDevice));
   b->host_prob.nblk_ax = b->nt_ax;
   if (b->graph) {
@@ -64,8 +64,14 @@ int ensure_bufs(mxsem_mesh* m, int vprec, SolverBufs** out) {
   const int64_t nl = m->nloc;
   b->epb = m->epb[m->N] > 0 ? m->epb[m->N] : default_epb(m->N);
   b->nt_ax = (m->E + b->epb - 1) / b->epb;
-  const int gs_items = m->nfree + m->nmask_entries;
-  b->nt_gs = (gs_items + GS_CHUNK - 1) / GS_CHUNK;
+  // gather-scatter tiles: free buckets and the mask list
+  std::vector<Tile> tg;
+  for (int q = 0; q <= m->plan.nall; ++q) {
+    if (q >= m->plan.nfree && q < m->plan.nall) continue;
+    const int ngq = m->plan.bk[q].ngroups;
+    for (int f = 0; f < ngq; f += GS_CHUNK) tg.push_back(Tile{0, f, q, 0});
+  }
+  b->nt_gs = (int)tg.size();
   b->nt_upd = (int)((nl + UPD_CHUNK - 1) / UPD_CHUNK);
   int rc = MXSEM_OK;
   auto A = [&](void** p, size_t bytes) {
@@ -91,10 +97,9 @@ int ensure_bufs(mxsem_mesh* m, int vprec, SolverBufs** out) {
     return rc;
   }
   hipStream_t s = m->ctx->stream;
-  std::vector<Tile> ta(b->nt_ax), tg(b->nt_gs), tu(b->nt_upd);
-  for (int q = 0; q < b->nt_ax; ++q) ta[q] = Tile{0, q * b->epb};
-  for (int q = 0; q < b->nt_gs; ++q) tg[q] = Tile{0, q * GS_CHUNK};
-  for (int q = 0; q < b->nt_upd; ++q) tu[q] = Tile{0, q * UPD_CHUNK};
+  std::vector<Tile> ta(b->nt_ax), tu(b->nt_upd);
+  for (int q = 0; q < b->nt_ax; ++q) ta[q] = Tile{0, q * b->epb, 0, 0};
+  for (int q = 0; q < b->nt_upd; ++q) tu[q] = Tile{0, q * UPD_CHUNK, 0, 0};
   MX_HIP(hipMemcpyAsync(b->tiles_ax, ta.data(), sizeof(Tile) * ta.size(), hipMemcpyHostToDevice, s));
   if (!tg.empty())
     MX_HIP(hipMemcpyAsync(b->tiles_gs, tg.data(), sizeof(Tile) * tg.size(), hipMemcpyHostToDevice, s));
@@ -108,11 +113,7 @@ int ensure_bufs(mxsem_mesh* m, int vprec, SolverBufs** out) {
   P.D = vprec == VP_F64 ? (const void*)m->D64 : (const void*)m->D32;
   P.dinv = vprec == VP_F64 ? (const void*)m->dinv64 : (const void*)m->dinv32;
   P.mult = m->mult;
-  P.gs_off = m->gs_off;
-  P.gs_idx = m->gs_idx;
-  P.mask_idx = m->gs_idx + m->mask_first;
-  P.ngroups = m->nfree;
-  P.nmask = m->nmask_entries;
+  P.gs = m->plan;
   P.x = b->x;
   P.r = b->r;
   P.z = b->z;

@@ -20,54 +20,121 @@
 namespace mx {
 
 // ------------------------------------------------------------ gather-scatter
-template <typename T, typename ACC>
-__global__ void gs_apply_kernel(T* __restrict__ v, const int* __restrict__ off,
-                                const int* __restrict__ idx, int nsum, int nfree,
-                                int nmask_entries, int mask_first) {
-  const int item = blockIdx.x * blockDim.x + threadIdx.x;
-  if (item < nsum) {
-    const int a = off[item], b = off[item + 1];
-    ACC s = ACC(0);
-    for (int q = a; q < b; ++q) s += (ACC)v[idx[q]];
-    const T val = (T)s;
-    for (int q = a; q < b; ++q) v[idx[q]] = val;
-  } else if (item - nsum < nmask_entries) {
-    v[idx[mask_first + item - nsum]] = T(0);
-  }
-  (void)nfree;
-}
+struct GsApi {
+  void* v;
+  GsPlan plan;
+  int bucket;
+};
 
-// solver variant on w, with the partial (p, w)_c over the groups: a group's
-// copies all hold p_g (p is continuous) and, after the sum, w_g, so their
-// c-weighted products add up to exactly p_g * w_g.
-template <typename T, typename ACC>
-__global__ void __launch_bounds__(GS_THREADS) gs_solver_kernel(const Tile* __restrict__ tiles,
-                                                               const ProbDev* __restrict__ probs) {
-  __shared__ ACC sred[16];
-  const Tile t = tiles[blockIdx.x];
-  const ProbDev& P = probs[t.prob];
-  if (P.st->done) return;
-  T* __restrict__ w = (T*)P.w;
-  const T* __restrict__ p = (const T*)P.p;
-  const int* __restrict__ off = P.gs_off;
-  const int* __restrict__ idx = P.gs_idx;
-  ACC dot = ACC(0);
+// One thread per group, GS_PER_THREAD groups per thread issued together:
+// all index loads, then all value loads, then sums (ascending local index,
+// in the accumulation type ACC), then the stores.  m = 0 is the mask list.
+template <typename T, typename ACC, bool SOLVER>
+__global__ void __launch_bounds__(GS_THREADS) gs_kernel(const Tile* __restrict__ tiles,
+                                                        const ProbDev* __restrict__ probs,
+                                                        GsApi api) {
+  const GsPlan* plan;
+  T* __restrict__ v;
+  int bucket, first;
+  if constexpr (SOLVER) {
+    const Tile t = tiles[blockIdx.x];
+    const ProbDev& P = probs[t.prob];
+    if (P.st->done) return;
+    plan = &P.gs;
+    v = (T*)P.w;
+    bucket = t.aux;
+    first = t.first;
+  } else {
+    plan = &api.plan;
+    v = (T*)api.v;
+    bucket = api.bucket;
+    first = blockIdx.x * GS_CHUNK;
+  }
+  const GsBucket bk = plan->bk[bucket];
+  const int* __restrict__ idx = plan->idx + bk.off;
+  const int m = bk.m;
+  int g[GS_PER_THREAD];
+  bool ok[GS_PER_THREAD];
 #pragma unroll
   for (int q = 0; q < GS_PER_THREAD; ++q) {
-    const int item = t.first + q * GS_THREADS + threadIdx.x;
-    if (item < P.ngroups) {
-      const int a = off[item], b = off[item + 1];
-      ACC s = ACC(0);
-      for (int k = a; k < b; ++k) s += (ACC)w[idx[k]];
-      const T val = (T)s;
-      for (int k = a; k < b; ++k) w[idx[k]] = val;
-      dot += (ACC)p[idx[a]] * (ACC)val;
-    } else if (item < P.ngroups + P.nmask) {
-      w[P.mask_idx[item - P.ngroups]] = T(0);
-    }
+    g[q] = first + q * GS_THREADS + threadIdx.x;
+    ok[q] = g[q] < bk.ngroups;
   }
-  ACC s = block_sum(dot, sred);
-  if (threadIdx.x == 0) P.part_gs[t.first / GS_CHUNK] = (double)s;
+  if (m == 0) {
+#pragma unroll
+    for (int q = 0; q < GS_PER_THREAD; ++q)
+      if (ok[q]) v[idx[g[q]]] = T(0);
+  } else if (m == 2) {
+    int2 ix[GS_PER_THREAD];
+    T a0[GS_PER_THREAD], a1[GS_PER_THREAD];
+#pragma unroll
+    for (int q = 0; q < GS_PER_THREAD; ++q)
+      if (ok[q]) ix[q] = ((const int2*)idx)[g[q]];
+#pragma unroll
+    for (int q = 0; q < GS_PER_THREAD; ++q)
+      if (ok[q]) {
+        a0[q] = v[ix[q].x];
+        a1[q] = v[ix[q].y];
+      }
+#pragma unroll
+    for (int q = 0; q < GS_PER_THREAD; ++q)
+      if (ok[q]) {
+        const T val = (T)((ACC)a0[q] + (ACC)a1[q]);
+        v[ix[q].x] = val;
+        v[ix[q].y] = val;
+      }
+  } else if (m == 4) {
+    int4 ix[GS_PER_THREAD];
+    T a[GS_PER_THREAD][4];
+#pragma unroll
+    for (int q = 0; q < GS_PER_THREAD; ++q)
+      if (ok[q]) ix[q] = ((const int4*)idx)[g[q]];
+#pragma unroll
+    for (int q = 0; q < GS_PER_THREAD; ++q)
+      if (ok[q]) {
+        a[q][0] = v[ix[q].x];
+        a[q][1] = v[ix[q].y];
+        a[q][2] = v[ix[q].z];
+        a[q][3] = v[ix[q].w];
+      }
+#pragma unroll
+    for (int q = 0; q < GS_PER_THREAD; ++q)
+      if (ok[q]) {
+        const T val = (T)((((ACC)a[q][0] + (ACC)a[q][1]) + (ACC)a[q][2]) + (ACC)a[q][3]);
+        v[ix[q].x] = val;
+        v[ix[q].y] = val;
+        v[ix[q].z] = val;
+        v[ix[q].w] = val;
+      }
+  } else if (m == 8) {
+#pragma unroll
+    for (int q = 0; q < GS_PER_THREAD; ++q)
+      if (ok[q]) {
+        const int4 i0 = ((const int4*)idx)[2 * g[q]];
+        const int4 i1 = ((const int4*)idx)[2 * g[q] + 1];
+        ACC s = (ACC)v[i0.x];
+        s += (ACC)v[i0.y];
+        s += (ACC)v[i0.z];
+        s += (ACC)v[i0.w];
+        s += (ACC)v[i1.x];
+        s += (ACC)v[i1.y];
+        s += (ACC)v[i1.z];
+        s += (ACC)v[i1.w];
+        const T val = (T)s;
+        v[i0.x] = val; v[i0.y] = val; v[i0.z] = val; v[i0.w] = val;
+        v[i1.x] = val; v[i1.y] = val; v[i1.z] = val; v[i1.w] = val;
+      }
+  } else {
+#pragma unroll
+    for (int q = 0; q < GS_PER_THREAD; ++q)
+      if (ok[q]) {
+        const int* gi = idx + (int64_t)g[q] * m;
+        ACC s = (ACC)v[gi[0]];
+        for (int k = 1; k < m; ++k) s += (ACC)v[gi[k]];
+        const T val = (T)s;
+        for (int k = 0; k < m; ++k) v[gi[k]] = val;
+      }
+  }
 }
 
 // ------------------------------------------------------------ vector pass
@@ -233,10 +300,9 @@ __global__ void fin_sigma_kernel(const ProbDev* __restrict__ probs) {
   const ProbDev& P = probs[blockIdx.x];
   State* st = P.st;
   if (st->done) return;
-  double a = fixed_sum(P.part_ax, P.nblk_ax, sred);
-  double g = fixed_sum(P.part_gs, P.nblk_gs, sred);
+  const double sigma_all = fixed_sum(P.part_ax, P.nblk_ax, sred);
   if (threadIdx.x == 0) {
-    const double sigma = a + g;
+    const double sigma = sigma_all;
     st->sigma = sigma;
     if (!(sigma > 0.0) || !isfinite(sigma)) {
       st->done = 1;
@@ -392,29 +458,31 @@ __global__ void fill_state_kernel(State* __restrict__ st, int nprob, const State
 // ------------------------------------------------------------ host launchers
 static inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
-hipError_t launch_gs_apply2(int prec_io, int prec_acc, void* v, const int* off, const int* idx,
-                            int ngroups_all, int nfree, int nmask_entries, int mask_first,
-                            bool mask, hipStream_t s) {
-  const int nsum = mask ? nfree : ngroups_all;
-  const int nm = mask ? nmask_entries : 0;
-  const int items = nsum + nm;
-  if (items == 0) return hipSuccess;
-  dim3 g(nblk(items, 256)), b(256);
-  if (prec_io == MXSEM_F64 && prec_acc == MXSEM_F64)
-    hipLaunchKernelGGL((gs_apply_kernel<double, double>), g, b, 0, s, (double*)v, off, idx, nsum,
-                       nfree, nm, mask_first);
-  else if (prec_io == MXSEM_F64 && prec_acc == MXSEM_F32)
-    hipLaunchKernelGGL((gs_apply_kernel<double, float>), g, b, 0, s, (double*)v, off, idx, nsum,
-                       nfree, nm, mask_first);
-  else if (prec_io == MXSEM_F32 && prec_acc == MXSEM_F64)
-    hipLaunchKernelGGL((gs_apply_kernel<float, double>), g, b, 0, s, (float*)v, off, idx, nsum,
-                       nfree, nm, mask_first);
-  else if (prec_io == MXSEM_F32 && prec_acc == MXSEM_F32)
-    hipLaunchKernelGGL((gs_apply_kernel<float, float>), g, b, 0, s, (float*)v, off, idx, nsum,
-                       nfree, nm, mask_first);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+// API gather-scatter: free buckets, then either the Dirichlet-group
+// buckets (no mask) or the mask list.  io/acc: MXSEM_F64 / MXSEM_F32.
+hipError_t launch_gs_apply(int prec_io, int prec_acc, void* v, const GsPlan& plan, bool mask,
+                           hipStream_t s) {
+  const int last = mask ? plan.nfree : plan.nall;
+  for (int bkt = 0; bkt <= plan.nall; ++bkt) {
+    if (bkt >= last && !(mask && bkt == plan.nall)) continue;
+    const int ng = plan.bk[bkt].ngroups;
+    if (ng == 0) continue;
+    GsApi a{v, plan, bkt};
+    dim3 g(nblk(ng, GS_CHUNK)), b(GS_THREADS);
+    if (prec_io == MXSEM_F64 && prec_acc == MXSEM_F64)
+      hipLaunchKernelGGL((gs_kernel<double, double, false>), g, b, 0, s, nullptr, nullptr, a);
+    else if (prec_io == MXSEM_F64 && prec_acc == MXSEM_F32)
+      hipLaunchKernelGGL((gs_kernel<double, float, false>), g, b, 0, s, nullptr, nullptr, a);
+    else if (prec_io == MXSEM_F32 && prec_acc == MXSEM_F64)
+      hipLaunchKernelGGL((gs_kernel<float, double, false>), g, b, 0, s, nullptr, nullptr, a);
+    else if (prec_io == MXSEM_F32 && prec_acc == MXSEM_F32)
+      hipLaunchKernelGGL((gs_kernel<float, float, false>), g, b, 0, s, nullptr, nullptr, a);
+    else
+      return hipErrorInvalidValue;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // vector precision: 0 FP64, 1 FP32 (FP64 accumulation), 3 FP32 (FP32 accumulation)
@@ -422,12 +490,13 @@ hipError_t launch_gs_solver(int vprec, const Tile* tiles, int ntiles, const Prob
                             hipStream_t s) {
   if (ntiles == 0) return hipSuccess;
   dim3 g(ntiles), b(GS_THREADS);
+  GsApi a{};
   if (vprec == 0)
-    hipLaunchKernelGGL((gs_solver_kernel<double, double>), g, b, 0, s, tiles, probs);
+    hipLaunchKernelGGL((gs_kernel<double, double, true>), g, b, 0, s, tiles, probs, a);
   else if (vprec == 1)
-    hipLaunchKernelGGL((gs_solver_kernel<float, double>), g, b, 0, s, tiles, probs);
+    hipLaunchKernelGGL((gs_kernel<float, double, true>), g, b, 0, s, tiles, probs, a);
   else
-    hipLaunchKernelGGL((gs_solver_kernel<float, float>), g, b, 0, s, tiles, probs);
+    hipLaunchKernelGGL((gs_kernel<float, float, true>), g, b, 0, s, tiles, probs, a);
   return hipGetLastError();
 }
 
