@@ -40,7 +40,7 @@ def main():
     ap.add_argument("--mode", default="mixed_ir", choices=["mixed_ir", "mixed_ir_bf16g", "fp64",
                                                            "mixed"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--cpu-iters", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "

@@ -13,6 +13,8 @@
 // Global traffic per local dof: u in, six G values in, w out (plus, in the
 // solver variant, z in and p in/out for the fused p update) - each a fully
 // coalesced n^2-wide stream per k.
+#include <hip/hip_ext.h>
+
 #include "common.hpp"
 
 namespace mx {
@@ -188,25 +190,32 @@ __global__ void __launch_bounds__(256) ax_kernel(const Tile* __restrict__ tiles,
   }
 }
 
+// With ev0/ev1 the launch records its own start and end (hipExtLaunchKernel),
+// so the elapsed time between them is the kernel's execution time.
 template <int N, typename T, typename TG, bool SOLVER>
 static hipError_t launch_one(const Tile* tiles, const ProbDev* probs, const AxApplyArgs& a,
-                             int ntiles, int epb, hipStream_t s) {
+                             int ntiles, int epb, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   constexpr int n = N + 1, n2 = n * n;
   int threads = ((epb * n2 + 63) / 64) * 64;
   if (epb < 1 || threads > 256) return hipErrorInvalidConfiguration;
   size_t shm = sizeof(T) * (n2 + (size_t)epb * 3 * n2);
-  hipLaunchKernelGGL((ax_kernel<N, T, TG, SOLVER>), dim3(ntiles), dim3(threads), shm, s, tiles,
-                     probs, a, epb);
+  if (ev0)
+    hipExtLaunchKernelGGL((ax_kernel<N, T, TG, SOLVER>), dim3(ntiles), dim3(threads), (uint32_t)shm,
+                          s, ev0, ev1, 0, tiles, probs, a, epb);
+  else
+    hipLaunchKernelGGL((ax_kernel<N, T, TG, SOLVER>), dim3(ntiles), dim3(threads), shm, s, tiles,
+                       probs, a, epb);
   return hipGetLastError();
 }
 
 template <typename T, typename TG, bool SOLVER>
 static hipError_t dispatch(int N, const Tile* tiles, const ProbDev* probs, const AxApplyArgs& a,
-                           int ntiles, int epb, hipStream_t s) {
+                           int ntiles, int epb, hipStream_t s, hipEvent_t ev0 = nullptr,
+                           hipEvent_t ev1 = nullptr) {
   switch (N) {
 #define MX_CASE(NN) \
   case NN:          \
-    return launch_one<NN, T, TG, SOLVER>(tiles, probs, a, ntiles, epb, s);
+    return launch_one<NN, T, TG, SOLVER>(tiles, probs, a, ntiles, epb, s, ev0, ev1);
     MX_CASE(1) MX_CASE(2) MX_CASE(3) MX_CASE(4) MX_CASE(5) MX_CASE(6) MX_CASE(7) MX_CASE(8)
     MX_CASE(9) MX_CASE(10) MX_CASE(11) MX_CASE(12) MX_CASE(13) MX_CASE(14) MX_CASE(15)
 #undef MX_CASE
@@ -229,12 +238,12 @@ hipError_t launch_ax_apply(int prec, int N, int E, int epb, const void* u, void*
 }
 
 hipError_t launch_ax_solver(int prec, int N, const Tile* tiles, int ntiles, const ProbDev* probs,
-                            int epb, hipStream_t s) {
+                            int epb, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   AxApplyArgs a{};
   switch (prec) {
-    case 0: return dispatch<double, double, true>(N, tiles, probs, a, ntiles, epb, s);
-    case 1: return dispatch<float, float, true>(N, tiles, probs, a, ntiles, epb, s);
-    case 2: return dispatch<float, bf16_t, true>(N, tiles, probs, a, ntiles, epb, s);
+    case 0: return dispatch<double, double, true>(N, tiles, probs, a, ntiles, epb, s, ev0, ev1);
+    case 1: return dispatch<float, float, true>(N, tiles, probs, a, ntiles, epb, s, ev0, ev1);
+    case 2: return dispatch<float, bf16_t, true>(N, tiles, probs, a, ntiles, epb, s, ev0, ev1);
     default: return hipErrorInvalidValue;
   }
 }

@@ -20,7 +20,8 @@ namespace mx {
 hipError_t launch_ax_apply(int prec, int N, int E, int epb, const void* u, void* w, const void* G,
                            const void* hB, const void* D, hipStream_t s);
 hipError_t launch_ax_solver(int prec, int N, const Tile* tiles, int ntiles, const ProbDev* probs,
-                            int epb, hipStream_t s);
+                            int epb, hipStream_t s, hipEvent_t ev0 = nullptr,
+                            hipEvent_t ev1 = nullptr);
 int max_epb(int N);
 hipError_t launch_gs_apply(int prec_io, int prec_acc, void* v, const GsPlan& plan, bool mask,
                            hipStream_t s);

@@ -215,10 +215,10 @@ static int run_pcg(mxsem_mesh* m, SolverBufs* b, int gprec, int pc, const double
   const int max_launch = maxit / K + 2;
   const int kprec = b->vprec == VP_F64 ? 0 : gprec;
   for (int l = 0; l < max_launch; ++l) {
-    // the chunk's first operator kernel, timed with events on this stream
-    MX_HIP(hipEventRecord(b->evA, s));
-    MX_HIP(launch_ax_solver(kprec, m->N, b->tiles_ax, b->nt_ax, b->probs, b->epb, s));
-    MX_HIP(hipEventRecord(b->evB, s));
+    // the chunk's first operator kernel, launched with its own start/end
+    // events on this stream
+    MX_HIP(launch_ax_solver(kprec, m->N, b->tiles_ax, b->nt_ax, b->probs, b->epb, s, b->evA,
+                            b->evB));
     MX_HIP(hipGraphLaunch(b->graph, s));
     MX_HIP(hipMemcpyAsync(flag, &b->st->done, sizeof(int), hipMemcpyDeviceToHost, s));
     MX_HIP(hipStreamSynchronize(s));
