@@ -226,13 +226,8 @@ int mxsem_mesh_destroy(mxsem_mesh* m) {
   hipSetDevice(m->ctx->device);
   if (m->ctx->stream) hipStreamSynchronize(m->ctx->stream);
   else hipDeviceSynchronize();
-  for (int q = 0; q < 4; ++q)
-    if (m->bufs[q]) {
-      if (m->bufs[q]->graph) hipGraphExecDestroy(m->bufs[q]->graph);
-      if (m->bufs[q]->evA) hipEventDestroy(m->bufs[q]->evA);
-      if (m->bufs[q]->evB) hipEventDestroy(m->bufs[q]->evB);
-      delete m->bufs[q];
-    }
+  mesh_drop_plans(m);
+  for (int q = 0; q < 4; ++q) delete m->bufs[q];
   for (void* p : m->allocs) hipFree(p);
   if (m->counted) m->ctx->live -= 1;
   delete m;

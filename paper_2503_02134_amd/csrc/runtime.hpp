@@ -60,28 +60,53 @@ void deriv_matrix(int N, const double* xi, double* D);
 // vector precision class of a solve
 enum VPrec { VP_F64 = 0, VP_F32 = 1, VP_F32ACC = 3 };
 
-// Device buffers and launch tables of one problem's iteration in one
-// vector precision (the same layout serves the batch, where several
-// problems share the launch tables).
+// Device work vectors and partial-sum arrays of one problem in one vector
+// precision (shared by every launch plan that contains the problem).
 struct SolverBufs {
   int vprec = 0;
   void *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *w = nullptr;
   double *part_ax = nullptr, *part_gs = nullptr, *part_u0 = nullptr, *part_u1 = nullptr,
          *part_u2 = nullptr;
-  State* st = nullptr;
-  ProbDev* probs = nullptr;  // device copy (1 entry)
-  ProbDev host_prob{};
-  State host_state{};        // staging copy for host<->device transfers
-  Tile *tiles_ax = nullptr, *tiles_gs = nullptr, *tiles_upd = nullptr;
-  int nt_ax = 0, nt_gs = 0, nt_upd = 0, epb = 1;
-  // cached graph of K iterations
+  int nt_upd = 0, nt_gs = 0;
+};
+
+// Operator-kernel launch class: problems of one order N and one tile size.
+struct AxClass {
+  int N = 0, epb = 1;
+  Tile* tiles = nullptr;
+  int ntiles = 0;
+};
+
+// Launch plan of the (P)CG iteration for a set of problems in one vector
+// precision: device problem views and states, tile tables spanning all
+// problems, and the cached HIP graph of K iterations.
+struct Plan {
+  int vprec = 0, P = 0, device = 0;
+  std::vector<mxsem_mesh*> meshes;
+  std::vector<SolverBufs*> bufs;
+  std::vector<int> epb_used;       // tile size per problem when built
+  std::vector<ProbDev> hprob;      // host copies
+  ProbDev* probs = nullptr;        // device [P]
+  State* states = nullptr;         // device [P]
+  State* hstate = nullptr;         // pinned host [P]
+  double* dnorm = nullptr;         // device [P] per-problem scalars
+  double* hnorm = nullptr;         // pinned host [P]
+  std::vector<AxClass> ax;
+  Tile* tiles_gs = nullptr;
+  int nt_gs = 0;
+  Tile* tiles_upd = nullptr;
+  int nt_upd = 0;
   hipGraphExec_t graph = nullptr;
-  int graph_k = 0, graph_pc = -1, graph_gprec = -1;
-  // events around the operator kernel of the graph's first iteration
+  int graph_k = 0, graph_pc = -1, graph_gprec = -1, graph_method = -1;
   hipEvent_t evA = nullptr, evB = nullptr;
   double ax_ms_sum = 0.0;
   int ax_samples = 0;
+  std::vector<void*> dev_allocs;
+  // learned preconditioner (flexible CG): per-problem network state
+  std::vector<void*> nn_dev;
 };
+
+void plan_destroy(Plan* pl);
 
 }  // namespace mx
 
@@ -116,6 +141,7 @@ struct mxsem_mesh {
   double* tmpb = nullptr;
   int epb[16] = {0};
   mx::SolverBufs* bufs[4] = {nullptr, nullptr, nullptr, nullptr};
+  mx::Plan* self_plan[4] = {nullptr, nullptr, nullptr, nullptr};
   mxsem_nn* nn = nullptr;
   std::vector<void*> allocs;
   bool counted = false;
@@ -125,7 +151,8 @@ namespace mx {
 int mesh_alloc(mxsem_mesh* m, void** p, size_t bytes);
 int default_epb(int N);
 int ensure_bufs(mxsem_mesh* m, int vprec, SolverBufs** out);
-int retile_ax(mxsem_mesh* m, SolverBufs* b);
+int mesh_epb(const mxsem_mesh* m);
+void mesh_drop_plans(mxsem_mesh* m);
 int ensure_tmp(mxsem_mesh* m);
 const void* G_ptr(const mxsem_mesh* m, int gprec);
 const void* hB_ptr(const mxsem_mesh* m, int gprec);

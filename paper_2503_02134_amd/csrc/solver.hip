@@ -1,19 +1,25 @@
-// (P)CG drivers: FP64, the paper's mixed FP32/FP64 recipe, FP64 iterative
-// refinement around the mixed inner solve, and the FP32-everything
-// ablation.  The iteration itself is captured once per (mesh, precision,
-// preconditioner, chunk) into a HIP graph of K iterations; the host
-// relaunches the graph and polls one device flag per launch.
+// (P)CG drivers for one problem or a batch of problems: FP64, the paper's
+// mixed FP32/FP64 recipe, FP64 iterative refinement around the mixed inner
+// solve, and the FP32-everything ablation.
 //
-// One iteration (PCG in the order of the paper's CG-loop table, Sec. 4.1,
+// One PCG iteration (the recurrence of the paper's CG-loop table, Sec. 4.1,
 // with the vector operations fused):
-//   [ax]   p = z + beta p; w = A_L p; partial (p,w) over element interiors
-//   [gs]   w = M QQ^T w (FP64 sums); partial (p,w)_c over face nodes
-//   [fin]  sigma = (p,w)_c; alpha = rho / sigma       (device scalars, FP64)
+//   [ax]   p = z + beta p; w = A_L p; partial (p, A_L p)
+//   [gs]   w = M QQ^T w  (FP64 sums in every mixed mode)
+//   [fin]  sigma = (p,w)_c; alpha = rho / sigma            (FP64 device scalars)
 //   [upd]  x += alpha p; r -= alpha w; z = M^-1 r; partials (r,z)_c, (r,r)_c
 //   [fin]  convergence / stagnation tests; beta = rho'/rho
+// A launch plan holds, for a set of problems, one tile table per stage that
+// spans every problem (the operator stage has one table per order/tile
+// class) and per-problem device states; K iterations are captured once into
+// a HIP graph that the host relaunches, polling the states once per launch.
+// Problems that have stopped make their tiles return at once, so a batch
+// runs until its slowest member and each member gets the same result as
+// when solved alone with the same tiles (same partial-sum decomposition).
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -21,14 +27,14 @@
 
 namespace mx {
 
-static int vprec_of_mode(int mode) {
+int vprec_of_mode(int mode) {
   switch (mode) {
     case MXSEM_MODE_FP64: return VP_F64;
     case MXSEM_MODE_FP32_ALL: return VP_F32ACC;
     default: return VP_F32;
   }
 }
-static int gprec_of_mode(int mode) {
+int gprec_of_mode(int mode) {
   switch (mode) {
     case MXSEM_MODE_FP64: return 0;
     case MXSEM_MODE_MIXED_IR_BF16G: return 2;
@@ -36,42 +42,22 @@ static int gprec_of_mode(int mode) {
   }
 }
 
-// operator tiles for the mesh's current elements-per-workgroup choice
-int retile_ax(mxsem_mesh* m, SolverBufs* b) {
-  const int epb = m->epb[m->N] > 0 ? m->epb[m->N] : default_epb(m->N);
-  if (epb == b->epb && b->host_prob.nblk_ax == (m->E + epb - 1) / epb) return MXSEM_OK;
-  b->epb = epb;
-  b->nt_ax = (m->E + epb - 1) / epb;
-  std::vector<Tile> ta(b->nt_ax);
-  for (int q = 0; q < b->nt_ax; ++q) ta[q] = Tile{0, q * epb, 0, 0};
-  MX_HIP(hipMemcpy(b->tiles_ax, ta.data(), sizeof(Tile) * ta.size(), hipMemcpyHostToDevice));
-  b->host_prob.nblk_ax = b->nt_ax;
-  if (b->graph) {
-    MX_HIP(hipGraphExecDestroy(b->graph));
-    b->graph = nullptr;
-  }
-  return MXSEM_OK;
-}
+int mesh_epb(const mxsem_mesh* m) { return m->epb[m->N] > 0 ? m->epb[m->N] : default_epb(m->N); }
 
 int ensure_bufs(mxsem_mesh* m, int vprec, SolverBufs** out) {
   if (m->bufs[vprec]) {
     *out = m->bufs[vprec];
-    return retile_ax(m, *out);
+    return MXSEM_OK;
   }
   SolverBufs* b = new SolverBufs();
   b->vprec = vprec;
   const size_t es = vprec == VP_F64 ? 8 : 4;
   const int64_t nl = m->nloc;
-  b->epb = m->epb[m->N] > 0 ? m->epb[m->N] : default_epb(m->N);
-  b->nt_ax = (m->E + b->epb - 1) / b->epb;
-  // gather-scatter tiles: free buckets and the mask list
-  std::vector<Tile> tg;
-  for (int q = 0; q <= m->plan.nall; ++q) {
-    if (q >= m->plan.nfree && q < m->plan.nall) continue;
-    const int ngq = m->plan.bk[q].ngroups;
-    for (int f = 0; f < ngq; f += GS_CHUNK) tg.push_back(Tile{0, f, q, 0});
-  }
-  b->nt_gs = (int)tg.size();
+  int ngs = 0;
+  for (int q = 0; q <= m->plan.nall; ++q)
+    if (q < m->plan.nfree || q == m->plan.nall)
+      ngs += (m->plan.bk[q].ngroups + GS_CHUNK - 1) / GS_CHUNK;
+  b->nt_gs = ngs;
   b->nt_upd = (int)((nl + UPD_CHUNK - 1) / UPD_CHUNK);
   int rc = MXSEM_OK;
   auto A = [&](void** p, size_t bytes) {
@@ -82,86 +68,192 @@ int ensure_bufs(mxsem_mesh* m, int vprec, SolverBufs** out) {
   A(&b->z, es * nl);
   A(&b->p, es * nl);
   A(&b->w, es * nl);
-  A((void**)&b->part_ax, sizeof(double) * (m->E + 1));  // any epb fits
+  A((void**)&b->part_ax, sizeof(double) * (m->E + 1));  // any tile size fits
   A((void**)&b->part_gs, sizeof(double) * (b->nt_gs + 1));
   A((void**)&b->part_u0, sizeof(double) * (b->nt_upd + 1));
   A((void**)&b->part_u1, sizeof(double) * (b->nt_upd + 1));
   A((void**)&b->part_u2, sizeof(double) * (b->nt_upd + b->nt_gs + 1));
-  A((void**)&b->st, sizeof(State));
-  A((void**)&b->probs, sizeof(ProbDev));
-  A((void**)&b->tiles_ax, sizeof(Tile) * (m->E + 1));
-  A((void**)&b->tiles_gs, sizeof(Tile) * (b->nt_gs + 1));
-  A((void**)&b->tiles_upd, sizeof(Tile) * (b->nt_upd + 1));
   if (rc != MXSEM_OK) {
     delete b;
     return rc;
   }
-  hipStream_t s = m->ctx->stream;
-  std::vector<Tile> ta(b->nt_ax), tu(b->nt_upd);
-  for (int q = 0; q < b->nt_ax; ++q) ta[q] = Tile{0, q * b->epb, 0, 0};
-  for (int q = 0; q < b->nt_upd; ++q) tu[q] = Tile{0, q * UPD_CHUNK, 0, 0};
-  MX_HIP(hipMemcpyAsync(b->tiles_ax, ta.data(), sizeof(Tile) * ta.size(), hipMemcpyHostToDevice, s));
-  if (!tg.empty())
-    MX_HIP(hipMemcpyAsync(b->tiles_gs, tg.data(), sizeof(Tile) * tg.size(), hipMemcpyHostToDevice, s));
-  MX_HIP(hipMemcpyAsync(b->tiles_upd, tu.data(), sizeof(Tile) * tu.size(), hipMemcpyHostToDevice, s));
-  MX_HIP(hipStreamSynchronize(s));
-  ProbDev& P = b->host_prob;
-  memset(&P, 0, sizeof(P));
-  P.E = m->E;
-  P.n3 = m->n3;
-  P.nloc = nl;
-  P.D = vprec == VP_F64 ? (const void*)m->D64 : (const void*)m->D32;
-  P.dinv = vprec == VP_F64 ? (const void*)m->dinv64 : (const void*)m->dinv32;
-  P.mult = m->mult;
-  P.gs = m->plan;
-  P.x = b->x;
-  P.r = b->r;
-  P.z = b->z;
-  P.p = b->p;
-  P.w = b->w;
-  P.part_ax = b->part_ax;
-  P.part_gs = b->part_gs;
-  P.part_u0 = b->part_u0;
-  P.part_u1 = b->part_u1;
-  P.part_u2 = b->part_u2;
-  P.nblk_ax = b->nt_ax;
-  P.nblk_gs = b->nt_gs;
-  P.nblk_upd = b->nt_upd;
-  P.st = b->st;
   m->bufs[vprec] = b;
   *out = b;
   return MXSEM_OK;
 }
 
-// enqueue one iteration; head = false leaves out the operator kernel (the
-// first iteration of a graph chunk launches it outside the graph, between
-// two timing events)
-static int enqueue_iteration(mxsem_mesh* m, SolverBufs* b, int gprec, int pc, hipStream_t s,
-                             bool head = true) {
-  const int kprec = b->vprec == VP_F64 ? 0 : gprec;  // operator kernel variant
-  if (head) MX_HIP(launch_ax_solver(kprec, m->N, b->tiles_ax, b->nt_ax, b->probs, b->epb, s));
-  MX_HIP(launch_gs_solver(b->vprec, b->tiles_gs, b->nt_gs, b->probs, s));
-  MX_HIP(launch_fin_sigma(b->probs, 1, s));
-  MX_HIP(launch_update(b->vprec, pc, b->tiles_upd, b->nt_upd, b->probs, s));
-  MX_HIP(launch_fin_rho(b->probs, 1, 0, s));
+void plan_destroy(Plan* pl) {
+  if (!pl) return;
+  if (pl->graph) hipGraphExecDestroy(pl->graph);
+  if (pl->evA) hipEventDestroy(pl->evA);
+  if (pl->evB) hipEventDestroy(pl->evB);
+  if (pl->hstate) hipHostFree(pl->hstate);
+  if (pl->hnorm) hipHostFree(pl->hnorm);
+  for (void* p : pl->dev_allocs) hipFree(p);
+  delete pl;
+}
+
+void mesh_drop_plans(mxsem_mesh* m) {
+  for (int q = 0; q < 4; ++q) {
+    plan_destroy(m->self_plan[q]);
+    m->self_plan[q] = nullptr;
+  }
+}
+
+static int plan_alloc(Plan* pl, void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes ? bytes : 256);
+  if (e != hipSuccess) {
+    set_error(std::string("plan: hipMalloc: ") + hipGetErrorString(e));
+    return MXSEM_ENOMEM;
+  }
+  pl->dev_allocs.push_back(*p);
   return MXSEM_OK;
 }
 
-static int get_graph(mxsem_mesh* m, SolverBufs* b, int gprec, int pc, int K) {
-  if (b->graph && b->graph_k == K && b->graph_pc == pc && b->graph_gprec == gprec) return MXSEM_OK;
-  if (b->graph) {
-    MX_HIP(hipGraphExecDestroy(b->graph));
-    b->graph = nullptr;
+// Build the launch plan of P problems (all on one context) in vprec.
+int plan_build(mxsem_mesh* const* meshes, int P, int vprec, Plan** out) {
+  Plan* pl = new Plan();
+  pl->vprec = vprec;
+  pl->P = P;
+  pl->device = meshes[0]->ctx->device;
+  int rc = MXSEM_OK;
+  auto fail = [&](int code) {
+    plan_destroy(pl);
+    return code;
+  };
+  std::vector<Tile> tg, tu;
+  pl->hprob.resize(P);
+  for (int p = 0; p < P; ++p) {
+    mxsem_mesh* m = meshes[p];
+    SolverBufs* b = nullptr;
+    rc = ensure_bufs(m, vprec, &b);
+    if (rc != MXSEM_OK) return fail(rc);
+    pl->meshes.push_back(m);
+    pl->bufs.push_back(b);
+    pl->epb_used.push_back(mesh_epb(m));
+    ProbDev& Q = pl->hprob[p];
+    memset(&Q, 0, sizeof(Q));
+    Q.E = m->E;
+    Q.n3 = m->n3;
+    Q.nloc = m->nloc;
+    Q.D = vprec == VP_F64 ? (const void*)m->D64 : (const void*)m->D32;
+    Q.dinv = vprec == VP_F64 ? (const void*)m->dinv64 : (const void*)m->dinv32;
+    Q.mult = m->mult;
+    Q.gs = m->plan;
+    Q.x = b->x;
+    Q.r = b->r;
+    Q.z = b->z;
+    Q.p = b->p;
+    Q.w = b->w;
+    Q.part_ax = b->part_ax;
+    Q.part_gs = b->part_gs;
+    Q.part_u0 = b->part_u0;
+    Q.part_u1 = b->part_u1;
+    Q.part_u2 = b->part_u2;
+    Q.nblk_ax = (m->E + pl->epb_used[p] - 1) / pl->epb_used[p];
+    Q.nblk_gs = b->nt_gs;
+    Q.nblk_upd = b->nt_upd;
+    for (int q = 0; q <= m->plan.nall; ++q) {
+      if (q >= m->plan.nfree && q < m->plan.nall) continue;
+      for (int f = 0; f < m->plan.bk[q].ngroups; f += GS_CHUNK) tg.push_back(Tile{p, f, q, 0});
+    }
+    for (int q = 0; q < b->nt_upd; ++q) tu.push_back(Tile{p, q * UPD_CHUNK, 0, 0});
   }
-  hipStream_t cs = m->ctx->capture;
+  // operator classes (N, tile size)
+  std::vector<std::pair<int, int>> keys;
+  for (int p = 0; p < P; ++p) {
+    std::pair<int, int> k{meshes[p]->N, pl->epb_used[p]};
+    if (std::find(keys.begin(), keys.end(), k) == keys.end()) keys.push_back(k);
+  }
+  std::sort(keys.begin(), keys.end());
+  std::vector<std::vector<Tile>> ta(keys.size());
+  for (int p = 0; p < P; ++p) {
+    const int c = (int)(std::find(keys.begin(), keys.end(),
+                                  std::pair<int, int>{meshes[p]->N, pl->epb_used[p]}) -
+                        keys.begin());
+    const int epb = pl->epb_used[p];
+    for (int e = 0; e < meshes[p]->E; e += epb) ta[c].push_back(Tile{p, e, 0, 0});
+  }
+  for (size_t c = 0; c < keys.size(); ++c) {
+    AxClass ac;
+    ac.N = keys[c].first;
+    ac.epb = keys[c].second;
+    ac.ntiles = (int)ta[c].size();
+    if ((rc = plan_alloc(pl, (void**)&ac.tiles, sizeof(Tile) * ac.ntiles)) != MXSEM_OK)
+      return fail(rc);
+    if (hipMemcpy(ac.tiles, ta[c].data(), sizeof(Tile) * ac.ntiles, hipMemcpyHostToDevice) !=
+        hipSuccess) {
+      set_error("plan: tile upload failed");
+      return fail(MXSEM_EHIP);
+    }
+    pl->ax.push_back(ac);
+  }
+  pl->nt_gs = (int)tg.size();
+  pl->nt_upd = (int)tu.size();
+  if ((rc = plan_alloc(pl, (void**)&pl->tiles_gs, sizeof(Tile) * (tg.size() + 1))) != MXSEM_OK ||
+      (rc = plan_alloc(pl, (void**)&pl->tiles_upd, sizeof(Tile) * (tu.size() + 1))) != MXSEM_OK ||
+      (rc = plan_alloc(pl, (void**)&pl->probs, sizeof(ProbDev) * P)) != MXSEM_OK ||
+      (rc = plan_alloc(pl, (void**)&pl->states, sizeof(State) * P)) != MXSEM_OK ||
+      (rc = plan_alloc(pl, (void**)&pl->dnorm, sizeof(double) * P)) != MXSEM_OK)
+    return fail(rc);
+  for (int p = 0; p < P; ++p) pl->hprob[p].st = pl->states + p;
+  if ((!tg.empty() &&
+       hipMemcpy(pl->tiles_gs, tg.data(), sizeof(Tile) * tg.size(), hipMemcpyHostToDevice) !=
+           hipSuccess) ||
+      hipMemcpy(pl->tiles_upd, tu.data(), sizeof(Tile) * tu.size(), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipHostMalloc((void**)&pl->hstate, sizeof(State) * P, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&pl->hnorm, sizeof(double) * P, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreate(&pl->evA) != hipSuccess || hipEventCreate(&pl->evB) != hipSuccess) {
+    set_error("plan: tile upload / host buffers failed");
+    return fail(MXSEM_EHIP);
+  }
+  *out = pl;
+  return MXSEM_OK;
+}
+
+bool plan_stale(const Plan* pl) {
+  for (int p = 0; p < pl->P; ++p)
+    if (pl->epb_used[p] != mesh_epb(pl->meshes[p])) return true;
+  return false;
+}
+
+// operator launches of one iteration; skip_first: the first class is
+// launched by the caller (timed)
+int enqueue_ax(Plan* pl, int gprec, hipStream_t s, bool skip_first) {
+  const int kprec = pl->vprec == VP_F64 ? 0 : gprec;
+  for (size_t c = skip_first ? 1 : 0; c < pl->ax.size(); ++c) {
+    const AxClass& ac = pl->ax[c];
+    MX_HIP(launch_ax_solver(kprec, ac.N, ac.tiles, ac.ntiles, pl->probs, ac.epb, s));
+  }
+  return MXSEM_OK;
+}
+
+static int enqueue_tail(Plan* pl, int pc, hipStream_t s) {
+  MX_HIP(launch_gs_solver(pl->vprec, pl->tiles_gs, pl->nt_gs, pl->probs, s));
+  MX_HIP(launch_fin_sigma(pl->probs, pl->P, s));
+  MX_HIP(launch_update(pl->vprec, pc, pl->tiles_upd, pl->nt_upd, pl->probs, s));
+  MX_HIP(launch_fin_rho(pl->probs, pl->P, 0, s));
+  return MXSEM_OK;
+}
+
+// K iterations; the first iteration's operator launches stay outside
+static int get_graph(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K) {
+  if (pl->graph && pl->graph_k == K && pl->graph_pc == pc && pl->graph_gprec == gprec &&
+      pl->graph_method == MXSEM_METHOD_PCG)
+    return MXSEM_OK;
+  if (pl->graph) {
+    MX_HIP(hipGraphExecDestroy(pl->graph));
+    pl->graph = nullptr;
+  }
+  hipStream_t cs = ctx->capture;
   hipGraph_t g = nullptr;
-  if (!b->evA) {
-    MX_HIP(hipEventCreate(&b->evA));
-    MX_HIP(hipEventCreate(&b->evB));
-  }
   MX_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   int rc = MXSEM_OK;
-  for (int k = 0; k < K && rc == MXSEM_OK; ++k) rc = enqueue_iteration(m, b, gprec, pc, cs, k > 0);
+  for (int k = 0; k < K && rc == MXSEM_OK; ++k) {
+    if (k > 0) rc = enqueue_ax(pl, gprec, cs, false);
+    if (rc == MXSEM_OK) rc = enqueue_tail(pl, pc, cs);
+  }
   hipError_t e = hipStreamEndCapture(cs, &g);
   if (rc != MXSEM_OK) {
     if (g) hipGraphDestroy(g);
@@ -171,97 +263,312 @@ static int get_graph(mxsem_mesh* m, SolverBufs* b, int gprec, int pc, int K) {
     set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
     return MXSEM_EHIP;
   }
-  e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(&pl->graph, g, nullptr, nullptr, 0);
   hipGraphDestroy(g);
   if (e != hipSuccess) {
     set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-    b->graph = nullptr;
+    pl->graph = nullptr;
     return MXSEM_EHIP;
   }
-  b->graph_k = K;
-  b->graph_pc = pc;
-  b->graph_gprec = gprec;
+  pl->graph_k = K;
+  pl->graph_pc = pc;
+  pl->graph_gprec = gprec;
+  pl->graph_method = MXSEM_METHOD_PCG;
   return MXSEM_OK;
 }
 
-struct InnerResult {
-  int iterations = 0;
-  int reason = 0;
-  double res = 0.0;
+// Inner (P)CG on the active problems: r = rhs[p] * scale[p], x = 0,
+// relative tolerance tol[p], at most maxit[p] iterations.  Inactive
+// problems are marked done and their tiles return at once.
+struct Inner {
+  std::vector<const double*> rhs;
+  std::vector<double> scale, tol;
+  std::vector<int> maxit;
+  std::vector<char> active;
+  double* history = nullptr;  // single-problem plans only
+  // results
+  std::vector<int> iterations, reason;
+  std::vector<double> res;
 };
 
-// One (P)CG solve on the device from r = rhs64 * scale (x = x0 or 0),
-// relative tolerance tol, at most maxit iterations.
-static int run_pcg(mxsem_mesh* m, SolverBufs* b, int gprec, int pc, const double* rhs64,
-                   double scale, const double* x0, double tol, int maxit, int K, double* history,
-                   InnerResult* res) {
-  hipStream_t s = m->ctx->stream;
-  b->host_prob.rhs64 = rhs64;
-  b->host_prob.rhs_scale = scale;
-  b->host_prob.G = G_ptr(m, b->vprec == VP_F64 ? 0 : gprec);
-  b->host_prob.hB = hB_ptr(m, b->vprec == VP_F64 ? 0 : gprec);
-  MX_HIP(hipMemcpyAsync(b->probs, &b->host_prob, sizeof(ProbDev), hipMemcpyHostToDevice, s));
-  State& st = b->host_state;
-  memset(&st, 0, sizeof(st));
-  st.tol2 = tol * tol;
-  st.maxit = maxit;
-  st.history = history;
-  st.pc = pc;
-  MX_HIP(hipMemcpyAsync(b->st, &st, sizeof(State), hipMemcpyHostToDevice, s));
-  MX_HIP(launch_init(b->vprec, pc, b->tiles_upd, b->nt_upd, b->probs, x0, s));
-  MX_HIP(launch_fin_rho(b->probs, 1, 1, s));
-  MX_TRY(get_graph(m, b, gprec, pc, K));
-  int* flag = m->ctx->pinned_flags;
-  const int max_launch = maxit / K + 2;
-  const int kprec = b->vprec == VP_F64 ? 0 : gprec;
+static int run_inner(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K, Inner& in) {
+  hipStream_t s = ctx->stream;
+  const int P = pl->P;
+  int max_launch = 0;
+  for (int p = 0; p < P; ++p) {
+    State& st = pl->hstate[p];
+    memset(&st, 0, sizeof(State));
+    st.tol2 = in.tol[p] * in.tol[p];
+    st.maxit = in.maxit[p];
+    st.history = (P == 1) ? in.history : nullptr;
+    st.pc = pc;
+    st.done = in.active[p] ? 0 : 1;
+    st.reason = in.active[p] ? 0 : MXSEM_CONVERGED;
+    ProbDev& Q = pl->hprob[p];
+    mxsem_mesh* m = pl->meshes[p];
+    const int gp = pl->vprec == VP_F64 ? 0 : gprec;
+    Q.rhs64 = in.rhs[p];
+    Q.rhs_scale = in.scale[p];
+    Q.G = G_ptr(m, gp);
+    Q.hB = hB_ptr(m, gp);
+    if (in.active[p]) max_launch = std::max(max_launch, in.maxit[p] / K + 2);
+  }
+  MX_HIP(hipMemcpyAsync(pl->probs, pl->hprob.data(), sizeof(ProbDev) * P, hipMemcpyHostToDevice, s));
+  MX_HIP(hipMemcpyAsync(pl->states, pl->hstate, sizeof(State) * P, hipMemcpyHostToDevice, s));
+  MX_HIP(launch_init(pl->vprec, pc, pl->tiles_upd, pl->nt_upd, pl->probs, nullptr, s));
+  MX_HIP(launch_fin_rho(pl->probs, P, 1, s));
+  MX_TRY(get_graph(pl, ctx, gprec, pc, K));
+  const int kprec = pl->vprec == VP_F64 ? 0 : gprec;
   for (int l = 0; l < max_launch; ++l) {
-    // the chunk's first operator kernel, launched with its own start/end
-    // events on this stream
-    MX_HIP(launch_ax_solver(kprec, m->N, b->tiles_ax, b->nt_ax, b->probs, b->epb, s, b->evA,
-                            b->evB));
-    MX_HIP(hipGraphLaunch(b->graph, s));
-    MX_HIP(hipMemcpyAsync(flag, &b->st->done, sizeof(int), hipMemcpyDeviceToHost, s));
+    // the chunk's first operator launch of class 0, with its own start/end events
+    const AxClass& a0 = pl->ax[0];
+    MX_HIP(launch_ax_solver(kprec, a0.N, a0.tiles, a0.ntiles, pl->probs, a0.epb, s, pl->evA,
+                            pl->evB));
+    MX_TRY(enqueue_ax(pl, gprec, s, true));
+    MX_HIP(hipGraphLaunch(pl->graph, s));
+    MX_HIP(hipMemcpyAsync(pl->hstate, pl->states, sizeof(State) * P, hipMemcpyDeviceToHost, s));
     MX_HIP(hipStreamSynchronize(s));
     float ms = 0.f;
-    MX_HIP(hipEventElapsedTime(&ms, b->evA, b->evB));
-    b->ax_ms_sum += ms;
-    b->ax_samples += 1;
-    if (flag[0]) break;
+    MX_HIP(hipEventElapsedTime(&ms, pl->evA, pl->evB));
+    pl->ax_ms_sum += ms;
+    pl->ax_samples += 1;
+    bool all = true;
+    for (int p = 0; p < P; ++p) all = all && pl->hstate[p].done;
+    if (all) break;
   }
-  MX_HIP(hipMemcpyAsync(&st, b->st, sizeof(State), hipMemcpyDeviceToHost, s));
-  MX_HIP(hipStreamSynchronize(s));
-  res->iterations = st.iter;
-  res->reason = st.done ? st.reason : MXSEM_MAX_ITER;
-  res->res = st.res;
+  in.iterations.assign(P, 0);
+  in.reason.assign(P, 0);
+  in.res.assign(P, 0.0);
+  for (int p = 0; p < P; ++p) {
+    if (!in.active[p]) continue;
+    const State& st = pl->hstate[p];
+    in.iterations[p] = st.iter;
+    in.reason[p] = st.done ? st.reason : MXSEM_MAX_ITER;
+    in.res[p] = st.res;
+  }
   return MXSEM_OK;
 }
 
-// r = b - A64 x  (FP64 operator with FP64 G); returns ||r||_c via host
-static int fp64_residual(mxsem_mesh* m, const double* b, const double* x, double* r,
-                         double* norm) {
+// per-problem FP64 scalars, one host synchronisation for all problems
+static int norms_of(Plan* pl, mxsem_ctx* ctx, std::vector<double>& out) {
+  hipStream_t s = ctx->stream;
+  MX_HIP(hipMemcpyAsync(pl->hnorm, pl->dnorm, sizeof(double) * pl->P, hipMemcpyDeviceToHost, s));
+  MX_HIP(hipStreamSynchronize(s));
+  out.assign(pl->hnorm, pl->hnorm + pl->P);
+  return MXSEM_OK;
+}
+
+// r = b - A64 x of problem p, (r,r)_c into pl->dnorm[p] (async); w: work
+static int residual64(Plan* pl, int p, const double* b, const double* x, double* r, double* w) {
+  mxsem_mesh* m = pl->meshes[p];
   hipStream_t s = m->ctx->stream;
-  MX_TRY(ensure_tmp(m));
-  double* w = (r == m->tmpa) ? m->tmpb : m->tmpa;
   MX_TRY(apply_impl(m, MXSEM_F64, x, w, 0, s));
-  MX_HIP(launch_residual(b, w, r, m->mult, m->nloc, m->part, m->scal, s));
-  double rr = 0.0;
-  MX_HIP(hipMemcpyAsync(&rr, m->scal, sizeof(double), hipMemcpyDeviceToHost, s));
-  MX_HIP(hipStreamSynchronize(s));
-  *norm = sqrt(rr);
+  MX_HIP(launch_residual(b, w, r, m->mult, m->nloc, m->part, pl->dnorm + p, s));
   return MXSEM_OK;
 }
 
-static int host_dot64(mxsem_mesh* m, const double* a, const double* b, double* out) {
-  hipStream_t s = m->ctx->stream;
-  MX_HIP(launch_dot(MXSEM_F64, a, b, m->mult, m->nloc, m->part, m->scal + 1, s));
-  MX_HIP(hipMemcpyAsync(out, m->scal + 1, sizeof(double), hipMemcpyDeviceToHost, s));
-  MX_HIP(hipStreamSynchronize(s));
+int get_self_plan(mxsem_mesh* m, int vprec, Plan** out) {
+  if (m->self_plan[vprec] && plan_stale(m->self_plan[vprec])) {
+    plan_destroy(m->self_plan[vprec]);
+    m->self_plan[vprec] = nullptr;
+  }
+  if (!m->self_plan[vprec]) MX_TRY(plan_build(&m, 1, vprec, &m->self_plan[vprec]));
+  *out = m->self_plan[vprec];
+  return MXSEM_OK;
+}
+
+// Solve every problem of a problem set; get(vprec, &plan) supplies the
+// launch plan of the set in a vector precision.
+template <typename GetPlan>
+static int solve_many(mxsem_ctx* ctx, const std::vector<mxsem_mesh*>& meshes, GetPlan get,
+                      const mxsem_solve_opts* o, const double* const* b, double* const* x,
+                      mxsem_solve_stats* st) {
+  const int P = (int)meshes.size();
+  const int mode = o->mode;
+  const int vprec = vprec_of_mode(mode);
+  const int gprec = gprec_of_mode(mode);
+  hipStream_t s = ctx->stream;
+  for (int p = 0; p < P; ++p) {
+    mxsem_mesh* m = meshes[p];
+    if (vprec != VP_F64)
+      MX_CHECK(m->dinv32 && (gprec == 2 || m->G32), MXSEM_ENOTSUP, "solve: mesh has no FP32 view");
+    if (gprec == 2) MX_CHECK(m->G16, MXSEM_ENOTSUP, "solve: mesh has no BF16 view");
+    MX_TRY(ensure_tmp(m));
+    memset(&st[p], 0, sizeof(mxsem_solve_stats));
+  }
+  Plan* pl = nullptr;
+  MX_TRY(get(vprec, &pl));
+  pl->ax_ms_sum = 0.0;
+  pl->ax_samples = 0;
+  MX_HIP(hipEventRecord(ctx->ev0, s));
+  // ||b||_c per problem
+  std::vector<double> bnorm;
+  for (int p = 0; p < P; ++p)
+    MX_HIP(launch_dot(MXSEM_F64, b[p], b[p], meshes[p]->mult, meshes[p]->nloc, meshes[p]->part,
+                      pl->dnorm + p, s));
+  MX_TRY(norms_of(pl, ctx, bnorm));
+  for (double& v : bnorm) v = sqrt(v);
+  const bool ir = mode == MXSEM_MODE_MIXED_IR || mode == MXSEM_MODE_MIXED_IR_BF16G;
+  const int xv = vprec == VP_F64 ? 0 : 1;
+  Inner in;
+  in.rhs.assign(P, nullptr);
+  in.scale.assign(P, 1.0);
+  in.tol.assign(P, o->tol);
+  in.maxit.assign(P, o->max_iter);
+  in.active.assign(P, 1);
+  in.history = o->history;
+  std::vector<char> fallback(P, 0);
+  if (!ir) {
+    std::vector<double> rn(P, 0.0);
+    if (o->x0_given) {
+      // solve A d = b - A x0 and add d: the iterates of a solve started at x0
+      for (int p = 0; p < P; ++p)
+        MX_TRY(residual64(pl, p, b[p], x[p], meshes[p]->tmpa, meshes[p]->tmpb));
+      MX_TRY(norms_of(pl, ctx, rn));
+      for (int p = 0; p < P; ++p) {
+        rn[p] = sqrt(rn[p]);
+        in.rhs[p] = meshes[p]->tmpa;
+        in.tol[p] = rn[p] > 0 ? o->tol * bnorm[p] / rn[p] : o->tol;
+      }
+    } else {
+      for (int p = 0; p < P; ++p) in.rhs[p] = b[p];
+    }
+    MX_TRY(run_inner(pl, ctx, gprec, o->pc, o->graph_chunk, in));
+    for (int p = 0; p < P; ++p) {
+      MX_HIP(launch_axpy_cast(xv, x[p], pl->bufs[p]->x, 1.0, o->x0_given ? 1.0 : 0.0,
+                              meshes[p]->nloc, s));
+      st[p].iterations = in.iterations[p];
+      st[p].reason = in.reason[p];
+      st[p].rel_res_recursive = in.res[p];
+    }
+  } else {
+    // FP64 iterative refinement: r = b - A64 x; d = inner mixed PCG on r/s; x += s d
+    std::vector<int> total(P, 0), outer(P, 0), slow(P, 0), live(P, 1);
+    std::vector<double> prev(P, -1.0), rn;
+    for (int p = 0; p < P; ++p) {
+      if (!o->x0_given) MX_HIP(launch_zero(x[p], meshes[p]->nloc, s));
+      st[p].reason = MXSEM_MAX_ITER;
+    }
+    for (;;) {
+      bool any = false;
+      for (int p = 0; p < P; ++p)
+        if (live[p]) MX_TRY(residual64(pl, p, b[p], x[p], meshes[p]->tmpa, meshes[p]->tmpb));
+      MX_TRY(norms_of(pl, ctx, rn));
+      for (int p = 0; p < P; ++p) {
+        in.active[p] = 0;
+        if (!live[p]) continue;
+        const double r = sqrt(rn[p]);
+        const double rel = bnorm[p] > 0 ? r / bnorm[p] : 0.0;
+        if (rel <= o->tol) {
+          st[p].reason = MXSEM_CONVERGED;
+          live[p] = 0;
+          continue;
+        }
+        if (outer[p] >= o->max_outer || total[p] >= o->max_iter) {
+          live[p] = 0;
+          continue;
+        }
+        if (prev[p] > 0 && rel > 0.5 * prev[p]) ++slow[p];
+        prev[p] = rel;
+        if (slow[p] >= 2) {  // refinement stopped contracting: finish in FP64
+          fallback[p] = 1;
+          live[p] = 0;
+          continue;
+        }
+        in.active[p] = 1;
+        in.rhs[p] = meshes[p]->tmpa;
+        in.scale[p] = 1.0 / r;
+        in.tol[p] = fmax(o->inner_tol, o->tol * bnorm[p] / r);
+        in.maxit[p] = o->max_iter - total[p];
+        rn[p] = r;
+        any = true;
+      }
+      if (!any) break;
+      MX_TRY(run_inner(pl, ctx, gprec, o->pc, o->graph_chunk, in));
+      for (int p = 0; p < P; ++p) {
+        if (!in.active[p]) continue;
+        MX_HIP(launch_axpy_cast(1, x[p], pl->bufs[p]->x, rn[p], 1.0, meshes[p]->nloc, s));
+        total[p] += in.iterations[p];
+        st[p].rel_res_recursive = in.res[p];
+        ++outer[p];
+        if (in.reason[p] == MXSEM_BREAKDOWN) {
+          st[p].reason = MXSEM_BREAKDOWN;
+          live[p] = 0;
+        }
+      }
+    }
+    for (int p = 0; p < P; ++p) {
+      st[p].iterations = total[p];
+      st[p].outer = outer[p];
+    }
+    // problems whose refinement stalled: FP64 PCG from the current x
+    bool anyf = false;
+    for (int p = 0; p < P; ++p) anyf = anyf || fallback[p];
+    if (anyf) {
+      Plan* p64 = nullptr;
+      MX_TRY(get(VP_F64, &p64));
+      Inner f;
+      f.rhs.assign(P, nullptr);
+      f.scale.assign(P, 1.0);
+      f.tol.assign(P, o->tol);
+      f.maxit.assign(P, 1);
+      f.active.assign(P, 0);
+      for (int p = 0; p < P; ++p)
+        if (fallback[p]) MX_TRY(residual64(p64, p, b[p], x[p], meshes[p]->tmpa, meshes[p]->tmpb));
+      std::vector<double> fr;
+      MX_TRY(norms_of(p64, ctx, fr));
+      for (int p = 0; p < P; ++p) {
+        if (!fallback[p]) continue;
+        const double r = sqrt(fr[p]);
+        f.active[p] = 1;
+        f.rhs[p] = meshes[p]->tmpa;
+        f.tol[p] = r > 0 ? o->tol * bnorm[p] / r : o->tol;
+        f.maxit[p] = std::max(1, o->max_iter - st[p].iterations);
+      }
+      MX_TRY(run_inner(p64, ctx, 0, o->pc, o->graph_chunk, f));
+      for (int p = 0; p < P; ++p) {
+        if (!fallback[p]) continue;
+        MX_HIP(launch_axpy_cast(0, x[p], p64->bufs[p]->x, 1.0, 1.0, meshes[p]->nloc, s));
+        st[p].iterations += f.iterations[p];
+        st[p].reason = f.reason[p];
+        st[p].fallback_used = 1;
+        st[p].rel_res_recursive = f.res[p];
+      }
+    }
+  }
+  // true FP64 residuals
+  std::vector<double> tr;
+  for (int p = 0; p < P; ++p)
+    MX_TRY(residual64(pl, p, b[p], x[p], meshes[p]->tmpb, meshes[p]->tmpa));
+  MX_TRY(norms_of(pl, ctx, tr));
+  MX_HIP(hipEventRecord(ctx->ev1, s));
+  MX_HIP(hipEventSynchronize(ctx->ev1));
+  float ms = 0.f;
+  MX_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  bool breakdown = false;
+  for (int p = 0; p < P; ++p) {
+    st[p].rel_res = bnorm[p] > 0 ? sqrt(tr[p]) / bnorm[p] : 0.0;
+    st[p].ms = ms;
+    st[p].ax_samples = pl->ax_samples;
+    st[p].ax_ms = pl->ax_samples ? pl->ax_ms_sum / pl->ax_samples : 0.0;
+    breakdown = breakdown || st[p].reason == MXSEM_BREAKDOWN;
+  }
+  if (breakdown) {
+    set_error("solve: (p, A p) <= 0 or non-finite");
+    return MXSEM_EBREAKDOWN;
+  }
   return MXSEM_OK;
 }
 
 }  // namespace mx
 
 using namespace mx;
+
+struct mxsem_batch {
+  mxsem_ctx* ctx = nullptr;
+  std::vector<mxsem_mesh*> meshes;
+  mx::Plan* plans[4] = {nullptr, nullptr, nullptr, nullptr};
+};
 
 extern "C" {
 
@@ -300,123 +607,108 @@ int mxsem_precond(mxsem_mesh* m, mxsem_pc pc, mxsem_prec io, const void* r, void
 int mxsem_fcg_solve_impl(mxsem_mesh* m, const mxsem_solve_opts* o, const double* b, double* x,
                          mxsem_solve_stats* st);
 
-int mxsem_solve(mxsem_mesh* m, const mxsem_solve_opts* o, const double* b, double* x,
-                mxsem_solve_stats* st) {
-  MX_CHECK(m && o && b && x && st, MXSEM_EINVAL, "solve: null argument");
-  MX_CHECK(o->tol >= 0.0 && o->max_iter >= 1 && o->graph_chunk >= 1, MXSEM_EINVAL,
-           "solve: bad tol / max_iter / graph_chunk");
+static int check_opts(const mxsem_solve_opts* o) {
+  MX_CHECK(o->tol >= 0.0 && o->max_iter >= 1 && o->graph_chunk >= 1 && o->graph_chunk <= 256,
+           MXSEM_EINVAL, "solve: bad tol / max_iter / graph_chunk");
   MX_CHECK(o->mode >= MXSEM_MODE_FP64 && o->mode <= MXSEM_MODE_FP32_ALL, MXSEM_EINVAL,
            "solve: unknown mode");
   MX_CHECK(o->pc == MXSEM_PC_IDENTITY || o->pc == MXSEM_PC_JACOBI || o->pc == MXSEM_PC_LEARNED,
            MXSEM_EINVAL, "solve: unknown preconditioner");
+  MX_CHECK(o->max_outer >= 0 && o->inner_tol > 0.0 && o->inner_tol < 1.0, MXSEM_EINVAL,
+           "solve: bad refinement options");
+  MX_CHECK(!o->x0_given || o->mode == MXSEM_MODE_FP64 || o->mode == MXSEM_MODE_MIXED_IR ||
+               o->mode == MXSEM_MODE_MIXED_IR_BF16G,
+           MXSEM_ENOTSUP, "solve: x0 is supported in the FP64 and refinement modes");
+  return MXSEM_OK;
+}
+
+int mxsem_solve(mxsem_mesh* m, const mxsem_solve_opts* o, const double* b, double* x,
+                mxsem_solve_stats* st) {
+  MX_CHECK(m && o && b && x && st, MXSEM_EINVAL, "solve: null argument");
+  MX_TRY(check_opts(o));
   MX_HIP(hipSetDevice(m->ctx->device));
-  (void)hipGetLastError();
   (void)hipGetLastError();  // clear any stale error left by other libraries
   memset(st, 0, sizeof(*st));
   if (o->method == MXSEM_METHOD_FCG || o->pc == MXSEM_PC_LEARNED)
     return mxsem_fcg_solve_impl(m, o, b, x, st);
-  const int mode = o->mode;
-  const int vprec = vprec_of_mode(mode);
-  const int gprec = gprec_of_mode(mode);
-  if (vprec != VP_F64) MX_CHECK(m->G32 || gprec == 2, MXSEM_ENOTSUP, "solve: mesh has no FP32 view");
-  if (gprec == 2) MX_CHECK(m->G16, MXSEM_ENOTSUP, "solve: mesh has no BF16 view");
-  MX_CHECK(vprec == VP_F64 || m->dinv32, MXSEM_ENOTSUP, "solve: mesh has no FP32 view");
-  MX_CHECK(!o->x0_given || mode == MXSEM_MODE_FP64 || mode == MXSEM_MODE_MIXED_IR ||
-               mode == MXSEM_MODE_MIXED_IR_BF16G,
-           MXSEM_ENOTSUP, "solve: x0 is supported in the FP64 and refinement modes");
-  hipStream_t s = m->ctx->stream;
-  SolverBufs* buf = nullptr;
-  MX_TRY(ensure_bufs(m, vprec, &buf));
-  MX_TRY(ensure_tmp(m));
-  buf->ax_ms_sum = 0.0;
-  buf->ax_samples = 0;
-  MX_HIP(hipEventRecord(m->ctx->ev0, s));
-  double bnorm = 0.0;
-  MX_TRY(host_dot64(m, b, b, &bnorm));
-  bnorm = sqrt(bnorm);
-  const bool ir = mode == MXSEM_MODE_MIXED_IR || mode == MXSEM_MODE_MIXED_IR_BF16G;
-  if (!ir) {
-    InnerResult r;
-    const double* x0 = nullptr;
-    if (o->x0_given) {
-      // solve A d = b - A x0 in FP64 and add: equivalent to starting at x0
-      double rn = 0.0;
-      MX_TRY(fp64_residual(m, b, x, m->tmpa, &rn));
-      MX_TRY(run_pcg(m, buf, gprec, o->pc, m->tmpa, 1.0, x0, o->tol * bnorm / (rn > 0 ? rn : 1.0),
-                     o->max_iter, o->graph_chunk, o->history, &r));
-      MX_HIP(launch_axpy_cast(vprec == VP_F64 ? 0 : 1, x, buf->x, 1.0, 1.0, m->nloc, s));
-    } else {
-      MX_TRY(run_pcg(m, buf, gprec, o->pc, b, 1.0, nullptr, o->tol, o->max_iter, o->graph_chunk,
-                     o->history, &r));
-      MX_HIP(launch_axpy_cast(vprec == VP_F64 ? 0 : 1, x, buf->x, 1.0, 0.0, m->nloc, s));
-    }
-    st->iterations = r.iterations;
-    st->reason = r.reason;
-    st->rel_res_recursive = r.res;
-  } else {
-    // FP64 iterative refinement: r = b - A64 x; d = inner MIXED PCG on r/s; x += s d
-    if (!o->x0_given) MX_HIP(launch_zero(x, m->nloc, s));
-    int total = 0, outer = 0, slow = 0;
-    double prev = -1.0;
-    st->reason = MXSEM_MAX_ITER;
-    for (;;) {
-      double rn = 0.0;
-      MX_TRY(fp64_residual(m, b, x, m->tmpa, &rn));
-      const double rel = bnorm > 0 ? rn / bnorm : 0.0;
-      if (rel <= o->tol) {
-        st->reason = MXSEM_CONVERGED;
-        break;
-      }
-      if (outer >= o->max_outer || total >= o->max_iter) break;
-      if (prev > 0 && rel > 0.5 * prev) ++slow;
-      prev = rel;
-      if (slow >= 2) {
-        // refinement no longer contracts: finish with FP64 PCG from x
-        SolverBufs* b64 = nullptr;
-        MX_TRY(ensure_bufs(m, VP_F64, &b64));
-        InnerResult r;
-        MX_TRY(run_pcg(m, b64, 0, o->pc, m->tmpa, 1.0, nullptr, o->tol * bnorm / rn,
-                       o->max_iter - total > 0 ? o->max_iter - total : 1, o->graph_chunk, nullptr,
-                       &r));
-        MX_HIP(launch_axpy_cast(0, x, b64->x, 1.0, 1.0, m->nloc, s));
-        total += r.iterations;
-        st->fallback_used = 1;
-        st->reason = r.reason;
-        st->rel_res_recursive = r.res;
-        break;
-      }
-      InnerResult r;
-      const double tin = fmax(o->inner_tol, o->tol * bnorm / rn);
-      MX_TRY(run_pcg(m, buf, gprec, o->pc, m->tmpa, 1.0 / rn, nullptr, tin,
-                     o->max_iter - total, o->graph_chunk, nullptr, &r));
-      MX_HIP(launch_axpy_cast(1, x, buf->x, rn, 1.0, m->nloc, s));
-      total += r.iterations;
-      st->rel_res_recursive = r.res;
-      ++outer;
-      if (r.reason == MXSEM_BREAKDOWN) {
-        st->reason = MXSEM_BREAKDOWN;
-        break;
-      }
-    }
-    st->iterations = total;
-    st->outer = outer;
+  std::vector<mxsem_mesh*> ms{m};
+  auto get = [m](int vp, Plan** out) { return get_self_plan(m, vp, out); };
+  return solve_many(m->ctx, ms, get, o, &b, &x, st);
+}
+
+// ------------------------------------------------------------------ batch
+int mxsem_autotune_cached(mxsem_ctx* ctx, int N, int E, int prec, const char* path, int* epb);
+
+int mxsem_batch_create(mxsem_ctx* ctx, int P, mxsem_mesh* const* meshes, const char* tune_cache,
+                       mxsem_batch** out) {
+  MX_CHECK(ctx && meshes && out && P >= 1, MXSEM_EINVAL, "batch_create: bad argument");
+  *out = nullptr;
+  for (int p = 0; p < P; ++p) {
+    MX_CHECK(meshes[p], MXSEM_EINVAL, "batch_create: null mesh");
+    MX_CHECK(meshes[p]->ctx == ctx, MXSEM_EINVAL, "batch_create: meshes must share the context");
+    for (int q = 0; q < p; ++q)
+      MX_CHECK(meshes[q] != meshes[p], MXSEM_EINVAL, "batch_create: a mesh appears twice");
   }
-  // true FP64 residual
-  double rn = 0.0;
-  MX_TRY(fp64_residual(m, b, x, m->tmpb, &rn));
-  st->rel_res = bnorm > 0 ? rn / bnorm : 0.0;
-  MX_HIP(hipEventRecord(m->ctx->ev1, s));
-  MX_HIP(hipEventSynchronize(m->ctx->ev1));
-  float ms = 0.f;
-  MX_HIP(hipEventElapsedTime(&ms, m->ctx->ev0, m->ctx->ev1));
-  st->ms = ms;
-  st->ax_samples = buf->ax_samples;
-  st->ax_ms = buf->ax_samples ? buf->ax_ms_sum / buf->ax_samples : 0.0;
-  if (st->reason == MXSEM_BREAKDOWN) {
-    set_error("solve: (p, A p) <= 0 or non-finite");
-    return MXSEM_EBREAKDOWN;
+  MX_HIP(hipSetDevice(ctx->device));
+  (void)hipGetLastError();
+  const char* path = tune_cache ? tune_cache : getenv("MXSEM_TUNE_CACHE");
+  if (path && path[0]) {
+    // one tuned tile per (N, E rounded up to a power of two), FP32 inner loop
+    for (int p = 0; p < P; ++p) {
+      mxsem_mesh* m = meshes[p];
+      if (m->epb[m->N] > 0) continue;
+      int e2 = 1;
+      while (e2 < m->E) e2 <<= 1;
+      int epb = 0;
+      MX_TRY(mxsem_autotune_cached(ctx, m->N, e2, MXSEM_F32, path, &epb));
+      mxsem_tuning t{};
+      t.epb[m->N] = epb;
+      MX_TRY(mxsem_mesh_set_tuning(m, &t));
+    }
   }
+  mxsem_batch* bt = new mxsem_batch();
+  bt->ctx = ctx;
+  bt->meshes.assign(meshes, meshes + P);
+  ctx->live += 1;
+  *out = bt;
   return MXSEM_OK;
+}
+
+int mxsem_batch_destroy(mxsem_batch* bt) {
+  if (!bt) return MXSEM_OK;
+  hipSetDevice(bt->ctx->device);
+  if (bt->ctx->stream) hipStreamSynchronize(bt->ctx->stream);
+  else hipDeviceSynchronize();
+  for (int q = 0; q < 4; ++q) plan_destroy(bt->plans[q]);
+  bt->ctx->live -= 1;
+  delete bt;
+  return MXSEM_OK;
+}
+
+int mxsem_batch_solve(mxsem_batch* bt, const mxsem_solve_opts* o, const double* const* b,
+                      double* const* x, mxsem_solve_stats* st) {
+  MX_CHECK(bt && o && b && x && st, MXSEM_EINVAL, "batch_solve: null argument");
+  MX_TRY(check_opts(o));
+  MX_CHECK(o->method == MXSEM_METHOD_PCG && o->pc != MXSEM_PC_LEARNED, MXSEM_ENOTSUP,
+           "batch_solve: batches run (P)CG with Jacobi or identity");
+  MX_CHECK(!o->history, MXSEM_ENOTSUP, "batch_solve: no residual history for batches");
+  const int P = (int)bt->meshes.size();
+  for (int p = 0; p < P; ++p) MX_CHECK(b[p] && x[p], MXSEM_EINVAL, "batch_solve: null vector");
+  MX_HIP(hipSetDevice(bt->ctx->device));
+  (void)hipGetLastError();
+  auto get = [bt](int vp, Plan** out) -> int {
+    if (bt->plans[vp] && plan_stale(bt->plans[vp])) {
+      plan_destroy(bt->plans[vp]);
+      bt->plans[vp] = nullptr;
+    }
+    if (!bt->plans[vp]) {
+      int rc = plan_build(bt->meshes.data(), (int)bt->meshes.size(), vp, &bt->plans[vp]);
+      if (rc != MXSEM_OK) return rc;
+    }
+    *out = bt->plans[vp];
+    return MXSEM_OK;
+  };
+  return solve_many(bt->ctx, bt->meshes, get, o, b, x, st);
 }
 
 }  // extern "C"

@@ -8,10 +8,6 @@ int mxsem_fcg_solve_impl(mxsem_mesh*, const mxsem_solve_opts*, const double*, do
   mx::set_error("flexible CG is not available in this build");
   return MXSEM_ENOTSUP;
 }
-int mxsem_batch_create(mxsem_ctx*, int, mxsem_mesh* const*, const char*, mxsem_batch**) { return MXSEM_ENOTSUP; }
-int mxsem_batch_destroy(mxsem_batch*) { return MXSEM_OK; }
-int mxsem_batch_solve(mxsem_batch*, const mxsem_solve_opts*, const double* const*, double* const*,
-                      mxsem_solve_stats*) { return MXSEM_ENOTSUP; }
 int mxsem_nn_create(mxsem_mesh*, const mxsem_nn_desc*, mxsem_nn**) { return MXSEM_ENOTSUP; }
 int mxsem_nn_destroy(mxsem_nn*) { return MXSEM_OK; }
 int mxsem_nn_set_params(mxsem_nn*, const float*, const float*) { return MXSEM_ENOTSUP; }

@@ -4,7 +4,11 @@
 // events over repeated launches on synthetic data of the requested (N, E,
 // precision), and the fastest wins.
 #include <math.h>
+#include <stdio.h>
 
+#include <fstream>
+#include <map>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -83,6 +87,43 @@ int autotune_epb(int device, hipStream_t s, int N, int E, int prec, int* best_ep
   return rc;
 }
 
+// Tuning cache: a flat JSON object {"gfx950:N7:E32768:p1": 1, ...}.
+static std::map<std::string, int> read_cache(const char* path) {
+  std::map<std::string, int> out;
+  std::ifstream f(path);
+  if (!f) return out;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string t = ss.str();
+  size_t i = 0;
+  while ((i = t.find('"', i)) != std::string::npos) {
+    const size_t j = t.find('"', i + 1);
+    if (j == std::string::npos) break;
+    const std::string key = t.substr(i + 1, j - i - 1);
+    const size_t c = t.find(':', j);
+    if (c == std::string::npos) break;
+    out[key] = atoi(t.c_str() + c + 1);
+    i = t.find_first_of(",}", c);
+    if (i == std::string::npos) break;
+  }
+  return out;
+}
+
+static void write_cache(const char* path, const std::map<std::string, int>& kv) {
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return;
+  fprintf(f, "{");
+  bool first = true;
+  for (const auto& e : kv) {
+    fprintf(f, "%s\n  \"%s\": %d", first ? "" : ",", e.first.c_str(), e.second);
+    first = false;
+  }
+  fprintf(f, "\n}\n");
+  fclose(f);
+  rename(tmp.c_str(), path);
+}
+
 }  // namespace mx
 
 using namespace mx;
@@ -103,6 +144,25 @@ int mxsem_autotune(mxsem_ctx* ctx, int N, int E, mxsem_prec prec, mxsem_tuning* 
   return MXSEM_OK;
 }
 
+// Tuned tile for (N, E, prec) from the cache file, autotuned and added to
+// the file when missing.
+int mxsem_autotune_cached(mxsem_ctx* ctx, int N, int E, int prec, const char* path, int* epb) {
+  char key[96];
+  snprintf(key, sizeof(key), "gfx950:N%d:E%d:p%d", N, E, prec);
+  std::map<std::string, int> kv = read_cache(path);
+  auto it = kv.find(key);
+  if (it != kv.end() && it->second >= 1 && it->second <= max_epb(N)) {
+    *epb = it->second;
+    return MXSEM_OK;
+  }
+  mxsem_tuning t{};
+  MX_TRY(mxsem_autotune(ctx, N, E, (mxsem_prec)prec, &t));
+  *epb = t.epb[N];
+  kv[key] = *epb;
+  write_cache(path, kv);
+  return MXSEM_OK;
+}
+
 int mxsem_mesh_set_tuning(mxsem_mesh* m, const mxsem_tuning* t) {
   MX_CHECK(m && t, MXSEM_EINVAL, "mesh_set_tuning: null argument");
   const int e = t->epb[m->N];
@@ -110,8 +170,7 @@ int mxsem_mesh_set_tuning(mxsem_mesh* m, const mxsem_tuning* t) {
            "mesh_set_tuning: elements per workgroup out of range for this order");
   MX_HIP(hipSetDevice(m->ctx->device));
   m->epb[m->N] = e;
-  for (int q = 0; q < 4; ++q)
-    if (m->bufs[q]) MX_TRY(retile_ax(m, m->bufs[q]));
+  mesh_drop_plans(m);  // plans are rebuilt with the new tiles on next use
   return MXSEM_OK;
 }
 

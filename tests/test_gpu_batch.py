@@ -1,0 +1,111 @@
+"""Batched solves of uneven problems (different E and N) in shared graph
+launches: each member equals its standalone solve bitwise (same tiles),
+reaches the oracle solution, and the tuning cache round-trips."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import log, rel_l2
+from paper_2503_02134_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(2, 5, 4001), (3, 7, 4002), (2, 9, 4003), (4, 5, 4004), (3, 9, 4005)]
+
+
+@pytest.fixture(scope="module")
+def mx():
+    from paper_2503_02134_amd import mxsem
+    mxsem.lib()
+    return mxsem
+
+
+@pytest.fixture(scope="module")
+def ctx(mx):
+    c = mx.Context(0)
+    yield c
+    c.close()
+
+
+def _problems(mx, ctx):
+    out = []
+    for ne, N, seed in CASES:
+        xi, _ = mx.mxsem_gll(N)
+        bm = W.box_mesh(ne, N, xi)
+        m = mx.Mesh(ctx, bm.E, N, bm.xyz, bm.glo, bm.bnd)
+        f = W.random_smooth_rhs(bm, seed)
+        b = m.mass_rhs(torch.as_tensor(f, device="cuda"))
+        out.append((m, b))
+    return out
+
+
+@pytest.mark.parametrize("mode", ["MODE_FP64", "MODE_MIXED_IR"])
+def test_batch_equals_standalone_bitwise(mx, ctx, mode):
+    log(f"batch vs standalone, {mode}")
+    probs = _problems(mx, ctx)
+    md = getattr(mx, mode)
+    alone = []
+    for m, b in probs:
+        x, st = m.solve(b, mode=md, tol=1e-10, max_iter=4000)
+        alone.append((x.clone(), st))
+    bt = mx.mxsem_batch_create(ctx.h, [m.h for m, _ in probs])
+    try:
+        xs = [torch.zeros_like(b) for _, b in probs]
+        sts = mx.mxsem_batch_solve(bt, mx.solve_opts(mode=md, tol=1e-10, max_iter=4000),
+                                   [b for _, b in probs], xs)
+    finally:
+        mx.mxsem_batch_destroy(bt)
+    for (xa, sa), xb, sb in zip(alone, xs, sts):
+        log(f"  alone it={sa.iterations} outer={sa.outer} | batch it={sb.iterations} "
+            f"outer={sb.outer} res={sb.rel_res:.2e}")
+        assert sb.reason == mx.CONVERGED
+        assert sb.iterations == sa.iterations and sb.outer == sa.outer
+        assert torch.equal(xa, xb)
+
+
+def test_batch_reaches_oracle(orc, mx, ctx):
+    log("batch mixed refinement vs oracle")
+    probs = _problems(mx, ctx)
+    bt = mx.mxsem_batch_create(ctx.h, [m.h for m, _ in probs])
+    xs = [torch.zeros_like(b) for _, b in probs]
+    try:
+        sts = mx.mxsem_batch_solve(bt, mx.solve_opts(mode=mx.MODE_MIXED_IR, tol=1e-10,
+                                                     max_iter=4000), [b for _, b in probs], xs)
+    finally:
+        mx.mxsem_batch_destroy(bt)
+    for (ne, N, seed), x, st in zip(CASES, xs, sts):
+        xo, _ = orc.gll(N)
+        bmo = W.box_mesh(ne, N, xo)
+        om = orc.Mesh(bmo.E, N, bmo.xyz, bmo.glo, bmo.bnd)
+        xstar, _ = om.pcg(om.rhs(W.random_smooth_rhs(bmo, seed)), tol=1e-13, maxit=5000)
+        err = rel_l2(x.cpu().numpy(), xstar, om.c)
+        log(f"  ne={ne} N={N}: it={st.iterations} outer={st.outer} err={err:.2e}")
+        assert st.reason == mx.CONVERGED and err <= 1e-8
+
+
+def test_tuning_cache_round_trip(mx, ctx, tmp_path):
+    log("autotune cache")
+    probs = _problems(mx, ctx)[:2]
+    path = str(tmp_path / "tune.json")
+    bt = mx.mxsem_batch_create(ctx.h, [m.h for m, _ in probs], tune_cache=path)
+    mx.mxsem_batch_destroy(bt)
+    kv = json.load(open(path))
+    assert len(kv) == 2 and all(k.startswith("gfx950:N") for k in kv)
+    for k, v in kv.items():
+        N = int(k.split(":")[1][1:])
+        assert 1 <= v and ((v * (N + 1) ** 2 + 63) // 64) * 64 <= 256
+    # a second batch reads the file instead of tuning again
+    mtime = os.path.getmtime(path)
+    probs2 = _problems(mx, ctx)[:2]
+    bt = mx.mxsem_batch_create(ctx.h, [m.h for m, _ in probs2], tune_cache=path)
+    mx.mxsem_batch_destroy(bt)
+    assert os.path.getmtime(path) == mtime
+
+
+def test_batch_rejects_bad_input(mx, ctx):
+    probs = _problems(mx, ctx)[:1]
+    with pytest.raises(mx.MxsemError):
+        mx.mxsem_batch_create(ctx.h, [probs[0][0].h, probs[0][0].h])
