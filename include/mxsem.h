@@ -271,7 +271,14 @@ typedef struct {
 /* Adam on the FP32 master weights with the gradient last computed by
  * mxsem_nn_loss_grad. Async. */
 int mxsem_nn_adam_step(mxsem_nn *nn, const mxsem_adam *opt);
+/* Attach (or with nn = NULL detach) a network as the mesh's learned
+ * preconditioner (solves with pc = MXSEM_PC_LEARNED use it). */
 int mxsem_mesh_attach_nn(mxsem_mesh *mesh, mxsem_nn *nn);
+/* One training pair from an FP64 iterate: r = (b - A x)/||b - A x||_c and
+ * e = (xstar - x)/||b - A x||_c as device FP32 vectors (the scaling keeps
+ * FP32 in range; the loss is scale-free).  b, x, xstar: device FP64. Async. */
+int mxsem_nn_make_pair(mxsem_mesh *mesh, const double *b, const double *x, const double *xstar,
+                       float *r_out, float *e_out);
 
 /* ---- diagnostics ------------------------------------------------------------ */
 const char *mxsem_status_str(int status);

@@ -98,7 +98,7 @@ struct State {
   int since;     // iterations since the last 10% improvement
   int fallback;  // learned-PC steps replaced by Jacobi
   int pc;        // mxsem_pc
-  int pad;
+  int fb_pending;  // flexible CG: this step's z must be replaced by Jacobi
 };
 
 // A tile: a block of work of one problem (elements, groups or entries);

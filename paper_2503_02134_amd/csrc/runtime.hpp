@@ -26,13 +26,21 @@ int max_epb(int N);
 hipError_t launch_gs_apply(int prec_io, int prec_acc, void* v, const GsPlan& plan, bool mask,
                            hipStream_t s);
 hipError_t launch_gs_solver(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs,
-                            hipStream_t s);
+                            hipStream_t s, bool on_z = false);
+hipError_t launch_zpc(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs, int pc,
+                      int only_pending, hipStream_t s);
+hipError_t launch_fcg_dots(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs,
+                           int only_pending, hipStream_t s);
+hipError_t launch_fin_beta(const ProbDev* probs, int nprob, int init, int second, hipStream_t s);
+hipError_t launch_nn_fwd(int N, const float* r, const float* dinv, const uint8_t* mult,
+                         const float* W1, const float* W2, float* zc, int E, hipStream_t s,
+                         const State* st);
 hipError_t launch_update(int vprec, int pc, const Tile* tiles, int ntiles, const ProbDev* probs,
                          hipStream_t s);
 hipError_t launch_init(int vprec, int pc, const Tile* tiles, int ntiles, const ProbDev* probs,
                        const double* x0, hipStream_t s);
 hipError_t launch_fin_sigma(const ProbDev* probs, int nprob, hipStream_t s);
-hipError_t launch_fin_rho(const ProbDev* probs, int nprob, int init, hipStream_t s);
+hipError_t launch_fin_rho(const ProbDev* probs, int nprob, int mode, hipStream_t s);
 hipError_t launch_dot(int prec, const void* a, const void* b, const uint8_t* mult, int64_t n,
                       double* part, double* out, hipStream_t s);
 hipError_t launch_precond(int prec, int pc, const void* r, void* z, const void* dinv, int64_t n,
@@ -157,4 +165,7 @@ int ensure_tmp(mxsem_mesh* m);
 const void* G_ptr(const mxsem_mesh* m, int gprec);
 const void* hB_ptr(const mxsem_mesh* m, int gprec);
 int apply_impl(mxsem_mesh* m, int prec, const void* u, void* w, unsigned flags, hipStream_t s);
+// learned preconditioner: forward of an attached network into zc (before
+// the gather-scatter); the kernel returns at once when st->done
+int nn_launch_fwd(mxsem_nn* nn, const float* r, float* zc, hipStream_t s, const State* st);
 }  // namespace mx

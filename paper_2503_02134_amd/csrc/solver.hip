@@ -287,7 +287,7 @@ struct Inner {
   std::vector<char> active;
   double* history = nullptr;  // single-problem plans only
   // results
-  std::vector<int> iterations, reason;
+  std::vector<int> iterations, reason, fallback;
   std::vector<double> res;
 };
 
@@ -345,6 +345,138 @@ static int run_inner(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K, Inner& 
     in.iterations[p] = st.iter;
     in.reason[p] = st.done ? st.reason : MXSEM_MAX_ITER;
     in.res[p] = st.res;
+  }
+  return MXSEM_OK;
+}
+
+// ------------------------------------------------------------------ flexible CG
+// z = M^-1 r for a flexible-CG step: the learned map (forward + FP64
+// gather-scatter of c z_L) or Jacobi/identity; then (r,z)_c, (z, A p)_c and
+// beta.  A rejected learned z is replaced by Jacobi within the same step.
+static int enqueue_fcg_z(Plan* pl, int pc, hipStream_t s, bool init) {
+  if (pc == MXSEM_PC_LEARNED) {
+    mxsem_mesh* m = pl->meshes[0];
+    MX_TRY(nn_launch_fwd(m->nn, (const float*)pl->bufs[0]->r, (float*)pl->bufs[0]->z, s,
+                         pl->hprob[0].st));
+    MX_HIP(launch_gs_solver(pl->vprec, pl->tiles_gs, pl->nt_gs, pl->probs, s, true));
+  } else {
+    MX_HIP(launch_zpc(pl->vprec, pl->tiles_upd, pl->nt_upd, pl->probs, pc, 0, s));
+  }
+  MX_HIP(launch_fcg_dots(pl->vprec, pl->tiles_upd, pl->nt_upd, pl->probs, 0, s));
+  MX_HIP(launch_fin_beta(pl->probs, pl->P, init ? 1 : 0, 0, s));
+  if (pc == MXSEM_PC_LEARNED) {
+    MX_HIP(launch_zpc(pl->vprec, pl->tiles_upd, pl->nt_upd, pl->probs, MXSEM_PC_JACOBI, 1, s));
+    MX_HIP(launch_fcg_dots(pl->vprec, pl->tiles_upd, pl->nt_upd, pl->probs, 1, s));
+    MX_HIP(launch_fin_beta(pl->probs, pl->P, init ? 1 : 0, 1, s));
+  }
+  return MXSEM_OK;
+}
+
+static int get_graph_fcg(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K) {
+  if (pl->graph && pl->graph_k == K && pl->graph_pc == pc && pl->graph_gprec == gprec &&
+      pl->graph_method == MXSEM_METHOD_FCG)
+    return MXSEM_OK;
+  if (pl->graph) {
+    MX_HIP(hipGraphExecDestroy(pl->graph));
+    pl->graph = nullptr;
+  }
+  hipStream_t cs = ctx->capture;
+  hipGraph_t g = nullptr;
+  MX_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  int rc = MXSEM_OK;
+  for (int k = 0; k < K && rc == MXSEM_OK; ++k) {
+    if (k > 0) rc = enqueue_ax(pl, gprec, cs, false);
+    if (rc != MXSEM_OK) break;
+    hipError_t e = launch_gs_solver(pl->vprec, pl->tiles_gs, pl->nt_gs, pl->probs, cs);
+    if (e == hipSuccess) e = launch_fin_sigma(pl->probs, pl->P, cs);
+    if (e == hipSuccess) e = launch_update(pl->vprec, -1, pl->tiles_upd, pl->nt_upd, pl->probs, cs);
+    if (e == hipSuccess) e = launch_fin_rho(pl->probs, pl->P, 2, cs);
+    if (e != hipSuccess) {
+      set_error(std::string("flexible CG capture: ") + hipGetErrorString(e));
+      rc = MXSEM_EHIP;
+      break;
+    }
+    rc = enqueue_fcg_z(pl, pc, cs, false);
+  }
+  hipError_t e = hipStreamEndCapture(cs, &g);
+  if (rc != MXSEM_OK) {
+    if (g) hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) {
+    set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    return MXSEM_EHIP;
+  }
+  e = hipGraphInstantiate(&pl->graph, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    pl->graph = nullptr;
+    return MXSEM_EHIP;
+  }
+  pl->graph_k = K;
+  pl->graph_pc = pc;
+  pl->graph_gprec = gprec;
+  pl->graph_method = MXSEM_METHOD_FCG;
+  return MXSEM_OK;
+}
+
+static int run_inner_fcg(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K, Inner& in) {
+  hipStream_t s = ctx->stream;
+  const int P = pl->P;
+  int max_launch = 0;
+  for (int p = 0; p < P; ++p) {
+    State& st = pl->hstate[p];
+    memset(&st, 0, sizeof(State));
+    st.tol2 = in.tol[p] * in.tol[p];
+    st.maxit = in.maxit[p];
+    st.history = (P == 1) ? in.history : nullptr;
+    st.pc = pc;
+    st.done = in.active[p] ? 0 : 1;
+    st.reason = in.active[p] ? 0 : MXSEM_CONVERGED;
+    ProbDev& Q = pl->hprob[p];
+    mxsem_mesh* m = pl->meshes[p];
+    const int gp = pl->vprec == VP_F64 ? 0 : gprec;
+    Q.rhs64 = in.rhs[p];
+    Q.rhs_scale = in.scale[p];
+    Q.G = G_ptr(m, gp);
+    Q.hB = hB_ptr(m, gp);
+    if (in.active[p]) max_launch = std::max(max_launch, in.maxit[p] / K + 2);
+  }
+  MX_HIP(hipMemcpyAsync(pl->probs, pl->hprob.data(), sizeof(ProbDev) * P, hipMemcpyHostToDevice, s));
+  MX_HIP(hipMemcpyAsync(pl->states, pl->hstate, sizeof(State) * P, hipMemcpyHostToDevice, s));
+  MX_HIP(launch_init(pl->vprec, -1, pl->tiles_upd, pl->nt_upd, pl->probs, nullptr, s));
+  MX_HIP(launch_fin_rho(pl->probs, P, 3, s));
+  MX_TRY(enqueue_fcg_z(pl, pc, s, true));
+  MX_TRY(get_graph_fcg(pl, ctx, gprec, pc, K));
+  const int kprec = pl->vprec == VP_F64 ? 0 : gprec;
+  for (int l = 0; l < max_launch; ++l) {
+    const AxClass& a0 = pl->ax[0];
+    MX_HIP(launch_ax_solver(kprec, a0.N, a0.tiles, a0.ntiles, pl->probs, a0.epb, s, pl->evA,
+                            pl->evB));
+    MX_TRY(enqueue_ax(pl, gprec, s, true));
+    MX_HIP(hipGraphLaunch(pl->graph, s));
+    MX_HIP(hipMemcpyAsync(pl->hstate, pl->states, sizeof(State) * P, hipMemcpyDeviceToHost, s));
+    MX_HIP(hipStreamSynchronize(s));
+    float ms = 0.f;
+    MX_HIP(hipEventElapsedTime(&ms, pl->evA, pl->evB));
+    pl->ax_ms_sum += ms;
+    pl->ax_samples += 1;
+    bool all = true;
+    for (int p = 0; p < P; ++p) all = all && pl->hstate[p].done;
+    if (all) break;
+  }
+  in.iterations.assign(P, 0);
+  in.reason.assign(P, 0);
+  in.res.assign(P, 0.0);
+  in.fallback.assign(P, 0);
+  for (int p = 0; p < P; ++p) {
+    if (!in.active[p]) continue;
+    const State& st = pl->hstate[p];
+    in.iterations[p] = st.iter;
+    in.reason[p] = st.done ? st.reason : MXSEM_MAX_ITER;
+    in.res[p] = st.res;
+    in.fallback[p] = st.fallback;
   }
   return MXSEM_OK;
 }
@@ -418,6 +550,12 @@ static int solve_many(mxsem_ctx* ctx, const std::vector<mxsem_mesh*>& meshes, Ge
   in.active.assign(P, 1);
   in.history = o->history;
   std::vector<char> fallback(P, 0);
+  const bool fcg = o->method == MXSEM_METHOD_FCG || o->pc == MXSEM_PC_LEARNED;
+  auto inner = [&](Plan* q, int gp, Inner& io) {
+    return fcg ? run_inner_fcg(q, ctx, gp, o->pc, o->graph_chunk, io)
+               : run_inner(q, ctx, gp, o->pc, o->graph_chunk, io);
+  };
+  std::vector<int> nfb(P, 0);
   if (!ir) {
     std::vector<double> rn(P, 0.0);
     if (o->x0_given) {
@@ -433,8 +571,9 @@ static int solve_many(mxsem_ctx* ctx, const std::vector<mxsem_mesh*>& meshes, Ge
     } else {
       for (int p = 0; p < P; ++p) in.rhs[p] = b[p];
     }
-    MX_TRY(run_inner(pl, ctx, gprec, o->pc, o->graph_chunk, in));
+    MX_TRY(inner(pl, gprec, in));
     for (int p = 0; p < P; ++p) {
+      if (fcg) nfb[p] += in.fallback[p];
       MX_HIP(launch_axpy_cast(xv, x[p], pl->bufs[p]->x, 1.0, o->x0_given ? 1.0 : 0.0,
                               meshes[p]->nloc, s));
       st[p].iterations = in.iterations[p];
@@ -484,9 +623,10 @@ static int solve_many(mxsem_ctx* ctx, const std::vector<mxsem_mesh*>& meshes, Ge
         any = true;
       }
       if (!any) break;
-      MX_TRY(run_inner(pl, ctx, gprec, o->pc, o->graph_chunk, in));
+      MX_TRY(inner(pl, gprec, in));
       for (int p = 0; p < P; ++p) {
         if (!in.active[p]) continue;
+        if (fcg) nfb[p] += in.fallback[p];
         MX_HIP(launch_axpy_cast(1, x[p], pl->bufs[p]->x, rn[p], 1.0, meshes[p]->nloc, s));
         total[p] += in.iterations[p];
         st[p].rel_res_recursive = in.res[p];
@@ -525,7 +665,8 @@ static int solve_many(mxsem_ctx* ctx, const std::vector<mxsem_mesh*>& meshes, Ge
         f.tol[p] = r > 0 ? o->tol * bnorm[p] / r : o->tol;
         f.maxit[p] = std::max(1, o->max_iter - st[p].iterations);
       }
-      MX_TRY(run_inner(p64, ctx, 0, o->pc, o->graph_chunk, f));
+      MX_TRY(run_inner(p64, ctx, 0, o->pc == MXSEM_PC_LEARNED ? MXSEM_PC_JACOBI : o->pc,
+                       o->graph_chunk, f));
       for (int p = 0; p < P; ++p) {
         if (!fallback[p]) continue;
         MX_HIP(launch_axpy_cast(0, x[p], p64->bufs[p]->x, 1.0, 1.0, meshes[p]->nloc, s));
@@ -551,6 +692,7 @@ static int solve_many(mxsem_ctx* ctx, const std::vector<mxsem_mesh*>& meshes, Ge
     st[p].ms = ms;
     st[p].ax_samples = pl->ax_samples;
     st[p].ax_ms = pl->ax_samples ? pl->ax_ms_sum / pl->ax_samples : 0.0;
+    if (fcg) st[p].fallback_used += nfb[p];
     breakdown = breakdown || st[p].reason == MXSEM_BREAKDOWN;
   }
   if (breakdown) {
@@ -604,9 +746,6 @@ int mxsem_precond(mxsem_mesh* m, mxsem_pc pc, mxsem_prec io, const void* r, void
   return MXSEM_OK;
 }
 
-int mxsem_fcg_solve_impl(mxsem_mesh* m, const mxsem_solve_opts* o, const double* b, double* x,
-                         mxsem_solve_stats* st);
-
 static int check_opts(const mxsem_solve_opts* o) {
   MX_CHECK(o->tol >= 0.0 && o->max_iter >= 1 && o->graph_chunk >= 1 && o->graph_chunk <= 256,
            MXSEM_EINVAL, "solve: bad tol / max_iter / graph_chunk");
@@ -629,8 +768,13 @@ int mxsem_solve(mxsem_mesh* m, const mxsem_solve_opts* o, const double* b, doubl
   MX_HIP(hipSetDevice(m->ctx->device));
   (void)hipGetLastError();  // clear any stale error left by other libraries
   memset(st, 0, sizeof(*st));
-  if (o->method == MXSEM_METHOD_FCG || o->pc == MXSEM_PC_LEARNED)
-    return mxsem_fcg_solve_impl(m, o, b, x, st);
+  if (o->pc == MXSEM_PC_LEARNED) {
+    MX_CHECK(m->nn, MXSEM_EINVAL, "solve: the learned preconditioner needs an attached network");
+    MX_CHECK(o->mode != MXSEM_MODE_FP64, MXSEM_ENOTSUP,
+             "solve: the learned preconditioner runs in the FP32 inner loop");
+  }
+  MX_CHECK(o->method == MXSEM_METHOD_PCG || o->method == MXSEM_METHOD_FCG, MXSEM_EINVAL,
+           "solve: unknown method");
   std::vector<mxsem_mesh*> ms{m};
   auto get = [m](int vp, Plan** out) { return get_self_plan(m, vp, out); };
   return solve_many(m->ctx, ms, get, o, &b, &x, st);
@@ -689,8 +833,8 @@ int mxsem_batch_solve(mxsem_batch* bt, const mxsem_solve_opts* o, const double* 
                       double* const* x, mxsem_solve_stats* st) {
   MX_CHECK(bt && o && b && x && st, MXSEM_EINVAL, "batch_solve: null argument");
   MX_TRY(check_opts(o));
-  MX_CHECK(o->method == MXSEM_METHOD_PCG && o->pc != MXSEM_PC_LEARNED, MXSEM_ENOTSUP,
-           "batch_solve: batches run (P)CG with Jacobi or identity");
+  MX_CHECK(o->pc != MXSEM_PC_LEARNED, MXSEM_ENOTSUP,
+           "batch_solve: batches run (flexible) CG with Jacobi or identity");
   MX_CHECK(!o->history, MXSEM_ENOTSUP, "batch_solve: no residual history for batches");
   const int P = (int)bt->meshes.size();
   for (int p = 0; p < P; ++p) MX_CHECK(b[p] && x[p], MXSEM_EINVAL, "batch_solve: null vector");

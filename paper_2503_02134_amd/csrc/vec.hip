@@ -24,6 +24,7 @@ struct GsApi {
   void* v;
   GsPlan plan;
   int bucket;
+  int on_z;  // solver variant: sum z instead of w
 };
 
 // One thread per group, GS_PER_THREAD groups per thread issued together:
@@ -41,7 +42,7 @@ __global__ void __launch_bounds__(GS_THREADS) gs_kernel(const Tile* __restrict__
     const ProbDev& P = probs[t.prob];
     if (P.st->done) return;
     plan = &P.gs;
-    v = (T*)P.w;
+    v = (T*)(api.on_z ? P.z : P.w);
     bucket = t.aux;
     first = t.first;
   } else {
@@ -313,9 +314,11 @@ __global__ void fin_sigma_kernel(const ProbDev* __restrict__ probs) {
   }
 }
 
-// after the vector pass: convergence / max-iteration / stagnation tests,
-// beta = rho_new / rho.  With init != 0: the start of a solve.
-__global__ void fin_rho_kernel(const ProbDev* __restrict__ probs, int init) {
+// After the vector pass.  mode 0 (PCG step): convergence / max-iteration /
+// stagnation tests, then beta = rho'/rho.  mode 1: start of a PCG solve.
+// mode 2 (flexible CG step): the tests only (beta comes later).  mode 3:
+// start of a flexible CG solve (rho comes later).
+__global__ void fin_rho_kernel(const ProbDev* __restrict__ probs, int mode) {
   __shared__ double sred[16];
   const ProbDev& P = probs[blockIdx.x];
   State* st = P.st;
@@ -324,9 +327,9 @@ __global__ void fin_rho_kernel(const ProbDev* __restrict__ probs, int init) {
   double rr = fixed_sum(P.part_u1, P.nblk_upd, sred);
   if (threadIdx.x != 0) return;
   st->rr = rr;
-  if (init) {
+  if (mode == 1 || mode == 3) {
     st->bb = rr;
-    st->rho = rz;
+    if (mode == 1) st->rho = rz;
     st->beta = 0.0;
     st->iter = 0;
     st->since = 0;
@@ -367,8 +370,86 @@ __global__ void fin_rho_kernel(const ProbDev* __restrict__ probs, int init) {
     st->reason = MXSEM_STAGNATED;
     return;
   }
-  st->beta = rz / st->rho;
+  if (mode == 0) {
+    st->beta = rz / st->rho;
+    st->rho = rz;
+  }
+}
+
+// ------------------------------------------------------------ flexible CG
+// z = M^-1 r (Jacobi or identity) for flexible CG steps; with only_pending,
+// only for problems whose learned z was rejected this step.
+template <typename T>
+__global__ void __launch_bounds__(UPD_THREADS) zpc_kernel(const Tile* __restrict__ tiles,
+                                                          const ProbDev* __restrict__ probs,
+                                                          int pc, int only_pending) {
+  const Tile t = tiles[blockIdx.x];
+  const ProbDev& P = probs[t.prob];
+  if (P.st->done || (only_pending && !P.st->fb_pending)) return;
+  const T* __restrict__ r = (const T*)P.r;
+  const T* __restrict__ dinv = (const T*)P.dinv;
+  T* __restrict__ z = (T*)P.z;
+#pragma unroll
+  for (int q = 0; q < UPD_PER_THREAD; ++q) {
+    const int64_t i = (int64_t)t.first + q * UPD_THREADS + threadIdx.x;
+    if (i < P.nloc) z[i] = pc == MXSEM_PC_IDENTITY ? r[i] : dinv[i] * r[i];
+  }
+}
+
+// partials (r,z)_c -> part_u0 and (z,w)_c -> part_u2 (w = A p of this step)
+template <typename T, typename ACC>
+__global__ void __launch_bounds__(UPD_THREADS) fcg_dots_kernel(const Tile* __restrict__ tiles,
+                                                               const ProbDev* __restrict__ probs,
+                                                               int only_pending) {
+  __shared__ ACC sred[16];
+  const Tile t = tiles[blockIdx.x];
+  const ProbDev& P = probs[t.prob];
+  if (P.st->done || (only_pending && !P.st->fb_pending)) return;
+  const T* __restrict__ r = (const T*)P.r;
+  const T* __restrict__ z = (const T*)P.z;
+  const T* __restrict__ w = (const T*)P.w;
+  ACC rz = ACC(0), zw = ACC(0);
+#pragma unroll
+  for (int q = 0; q < UPD_PER_THREAD; ++q) {
+    const int64_t i = (int64_t)t.first + q * UPD_THREADS + threadIdx.x;
+    if (i < P.nloc) {
+      const ACC c = (ACC)cweight(P.mult[i]);
+      rz += (ACC)r[i] * c * (ACC)z[i];
+      zw += (ACC)z[i] * c * (ACC)w[i];
+    }
+  }
+  ACC s0 = block_sum(rz, sred);
+  ACC s1 = block_sum(zw, sred);
+  if (threadIdx.x == 0) {
+    const int b = t.first / UPD_CHUNK;
+    P.part_u0[b] = (double)s0;
+    P.part_u2[b] = (double)s1;
+  }
+}
+
+// beta = -(z, A p_old)_c / (p_old, A p_old)_c, rho = (r,z)_c.  A learned z
+// that is not a descent direction ((r,z)_c <= 0 or non-finite) is flagged
+// for replacement by Jacobi.  init: first z of a solve (beta = 0).
+// second: after the replacement (clears the flag, counts the fallback).
+__global__ void fin_beta_kernel(const ProbDev* __restrict__ probs, int init, int second) {
+  __shared__ double sred[16];
+  const ProbDev& P = probs[blockIdx.x];
+  State* st = P.st;
+  if (st->done || (second && !st->fb_pending)) return;
+  double rz = fixed_sum(P.part_u0, P.nblk_upd, sred);
+  double zw = fixed_sum(P.part_u2, P.nblk_upd, sred);
+  if (threadIdx.x != 0) return;
+  if (!second && st->pc == MXSEM_PC_LEARNED &&
+      (!(rz > 0.0) || !isfinite(rz) || (!init && !isfinite(zw)))) {
+    st->fb_pending = 1;
+    return;
+  }
+  if (second) {
+    st->fb_pending = 0;
+    st->fallback += 1;
+  }
   st->rho = rz;
+  st->beta = init ? 0.0 : -zw / st->sigma;
 }
 
 // ------------------------------------------------------------ API kernels
@@ -467,7 +548,7 @@ hipError_t launch_gs_apply(int prec_io, int prec_acc, void* v, const GsPlan& pla
     if (bkt >= last && !(mask && bkt == plan.nall)) continue;
     const int ng = plan.bk[bkt].ngroups;
     if (ng == 0) continue;
-    GsApi a{v, plan, bkt};
+    GsApi a{v, plan, bkt, 0};
     dim3 g(nblk(ng, GS_CHUNK)), b(GS_THREADS);
     if (prec_io == MXSEM_F64 && prec_acc == MXSEM_F64)
       hipLaunchKernelGGL((gs_kernel<double, double, false>), g, b, 0, s, nullptr, nullptr, a);
@@ -487,10 +568,11 @@ hipError_t launch_gs_apply(int prec_io, int prec_acc, void* v, const GsPlan& pla
 
 // vector precision: 0 FP64, 1 FP32 (FP64 accumulation), 3 FP32 (FP32 accumulation)
 hipError_t launch_gs_solver(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs,
-                            hipStream_t s) {
+                            hipStream_t s, bool on_z) {
   if (ntiles == 0) return hipSuccess;
   dim3 g(ntiles), b(GS_THREADS);
   GsApi a{};
+  a.on_z = on_z ? 1 : 0;
   if (vprec == 0)
     hipLaunchKernelGGL((gs_kernel<double, double, true>), g, b, 0, s, tiles, probs, a);
   else if (vprec == 1)
@@ -545,8 +627,38 @@ hipError_t launch_fin_sigma(const ProbDev* probs, int nprob, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_fin_rho(const ProbDev* probs, int nprob, int init, hipStream_t s) {
-  hipLaunchKernelGGL(fin_rho_kernel, dim3(nprob), dim3(FIN_THREADS), 0, s, probs, init);
+hipError_t launch_fin_rho(const ProbDev* probs, int nprob, int mode, hipStream_t s) {
+  hipLaunchKernelGGL(fin_rho_kernel, dim3(nprob), dim3(FIN_THREADS), 0, s, probs, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_zpc(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs, int pc,
+                      int only_pending, hipStream_t s) {
+  if (vprec == 0)
+    hipLaunchKernelGGL((zpc_kernel<double>), dim3(ntiles), dim3(UPD_THREADS), 0, s, tiles, probs,
+                       pc, only_pending);
+  else
+    hipLaunchKernelGGL((zpc_kernel<float>), dim3(ntiles), dim3(UPD_THREADS), 0, s, tiles, probs,
+                       pc, only_pending);
+  return hipGetLastError();
+}
+
+hipError_t launch_fcg_dots(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs,
+                           int only_pending, hipStream_t s) {
+  if (vprec == 0)
+    hipLaunchKernelGGL((fcg_dots_kernel<double, double>), dim3(ntiles), dim3(UPD_THREADS), 0, s,
+                       tiles, probs, only_pending);
+  else if (vprec == 1)
+    hipLaunchKernelGGL((fcg_dots_kernel<float, double>), dim3(ntiles), dim3(UPD_THREADS), 0, s,
+                       tiles, probs, only_pending);
+  else
+    hipLaunchKernelGGL((fcg_dots_kernel<float, float>), dim3(ntiles), dim3(UPD_THREADS), 0, s,
+                       tiles, probs, only_pending);
+  return hipGetLastError();
+}
+
+hipError_t launch_fin_beta(const ProbDev* probs, int nprob, int init, int second, hipStream_t s) {
+  hipLaunchKernelGGL(fin_beta_kernel, dim3(nprob), dim3(FIN_THREADS), 0, s, probs, init, second);
   return hipGetLastError();
 }
 

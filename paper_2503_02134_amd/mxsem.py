@@ -107,6 +107,7 @@ _SIGS = {
     "mxsem_nn_loss_grad": [vp, vp, vp, C.c_int, vp, vp],
     "mxsem_nn_adam_step": [vp, C.POINTER(mxsem_adam)],
     "mxsem_mesh_attach_nn": [vp, vp],
+    "mxsem_nn_make_pair": [vp, vp, vp, vp, vp, vp],
     "mxsem_version": [],
 }
 
@@ -321,6 +322,11 @@ def mxsem_nn_adam_step(nn, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, step=1):
 
 def mxsem_mesh_attach_nn(mesh, nn):
     _check("mxsem_mesh_attach_nn", lib().mxsem_mesh_attach_nn(mesh, nn))
+
+
+def mxsem_nn_make_pair(mesh, b, x, xstar, r_out, e_out):
+    _check("mxsem_nn_make_pair", lib().mxsem_nn_make_pair(mesh, _ptr(b), _ptr(x), _ptr(xstar),
+                                                           _ptr(r_out), _ptr(e_out)))
 
 
 # ---------------------------------------------------------------- convenience
