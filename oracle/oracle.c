@@ -539,7 +539,8 @@ typedef struct {
 } orc_stats;
 
 /* stagnation: the best relative residual has not improved by >= 10% over
- * 50 consecutive iterations */
+ * 500 consecutive iterations (a CG residual on a high-contrast coefficient
+ * can plateau for hundreds of iterations before it falls again) */
 typedef struct {
   double ref;
   int since;
@@ -550,7 +551,7 @@ static int stag_update(stag_t *s, double res) {
     s->since = 0;
     return 0;
   }
-  return ++s->since >= 50;
+  return ++s->since >= 500;
 }
 
 static double true_rel_res(const orc_mesh *m, const double *b, const double *x,

@@ -167,6 +167,10 @@ constexpr int UPD_PER_THREAD = 8;  // entries per thread (two 4-wide vectors)
 constexpr int UPD_CHUNK = UPD_THREADS * UPD_PER_THREAD;
 constexpr int FIN_THREADS = 1024;  // final-reduction workgroup
 constexpr int MAX_N = 15;
+// stagnation: no 10% improvement of the best relative residual in this many
+// iterations (CG residuals on high-contrast coefficients plateau for
+// hundreds of iterations before falling again)
+constexpr int STAG_WINDOW = 500;
 
 // ---------------------------------------------------------------- reductions
 // Deterministic block sum of one double per thread (wave64 shuffles, then

@@ -365,7 +365,7 @@ __global__ void fin_rho_kernel(const ProbDev* __restrict__ probs, int mode) {
   if (res < 0.9 * st->best) {
     st->best = res;
     st->since = 0;
-  } else if (++st->since >= 50) {
+  } else if (++st->since >= STAG_WINDOW) {
     st->done = 1;
     st->reason = MXSEM_STAGNATED;
     return;

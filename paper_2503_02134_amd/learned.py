@@ -69,22 +69,32 @@ class Network:
         mx.mxsem_nn_adam_step(self.h, lr, beta1, beta2, eps, self.step)
 
 
-def make_pairs(mesh: "mx.Mesh", rhs: list, samples: int, chunk: int | None = None,
+def make_pairs(mesh: "mx.Mesh", rhs: list, samples: int = 8, mesh_np=None, seed: int = 0,
                tol_star: float = 1e-12):
-    """(R, E) device FP32 tensors [len(rhs) * samples, nloc] of training pairs."""
+    """(R, E) device FP32 tensors [len(rhs) * samples, nloc] of training pairs.
+
+    For each right-hand side: x* from a tight FP64 solve; then, from a rough
+    seeded initial guess x0 (when mesh_np is given, else x0 = 0), restarted
+    FP64 PCG chunks of 0, 1, 1, 2, 4, 8, ... iterations; each chunk end gives
+    one pair, so the errors range from rough to smooth."""
     R, E = [], []
-    for b in rhs:
+    for q, b in enumerate(rhs):
         xs = torch.zeros_like(b)
-        _, st = mesh.solve(b, xs, mode=mx.MODE_FP64, tol=tol_star, max_iter=50000)
-        step = chunk or max(1, st.iterations // (samples + 1))
-        x = torch.zeros_like(b)
-        for _ in range(samples):
-            mesh.solve(b, x, mode=mx.MODE_FP64, tol=0.0, max_iter=step, x0_given=1)
+        mesh.solve(b, xs, mode=mx.MODE_FP64, tol=tol_star, max_iter=50000)
+        if mesh_np is not None:
+            x = torch.as_tensor(W.random_nodal_field(mesh_np, seed + 7919 * q), device=b.device)
+        else:
+            x = torch.zeros_like(b)
+        step = 0
+        for k in range(samples):
+            if step > 0:
+                mesh.solve(b, x, mode=mx.MODE_FP64, tol=0.0, max_iter=step, x0_given=1)
             r = torch.empty(mesh.nloc, dtype=torch.float32, device=b.device)
             e = torch.empty_like(r)
             mx.mxsem_nn_make_pair(mesh.h, b, x, xs, r, e)
             R.append(r)
             E.append(e)
+            step = 1 if step == 0 else (step if k == 1 else 2 * step)
     return torch.stack(R), torch.stack(E)
 
 
@@ -103,3 +113,37 @@ def train(net: Network, R, E, steps: int, batch: int = 4, lr: float = 1e-3, seed
         if log and (it % 25 == 0 or it == steps - 1):
             log(f"train step {it}: loss {losses[-1]:.4f}")
     return losses
+
+
+def rhs_batch(mesh_np, mesh: "mx.Mesh", seeds):
+    """Device right-hand sides b = M QQ^T (B f) for seeded random smooth f."""
+    out = []
+    for s in seeds:
+        f = W.random_smooth_rhs(mesh_np, s)
+        out.append(mesh.mass_rhs(torch.as_tensor(f, device=mesh.dev)))
+    return out
+
+
+def compare_on(mesh: "mx.Mesh", rhs: list, net: Network, tol: float = 1e-10,
+               max_iter: int = 50000):
+    """Learned flexible CG vs Jacobi PCG (both inside FP64 refinement with the
+    FP32 inner loop) and FP64 Jacobi PCG on the same right-hand sides."""
+    net.attach()
+    rows = []
+    for b in rhs:
+        x64 = torch.zeros_like(b)
+        _, s64 = mesh.solve(b, x64, mode=mx.MODE_FP64, tol=tol, max_iter=max_iter)
+        xj = torch.zeros_like(b)
+        _, sj = mesh.solve(b, xj, mode=mx.MODE_MIXED_IR, tol=tol, max_iter=max_iter)
+        xl = torch.zeros_like(b)
+        _, sl = mesh.solve(b, xl, mode=mx.MODE_MIXED_IR, pc=mx.PC_LEARNED,
+                           method=mx.METHOD_FCG, tol=tol, max_iter=max_iter)
+        dn = float(torch.linalg.vector_norm(x64))
+        rows.append({
+            "fp64": (s64.iterations, s64.ms, s64.rel_res),
+            "jacobi": (sj.iterations + sj.outer, sj.ms, sj.rel_res),
+            "learned": (sl.iterations + sl.outer, sl.ms, sl.rel_res, sl.fallback_used),
+            "learned_vs_fp64": float(torch.linalg.vector_norm(xl - x64)) / dn,
+            "jacobi_vs_fp64": float(torch.linalg.vector_norm(xj - x64)) / dn,
+        })
+    return rows

@@ -172,6 +172,16 @@ def lognormal_k(mesh: BoxMesh, seed: int, corr: float = 0.2, sigma: float = 1.0,
     return mesh.to_local(np.exp(g))
 
 
+def random_nodal_field(mesh: BoxMesh, seed: int) -> np.ndarray:
+    """Seeded N(0,1) value per global node, 0 on the cube boundary, in local
+    layout (a rough, continuous field: initial guesses for training data)."""
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal(len(mesh.gxyz))
+    loc = mesh.to_local(g)
+    loc[mesh.bnd.reshape(-1) > 0] = 0.0
+    return loc
+
+
 def he_normal_weights(seed: int, ch: int = 32, cin: int = 2):
     """He-normal initial weights for the two 3x3x3 convolutions (no bias):
     W1 [ch][cin][27] ~ N(0, 2/(27 cin)), W2 [ch][27] ~ N(0, 2/(27 ch))."""
