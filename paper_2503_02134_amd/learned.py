@@ -147,3 +147,25 @@ def compare_on(mesh: "mx.Mesh", rhs: list, net: Network, tol: float = 1e-10,
             "jacobi_vs_fp64": float(torch.linalg.vector_norm(xj - x64)) / dn,
         })
     return rows
+
+
+def calibrate_scale(net: Network, mesh: "mx.Mesh", b, scales=(1.0, 0.5, 0.35, 0.25, 0.18, 0.125),
+                    tol: float = 1e-8, max_iter: int = 50000, log=None):
+    """Choose the factor applied to the learned correction (W2 scaled, so
+    z_L = dinv r + lambda s_e y) by the flexible-CG iteration count on a
+    training right-hand side: the A-norm loss fits one application, while CG
+    prefers a damped correction.  Leaves the best scale in the network and
+    returns (scale, {scale: iterations})."""
+    W1, W2 = net.get()
+    net.attach()
+    its = {}
+    for lam in scales:
+        net.set(W1, W2 * lam)
+        _, st = mesh.solve(b, mode=mx.MODE_MIXED_IR, pc=mx.PC_LEARNED, method=mx.METHOD_FCG,
+                           tol=tol, max_iter=max_iter)
+        its[lam] = st.iterations + st.outer if st.reason == mx.CONVERGED else 10 ** 9
+        if log:
+            log(f"calibrate lambda {lam}: {its[lam]} iterations")
+    best = min(its, key=its.get)
+    net.set(W1, W2 * best)
+    return best, its
