@@ -36,9 +36,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="box32_N7_deformed")
+    ap.add_argument("--workload", default="box32_N7_deformed",
+                    help="box4_N7 | box16_N9_deformed | box32_N7_deformed | "
+                         "box24_N7_lognormal_helmholtz | batch64")
     ap.add_argument("--mode", default="mixed_ir", choices=["mixed_ir", "mixed_ir_bf16g", "fp64",
-                                                           "mixed"])
+                                                           "mixed", "learned"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=200)
     args = ap.parse_args()
@@ -55,6 +57,10 @@ def main():
     from paper_2503_02134_amd import workloads as W
 
     mx.lib()
+    if args.workload == "batch64":
+        return bench_batch(args)
+    if args.mode == "learned":
+        return bench_learned(args)
     wl = W.WORKLOADS[args.workload]
     modes = {"mixed_ir": mx.MODE_MIXED_IR, "mixed_ir_bf16g": mx.MODE_MIXED_IR_BF16G,
              "fp64": mx.MODE_FP64, "mixed": mx.MODE_MIXED}
@@ -164,6 +170,168 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_iters)
     print(json.dumps(out), flush=True)
+    mesh.close()
+    ctx.close()
+
+
+def bench_batch(args):
+    """64 uneven Poisson problems (E in {8^3,12^3,16^3,24^3}, N in {5,7,9},
+    seeded smooth RHS) solved together in shared graph launches (mixed
+    refinement), against 64 sequential FP64 solves on the same GPU."""
+    import torch
+
+    from paper_2503_02134_amd import mxsem as mx
+    from paper_2503_02134_amd import workloads as W
+    ctx = mx.Context(0)
+    draws = W.batch_draws()
+    meshes, bs = [], []
+    t0 = time.perf_counter()
+    for ne, N, seed in draws:
+        xi, _ = mx.mxsem_gll(N)
+        bm = W.box_mesh(ne, N, xi)
+        m = mx.Mesh(ctx, bm.E, N, bm.xyz, bm.glo, bm.bnd)
+        f = W.random_smooth_rhs(bm, seed)
+        bs.append(m.mass_rhs(torch.as_tensor(f, device="cuda")))
+        meshes.append(m)
+        del bm
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    nloc = [m.nloc for m in meshes]
+    log(f"batch64: {len(meshes)} problems, {sum(nloc)} local dofs, setup {t_setup:.1f}s")
+    cache = os.path.join(os.environ.get("TMPDIR", "/tmp"), "mxsem_tune.json")
+    t0 = time.perf_counter()
+    bt = mx.mxsem_batch_create(ctx.h, [m.h for m in meshes], tune_cache=cache)
+    t_tune = time.perf_counter() - t0
+    xs = [torch.zeros_like(b) for b in bs]
+    opts = mx.solve_opts(mode=mx.MODE_MIXED_IR, tol=1e-10, max_iter=20000, graph_chunk=16)
+    for _ in range(args.warmup):
+        for x in xs:
+            x.zero_()
+        mx.mxsem_batch_solve(bt, opts, bs, xs)
+    torch.cuda.synchronize()
+    its = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for x in xs:
+            x.zero_()
+        sts = mx.mxsem_batch_solve(bt, opts, bs, xs)
+        its += sum(n * (s.iterations + s.outer) for n, s in zip(nloc, sts))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    conv = sum(s.reason == mx.CONVERGED for s in sts)
+    worst = max(s.rel_res for s in sts)
+    # the same problems one after another in FP64
+    t0 = time.perf_counter()
+    its64 = 0
+    for m, b in zip(meshes, bs):
+        _, s = m.solve(b, mode=mx.MODE_FP64, tol=1e-10, max_iter=20000)
+        its64 += m.nloc * s.iterations
+    torch.cuda.synchronize()
+    el64 = time.perf_counter() - t0
+    out = {
+        "metric": "GDOF*iter/s (local dofs x iterations / s) of the SEM PCG solve",
+        "value": round(its / el / 1e9, 4), "unit": "GDOF*iter/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(el * 1e3 / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (f64 gather-scatter sums, dots, refinement residuals)",
+        "data": "synthetic",
+        "config": {"workload": "batch64", "problems": len(meshes), "nloc_total": sum(nloc),
+                   "mode": "mixed_ir (batched)", "tol": 1e-10},
+        "converged": conv, "worst_rel_res": worst,
+        "sequential_fp64": {"ms": round(el64 * 1e3, 3),
+                            "gdof_iter_s": round(its64 / el64 / 1e9, 4)},
+        "batch_vs_sequential_fp64_time": round(el64 / (el / args.steps), 3),
+        "setup_s": round(t_setup, 2), "tune_s": round(t_tune, 2),
+    }
+    print(json.dumps(out), flush=True)
+    mx.mxsem_batch_destroy(bt)
+    for m in meshes:
+        m.close()
+    ctx.close()
+
+
+def bench_learned(args):
+    """Log-normal Helmholtz (24^3, N = 7, k = exp(g), h = 1): train the
+    learned preconditioner on GPU-generated pairs, calibrate its scale on a
+    training right-hand side, then time learned flexible CG (inside FP64
+    refinement) on held-out right-hand sides against Jacobi PCG (same
+    refinement) and FP64 Jacobi PCG."""
+    import numpy as np
+    import torch
+
+    from paper_2503_02134_amd import mxsem as mx
+    from paper_2503_02134_amd import workloads as W
+    from paper_2503_02134_amd.learned import (Network, calibrate_scale, make_pairs, rhs_batch,
+                                              train)
+    wl = W.WORKLOADS["box24_N7_lognormal_helmholtz"]
+    ctx = mx.Context(0)
+    xi, _ = mx.mxsem_gll(wl.N)
+    bm = W.box_mesh(wl.ne, wl.N, xi)
+    kf = W.lognormal_k(bm, wl.k_seed)
+    mesh = mx.Mesh(ctx, bm.E, wl.N, bm.xyz, bm.glo, bm.bnd, kcoef=kf, helm_h=wl.helm_h)
+    t0 = time.perf_counter()
+    train_rhs = rhs_batch(bm, mesh, range(5100, 5116))
+    R, E = make_pairs(mesh, train_rhs, samples=8, mesh_np=bm, seed=11)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    net = Network(mesh, seed=3)
+    t0 = time.perf_counter()
+    losses = train(net, R, E, steps=300, batch=4, lr=2e-3, seed=1, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del R, E
+    lam, cal = calibrate_scale(net, mesh, train_rhs[0], log=log)
+    net.attach()
+    ev = rhs_batch(bm, mesh, range(5900, 5900 + max(args.steps, 1)))
+    nloc = mesh.nloc
+    for b in ev[: args.warmup]:
+        mesh.solve(b, mode=mx.MODE_MIXED_IR, pc=mx.PC_LEARNED, method=mx.METHOD_FCG, tol=wl.tol)
+    torch.cuda.synchronize()
+    rows = []
+    its = 0
+    xl = [torch.zeros_like(b) for b in ev]
+    t0 = time.perf_counter()
+    for b, x in zip(ev, xl):
+        _, st = mesh.solve(b, x, mode=mx.MODE_MIXED_IR, pc=mx.PC_LEARNED, method=mx.METHOD_FCG,
+                           tol=wl.tol, max_iter=50000)
+        its += st.iterations + st.outer
+        rows.append(st)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    jac, f64, errs = [], [], []
+    for b, x in zip(ev, xl):
+        xj = torch.zeros_like(b)
+        _, sj = mesh.solve(b, xj, mode=mx.MODE_MIXED_IR, tol=wl.tol, max_iter=50000)
+        x6 = torch.zeros_like(b)
+        _, s6 = mesh.solve(b, x6, mode=mx.MODE_FP64, tol=wl.tol, max_iter=50000)
+        jac.append(sj)
+        f64.append(s6)
+        errs.append(float(torch.linalg.vector_norm(x - x6) / torch.linalg.vector_norm(x6)))
+    out = {
+        "metric": "GDOF*iter/s (local dofs x iterations / s) of the SEM PCG solve",
+        "value": round(nloc * its / el / 1e9, 4), "unit": "GDOF*iter/s", "n_gpus": 1,
+        "steps": len(ev), "warmup": args.warmup, "ms_per_step": round(el * 1e3 / len(ev), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 loop, bf16-in/f32-accumulate network, f64 sums/dots/refinement",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "E": bm.E, "N": wl.N, "nloc": nloc,
+                   "mode": "mixed_ir + flexible CG, learned preconditioner", "tol": wl.tol},
+        "learned": {"iterations": [s.iterations + s.outer for s in rows],
+                    "ms": [round(s.ms, 2) for s in rows],
+                    "fallback_steps": [s.fallback_used for s in rows],
+                    "rel_res": [s.rel_res for s in rows], "rel_diff_vs_fp64": errs,
+                    "scale": lam, "calibration_iterations": {str(k): v for k, v in cal.items()},
+                    "train_loss_first": losses[0],
+                    "train_loss_last20": float(np.mean(losses[-20:])),
+                    "train_s": round(t_train, 2), "data_s": round(t_data, 2)},
+        "jacobi_mixed_ir": {"iterations": [s.iterations + s.outer for s in jac],
+                            "ms": [round(s.ms, 2) for s in jac]},
+        "fp64_jacobi": {"iterations": [s.iterations for s in f64],
+                        "ms": [round(s.ms, 2) for s in f64]},
+    }
+    print(json.dumps(out), flush=True)
+    net.close()
     mesh.close()
     ctx.close()
 
