@@ -141,6 +141,129 @@ __global__ void __launch_bounds__(NN_THREADS)
   }
 }
 
+// Forward for N = 7 on the matrix cores (gfx950 v_mfma_f32_32x32x16_bf16).
+// Per element both layers are small GEMMs over the 512 positions:
+//   layer 1: A1[p][c] = sum_j X[p][j] W1[c][j],  j = (ci, o), K = 54 -> 64
+//   layer 2: T[p][o]  = sum_c H[p][c] W2[c][o],  N = 27 -> 32, K = 32
+// Each of the 4 waves owns 128 positions (4 row tiles of 32).  Operand
+// layout of the 32x32x16 instruction (lane l): A row l%32, k = 8(l/32)+t;
+// B column l%32, same k; result column l%32, rows 8(v/4) + 4(l/32) + v%4.
+// The hidden tile goes through LDS once to turn the result layout (lane =
+// channel) into the A layout (lane = position).  Same roundings as the
+// vector kernel: BF16 inputs, weights and h; FP32 accumulation.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float floatx16_t __attribute__((ext_vector_type(16)));
+
+__global__ void __launch_bounds__(NN_THREADS)
+    nn_fwd_mfma_n8_kernel(const float* __restrict__ r, const float* __restrict__ dinv,
+                          const uint8_t* __restrict__ mult, const float* __restrict__ W1,
+                          const float* __restrict__ W2, float* __restrict__ zc, int E,
+                          const State* __restrict__ st) {
+  constexpr int n = 8, n3 = 512, HS = 40;  // H tile row stride (bf16), 16-byte aligned rows
+  extern __shared__ float sm[];
+  float* x0 = sm;                                  // [2][512]
+  float* T = x0 + 2 * n3;                          // [512][27]
+  __bf16* Hs = (__bf16*)(T + 27 * n3);             // [4 waves][32][HS]
+  __shared__ float sred[8];
+  const int e = blockIdx.x;
+  if (e >= E || (st && st->done)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t base = (int64_t)e * n3;
+  float rv[2], dv[2];
+  float ss = 0.f;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int p = tid + q * NN_THREADS;
+    rv[q] = r[base + p];
+    dv[q] = dinv[base + p] * rv[q];
+    ss += dv[q] * dv[q];
+  }
+  const float s = sqrtf(block_sum_bcast(ss, sred));
+  const float inv = s > 0.f ? 1.f / s : 0.f;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int p = tid + q * NN_THREADS;
+    x0[p] = bf16r(rv[q] * inv);
+    x0[n3 + p] = bf16r(dv[q] * inv);
+  }
+  // weight operands (identical for every element)
+  const int col = lane & 31, kh = (lane >> 5) * 8;
+  bf16x8_t b1[4], b2[2];
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int j = ks * 16 + kh + t;
+      b1[ks][t] = (__bf16)(j < 54 ? W1[col * 54 + j] : 0.f);
+    }
+#pragma unroll
+  for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int c = ks * 16 + kh + t;
+      b2[ks][t] = (__bf16)(col < 27 ? W2[c * 27 + col] : 0.f);
+    }
+  __syncthreads();
+  __bf16* Hw = Hs + wave * 32 * HS;
+#pragma unroll 1
+  for (int mt = 0; mt < 4; ++mt) {
+    const int tb = wave * 128 + mt * 32;
+    const int p = tb + col;
+    const int i = p & 7, jy = (p >> 3) & 7, kz = p >> 6;
+    floatx16_t acc = {0};
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      bf16x8_t a;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int j = ks * 16 + kh + t;
+        float v = 0.f;
+        if (j < 54) {
+          const int ci = j >= 27 ? 1 : 0, o = j - 27 * ci;
+          const int nb = nbr_of<n>(i, jy, kz, o);
+          if (nb >= 0) v = x0[ci * n3 + nb];
+        }
+        a[t] = (__bf16)v;
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1[ks], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+      Hw[row * HS + col] = (__bf16)fmaxf(acc[v], 0.f);
+    }
+    __syncthreads();
+    floatx16_t acc2 = {0};
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const bf16x8_t a2 = *(const bf16x8_t*)(Hw + col * HS + ks * 16 + kh);
+      acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, b2[ks], acc2, 0, 0, 0);
+    }
+    if (col < 27) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        T[(tb + row) * 27 + col] = acc2[v];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int p = tid + q * NN_THREADS;
+    const int i = p & 7, j = (p >> 3) & 7, k = p >> 6;
+    float y = 0.f;
+#pragma unroll
+    for (int o = 0; o < 27; ++o) {
+      const int nb = nbr_of<n>(i, j, k, o);
+      if (nb >= 0) y += T[nb * 27 + o];
+    }
+    const float zl = dv[q] + s * y;
+    const uint8_t m = mult[base + p];
+    zc[base + p] = m == 1 ? zl : zl / (float)m;
+  }
+}
+
 // Backward: part[blockIdx.x][*] += gradient of sum_p gzl[p] z_L[p] with
 // respect to (W1, W2), over the elements blockIdx.x, +gridDim.x, ...
 template <int N>
@@ -383,6 +506,12 @@ static size_t bwd_lds() {
 hipError_t launch_nn_fwd(int N, const float* r, const float* dinv, const uint8_t* mult,
                          const float* W1, const float* W2, float* zc, int E, hipStream_t s,
                          const State* st) {
+  if (N == 7) {
+    const size_t lds = sizeof(float) * (2 * 512 + 27 * 512) + sizeof(__bf16) * 4 * 32 * 40;
+    hipLaunchKernelGGL(nn_fwd_mfma_n8_kernel, dim3(E), dim3(NN_THREADS), lds, s, r, dinv, mult,
+                       W1, W2, zc, E, st);
+    return hipGetLastError();
+  }
   switch (N) {
 #define MX_NN(NN_)                                                                          \
   case NN_:                                                                                 \
