@@ -154,11 +154,29 @@ __global__ void __launch_bounds__(NN_THREADS)
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float floatx16_t __attribute__((ext_vector_type(16)));
 
+// Weight operands in the per-lane B layout, packed once per weight update:
+// pk[ks * 64 + lane] for the 4 first-layer and then 2 second-layer k steps.
+__global__ void nn_pack_kernel(const float* __restrict__ W1, const float* __restrict__ W2,
+                               bf16x8_t* __restrict__ pk) {
+  const int lane = threadIdx.x & 63, ks = threadIdx.x >> 6;  // 6 x 64 threads
+  const int col = lane & 31, kh = (lane >> 5) * 8;
+  bf16x8_t v;
+  for (int t = 0; t < 8; ++t) {
+    if (ks < 4) {
+      const int j = ks * 16 + kh + t;
+      v[t] = (__bf16)(j < 54 ? W1[col * 54 + j] : 0.f);
+    } else {
+      const int c = (ks - 4) * 16 + kh + t;
+      v[t] = (__bf16)(col < 27 ? W2[c * 27 + col] : 0.f);
+    }
+  }
+  pk[ks * 64 + lane] = v;
+}
+
 __global__ void __launch_bounds__(NN_THREADS)
     nn_fwd_mfma_n8_kernel(const float* __restrict__ r, const float* __restrict__ dinv,
-                          const uint8_t* __restrict__ mult, const float* __restrict__ W1,
-                          const float* __restrict__ W2, float* __restrict__ zc, int E,
-                          const State* __restrict__ st) {
+                          const uint8_t* __restrict__ mult, const bf16x8_t* __restrict__ pk,
+                          float* __restrict__ zc, int E, const State* __restrict__ st) {
   constexpr int n = 8, n3 = 512, HS = 40;  // H tile row stride (bf16), 16-byte aligned rows
   extern __shared__ float sm[];
   float* x0 = sm;                                  // [2][512]
@@ -186,22 +204,24 @@ __global__ void __launch_bounds__(NN_THREADS)
     x0[p] = bf16r(rv[q] * inv);
     x0[n3 + p] = bf16r(dv[q] * inv);
   }
-  // weight operands (identical for every element)
+  // weight operands (identical for every element), six 16-byte loads
   const int col = lane & 31, kh = (lane >> 5) * 8;
   bf16x8_t b1[4], b2[2];
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) b1[ks] = pk[ks * 64 + lane];
+#pragma unroll
+  for (int ks = 0; ks < 2; ++ks) b2[ks] = pk[(4 + ks) * 64 + lane];
+  // this lane's 32 input slots (k = 16 ks + kh + t): channel and offset,
+  // decoded once (kh depends on the lane, so the divisions stay out of the
+  // position loop); bit 7 = slot in use
+  int code[4][8];
 #pragma unroll
   for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int j = ks * 16 + kh + t;
-      b1[ks][t] = (__bf16)(j < 54 ? W1[col * 54 + j] : 0.f);
-    }
-#pragma unroll
-  for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int c = ks * 16 + kh + t;
-      b2[ks][t] = (__bf16)(col < 27 ? W2[c * 27 + col] : 0.f);
+      const int ci = j >= 27 ? 1 : 0, o = j - 27 * ci;
+      code[ks][t] = j < 54 ? (128 | (ci << 6) | ((o % 3) << 4) | (((o / 3) % 3) << 2) | (o / 9)) : 0;
     }
   __syncthreads();
   __bf16* Hw = Hs + wave * 32 * HS;
@@ -216,13 +236,10 @@ __global__ void __launch_bounds__(NN_THREADS)
       bf16x8_t a;
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
-        const int j = ks * 16 + kh + t;
-        float v = 0.f;
-        if (j < 54) {
-          const int ci = j >= 27 ? 1 : 0, o = j - 27 * ci;
-          const int nb = nbr_of<n>(i, jy, kz, o);
-          if (nb >= 0) v = x0[ci * n3 + nb];
-        }
+        const int cd = code[ks][t];
+        const int ii = i + ((cd >> 4) & 3) - 1, jj = jy + ((cd >> 2) & 3) - 1, kk = kz + (cd & 3) - 1;
+        const bool ok = (cd & 128) && ii >= 0 && ii < n && jj >= 0 && jj < n && kk >= 0 && kk < n;
+        const float v = ok ? x0[((cd >> 6) & 1) * n3 + ii + n * (jj + n * kk)] : 0.f;
         a[t] = (__bf16)v;
       }
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1[ks], acc, 0, 0, 0);
@@ -505,11 +522,11 @@ static size_t bwd_lds() {
 
 hipError_t launch_nn_fwd(int N, const float* r, const float* dinv, const uint8_t* mult,
                          const float* W1, const float* W2, float* zc, int E, hipStream_t s,
-                         const State* st) {
+                         const State* st, const void* packed) {
   if (N == 7) {
     const size_t lds = sizeof(float) * (2 * 512 + 27 * 512) + sizeof(__bf16) * 4 * 32 * 40;
     hipLaunchKernelGGL(nn_fwd_mfma_n8_kernel, dim3(E), dim3(NN_THREADS), lds, s, r, dinv, mult,
-                       W1, W2, zc, E, st);
+                       (const bf16x8_t*)packed, zc, E, st);
     return hipGetLastError();
   }
   switch (N) {
@@ -552,6 +569,7 @@ struct mxsem_nn {
   int cin = NN_CIN, ch = NN_CH;
   float *W = nullptr, *Wq = nullptr, *grad = nullptr, *mo = nullptr, *ve = nullptr;
   float* part = nullptr;  // [NN_BWD_BLOCKS][NN_NP]
+  void* packed = nullptr; // [6][64] BF16x8 weight operands of the matrix-core forward
   float *z = nullptr, *d = nullptr, *Ad = nullptr, *g = nullptr;
   double* nd = nullptr;   // [2 * max samples] numerators / denominators
   int nd_cap = 0;
@@ -574,14 +592,15 @@ static inline unsigned nb256(int64_t n) { return (unsigned)((n + 255) / 256); }
 // z = M QQ^T (c z_L(r)) into out (FP32)
 int nn_launch_fwd(mxsem_nn* nn, const float* r, float* zc, hipStream_t s, const State* st) {
   mxsem_mesh* m = nn->mesh;
-  MX_HIP(launch_nn_fwd(m->N, r, m->dinv32, m->mult, nn->Wq, nn->Wq + NN_W1, zc, m->E, s, st));
+  MX_HIP(launch_nn_fwd(m->N, r, m->dinv32, m->mult, nn->Wq, nn->Wq + NN_W1, zc, m->E, s, st,
+                       nn->packed));
   return MXSEM_OK;
 }
 
 int nn_forward_into(mxsem_nn* nn, const float* r, float* out, hipStream_t s) {
   mxsem_mesh* m = nn->mesh;
   MX_HIP(launch_nn_fwd(m->N, r, m->dinv32, m->mult, nn->Wq, nn->Wq + NN_W1, out, m->E, s,
-                       nullptr));
+                       nullptr, nn->packed));
   MX_HIP(launch_gs_apply(MXSEM_F32, MXSEM_F64, out, m->plan, true, s));
   return MXSEM_OK;
 }
@@ -613,6 +632,7 @@ int mxsem_nn_create(mxsem_mesh* m, const mxsem_nn_desc* d, mxsem_nn** out) {
   A((void**)&nn->mo, sizeof(float) * NN_NP);
   A((void**)&nn->ve, sizeof(float) * NN_NP);
   A((void**)&nn->part, sizeof(float) * NN_NP * nn->nbwd);
+  A((void**)&nn->packed, 16 * 6 * 64);
   A((void**)&nn->z, sizeof(float) * nl);
   A((void**)&nn->d, sizeof(float) * nl);
   A((void**)&nn->Ad, sizeof(float) * nl);
@@ -624,6 +644,8 @@ int mxsem_nn_create(mxsem_mesh* m, const mxsem_nn_desc* d, mxsem_nn** out) {
   hipStream_t s = m->ctx->stream;
   for (float* p : {nn->W, nn->Wq, nn->grad, nn->mo, nn->ve})
     hipLaunchKernelGGL(nn_fill_kernel, dim3(nb256(NN_NP)), dim3(256), 0, s, p, (int64_t)NN_NP, 0.f);
+  hipLaunchKernelGGL(nn_pack_kernel, dim3(1), dim3(6 * 64), 0, s, nn->Wq, nn->Wq + NN_W1,
+                     (bf16x8_t*)nn->packed);
   MX_HIP(hipGetLastError());
   MX_HIP(hipStreamSynchronize(s));
   m->ctx->live += 1;
@@ -650,6 +672,8 @@ int mxsem_nn_set_params(mxsem_nn* nn, const float* W1, const float* W2) {
   MX_HIP(hipMemcpyAsync(nn->W, W1, sizeof(float) * NN_W1, hipMemcpyHostToDevice, s));
   MX_HIP(hipMemcpyAsync(nn->W + NN_W1, W2, sizeof(float) * NN_W2, hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(nn_round_kernel, dim3(nb256(NN_NP)), dim3(256), 0, s, nn->W, nn->Wq);
+  hipLaunchKernelGGL(nn_pack_kernel, dim3(1), dim3(6 * 64), 0, s, nn->Wq, nn->Wq + NN_W1,
+                     (bf16x8_t*)nn->packed);
   for (float* p : {nn->mo, nn->ve})
     hipLaunchKernelGGL(nn_fill_kernel, dim3(nb256(NN_NP)), dim3(256), 0, s, p, (int64_t)NN_NP, 0.f);
   MX_HIP(hipGetLastError());
@@ -720,6 +744,8 @@ int mxsem_nn_adam_step(mxsem_nn* nn, const mxsem_adam* o) {
   hipLaunchKernelGGL(nn_adam_kernel, dim3(nb256(NN_NP)), dim3(256), 0, nn->mesh->ctx->stream,
                      nn->W, nn->Wq, nn->grad, nn->mo, nn->ve, (float)o->lr, (float)o->beta1,
                      (float)o->beta2, (float)o->eps, c1, c2);
+  hipLaunchKernelGGL(nn_pack_kernel, dim3(1), dim3(6 * 64), 0, nn->mesh->ctx->stream, nn->Wq,
+                     nn->Wq + NN_W1, (bf16x8_t*)nn->packed);
   MX_HIP(hipGetLastError());
   return MXSEM_OK;
 }

@@ -34,7 +34,7 @@ hipError_t launch_fcg_dots(int vprec, const Tile* tiles, int ntiles, const ProbD
 hipError_t launch_fin_beta(const ProbDev* probs, int nprob, int init, int second, hipStream_t s);
 hipError_t launch_nn_fwd(int N, const float* r, const float* dinv, const uint8_t* mult,
                          const float* W1, const float* W2, float* zc, int E, hipStream_t s,
-                         const State* st);
+                         const State* st, const void* packed);
 hipError_t launch_update(int vprec, int pc, const Tile* tiles, int ntiles, const ProbDev* probs,
                          hipStream_t s);
 hipError_t launch_init(int vprec, int pc, const Tile* tiles, int ntiles, const ProbDev* probs,
