@@ -21,6 +21,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -141,143 +142,190 @@ __global__ void __launch_bounds__(NN_THREADS)
   }
 }
 
-// Forward for N = 7 on the matrix cores (gfx950 v_mfma_f32_32x32x16_bf16).
-// Per element both layers are small GEMMs over the 512 positions:
-//   layer 1: A1[p][c] = sum_j X[p][j] W1[c][j],  j = (ci, o), K = 54 -> 64
-//   layer 2: T[p][o]  = sum_c H[p][c] W2[c][o],  N = 27 -> 32, K = 32
-// Each of the 4 waves owns 128 positions (4 row tiles of 32).  Operand
-// layout of the 32x32x16 instruction (lane l): A row l%32, k = 8(l/32)+t;
-// B column l%32, same k; result column l%32, rows 8(v/4) + 4(l/32) + v%4.
-// The hidden tile goes through LDS once to turn the result layout (lane =
-// channel) into the A layout (lane = position).  Same roundings as the
-// vector kernel: BF16 inputs, weights and h; FP32 accumulation.
+// Forward for N = 7 on the matrix cores (gfx950 v_mfma_f32_32x32x16_bf16),
+// both layers as small GEMMs over the 512 positions of an element, computed
+// transposed so that positions run along the result columns:
+//   layer 1: H[c][p] = relu(sum_k W1[c][k] X[k][p]),  k = (tap, ci), K = 64
+//   layer 2: T[o][p] = sum_c W2[c][o] H[c][p],         27 taps -> 32 rows
+//   y[p]     = sum_o T[o][p + d_o]                     (zero outside)
+// Operand layout of the instruction (lane l, h = l/32): A row l%32 and
+// B column l%32, with k = 8h + t; result column l%32, rows
+// 8(v/4) + 4h + v%4.  The first layer's result is therefore already the
+// second layer's B operand in the same lane (the channel order inside K is
+// absorbed into the packed W2), so the hidden tile never leaves registers.
+//
+// LDS: X holds (x0, x1) as one BF16 pair per position in a zero-bordered
+// 10^3 grid, so every im2col operand is four 32-bit loads at fixed offsets.
+// T is written scattered, T[o][q] to slot q - d_o of tap o's plane; each
+// plane is a 9^3 (or smaller) box with row stride 9 and layer stride 81
+// whose slots outside the element are written but never read, and whose
+// in-element slots that no position writes (the convolution's zero padding)
+// are cleared once per workgroup.  The sum over taps is then 27 loads at
+// fixed offsets per position.  75.5 KB + 4 KB keeps two workgroups per CU.
+// Workgroups are persistent over elements.  Same roundings as the vector
+// kernel: BF16 inputs, weights and h; FP32 accumulation; y summed in tap
+// order.
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float floatx16_t __attribute__((ext_vector_type(16)));
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
 
-// Weight operands in the per-lane B layout, packed once per weight update:
+namespace nnm {
+constexpr int XP = 10;                  // bordered grid edge
+constexpr int XWORDS = XP * XP * XP;    // 1000
+constexpr int tdx(int o) { return o % 3 - 1; }
+constexpr int tdy(int o) { return (o / 3) % 3 - 1; }
+constexpr int tdz(int o) { return o / 9 - 1; }
+constexpr int ext(int d) { return d != 0 ? 8 : 7; }  // slot span hi - lo per direction
+constexpr int lo(int d) { return d > 0 ? -1 : 0; }
+constexpr int pmap(int i, int j, int k) { return i + 9 * j + 81 * k; }
+constexpr int plane_size(int o) {
+  return 1 + ext(tdx(o)) + 9 * ext(tdy(o)) + 81 * ext(tdz(o));
+}
+// second-layer result slot -> tap (slots 26, 27, 29, 30, 31 are padding)
+constexpr int slot_tap(int s) { return s < 26 ? s : (s == 28 ? 26 : -1); }
+struct Tables {
+  int rof[27];  // read offset of tap o for position p: rof[o] + pmap(p)
+  int wof[27];  // write offset of tap o for source position q: wof[o] + pmap(q)
+  int size;     // words of all planes
+  constexpr Tables() : rof(), wof(), size(0) {
+    int b = 0;
+    for (int o = 0; o < 27; ++o) {
+      rof[o] = b - pmap(lo(tdx(o)), lo(tdy(o)), lo(tdz(o)));
+      wof[o] = rof[o] - pmap(tdx(o), tdy(o), tdz(o));
+      b += plane_size(o);
+    }
+    size = b;
+  }
+};
+constexpr Tables TB{};
+constexpr int UWORDS = TB.size;
+constexpr int LDS_BYTES = 4 * (XWORDS + UWORDS);
+static_assert(UWORDS == 18864, "tap planes");
+}  // namespace nnm
+
+// Weight operands in the per-lane A layout, packed once per weight update:
 // pk[ks * 64 + lane] for the 4 first-layer and then 2 second-layer k steps.
+// First layer: row = channel, k = 16 ks + 8h + 2u + ci <-> tap 8 ks + 4h + u.
+// Second layer: row = result slot, k = 16 ks + 8h + t <-> channel
+// 16 ks + 8(t/4) + 4h + t%4 (the first layer's result rows in that lane).
 __global__ void nn_pack_kernel(const float* __restrict__ W1, const float* __restrict__ W2,
                                bf16x8_t* __restrict__ pk) {
   const int lane = threadIdx.x & 63, ks = threadIdx.x >> 6;  // 6 x 64 threads
-  const int col = lane & 31, kh = (lane >> 5) * 8;
+  const int row = lane & 31, h = lane >> 5;
   bf16x8_t v;
   for (int t = 0; t < 8; ++t) {
     if (ks < 4) {
-      const int j = ks * 16 + kh + t;
-      v[t] = (__bf16)(j < 54 ? W1[col * 54 + j] : 0.f);
+      const int tap = 8 * ks + 4 * h + (t >> 1), ci = t & 1;
+      v[t] = (__bf16)(tap < 27 ? W1[row * 54 + ci * 27 + tap] : 0.f);
     } else {
-      const int c = (ks - 4) * 16 + kh + t;
-      v[t] = (__bf16)(col < 27 ? W2[c * 27 + col] : 0.f);
+      const int c = 16 * (ks - 4) + 8 * (t >> 2) + 4 * h + (t & 3);
+      const int tap = nnm::slot_tap(row);
+      v[t] = (__bf16)(tap >= 0 ? W2[c * 27 + tap] : 0.f);
     }
   }
   pk[ks * 64 + lane] = v;
 }
 
-__global__ void __launch_bounds__(NN_THREADS)
+__device__ inline unsigned pack_bf16x2(float lo_, float hi_) {
+  return (unsigned)float_to_bf16(lo_) | ((unsigned)float_to_bf16(hi_) << 16);
+}
+
+__global__ void __launch_bounds__(NN_THREADS, 2)
     nn_fwd_mfma_n8_kernel(const float* __restrict__ r, const float* __restrict__ dinv,
                           const uint8_t* __restrict__ mult, const bf16x8_t* __restrict__ pk,
                           float* __restrict__ zc, int E, const State* __restrict__ st) {
-  constexpr int n = 8, n3 = 512, HS = 40;  // H tile row stride (bf16), 16-byte aligned rows
+  using namespace nnm;
+  constexpr int n3 = 512;
   extern __shared__ float sm[];
-  float* x0 = sm;                                  // [2][512]
-  float* T = x0 + 2 * n3;                          // [512][27]
-  __bf16* Hs = (__bf16*)(T + 27 * n3);             // [4 waves][32][HS]
+  unsigned* X = (unsigned*)sm;  // [10][10][10] BF16 pairs
+  float* U = sm + XWORDS;       // tap planes
   __shared__ float sred[8];
-  const int e = blockIdx.x;
-  if (e >= E || (st && st->done)) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t base = (int64_t)e * n3;
-  float rv[2], dv[2];
-  float ss = 0.f;
+  if (st && st->done) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, c = lane & 31;
+  // clear both buffers once: borders of X and never-written slots of U stay 0
+  for (int q = tid; q < XWORDS + UWORDS; q += NN_THREADS) sm[q] = 0.f;
+  // weight operands (identical for every element)
+  bf16x8_t a1[4], a2[2];
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int p = tid + q * NN_THREADS;
-    rv[q] = r[base + p];
-    dv[q] = dinv[base + p] * rv[q];
-    ss += dv[q] * dv[q];
-  }
-  const float s = sqrtf(block_sum_bcast(ss, sred));
-  const float inv = s > 0.f ? 1.f / s : 0.f;
+  for (int ks = 0; ks < 4; ++ks) a1[ks] = pk[ks * 64 + lane];
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int p = tid + q * NN_THREADS;
-    x0[p] = bf16r(rv[q] * inv);
-    x0[n3 + p] = bf16r(dv[q] * inv);
-  }
-  // weight operands (identical for every element), six 16-byte loads
-  const int col = lane & 31, kh = (lane >> 5) * 8;
-  bf16x8_t b1[4], b2[2];
-#pragma unroll
-  for (int ks = 0; ks < 4; ++ks) b1[ks] = pk[ks * 64 + lane];
-#pragma unroll
-  for (int ks = 0; ks < 2; ++ks) b2[ks] = pk[(4 + ks) * 64 + lane];
-  // this lane's 32 input slots (k = 16 ks + kh + t): channel and offset,
-  // decoded once (kh depends on the lane, so the divisions stay out of the
-  // position loop); bit 7 = slot in use
-  int code[4][8];
+  for (int ks = 0; ks < 2; ++ks) a2[ks] = pk[(4 + ks) * 64 + lane];
+  // this lane's first tile (tile 4*wave): i = c%8, j = c/8, k = 2*wave
+  const int ci_ = c & 7, cj = c >> 3, ck = 2 * wave;
+  const int xq = (ci_ + 1) + XP * (cj + 1) + XP * XP * (ck + 1);
+  int xa[4][4];  // im2col load address per (k step, tap quad)
 #pragma unroll
   for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int j = ks * 16 + kh + t;
-      const int ci = j >= 27 ? 1 : 0, o = j - 27 * ci;
-      code[ks][t] = j < 54 ? (128 | (ci << 6) | ((o % 3) << 4) | (((o / 3) % 3) << 2) | (o / 9)) : 0;
+    for (int u = 0; u < 4; ++u) {
+      const int tap = 8 * ks + 4 * h + u;
+      xa[ks][u] = xq + (tap < 27 ? tdx(tap) + XP * tdy(tap) + XP * XP * tdz(tap) : 0);
     }
-  __syncthreads();
-  __bf16* Hw = Hs + wave * 32 * HS;
-#pragma unroll 1
-  for (int mt = 0; mt < 4; ++mt) {
-    const int tb = wave * 128 + mt * 32;
-    const int p = tb + col;
-    const int i = p & 7, jy = (p >> 3) & 7, kz = p >> 6;
-    floatx16_t acc = {0};
+  const int uq = XWORDS + pmap(ci_, cj, ck);
+  int wa[14];  // T store address per result register (v = 13: h = 0 only)
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      bf16x8_t a;
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int cd = code[ks][t];
-        const int ii = i + ((cd >> 4) & 3) - 1, jj = jy + ((cd >> 2) & 3) - 1, kk = kz + (cd & 3) - 1;
-        const bool ok = (cd & 128) && ii >= 0 && ii < n && jj >= 0 && jj < n && kk >= 0 && kk < n;
-        const float v = ok ? x0[((cd >> 6) & 1) * n3 + ii + n * (jj + n * kk)] : 0.f;
-        a[t] = (__bf16)v;
-      }
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1[ks], acc, 0, 0, 0);
-    }
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-      Hw[row * HS + col] = (__bf16)fmaxf(acc[v], 0.f);
-    }
-    __syncthreads();
-    floatx16_t acc2 = {0};
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      const bf16x8_t a2 = *(const bf16x8_t*)(Hw + col * HS + ks * 16 + kh);
-      acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, b2[ks], acc2, 0, 0, 0);
-    }
-    if (col < 27) {
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        T[(tb + row) * 27 + col] = acc2[v];
-      }
-    }
-    __syncthreads();
+  for (int v = 0; v < 14; ++v) {
+    const int s0 = 8 * (v >> 2) + (v & 3);
+    const int t0 = slot_tap(s0), t1 = slot_tap(s0 + 4);
+    wa[v] = uq + (h ? (t1 >= 0 ? TB.wof[t1] : 0) : TB.wof[t0]);
   }
+  // positions of the sum over taps: p = tid and tid + 256
+  const int pi = tid & 7, pj = (tid >> 3) & 7, pk0 = tid >> 6;
+  const int ur = XWORDS + pmap(pi, pj, pk0);
+  const int xw = (pi + 1) + XP * (pj + 1) + XP * XP * (pk0 + 1);
+  __syncthreads();
+
+  for (int e = blockIdx.x; e < E; e += gridDim.x) {
+    const int64_t base = (int64_t)e * n3;
+    float rv[2], dv[2];
+    float ss = 0.f;
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int p = tid + q * NN_THREADS;
-    const int i = p & 7, j = (p >> 3) & 7, k = p >> 6;
-    float y = 0.f;
-#pragma unroll
-    for (int o = 0; o < 27; ++o) {
-      const int nb = nbr_of<n>(i, j, k, o);
-      if (nb >= 0) y += T[nb * 27 + o];
+    for (int q = 0; q < 2; ++q) {
+      rv[q] = r[base + tid + q * NN_THREADS];
+      dv[q] = dinv[base + tid + q * NN_THREADS] * rv[q];
+      ss += dv[q] * dv[q];
     }
-    const float zl = dv[q] + s * y;
-    const uint8_t m = mult[base + p];
-    zc[base + p] = m == 1 ? zl : zl / (float)m;
+    const float s = sqrtf(block_sum_bcast(ss, sred));
+    const float inv = s > 0.f ? 1.f / s : 0.f;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) X[xw + q * 4 * XP * XP] = pack_bf16x2(rv[q] * inv, dv[q] * inv);
+    __syncthreads();
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      const int xs = XP * XP * (mt >> 1) + 4 * XP * (mt & 1);  // tile shift in X
+      const int us = 81 * (mt >> 1) + 36 * (mt & 1);           // tile shift in pmap
+      floatx16_t acc = {0};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        u32x4_t w;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) w[u] = X[xa[ks][u] + xs];
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[ks], __builtin_bit_cast(bf16x8_t, w),
+                                                      acc, 0, 0, 0);
+      }
+      bf16x8_t hb[2];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) hb[v >> 3][v & 7] = (__bf16)fmaxf(acc[v], 0.f);
+      floatx16_t acc2 = {0};
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks)
+        acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[ks], hb[ks], acc2, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 13; ++v) U[wa[v] - XWORDS + us] = acc2[v];
+      if (h == 0) U[wa[13] - XWORDS + us] = acc2[13];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int p = tid + q * NN_THREADS;
+      const float* up = U + (ur - XWORDS) + q * 4 * 81;
+      float y = 0.f;
+#pragma unroll
+      for (int o = 0; o < 27; ++o) y += up[TB.rof[o]];
+      const float zl = dv[q] + s * y;
+      const uint8_t m = mult[base + p];
+      zc[base + p] = m == 1 ? zl : zl / (float)m;
+    }
   }
 }
 
@@ -524,9 +572,15 @@ hipError_t launch_nn_fwd(int N, const float* r, const float* dinv, const uint8_t
                          const float* W1, const float* W2, float* zc, int E, hipStream_t s,
                          const State* st, const void* packed) {
   if (N == 7) {
-    const size_t lds = sizeof(float) * (2 * 512 + 27 * 512) + sizeof(__bf16) * 4 * 32 * 40;
-    hipLaunchKernelGGL(nn_fwd_mfma_n8_kernel, dim3(E), dim3(NN_THREADS), lds, s, r, dinv, mult,
-                       (const bf16x8_t*)packed, zc, E, st);
+    // persistent: two workgroups per CU, each walking elements blockIdx.x, +grid, ...
+    int dev = 0, ncu = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err == hipSuccess) err = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (err != hipSuccess) return err;
+    const int grid = std::min(E, 2 * std::max(ncu, 1));
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(nn_fwd_mfma_n8_kernel, dim3(grid), dim3(NN_THREADS), nnm::LDS_BYTES, s, r,
+                       dinv, mult, (const bf16x8_t*)packed, zc, E, st);
     return hipGetLastError();
   }
   switch (N) {
