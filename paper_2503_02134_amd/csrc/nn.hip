@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(NN_THREADS)
 // Forward for N = 7 on the matrix cores (gfx950 v_mfma_f32_32x32x16_bf16),
 // both layers as small GEMMs over the 512 positions of an element, computed
 // transposed so that positions run along the result columns:
-//   layer 1: H[c][p] = relu(sum_k W1[c][k] X[k][p]),  k = (tap, ci), K = 64
+//   layer 1: H[c][p] = relu(sum_k W1[c][k] X[k][p]),  k = (slot, ci), K = 64
 //   layer 2: T[o][p] = sum_c W2[c][o] H[c][p],         27 taps -> 32 rows
 //   y[p]     = sum_o T[o][p + d_o]                     (zero outside)
 // Operand layout of the instruction (lane l, h = l/32): A row l%32 and
@@ -153,61 +153,93 @@ __global__ void __launch_bounds__(NN_THREADS)
 // 8(v/4) + 4h + v%4.  The first layer's result is therefore already the
 // second layer's B operand in the same lane (the channel order inside K is
 // absorbed into the packed W2), so the hidden tile never leaves registers.
+// A tile is 32 positions: 8 along i times 4 along j in one k layer; a wave
+// runs its 4 tiles as two interleaved pairs.
 //
-// LDS: X holds (x0, x1) as one BF16 pair per position in a zero-bordered
-// 10^3 grid, so every im2col operand is four 32-bit loads at fixed offsets.
-// T is written scattered, T[o][q] to slot q - d_o of tap o's plane; each
-// plane is a 9^3 (or smaller) box with row stride 9 and layer stride 81
-// whose slots outside the element are written but never read, and whose
-// in-element slots that no position writes (the convolution's zero padding)
-// are cleared once per workgroup.  The sum over taps is then 27 loads at
-// fixed offsets per position.  75.5 KB + 4 KB keeps two workgroups per CU.
-// Workgroups are persistent over elements.  Same roundings as the vector
-// kernel: BF16 inputs, weights and h; FP32 accumulation; y summed in tap
-// order.
+// LDS, laid out so that every access of a half wave hits 32 distinct banks:
+//  * X holds (x0, x1) as one BF16 pair per position in a zero-bordered
+//    10^3 grid with row stride 40 and plane stride 400 (the 4 rows of a
+//    tile fall into 4 disjoint groups of 8 banks).  The 27 taps sit in the
+//    32 input slots so that each operand's two halves are taps whose
+//    offsets differ by the same constant in both half waves (1 or 40): an
+//    operand is two paired 32-bit loads.
+//  * U[o][p] = T[o][p + d_o]: tap o's result for source q is stored at
+//    p = q - d_o of plane o (27 planes of 512, unpadded).  Stores whose p
+//    falls outside the element, and the padding rows of the second layer,
+//    go to a 32-word trash row on the bank they would have used; slots that
+//    no source reaches (the convolution's zero border) are cleared once per
+//    workgroup and never written.  The sum over taps is then 27 loads of
+//    consecutive words per position.
+// 16 KB + 55.4 KB keeps two workgroups per CU; workgroups are persistent.
+// Same roundings as the vector kernel: BF16 inputs, weights and h; FP32
+// accumulation; y summed in tap order.
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef short short2_t __attribute__((ext_vector_type(2)));
 typedef float floatx16_t __attribute__((ext_vector_type(16)));
 typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
 
 namespace nnm {
-constexpr int XP = 10;                  // bordered grid edge
-constexpr int XWORDS = XP * XP * XP;    // 1000
+constexpr int XR = 40, XPL = 400, XWORDS = 10 * XPL;  // bordered input grid
+constexpr int UOFF = XWORDS;                          // tap planes after X
+constexpr int TRASH = 27 * 512;                       // 32-word trash row
+constexpr int UWORDS = TRASH + 32;
+constexpr int LDS_BYTES = 4 * (XWORDS + UWORDS);
 constexpr int tdx(int o) { return o % 3 - 1; }
 constexpr int tdy(int o) { return (o / 3) % 3 - 1; }
 constexpr int tdz(int o) { return o / 9 - 1; }
-constexpr int ext(int d) { return d != 0 ? 8 : 7; }  // slot span hi - lo per direction
-constexpr int lo(int d) { return d > 0 ? -1 : 0; }
-constexpr int pmap(int i, int j, int k) { return i + 9 * j + 81 * k; }
-constexpr int plane_size(int o) {
-  return 1 + ext(tdx(o)) + 9 * ext(tdy(o)) + 81 * ext(tdz(o));
-}
-// second-layer result slot -> tap (slots 26, 27, 29, 30, 31 are padding)
-constexpr int slot_tap(int s) { return s < 26 ? s : (s == 28 ? 26 : -1); }
-struct Tables {
-  int rof[27];  // read offset of tap o for position p: rof[o] + pmap(p)
-  int wof[27];  // write offset of tap o for source position q: wof[o] + pmap(q)
-  int size;     // words of all planes
-  constexpr Tables() : rof(), wof(), size(0) {
-    int b = 0;
-    for (int o = 0; o < 27; ++o) {
-      rof[o] = b - pmap(lo(tdx(o)), lo(tdy(o)), lo(tdz(o)));
-      wof[o] = rof[o] - pmap(tdx(o), tdy(o), tdz(o));
-      b += plane_size(o);
+constexpr int xoff(int o) { return tdx(o) + XR * tdy(o) + XPL * tdz(o); }
+constexpr int tap_of(int dx, int dy, int dz) { return (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1); }
+// First-layer input slots: slot = 8 ks + 4h + u holds tap in_tap[slot]
+// (-1: padding, zero weight).  Slots u = 2m, 2m+1 are read as one pair at
+// offsets in_off[8ks + 4h + 2m] + {0, pair_gap(ks)}.
+struct InSlots {
+  int tap[32];
+  int off[32];  // X offset of the pair's first load (even u only)
+  constexpr InSlots() : tap(), off() {
+    int q = 0;
+    // gap-1 pairs: (dx = -1, dx = 0) of every row, then (dx = +1, padding)
+    // of the rows dy = +1; gap-40 pairs: (dx = +1, dy = -1 / 0), then
+    // two padding slots
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy) {
+        tap[q] = tap_of(-1, dy, dz), tap[q + 1] = tap_of(0, dy, dz);
+        off[q] = xoff(tap[q]);
+        q = next(q);
+      }
+    for (int dz = -1; dz <= 1; ++dz) {
+      tap[q] = tap_of(1, 1, dz), tap[q + 1] = -1;
+      off[q] = xoff(tap[q]);
+      q = next(q);
     }
-    size = b;
+    for (int dz = -1; dz <= 1; ++dz) {
+      tap[q] = tap_of(1, -1, dz), tap[q + 1] = tap_of(1, 0, dz);
+      off[q] = xoff(tap[q]);
+      q = next(q);
+    }
+    tap[q] = tap[q + 1] = -1;
+    off[q] = 0;
+  }
+  // pairs in the order (ks, m, h): fill h = 0 then h = 1 of one (ks, m)
+  static constexpr int next(int q) {
+    // q = 8ks + 4h + 2m
+    const int ks = q / 8, h = (q / 4) % 2, m = (q / 2) % 2;
+    if (h == 0) return 8 * ks + 4 + 2 * m;
+    return m == 0 ? 8 * ks + 2 : 8 * (ks + 1);
   }
 };
-constexpr Tables TB{};
-constexpr int UWORDS = TB.size;
-constexpr int LDS_BYTES = 4 * (XWORDS + UWORDS);
-static_assert(UWORDS == 18864, "tap planes");
+constexpr InSlots IN{};
+constexpr int pair_gap(int ks) { return ks < 3 ? 1 : XR; }
+// second-layer result slot -> tap (slots 26, 27, 29, 30, 31 are padding)
+constexpr int slot_tap(int s) { return s < 26 ? s : (s == 28 ? 26 : -1); }
+static_assert(26 * 512 / 64 <= 255, "tap planes reachable by 64-word load offsets");
 }  // namespace nnm
 
 // Weight operands in the per-lane A layout, packed once per weight update:
 // pk[ks * 64 + lane] for the 4 first-layer and then 2 second-layer k steps.
-// First layer: row = channel, k = 16 ks + 8h + 2u + ci <-> tap 8 ks + 4h + u.
-// Second layer: row = result slot, k = 16 ks + 8h + t <-> channel
-// 16 ks + 8(t/4) + 4h + t%4 (the first layer's result rows in that lane).
+// First layer: row = channel, k = 16 ks + 8h + 2u + ci <-> input slot
+// 8 ks + 4h + u.  Second layer: row = result slot, k = 16 ks + 8h + t <->
+// channel 16 ks + 8(t/4) + 4h + t%4 (the first layer's result rows there).
 __global__ void nn_pack_kernel(const float* __restrict__ W1, const float* __restrict__ W2,
                                bf16x8_t* __restrict__ pk) {
   const int lane = threadIdx.x & 63, ks = threadIdx.x >> 6;  // 6 x 64 threads
@@ -215,8 +247,8 @@ __global__ void nn_pack_kernel(const float* __restrict__ W1, const float* __rest
   bf16x8_t v;
   for (int t = 0; t < 8; ++t) {
     if (ks < 4) {
-      const int tap = 8 * ks + 4 * h + (t >> 1), ci = t & 1;
-      v[t] = (__bf16)(tap < 27 ? W1[row * 54 + ci * 27 + tap] : 0.f);
+      const int tap = nnm::IN.tap[8 * ks + 4 * h + (t >> 1)], ci = t & 1;
+      v[t] = (__bf16)(tap >= 0 ? W1[row * 54 + ci * 27 + tap] : 0.f);
     } else {
       const int c = 16 * (ks - 4) + 8 * (t >> 2) + 4 * h + (t & 3);
       const int tap = nnm::slot_tap(row);
@@ -226,10 +258,6 @@ __global__ void nn_pack_kernel(const float* __restrict__ W1, const float* __rest
   pk[ks * 64 + lane] = v;
 }
 
-__device__ inline unsigned pack_bf16x2(float lo_, float hi_) {
-  return (unsigned)float_to_bf16(lo_) | ((unsigned)float_to_bf16(hi_) << 16);
-}
-
 __global__ void __launch_bounds__(NN_THREADS, 2)
     nn_fwd_mfma_n8_kernel(const float* __restrict__ r, const float* __restrict__ dinv,
                           const uint8_t* __restrict__ mult, const bf16x8_t* __restrict__ pk,
@@ -237,12 +265,12 @@ __global__ void __launch_bounds__(NN_THREADS, 2)
   using namespace nnm;
   constexpr int n3 = 512;
   extern __shared__ float sm[];
-  unsigned* X = (unsigned*)sm;  // [10][10][10] BF16 pairs
-  float* U = sm + XWORDS;       // tap planes
-  __shared__ float sred[8];
+  unsigned* X = (unsigned*)sm;  // bordered BF16-pair grid
+  float* U = sm + UOFF;         // 27 tap planes + trash row
+  __shared__ float sred2[2][NN_THREADS / 64];
   if (st && st->done) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, c = lane & 31;
-  // clear both buffers once: borders of X and never-written slots of U stay 0
+  // clear once: the borders of X and the unreached slots of U stay 0
   for (int q = tid; q < XWORDS + UWORDS; q += NN_THREADS) sm[q] = 0.f;
   // weight operands (identical for every element)
   bf16x8_t a1[4], a2[2];
@@ -250,82 +278,145 @@ __global__ void __launch_bounds__(NN_THREADS, 2)
   for (int ks = 0; ks < 4; ++ks) a1[ks] = pk[ks * 64 + lane];
 #pragma unroll
   for (int ks = 0; ks < 2; ++ks) a2[ks] = pk[(4 + ks) * 64 + lane];
-  // this lane's first tile (tile 4*wave): i = c%8, j = c/8, k = 2*wave
+  // Consume the weight loads here: otherwise the first use inside the loop
+  // carries a memory-counter wait that, on later elements, waits for the
+  // previous element's result stores instead.
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) asm volatile("" ::"v"(__builtin_bit_cast(u32x4_t, a1[ks])));
+#pragma unroll
+  for (int ks = 0; ks < 2; ++ks) asm volatile("" ::"v"(__builtin_bit_cast(u32x4_t, a2[ks])));
+  // this lane's column in the wave's tiles 4*wave + mt
   const int ci_ = c & 7, cj = c >> 3, ck = 2 * wave;
-  const int xq = (ci_ + 1) + XP * (cj + 1) + XP * XP * (ck + 1);
-  int xa[4][4];  // im2col load address per (k step, tap quad)
+  const int xq = (ci_ + 1) + XR * (cj + 1) + XPL * (ck + 1);
+  int xb[4][4][2];  // im2col pair address per (tile, k step, pair)
 #pragma unroll
-  for (int ks = 0; ks < 4; ++ks)
+  for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int tap = 8 * ks + 4 * h + u;
-      xa[ks][u] = xq + (tap < 27 ? tdx(tap) + XP * tdy(tap) + XP * XP * tdz(tap) : 0);
+    for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+        xb[mt][ks][m] = xq + XPL * (mt >> 1) + 4 * XR * (mt & 1) + IN.off[8 * ks + 4 * h + 2 * m];
+  int wa[4][14];  // second-layer store address per (tile, result register)
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int v = 0; v < 14; ++v) {
+      const int o = slot_tap(8 * (v >> 2) + 4 * h + (v & 3));
+      const int dx = o >= 0 ? tdx(o) : 0, dy = o >= 0 ? tdy(o) : 0, dz = o >= 0 ? tdz(o) : 0;
+      const int pi = ci_ - dx, pj = cj + 4 * (mt & 1) - dy, pk_ = ck + (mt >> 1) - dz;
+      const int a = 512 * (o >= 0 ? o : 0) + pi + 8 * pj + 64 * pk_;
+      const bool live = o >= 0 && (unsigned)pi < 8u && (unsigned)pj < 8u && (unsigned)pk_ < 8u;
+      wa[mt][v] = live ? a : TRASH + (a & 31);
     }
-  const int uq = XWORDS + pmap(ci_, cj, ck);
-  int wa[14];  // T store address per result register (v = 13: h = 0 only)
-#pragma unroll
-  for (int v = 0; v < 14; ++v) {
-    const int s0 = 8 * (v >> 2) + (v & 3);
-    const int t0 = slot_tap(s0), t1 = slot_tap(s0 + 4);
-    wa[v] = uq + (h ? (t1 >= 0 ? TB.wof[t1] : 0) : TB.wof[t0]);
-  }
   // positions of the sum over taps: p = tid and tid + 256
   const int pi = tid & 7, pj = (tid >> 3) & 7, pk0 = tid >> 6;
-  const int ur = XWORDS + pmap(pi, pj, pk0);
-  const int xw = (pi + 1) + XP * (pj + 1) + XP * XP * (pk0 + 1);
-  __syncthreads();
-
-  for (int e = blockIdx.x; e < E; e += gridDim.x) {
-    const int64_t base = (int64_t)e * n3;
-    float rv[2], dv[2];
-    float ss = 0.f;
+  const int xw = (pi + 1) + XR * (pj + 1) + XPL * (pk0 + 1);
+  // The next element's r and dinv are loaded while this one is on the matrix
+  // cores; its per-wave partial of ||dinv r||^2 goes to the other half of
+  // sred2, so one barrier per element serves both the norm and the reuse of U.
+  float rv[2] = {0.f, 0.f}, dv[2] = {0.f, 0.f};
+  auto partial = [&](int slot) {
+    float ss = dv[0] * dv[0] + dv[1] * dv[1];
+    for (int off = 32; off > 0; off >>= 1) ss += __shfl_down(ss, off, 64);
+    if (lane == 0) sred2[slot][wave] = ss;
+  };
+  if ((int)blockIdx.x < E) {
+    const int64_t base = (int64_t)blockIdx.x * n3;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       rv[q] = r[base + tid + q * NN_THREADS];
       dv[q] = dinv[base + tid + q * NN_THREADS] * rv[q];
-      ss += dv[q] * dv[q];
     }
-    const float s = sqrtf(block_sum_bcast(ss, sred));
-    const float inv = s > 0.f ? 1.f / s : 0.f;
+    partial(0);
+  }
+  int it = 0;
+  for (int e = blockIdx.x; e < E; e += gridDim.x, ++it) {
+    const int64_t base = (int64_t)e * n3;
+    __syncthreads();  // norm partials complete; U no longer read
+    const float* sp = sred2[it & 1];
+    const float ss = (sp[0] + sp[1]) + (sp[2] + sp[3]);
+    const float inv = ss > 0.f ? rsqrtf(ss) : 0.f;
+    const float s = ss * inv;
 #pragma unroll
-    for (int q = 0; q < 2; ++q) X[xw + q * 4 * XP * XP] = pack_bf16x2(rv[q] * inv, dv[q] * inv);
+    for (int q = 0; q < 2; ++q) {
+      const bf16x2_t xv = {(__bf16)(rv[q] * inv), (__bf16)(dv[q] * inv)};
+      X[xw + q * 4 * XPL] = __builtin_bit_cast(unsigned, xv);
+    }
     __syncthreads();
+    // next element (the last one again past the end: loads stay in bounds
+    // and branch-free; the values are then unused)
+    const int en = min(e + (int)gridDim.x, E - 1);
+    float rn[2], dn[2];
+    {
+      const int64_t bn = (int64_t)en * n3;
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-      const int xs = XP * XP * (mt >> 1) + 4 * XP * (mt & 1);  // tile shift in X
-      const int us = 81 * (mt >> 1) + 36 * (mt & 1);           // tile shift in pmap
-      floatx16_t acc = {0};
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        u32x4_t w;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) w[u] = X[xa[ks][u] + xs];
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[ks], __builtin_bit_cast(bf16x8_t, w),
-                                                      acc, 0, 0, 0);
+      for (int q = 0; q < 2; ++q) {
+        rn[q] = r[bn + tid + q * NN_THREADS];
+        dn[q] = dinv[bn + tid + q * NN_THREADS];
       }
-      bf16x8_t hb[2];
+    }
+    uint8_t mv[2];
 #pragma unroll
-      for (int v = 0; v < 16; ++v) hb[v >> 3][v & 7] = (__bf16)fmaxf(acc[v], 0.f);
-      floatx16_t acc2 = {0};
+    for (int q = 0; q < 2; ++q) mv[q] = mult[base + tid + q * NN_THREADS];
+#pragma unroll
+    for (int mp = 0; mp < 4; mp += 2) {
+      floatx16_t acc[2] = {{0}, {0}};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+        for (int t2 = 0; t2 < 2; ++t2) {
+          const int mt = mp + t2;
+          u32x4_t w;
+#pragma unroll
+          for (int m = 0; m < 2; ++m) {
+            w[2 * m] = X[xb[mt][ks][m]];
+            w[2 * m + 1] = X[xb[mt][ks][m] + pair_gap(ks)];
+          }
+          acc[t2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              a1[ks], __builtin_bit_cast(bf16x8_t, w), acc[t2], 0, 0, 0);
+        }
+      u32x4_t hb[2][2];
+#pragma unroll
+      for (int t2 = 0; t2 < 2; ++t2)
+#pragma unroll
+        for (int v = 0; v < 16; v += 2) {
+          // relu after rounding: on BF16 bit patterns a signed 16-bit max
+          // with 0 clears exactly the negative values
+          typedef float float2_t __attribute__((ext_vector_type(2)));
+          const float2_t fv = {acc[t2][v], acc[t2][v + 1]};
+          const bf16x2_t hv = __builtin_convertvector(fv, bf16x2_t);
+          const short2_t hz = __builtin_elementwise_max(__builtin_bit_cast(short2_t, hv),
+                                                        (short2_t){0, 0});
+          hb[t2][v >> 3][(v & 7) >> 1] = __builtin_bit_cast(unsigned, hz);
+        }
+      floatx16_t acc2[2] = {{0}, {0}};
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks)
-        acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[ks], hb[ks], acc2, 0, 0, 0);
 #pragma unroll
-      for (int v = 0; v < 13; ++v) U[wa[v] - XWORDS + us] = acc2[v];
-      if (h == 0) U[wa[13] - XWORDS + us] = acc2[13];
+        for (int t2 = 0; t2 < 2; ++t2)
+          acc2[t2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              a2[ks], __builtin_bit_cast(bf16x8_t, hb[t2][ks]), acc2[t2], 0, 0, 0);
+#pragma unroll
+      for (int t2 = 0; t2 < 2; ++t2)
+#pragma unroll
+        for (int v = 0; v < 14; ++v) U[wa[mp + t2][v]] = acc2[t2][v];
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int p = tid + q * NN_THREADS;
-      const float* up = U + (ur - XWORDS) + q * 4 * 81;
       float y = 0.f;
 #pragma unroll
-      for (int o = 0; o < 27; ++o) y += up[TB.rof[o]];
+      for (int o = 0; o < 27; ++o) y += U[512 * o + p];
       const float zl = dv[q] + s * y;
-      const uint8_t m = mult[base + p];
-      zc[base + p] = m == 1 ? zl : zl / (float)m;
+      zc[base + p] = mv[q] == 1 ? zl : zl * __builtin_amdgcn_rcpf((float)mv[q]);
     }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      rv[q] = rn[q];
+      dv[q] = dn[q] * rn[q];
+    }
+    partial((it + 1) & 1);
   }
 }
 
