@@ -43,6 +43,9 @@ def main():
                                                            "mixed", "learned"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=200)
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="short run for hardware-counter collection: a 1 GiB device copy "
+                         "(calibration), then 20 inner iterations of the solve; no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -84,6 +87,8 @@ def main():
     b = mesh.mass_rhs(torch.as_tensor(f, device="cuda"))
     x = torch.zeros_like(b)
     opts = dict(mode=mode, tol=wl.tol, max_iter=20000, graph_chunk=16)
+    if args.traffic_probe:
+        return traffic_probe(mesh, b, mode)
 
     for i in range(args.warmup):
         x.zero_()
@@ -115,7 +120,7 @@ def main():
     vec_bytes = 8 if mode == mx.MODE_FP64 else 4
     g_bytes = 6 * (8 if mode == mx.MODE_FP64 else 2 if mode == mx.MODE_MIXED_IR_BF16G else 4)
     hb = 0 if wl.helm_h == 0 else g_bytes // 6
-    bytes_per_dof = 5 * vec_bytes + g_bytes + hb  # z, p_old in; p, w out; G (and h*B) in
+    bytes_per_dof = 4 * vec_bytes + g_bytes + hb  # z, p_old in; p, w out; G (and h*B) in
     traffic_bytes = nloc * bytes_per_dof
     achieved = traffic_bytes / (ax_avg_ms * 1e-3) / 1e9 if ax_avg_ms > 0 else 0.0
 
@@ -160,7 +165,9 @@ def main():
                    "iterations_per_step": iters / args.steps},
         "roofline": {"bound": "hbm", "kernel": "ax_kernel (fused p-update + local operator)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": ax_traffic_from_profile(mode) if wl.name == "box32_N7_deformed"
+                     else None,
                      "bytes_per_launch": traffic_bytes, "avg_launch_us": round(ax_avg_ms * 1e3, 2),
                      "launches_timed": tot},
         "setup_s": round(t_setup, 3),
@@ -172,6 +179,49 @@ def main():
     print(json.dumps(out), flush=True)
     mesh.close()
     ctx.close()
+
+
+def traffic_probe(mesh, b, mode):
+    """Kernels whose per-dispatch FETCH_SIZE / WRITE_SIZE counters give the
+    operator kernel's HBM traffic: a plain 1 GiB device-to-device copy of
+    known size (its counters calibrate the scale), then 20 iterations of the
+    inner solve (20 operator-kernel dispatches)."""
+    import torch
+
+    from paper_2503_02134_amd import mxsem as mx
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy of {src.numel() * 4} bytes done")
+    x = torch.zeros_like(b)
+    _, st = mesh.solve(b, x, mode=mx.MODE_MIXED if mode == mx.MODE_MIXED_IR else mode,
+                       tol=0.0, max_iter=20, graph_chunk=4)
+    torch.cuda.synchronize()
+    log(f"probe solve: {st.iterations} iterations")
+
+
+def ax_traffic_from_profile(mode):
+    """HBM bytes per operator-kernel launch measured by the hardware counters,
+    read from the committed profile summary; None when the operator kernel's
+    source has changed since (its SHA-256 is recorded with the figures)."""
+    import hashlib
+    import re
+    from paper_2503_02134_amd import mxsem as mx
+    if mode != mx.MODE_MIXED_IR:
+        return None
+    prof = os.path.join(ROOT, "profiles", "ax_traffic_box32_N7_deformed.md")
+    src = os.path.join(ROOT, "paper_2503_02134_amd", "csrc", "ax.hip")
+    try:
+        text = open(prof).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m_sha = re.search(r"ax\.hip sha256: ([0-9a-f]{64})", text)
+    m_b = re.search(r"traffic_bytes_per_launch: ([0-9]+)", text)
+    if not m_sha or not m_b or m_sha.group(1) != sha:
+        return None
+    return int(m_b.group(1))
 
 
 def bench_batch(args):
