@@ -28,6 +28,52 @@ struct AxApplyArgs {
   int E;
 };
 
+// The six geometric factors of local node `node` (= e n^3 + p).  FP64: the
+// master layout [E][6][n^3].  FP32 / BF16: the split layout (a 4-vector of
+// rr, rs, rt, ss per node, then a 2-vector of st, tt per node after all
+// nloc 4-vectors), i.e. two coalesced vector loads.  G is read once per
+// operator application and not again before the next one: non-temporal
+// loads keep it from displacing the CG vectors in the last-level cache.
+typedef float gf4_t __attribute__((ext_vector_type(4)));
+typedef float gf2_t __attribute__((ext_vector_type(2)));
+typedef uint16_t gh4_t __attribute__((ext_vector_type(4)));
+typedef uint16_t gh2_t __attribute__((ext_vector_type(2)));
+template <typename T, typename TG>
+__device__ inline void load_g(const gptr<const TG> G, int64_t nloc, int64_t node, int n3, T* g) {
+  if constexpr (sizeof(TG) == 8) {
+    const int64_t e = node / n3, p = node - e * n3;
+    const gptr<const TG> ge = G + e * 6 * n3 + p;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) g[q] = (T)__builtin_nontemporal_load(&ge[q * n3]);
+  } else if constexpr (sizeof(TG) == 4) {
+    const gf4_t a = __builtin_nontemporal_load(&((gptr<const gf4_t>)G)[node]);
+    const gf2_t b = __builtin_nontemporal_load(&((gptr<const gf2_t>)(G + 4 * nloc))[node]);
+    g[0] = a.x, g[1] = a.y, g[2] = a.z, g[3] = a.w, g[4] = b.x, g[5] = b.y;
+  } else {
+    const gh4_t a = __builtin_nontemporal_load(&((gptr<const gh4_t>)G)[node]);
+    const gh2_t b = __builtin_nontemporal_load(&((gptr<const gh2_t>)(G + 4 * nloc))[node]);
+    g[0] = cvt<T>((bf16_t)a.x), g[1] = cvt<T>((bf16_t)a.y), g[2] = cvt<T>((bf16_t)a.z);
+    g[3] = cvt<T>((bf16_t)a.w), g[4] = cvt<T>((bf16_t)b.x), g[5] = cvt<T>((bf16_t)b.y);
+  }
+}
+
+// Synchronisation of one element's threads around its LDS slabs.  When
+// n^2 divides 64, no element straddles two wave64s, and the slab exchange
+// stays inside one wave: LDS instructions of a wave complete in issue
+// order, so a compiler-level wave barrier (no instruction) suffices and the
+// elements of a workgroup run unsynchronised.  Otherwise a workgroup
+// barrier.
+template <int n2>
+__device__ inline void elem_sync() {
+  if constexpr (64 % n2 == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // Solver variant: p = z + beta p_old (beta from the device state, p
 // written back), w = A_L p, and the workgroup's partial sum of p.w.
 template <int N, typename T, typename TG, bool SOLVER>
@@ -39,33 +85,36 @@ __global__ void __launch_bounds__(256) ax_kernel(const Tile* __restrict__ tiles,
   T* slab = sD + n2;
   __shared__ double sred[16];
 
-  const T* __restrict__ Dg;
-  const TG* __restrict__ G;
-  const TG* __restrict__ hB;
-  const T* __restrict__ U;
-  T* __restrict__ Wout;
-  const T* __restrict__ Z = nullptr;
+  gptr<const T> __restrict__ Dg;
+  gptr<const TG> __restrict__ G;
+  gptr<const TG> __restrict__ hB;
+  gptr<const T> __restrict__ U;
+  gptr<T> __restrict__ Wout;
+  gptr<const T> __restrict__ Z = nullptr;
   int E, first;
+  int64_t nloc_all;  // local entries of the whole problem (locates the split G parts)
   const ProbDev* P = nullptr;
   if constexpr (SOLVER) {
     const Tile t = tiles[blockIdx.x];
     P = &probs[t.prob];
-    if (P->st->done) return;  // uniform across the workgroup
-    Dg = (const T*)P->D;
-    G = (const TG*)P->G;
-    hB = (const TG*)P->hB;
-    U = (const T*)P->p;
-    Wout = (T*)P->w;
-    Z = (const T*)P->z;
+    if (gcast(P->st)->done) return;  // uniform across the workgroup
+    Dg = gcast((const T*)P->D);
+    G = gcast((const TG*)P->G);
+    hB = gcast((const TG*)P->hB);
+    U = gcast((const T*)P->p);
+    Wout = gcast((T*)P->w);
+    Z = gcast((const T*)P->z);
     E = P->E;
+    nloc_all = P->nloc;
     first = t.first;
   } else {
-    Dg = (const T*)apply.D;
-    G = (const TG*)apply.G;
-    hB = (const TG*)apply.hB;
-    U = (const T*)apply.u;
-    Wout = (T*)apply.w;
+    Dg = gcast((const T*)apply.D);
+    G = gcast((const TG*)apply.G);
+    hB = gcast((const TG*)apply.hB);
+    U = gcast((const T*)apply.u);
+    Wout = gcast((T*)apply.w);
     E = apply.E;
+    nloc_all = (int64_t)E * n3;
     first = blockIdx.x * epb;
   }
 
@@ -93,8 +142,8 @@ __global__ void __launch_bounds__(256) ax_kernel(const Tile* __restrict__ tiles,
   const int64_t base = (int64_t)e * n3 + ij;
   if (active) {
     if constexpr (SOLVER) {
-      const T beta = (T)P->st->beta;
-      T* __restrict__ Pw = (T*)P->p;
+      const T beta = (T)gcast(P->st)->beta;
+      gptr<T> __restrict__ Pw = gcast((T*)P->p);
 #pragma unroll
       for (int k = 0; k < n; ++k) {
         T pv = Z[base + k * n2] + beta * U[base + k * n2];
@@ -114,20 +163,22 @@ __global__ void __launch_bounds__(256) ax_kernel(const Tile* __restrict__ tiles,
   // they fit in registers, so every load of the element is in flight at
   // once (the workgroup barriers inside the loop would otherwise serialise
   // one HBM round trip per k).
-  const TG* __restrict__ Ge = G + (int64_t)e * 6 * n3 + ij;
+  const int64_t gnode = (int64_t)(active ? e : 0) * n3 + ij;  // inactive lanes read element 0
   constexpr bool PREFETCH = 6 * n * sizeof(T) <= 512;
   T gpre[PREFETCH ? 6 * n : 1];
   if constexpr (PREFETCH) {
 #pragma unroll
-    for (int k = 0; k < n; ++k)
+    for (int k = 0; k < n; ++k) {
+      T gk[6];
+      load_g<T, TG>(G, nloc_all, gnode + k * n2, n3, gk);
 #pragma unroll
-      for (int q = 0; q < 6; ++q)
-        gpre[q * n + k] = active ? cvt<T>(Ge[q * n3 + k * n2]) : T(0);
+      for (int q = 0; q < 6; ++q) gpre[q * n + k] = active ? gk[q] : T(0);
+    }
   }
 #pragma unroll
   for (int k = 0; k < n; ++k) {
     if (active) su[ij] = u[k];
-    __syncthreads();
+    elem_sync<n2>();
     if (active) {
       T ur = T(0), us = T(0), ut = T(0);
 #pragma unroll
@@ -136,7 +187,6 @@ __global__ void __launch_bounds__(256) ax_kernel(const Tile* __restrict__ tiles,
         us += Dj[l] * su[l * n + i];
         ut += sD[k * n + l] * u[l];
       }
-      const int off = k * n2;
       T g0, g1, g2, g3, g4, g5;
       if constexpr (PREFETCH) {
         g0 = gpre[0 * n + k];
@@ -146,12 +196,9 @@ __global__ void __launch_bounds__(256) ax_kernel(const Tile* __restrict__ tiles,
         g4 = gpre[4 * n + k];
         g5 = gpre[5 * n + k];
       } else {
-        g0 = cvt<T>(Ge[0 * n3 + off]);
-        g1 = cvt<T>(Ge[1 * n3 + off]);
-        g2 = cvt<T>(Ge[2 * n3 + off]);
-        g3 = cvt<T>(Ge[3 * n3 + off]);
-        g4 = cvt<T>(Ge[4 * n3 + off]);
-        g5 = cvt<T>(Ge[5 * n3 + off]);
+        T gk[6];
+        load_g<T, TG>(G, nloc_all, gnode + k * n2, n3, gk);
+        g0 = gk[0], g1 = gk[1], g2 = gk[2], g3 = gk[3], g4 = gk[4], g5 = gk[5];
       }
       const T wr = g0 * ur + g1 * us + g2 * ut;
       const T ws = g1 * ur + g3 * us + g4 * ut;
@@ -161,14 +208,14 @@ __global__ void __launch_bounds__(256) ax_kernel(const Tile* __restrict__ tiles,
       sr[ij] = wr;
       ss[ij] = ws;
     }
-    __syncthreads();
+    elem_sync<n2>();
     if (active) {
       T acc = T(0);
 #pragma unroll
       for (int l = 0; l < n; ++l) acc += DiT[l] * sr[j * n + l] + DjT[l] * ss[l * n + i];
       w[k] += acc;
     }
-    __syncthreads();
+    elem_sync<n2>();
   }
 
   // (p, QQ^T A_L p)_c = sum_i p_i (A_L p)_i over all local entries, because
@@ -179,14 +226,14 @@ __global__ void __launch_bounds__(256) ax_kernel(const Tile* __restrict__ tiles,
 #pragma unroll
     for (int k = 0; k < n; ++k) {
       T wv = w[k];
-      if (hB) wv += cvt<T>(hB[(int64_t)e * n3 + k * n2 + ij]) * u[k];
+      if (hB) wv += cvt<T>(__builtin_nontemporal_load(&hB[(int64_t)e * n3 + k * n2 + ij])) * u[k];
       Wout[base + k * n2] = wv;
       if constexpr (SOLVER) dot += (double)u[k] * (double)wv;
     }
   }
   if constexpr (SOLVER) {
     double s = block_sum(dot, sred);
-    if (tid == 0) P->part_ax[first / epb] = s;
+    if (tid == 0) gcast(P->part_ax)[first / epb] = s;
   }
 }
 

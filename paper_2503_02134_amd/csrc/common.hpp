@@ -103,6 +103,17 @@ struct State {
 
 // A tile: a block of work of one problem (elements, groups or entries);
 // aux selects the gather-scatter bucket.
+// Device pointers read from device-side structs are generic (flat)
+// pointers to the compiler; flat loads count against the LDS counter as
+// well, so every LDS wait would also wait for them.  Kernels cast such
+// pointers to the global address space, which gives global_load/store.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ inline gptr<T> gcast(T* p) {
+  return (gptr<T>)p;
+}
+
 struct Tile {
   int prob;
   int first;

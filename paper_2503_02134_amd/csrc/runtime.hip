@@ -443,7 +443,7 @@ int mxsem_mesh_create(mxsem_ctx* ctx, const mxsem_mesh_desc* d, mxsem_mesh** out
   }
   if (m->views & MXSEM_VIEW_F32) {
     MX_MTRY(mesh_alloc(m, (void**)&m->G32, sizeof(float) * 6 * nloc));
-    MX_MHIP(launch_cast_f32(m->G32, m->G64, 6 * nloc, s));
+    MX_MHIP(launch_cast_g_split(1, m->G32, m->G64, m->E, n * n * n, s));
     if (m->hB64) {
       MX_MTRY(mesh_alloc(m, (void**)&m->hB32, sizeof(float) * nloc));
       MX_MHIP(launch_cast_f32(m->hB32, m->hB64, nloc, s));
@@ -451,7 +451,7 @@ int mxsem_mesh_create(mxsem_ctx* ctx, const mxsem_mesh_desc* d, mxsem_mesh** out
   }
   if (m->views & MXSEM_VIEW_BF16) {
     MX_MTRY(mesh_alloc(m, (void**)&m->G16, sizeof(bf16_t) * 6 * nloc));
-    MX_MHIP(launch_cast_bf16(m->G16, m->G64, 6 * nloc, s));
+    MX_MHIP(launch_cast_g_split(2, m->G16, m->G64, m->E, n * n * n, s));
     if (m->hB64) {
       MX_MTRY(mesh_alloc(m, (void**)&m->hB16, sizeof(bf16_t) * nloc));
       MX_MHIP(launch_cast_bf16(m->hB16, m->hB64, nloc, s));

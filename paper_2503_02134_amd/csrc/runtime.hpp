@@ -53,6 +53,8 @@ hipError_t launch_zero(double* x, int64_t n, hipStream_t s);
 hipError_t launch_mass(const double* B, const double* f, double* b, int64_t n, hipStream_t s);
 hipError_t launch_cast_f32(float* d, const double* src, int64_t n, hipStream_t s);
 hipError_t launch_cast_bf16(bf16_t* d, const double* src, int64_t n, hipStream_t s);
+hipError_t launch_cast_g_split(int gprec, void* d, const double* G64, int E, int n3,
+                               hipStream_t s);
 hipError_t launch_geom(int E, int n, const double* xyz, const double* D, const double* wq,
                        const double* kcoef, double* G, double* B, double* detmin, int* nblocks,
                        hipStream_t s);
@@ -128,8 +130,8 @@ struct mxsem_mesh {
   double* D64 = nullptr;
   float* D32 = nullptr;
   double* G64 = nullptr;
-  float* G32 = nullptr;
-  mx::bf16_t* G16 = nullptr;
+  float* G32 = nullptr;       // split layout: [nloc] x 4 (rr rs rt ss), then [nloc] x 2 (st tt)
+  mx::bf16_t* G16 = nullptr;  // same split layout in BF16
   double* B64 = nullptr;
   double* hB64 = nullptr;
   float* hB32 = nullptr;

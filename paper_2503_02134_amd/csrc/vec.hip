@@ -20,6 +20,9 @@
 namespace mx {
 
 // ------------------------------------------------------------ gather-scatter
+typedef int gi2_t __attribute__((ext_vector_type(2)));
+typedef int gi4_t __attribute__((ext_vector_type(4)));
+
 struct GsApi {
   void* v;
   GsPlan plan;
@@ -35,24 +38,24 @@ __global__ void __launch_bounds__(GS_THREADS) gs_kernel(const Tile* __restrict__
                                                         const ProbDev* __restrict__ probs,
                                                         GsApi api) {
   const GsPlan* plan;
-  T* __restrict__ v;
+  gptr<T> __restrict__ v;
   int bucket, first;
   if constexpr (SOLVER) {
     const Tile t = tiles[blockIdx.x];
     const ProbDev& P = probs[t.prob];
-    if (P.st->done) return;
+    if (gcast(P.st)->done) return;
     plan = &P.gs;
-    v = (T*)(api.on_z ? P.z : P.w);
+    v = gcast((T*)(api.on_z ? P.z : P.w));
     bucket = t.aux;
     first = t.first;
   } else {
     plan = &api.plan;
-    v = (T*)api.v;
+    v = gcast((T*)api.v);
     bucket = api.bucket;
     first = blockIdx.x * GS_CHUNK;
   }
   const GsBucket bk = plan->bk[bucket];
-  const int* __restrict__ idx = plan->idx + bk.off;
+  const gptr<const int> __restrict__ idx = gcast((const int*)plan->idx) + bk.off;
   const int m = bk.m;
   int g[GS_PER_THREAD];
   bool ok[GS_PER_THREAD];
@@ -66,11 +69,11 @@ __global__ void __launch_bounds__(GS_THREADS) gs_kernel(const Tile* __restrict__
     for (int q = 0; q < GS_PER_THREAD; ++q)
       if (ok[q]) v[idx[g[q]]] = T(0);
   } else if (m == 2) {
-    int2 ix[GS_PER_THREAD];
+    gi2_t ix[GS_PER_THREAD];
     T a0[GS_PER_THREAD], a1[GS_PER_THREAD];
 #pragma unroll
     for (int q = 0; q < GS_PER_THREAD; ++q)
-      if (ok[q]) ix[q] = ((const int2*)idx)[g[q]];
+      if (ok[q]) ix[q] = ((gptr<const gi2_t>)idx)[g[q]];
 #pragma unroll
     for (int q = 0; q < GS_PER_THREAD; ++q)
       if (ok[q]) {
@@ -85,11 +88,11 @@ __global__ void __launch_bounds__(GS_THREADS) gs_kernel(const Tile* __restrict__
         v[ix[q].y] = val;
       }
   } else if (m == 4) {
-    int4 ix[GS_PER_THREAD];
+    gi4_t ix[GS_PER_THREAD];
     T a[GS_PER_THREAD][4];
 #pragma unroll
     for (int q = 0; q < GS_PER_THREAD; ++q)
-      if (ok[q]) ix[q] = ((const int4*)idx)[g[q]];
+      if (ok[q]) ix[q] = ((gptr<const gi4_t>)idx)[g[q]];
 #pragma unroll
     for (int q = 0; q < GS_PER_THREAD; ++q)
       if (ok[q]) {
@@ -111,8 +114,8 @@ __global__ void __launch_bounds__(GS_THREADS) gs_kernel(const Tile* __restrict__
 #pragma unroll
     for (int q = 0; q < GS_PER_THREAD; ++q)
       if (ok[q]) {
-        const int4 i0 = ((const int4*)idx)[2 * g[q]];
-        const int4 i1 = ((const int4*)idx)[2 * g[q] + 1];
+        const gi4_t i0 = ((gptr<const gi4_t>)idx)[2 * g[q]];
+        const gi4_t i1 = ((gptr<const gi4_t>)idx)[2 * g[q] + 1];
         ACC s = (ACC)v[i0.x];
         s += (ACC)v[i0.y];
         s += (ACC)v[i0.z];
@@ -129,7 +132,7 @@ __global__ void __launch_bounds__(GS_THREADS) gs_kernel(const Tile* __restrict__
 #pragma unroll
     for (int q = 0; q < GS_PER_THREAD; ++q)
       if (ok[q]) {
-        const int* gi = idx + (int64_t)g[q] * m;
+        const gptr<const int> gi = idx + (int64_t)g[q] * m;
         ACC s = (ACC)v[gi[0]];
         for (int k = 1; k < m; ++k) s += (ACC)v[gi[k]];
         const T val = (T)s;
@@ -152,6 +155,36 @@ struct V4<double> {
   typedef double4 type;
 };
 
+
+// Cache policy of the CG step on gfx950.  Per iteration the solve streams
+// about 1.4 GB (FP32) through a 256 MB last-level cache (MALL).  Arrays read
+// or written once per iteration and not again before the next iteration (G,
+// dinv, multiplicity, x, r) use non-temporal accesses, so that they do not
+// displace the vectors that are reused within the iteration (p and w from
+// the operator kernel to the update, z from the update to the next operator
+// kernel), and so that each kernel's dirty lines reach HBM during that
+// kernel instead of being written back during the next one.
+template <typename VT, typename T>
+__device__ inline void st4_nt(T* dst, const VT& v) {
+  typedef T E4 __attribute__((ext_vector_type(4)));
+  E4 e = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(e, (E4*)dst);
+}
+template <typename VT, typename T>
+__device__ inline VT ld4_nt(const T* src) {
+  typedef T E4 __attribute__((ext_vector_type(4)));
+  E4 e = __builtin_nontemporal_load((const E4*)src);
+  VT v;
+  v.x = e.x, v.y = e.y, v.z = e.z, v.w = e.w;
+  return v;
+}
+__device__ inline uchar4 ld_u8x4_nt(const uint8_t* src) {
+  const uint32_t m4 = __builtin_nontemporal_load((const uint32_t*)src);
+  uchar4 m;
+  m.x = m4 & 255, m.y = (m4 >> 8) & 255, m.z = (m4 >> 16) & 255, m.w = m4 >> 24;
+  return m;
+}
+
 // PC: 0 identity, 1 Jacobi, -1 none (z left alone; flexible CG computes it)
 // x += alpha p; r -= alpha w; z = M^-1 r; partials (r,z)_c and (r,r)_c.
 // Each thread handles UPD_PER_THREAD entries as 4-wide vectors when the
@@ -163,15 +196,15 @@ __global__ void __launch_bounds__(UPD_THREADS) update_kernel(const Tile* __restr
   __shared__ ACC sred[16];
   const Tile t = tiles[blockIdx.x];
   const ProbDev& P = probs[t.prob];
-  if (P.st->done) return;
-  const T alpha = (T)P.st->alpha;
-  T* __restrict__ x = (T*)P.x;
-  T* __restrict__ r = (T*)P.r;
-  T* __restrict__ z = (T*)P.z;
-  const T* __restrict__ p = (const T*)P.p;
-  const T* __restrict__ w = (const T*)P.w;
-  const T* __restrict__ dinv = (const T*)P.dinv;
-  const uint8_t* __restrict__ mult = P.mult;
+  if (gcast(P.st)->done) return;
+  const T alpha = (T)gcast(P.st)->alpha;
+  gptr<T> __restrict__ x = gcast((T*)P.x);
+  gptr<T> __restrict__ r = gcast((T*)P.r);
+  gptr<T> __restrict__ z = gcast((T*)P.z);
+  const gptr<const T> __restrict__ p = gcast((const T*)P.p);
+  const gptr<const T> __restrict__ w = gcast((const T*)P.w);
+  const gptr<const T> __restrict__ dinv = gcast((const T*)P.dinv);
+  const gptr<const uint8_t> __restrict__ mult = gcast(P.mult);
   ACC rz = ACC(0), rr = ACC(0);
   if ((P.nloc & 3) == 0) {
     typedef typename V4<T>::type VT;
@@ -179,13 +212,13 @@ __global__ void __launch_bounds__(UPD_THREADS) update_kernel(const Tile* __restr
     for (int q = 0; q < UPD_PER_THREAD / 4; ++q) {
       const int64_t v = (int64_t)t.first / 4 + q * UPD_THREADS + threadIdx.x;
       if (4 * v < P.nloc) {
-        VT xv = ((const VT*)x)[v], pv = ((const VT*)p)[v], rv = ((const VT*)r)[v],
-           wv = ((const VT*)w)[v];
-        const uchar4 mv = ((const uchar4*)mult)[v];
+        VT xv = ld4_nt<VT>((const T*)&((const VT*)x)[v]), pv = ((const VT*)p)[v],
+           rv = ld4_nt<VT>((const T*)&((const VT*)r)[v]), wv = ((const VT*)w)[v];
+        const uchar4 mv = ld_u8x4_nt((const uint8_t*)&((const uchar4*)mult)[v]);
         xv.x += alpha * pv.x; xv.y += alpha * pv.y; xv.z += alpha * pv.z; xv.w += alpha * pv.w;
         rv.x -= alpha * wv.x; rv.y -= alpha * wv.y; rv.z -= alpha * wv.z; rv.w -= alpha * wv.w;
-        ((VT*)x)[v] = xv;
-        ((VT*)r)[v] = rv;
+        st4_nt<VT>((T*)&((VT*)x)[v], xv);
+        st4_nt<VT>((T*)&((VT*)r)[v], rv);
         const ACC c0 = (ACC)cweight(mv.x), c1 = (ACC)cweight(mv.y), c2 = (ACC)cweight(mv.z),
                   c3 = (ACC)cweight(mv.w);
         rr += (ACC)rv.x * c0 * (ACC)rv.x;
@@ -195,7 +228,7 @@ __global__ void __launch_bounds__(UPD_THREADS) update_kernel(const Tile* __restr
         if constexpr (PC >= 0) {
           VT zv = rv;
           if constexpr (PC == 1) {
-            const VT dv = ((const VT*)dinv)[v];
+            const VT dv = ld4_nt<VT>((const T*)&((const VT*)dinv)[v]);
             zv.x = dv.x * rv.x; zv.y = dv.y * rv.y; zv.z = dv.z * rv.z; zv.w = dv.w * rv.w;
           }
           ((VT*)z)[v] = zv;
@@ -229,8 +262,8 @@ __global__ void __launch_bounds__(UPD_THREADS) update_kernel(const Tile* __restr
   ACC s1 = block_sum(rr, sred);
   if (threadIdx.x == 0) {
     const int b = t.first / UPD_CHUNK;
-    P.part_u0[b] = (double)s0;
-    P.part_u1[b] = (double)s1;
+    gcast(P.part_u0)[b] = (double)s0;
+    gcast(P.part_u1)[b] = (double)s1;
   }
 }
 
@@ -242,23 +275,23 @@ __global__ void init_kernel(const Tile* __restrict__ tiles, const ProbDev* __res
   __shared__ ACC sred[16];
   const Tile t = tiles[blockIdx.x];
   const ProbDev& P = probs[t.prob];
-  if (P.st->done) return;
-  T* __restrict__ x = (T*)P.x;
-  T* __restrict__ r = (T*)P.r;
-  T* __restrict__ z = (T*)P.z;
-  T* __restrict__ p = (T*)P.p;
-  const T* __restrict__ dinv = (const T*)P.dinv;
+  if (gcast(P.st)->done) return;
+  gptr<T> __restrict__ x = gcast((T*)P.x);
+  gptr<T> __restrict__ r = gcast((T*)P.r);
+  gptr<T> __restrict__ z = gcast((T*)P.z);
+  gptr<T> __restrict__ p = gcast((T*)P.p);
+  const gptr<const T> __restrict__ dinv = gcast((const T*)P.dinv);
   const double scale = P.rhs_scale;
   ACC rz = ACC(0), rr = ACC(0);
 #pragma unroll
   for (int q = 0; q < UPD_PER_THREAD; ++q) {
     const int64_t i = (int64_t)t.first + q * UPD_THREADS + threadIdx.x;
     if (i < P.nloc) {
-      const T rv = (T)(P.rhs64[i] * scale);
+      const T rv = (T)(gcast(P.rhs64)[i] * scale);
       r[i] = rv;
       x[i] = x0 ? (T)x0[i] : T(0);
       p[i] = T(0);
-      const ACC c = (ACC)cweight(P.mult[i]);
+      const ACC c = (ACC)cweight(gcast(P.mult)[i]);
       rr += (ACC)rv * c * (ACC)rv;
       if constexpr (PC >= 0) {
         const T zv = (PC == 1) ? dinv[i] * rv : rv;
@@ -271,8 +304,8 @@ __global__ void init_kernel(const Tile* __restrict__ tiles, const ProbDev* __res
   ACC s1 = block_sum(rr, sred);
   if (threadIdx.x == 0) {
     const int b = t.first / UPD_CHUNK;
-    P.part_u0[b] = (double)s0;
-    P.part_u1[b] = (double)s1;
+    gcast(P.part_u0)[b] = (double)s0;
+    gcast(P.part_u1)[b] = (double)s1;
   }
 }
 
@@ -281,7 +314,8 @@ __global__ void init_kernel(const Tile* __restrict__ tiles, const ProbDev* __res
 // thread t adds parts[t + k*FIN_THREADS] into accumulator k % 8 (eight
 // independent chains keep eight loads in flight), then the accumulators,
 // then the block.  The order depends only on n.
-__device__ inline double fixed_sum(const double* __restrict__ parts, int n, double* sred) {
+__device__ inline double fixed_sum(const gptr<const double> __restrict__ parts, int n,
+                                   double* sred) {
   double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int q = threadIdx.x;
   for (; q + 7 * FIN_THREADS < n; q += 8 * FIN_THREADS) {
@@ -299,9 +333,9 @@ __device__ inline double fixed_sum(const double* __restrict__ parts, int n, doub
 __global__ void fin_sigma_kernel(const ProbDev* __restrict__ probs) {
   __shared__ double sred[16];
   const ProbDev& P = probs[blockIdx.x];
-  State* st = P.st;
+  const gptr<State> st = gcast(P.st);
   if (st->done) return;
-  const double sigma_all = fixed_sum(P.part_ax, P.nblk_ax, sred);
+  const double sigma_all = fixed_sum(gcast((const double*)P.part_ax), P.nblk_ax, sred);
   if (threadIdx.x == 0) {
     const double sigma = sigma_all;
     st->sigma = sigma;
@@ -321,10 +355,10 @@ __global__ void fin_sigma_kernel(const ProbDev* __restrict__ probs) {
 __global__ void fin_rho_kernel(const ProbDev* __restrict__ probs, int mode) {
   __shared__ double sred[16];
   const ProbDev& P = probs[blockIdx.x];
-  State* st = P.st;
+  const gptr<State> st = gcast(P.st);
   if (st->done) return;
-  double rz = fixed_sum(P.part_u0, P.nblk_upd, sred);
-  double rr = fixed_sum(P.part_u1, P.nblk_upd, sred);
+  double rz = fixed_sum(gcast((const double*)P.part_u0), P.nblk_upd, sred);
+  double rr = fixed_sum(gcast((const double*)P.part_u1), P.nblk_upd, sred);
   if (threadIdx.x != 0) return;
   st->rr = rr;
   if (mode == 1 || mode == 3) {
@@ -335,7 +369,7 @@ __global__ void fin_rho_kernel(const ProbDev* __restrict__ probs, int mode) {
     st->since = 0;
     st->best = 1.0;
     st->res = rr > 0.0 ? 1.0 : 0.0;
-    if (st->history) st->history[0] = st->res;
+    if (st->history) gcast(st->history)[0] = st->res;
     if (!(rr > 0.0)) {
       st->done = 1;
       st->reason = MXSEM_CONVERGED;
@@ -346,7 +380,7 @@ __global__ void fin_rho_kernel(const ProbDev* __restrict__ probs, int mode) {
   st->iter = it;
   const double res = sqrt(rr / st->bb);
   st->res = res;
-  if (st->history) st->history[it] = res;
+  if (st->history) gcast(st->history)[it] = res;
   if (rr <= st->tol2 * st->bb) {
     st->done = 1;
     st->reason = MXSEM_CONVERGED;
@@ -385,10 +419,10 @@ __global__ void __launch_bounds__(UPD_THREADS) zpc_kernel(const Tile* __restrict
                                                           int pc, int only_pending) {
   const Tile t = tiles[blockIdx.x];
   const ProbDev& P = probs[t.prob];
-  if (P.st->done || (only_pending && !P.st->fb_pending)) return;
-  const T* __restrict__ r = (const T*)P.r;
-  const T* __restrict__ dinv = (const T*)P.dinv;
-  T* __restrict__ z = (T*)P.z;
+  if (gcast(P.st)->done || (only_pending && !gcast(P.st)->fb_pending)) return;
+  const gptr<const T> __restrict__ r = gcast((const T*)P.r);
+  const gptr<const T> __restrict__ dinv = gcast((const T*)P.dinv);
+  gptr<T> __restrict__ z = gcast((T*)P.z);
 #pragma unroll
   for (int q = 0; q < UPD_PER_THREAD; ++q) {
     const int64_t i = (int64_t)t.first + q * UPD_THREADS + threadIdx.x;
@@ -404,16 +438,16 @@ __global__ void __launch_bounds__(UPD_THREADS) fcg_dots_kernel(const Tile* __res
   __shared__ ACC sred[16];
   const Tile t = tiles[blockIdx.x];
   const ProbDev& P = probs[t.prob];
-  if (P.st->done || (only_pending && !P.st->fb_pending)) return;
-  const T* __restrict__ r = (const T*)P.r;
-  const T* __restrict__ z = (const T*)P.z;
-  const T* __restrict__ w = (const T*)P.w;
+  if (gcast(P.st)->done || (only_pending && !gcast(P.st)->fb_pending)) return;
+  const gptr<const T> __restrict__ r = gcast((const T*)P.r);
+  const gptr<const T> __restrict__ z = gcast((const T*)P.z);
+  const gptr<const T> __restrict__ w = gcast((const T*)P.w);
   ACC rz = ACC(0), zw = ACC(0);
 #pragma unroll
   for (int q = 0; q < UPD_PER_THREAD; ++q) {
     const int64_t i = (int64_t)t.first + q * UPD_THREADS + threadIdx.x;
     if (i < P.nloc) {
-      const ACC c = (ACC)cweight(P.mult[i]);
+      const ACC c = (ACC)cweight(gcast(P.mult)[i]);
       rz += (ACC)r[i] * c * (ACC)z[i];
       zw += (ACC)z[i] * c * (ACC)w[i];
     }
@@ -422,8 +456,8 @@ __global__ void __launch_bounds__(UPD_THREADS) fcg_dots_kernel(const Tile* __res
   ACC s1 = block_sum(zw, sred);
   if (threadIdx.x == 0) {
     const int b = t.first / UPD_CHUNK;
-    P.part_u0[b] = (double)s0;
-    P.part_u2[b] = (double)s1;
+    gcast(P.part_u0)[b] = (double)s0;
+    gcast(P.part_u2)[b] = (double)s1;
   }
 }
 
@@ -434,10 +468,10 @@ __global__ void __launch_bounds__(UPD_THREADS) fcg_dots_kernel(const Tile* __res
 __global__ void fin_beta_kernel(const ProbDev* __restrict__ probs, int init, int second) {
   __shared__ double sred[16];
   const ProbDev& P = probs[blockIdx.x];
-  State* st = P.st;
+  const gptr<State> st = gcast(P.st);
   if (st->done || (second && !st->fb_pending)) return;
-  double rz = fixed_sum(P.part_u0, P.nblk_upd, sred);
-  double zw = fixed_sum(P.part_u2, P.nblk_upd, sred);
+  double rz = fixed_sum(gcast((const double*)P.part_u0), P.nblk_upd, sred);
+  double zw = fixed_sum(gcast((const double*)P.part_u2), P.nblk_upd, sred);
   if (threadIdx.x != 0) return;
   if (!second && st->pc == MXSEM_PC_LEARNED &&
       (!(rz > 0.0) || !isfinite(rz) || (!init && !isfinite(zw)))) {
@@ -469,7 +503,7 @@ __global__ void dot_kernel(const T* __restrict__ a, const T* __restrict__ b,
 
 __global__ void final_sum_kernel(const double* __restrict__ part, int n, double* __restrict__ out) {
   __shared__ double sred[16];
-  double s = fixed_sum(part, n, sred);
+  double s = fixed_sum(gcast(part), n, sred);
   if (threadIdx.x == 0) *out = s;
 }
 
@@ -529,6 +563,35 @@ __global__ void cast_kernel(TD* __restrict__ d, const TS* __restrict__ s, int64_
 __global__ void cast_bf16_kernel(bf16_t* __restrict__ d, const double* __restrict__ s, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) d[i] = float_to_bf16((float)s[i]);
+}
+
+// FP32 / BF16 copies of the geometric factors in the node-interleaved
+// layout the operator kernels read: per local node (e, p) the components
+// rr, rs, rt, ss of G as one 4-vector, then (after all E n^3 of those) st,
+// tt as one 2-vector.  A thread then loads its node's six factors with two
+// coalesced vector loads instead of six scalar ones.
+template <typename TG>
+__global__ void cast_g_split_kernel(TG* __restrict__ d, const double* __restrict__ G64, int E,
+                                    int n3) {
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nloc = (int64_t)E * n3;
+  if (node >= nloc) return;
+  const int64_t e = node / n3, p = node - e * n3;
+  const double* g = G64 + e * 6 * n3 + p;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if constexpr (sizeof(TG) == 2)
+      d[node * 4 + c] = float_to_bf16((float)g[c * n3]);
+    else
+      d[node * 4 + c] = (TG)g[c * n3];
+  }
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    if constexpr (sizeof(TG) == 2)
+      d[4 * nloc + node * 2 + c] = float_to_bf16((float)g[(4 + c) * n3]);
+    else
+      d[4 * nloc + node * 2 + c] = (TG)g[(4 + c) * n3];
+  }
 }
 
 __global__ void fill_state_kernel(State* __restrict__ st, int nprob, const State* __restrict__ tmpl) {
@@ -719,6 +782,18 @@ hipError_t launch_mass(const double* B, const double* f, double* b, int64_t n, h
 
 hipError_t launch_cast_f32(float* d, const double* src, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL((cast_kernel<float, double>), dim3(nblk(n, 256)), dim3(256), 0, s, d, src, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_g_split(int gprec, void* d, const double* G64, int E, int n3,
+                               hipStream_t s) {
+  const int64_t nloc = (int64_t)E * n3;
+  if (gprec == 1)
+    hipLaunchKernelGGL(cast_g_split_kernel<float>, dim3(nblk(nloc, 256)), dim3(256), 0, s,
+                       (float*)d, G64, E, n3);
+  else
+    hipLaunchKernelGGL(cast_g_split_kernel<bf16_t>, dim3(nblk(nloc, 256)), dim3(256), 0, s,
+                       (bf16_t*)d, G64, E, n3);
   return hipGetLastError();
 }
 
