@@ -178,6 +178,9 @@ constexpr int UPD_PER_THREAD = 8;  // entries per thread (two 4-wide vectors)
 constexpr int UPD_CHUNK = UPD_THREADS * UPD_PER_THREAD;
 constexpr int FIN_THREADS = 1024;  // final-reduction workgroup
 constexpr int MAX_N = 15;
+// accelerator dies (XCDs) of the MI355X: consecutive workgroups of a launch
+// are dealt to them in turn, each die with its own L2
+constexpr int XCDS = 8;
 // stagnation: no 10% improvement of the best relative residual in this many
 // iterations (CG residuals on high-contrast coefficients plateau for
 // hundreds of iterations before falling again)

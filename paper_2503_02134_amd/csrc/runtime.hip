@@ -382,6 +382,7 @@ int mxsem_mesh_create(mxsem_ctx* ctx, const mxsem_mesh_desc* d, mxsem_mesh** out
   std::vector<int32_t> idx;
   GsPlan plan{};
   int nb = 0;
+  m->gs_first.assign(MAX_BUCKETS, {});
   auto emit = [&](std::vector<std::vector<Grp>>& bks) -> bool {
     for (int mm : morder) {
       auto& gv = bks[mm];
@@ -391,8 +392,12 @@ int mxsem_mesh_create(mxsem_ctx* ctx, const mxsem_mesh_desc* d, mxsem_mesh** out
                 [&order](const Grp& x, const Grp& y) { return order[x.first] < order[y.first]; });
       while (idx.size() % 4) idx.push_back(0);  // 16-byte aligned bucket start
       plan.bk[nb] = GsBucket{mm, (int)gv.size(), (int)idx.size(), 0};
-      for (const Grp& gr : gv)
+      std::vector<int32_t>& gf = m->gs_first[nb];
+      gf.reserve(gv.size());
+      for (const Grp& gr : gv) {
+        gf.push_back(order[gr.first]);
         for (int t = 0; t < gr.m; ++t) idx.push_back(order[gr.first + t]);
+      }
       ++nb;
     }
     return true;
@@ -404,6 +409,7 @@ int mxsem_mesh_create(mxsem_ctx* ctx, const mxsem_mesh_desc* d, mxsem_mesh** out
   while (idx.size() % 4) idx.push_back(0);
   plan.bk[nb] = GsBucket{0, (int)masklist.size(), (int)idx.size(), 0};
   idx.insert(idx.end(), masklist.begin(), masklist.end());
+  m->gs_first[nb] = masklist;
   m->ngroups = ngroups;
   m->nmask_entries = (int)masklist.size();
   MX_MTRY(mesh_alloc(m, (void**)&m->gs_idx, sizeof(int) * std::max<size_t>(idx.size(), 4)));

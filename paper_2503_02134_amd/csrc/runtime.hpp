@@ -141,6 +141,9 @@ struct mxsem_mesh {
   uint8_t* mult = nullptr;
   int* gs_idx = nullptr;
   mx::GsPlan plan{};          // device index array + bucket table
+  // host copy, per bucket: the first (smallest) local index of each group
+  // in bucket order (mask list: its entries); places solver tiles
+  std::vector<std::vector<int32_t>> gs_first;
   int64_t ngroups = 0;        // groups of >= 2 copies
   int nmask_entries = 0;      // Dirichlet entries
   double min_det = 0.0;

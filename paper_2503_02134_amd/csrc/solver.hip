@@ -110,6 +110,36 @@ static int plan_alloc(Plan* pl, void** p, size_t bytes) {
   return MXSEM_OK;
 }
 
+// Gather-scatter tiles of problem p, sorted into one list per XCD.  The
+// gather-scatter is the one kernel whose workgroups share cache lines (a
+// line of w holds entries of several groups, of several multiplicities),
+// and each XCD has its own L2: tiles that touch the same elements should
+// run on the same XCD, close together in time.  So the elements are cut
+// into XCDS contiguous chunks, each chunk into blocks of about 32K local
+// entries, and for every block the groups of every bucket whose first
+// copy lies in the block become tiles of that chunk's list, block by
+// block.  Tile.pad is the tile's group count (at most GS_CHUNK).
+static void gs_tiles_by_xcd(const mxsem_mesh* m, int p, std::vector<std::vector<Tile>>& lists) {
+  const int nx = (int)lists.size();
+  const int64_t n3 = m->n3;
+  const int eb = (int)std::max<int64_t>(1, 32768 / n3);
+  std::vector<size_t> cur(MAX_BUCKETS, 0);
+  for (int e0 = 0; e0 < m->E; e0 += eb) {
+    const int e1 = std::min(m->E, e0 + eb);
+    const int x = (int)((int64_t)e0 * nx / m->E);
+    const int64_t lim = (int64_t)e1 * n3;
+    for (int q = 0; q <= m->plan.nall; ++q) {
+      if (q >= m->plan.nfree && q < m->plan.nall) continue;  // Dirichlet groups: masked instead
+      const std::vector<int32_t>& gf = m->gs_first[q];
+      size_t g1 = cur[q];
+      while (g1 < gf.size() && gf[g1] < lim) ++g1;
+      for (size_t f = cur[q]; f < g1; f += GS_CHUNK)
+        lists[x].push_back(Tile{p, (int)f, q, (int)std::min<size_t>(GS_CHUNK, g1 - f)});
+      cur[q] = g1;
+    }
+  }
+}
+
 // Build the launch plan of P problems (all on one context) in vprec.
 int plan_build(mxsem_mesh* const* meshes, int P, int vprec, Plan** out) {
   Plan* pl = new Plan();
@@ -122,6 +152,7 @@ int plan_build(mxsem_mesh* const* meshes, int P, int vprec, Plan** out) {
     return code;
   };
   std::vector<Tile> tg, tu;
+  std::vector<std::vector<Tile>> gsl(XCDS);
   pl->hprob.resize(P);
   for (int p = 0; p < P; ++p) {
     mxsem_mesh* m = meshes[p];
@@ -153,11 +184,17 @@ int plan_build(mxsem_mesh* const* meshes, int P, int vprec, Plan** out) {
     Q.nblk_ax = (m->E + pl->epb_used[p] - 1) / pl->epb_used[p];
     Q.nblk_gs = b->nt_gs;
     Q.nblk_upd = b->nt_upd;
-    for (int q = 0; q <= m->plan.nall; ++q) {
-      if (q >= m->plan.nfree && q < m->plan.nall) continue;
-      for (int f = 0; f < m->plan.bk[q].ngroups; f += GS_CHUNK) tg.push_back(Tile{p, f, q, 0});
-    }
+    gs_tiles_by_xcd(m, p, gsl);
     for (int q = 0; q < b->nt_upd; ++q) tu.push_back(Tile{p, q * UPD_CHUNK, 0, 0});
+  }
+  // workgroup b of a launch runs on XCD b % XCDS: interleave the lists,
+  // padding with empty tiles so that the alignment holds to the end
+  {
+    size_t len = 0;
+    for (const auto& l : gsl) len = std::max(len, l.size());
+    for (size_t i = 0; i < len; ++i)
+      for (int x = 0; x < XCDS; ++x)
+        tg.push_back(i < gsl[x].size() ? gsl[x][i] : Tile{0, 0, 0, 0});
   }
   // operator classes (N, tile size)
   std::vector<std::pair<int, int>> keys;

@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(GS_THREADS) gs_kernel(const Tile* __restrict__
                                                         GsApi api) {
   const GsPlan* plan;
   gptr<T> __restrict__ v;
-  int bucket, first;
+  int bucket, first, count = GS_CHUNK;
   if constexpr (SOLVER) {
     const Tile t = tiles[blockIdx.x];
     const ProbDev& P = probs[t.prob];
@@ -48,6 +48,7 @@ __global__ void __launch_bounds__(GS_THREADS) gs_kernel(const Tile* __restrict__
     v = gcast((T*)(api.on_z ? P.z : P.w));
     bucket = t.aux;
     first = t.first;
+    count = t.pad;
   } else {
     plan = &api.plan;
     v = gcast((T*)api.v);
@@ -62,7 +63,7 @@ __global__ void __launch_bounds__(GS_THREADS) gs_kernel(const Tile* __restrict__
 #pragma unroll
   for (int q = 0; q < GS_PER_THREAD; ++q) {
     g[q] = first + q * GS_THREADS + threadIdx.x;
-    ok[q] = g[q] < bk.ngroups;
+    ok[q] = g[q] < bk.ngroups && g[q] < first + count;
   }
   if (m == 0) {
 #pragma unroll
