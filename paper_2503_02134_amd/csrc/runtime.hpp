@@ -25,8 +25,10 @@ hipError_t launch_ax_solver(int prec, int N, const Tile* tiles, int ntiles, cons
 int max_epb(int N);
 hipError_t launch_gs_apply(int prec_io, int prec_acc, void* v, const GsPlan& plan, bool mask,
                            hipStream_t s);
+// sigma_probs > 0: the launch also finishes sigma and alpha of problems
+// 0..sigma_probs-1 (alpha = rho / sigma, breakdown test) in workgroups of its own
 hipError_t launch_gs_solver(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs,
-                            hipStream_t s, bool on_z = false);
+                            hipStream_t s, bool on_z = false, int sigma_probs = 0);
 hipError_t launch_zpc(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs, int pc,
                       int only_pending, hipStream_t s);
 hipError_t launch_fcg_dots(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs,
@@ -39,7 +41,6 @@ hipError_t launch_update(int vprec, int pc, const Tile* tiles, int ntiles, const
                          hipStream_t s);
 hipError_t launch_init(int vprec, int pc, const Tile* tiles, int ntiles, const ProbDev* probs,
                        const double* x0, hipStream_t s);
-hipError_t launch_fin_sigma(const ProbDev* probs, int nprob, hipStream_t s);
 hipError_t launch_fin_rho(const ProbDev* probs, int nprob, int mode, hipStream_t s);
 hipError_t launch_dot(int prec, const void* a, const void* b, const uint8_t* mult, int64_t n,
                       double* part, double* out, hipStream_t s);

@@ -267,8 +267,7 @@ int enqueue_ax(Plan* pl, int gprec, hipStream_t s, bool skip_first) {
 }
 
 static int enqueue_tail(Plan* pl, int pc, hipStream_t s) {
-  MX_HIP(launch_gs_solver(pl->vprec, pl->tiles_gs, pl->nt_gs, pl->probs, s));
-  MX_HIP(launch_fin_sigma(pl->probs, pl->P, s));
+  MX_HIP(launch_gs_solver(pl->vprec, pl->tiles_gs, pl->nt_gs, pl->probs, s, false, pl->P));
   MX_HIP(launch_update(pl->vprec, pc, pl->tiles_upd, pl->nt_upd, pl->probs, s));
   MX_HIP(launch_fin_rho(pl->probs, pl->P, 0, s));
   return MXSEM_OK;
@@ -424,8 +423,7 @@ static int get_graph_fcg(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K) {
   for (int k = 0; k < K && rc == MXSEM_OK; ++k) {
     if (k > 0) rc = enqueue_ax(pl, gprec, cs, false);
     if (rc != MXSEM_OK) break;
-    hipError_t e = launch_gs_solver(pl->vprec, pl->tiles_gs, pl->nt_gs, pl->probs, cs);
-    if (e == hipSuccess) e = launch_fin_sigma(pl->probs, pl->P, cs);
+    hipError_t e = launch_gs_solver(pl->vprec, pl->tiles_gs, pl->nt_gs, pl->probs, cs, false, pl->P);
     if (e == hipSuccess) e = launch_update(pl->vprec, -1, pl->tiles_upd, pl->nt_upd, pl->probs, cs);
     if (e == hipSuccess) e = launch_fin_rho(pl->probs, pl->P, 2, cs);
     if (e != hipSuccess) {

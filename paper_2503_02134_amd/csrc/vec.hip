@@ -27,8 +27,15 @@ struct GsApi {
   void* v;
   GsPlan plan;
   int bucket;
-  int on_z;  // solver variant: sum z instead of w
+  int on_z;   // solver variant: sum z instead of w
+  int nfin;   // solver variant: leading workgroups that finish sigma (0: none)
+  int nprob;  // problems whose sigma they finish (the rest of the nfin do nothing)
 };
+
+template <int NT>
+__device__ inline double fixed_sum(const gptr<const double> __restrict__ parts, int n,
+                                   double* sred);
+__device__ inline void fin_sigma_step(const ProbDev& P, double* sred);
 
 // One thread per group, GS_PER_THREAD groups per thread issued together:
 // all index loads, then all value loads, then sums (ascending local index,
@@ -41,7 +48,16 @@ __global__ void __launch_bounds__(GS_THREADS) gs_kernel(const Tile* __restrict__
   gptr<T> __restrict__ v;
   int bucket, first, count = GS_CHUNK;
   if constexpr (SOLVER) {
-    const Tile t = tiles[blockIdx.x];
+    // sigma = (p, A p)_c and alpha need only the operator kernel's partial
+    // sums, not the gather-scatter: the first nfin workgroups finish them
+    // while the others sum copies (nfin is a multiple of XCDS, so the tiles
+    // keep their XCD placement)
+    if ((int)blockIdx.x < api.nfin) {
+      __shared__ double sred[16];
+      if ((int)blockIdx.x < api.nprob) fin_sigma_step(probs[blockIdx.x], sred);
+      return;
+    }
+    const Tile t = tiles[blockIdx.x - api.nfin];
     const ProbDev& P = probs[t.prob];
     if (gcast(P.st)->done) return;
     plan = &P.gs;
@@ -315,30 +331,29 @@ __global__ void init_kernel(const Tile* __restrict__ tiles, const ProbDev* __res
 // thread t adds parts[t + k*FIN_THREADS] into accumulator k % 8 (eight
 // independent chains keep eight loads in flight), then the accumulators,
 // then the block.  The order depends only on n.
+template <int NT>
 __device__ inline double fixed_sum(const gptr<const double> __restrict__ parts, int n,
                                    double* sred) {
   double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int q = threadIdx.x;
-  for (; q + 7 * FIN_THREADS < n; q += 8 * FIN_THREADS) {
+  for (; q + 7 * NT < n; q += 8 * NT) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) a[k] += parts[q + k * FIN_THREADS];
+    for (int k = 0; k < 8; ++k) a[k] += parts[q + k * NT];
   }
 #pragma unroll
   for (int k = 0; k < 8; ++k)
-    if (q + k * FIN_THREADS < n) a[k] += parts[q + k * FIN_THREADS];
+    if (q + k * NT < n) a[k] += parts[q + k * NT];
   const double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   return block_sum(s, sred);
 }
 
-// sigma = (p, A p)_c; alpha = rho / sigma; breakdown if sigma <= 0 or not finite
-__global__ void fin_sigma_kernel(const ProbDev* __restrict__ probs) {
-  __shared__ double sred[16];
-  const ProbDev& P = probs[blockIdx.x];
+// sigma = (p, A p)_c; alpha = rho / sigma; breakdown if sigma <= 0 or not
+// finite.  Run by a workgroup of the gather-scatter launch of the same step.
+__device__ inline void fin_sigma_step(const ProbDev& P, double* sred) {
   const gptr<State> st = gcast(P.st);
   if (st->done) return;
-  const double sigma_all = fixed_sum(gcast((const double*)P.part_ax), P.nblk_ax, sred);
+  const double sigma = fixed_sum<GS_THREADS>(gcast((const double*)P.part_ax), P.nblk_ax, sred);
   if (threadIdx.x == 0) {
-    const double sigma = sigma_all;
     st->sigma = sigma;
     if (!(sigma > 0.0) || !isfinite(sigma)) {
       st->done = 1;
@@ -358,8 +373,8 @@ __global__ void fin_rho_kernel(const ProbDev* __restrict__ probs, int mode) {
   const ProbDev& P = probs[blockIdx.x];
   const gptr<State> st = gcast(P.st);
   if (st->done) return;
-  double rz = fixed_sum(gcast((const double*)P.part_u0), P.nblk_upd, sred);
-  double rr = fixed_sum(gcast((const double*)P.part_u1), P.nblk_upd, sred);
+  double rz = fixed_sum<FIN_THREADS>(gcast((const double*)P.part_u0), P.nblk_upd, sred);
+  double rr = fixed_sum<FIN_THREADS>(gcast((const double*)P.part_u1), P.nblk_upd, sred);
   if (threadIdx.x != 0) return;
   st->rr = rr;
   if (mode == 1 || mode == 3) {
@@ -471,8 +486,8 @@ __global__ void fin_beta_kernel(const ProbDev* __restrict__ probs, int init, int
   const ProbDev& P = probs[blockIdx.x];
   const gptr<State> st = gcast(P.st);
   if (st->done || (second && !st->fb_pending)) return;
-  double rz = fixed_sum(gcast((const double*)P.part_u0), P.nblk_upd, sred);
-  double zw = fixed_sum(gcast((const double*)P.part_u2), P.nblk_upd, sred);
+  double rz = fixed_sum<FIN_THREADS>(gcast((const double*)P.part_u0), P.nblk_upd, sred);
+  double zw = fixed_sum<FIN_THREADS>(gcast((const double*)P.part_u2), P.nblk_upd, sred);
   if (threadIdx.x != 0) return;
   if (!second && st->pc == MXSEM_PC_LEARNED &&
       (!(rz > 0.0) || !isfinite(rz) || (!init && !isfinite(zw)))) {
@@ -504,7 +519,7 @@ __global__ void dot_kernel(const T* __restrict__ a, const T* __restrict__ b,
 
 __global__ void final_sum_kernel(const double* __restrict__ part, int n, double* __restrict__ out) {
   __shared__ double sred[16];
-  double s = fixed_sum(gcast(part), n, sred);
+  double s = fixed_sum<FIN_THREADS>(gcast(part), n, sred);
   if (threadIdx.x == 0) *out = s;
 }
 
@@ -632,11 +647,14 @@ hipError_t launch_gs_apply(int prec_io, int prec_acc, void* v, const GsPlan& pla
 
 // vector precision: 0 FP64, 1 FP32 (FP64 accumulation), 3 FP32 (FP32 accumulation)
 hipError_t launch_gs_solver(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs,
-                            hipStream_t s, bool on_z) {
-  if (ntiles == 0) return hipSuccess;
-  dim3 g(ntiles), b(GS_THREADS);
+                            hipStream_t s, bool on_z, int sigma_probs) {
+  const int nfin = ((sigma_probs + XCDS - 1) / XCDS) * XCDS;
+  if (ntiles + nfin == 0) return hipSuccess;
+  dim3 g(nfin + ntiles), b(GS_THREADS);
   GsApi a{};
   a.on_z = on_z ? 1 : 0;
+  a.nfin = nfin;
+  a.nprob = sigma_probs;
   if (vprec == 0)
     hipLaunchKernelGGL((gs_kernel<double, double, true>), g, b, 0, s, tiles, probs, a);
   else if (vprec == 1)
@@ -683,11 +701,6 @@ hipError_t launch_init(int vprec, int pc, const Tile* tiles, int ntiles, const P
   if (vprec == 0) init_dispatch<double, double>(pc, g, b, s, tiles, probs, x0);
   else if (vprec == 1) init_dispatch<float, double>(pc, g, b, s, tiles, probs, x0);
   else init_dispatch<float, float>(pc, g, b, s, tiles, probs, x0);
-  return hipGetLastError();
-}
-
-hipError_t launch_fin_sigma(const ProbDev* probs, int nprob, hipStream_t s) {
-  hipLaunchKernelGGL(fin_sigma_kernel, dim3(nprob), dim3(FIN_THREADS), 0, s, probs);
   return hipGetLastError();
 }
 
