@@ -137,6 +137,20 @@ def main():
     d = (x_mixed - x64).double()
     extra["rel_diff_vs_fp64_solution"] = float(torch.linalg.vector_norm(d)
                                                / torch.linalg.vector_norm(x64))
+    if mode == mx.MODE_MIXED_IR:
+        # the same refinement with BF16 geometric factors (FP32 vectors,
+        # FP32 accumulation in the operator)
+        xb = torch.zeros_like(b)
+        _, sb = mesh.solve(b, xb, mode=mx.MODE_MIXED_IR_BF16G, tol=wl.tol, max_iter=20000,
+                           graph_chunk=16)
+        bb = 4 * 4 + 6 * 2 + (2 if wl.helm_h else 0)
+        extra["mixed_ir_bf16g"] = {
+            "ms": round(sb.ms, 3), "iterations": sb.iterations, "outer": sb.outer,
+            "rel_res": sb.rel_res, "gain_vs_fp64": round(s64.ms / sb.ms, 3),
+            "rel_diff_vs_fp64_solution": float(torch.linalg.vector_norm((xb - x64).double())
+                                               / torch.linalg.vector_norm(x64)),
+            "ax_us": round(sb.ax_ms * 1e3, 2),
+            "ax_gbs": round(nloc * bb / (sb.ax_ms * 1e-3) / 1e9, 1) if sb.ax_ms > 0 else None}
     tt = {}
     for name, md in (("fp64", mx.MODE_FP64), (args.mode, mode)):
         xt = torch.zeros_like(b)

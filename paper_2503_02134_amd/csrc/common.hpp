@@ -190,6 +190,9 @@ constexpr int STAG_WINDOW = 500;
 // Deterministic block sum of one double per thread (wave64 shuffles, then
 // LDS across waves).  Every thread of the block must call it.  Returns the
 // sum on thread 0.
+// c = 1/m, the weight of a local copy in the c-weighted dots
+__device__ inline double cweight(uint8_t m) { return m == 1 ? 1.0 : 1.0 / (double)m; }
+
 template <typename A>
 __device__ inline A block_sum(A v, A* sred) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);

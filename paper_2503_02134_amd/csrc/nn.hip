@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(NN_THREADS)
     nn_fwd_kernel(const float* __restrict__ r, const float* __restrict__ dinv,
                   const uint8_t* __restrict__ mult, const float* __restrict__ W1,
                   const float* __restrict__ W2, float* __restrict__ zc, int E,
-                  const State* __restrict__ st) {
+                  const State* __restrict__ st, NnDots dd) {
   constexpr int n = N + 1, n3 = n * n * n, PPT = (n3 + NN_THREADS - 1) / NN_THREADS;
   extern __shared__ float sm[];
   float* x0 = sm;           // [2][n3]
@@ -125,6 +125,7 @@ __global__ void __launch_bounds__(NN_THREADS)
     for (int o = 0; o < 27; ++o) T[p * 27 + o] = t[o];
   }
   __syncthreads();
+  double dsum[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     const int p = threadIdx.x + q * NN_THREADS;
@@ -138,7 +139,23 @@ __global__ void __launch_bounds__(NN_THREADS)
     }
     const float zl = dv[q] + s * y;
     const uint8_t m = mult[base + p];
-    zc[base + p] = m == 1 ? zl : zl / (float)m;
+    const float zv = m == 1 ? zl : zl / (float)m;
+    zc[base + p] = zv;
+    if (dd.dots) {
+      const double wq = (double)dd.w[base + p], cj = cweight(m) * (double)dv[q];
+      dsum[0] += (double)rv[q] * (double)zv;
+      dsum[1] += wq * (double)zv;
+      dsum[2] += (double)rv[q] * cj;
+      dsum[3] += wq * cj;
+    }
+  }
+  if (dd.dots) {
+    __shared__ double dred[16];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double a = block_sum(dsum[k], dred);
+      if (threadIdx.x == 0) dd.dots[k * dd.dstride + e] = a;
+    }
   }
 }
 
@@ -261,7 +278,8 @@ __global__ void nn_pack_kernel(const float* __restrict__ W1, const float* __rest
 __global__ void __launch_bounds__(NN_THREADS, 2)
     nn_fwd_mfma_n8_kernel(const float* __restrict__ r, const float* __restrict__ dinv,
                           const uint8_t* __restrict__ mult, const bf16x8_t* __restrict__ pk,
-                          float* __restrict__ zc, int E, const State* __restrict__ st) {
+                          float* __restrict__ zc, int E, const State* __restrict__ st,
+                          NnDots dd) {
   using namespace nnm;
   constexpr int n3 = 512;
   extern __shared__ float sm[];
@@ -314,7 +332,10 @@ __global__ void __launch_bounds__(NN_THREADS, 2)
   // The next element's r and dinv are loaded while this one is on the matrix
   // cores; its per-wave partial of ||dinv r||^2 goes to the other half of
   // sred2, so one barrier per element serves both the norm and the reuse of U.
-  float rv[2] = {0.f, 0.f}, dv[2] = {0.f, 0.f};
+  // w for the dots, loaded with r and dinv one element ahead (r stands in
+  // when no dots are asked for, so the loop has no branch)
+  const float* __restrict__ wsrc = dd.dots ? dd.w : r;
+  float rv[2] = {0.f, 0.f}, dv[2] = {0.f, 0.f}, wv[2] = {0.f, 0.f};
   auto partial = [&](int slot) {
     float ss = dv[0] * dv[0] + dv[1] * dv[1];
     for (int off = 32; off > 0; off >>= 1) ss += __shfl_down(ss, off, 64);
@@ -326,9 +347,11 @@ __global__ void __launch_bounds__(NN_THREADS, 2)
     for (int q = 0; q < 2; ++q) {
       rv[q] = r[base + tid + q * NN_THREADS];
       dv[q] = dinv[base + tid + q * NN_THREADS] * rv[q];
+      wv[q] = wsrc[base + tid + q * NN_THREADS];
     }
     partial(0);
   }
+  double dsum[4] = {0.0, 0.0, 0.0, 0.0};  // this workgroup's share of the dots
   int it = 0;
   for (int e = blockIdx.x; e < E; e += gridDim.x, ++it) {
     const int64_t base = (int64_t)e * n3;
@@ -346,13 +369,14 @@ __global__ void __launch_bounds__(NN_THREADS, 2)
     // next element (the last one again past the end: loads stay in bounds
     // and branch-free; the values are then unused)
     const int en = min(e + (int)gridDim.x, E - 1);
-    float rn[2], dn[2];
+    float rn[2], dn[2], wn[2];
     {
       const int64_t bn = (int64_t)en * n3;
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         rn[q] = r[bn + tid + q * NN_THREADS];
         dn[q] = dinv[bn + tid + q * NN_THREADS];
+        wn[q] = wsrc[bn + tid + q * NN_THREADS];
       }
     }
     uint8_t mv[2];
@@ -409,14 +433,32 @@ __global__ void __launch_bounds__(NN_THREADS, 2)
 #pragma unroll
       for (int o = 0; o < 27; ++o) y += U[512 * o + p];
       const float zl = dv[q] + s * y;
-      zc[base + p] = mv[q] == 1 ? zl : zl * __builtin_amdgcn_rcpf((float)mv[q]);
+      // the weight applied to z_L also weights the Jacobi candidate's dots
+      // (exact for the power-of-two multiplicities of a box mesh)
+      const float cq = mv[q] == 1 ? 1.f : __builtin_amdgcn_rcpf((float)mv[q]);
+      const float zv = zl * cq;
+      zc[base + p] = zv;
+      const double cj = (double)cq * (double)dv[q];
+      dsum[0] += (double)rv[q] * (double)zv;
+      dsum[1] += (double)wv[q] * (double)zv;
+      dsum[2] += (double)rv[q] * cj;
+      dsum[3] += (double)wv[q] * cj;
     }
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       rv[q] = rn[q];
       dv[q] = dn[q] * rn[q];
+      wv[q] = wn[q];
     }
     partial((it + 1) & 1);
+  }
+  if (dd.dots) {
+    __shared__ double dred[16];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double a = block_sum(dsum[k], dred);
+      if (tid == 0) dd.dots[k * dd.dstride + blockIdx.x] = a;
+    }
   }
 }
 
@@ -661,7 +703,7 @@ static size_t bwd_lds() {
 
 hipError_t launch_nn_fwd(int N, const float* r, const float* dinv, const uint8_t* mult,
                          const float* W1, const float* W2, float* zc, int E, hipStream_t s,
-                         const State* st, const void* packed) {
+                         const State* st, const void* packed, NnDots dd, int* nparts) {
   if (N == 7) {
     // persistent: two workgroups per CU, each walking elements blockIdx.x, +grid, ...
     int dev = 0, ncu = 0;
@@ -669,16 +711,20 @@ hipError_t launch_nn_fwd(int N, const float* r, const float* dinv, const uint8_t
     if (err == hipSuccess) err = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (err != hipSuccess) return err;
     const int grid = std::min(E, 2 * std::max(ncu, 1));
+    if (nparts) *nparts = grid;
     if (grid <= 0) return hipSuccess;
+    if (dd.dots && grid > dd.dstride) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(nn_fwd_mfma_n8_kernel, dim3(grid), dim3(NN_THREADS), nnm::LDS_BYTES, s, r,
-                       dinv, mult, (const bf16x8_t*)packed, zc, E, st);
+                       dinv, mult, (const bf16x8_t*)packed, zc, E, st, dd);
     return hipGetLastError();
   }
+  if (nparts) *nparts = E;
+  if (dd.dots && E > dd.dstride) return hipErrorInvalidConfiguration;
   switch (N) {
 #define MX_NN(NN_)                                                                          \
   case NN_:                                                                                 \
     hipLaunchKernelGGL((nn_fwd_kernel<NN_>), dim3(E), dim3(NN_THREADS), fwd_lds<NN_>(), s, r, \
-                       dinv, mult, W1, W2, zc, E, st);                                      \
+                       dinv, mult, W1, W2, zc, E, st, dd);                                  \
     break;
     MX_NN(3) MX_NN(5) MX_NN(7)
 #undef MX_NN
@@ -717,6 +763,8 @@ struct mxsem_nn {
   void* packed = nullptr; // [6][64] BF16x8 weight operands of the matrix-core forward
   float *z = nullptr, *d = nullptr, *Ad = nullptr, *g = nullptr;
   double* nd = nullptr;   // [2 * max samples] numerators / denominators
+  double* dots = nullptr; // [4][dstride] per-workgroup flexible-CG dot partials of the forward
+  int dstride = 0;
   int nd_cap = 0;
   int nbwd = 0;
   std::vector<void*> allocs;
@@ -734,18 +782,24 @@ static int nn_alloc(mxsem_nn* nn, void** p, size_t bytes) {
 }
 static inline unsigned nb256(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-// z = M QQ^T (c z_L(r)) into out (FP32)
-int nn_launch_fwd(mxsem_nn* nn, const float* r, float* zc, hipStream_t s, const State* st) {
+// zc = c z_L(r) (the caller's gather-scatter then gives z = M QQ^T zc);
+// with w, also the partials of (r, z)_c and (z, w)_c: nn->dots, *nparts
+// per dot, nn->dstride apart
+int nn_launch_fwd(mxsem_nn* nn, const float* r, float* zc, hipStream_t s, const State* st,
+                  const float* w, int* nparts, const double** dots, int* dstride) {
   mxsem_mesh* m = nn->mesh;
+  NnDots dd{w, w ? nn->dots : nullptr, nn->dstride};
   MX_HIP(launch_nn_fwd(m->N, r, m->dinv32, m->mult, nn->Wq, nn->Wq + NN_W1, zc, m->E, s, st,
-                       nn->packed));
+                       nn->packed, dd, nparts));
+  if (dots) *dots = nn->dots;
+  if (dstride) *dstride = nn->dstride;
   return MXSEM_OK;
 }
 
 int nn_forward_into(mxsem_nn* nn, const float* r, float* out, hipStream_t s) {
   mxsem_mesh* m = nn->mesh;
   MX_HIP(launch_nn_fwd(m->N, r, m->dinv32, m->mult, nn->Wq, nn->Wq + NN_W1, out, m->E, s,
-                       nullptr, nn->packed));
+                       nullptr, nn->packed, NnDots{nullptr, nullptr, 0}, nullptr));
   MX_HIP(launch_gs_apply(MXSEM_F32, MXSEM_F64, out, m->plan, true, s));
   return MXSEM_OK;
 }
@@ -777,6 +831,8 @@ int mxsem_nn_create(mxsem_mesh* m, const mxsem_nn_desc* d, mxsem_nn** out) {
   A((void**)&nn->mo, sizeof(float) * NN_NP);
   A((void**)&nn->ve, sizeof(float) * NN_NP);
   A((void**)&nn->part, sizeof(float) * NN_NP * nn->nbwd);
+  nn->dstride = std::max(m->E, 4096);  // at least every forward grid's workgroup count
+  A((void**)&nn->dots, sizeof(double) * 4 * nn->dstride);
   A((void**)&nn->packed, 16 * 6 * 64);
   A((void**)&nn->z, sizeof(float) * nl);
   A((void**)&nn->d, sizeof(float) * nl);

@@ -26,17 +26,42 @@ int max_epb(int N);
 hipError_t launch_gs_apply(int prec_io, int prec_acc, void* v, const GsPlan& plan, bool mask,
                            hipStream_t s);
 // sigma_probs > 0: the launch also finishes sigma and alpha of problems
-// 0..sigma_probs-1 (alpha = rho / sigma, breakdown test) in workgroups of its own
+// 0..sigma_probs-1 (alpha = rho / sigma, breakdown test) in workgroups of its own.
+// ztiles (with on_z): vector-pass tiles of workgroups that set z = dinv r
+// where the step's learned z was rejected (fb_pending); the gather-scatter
+// tiles of such a problem do nothing.
 hipError_t launch_gs_solver(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs,
-                            hipStream_t s, bool on_z = false, int sigma_probs = 0);
+                            hipStream_t s, bool on_z = false, int sigma_probs = 0,
+                            const Tile* ztiles = nullptr, int nz = 0);
 hipError_t launch_zpc(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs, int pc,
-                      int only_pending, hipStream_t s);
+                      hipStream_t s);
 hipError_t launch_fcg_dots(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs,
-                           int only_pending, hipStream_t s);
-hipError_t launch_fin_beta(const ProbDev* probs, int nprob, int init, int second, hipStream_t s);
+                           hipStream_t s);
+// dots (optional, single problem): the learned forward's partials of the
+// learned and the Jacobi candidate's dots (NnDots layout, ndots per dot):
+// the step takes the learned z unless it is rejected, then the Jacobi z
+// (fb_pending tells the following gather-scatter launch to form it)
+hipError_t launch_fin_beta(const ProbDev* probs, int nprob, int init, hipStream_t s,
+                           const double* dots = nullptr, int ndots = 0, int dstride = 0);
+// The flexible-CG dots of the step, from zc = c z_L before assembly: r
+// and w = A p are continuous and zero on Dirichlet nodes, and z = M QQ^T zc
+// with the weights c summing to 1 over a node's copies, so
+//   (r, z)_c = sum_i r_i zc_i,   (z, w)_c = sum_i w_i zc_i
+// over all local entries (equal up to rounding to the dots of the assembled
+// z).  The same pass gives the dots of the Jacobi candidate z_J = dinv r
+// (continuous already): sum_i r_i c_i z_J,i and sum_i w_i c_i z_J,i.  Each
+// workgroup of the forward writes its four partials to
+// dots[k * dstride + blockIdx.x], k = 0..3 in that order; dots == nullptr
+// skips them.
+struct NnDots {
+  const float* w;
+  double* dots;
+  int dstride;
+};
+// nparts (optional): workgroups of the launch, i.e. partials per dot
 hipError_t launch_nn_fwd(int N, const float* r, const float* dinv, const uint8_t* mult,
                          const float* W1, const float* W2, float* zc, int E, hipStream_t s,
-                         const State* st, const void* packed);
+                         const State* st, const void* packed, NnDots dd, int* nparts);
 hipError_t launch_update(int vprec, int pc, const Tile* tiles, int ntiles, const ProbDev* probs,
                          hipStream_t s);
 hipError_t launch_init(int vprec, int pc, const Tile* tiles, int ntiles, const ProbDev* probs,
@@ -172,6 +197,10 @@ const void* G_ptr(const mxsem_mesh* m, int gprec);
 const void* hB_ptr(const mxsem_mesh* m, int gprec);
 int apply_impl(mxsem_mesh* m, int prec, const void* u, void* w, unsigned flags, hipStream_t s);
 // learned preconditioner: forward of an attached network into zc (before
-// the gather-scatter); the kernel returns at once when st->done
-int nn_launch_fwd(mxsem_nn* nn, const float* r, float* zc, hipStream_t s, const State* st);
+// the gather-scatter); the kernel returns at once when st->done.  With w
+// (= A p of the step), also the partials of (r,z)_c and (z,w)_c: *dots,
+// *nparts per dot, *dstride apart.
+int nn_launch_fwd(mxsem_nn* nn, const float* r, float* zc, hipStream_t s, const State* st,
+                  const float* w = nullptr, int* nparts = nullptr, const double** dots = nullptr,
+                  int* dstride = nullptr);
 }  // namespace mx

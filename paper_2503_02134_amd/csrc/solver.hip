@@ -391,19 +391,22 @@ static int run_inner(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K, Inner& 
 // beta.  A rejected learned z is replaced by Jacobi within the same step.
 static int enqueue_fcg_z(Plan* pl, int pc, hipStream_t s, bool init) {
   if (pc == MXSEM_PC_LEARNED) {
+    // The forward also sums the step's dots, for the learned z (from c z_L)
+    // and for the Jacobi candidate dinv r, so beta and the choice between
+    // them come before the assembly; one launch then assembles the learned
+    // z or, where it was rejected, writes dinv r.
     mxsem_mesh* m = pl->meshes[0];
+    int nparts = 0, dstride = 0;
+    const double* dots = nullptr;
     MX_TRY(nn_launch_fwd(m->nn, (const float*)pl->bufs[0]->r, (float*)pl->bufs[0]->z, s,
-                         pl->hprob[0].st));
-    MX_HIP(launch_gs_solver(pl->vprec, pl->tiles_gs, pl->nt_gs, pl->probs, s, true));
+                         pl->hprob[0].st, (const float*)pl->bufs[0]->w, &nparts, &dots, &dstride));
+    MX_HIP(launch_fin_beta(pl->probs, pl->P, init ? 1 : 0, s, dots, nparts, dstride));
+    MX_HIP(launch_gs_solver(pl->vprec, pl->tiles_gs, pl->nt_gs, pl->probs, s, true, 0,
+                            pl->tiles_upd, pl->nt_upd));
   } else {
-    MX_HIP(launch_zpc(pl->vprec, pl->tiles_upd, pl->nt_upd, pl->probs, pc, 0, s));
-  }
-  MX_HIP(launch_fcg_dots(pl->vprec, pl->tiles_upd, pl->nt_upd, pl->probs, 0, s));
-  MX_HIP(launch_fin_beta(pl->probs, pl->P, init ? 1 : 0, 0, s));
-  if (pc == MXSEM_PC_LEARNED) {
-    MX_HIP(launch_zpc(pl->vprec, pl->tiles_upd, pl->nt_upd, pl->probs, MXSEM_PC_JACOBI, 1, s));
-    MX_HIP(launch_fcg_dots(pl->vprec, pl->tiles_upd, pl->nt_upd, pl->probs, 1, s));
-    MX_HIP(launch_fin_beta(pl->probs, pl->P, init ? 1 : 0, 1, s));
+    MX_HIP(launch_zpc(pl->vprec, pl->tiles_upd, pl->nt_upd, pl->probs, pc, s));
+    MX_HIP(launch_fcg_dots(pl->vprec, pl->tiles_upd, pl->nt_upd, pl->probs, s));
+    MX_HIP(launch_fin_beta(pl->probs, pl->P, init ? 1 : 0, s));
   }
   return MXSEM_OK;
 }

@@ -30,6 +30,8 @@ struct GsApi {
   int on_z;   // solver variant: sum z instead of w
   int nfin;   // solver variant: leading workgroups that finish sigma (0: none)
   int nprob;  // problems whose sigma they finish (the rest of the nfin do nothing)
+  const Tile* ztiles;  // solver variant on z: trailing workgroups forming the Jacobi z
+  int nz;
 };
 
 template <int NT>
@@ -57,9 +59,26 @@ __global__ void __launch_bounds__(GS_THREADS) gs_kernel(const Tile* __restrict__
       if ((int)blockIdx.x < api.nprob) fin_sigma_step(probs[blockIdx.x], sred);
       return;
     }
-    const Tile t = tiles[blockIdx.x - api.nfin];
+    const int tb = (int)blockIdx.x - api.nfin;
+    if (tb >= (int)gridDim.x - api.nfin - api.nz) {
+      // z = dinv r where the learned z of this step was rejected
+      const Tile t = api.ztiles[tb - ((int)gridDim.x - api.nfin - api.nz)];
+      const ProbDev& P = probs[t.prob];
+      const gptr<const State> st = gcast((const State*)P.st);
+      if (st->done || !st->fb_pending) return;
+      const gptr<const T> __restrict__ rr = gcast((const T*)P.r);
+      const gptr<const T> __restrict__ dinv = gcast((const T*)P.dinv);
+      gptr<T> __restrict__ z = gcast((T*)P.z);
+#pragma unroll
+      for (int q = 0; q < UPD_PER_THREAD; ++q) {
+        const int64_t i = (int64_t)t.first + q * UPD_THREADS + threadIdx.x;
+        if (i < P.nloc) z[i] = dinv[i] * rr[i];
+      }
+      return;
+    }
+    const Tile t = tiles[tb];
     const ProbDev& P = probs[t.prob];
-    if (gcast(P.st)->done) return;
+    if (gcast(P.st)->done || (api.nz && gcast(P.st)->fb_pending)) return;
     plan = &P.gs;
     v = gcast((T*)(api.on_z ? P.z : P.w));
     bucket = t.aux;
@@ -159,7 +178,6 @@ __global__ void __launch_bounds__(GS_THREADS) gs_kernel(const Tile* __restrict__
 }
 
 // ------------------------------------------------------------ vector pass
-__device__ inline double cweight(uint8_t m) { return m == 1 ? 1.0 : 1.0 / (double)m; }
 
 template <typename T>
 struct V4;
@@ -432,10 +450,10 @@ __global__ void fin_rho_kernel(const ProbDev* __restrict__ probs, int mode) {
 template <typename T>
 __global__ void __launch_bounds__(UPD_THREADS) zpc_kernel(const Tile* __restrict__ tiles,
                                                           const ProbDev* __restrict__ probs,
-                                                          int pc, int only_pending) {
+                                                          int pc) {
   const Tile t = tiles[blockIdx.x];
   const ProbDev& P = probs[t.prob];
-  if (gcast(P.st)->done || (only_pending && !gcast(P.st)->fb_pending)) return;
+  if (gcast(P.st)->done) return;
   const gptr<const T> __restrict__ r = gcast((const T*)P.r);
   const gptr<const T> __restrict__ dinv = gcast((const T*)P.dinv);
   gptr<T> __restrict__ z = gcast((T*)P.z);
@@ -449,12 +467,11 @@ __global__ void __launch_bounds__(UPD_THREADS) zpc_kernel(const Tile* __restrict
 // partials (r,z)_c -> part_u0 and (z,w)_c -> part_u2 (w = A p of this step)
 template <typename T, typename ACC>
 __global__ void __launch_bounds__(UPD_THREADS) fcg_dots_kernel(const Tile* __restrict__ tiles,
-                                                               const ProbDev* __restrict__ probs,
-                                                               int only_pending) {
+                                                               const ProbDev* __restrict__ probs) {
   __shared__ ACC sred[16];
   const Tile t = tiles[blockIdx.x];
   const ProbDev& P = probs[t.prob];
-  if (gcast(P.st)->done || (only_pending && !gcast(P.st)->fb_pending)) return;
+  if (gcast(P.st)->done) return;
   const gptr<const T> __restrict__ r = gcast((const T*)P.r);
   const gptr<const T> __restrict__ z = gcast((const T*)P.z);
   const gptr<const T> __restrict__ w = gcast((const T*)P.w);
@@ -477,27 +494,33 @@ __global__ void __launch_bounds__(UPD_THREADS) fcg_dots_kernel(const Tile* __res
   }
 }
 
-// beta = -(z, A p_old)_c / (p_old, A p_old)_c, rho = (r,z)_c.  A learned z
-// that is not a descent direction ((r,z)_c <= 0 or non-finite) is flagged
-// for replacement by Jacobi.  init: first z of a solve (beta = 0).
-// second: after the replacement (clears the flag, counts the fallback).
-__global__ void fin_beta_kernel(const ProbDev* __restrict__ probs, int init, int second) {
+// beta = -(z, A p_old)_c / (p_old, A p_old)_c, rho = (r,z)_c; init: first
+// z of a solve (beta = 0).  With dots (learned step), the learned z is
+// taken unless it is not a descent direction ((r,z)_c <= 0 or non-finite
+// dots), else the Jacobi candidate: fb_pending tells the following
+// assembly launch to write dinv r, and the fallback is counted.
+__global__ void fin_beta_kernel(const ProbDev* __restrict__ probs, int init,
+                                const double* __restrict__ dots, int ndots, int dstride) {
   __shared__ double sred[16];
   const ProbDev& P = probs[blockIdx.x];
   const gptr<State> st = gcast(P.st);
-  if (st->done || (second && !st->fb_pending)) return;
+  if (st->done) return;
+  if (dots) {
+    // learned step: the forward summed the dots of both candidates
+    double d[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) d[k] = fixed_sum<FIN_THREADS>(gcast(dots + k * dstride), ndots, sred);
+    if (threadIdx.x != 0) return;
+    const bool reject = !(d[0] > 0.0) || !isfinite(d[0]) || (!init && !isfinite(d[1]));
+    st->fb_pending = reject ? 1 : 0;
+    if (reject) st->fallback += 1;
+    st->rho = reject ? d[2] : d[0];
+    st->beta = init ? 0.0 : -(reject ? d[3] : d[1]) / st->sigma;
+    return;
+  }
   double rz = fixed_sum<FIN_THREADS>(gcast((const double*)P.part_u0), P.nblk_upd, sred);
   double zw = fixed_sum<FIN_THREADS>(gcast((const double*)P.part_u2), P.nblk_upd, sred);
   if (threadIdx.x != 0) return;
-  if (!second && st->pc == MXSEM_PC_LEARNED &&
-      (!(rz > 0.0) || !isfinite(rz) || (!init && !isfinite(zw)))) {
-    st->fb_pending = 1;
-    return;
-  }
-  if (second) {
-    st->fb_pending = 0;
-    st->fallback += 1;
-  }
   st->rho = rz;
   st->beta = init ? 0.0 : -zw / st->sigma;
 }
@@ -647,14 +670,17 @@ hipError_t launch_gs_apply(int prec_io, int prec_acc, void* v, const GsPlan& pla
 
 // vector precision: 0 FP64, 1 FP32 (FP64 accumulation), 3 FP32 (FP32 accumulation)
 hipError_t launch_gs_solver(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs,
-                            hipStream_t s, bool on_z, int sigma_probs) {
+                            hipStream_t s, bool on_z, int sigma_probs, const Tile* ztiles, int nz) {
+  static_assert(GS_THREADS == UPD_THREADS, "the Jacobi-z workgroups use the vector-pass tiles");
   const int nfin = ((sigma_probs + XCDS - 1) / XCDS) * XCDS;
-  if (ntiles + nfin == 0) return hipSuccess;
-  dim3 g(nfin + ntiles), b(GS_THREADS);
+  if (ntiles + nfin + nz == 0) return hipSuccess;
+  dim3 g(nfin + ntiles + nz), b(GS_THREADS);
   GsApi a{};
   a.on_z = on_z ? 1 : 0;
   a.nfin = nfin;
   a.nprob = sigma_probs;
+  a.ztiles = ztiles;
+  a.nz = ztiles ? nz : 0;
   if (vprec == 0)
     hipLaunchKernelGGL((gs_kernel<double, double, true>), g, b, 0, s, tiles, probs, a);
   else if (vprec == 1)
@@ -710,32 +736,34 @@ hipError_t launch_fin_rho(const ProbDev* probs, int nprob, int mode, hipStream_t
 }
 
 hipError_t launch_zpc(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs, int pc,
-                      int only_pending, hipStream_t s) {
+                      hipStream_t s) {
   if (vprec == 0)
     hipLaunchKernelGGL((zpc_kernel<double>), dim3(ntiles), dim3(UPD_THREADS), 0, s, tiles, probs,
-                       pc, only_pending);
+                       pc);
   else
     hipLaunchKernelGGL((zpc_kernel<float>), dim3(ntiles), dim3(UPD_THREADS), 0, s, tiles, probs,
-                       pc, only_pending);
+                       pc);
   return hipGetLastError();
 }
 
 hipError_t launch_fcg_dots(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs,
-                           int only_pending, hipStream_t s) {
+                           hipStream_t s) {
   if (vprec == 0)
     hipLaunchKernelGGL((fcg_dots_kernel<double, double>), dim3(ntiles), dim3(UPD_THREADS), 0, s,
-                       tiles, probs, only_pending);
+                       tiles, probs);
   else if (vprec == 1)
     hipLaunchKernelGGL((fcg_dots_kernel<float, double>), dim3(ntiles), dim3(UPD_THREADS), 0, s,
-                       tiles, probs, only_pending);
+                       tiles, probs);
   else
     hipLaunchKernelGGL((fcg_dots_kernel<float, float>), dim3(ntiles), dim3(UPD_THREADS), 0, s,
-                       tiles, probs, only_pending);
+                       tiles, probs);
   return hipGetLastError();
 }
 
-hipError_t launch_fin_beta(const ProbDev* probs, int nprob, int init, int second, hipStream_t s) {
-  hipLaunchKernelGGL(fin_beta_kernel, dim3(nprob), dim3(FIN_THREADS), 0, s, probs, init, second);
+hipError_t launch_fin_beta(const ProbDev* probs, int nprob, int init, hipStream_t s,
+                           const double* dots, int ndots, int dstride) {
+  hipLaunchKernelGGL(fin_beta_kernel, dim3(nprob), dim3(FIN_THREADS), 0, s, probs, init,
+                     dots, ndots, dstride);
   return hipGetLastError();
 }
 
