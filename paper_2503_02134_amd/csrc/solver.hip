@@ -115,14 +115,14 @@ static int plan_alloc(Plan* pl, void** p, size_t bytes) {
 // line of w holds entries of several groups, of several multiplicities),
 // and each XCD has its own L2: tiles that touch the same elements should
 // run on the same XCD, close together in time.  So the elements are cut
-// into XCDS contiguous chunks, each chunk into blocks of about 32K local
+// into XCDS contiguous chunks, each chunk into blocks of about 8K local
 // entries, and for every block the groups of every bucket whose first
 // copy lies in the block become tiles of that chunk's list, block by
 // block.  Tile.pad is the tile's group count (at most GS_CHUNK).
 static void gs_tiles_by_xcd(const mxsem_mesh* m, int p, std::vector<std::vector<Tile>>& lists) {
   const int nx = (int)lists.size();
   const int64_t n3 = m->n3;
-  const int eb = (int)std::max<int64_t>(1, 32768 / n3);
+  const int eb = (int)std::max<int64_t>(1, 8192 / n3);
   std::vector<size_t> cur(MAX_BUCKETS, 0);
   for (int e0 = 0; e0 < m->E; e0 += eb) {
     const int e1 = std::min(m->E, e0 + eb);
