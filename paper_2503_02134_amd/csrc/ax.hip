@@ -237,12 +237,227 @@ __global__ void __launch_bounds__(256) ax_kernel(const Tile* __restrict__ tiles,
   }
 }
 
+// Mapping with two columns per thread, for even n with n^2/2 <= 64 (N = 5,
+// 9; FP32 vectors): thread (i, jh) of an element owns the columns (i, jh) and
+// (i, jh + n/2), so an element takes n^2/2 lanes and never straddles two
+// wave64s (for N = 9, 50 lanes per wave; for N = 5, three elements of 18
+// lanes per wave).  Every slab exchange is then wave-local (wave barrier,
+// no workgroup barrier), where the one-column mapping (n^2 = 100 or 36
+// lanes per element) needs workgroup barriers.  Arithmetic and summation
+// order per output are those of ax_kernel.
+template <int N, typename T>
+constexpr bool two_col() {
+  return (N == 5 || N == 9) && sizeof(T) == 4;  // FP64 columns do not fit twice in registers
+}
+template <int N>
+constexpr int ax2_epw() {  // elements per wave
+  return 64 / ((N + 1) * ((N + 1) / 2));
+}
+
+template <int N, typename T, typename TG, bool SOLVER>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) ax2_kernel(const Tile* __restrict__ tiles, const ProbDev* __restrict__ probs,
+                           AxApplyArgs apply, int epb) {
+  constexpr int n = N + 1, n2 = n * n, n3 = n2 * n, hn = n / 2, TPE = n * hn, EPW = 64 / TPE;
+  static_assert(n % 2 == 0 && TPE <= 64, "two columns per thread need even n and n^2/2 <= 64");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sD = reinterpret_cast<T*>(smem_raw);
+  T* slab = sD + n2;
+  __shared__ double sred[16];
+
+  gptr<const T> __restrict__ Dg;
+  gptr<const TG> __restrict__ G;
+  gptr<const TG> __restrict__ hB;
+  gptr<const T> __restrict__ U;
+  gptr<T> __restrict__ Wout;
+  gptr<const T> __restrict__ Z = nullptr;
+  int E, first;
+  int64_t nloc_all;
+  const ProbDev* P = nullptr;
+  if constexpr (SOLVER) {
+    const Tile t = tiles[blockIdx.x];
+    P = &probs[t.prob];
+    if (gcast(P->st)->done) return;  // uniform across the workgroup
+    Dg = gcast((const T*)P->D);
+    G = gcast((const TG*)P->G);
+    hB = gcast((const TG*)P->hB);
+    U = gcast((const T*)P->p);
+    Wout = gcast((T*)P->w);
+    Z = gcast((const T*)P->z);
+    E = P->E;
+    nloc_all = P->nloc;
+    first = t.first;
+  } else {
+    Dg = gcast((const T*)apply.D);
+    G = gcast((const TG*)apply.G);
+    hB = gcast((const TG*)apply.hB);
+    U = gcast((const T*)apply.u);
+    Wout = gcast((T*)apply.w);
+    E = apply.E;
+    nloc_all = (int64_t)E * n3;
+    first = blockIdx.x * epb;
+  }
+
+  const int tid = threadIdx.x;
+  for (int q = tid; q < n2; q += blockDim.x) sD[q] = Dg[q];
+  const int wave = tid >> 6, lane = tid & 63;
+  const int slot = lane / TPE;  // == EPW for the lanes past the wave's last element
+  const int tl = lane - slot * TPE;
+  const int le = wave * EPW + slot;
+  const int i = tl % n, j0 = tl / n, j1 = j0 + hn;
+  const int e = first + le;
+  const bool active = slot < EPW && le < epb && e < E;
+  T* su = slab + (wave * EPW + (slot < EPW ? slot : 0)) * 3 * n2;  // touched by active lanes only
+  T* sr = su + n2;
+  T* ss = sr + n2;
+  __syncthreads();
+
+  T u0[n], u1[n], w0[n], w1[n], Di[n], DiT[n], Dj0[n], Dj1[n], Dj0T[n], Dj1T[n];
+#pragma unroll
+  for (int l = 0; l < n; ++l) {
+    Di[l] = sD[i * n + l];
+    DiT[l] = sD[l * n + i];
+    Dj0[l] = sD[j0 * n + l];
+    Dj1[l] = sD[j1 * n + l];
+    Dj0T[l] = sD[l * n + j0];
+    Dj1T[l] = sD[l * n + j1];
+    w0[l] = T(0);
+    w1[l] = T(0);
+  }
+  const int ij0 = j0 * n + i, ij1 = j1 * n + i;
+  const int64_t base0 = (int64_t)e * n3 + ij0, base1 = (int64_t)e * n3 + ij1;
+  if (active) {
+    if constexpr (SOLVER) {
+      const T beta = (T)gcast(P->st)->beta;
+      gptr<T> __restrict__ Pw = gcast((T*)P->p);
+#pragma unroll
+      for (int k = 0; k < n; ++k) {
+        const T p0 = Z[base0 + k * n2] + beta * U[base0 + k * n2];
+        const T p1 = Z[base1 + k * n2] + beta * U[base1 + k * n2];
+        Pw[base0 + k * n2] = p0;
+        Pw[base1 + k * n2] = p1;
+        u0[k] = p0;
+        u1[k] = p1;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < n; ++k) {
+        u0[k] = U[base0 + k * n2];
+        u1[k] = U[base1 + k * n2];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < n; ++k) u0[k] = u1[k] = T(0);
+  }
+
+  const int64_t g0n = (int64_t)(active ? e : 0) * n3 + ij0;
+  const int64_t g1n = (int64_t)(active ? e : 0) * n3 + ij1;
+  // G of the next k slab in flight while this one is used (registers for
+  // the whole column pair do not fit next to the two columns' u, w and D
+  // rows; one slab ahead keeps the kernel at three waves per SIMD, which
+  // measured 10% faster than two slabs at two waves)
+  constexpr int LA = 1;
+  T gbuf[n][12];
+#pragma unroll
+  for (int k = 0; k < LA && k < n; ++k) {
+    load_g<T, TG>(G, nloc_all, g0n + k * n2, n3, gbuf[k]);
+    load_g<T, TG>(G, nloc_all, g1n + k * n2, n3, gbuf[k] + 6);
+  }
+#pragma unroll
+  for (int k = 0; k < n; ++k) {
+    if (k + LA < n) {
+      load_g<T, TG>(G, nloc_all, g0n + (k + LA) * n2, n3, gbuf[k + LA]);
+      load_g<T, TG>(G, nloc_all, g1n + (k + LA) * n2, n3, gbuf[k + LA] + 6);
+    }
+    if (active) {
+      su[ij0] = u0[k];
+      su[ij1] = u1[k];
+    }
+    elem_sync<1>();
+    if (active) {
+      T ur0 = T(0), us0 = T(0), ut0 = T(0), ur1 = T(0), us1 = T(0), ut1 = T(0);
+#pragma unroll
+      for (int l = 0; l < n; ++l) {
+        const T scol = su[l * n + i];
+        ur0 += Di[l] * su[j0 * n + l];
+        us0 += Dj0[l] * scol;
+        ut0 += sD[k * n + l] * u0[l];
+        ur1 += Di[l] * su[j1 * n + l];
+        us1 += Dj1[l] * scol;
+        ut1 += sD[k * n + l] * u1[l];
+      }
+      const T* ga = gbuf[k];
+      const T* gb = gbuf[k] + 6;
+      const T wr0 = ga[0] * ur0 + ga[1] * us0 + ga[2] * ut0;
+      const T ws0 = ga[1] * ur0 + ga[3] * us0 + ga[4] * ut0;
+      const T wt0 = ga[2] * ur0 + ga[4] * us0 + ga[5] * ut0;
+      const T wr1 = gb[0] * ur1 + gb[1] * us1 + gb[2] * ut1;
+      const T ws1 = gb[1] * ur1 + gb[3] * us1 + gb[4] * ut1;
+      const T wt1 = gb[2] * ur1 + gb[4] * us1 + gb[5] * ut1;
+#pragma unroll
+      for (int m = 0; m < n; ++m) {
+        w0[m] += sD[k * n + m] * wt0;
+        w1[m] += sD[k * n + m] * wt1;
+      }
+      sr[ij0] = wr0;
+      ss[ij0] = ws0;
+      sr[ij1] = wr1;
+      ss[ij1] = ws1;
+    }
+    elem_sync<1>();
+    if (active) {
+      T acc0 = T(0), acc1 = T(0);
+#pragma unroll
+      for (int l = 0; l < n; ++l) {
+        const T rcol = sr[j0 * n + l], rcol1 = sr[j1 * n + l];
+        acc0 += DiT[l] * rcol + Dj0T[l] * ss[l * n + i];
+        acc1 += DiT[l] * rcol1 + Dj1T[l] * ss[l * n + i];
+      }
+      w0[k] += acc0;
+      w1[k] += acc1;
+    }
+    elem_sync<1>();
+  }
+
+  double dot = 0.0;
+  if (active) {
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+      T wv0 = w0[k], wv1 = w1[k];
+      if (hB) {
+        wv0 += cvt<T>(__builtin_nontemporal_load(&hB[base0 + k * n2])) * u0[k];
+        wv1 += cvt<T>(__builtin_nontemporal_load(&hB[base1 + k * n2])) * u1[k];
+      }
+      Wout[base0 + k * n2] = wv0;
+      Wout[base1 + k * n2] = wv1;
+      if constexpr (SOLVER) dot += (double)u0[k] * (double)wv0 + (double)u1[k] * (double)wv1;
+    }
+  }
+  if constexpr (SOLVER) {
+    double s = block_sum(dot, sred);
+    if (tid == 0) gcast(P->part_ax)[first / epb] = s;
+  }
+}
+
 // With ev0/ev1 the launch records its own start and end (hipExtLaunchKernel),
 // so the elapsed time between them is the kernel's execution time.
 template <int N, typename T, typename TG, bool SOLVER>
 static hipError_t launch_one(const Tile* tiles, const ProbDev* probs, const AxApplyArgs& a,
                              int ntiles, int epb, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   constexpr int n = N + 1, n2 = n * n;
+  if constexpr (two_col<N, T>()) {
+    constexpr int EPW = ax2_epw<N>();
+    const int waves = (epb + EPW - 1) / EPW;
+    if (epb < 1 || waves > 4) return hipErrorInvalidConfiguration;
+    const size_t shm = sizeof(T) * (n2 + (size_t)waves * EPW * 3 * n2);
+    if (ev0)
+      hipExtLaunchKernelGGL((ax2_kernel<N, T, TG, SOLVER>), dim3(ntiles), dim3(64 * waves),
+                            (uint32_t)shm, s, ev0, ev1, 0, tiles, probs, a, epb);
+    else
+      hipLaunchKernelGGL((ax2_kernel<N, T, TG, SOLVER>), dim3(ntiles), dim3(64 * waves), shm, s,
+                         tiles, probs, a, epb);
+    return hipGetLastError();
+  }
   int threads = ((epb * n2 + 63) / 64) * 64;
   if (epb < 1 || threads > 256) return hipErrorInvalidConfiguration;
   size_t shm = sizeof(T) * (n2 + (size_t)epb * 3 * n2);
@@ -295,7 +510,16 @@ hipError_t launch_ax_solver(int prec, int N, const Tile* tiles, int ntiles, cons
   }
 }
 
-// largest epb whose workgroup (rounded to wave64s) fits 256 threads
+// elements per wave of the two-column mapping (FP32 vectors; 0: N uses the
+// one-column mapping only).  Tiles of that many elements suit both mappings.
+int ax_wave_elements(int N) {
+  if (N == 5) return ax2_epw<5>();
+  if (N == 9) return ax2_epw<9>();
+  return 0;
+}
+
+// largest epb whose one-column workgroup (rounded to wave64s) fits 256
+// threads (the two-column mapping takes any such tile)
 int max_epb(int N) {
   const int n2 = (N + 1) * (N + 1);
   int e = 1;

@@ -100,9 +100,11 @@ int mesh_alloc(mxsem_mesh* m, void** p, size_t bytes) {
 }
 
 // Elements per workgroup of the operator kernel (workgroups of at most 256
-// threads, rounded up to whole wave64s): the smallest count whose idle
-// lanes are under 5%, else the count with the fewest idle lanes.
+// threads, rounded up to whole wave64s): one wave's worth for the
+// two-column mapping, else the smallest count whose idle lanes are under 5%,
+// else the count with the fewest idle lanes.
 int default_epb(int N) {
+  if (ax_wave_elements(N) > 0) return ax_wave_elements(N);  // one wave per workgroup
   const int n2 = (N + 1) * (N + 1);
   int best = 1;
   double bestw = 1.0;

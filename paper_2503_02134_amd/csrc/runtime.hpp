@@ -23,6 +23,7 @@ hipError_t launch_ax_solver(int prec, int N, const Tile* tiles, int ntiles, cons
                             int epb, hipStream_t s, hipEvent_t ev0 = nullptr,
                             hipEvent_t ev1 = nullptr);
 int max_epb(int N);
+int ax_wave_elements(int N);
 hipError_t launch_gs_apply(int prec_io, int prec_acc, void* v, const GsPlan& plan, bool mask,
                            hipStream_t s);
 // sigma_probs > 0: the launch also finishes sigma and alpha of problems
