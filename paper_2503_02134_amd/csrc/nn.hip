@@ -74,6 +74,7 @@ __global__ void __launch_bounds__(NN_THREADS)
   const int e = blockIdx.x;
   if (e >= E || (st && st->done)) return;
   const int64_t base = (int64_t)e * n3;
+  const float alpha = dd.x ? (float)st->alpha : 0.f;
   float rv[PPT], dv[PPT];
   float ss = 0.f;
 #pragma unroll
@@ -82,6 +83,11 @@ __global__ void __launch_bounds__(NN_THREADS)
     rv[q] = dv[q] = 0.f;
     if (p < n3) {
       rv[q] = r[base + p];
+      if (dd.x) {  // the step's vector update (uniform branch)
+        rv[q] = rv[q] - alpha * dd.w[base + p];
+        const_cast<float*>(r)[base + p] = rv[q];
+        dd.x[base + p] = dd.x[base + p] + alpha * dd.p[base + p];
+      }
       dv[q] = dinv[base + p] * rv[q];
       ss += dv[q] * dv[q];
     }
@@ -125,7 +131,7 @@ __global__ void __launch_bounds__(NN_THREADS)
     for (int o = 0; o < 27; ++o) T[p * 27 + o] = t[o];
   }
   __syncthreads();
-  double dsum[4] = {0.0, 0.0, 0.0, 0.0};
+  double dsum[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     const int p = threadIdx.x + q * NN_THREADS;
@@ -142,17 +148,18 @@ __global__ void __launch_bounds__(NN_THREADS)
     const float zv = m == 1 ? zl : zl / (float)m;
     zc[base + p] = zv;
     if (dd.dots) {
-      const double wq = (double)dd.w[base + p], cj = cweight(m) * (double)dv[q];
+      const double wq = (double)dd.w[base + p], c = cweight(m), cj = c * (double)dv[q];
       dsum[0] += (double)rv[q] * (double)zv;
       dsum[1] += wq * (double)zv;
       dsum[2] += (double)rv[q] * cj;
       dsum[3] += wq * cj;
+      dsum[4] += (double)rv[q] * c * (double)rv[q];
     }
   }
   if (dd.dots) {
     __shared__ double dred[16];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < 5; ++k) {
       const double a = block_sum(dsum[k], dred);
       if (threadIdx.x == 0) dd.dots[k * dd.dstride + e] = a;
     }
@@ -332,9 +339,15 @@ __global__ void __launch_bounds__(NN_THREADS, 2)
   // The next element's r and dinv are loaded while this one is on the matrix
   // cores; its per-wave partial of ||dinv r||^2 goes to the other half of
   // sred2, so one barrier per element serves both the norm and the reuse of U.
-  // w for the dots, loaded with r and dinv one element ahead (r stands in
-  // when no dots are asked for, so the loop has no branch)
+  // w for the dots and the update, loaded with r and dinv one element ahead
+  // (r stands in when no dots are asked for, so the loop has no branch);
+  // with the update, r is updated as it is loaded (r - alpha w) and x, p
+  // of the element in hand are loaded with its multiplicities
   const float* __restrict__ wsrc = dd.dots ? dd.w : r;
+  const bool upd = dd.x != nullptr;
+  const float alpha = upd ? (float)st->alpha : 0.f;
+  const float* __restrict__ xsrc = upd ? dd.x : r;
+  const float* __restrict__ psrc = upd ? dd.p : r;
   float rv[2] = {0.f, 0.f}, dv[2] = {0.f, 0.f}, wv[2] = {0.f, 0.f};
   auto partial = [&](int slot) {
     float ss = dv[0] * dv[0] + dv[1] * dv[1];
@@ -345,13 +358,14 @@ __global__ void __launch_bounds__(NN_THREADS, 2)
     const int64_t base = (int64_t)blockIdx.x * n3;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      rv[q] = r[base + tid + q * NN_THREADS];
-      dv[q] = dinv[base + tid + q * NN_THREADS] * rv[q];
+      const float r0 = r[base + tid + q * NN_THREADS];
       wv[q] = wsrc[base + tid + q * NN_THREADS];
+      rv[q] = upd ? r0 - alpha * wv[q] : r0;
+      dv[q] = dinv[base + tid + q * NN_THREADS] * rv[q];
     }
     partial(0);
   }
-  double dsum[4] = {0.0, 0.0, 0.0, 0.0};  // this workgroup's share of the dots
+  double dsum[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // this workgroup's share of the dots
   int it = 0;
   for (int e = blockIdx.x; e < E; e += gridDim.x, ++it) {
     const int64_t base = (int64_t)e * n3;
@@ -380,8 +394,13 @@ __global__ void __launch_bounds__(NN_THREADS, 2)
       }
     }
     uint8_t mv[2];
+    float xo[2], po[2];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) mv[q] = mult[base + tid + q * NN_THREADS];
+    for (int q = 0; q < 2; ++q) {
+      mv[q] = mult[base + tid + q * NN_THREADS];
+      xo[q] = xsrc[base + tid + q * NN_THREADS];
+      po[q] = psrc[base + tid + q * NN_THREADS];
+    }
 #pragma unroll
     for (int mp = 0; mp < 4; mp += 2) {
       floatx16_t acc[2] = {{0}, {0}};
@@ -443,19 +462,24 @@ __global__ void __launch_bounds__(NN_THREADS, 2)
       dsum[1] += (double)wv[q] * (double)zv;
       dsum[2] += (double)rv[q] * cj;
       dsum[3] += (double)wv[q] * cj;
+      dsum[4] += (double)rv[q] * (double)cq * (double)rv[q];
+      if (upd) {
+        const_cast<float*>(r)[base + p] = rv[q];
+        dd.x[base + p] = xo[q] + alpha * po[q];
+      }
     }
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      rv[q] = rn[q];
-      dv[q] = dn[q] * rn[q];
       wv[q] = wn[q];
+      rv[q] = upd ? rn[q] - alpha * wn[q] : rn[q];
+      dv[q] = dn[q] * rv[q];
     }
     partial((it + 1) & 1);
   }
   if (dd.dots) {
     __shared__ double dred[16];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < 5; ++k) {
       const double a = block_sum(dsum[k], dred);
       if (tid == 0) dd.dots[k * dd.dstride + blockIdx.x] = a;
     }
@@ -763,7 +787,7 @@ struct mxsem_nn {
   void* packed = nullptr; // [6][64] BF16x8 weight operands of the matrix-core forward
   float *z = nullptr, *d = nullptr, *Ad = nullptr, *g = nullptr;
   double* nd = nullptr;   // [2 * max samples] numerators / denominators
-  double* dots = nullptr; // [4][dstride] per-workgroup flexible-CG dot partials of the forward
+  double* dots = nullptr; // [5][dstride] per-workgroup flexible-CG dot partials of the forward
   int dstride = 0;
   int nd_cap = 0;
   int nbwd = 0;
@@ -786,9 +810,14 @@ static inline unsigned nb256(int64_t n) { return (unsigned)((n + 255) / 256); }
 // with w, also the partials of (r, z)_c and (z, w)_c: nn->dots, *nparts
 // per dot, nn->dstride apart
 int nn_launch_fwd(mxsem_nn* nn, const float* r, float* zc, hipStream_t s, const State* st,
-                  const float* w, int* nparts, const double** dots, int* dstride) {
+                  const float* w, int* nparts, const double** dots, int* dstride, float* x,
+                  const float* p) {
+  if (x && !(w && p && st)) {
+    set_error("nn forward: the fused vector update needs w, p and the state");
+    return MXSEM_EINVAL;
+  }
   mxsem_mesh* m = nn->mesh;
-  NnDots dd{w, w ? nn->dots : nullptr, nn->dstride};
+  NnDots dd{w, w ? nn->dots : nullptr, nn->dstride, x, p};
   MX_HIP(launch_nn_fwd(m->N, r, m->dinv32, m->mult, nn->Wq, nn->Wq + NN_W1, zc, m->E, s, st,
                        nn->packed, dd, nparts));
   if (dots) *dots = nn->dots;
@@ -799,7 +828,7 @@ int nn_launch_fwd(mxsem_nn* nn, const float* r, float* zc, hipStream_t s, const 
 int nn_forward_into(mxsem_nn* nn, const float* r, float* out, hipStream_t s) {
   mxsem_mesh* m = nn->mesh;
   MX_HIP(launch_nn_fwd(m->N, r, m->dinv32, m->mult, nn->Wq, nn->Wq + NN_W1, out, m->E, s,
-                       nullptr, nn->packed, NnDots{nullptr, nullptr, 0}, nullptr));
+                       nullptr, nn->packed, NnDots{nullptr, nullptr, 0, nullptr, nullptr}, nullptr));
   MX_HIP(launch_gs_apply(MXSEM_F32, MXSEM_F64, out, m->plan, true, s));
   return MXSEM_OK;
 }
@@ -832,7 +861,7 @@ int mxsem_nn_create(mxsem_mesh* m, const mxsem_nn_desc* d, mxsem_nn** out) {
   A((void**)&nn->ve, sizeof(float) * NN_NP);
   A((void**)&nn->part, sizeof(float) * NN_NP * nn->nbwd);
   nn->dstride = std::max(m->E, 4096);  // at least every forward grid's workgroup count
-  A((void**)&nn->dots, sizeof(double) * 4 * nn->dstride);
+  A((void**)&nn->dots, sizeof(double) * 5 * nn->dstride);
   A((void**)&nn->packed, 16 * 6 * 64);
   A((void**)&nn->z, sizeof(float) * nl);
   A((void**)&nn->d, sizeof(float) * nl);

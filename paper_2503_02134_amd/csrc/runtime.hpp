@@ -50,14 +50,18 @@ hipError_t launch_fin_beta(const ProbDev* probs, int nprob, int init, hipStream_
 //   (r, z)_c = sum_i r_i zc_i,   (z, w)_c = sum_i w_i zc_i
 // over all local entries (equal up to rounding to the dots of the assembled
 // z).  The same pass gives the dots of the Jacobi candidate z_J = dinv r
-// (continuous already): sum_i r_i c_i z_J,i and sum_i w_i c_i z_J,i.  Each
-// workgroup of the forward writes its four partials to
-// dots[k * dstride + blockIdx.x], k = 0..3 in that order; dots == nullptr
-// skips them.
+// (continuous already), sum_i r_i c_i z_J,i and sum_i w_i c_i z_J,i, and
+// (r,r)_c.  Each workgroup of the forward writes its five partials to
+// dots[k * dstride + blockIdx.x], k = 0..4 in that order; dots == nullptr
+// skips them.  With x (and p), the forward first applies the step's vector
+// update to each element it reads, r -= alpha w and x += alpha p (alpha from
+// the state), writes r and x back, and works on the updated r.
 struct NnDots {
   const float* w;
   double* dots;
   int dstride;
+  float* x;
+  const float* p;
 };
 // nparts (optional): workgroups of the launch, i.e. partials per dot
 hipError_t launch_nn_fwd(int N, const float* r, const float* dinv, const uint8_t* mult,
@@ -199,9 +203,9 @@ const void* hB_ptr(const mxsem_mesh* m, int gprec);
 int apply_impl(mxsem_mesh* m, int prec, const void* u, void* w, unsigned flags, hipStream_t s);
 // learned preconditioner: forward of an attached network into zc (before
 // the gather-scatter); the kernel returns at once when st->done.  With w
-// (= A p of the step), also the partials of (r,z)_c and (z,w)_c: *dots,
-// *nparts per dot, *dstride apart.
+// (= A p of the step), also the dot partials of NnDots: *dots, *nparts per
+// dot, *dstride apart; with x and p, the step's vector update as well.
 int nn_launch_fwd(mxsem_nn* nn, const float* r, float* zc, hipStream_t s, const State* st,
                   const float* w = nullptr, int* nparts = nullptr, const double** dots = nullptr,
-                  int* dstride = nullptr);
+                  int* dstride = nullptr, float* x = nullptr, const float* p = nullptr);
 }  // namespace mx

@@ -391,15 +391,19 @@ static int run_inner(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K, Inner& 
 // beta.  A rejected learned z is replaced by Jacobi within the same step.
 static int enqueue_fcg_z(Plan* pl, int pc, hipStream_t s, bool init) {
   if (pc == MXSEM_PC_LEARNED) {
-    // The forward also sums the step's dots, for the learned z (from c z_L)
-    // and for the Jacobi candidate dinv r, so beta and the choice between
-    // them come before the assembly; one launch then assembles the learned
-    // z or, where it was rejected, writes dinv r.
+    // One forward launch applies the step's vector update (x += alpha p,
+    // r -= alpha w; not at the start of a solve) and sums (r,r)_c and the
+    // step's dots, for the learned z (from c z_L) and for the Jacobi
+    // candidate dinv r; the end-of-step tests, beta and the choice between
+    // the candidates then come before the assembly, and one launch
+    // assembles the learned z or, where it was rejected, writes dinv r.
     mxsem_mesh* m = pl->meshes[0];
+    const SolverBufs* b = pl->bufs[0];
     int nparts = 0, dstride = 0;
     const double* dots = nullptr;
-    MX_TRY(nn_launch_fwd(m->nn, (const float*)pl->bufs[0]->r, (float*)pl->bufs[0]->z, s,
-                         pl->hprob[0].st, (const float*)pl->bufs[0]->w, &nparts, &dots, &dstride));
+    MX_TRY(nn_launch_fwd(m->nn, (const float*)b->r, (float*)b->z, s, pl->hprob[0].st,
+                         (const float*)b->w, &nparts, &dots, &dstride,
+                         init ? nullptr : (float*)b->x, init ? nullptr : (const float*)b->p));
     MX_HIP(launch_fin_beta(pl->probs, pl->P, init ? 1 : 0, s, dots, nparts, dstride));
     MX_HIP(launch_gs_solver(pl->vprec, pl->tiles_gs, pl->nt_gs, pl->probs, s, true, 0,
                             pl->tiles_upd, pl->nt_upd));
@@ -427,8 +431,10 @@ static int get_graph_fcg(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K) {
     if (k > 0) rc = enqueue_ax(pl, gprec, cs, false);
     if (rc != MXSEM_OK) break;
     hipError_t e = launch_gs_solver(pl->vprec, pl->tiles_gs, pl->nt_gs, pl->probs, cs, false, pl->P);
-    if (e == hipSuccess) e = launch_update(pl->vprec, -1, pl->tiles_upd, pl->nt_upd, pl->probs, cs);
-    if (e == hipSuccess) e = launch_fin_rho(pl->probs, pl->P, 2, cs);
+    if (pc != MXSEM_PC_LEARNED) {  // the learned forward does the update and the tests itself
+      if (e == hipSuccess) e = launch_update(pl->vprec, -1, pl->tiles_upd, pl->nt_upd, pl->probs, cs);
+      if (e == hipSuccess) e = launch_fin_rho(pl->probs, pl->P, 2, cs);
+    }
     if (e != hipSuccess) {
       set_error(std::string("flexible CG capture: ") + hipGetErrorString(e));
       rc = MXSEM_EHIP;

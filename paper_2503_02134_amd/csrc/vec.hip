@@ -386,6 +386,37 @@ __device__ inline void fin_sigma_step(const ProbDev& P, double* sred) {
 // stagnation tests, then beta = rho'/rho.  mode 1: start of a PCG solve.
 // mode 2 (flexible CG step): the tests only (beta comes later).  mode 3:
 // start of a flexible CG solve (rho comes later).
+// End-of-step tests on the recursive residual rr = (r,r)_c: iteration
+// count, convergence, non-finite residual, iteration limit, stagnation.
+// Returns false when the problem is done (reason set).
+__device__ inline bool step_test(const gptr<State> st, double rr) {
+  st->rr = rr;
+  const int it = st->iter + 1;
+  st->iter = it;
+  const double res = sqrt(rr / st->bb);
+  st->res = res;
+  if (st->history) gcast(st->history)[it] = res;
+  int reason = 0;
+  if (rr <= st->tol2 * st->bb)
+    reason = MXSEM_CONVERGED;
+  else if (!isfinite(rr))
+    reason = MXSEM_BREAKDOWN;
+  else if (it >= st->maxit)
+    reason = MXSEM_MAX_ITER;
+  else if (res < 0.9 * st->best) {
+    st->best = res;
+    st->since = 0;
+  } else if (++st->since >= STAG_WINDOW) {
+    reason = MXSEM_STAGNATED;
+  }
+  if (reason) {
+    st->done = 1;
+    st->reason = reason;
+    return false;
+  }
+  return true;
+}
+
 __global__ void fin_rho_kernel(const ProbDev* __restrict__ probs, int mode) {
   __shared__ double sred[16];
   const ProbDev& P = probs[blockIdx.x];
@@ -410,34 +441,7 @@ __global__ void fin_rho_kernel(const ProbDev* __restrict__ probs, int mode) {
     }
     return;
   }
-  const int it = st->iter + 1;
-  st->iter = it;
-  const double res = sqrt(rr / st->bb);
-  st->res = res;
-  if (st->history) gcast(st->history)[it] = res;
-  if (rr <= st->tol2 * st->bb) {
-    st->done = 1;
-    st->reason = MXSEM_CONVERGED;
-    return;
-  }
-  if (!isfinite(rr)) {
-    st->done = 1;
-    st->reason = MXSEM_BREAKDOWN;
-    return;
-  }
-  if (it >= st->maxit) {
-    st->done = 1;
-    st->reason = MXSEM_MAX_ITER;
-    return;
-  }
-  if (res < 0.9 * st->best) {
-    st->best = res;
-    st->since = 0;
-  } else if (++st->since >= STAG_WINDOW) {
-    st->done = 1;
-    st->reason = MXSEM_STAGNATED;
-    return;
-  }
+  if (!step_test(st, rr)) return;
   if (mode == 0) {
     st->beta = rz / st->rho;
     st->rho = rz;
@@ -495,10 +499,11 @@ __global__ void __launch_bounds__(UPD_THREADS) fcg_dots_kernel(const Tile* __res
 }
 
 // beta = -(z, A p_old)_c / (p_old, A p_old)_c, rho = (r,z)_c; init: first
-// z of a solve (beta = 0).  With dots (learned step), the learned z is
-// taken unless it is not a descent direction ((r,z)_c <= 0 or non-finite
-// dots), else the Jacobi candidate: fb_pending tells the following
-// assembly launch to write dinv r, and the fallback is counted.
+// z of a solve (beta = 0).  With dots (learned step), first the end-of-step
+// tests on (r,r)_c (not at init), then the learned z is taken unless it is
+// not a descent direction ((r,z)_c <= 0 or non-finite dots), else the
+// Jacobi candidate: fb_pending tells the following assembly launch to write
+// dinv r, and the fallback is counted.
 __global__ void fin_beta_kernel(const ProbDev* __restrict__ probs, int init,
                                 const double* __restrict__ dots, int ndots, int dstride) {
   __shared__ double sred[16];
@@ -506,11 +511,13 @@ __global__ void fin_beta_kernel(const ProbDev* __restrict__ probs, int init,
   const gptr<State> st = gcast(P.st);
   if (st->done) return;
   if (dots) {
-    // learned step: the forward summed the dots of both candidates
-    double d[4];
+    // learned step: the forward summed the dots of both candidates and,
+    // past the first step, (r,r)_c of the updated residual
+    double d[5];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) d[k] = fixed_sum<FIN_THREADS>(gcast(dots + k * dstride), ndots, sred);
+    for (int k = 0; k < 5; ++k) d[k] = fixed_sum<FIN_THREADS>(gcast(dots + k * dstride), ndots, sred);
     if (threadIdx.x != 0) return;
+    if (!init && !step_test(st, d[4])) return;
     const bool reject = !(d[0] > 0.0) || !isfinite(d[0]) || (!init && !isfinite(d[1]));
     st->fb_pending = reject ? 1 : 0;
     if (reject) st->fallback += 1;
