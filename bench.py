@@ -113,6 +113,7 @@ def main():
             f"res={st.rel_res:.2e} {st.ms:.1f} ms ax={st.ax_ms * 1e3:.1f} us")
     value = nloc * iters / elapsed / 1e9
     x_mixed = x.clone()
+    copy_gbs = copy_ceiling(nloc * 20)
 
     # dominant kernel: fused operator kernel of the inner loop
     tot = sum(s for _, s in ax_ms)
@@ -180,6 +181,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "ax_kernel (fused p-update + local operator)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "copy_ceiling_gbs": copy_gbs,
                      "traffic": ax_traffic_from_profile(mode) if wl.name == "box32_N7_deformed"
                      else None,
                      "bytes_per_launch": traffic_bytes, "avg_launch_us": round(ax_avg_ms * 1e3, 2),
@@ -193,6 +195,29 @@ def main():
     print(json.dumps(out), flush=True)
     mesh.close()
     ctx.close()
+
+
+def copy_ceiling(nbytes):
+    """Read + write bandwidth of a plain device-to-device copy of nbytes
+    (torch's copy kernel), the same 2 x nbytes of traffic as one operator
+    launch when nbytes = 20 B per local dof: a measured ceiling to set beside
+    the operator kernel's achieved bandwidth."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del src, dst
+    return round(2 * nbytes / sec / 1e9, 1)
 
 
 def traffic_probe(mesh, b, mode):
