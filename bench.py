@@ -6,10 +6,14 @@ Jacobi-PCG with FP64 gather-scatter sums and dots, FP64 residuals in the
 refinement loop).  value = local dofs x (inner + outer iterations) per
 second over the timed steps.  Inputs are resident in HBM before timing.
 
-Beside it: the FP64 solve on the same GPU, time-to-1e-8 for both, the
-roofline of the dominant kernel (the fused operator kernel of the inner
-loop, timed with HIP events around its graph node on the solve's stream),
-and the FP64 CPU oracle timed on a bounded sample of the same workload.
+Beside it: the FP64 solve on the same GPU, the same refinement with BF16
+geometric factors, time-to-1e-8, the roofline of the dominant kernel (the
+fused operator kernel of the inner loop: the first operator launch of every
+graph chunk records its own start and end events on the solve's stream),
+a measured copy-kernel ceiling, and the FP64 CPU oracle timed on a bounded
+sample of the same workload.  Other workloads: --workload batch64 (64
+uneven problems) and --workload box24_N7_lognormal_helmholtz --mode learned
+(the learned preconditioner against Jacobi PCG and FP64 PCG).
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
