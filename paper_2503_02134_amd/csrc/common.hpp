@@ -171,7 +171,7 @@ struct ProbDev {
 };
 
 constexpr int GS_THREADS = 256;  // gather-scatter workgroup
-constexpr int GS_PER_THREAD = 4;
+constexpr int GS_PER_THREAD = 2;
 constexpr int GS_CHUNK = GS_THREADS * GS_PER_THREAD;  // items per workgroup
 constexpr int UPD_THREADS = 256; // threads per vector-update workgroup
 constexpr int UPD_PER_THREAD = 8;  // entries per thread (two 4-wide vectors)
