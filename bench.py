@@ -12,8 +12,10 @@ fused operator kernel of the inner loop: the first operator launch of every
 graph chunk records its own start and end events on the solve's stream),
 a measured copy-kernel ceiling, and the FP64 CPU oracle timed on a bounded
 sample of the same workload.  Other workloads: --workload batch64 (64
-uneven problems) and --workload box24_N7_lognormal_helmholtz --mode learned
-(the learned preconditioner against Jacobi PCG and FP64 PCG).
+uneven problems), --workload box24_N7_lognormal_helmholtz --mode learned
+(the learned preconditioner against Jacobi PCG and FP64 PCG) and --workload
+box20_N7 --mode strategies (the mixed-precision strategy table: gather-scatter
+sums, dot accumulation and gather-scatter order).
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -42,9 +44,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="box32_N7_deformed",
                     help="box4_N7 | box16_N9_deformed | box32_N7_deformed | "
-                         "box24_N7_lognormal_helmholtz | batch64")
+                         "box24_N7_lognormal_helmholtz | box20_N7 | batch64")
     ap.add_argument("--mode", default="mixed_ir", choices=["mixed_ir", "mixed_ir_bf16g", "fp64",
-                                                           "mixed", "learned"])
+                                                           "mixed", "learned", "strategies"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=200)
     ap.add_argument("--traffic-probe", action="store_true",
@@ -68,6 +70,8 @@ def main():
         return bench_batch(args)
     if args.mode == "learned":
         return bench_learned(args)
+    if args.mode == "strategies":
+        return bench_strategies(args)
     wl = W.WORKLOADS[args.workload]
     modes = {"mixed_ir": mx.MODE_MIXED_IR, "mixed_ir_bf16g": mx.MODE_MIXED_IR_BF16G,
              "fp64": mx.MODE_FP64, "mixed": mx.MODE_MIXED}
@@ -437,6 +441,81 @@ def bench_learned(args):
     }
     print(json.dumps(out), flush=True)
     net.close()
+    mesh.close()
+    ctx.close()
+
+
+def bench_strategies(args):
+    """The mixed-precision strategies of Sec. 4.2.1-4.2.2 on one GPU: the
+    FP32 CG loop with the gather-scatter sums in FP32 or FP64, the dots in
+    FP32, FP64 or compensated FP32 (Dot2), and the gather-scatter in one
+    order per node or in each copy's own order (the summation order of a
+    pairwise exchange between ranks, one copy per rank), with the identity
+    and the Jacobi preconditioner, to the workload's recursive tolerance;
+    FP64 CG beside.  value: local dofs x iterations / s over every solve of
+    the table (the solves differ in cost only by their reductions)."""
+    import torch
+
+    from paper_2503_02134_amd import mxsem as mx
+    from paper_2503_02134_amd import workloads as W
+    wl = W.WORKLOADS[args.workload]
+    ctx = mx.Context(0)
+    xi, _ = mx.mxsem_gll(wl.N)
+    bm = W.box_mesh(wl.ne, wl.N, xi, seed=wl.deform_seed)
+    f, _ = W.manufactured(bm)
+    mesh = mx.Mesh(ctx, bm.E, wl.N, bm.xyz, bm.glo, bm.bnd)
+    nloc = mesh.nloc
+    b = mesh.mass_rhs(torch.as_tensor(f, device="cuda"))
+    log(f"strategies on {wl.name}: E={bm.E} N={wl.N} nloc={nloc} tol={wl.tol}")
+    pcs = (("identity", mx.PC_IDENTITY), ("jacobi", mx.PC_JACOBI))
+    ref = {}
+    rows = []
+    its = 0
+    el = 0.0
+    for pname, pc in pcs:
+        x64 = torch.zeros_like(b)
+        mesh.solve(b, x64, mode=mx.MODE_FP64, pc=pc, tol=wl.tol, max_iter=wl.maxit)  # warm-up
+        x64.zero_()
+        _, s6 = mesh.solve(b, x64, mode=mx.MODE_FP64, pc=pc, tol=wl.tol, max_iter=wl.maxit)
+        ref[pname] = x64
+        rows.append({"pc": pname, "loop": "fp64", "gs_sums": "fp64", "dot": "fp64",
+                     "order": "one", "reason": s6.reason, "iterations": s6.iterations,
+                     "rec_res": s6.rel_res_recursive, "true_res": s6.rel_res,
+                     "rel_diff_vs_fp64": 0.0, "ms": round(s6.ms, 2)})
+        its += s6.iterations
+        el += s6.ms
+        for gname, mode in (("fp64", mx.MODE_MIXED), ("fp32", mx.MODE_FP32_ALL)):
+            for dname, dot in (("fp64", mx.DOT_F64), ("fp32", mx.DOT_F32), ("dot2", mx.DOT_DOT2)):
+                for oname, order in (("one", mx.GS_ORDER_ONE), ("per_copy", mx.GS_ORDER_PER_COPY)):
+                    x = torch.zeros_like(b)
+                    _, st = mesh.solve(b, x, mode=mode, pc=pc, tol=wl.tol, max_iter=wl.maxit,
+                                       dot=dot, gs_order=order)
+                    d = float(torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64))
+                    log(f"  {pname:8s} gs {gname} dot {dname:4s} {oname:8s}: it={st.iterations:5d} "
+                        f"reason={st.reason} rec={st.rel_res_recursive:.2e} true={st.rel_res:.2e} "
+                        f"diff={d:.2e} {st.ms:.1f} ms")
+                    rows.append({"pc": pname, "loop": "fp32", "gs_sums": gname, "dot": dname,
+                                 "order": oname, "reason": st.reason,
+                                 "iterations": st.iterations, "rec_res": st.rel_res_recursive,
+                                 "true_res": st.rel_res, "rel_diff_vs_fp64": d,
+                                 "ms": round(st.ms, 2)})
+                    its += st.iterations
+                    el += st.ms
+    reasons = {mx.CONVERGED: "converged", mx.MAX_ITER: "max_iter", mx.STAGNATED: "stagnated",
+               mx.BREAKDOWN: "breakdown"}
+    for r in rows:
+        r["reason"] = reasons.get(r["reason"], str(r["reason"]))
+    out = {
+        "metric": "GDOF*iter/s (local dofs x iterations / s) of the SEM PCG solve",
+        "value": round(nloc * its / (el / 1e3) / 1e9, 4), "unit": "GDOF*iter/s", "n_gpus": 1,
+        "steps": len(rows), "warmup": 1, "ms_per_step": round(el / len(rows), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 loop; gather-scatter sums and dots per row", "data": "synthetic",
+        "config": {"workload": wl.name, "E": bm.E, "N": wl.N, "nloc": nloc,
+                   "mode": "strategy table", "tol": wl.tol},
+        "strategies": rows,
+    }
+    print(json.dumps(out), flush=True)
     mesh.close()
     ctx.close()
 

@@ -87,6 +87,30 @@ typedef enum {
 
 typedef enum { MXSEM_METHOD_PCG = 0, MXSEM_METHOD_FCG = 1 } mxsem_method;
 
+/* ---- accumulation of the dot products of the FP32 loop (Sec. 4.2.2) ------ */
+typedef enum {
+  MXSEM_DOT_DEFAULT = 0, /* the mode's own: FP32 in MXSEM_MODE_FP32_ALL, else FP64 */
+  MXSEM_DOT_F64 = 1,     /* FP32 inputs, products and sums in FP64           */
+  MXSEM_DOT_F32 = 2,     /* products and sums in FP32                        */
+  MXSEM_DOT_DOT2 = 3     /* compensated FP32: the Dot2 algorithm of Ogita,
+                            Rump and Oishi (2005) within each thread, partial
+                            results (sum, correction) combined by TwoSum
+                            across threads and workgroups; the result is
+                            the FP32 rounding of sum + correction          */
+} mxsem_dot_acc;
+
+/* ---- summation order of the gather-scatter in the solve ------------------ */
+typedef enum {
+  MXSEM_GS_ORDER_ONE = 0,      /* one sum per node (ascending local index),
+                                  written to every copy: the copies stay equal */
+  MXSEM_GS_ORDER_PER_COPY = 1  /* each copy sums the node's copies in an order
+                                  of its own (itself first, then the others
+                                  cyclically): the order of a pairwise
+                                  exchange between ranks, each copy standing
+                                  for a rank (Sec. 4.2.1).  FP32 vectors,
+                                  at most 16 copies per node                 */
+} mxsem_gs_order;
+
 /* termination reasons */
 #define MXSEM_CONVERGED 1
 #define MXSEM_MAX_ITER 2
@@ -96,6 +120,7 @@ typedef enum { MXSEM_METHOD_PCG = 0, MXSEM_METHOD_FCG = 1 } mxsem_method;
 /* apply / gather-scatter flags */
 #define MXSEM_LOCAL_ONLY 1u /* apply: w = A_L u only (no QQ^T, no mask)      */
 #define MXSEM_MASK 2u       /* gather_scatter: also zero Dirichlet entries   */
+#define MXSEM_GS_PER_COPY 4u /* gather_scatter: MXSEM_GS_ORDER_PER_COPY sums  */
 
 /* mesh views (bitmask): which operator copies to keep on the device */
 #define MXSEM_VIEW_F64 1u
@@ -165,7 +190,11 @@ int mxsem_apply(mxsem_mesh *mesh, mxsem_prec io, const void *u, void *w, unsigne
 /* In place v <- QQ^T v: each shared node's copies are summed in ascending
  * local-index order in acc precision (MXSEM_F64 or MXSEM_F32), rounded once
  * to io and written to every copy.  MXSEM_MASK also zeroes Dirichlet
- * entries.  io: MXSEM_F64 or MXSEM_F32. */
+ * entries.  io: MXSEM_F64 or MXSEM_F32.  MXSEM_GS_PER_COPY (io MXSEM_F32,
+ * at most 16 copies per node, else MXSEM_ENOTSUP): copy k of a node with
+ * copies v_0..v_{m-1} (ascending local index) receives
+ * (..((v_k + v_{k+1}) + v_{k+2}) + ..) + v_{k-1}, indices mod m, summed in
+ * acc and rounded once to FP32. */
 int mxsem_gather_scatter(mxsem_mesh *mesh, mxsem_prec io, mxsem_prec acc, void *v,
                          unsigned flags);
 
@@ -173,6 +202,13 @@ int mxsem_gather_scatter(mxsem_mesh *mesh, mxsem_prec io, mxsem_prec acc, void *
  * products and accumulation in FP64 (glsc3).  io: MXSEM_F64 or MXSEM_F32. */
 int mxsem_dot(mxsem_mesh *mesh, mxsem_prec io, const void *a, const void *b,
               double *out_dev);
+
+/* As mxsem_dot with the accumulation acc (mxsem_dot_acc; MXSEM_DOT_DEFAULT
+ * is FP64).  MXSEM_DOT_F32 and MXSEM_DOT_DOT2 take io MXSEM_F32 and write an
+ * FP32 value (widened to FP64) to *out_dev; each term is (a_i c_i) b_i with
+ * a_i c_i rounded to FP32 (exact when the multiplicity is a power of two). */
+int mxsem_dot_ex(mxsem_mesh *mesh, mxsem_prec io, int acc, const void *a, const void *b,
+                 double *out_dev);
 
 /* z = M^-1 r for pc = identity or Jacobi (io MXSEM_F64 / MXSEM_F32), or the
  * learned map (MXSEM_F32, network attached). */
@@ -194,6 +230,11 @@ typedef struct {
   int x0_given;       /* 1: start from x (FP64 modes); 0: x = 0            */
   double *history;    /* nullable device FP64 [max_iter+1]: relative
                          recursive residual per iteration                   */
+  int dot;            /* mxsem_dot_acc of the loop's dots: PCG, FP32 vectors
+                         with FP32 G (MIXED, MIXED_IR, FP32_ALL); otherwise
+                         MXSEM_DOT_DEFAULT (or MXSEM_DOT_F64)               */
+  int gs_order;       /* mxsem_gs_order of the loop's gather-scatter: PCG in
+                         MIXED or FP32_ALL; otherwise MXSEM_GS_ORDER_ONE    */
 } mxsem_solve_opts;
 
 typedef struct {
@@ -214,7 +255,7 @@ typedef struct {
 
 /* Solve A x = b.  b, x: device FP64 local vectors (b continuous and masked,
  * e.g. from mxsem_mass_rhs).  Stops at tol, max_iter, stagnation (the best
- * residual has not improved by 10% in 50 iterations) or breakdown.
+ * residual has not improved by 10% in 500 iterations) or breakdown.
  * Synchronous on the context stream; fills st. */
 int mxsem_solve(mxsem_mesh *mesh, const mxsem_solve_opts *opts, const double *b, double *x,
                 mxsem_solve_stats *st);

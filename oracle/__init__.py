@@ -52,6 +52,14 @@ def _load():
     lib.orc_mesh_destroy.argtypes = [vp]
     lib.orc_mesh_nloc.argtypes = [vp]
     lib.orc_mesh_nloc.restype = C.c_int64
+    lib.orc_dot2_f32.argtypes = [C.c_int64, vp, vp]
+    lib.orc_dot2_f32.restype = C.c_float
+    lib.orc_dot_f32.argtypes = [C.c_int64, vp, vp]
+    lib.orc_dot_f32.restype = C.c_float
+    lib.orc_dot_c_f32.argtypes = [vp, C.c_int, vp, vp]
+    lib.orc_dot_c_f32.restype = C.c_float
+    lib.orc_gs_f32.argtypes = [vp, vp, C.c_int, C.c_int]
+    lib.orc_gs_f32.restype = C.c_int
     lib.orc_max_threads.argtypes = []
     lib.orc_max_threads.restype = C.c_int
     lib.orc_mesh_ngroups.argtypes = [vp]
@@ -104,6 +112,24 @@ class SolveStats:
     fallback: int
     rel_res_recursive: float
     rel_res_true: float
+
+
+def _f32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float32).reshape(-1)
+
+
+def dot2_f32(x, y) -> np.float32:
+    """Dot2 (Ogita, Rump, Oishi 2005) of two FP32 vectors, in index order."""
+    x, y = _f32(x), _f32(y)
+    assert x.size == y.size
+    return np.float32(_load().orc_dot2_f32(x.size, _p(x), _p(y)))
+
+
+def dot_f32(x, y) -> np.float32:
+    """Recursive FP32 dot in index order."""
+    x, y = _f32(x), _f32(y)
+    assert x.size == y.size
+    return np.float32(_load().orc_dot_f32(x.size, _p(x), _p(y)))
 
 
 def max_threads() -> int:
@@ -241,6 +267,20 @@ class Mesh:
         a = _f64(a).reshape(-1)
         b = _f64(b).reshape(-1)
         return float(_lib.orc_dot(self._h, _p(a), _p(b)))
+
+    def dot_c_f32(self, a, b, dot2: bool) -> np.float32:
+        """(a, b)_c in FP32: terms (fl(a_i c_i), b_i), Dot2 or recursive sum."""
+        a, b = _f32(a), _f32(b)
+        return np.float32(_lib.orc_dot_c_f32(self._h, 1 if dot2 else 0, _p(a), _p(b)))
+
+    def gs_f32(self, v, acc64: bool, per_copy: bool) -> np.ndarray:
+        """QQ^T on an FP32 vector: FP64 or FP32 sums, one order per group or
+        each copy's own cyclic order (see orc_gs_f32)."""
+        v = _f32(v).copy()
+        rc = _lib.orc_gs_f32(self._h, _p(v), 1 if acc64 else 0, 1 if per_copy else 0)
+        if rc != 0:
+            raise ValueError(f"orc_gs_f32 failed: {rc}")
+        return v
 
     # --- solvers -----------------------------------------------------------
     def pcg(self, b, pc=PC_JACOBI, tol=1e-10, maxit=1000, x0=None, history=False, nn=None):

@@ -379,6 +379,103 @@ double orc_dot(const orc_mesh *m, const double *a, const double *b) {
   return s;
 }
 
+/* ------------------------------------------------------------------------ */
+/* FP32 reductions of the extended-precision study (Sec. 4.2.2, and the     */
+/* gather-scatter modes of Sec. 4.2.1).  The only FP32 routines here: they  */
+/* define what the working-precision variants of the dot products and of    */
+/* the gather-scatter compute.  Compiled with contraction off, so every     */
+/* operation below is one IEEE FP32 operation.                               */
+/* ------------------------------------------------------------------------ */
+
+/* TwoSum (Knuth): s = fl(a + b) and e with a + b = s + e exactly. */
+static void orc_two_sum(float a, float b, float *s, float *e) {
+  const float x = a + b;
+  const float z = x - a;
+  *e = (a - (x - z)) + (b - z);
+  *s = x;
+}
+
+/* TwoProduct by a fused multiply-add: p = fl(a b), e = a b - p exactly. */
+static void orc_two_prod(float a, float b, float *p, float *e) {
+  const float x = a * b;
+  *e = fmaf(a, b, -x);
+  *p = x;
+}
+
+/* Dot2 of Ogita, Rump and Oishi (2005), in index order: the running sum p
+ * takes each rounded product by TwoSum; the product errors and the TwoSum
+ * errors accumulate in s; the result is fl(p + s). */
+float orc_dot2_f32(int64_t n, const float *x, const float *y) {
+  float p = 0.f, s = 0.f;
+  for (int64_t i = 0; i < n; ++i) {
+    float h, r, q;
+    orc_two_prod(x[i], y[i], &h, &r);
+    orc_two_sum(p, h, &p, &q);
+    s = s + (q + r);
+  }
+  return p + s;
+}
+
+/* Recursive FP32 dot in index order: s = fl(s + fl(x_i y_i)). */
+float orc_dot_f32(int64_t n, const float *x, const float *y) {
+  float s = 0.f;
+  for (int64_t i = 0; i < n; ++i) s = s + x[i] * y[i];
+  return s;
+}
+
+/* Weighted dot (a, b)_c in the working precision: the terms are
+ * (fl(a_i c_i), b_i) with c_i rounded to FP32, then summed by Dot2 (dot2 =
+ * 1) or recursively in FP32 (dot2 = 0). */
+float orc_dot_c_f32(const orc_mesh *m, int dot2, const float *a, const float *b) {
+  float *t = (float *)malloc(sizeof(float) * (size_t)(m->nloc ? m->nloc : 1));
+  if (!t) return NAN;
+  for (int64_t i = 0; i < m->nloc; ++i) t[i] = a[i] * (float)m->c[i];
+  const float r = dot2 ? orc_dot2_f32(m->nloc, t, b) : orc_dot_f32(m->nloc, t, b);
+  free(t);
+  return r;
+}
+
+/* QQ^T on an FP32 vector.  acc64: sums in FP64 (else FP32), rounded once to
+ * FP32.  per_copy = 0: one sum per group in ascending local index order,
+ * written to every copy.  per_copy = 1: copy k (k-th in ascending local
+ * index order) receives v_k + v_{k+1} + ... + v_{m-1} + v_0 + ... + v_{k-1},
+ * added left to right: the order in which a rank adds its neighbours'
+ * contributions to its own in a pairwise exchange, each copy standing for a
+ * rank.  Groups of up to 64 copies. */
+int orc_gs_f32(const orc_mesh *m, float *v, int acc64, int per_copy) {
+  for (int64_t q = 0; q < m->ngroups; ++q)
+    if (m->goff[q + 1] - m->goff[q] > 64) return ORC_EINVAL;
+#pragma omp parallel for schedule(static)
+  for (int64_t q = 0; q < m->ngroups; ++q) {
+    const int64_t o = m->goff[q];
+    const int cnt = (int)(m->goff[q + 1] - o);
+    float val[64], out[64];
+    for (int k = 0; k < cnt; ++k) val[k] = v[m->gidx[o + k]];
+    for (int k = 0; k < cnt; ++k) {
+      const int k0 = per_copy ? k : 0;
+      if (!per_copy && k > 0) {
+        out[k] = out[0];
+        continue;
+      }
+      double sd = 0.0;
+      float sf = 0.f;
+      for (int j = 0; j < cnt; ++j) {
+        const float a = val[(k0 + j) % cnt];
+        if (j == 0) {
+          sd = (double)a;
+          sf = a;
+        } else {
+          sd = sd + (double)a;
+          sf = sf + a;
+        }
+      }
+      out[k] = acc64 ? (float)sd : sf;
+    }
+    for (int k = 0; k < cnt; ++k) v[m->gidx[o + k]] = out[k];
+  }
+  return ORC_OK;
+}
+
 /* O8: right-hand side b = M QQ^T (B f) */
 void orc_rhs(const orc_mesh *m, const double *f, double *b) {
 #pragma omp parallel for schedule(static)

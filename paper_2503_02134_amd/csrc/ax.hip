@@ -75,8 +75,9 @@ __device__ inline void elem_sync() {
 }
 
 // Solver variant: p = z + beta p_old (beta from the device state, p
-// written back), w = A_L p, and the workgroup's partial sum of p.w.
-template <int N, typename T, typename TG, bool SOLVER>
+// written back), w = A_L p, and the workgroup's partial sum of p.w,
+// accumulated as DotMode DM says.
+template <int N, typename T, typename TG, bool SOLVER, int DM>
 __global__ void __launch_bounds__(256) ax_kernel(const Tile* __restrict__ tiles, const ProbDev* __restrict__ probs,
                           AxApplyArgs apply, int epb) {
   constexpr int n = N + 1, n2 = n * n, n3 = n2 * n;
@@ -221,18 +222,18 @@ __global__ void __launch_bounds__(256) ax_kernel(const Tile* __restrict__ tiles,
   // (p, QQ^T A_L p)_c = sum_i p_i (A_L p)_i over all local entries, because
   // p is continuous and zero on Dirichlet nodes: the solver takes sigma
   // from the local result, before the gather-scatter.
-  double dot = 0.0;
+  DotAcc<DM> dot;
   if (active) {
 #pragma unroll
     for (int k = 0; k < n; ++k) {
       T wv = w[k];
       if (hB) wv += cvt<T>(__builtin_nontemporal_load(&hB[(int64_t)e * n3 + k * n2 + ij])) * u[k];
       Wout[base + k * n2] = wv;
-      if constexpr (SOLVER) dot += (double)u[k] * (double)wv;
+      if constexpr (SOLVER) dot.add(u[k], wv);
     }
   }
   if constexpr (SOLVER) {
-    double s = block_sum(dot, sred);
+    double s = dot.block(sred);
     if (tid == 0) gcast(P->part_ax)[first / epb] = s;
   }
 }
@@ -254,7 +255,7 @@ constexpr int ax2_epw() {  // elements per wave
   return 64 / ((N + 1) * ((N + 1) / 2));
 }
 
-template <int N, typename T, typename TG, bool SOLVER>
+template <int N, typename T, typename TG, bool SOLVER, int DM>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) ax2_kernel(const Tile* __restrict__ tiles, const ProbDev* __restrict__ probs,
                            AxApplyArgs apply, int epb) {
   constexpr int n = N + 1, n2 = n * n, n3 = n2 * n, hn = n / 2, TPE = n * hn, EPW = 64 / TPE;
@@ -419,7 +420,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
     elem_sync<1>();
   }
 
-  double dot = 0.0;
+  DotAcc<DM> dot;
   if (active) {
 #pragma unroll
     for (int k = 0; k < n; ++k) {
@@ -430,18 +431,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
       }
       Wout[base0 + k * n2] = wv0;
       Wout[base1 + k * n2] = wv1;
-      if constexpr (SOLVER) dot += (double)u0[k] * (double)wv0 + (double)u1[k] * (double)wv1;
+      if constexpr (SOLVER) dot.add2(u0[k], wv0, u1[k], wv1);
     }
   }
   if constexpr (SOLVER) {
-    double s = block_sum(dot, sred);
+    double s = dot.block(sred);
     if (tid == 0) gcast(P->part_ax)[first / epb] = s;
   }
 }
 
 // With ev0/ev1 the launch records its own start and end (hipExtLaunchKernel),
 // so the elapsed time between them is the kernel's execution time.
-template <int N, typename T, typename TG, bool SOLVER>
+template <int N, typename T, typename TG, bool SOLVER, int DM>
 static hipError_t launch_one(const Tile* tiles, const ProbDev* probs, const AxApplyArgs& a,
                              int ntiles, int epb, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   constexpr int n = N + 1, n2 = n * n;
@@ -451,10 +452,10 @@ static hipError_t launch_one(const Tile* tiles, const ProbDev* probs, const AxAp
     if (epb < 1 || waves > 4) return hipErrorInvalidConfiguration;
     const size_t shm = sizeof(T) * (n2 + (size_t)waves * EPW * 3 * n2);
     if (ev0)
-      hipExtLaunchKernelGGL((ax2_kernel<N, T, TG, SOLVER>), dim3(ntiles), dim3(64 * waves),
+      hipExtLaunchKernelGGL((ax2_kernel<N, T, TG, SOLVER, DM>), dim3(ntiles), dim3(64 * waves),
                             (uint32_t)shm, s, ev0, ev1, 0, tiles, probs, a, epb);
     else
-      hipLaunchKernelGGL((ax2_kernel<N, T, TG, SOLVER>), dim3(ntiles), dim3(64 * waves), shm, s,
+      hipLaunchKernelGGL((ax2_kernel<N, T, TG, SOLVER, DM>), dim3(ntiles), dim3(64 * waves), shm, s,
                          tiles, probs, a, epb);
     return hipGetLastError();
   }
@@ -462,22 +463,22 @@ static hipError_t launch_one(const Tile* tiles, const ProbDev* probs, const AxAp
   if (epb < 1 || threads > 256) return hipErrorInvalidConfiguration;
   size_t shm = sizeof(T) * (n2 + (size_t)epb * 3 * n2);
   if (ev0)
-    hipExtLaunchKernelGGL((ax_kernel<N, T, TG, SOLVER>), dim3(ntiles), dim3(threads), (uint32_t)shm,
+    hipExtLaunchKernelGGL((ax_kernel<N, T, TG, SOLVER, DM>), dim3(ntiles), dim3(threads), (uint32_t)shm,
                           s, ev0, ev1, 0, tiles, probs, a, epb);
   else
-    hipLaunchKernelGGL((ax_kernel<N, T, TG, SOLVER>), dim3(ntiles), dim3(threads), shm, s, tiles,
+    hipLaunchKernelGGL((ax_kernel<N, T, TG, SOLVER, DM>), dim3(ntiles), dim3(threads), shm, s, tiles,
                        probs, a, epb);
   return hipGetLastError();
 }
 
-template <typename T, typename TG, bool SOLVER>
+template <typename T, typename TG, bool SOLVER, int DM = DOT_F64>
 static hipError_t dispatch(int N, const Tile* tiles, const ProbDev* probs, const AxApplyArgs& a,
                            int ntiles, int epb, hipStream_t s, hipEvent_t ev0 = nullptr,
                            hipEvent_t ev1 = nullptr) {
   switch (N) {
 #define MX_CASE(NN) \
   case NN:          \
-    return launch_one<NN, T, TG, SOLVER>(tiles, probs, a, ntiles, epb, s, ev0, ev1);
+    return launch_one<NN, T, TG, SOLVER, DM>(tiles, probs, a, ntiles, epb, s, ev0, ev1);
     MX_CASE(1) MX_CASE(2) MX_CASE(3) MX_CASE(4) MX_CASE(5) MX_CASE(6) MX_CASE(7) MX_CASE(8)
     MX_CASE(9) MX_CASE(10) MX_CASE(11) MX_CASE(12) MX_CASE(13) MX_CASE(14) MX_CASE(15)
 #undef MX_CASE
@@ -499,9 +500,17 @@ hipError_t launch_ax_apply(int prec, int N, int E, int epb, const void* u, void*
   }
 }
 
-hipError_t launch_ax_solver(int prec, int N, const Tile* tiles, int ntiles, const ProbDev* probs,
-                            int epb, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+// dm: DotMode of the sigma partials (FP32 vectors with FP32 G; FP64
+// vectors and BF16 G take DOT_F64)
+hipError_t launch_ax_solver(int prec, int dm, int N, const Tile* tiles, int ntiles,
+                            const ProbDev* probs, int epb, hipStream_t s, hipEvent_t ev0,
+                            hipEvent_t ev1) {
   AxApplyArgs a{};
+  if (prec == 1 && dm == DOT_F32)
+    return dispatch<float, float, true, DOT_F32>(N, tiles, probs, a, ntiles, epb, s, ev0, ev1);
+  if (prec == 1 && dm == DOT_DOT2)
+    return dispatch<float, float, true, DOT_DOT2>(N, tiles, probs, a, ntiles, epb, s, ev0, ev1);
+  if (dm != DOT_F64) return hipErrorInvalidValue;
   switch (prec) {
     case 0: return dispatch<double, double, true>(N, tiles, probs, a, ntiles, epb, s, ev0, ev1);
     case 1: return dispatch<float, float, true>(N, tiles, probs, a, ntiles, epb, s, ev0, ev1);

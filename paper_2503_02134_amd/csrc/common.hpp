@@ -167,12 +167,14 @@ struct ProbDev {
   double* part_u1;   // per update tile: (r,r)_c
   double* part_u2;   // per tile: (z,w)_c (flexible CG)
   int nblk_ax, nblk_gs, nblk_upd;
+  int dm;            // DotMode of the partial sums (PCG)
   State* st;
 };
 
 constexpr int GS_THREADS = 256;  // gather-scatter workgroup
 constexpr int GS_PER_THREAD = 2;
 constexpr int GS_CHUNK = GS_THREADS * GS_PER_THREAD;  // items per workgroup
+constexpr int GS_PERCOPY_MAXM = 16;  // largest group of the per-copy summation order
 constexpr int UPD_THREADS = 256; // threads per vector-update workgroup
 constexpr int UPD_PER_THREAD = 8;  // entries per thread (two 4-wide vectors)
 constexpr int UPD_CHUNK = UPD_THREADS * UPD_PER_THREAD;
@@ -187,12 +189,12 @@ constexpr int XCDS = 8;
 constexpr int STAG_WINDOW = 500;
 
 // ---------------------------------------------------------------- reductions
-// Deterministic block sum of one double per thread (wave64 shuffles, then
-// LDS across waves).  Every thread of the block must call it.  Returns the
-// sum on thread 0.
 // c = 1/m, the weight of a local copy in the c-weighted dots
 __device__ inline double cweight(uint8_t m) { return m == 1 ? 1.0 : 1.0 / (double)m; }
 
+// Deterministic block sum of one value per thread (wave64 shuffles, then
+// LDS across waves).  Every thread of the block must call it.  Returns the
+// sum on thread 0.
 template <typename A>
 __device__ inline A block_sum(A v, A* sred) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -205,6 +207,129 @@ __device__ inline A block_sum(A v, A* sred) {
   if (threadIdx.x == 0)
     for (int q = 0; q < nw; ++q) s += sred[q];
   return s;
+}
+
+// ---------------------------------------------------------------- dot accumulation
+// Accumulation of the dots of an FP32 iteration (the extended-precision
+// study of Sec. 4.2.2):
+//   DOT_F64   products and sums in FP64 (the mixed recipe);
+//   DOT_F32   products and sums in FP32, the working precision;
+//   DOT_DOT2  compensated FP32, the Dot2 algorithm of Ogita, Rump and Oishi
+//             (2005): each product is split exactly into its rounded value
+//             and its error (TwoProduct), the value enters the running sum
+//             by TwoSum, whose error joins the product error in a running
+//             FP32 correction.  Two partial results (sum, correction) are
+//             combined by TwoSum of the sums plus both corrections (the
+//             reduction of size-two expansions that the paper applies across
+//             ranks, here across lanes, waves and workgroups).  The result is
+//             the FP32 rounding of sum + correction.
+// A weighted term a c b (c = 1/m) is formed as (a c) b; a c is exact in
+// FP32 when m is a power of two (every copy count of a hexahedral box).
+enum DotMode { DOT_F64 = 0, DOT_F32 = 1, DOT_DOT2 = 2 };
+
+// Error-free transformations in FP32.  Contraction stays off inside them:
+// a product fused into the following sum would lose the error term.
+__device__ inline void two_sum(float a, float b, float& s, float& e) {
+#pragma clang fp contract(off)
+  s = a + b;
+  const float z = s - a;
+  e = (a - (s - z)) + (b - z);
+}
+__device__ inline void two_prod(float a, float b, float& p, float& e) {
+#pragma clang fp contract(off)
+  p = a * b;
+  e = __builtin_fmaf(a, b, -p);
+}
+
+struct F2 {
+  float s, c;  // running sum and its correction
+};
+__device__ inline F2 f2_combine(F2 a, F2 b) {
+#pragma clang fp contract(off)
+  F2 r;
+  float e;
+  two_sum(a.s, b.s, r.s, e);
+  r.c = (a.c + b.c) + e;
+  return r;
+}
+
+// Per-thread accumulator; block() reduces over the workgroup and returns
+// the workgroup's partial on thread 0, encoded in one double (FP64 and
+// FP32 modes: the value; Dot2: the (sum, correction) pair's bits).
+template <int DM>
+struct DotAcc;
+template <>
+struct DotAcc<DOT_F64> {
+  double s = 0.0;
+  template <typename T>
+  __device__ void add(T a, T b) { s += (double)a * (double)b; }
+  template <typename T>
+  __device__ void add2(T a0, T b0, T a1, T b1) { s += (double)a0 * (double)b0 + (double)a1 * (double)b1; }
+  template <typename T>
+  __device__ void addw(T a, double c, T b) { s += (double)a * c * (double)b; }
+  __device__ double block(double* sred) { return block_sum(s, sred); }
+};
+template <>
+struct DotAcc<DOT_F32> {
+  float s = 0.f;
+  __device__ void add(float a, float b) { s += a * b; }
+  __device__ void add2(float a0, float b0, float a1, float b1) { s += a0 * b0; s += a1 * b1; }
+  __device__ void addw(float a, double c, float b) { s += (a * (float)c) * b; }
+  __device__ double block(double* sred) { return (double)block_sum(s, (float*)sred); }
+};
+template <>
+struct DotAcc<DOT_DOT2> {
+  F2 v = {0.f, 0.f};
+  __device__ void add(float a, float b) {
+#pragma clang fp contract(off)
+    float h, r, q;
+    two_prod(a, b, h, r);
+    two_sum(v.s, h, v.s, q);
+    v.c += q + r;
+  }
+  __device__ void add2(float a0, float b0, float a1, float b1) { add(a0, b0); add(a1, b1); }
+  __device__ void addw(float a, double c, float b) {
+#pragma clang fp contract(off)
+    add(a * (float)c, b);
+  }
+  __device__ double block(double* sred) {
+    F2 x = v;
+    for (int off = 32; off > 0; off >>= 1) {
+      F2 y;
+      y.s = __shfl_down(x.s, off, 64);
+      y.c = __shfl_down(x.c, off, 64);
+      x = f2_combine(x, y);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if (lane == 0) sred[wid] = __builtin_bit_cast(double, x);
+    __syncthreads();
+    F2 t = {0.f, 0.f};
+    if (threadIdx.x == 0)
+      for (int q = 0; q < nw; ++q) t = f2_combine(t, __builtin_bit_cast(F2, sred[q]));
+    return __builtin_bit_cast(double, t);
+  }
+};
+
+// Sum of n workgroup partials of mode dm by one workgroup of NT threads in a
+// fixed order (thread t takes parts t, t + NT, ...; then the block); the
+// FP32 modes return an FP32 value.
+template <int NT>
+__device__ inline double dot_finish(int dm, const gptr<const double> __restrict__ parts, int n,
+                                    double* sred) {
+  if (dm == DOT_F32) {
+    float a = 0.f;
+    for (int q = threadIdx.x; q < n; q += NT) a += (float)parts[q];
+    return (double)block_sum(a, (float*)sred);
+  }
+  // DOT_DOT2
+  F2 a = {0.f, 0.f};
+  for (int q = threadIdx.x; q < n; q += NT) a = f2_combine(a, __builtin_bit_cast(F2, parts[q]));
+  DotAcc<DOT_DOT2> acc;
+  acc.v = a;
+  const F2 t = __builtin_bit_cast(F2, acc.block(sred));
+  return (double)(t.s + t.c);
 }
 
 }  // namespace mx

@@ -136,6 +136,12 @@ int ensure_tmp(mxsem_mesh* m) {
   return MXSEM_OK;
 }
 
+int max_copies(const mxsem_mesh* m) {
+  int mx = 1;
+  for (int q = 0; q < m->plan.nall; ++q) mx = std::max(mx, m->plan.bk[q].m);
+  return mx;
+}
+
 int apply_impl(mxsem_mesh* m, int prec, const void* u, void* w, unsigned flags, hipStream_t s) {
   const int gprec = prec;  // 0 F64, 1 F32, 2 BF16 G with FP32 vectors
   const void* D = prec == MXSEM_F64 ? (const void*)m->D64 : (const void*)m->D32;
@@ -542,9 +548,16 @@ int mxsem_gather_scatter(mxsem_mesh* m, mxsem_prec io, mxsem_prec acc, void* v, 
   MX_CHECK(m && v, MXSEM_EINVAL, "gather_scatter: null argument");
   MX_CHECK(io == MXSEM_F64 || io == MXSEM_F32, MXSEM_EINVAL, "gather_scatter: io must be F64/F32");
   MX_CHECK(acc == MXSEM_F64 || acc == MXSEM_F32, MXSEM_EINVAL, "gather_scatter: acc must be F64/F32");
+  const bool percopy = (flags & MXSEM_GS_PER_COPY) != 0;
+  if (percopy) {
+    MX_CHECK(io == MXSEM_F32, MXSEM_ENOTSUP, "gather_scatter: per-copy order takes FP32 vectors");
+    MX_CHECK(max_copies(m) <= GS_PERCOPY_MAXM, MXSEM_ENOTSUP,
+             "gather_scatter: per-copy order takes at most 16 copies per node");
+  }
   MX_HIP(hipSetDevice(m->ctx->device));
   (void)hipGetLastError();
-  MX_HIP(launch_gs_apply(io, acc, v, m->plan, (flags & MXSEM_MASK) != 0, m->ctx->stream));
+  MX_HIP(launch_gs_apply(io, acc, v, m->plan, (flags & MXSEM_MASK) != 0, m->ctx->stream,
+                         percopy));
   return MXSEM_OK;
 }
 
@@ -554,6 +567,21 @@ int mxsem_dot(mxsem_mesh* m, mxsem_prec io, const void* a, const void* b, double
   MX_HIP(hipSetDevice(m->ctx->device));
   (void)hipGetLastError();
   MX_HIP(launch_dot(io, a, b, m->mult, m->nloc, m->part, out_dev, m->ctx->stream));
+  return MXSEM_OK;
+}
+
+int mxsem_dot_ex(mxsem_mesh* m, mxsem_prec io, int acc, const void* a, const void* b,
+                 double* out_dev) {
+  MX_CHECK(m && a && b && out_dev, MXSEM_EINVAL, "dot_ex: null argument");
+  MX_CHECK(io == MXSEM_F64 || io == MXSEM_F32, MXSEM_EINVAL, "dot_ex: io must be F64/F32");
+  MX_CHECK(acc >= MXSEM_DOT_DEFAULT && acc <= MXSEM_DOT_DOT2, MXSEM_EINVAL,
+           "dot_ex: unknown accumulation");
+  const int dm = dot_mode_of(acc, DOT_F64);
+  MX_CHECK(io == MXSEM_F32 || dm == DOT_F64, MXSEM_ENOTSUP,
+           "dot_ex: FP32 and Dot2 accumulation take FP32 vectors");
+  MX_HIP(hipSetDevice(m->ctx->device));
+  (void)hipGetLastError();
+  MX_HIP(launch_dot(io, a, b, m->mult, m->nloc, m->part, out_dev, m->ctx->stream, dm));
   return MXSEM_OK;
 }
 

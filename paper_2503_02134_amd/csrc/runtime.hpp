@@ -19,13 +19,14 @@ namespace mx {
 // launchers (defined in the .hip files)
 hipError_t launch_ax_apply(int prec, int N, int E, int epb, const void* u, void* w, const void* G,
                            const void* hB, const void* D, hipStream_t s);
-hipError_t launch_ax_solver(int prec, int N, const Tile* tiles, int ntiles, const ProbDev* probs,
+hipError_t launch_ax_solver(int prec, int dm, int N, const Tile* tiles, int ntiles, const ProbDev* probs,
                             int epb, hipStream_t s, hipEvent_t ev0 = nullptr,
                             hipEvent_t ev1 = nullptr);
 int max_epb(int N);
 int ax_wave_elements(int N);
+// percopy: every copy sums in its own order (FP32 vectors; see gs_kernel)
 hipError_t launch_gs_apply(int prec_io, int prec_acc, void* v, const GsPlan& plan, bool mask,
-                           hipStream_t s);
+                           hipStream_t s, bool percopy = false);
 // sigma_probs > 0: the launch also finishes sigma and alpha of problems
 // 0..sigma_probs-1 (alpha = rho / sigma, breakdown test) in workgroups of its own.
 // ztiles (with on_z): vector-pass tiles of workgroups that set z = dinv r
@@ -33,7 +34,7 @@ hipError_t launch_gs_apply(int prec_io, int prec_acc, void* v, const GsPlan& pla
 // tiles of such a problem do nothing.
 hipError_t launch_gs_solver(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs,
                             hipStream_t s, bool on_z = false, int sigma_probs = 0,
-                            const Tile* ztiles = nullptr, int nz = 0);
+                            const Tile* ztiles = nullptr, int nz = 0, bool percopy = false);
 hipError_t launch_zpc(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs, int pc,
                       hipStream_t s);
 hipError_t launch_fcg_dots(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs,
@@ -67,13 +68,14 @@ struct NnDots {
 hipError_t launch_nn_fwd(int N, const float* r, const float* dinv, const uint8_t* mult,
                          const float* W1, const float* W2, float* zc, int E, hipStream_t s,
                          const State* st, const void* packed, NnDots dd, int* nparts);
+// dm: DotMode of the dots (FP32 vectors; FP64 vectors take DOT_F64)
 hipError_t launch_update(int vprec, int pc, const Tile* tiles, int ntiles, const ProbDev* probs,
-                         hipStream_t s);
+                         hipStream_t s, int dm = DOT_F64);
 hipError_t launch_init(int vprec, int pc, const Tile* tiles, int ntiles, const ProbDev* probs,
-                       const double* x0, hipStream_t s);
+                       const double* x0, hipStream_t s, int dm = DOT_F64);
 hipError_t launch_fin_rho(const ProbDev* probs, int nprob, int mode, hipStream_t s);
 hipError_t launch_dot(int prec, const void* a, const void* b, const uint8_t* mult, int64_t n,
-                      double* part, double* out, hipStream_t s);
+                      double* part, double* out, hipStream_t s, int dm = DOT_F64);
 hipError_t launch_precond(int prec, int pc, const void* r, void* z, const void* dinv, int64_t n,
                           hipStream_t s);
 hipError_t launch_residual(const double* b, const double* w, double* r, const uint8_t* mult,
@@ -139,6 +141,10 @@ struct Plan {
   int nt_upd = 0;
   hipGraphExec_t graph = nullptr;
   int graph_k = 0, graph_pc = -1, graph_gprec = -1, graph_method = -1;
+  // dot accumulation (DotMode) and gather-scatter order of the captured
+  // iteration, set per solve
+  int dm = 0, percopy = 0;
+  int graph_dm = -1, graph_percopy = -1;
   hipEvent_t evA = nullptr, evB = nullptr;
   double ax_ms_sum = 0.0;
   int ax_samples = 0;
@@ -201,6 +207,15 @@ int ensure_tmp(mxsem_mesh* m);
 const void* G_ptr(const mxsem_mesh* m, int gprec);
 const void* hB_ptr(const mxsem_mesh* m, int gprec);
 int apply_impl(mxsem_mesh* m, int prec, const void* u, void* w, unsigned flags, hipStream_t s);
+// largest copy count of a node of the mesh
+int max_copies(const mxsem_mesh* m);
+// DotMode of an mxsem_dot_acc value (MXSEM_DOT_DEFAULT: fallback)
+inline int dot_mode_of(int acc, int fallback) {
+  return acc == MXSEM_DOT_F64 ? DOT_F64
+         : acc == MXSEM_DOT_F32 ? DOT_F32
+         : acc == MXSEM_DOT_DOT2 ? DOT_DOT2
+                                 : fallback;
+}
 // learned preconditioner: forward of an attached network into zc (before
 // the gather-scatter); the kernel returns at once when st->done.  With w
 // (= A p of the step), also the dot partials of NnDots: *dots, *nparts per

@@ -261,14 +261,15 @@ int enqueue_ax(Plan* pl, int gprec, hipStream_t s, bool skip_first) {
   const int kprec = pl->vprec == VP_F64 ? 0 : gprec;
   for (size_t c = skip_first ? 1 : 0; c < pl->ax.size(); ++c) {
     const AxClass& ac = pl->ax[c];
-    MX_HIP(launch_ax_solver(kprec, ac.N, ac.tiles, ac.ntiles, pl->probs, ac.epb, s));
+    MX_HIP(launch_ax_solver(kprec, pl->dm, ac.N, ac.tiles, ac.ntiles, pl->probs, ac.epb, s));
   }
   return MXSEM_OK;
 }
 
 static int enqueue_tail(Plan* pl, int pc, hipStream_t s) {
-  MX_HIP(launch_gs_solver(pl->vprec, pl->tiles_gs, pl->nt_gs, pl->probs, s, false, pl->P));
-  MX_HIP(launch_update(pl->vprec, pc, pl->tiles_upd, pl->nt_upd, pl->probs, s));
+  MX_HIP(launch_gs_solver(pl->vprec, pl->tiles_gs, pl->nt_gs, pl->probs, s, false, pl->P, nullptr,
+                          0, pl->percopy != 0));
+  MX_HIP(launch_update(pl->vprec, pc, pl->tiles_upd, pl->nt_upd, pl->probs, s, pl->dm));
   MX_HIP(launch_fin_rho(pl->probs, pl->P, 0, s));
   return MXSEM_OK;
 }
@@ -276,7 +277,8 @@ static int enqueue_tail(Plan* pl, int pc, hipStream_t s) {
 // K iterations; the first iteration's operator launches stay outside
 static int get_graph(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K) {
   if (pl->graph && pl->graph_k == K && pl->graph_pc == pc && pl->graph_gprec == gprec &&
-      pl->graph_method == MXSEM_METHOD_PCG)
+      pl->graph_method == MXSEM_METHOD_PCG && pl->graph_dm == pl->dm &&
+      pl->graph_percopy == pl->percopy)
     return MXSEM_OK;
   if (pl->graph) {
     MX_HIP(hipGraphExecDestroy(pl->graph));
@@ -310,6 +312,8 @@ static int get_graph(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K) {
   pl->graph_pc = pc;
   pl->graph_gprec = gprec;
   pl->graph_method = MXSEM_METHOD_PCG;
+  pl->graph_dm = pl->dm;
+  pl->graph_percopy = pl->percopy;
   return MXSEM_OK;
 }
 
@@ -322,6 +326,8 @@ struct Inner {
   std::vector<int> maxit;
   std::vector<char> active;
   double* history = nullptr;  // single-problem plans only
+  int dm = DOT_F64;            // DotMode of the dots (PCG)
+  int percopy = 0;             // per-copy gather-scatter order (PCG)
   // results
   std::vector<int> iterations, reason, fallback;
   std::vector<double> res;
@@ -331,6 +337,8 @@ static int run_inner(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K, Inner& 
   hipStream_t s = ctx->stream;
   const int P = pl->P;
   int max_launch = 0;
+  pl->dm = in.dm;
+  pl->percopy = in.percopy;
   for (int p = 0; p < P; ++p) {
     State& st = pl->hstate[p];
     memset(&st, 0, sizeof(State));
@@ -347,19 +355,20 @@ static int run_inner(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K, Inner& 
     Q.rhs_scale = in.scale[p];
     Q.G = G_ptr(m, gp);
     Q.hB = hB_ptr(m, gp);
+    Q.dm = in.dm;
     if (in.active[p]) max_launch = std::max(max_launch, in.maxit[p] / K + 2);
   }
   MX_HIP(hipMemcpyAsync(pl->probs, pl->hprob.data(), sizeof(ProbDev) * P, hipMemcpyHostToDevice, s));
   MX_HIP(hipMemcpyAsync(pl->states, pl->hstate, sizeof(State) * P, hipMemcpyHostToDevice, s));
-  MX_HIP(launch_init(pl->vprec, pc, pl->tiles_upd, pl->nt_upd, pl->probs, nullptr, s));
+  MX_HIP(launch_init(pl->vprec, pc, pl->tiles_upd, pl->nt_upd, pl->probs, nullptr, s, in.dm));
   MX_HIP(launch_fin_rho(pl->probs, P, 1, s));
   MX_TRY(get_graph(pl, ctx, gprec, pc, K));
   const int kprec = pl->vprec == VP_F64 ? 0 : gprec;
   for (int l = 0; l < max_launch; ++l) {
     // the chunk's first operator launch of class 0, with its own start/end events
     const AxClass& a0 = pl->ax[0];
-    MX_HIP(launch_ax_solver(kprec, a0.N, a0.tiles, a0.ntiles, pl->probs, a0.epb, s, pl->evA,
-                            pl->evB));
+    MX_HIP(launch_ax_solver(kprec, pl->dm, a0.N, a0.tiles, a0.ntiles, pl->probs, a0.epb, s,
+                            pl->evA, pl->evB));
     MX_TRY(enqueue_ax(pl, gprec, s, true));
     MX_HIP(hipGraphLaunch(pl->graph, s));
     MX_HIP(hipMemcpyAsync(pl->hstate, pl->states, sizeof(State) * P, hipMemcpyDeviceToHost, s));
@@ -417,7 +426,8 @@ static int enqueue_fcg_z(Plan* pl, int pc, hipStream_t s, bool init) {
 
 static int get_graph_fcg(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K) {
   if (pl->graph && pl->graph_k == K && pl->graph_pc == pc && pl->graph_gprec == gprec &&
-      pl->graph_method == MXSEM_METHOD_FCG)
+      pl->graph_method == MXSEM_METHOD_FCG && pl->graph_dm == pl->dm &&
+      pl->graph_percopy == pl->percopy)
     return MXSEM_OK;
   if (pl->graph) {
     MX_HIP(hipGraphExecDestroy(pl->graph));
@@ -462,6 +472,8 @@ static int get_graph_fcg(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K) {
   pl->graph_pc = pc;
   pl->graph_gprec = gprec;
   pl->graph_method = MXSEM_METHOD_FCG;
+  pl->graph_dm = pl->dm;
+  pl->graph_percopy = pl->percopy;
   return MXSEM_OK;
 }
 
@@ -469,6 +481,8 @@ static int run_inner_fcg(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K, Inn
   hipStream_t s = ctx->stream;
   const int P = pl->P;
   int max_launch = 0;
+  pl->dm = DOT_F64;  // flexible CG: FP64 partials (the mode's own accumulation inside them)
+  pl->percopy = 0;
   for (int p = 0; p < P; ++p) {
     State& st = pl->hstate[p];
     memset(&st, 0, sizeof(State));
@@ -485,6 +499,7 @@ static int run_inner_fcg(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K, Inn
     Q.rhs_scale = in.scale[p];
     Q.G = G_ptr(m, gp);
     Q.hB = hB_ptr(m, gp);
+    Q.dm = DOT_F64;
     if (in.active[p]) max_launch = std::max(max_launch, in.maxit[p] / K + 2);
   }
   MX_HIP(hipMemcpyAsync(pl->probs, pl->hprob.data(), sizeof(ProbDev) * P, hipMemcpyHostToDevice, s));
@@ -496,8 +511,8 @@ static int run_inner_fcg(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K, Inn
   const int kprec = pl->vprec == VP_F64 ? 0 : gprec;
   for (int l = 0; l < max_launch; ++l) {
     const AxClass& a0 = pl->ax[0];
-    MX_HIP(launch_ax_solver(kprec, a0.N, a0.tiles, a0.ntiles, pl->probs, a0.epb, s, pl->evA,
-                            pl->evB));
+    MX_HIP(launch_ax_solver(kprec, pl->dm, a0.N, a0.tiles, a0.ntiles, pl->probs, a0.epb, s,
+                            pl->evA, pl->evB));
     MX_TRY(enqueue_ax(pl, gprec, s, true));
     MX_HIP(hipGraphLaunch(pl->graph, s));
     MX_HIP(hipMemcpyAsync(pl->hstate, pl->states, sizeof(State) * P, hipMemcpyDeviceToHost, s));
@@ -566,6 +581,9 @@ static int solve_many(mxsem_ctx* ctx, const std::vector<mxsem_mesh*>& meshes, Ge
   hipStream_t s = ctx->stream;
   for (int p = 0; p < P; ++p) {
     mxsem_mesh* m = meshes[p];
+    if (o->gs_order == MXSEM_GS_ORDER_PER_COPY)
+      MX_CHECK(max_copies(m) <= GS_PERCOPY_MAXM, MXSEM_ENOTSUP,
+               "solve: per-copy gather-scatter order takes at most 16 copies per node");
     if (vprec != VP_F64)
       MX_CHECK(m->dinv32 && (gprec == 2 || m->G32), MXSEM_ENOTSUP, "solve: mesh has no FP32 view");
     if (gprec == 2) MX_CHECK(m->G16, MXSEM_ENOTSUP, "solve: mesh has no BF16 view");
@@ -593,6 +611,9 @@ static int solve_many(mxsem_ctx* ctx, const std::vector<mxsem_mesh*>& meshes, Ge
   in.maxit.assign(P, o->max_iter);
   in.active.assign(P, 1);
   in.history = o->history;
+  in.dm = vprec == VP_F64 ? DOT_F64
+                          : dot_mode_of(o->dot, mode == MXSEM_MODE_FP32_ALL ? DOT_F32 : DOT_F64);
+  in.percopy = o->gs_order == MXSEM_GS_ORDER_PER_COPY ? 1 : 0;
   std::vector<char> fallback(P, 0);
   const bool fcg = o->method == MXSEM_METHOD_FCG || o->pc == MXSEM_PC_LEARNED;
   auto inner = [&](Plan* q, int gp, Inner& io) {
@@ -802,6 +823,21 @@ static int check_opts(const mxsem_solve_opts* o) {
   MX_CHECK(!o->x0_given || o->mode == MXSEM_MODE_FP64 || o->mode == MXSEM_MODE_MIXED_IR ||
                o->mode == MXSEM_MODE_MIXED_IR_BF16G,
            MXSEM_ENOTSUP, "solve: x0 is supported in the FP64 and refinement modes");
+  MX_CHECK(o->dot >= MXSEM_DOT_DEFAULT && o->dot <= MXSEM_DOT_DOT2, MXSEM_EINVAL,
+           "solve: unknown dot accumulation");
+  MX_CHECK(o->gs_order == MXSEM_GS_ORDER_ONE || o->gs_order == MXSEM_GS_ORDER_PER_COPY,
+           MXSEM_EINVAL, "solve: unknown gather-scatter order");
+  const bool pcg = o->method == MXSEM_METHOD_PCG && o->pc != MXSEM_PC_LEARNED;
+  MX_CHECK(o->dot == MXSEM_DOT_DEFAULT || o->dot == MXSEM_DOT_F64 ||
+               (pcg && (o->mode == MXSEM_MODE_MIXED || o->mode == MXSEM_MODE_MIXED_IR ||
+                        o->mode == MXSEM_MODE_FP32_ALL)),
+           MXSEM_ENOTSUP,
+           "solve: FP32 and Dot2 dots are for PCG with FP32 vectors and FP32 G");
+  MX_CHECK(o->dot != MXSEM_DOT_F64 || o->mode != MXSEM_MODE_FP32_ALL || pcg, MXSEM_ENOTSUP,
+           "solve: flexible CG keeps the mode's own dots");
+  MX_CHECK(o->gs_order == MXSEM_GS_ORDER_ONE ||
+               (pcg && (o->mode == MXSEM_MODE_MIXED || o->mode == MXSEM_MODE_FP32_ALL)),
+           MXSEM_ENOTSUP, "solve: the per-copy gather-scatter order is for PCG in MIXED / FP32_ALL");
   return MXSEM_OK;
 }
 

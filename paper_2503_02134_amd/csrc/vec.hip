@@ -42,7 +42,13 @@ __device__ inline void fin_sigma_step(const ProbDev& P, double* sred);
 // One thread per group, GS_PER_THREAD groups per thread issued together:
 // all index loads, then all value loads, then sums (ascending local index,
 // in the accumulation type ACC), then the stores.  m = 0 is the mask list.
-template <typename T, typename ACC, bool SOLVER>
+// PERCOPY: every copy takes the sum in an order of its own instead -- its
+// own value first, then the group's other copies cyclically after it.  This
+// is the summation order of a pairwise exchange between ranks (each rank
+// adds the others' contributions to its own), with every copy standing for
+// a rank: the copies of a node shared by three or more may then differ in
+// their last bits when the sum is rounded in FP32 (m <= GS_PERCOPY_MAXM).
+template <typename T, typename ACC, bool SOLVER, bool PERCOPY = false>
 __global__ void __launch_bounds__(GS_THREADS) gs_kernel(const Tile* __restrict__ tiles,
                                                         const ProbDev* __restrict__ probs,
                                                         GsApi api) {
@@ -104,6 +110,21 @@ __global__ void __launch_bounds__(GS_THREADS) gs_kernel(const Tile* __restrict__
 #pragma unroll
     for (int q = 0; q < GS_PER_THREAD; ++q)
       if (ok[q]) v[idx[g[q]]] = T(0);
+  } else if constexpr (PERCOPY) {
+    if (m > GS_PERCOPY_MAXM) return;  // rejected on the host
+#pragma unroll
+    for (int q = 0; q < GS_PER_THREAD; ++q)
+      if (ok[q]) {
+        const gptr<const int> gi = idx + (int64_t)g[q] * m;
+        T a[GS_PERCOPY_MAXM];
+        for (int k = 0; k < m; ++k) a[k] = v[gi[k]];
+        for (int k = 0; k < m; ++k) {
+          ACC sum = (ACC)a[k];
+          for (int j = k + 1; j < m; ++j) sum += (ACC)a[j];
+          for (int j = 0; j < k; ++j) sum += (ACC)a[j];
+          v[gi[k]] = (T)sum;
+        }
+      }
   } else if (m == 2) {
     gi2_t ix[GS_PER_THREAD];
     T a0[GS_PER_THREAD], a1[GS_PER_THREAD];
@@ -225,10 +246,10 @@ __device__ inline uchar4 ld_u8x4_nt(const uint8_t* src) {
 // Each thread handles UPD_PER_THREAD entries as 4-wide vectors when the
 // problem's entry count is a multiple of 4, else one by one (decided per
 // problem, so a problem is reduced the same way alone or in a batch).
-template <typename T, typename ACC, int PC>
+template <typename T, int DM, int PC>
 __global__ void __launch_bounds__(UPD_THREADS) update_kernel(const Tile* __restrict__ tiles,
                                                              const ProbDev* __restrict__ probs) {
-  __shared__ ACC sred[16];
+  __shared__ double sred[16];
   const Tile t = tiles[blockIdx.x];
   const ProbDev& P = probs[t.prob];
   if (gcast(P.st)->done) return;
@@ -240,7 +261,7 @@ __global__ void __launch_bounds__(UPD_THREADS) update_kernel(const Tile* __restr
   const gptr<const T> __restrict__ w = gcast((const T*)P.w);
   const gptr<const T> __restrict__ dinv = gcast((const T*)P.dinv);
   const gptr<const uint8_t> __restrict__ mult = gcast(P.mult);
-  ACC rz = ACC(0), rr = ACC(0);
+  DotAcc<DM> rz, rr;
   if ((P.nloc & 3) == 0) {
     typedef typename V4<T>::type VT;
 #pragma unroll
@@ -254,12 +275,12 @@ __global__ void __launch_bounds__(UPD_THREADS) update_kernel(const Tile* __restr
         rv.x -= alpha * wv.x; rv.y -= alpha * wv.y; rv.z -= alpha * wv.z; rv.w -= alpha * wv.w;
         st4_nt<VT>((T*)&((VT*)x)[v], xv);
         st4_nt<VT>((T*)&((VT*)r)[v], rv);
-        const ACC c0 = (ACC)cweight(mv.x), c1 = (ACC)cweight(mv.y), c2 = (ACC)cweight(mv.z),
-                  c3 = (ACC)cweight(mv.w);
-        rr += (ACC)rv.x * c0 * (ACC)rv.x;
-        rr += (ACC)rv.y * c1 * (ACC)rv.y;
-        rr += (ACC)rv.z * c2 * (ACC)rv.z;
-        rr += (ACC)rv.w * c3 * (ACC)rv.w;
+        const double c0 = cweight(mv.x), c1 = cweight(mv.y), c2 = cweight(mv.z),
+                     c3 = cweight(mv.w);
+        rr.addw(rv.x, c0, rv.x);
+        rr.addw(rv.y, c1, rv.y);
+        rr.addw(rv.z, c2, rv.z);
+        rr.addw(rv.w, c3, rv.w);
         if constexpr (PC >= 0) {
           VT zv = rv;
           if constexpr (PC == 1) {
@@ -267,10 +288,10 @@ __global__ void __launch_bounds__(UPD_THREADS) update_kernel(const Tile* __restr
             zv.x = dv.x * rv.x; zv.y = dv.y * rv.y; zv.z = dv.z * rv.z; zv.w = dv.w * rv.w;
           }
           ((VT*)z)[v] = zv;
-          rz += (ACC)rv.x * c0 * (ACC)zv.x;
-          rz += (ACC)rv.y * c1 * (ACC)zv.y;
-          rz += (ACC)rv.z * c2 * (ACC)zv.z;
-          rz += (ACC)rv.w * c3 * (ACC)zv.w;
+          rz.addw(rv.x, c0, zv.x);
+          rz.addw(rv.y, c1, zv.y);
+          rz.addw(rv.z, c2, zv.z);
+          rz.addw(rv.w, c3, zv.w);
         }
       }
     }
@@ -283,31 +304,31 @@ __global__ void __launch_bounds__(UPD_THREADS) update_kernel(const Tile* __restr
         const T rv = r[i] - alpha * w[i];
         x[i] = xv;
         r[i] = rv;
-        const ACC c = (ACC)cweight(mult[i]);
-        rr += (ACC)rv * c * (ACC)rv;
+        const double c = cweight(mult[i]);
+        rr.addw(rv, c, rv);
         if constexpr (PC >= 0) {
           const T zv = (PC == 1) ? dinv[i] * rv : rv;
           z[i] = zv;
-          rz += (ACC)rv * c * (ACC)zv;
+          rz.addw(rv, c, zv);
         }
       }
     }
   }
-  ACC s0 = block_sum(rz, sred);
-  ACC s1 = block_sum(rr, sred);
+  const double s0 = rz.block(sred);
+  const double s1 = rr.block(sred);
   if (threadIdx.x == 0) {
     const int b = t.first / UPD_CHUNK;
-    gcast(P.part_u0)[b] = (double)s0;
-    gcast(P.part_u1)[b] = (double)s1;
+    gcast(P.part_u0)[b] = s0;
+    gcast(P.part_u1)[b] = s1;
   }
 }
 
 // start of a solve: r = rhs64 * scale (cast to T), x = x0 or 0, p = 0,
 // z = M^-1 r, partials (r,z)_c and (r,r)_c
-template <typename T, typename ACC, int PC>
+template <typename T, int DM, int PC>
 __global__ void init_kernel(const Tile* __restrict__ tiles, const ProbDev* __restrict__ probs,
                             const double* __restrict__ x0) {
-  __shared__ ACC sred[16];
+  __shared__ double sred[16];
   const Tile t = tiles[blockIdx.x];
   const ProbDev& P = probs[t.prob];
   if (gcast(P.st)->done) return;
@@ -317,7 +338,7 @@ __global__ void init_kernel(const Tile* __restrict__ tiles, const ProbDev* __res
   gptr<T> __restrict__ p = gcast((T*)P.p);
   const gptr<const T> __restrict__ dinv = gcast((const T*)P.dinv);
   const double scale = P.rhs_scale;
-  ACC rz = ACC(0), rr = ACC(0);
+  DotAcc<DM> rz, rr;
 #pragma unroll
   for (int q = 0; q < UPD_PER_THREAD; ++q) {
     const int64_t i = (int64_t)t.first + q * UPD_THREADS + threadIdx.x;
@@ -326,21 +347,21 @@ __global__ void init_kernel(const Tile* __restrict__ tiles, const ProbDev* __res
       r[i] = rv;
       x[i] = x0 ? (T)x0[i] : T(0);
       p[i] = T(0);
-      const ACC c = (ACC)cweight(gcast(P.mult)[i]);
-      rr += (ACC)rv * c * (ACC)rv;
+      const double c = cweight(gcast(P.mult)[i]);
+      rr.addw(rv, c, rv);
       if constexpr (PC >= 0) {
         const T zv = (PC == 1) ? dinv[i] * rv : rv;
         z[i] = zv;
-        rz += (ACC)rv * c * (ACC)zv;
+        rz.addw(rv, c, zv);
       }
     }
   }
-  ACC s0 = block_sum(rz, sred);
-  ACC s1 = block_sum(rr, sred);
+  const double s0 = rz.block(sred);
+  const double s1 = rr.block(sred);
   if (threadIdx.x == 0) {
     const int b = t.first / UPD_CHUNK;
-    gcast(P.part_u0)[b] = (double)s0;
-    gcast(P.part_u1)[b] = (double)s1;
+    gcast(P.part_u0)[b] = s0;
+    gcast(P.part_u1)[b] = s1;
   }
 }
 
@@ -370,7 +391,9 @@ __device__ inline double fixed_sum(const gptr<const double> __restrict__ parts, 
 __device__ inline void fin_sigma_step(const ProbDev& P, double* sred) {
   const gptr<State> st = gcast(P.st);
   if (st->done) return;
-  const double sigma = fixed_sum<GS_THREADS>(gcast((const double*)P.part_ax), P.nblk_ax, sred);
+  const gptr<const double> pa = gcast((const double*)P.part_ax);
+  const double sigma = P.dm == DOT_F64 ? fixed_sum<GS_THREADS>(pa, P.nblk_ax, sred)
+                                       : dot_finish<GS_THREADS>(P.dm, pa, P.nblk_ax, sred);
   if (threadIdx.x == 0) {
     st->sigma = sigma;
     if (!(sigma > 0.0) || !isfinite(sigma)) {
@@ -422,8 +445,16 @@ __global__ void fin_rho_kernel(const ProbDev* __restrict__ probs, int mode) {
   const ProbDev& P = probs[blockIdx.x];
   const gptr<State> st = gcast(P.st);
   if (st->done) return;
-  double rz = fixed_sum<FIN_THREADS>(gcast((const double*)P.part_u0), P.nblk_upd, sred);
-  double rr = fixed_sum<FIN_THREADS>(gcast((const double*)P.part_u1), P.nblk_upd, sred);
+  const gptr<const double> p0 = gcast((const double*)P.part_u0);
+  const gptr<const double> p1 = gcast((const double*)P.part_u1);
+  double rz, rr;
+  if (P.dm == DOT_F64) {
+    rz = fixed_sum<FIN_THREADS>(p0, P.nblk_upd, sred);
+    rr = fixed_sum<FIN_THREADS>(p1, P.nblk_upd, sred);
+  } else {
+    rz = dot_finish<FIN_THREADS>(P.dm, p0, P.nblk_upd, sred);
+    rr = dot_finish<FIN_THREADS>(P.dm, p1, P.nblk_upd, sred);
+  }
   if (threadIdx.x != 0) return;
   st->rr = rr;
   if (mode == 1 || mode == 3) {
@@ -533,23 +564,25 @@ __global__ void fin_beta_kernel(const ProbDev* __restrict__ probs, int init,
 }
 
 // ------------------------------------------------------------ API kernels
-template <typename T>
+template <typename T, int DM>
 __global__ void dot_kernel(const T* __restrict__ a, const T* __restrict__ b,
                            const uint8_t* __restrict__ mult, int64_t n, double* __restrict__ part) {
   __shared__ double sred[16];
-  double s = 0.0;
+  DotAcc<DM> s;
 #pragma unroll
   for (int q = 0; q < UPD_PER_THREAD; ++q) {
     const int64_t i = (int64_t)blockIdx.x * UPD_CHUNK + q * UPD_THREADS + threadIdx.x;
-    if (i < n) s += (double)a[i] * cweight(mult[i]) * (double)b[i];
+    if (i < n) s.addw(a[i], cweight(mult[i]), b[i]);
   }
-  double t = block_sum(s, sred);
+  const double t = s.block(sred);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-__global__ void final_sum_kernel(const double* __restrict__ part, int n, double* __restrict__ out) {
+__global__ void final_sum_kernel(const double* __restrict__ part, int n, double* __restrict__ out,
+                                 int dm) {
   __shared__ double sred[16];
-  double s = fixed_sum<FIN_THREADS>(gcast(part), n, sred);
+  const double s = dm == DOT_F64 ? fixed_sum<FIN_THREADS>(gcast(part), n, sred)
+                                 : dot_finish<FIN_THREADS>(dm, gcast(part), n, sred);
   if (threadIdx.x == 0) *out = s;
 }
 
@@ -651,7 +684,7 @@ static inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1
 // API gather-scatter: free buckets, then either the Dirichlet-group
 // buckets (no mask) or the mask list.  io/acc: MXSEM_F64 / MXSEM_F32.
 hipError_t launch_gs_apply(int prec_io, int prec_acc, void* v, const GsPlan& plan, bool mask,
-                           hipStream_t s) {
+                           hipStream_t s, bool percopy) {
   const int last = mask ? plan.nfree : plan.nall;
   for (int bkt = 0; bkt <= plan.nall; ++bkt) {
     if (bkt >= last && !(mask && bkt == plan.nall)) continue;
@@ -659,7 +692,13 @@ hipError_t launch_gs_apply(int prec_io, int prec_acc, void* v, const GsPlan& pla
     if (ng == 0) continue;
     GsApi a{v, plan, bkt, 0};
     dim3 g(nblk(ng, GS_CHUNK)), b(GS_THREADS);
-    if (prec_io == MXSEM_F64 && prec_acc == MXSEM_F64)
+    if (percopy) {
+      if (prec_io != MXSEM_F32) return hipErrorInvalidValue;
+      if (prec_acc == MXSEM_F64)
+        hipLaunchKernelGGL((gs_kernel<float, double, false, true>), g, b, 0, s, nullptr, nullptr, a);
+      else
+        hipLaunchKernelGGL((gs_kernel<float, float, false, true>), g, b, 0, s, nullptr, nullptr, a);
+    } else if (prec_io == MXSEM_F64 && prec_acc == MXSEM_F64)
       hipLaunchKernelGGL((gs_kernel<double, double, false>), g, b, 0, s, nullptr, nullptr, a);
     else if (prec_io == MXSEM_F64 && prec_acc == MXSEM_F32)
       hipLaunchKernelGGL((gs_kernel<double, float, false>), g, b, 0, s, nullptr, nullptr, a);
@@ -677,7 +716,8 @@ hipError_t launch_gs_apply(int prec_io, int prec_acc, void* v, const GsPlan& pla
 
 // vector precision: 0 FP64, 1 FP32 (FP64 accumulation), 3 FP32 (FP32 accumulation)
 hipError_t launch_gs_solver(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs,
-                            hipStream_t s, bool on_z, int sigma_probs, const Tile* ztiles, int nz) {
+                            hipStream_t s, bool on_z, int sigma_probs, const Tile* ztiles, int nz,
+                            bool percopy) {
   static_assert(GS_THREADS == UPD_THREADS, "the Jacobi-z workgroups use the vector-pass tiles");
   const int nfin = ((sigma_probs + XCDS - 1) / XCDS) * XCDS;
   if (ntiles + nfin + nz == 0) return hipSuccess;
@@ -688,7 +728,12 @@ hipError_t launch_gs_solver(int vprec, const Tile* tiles, int ntiles, const Prob
   a.nprob = sigma_probs;
   a.ztiles = ztiles;
   a.nz = ztiles ? nz : 0;
-  if (vprec == 0)
+  if (percopy && (vprec == 0 || on_z || nz)) return hipErrorInvalidValue;
+  if (percopy && vprec == 1)
+    hipLaunchKernelGGL((gs_kernel<float, double, true, true>), g, b, 0, s, tiles, probs, a);
+  else if (percopy)
+    hipLaunchKernelGGL((gs_kernel<float, float, true, true>), g, b, 0, s, tiles, probs, a);
+  else if (vprec == 0)
     hipLaunchKernelGGL((gs_kernel<double, double, true>), g, b, 0, s, tiles, probs, a);
   else if (vprec == 1)
     hipLaunchKernelGGL((gs_kernel<float, double, true>), g, b, 0, s, tiles, probs, a);
@@ -697,43 +742,50 @@ hipError_t launch_gs_solver(int vprec, const Tile* tiles, int ntiles, const Prob
   return hipGetLastError();
 }
 
-template <typename T, typename ACC>
+template <typename T, int DM>
 static void upd_dispatch(int pc, dim3 g, dim3 b, hipStream_t s, const Tile* tiles,
                          const ProbDev* probs) {
   if (pc == MXSEM_PC_JACOBI)
-    hipLaunchKernelGGL((update_kernel<T, ACC, 1>), g, b, 0, s, tiles, probs);
+    hipLaunchKernelGGL((update_kernel<T, DM, 1>), g, b, 0, s, tiles, probs);
   else if (pc == MXSEM_PC_IDENTITY)
-    hipLaunchKernelGGL((update_kernel<T, ACC, 0>), g, b, 0, s, tiles, probs);
+    hipLaunchKernelGGL((update_kernel<T, DM, 0>), g, b, 0, s, tiles, probs);
   else
-    hipLaunchKernelGGL((update_kernel<T, ACC, -1>), g, b, 0, s, tiles, probs);
+    hipLaunchKernelGGL((update_kernel<T, DM, -1>), g, b, 0, s, tiles, probs);
 }
 
+// dm: DotMode of the dots (FP64 vectors: DOT_F64 only)
 hipError_t launch_update(int vprec, int pc, const Tile* tiles, int ntiles, const ProbDev* probs,
-                         hipStream_t s) {
+                         hipStream_t s, int dm) {
   dim3 g(ntiles), b(UPD_THREADS);
-  if (vprec == 0) upd_dispatch<double, double>(pc, g, b, s, tiles, probs);
-  else if (vprec == 1) upd_dispatch<float, double>(pc, g, b, s, tiles, probs);
-  else upd_dispatch<float, float>(pc, g, b, s, tiles, probs);
+  if (vprec == 0 && dm != DOT_F64) return hipErrorInvalidValue;
+  if (vprec == 0) upd_dispatch<double, DOT_F64>(pc, g, b, s, tiles, probs);
+  else if (dm == DOT_F64) upd_dispatch<float, DOT_F64>(pc, g, b, s, tiles, probs);
+  else if (dm == DOT_F32) upd_dispatch<float, DOT_F32>(pc, g, b, s, tiles, probs);
+  else if (dm == DOT_DOT2) upd_dispatch<float, DOT_DOT2>(pc, g, b, s, tiles, probs);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-template <typename T, typename ACC>
+template <typename T, int DM>
 static void init_dispatch(int pc, dim3 g, dim3 b, hipStream_t s, const Tile* tiles,
                           const ProbDev* probs, const double* x0) {
   if (pc == MXSEM_PC_JACOBI)
-    hipLaunchKernelGGL((init_kernel<T, ACC, 1>), g, b, 0, s, tiles, probs, x0);
+    hipLaunchKernelGGL((init_kernel<T, DM, 1>), g, b, 0, s, tiles, probs, x0);
   else if (pc == MXSEM_PC_IDENTITY)
-    hipLaunchKernelGGL((init_kernel<T, ACC, 0>), g, b, 0, s, tiles, probs, x0);
+    hipLaunchKernelGGL((init_kernel<T, DM, 0>), g, b, 0, s, tiles, probs, x0);
   else
-    hipLaunchKernelGGL((init_kernel<T, ACC, -1>), g, b, 0, s, tiles, probs, x0);
+    hipLaunchKernelGGL((init_kernel<T, DM, -1>), g, b, 0, s, tiles, probs, x0);
 }
 
 hipError_t launch_init(int vprec, int pc, const Tile* tiles, int ntiles, const ProbDev* probs,
-                       const double* x0, hipStream_t s) {
+                       const double* x0, hipStream_t s, int dm) {
   dim3 g(ntiles), b(UPD_THREADS);
-  if (vprec == 0) init_dispatch<double, double>(pc, g, b, s, tiles, probs, x0);
-  else if (vprec == 1) init_dispatch<float, double>(pc, g, b, s, tiles, probs, x0);
-  else init_dispatch<float, float>(pc, g, b, s, tiles, probs, x0);
+  if (vprec == 0 && dm != DOT_F64) return hipErrorInvalidValue;
+  if (vprec == 0) init_dispatch<double, DOT_F64>(pc, g, b, s, tiles, probs, x0);
+  else if (dm == DOT_F64) init_dispatch<float, DOT_F64>(pc, g, b, s, tiles, probs, x0);
+  else if (dm == DOT_F32) init_dispatch<float, DOT_F32>(pc, g, b, s, tiles, probs, x0);
+  else if (dm == DOT_DOT2) init_dispatch<float, DOT_DOT2>(pc, g, b, s, tiles, probs, x0);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -774,16 +826,27 @@ hipError_t launch_fin_beta(const ProbDev* probs, int nprob, int init, hipStream_
   return hipGetLastError();
 }
 
+// dm: DotMode (FP64 inputs: DOT_F64 only)
 hipError_t launch_dot(int prec, const void* a, const void* b, const uint8_t* mult, int64_t n,
-                      double* part, double* out, hipStream_t s) {
+                      double* part, double* out, hipStream_t s, int dm) {
   const unsigned nb = nblk(n, UPD_CHUNK);
-  if (prec == MXSEM_F64)
-    hipLaunchKernelGGL((dot_kernel<double>), dim3(nb), dim3(UPD_THREADS), 0, s, (const double*)a,
+  dim3 g(nb), t(UPD_THREADS);
+  const float* af = (const float*)a;
+  const float* bf = (const float*)b;
+  if (prec == MXSEM_F64 && dm == DOT_F64)
+    hipLaunchKernelGGL((dot_kernel<double, DOT_F64>), g, t, 0, s, (const double*)a,
                        (const double*)b, mult, n, part);
+  else if (prec == MXSEM_F64)
+    return hipErrorInvalidValue;
+  else if (dm == DOT_F64)
+    hipLaunchKernelGGL((dot_kernel<float, DOT_F64>), g, t, 0, s, af, bf, mult, n, part);
+  else if (dm == DOT_F32)
+    hipLaunchKernelGGL((dot_kernel<float, DOT_F32>), g, t, 0, s, af, bf, mult, n, part);
+  else if (dm == DOT_DOT2)
+    hipLaunchKernelGGL((dot_kernel<float, DOT_DOT2>), g, t, 0, s, af, bf, mult, n, part);
   else
-    hipLaunchKernelGGL((dot_kernel<float>), dim3(nb), dim3(UPD_THREADS), 0, s, (const float*)a,
-                       (const float*)b, mult, n, part);
-  hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(FIN_THREADS), 0, s, part, (int)nb, out);
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(FIN_THREADS), 0, s, part, (int)nb, out, dm);
   return hipGetLastError();
 }
 
@@ -803,7 +866,8 @@ hipError_t launch_residual(const double* b, const double* w, double* r, const ui
                            int64_t n, double* part, double* out, hipStream_t s) {
   const unsigned nb = nblk(n, UPD_CHUNK);
   hipLaunchKernelGGL(residual_kernel, dim3(nb), dim3(UPD_THREADS), 0, s, b, w, r, mult, n, part);
-  hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(FIN_THREADS), 0, s, part, (int)nb, out);
+  hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(FIN_THREADS), 0, s, part, (int)nb, out,
+                     (int)DOT_F64);
   return hipGetLastError();
 }
 

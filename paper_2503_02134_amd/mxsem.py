@@ -32,7 +32,10 @@ PC_IDENTITY, PC_JACOBI, PC_LEARNED = 0, 1, 2
 MODE_FP64, MODE_MIXED, MODE_MIXED_IR, MODE_MIXED_IR_BF16G, MODE_FP32_ALL = 0, 1, 2, 3, 4
 METHOD_PCG, METHOD_FCG = 0, 1
 CONVERGED, MAX_ITER, STAGNATED, BREAKDOWN = 1, 2, 3, 4
-LOCAL_ONLY, MASK = 1, 2
+LOCAL_ONLY, MASK, GS_PER_COPY = 1, 2, 4
+# dot accumulation of the FP32 loop, and gather-scatter order
+DOT_DEFAULT, DOT_F64, DOT_F32, DOT_DOT2 = 0, 1, 2, 3
+GS_ORDER_ONE, GS_ORDER_PER_COPY = 0, 1
 VIEW_F64, VIEW_F32, VIEW_BF16 = 1, 2, 4
 
 MODE_NAMES = {MODE_FP64: "fp64", MODE_MIXED: "mixed", MODE_MIXED_IR: "mixed_ir",
@@ -54,7 +57,8 @@ class mxsem_mesh_desc(C.Structure):
 class mxsem_solve_opts(C.Structure):
     _fields_ = [("method", C.c_int), ("pc", C.c_int), ("mode", C.c_int), ("tol", C.c_double),
                 ("max_iter", C.c_int), ("inner_tol", C.c_double), ("max_outer", C.c_int),
-                ("graph_chunk", C.c_int), ("x0_given", C.c_int), ("history", C.c_void_p)]
+                ("graph_chunk", C.c_int), ("x0_given", C.c_int), ("history", C.c_void_p),
+                ("dot", C.c_int), ("gs_order", C.c_int)]
 
 
 class mxsem_solve_stats(C.Structure):
@@ -91,6 +95,7 @@ _SIGS = {
     "mxsem_apply": [vp, C.c_int, vp, vp, C.c_uint],
     "mxsem_gather_scatter": [vp, C.c_int, C.c_int, vp, C.c_uint],
     "mxsem_dot": [vp, C.c_int, vp, vp, vp],
+    "mxsem_dot_ex": [vp, C.c_int, C.c_int, vp, vp, vp],
     "mxsem_precond": [vp, C.c_int, C.c_int, vp, vp],
     "mxsem_mass_rhs": [vp, vp, vp],
     "mxsem_solve": [vp, C.POINTER(mxsem_solve_opts), vp, vp, C.POINTER(mxsem_solve_stats)],
@@ -215,6 +220,10 @@ def mxsem_gather_scatter(mesh, io, acc, v, flags=0):
 
 def mxsem_dot(mesh, io, a, b, out_dev):
     _check("mxsem_dot", lib().mxsem_dot(mesh, io, _ptr(a), _ptr(b), _ptr(out_dev)))
+
+
+def mxsem_dot_ex(mesh, io, acc, a, b, out_dev):
+    _check("mxsem_dot_ex", lib().mxsem_dot_ex(mesh, io, acc, _ptr(a), _ptr(b), _ptr(out_dev)))
 
 
 def mxsem_precond(mesh, pc, io, r, z):
@@ -430,15 +439,20 @@ class Mesh:
         mxsem_apply(self.h, prec, u, w, LOCAL_ONLY if local_only else 0)
         return w
 
-    def gs(self, v, acc=F64, mask=False):
+    def gs(self, v, acc=F64, mask=False, per_copy=False):
         v = v.clone()
         io = F64 if v.dtype == torch.float64 else F32
-        mxsem_gather_scatter(self.h, io, acc, v, MASK if mask else 0)
+        flags = (MASK if mask else 0) | (GS_PER_COPY if per_copy else 0)
+        mxsem_gather_scatter(self.h, io, acc, v, flags)
         return v
 
-    def dot(self, a, b) -> float:
+    def dot(self, a, b, acc=DOT_DEFAULT) -> float:
         out = torch.zeros(1, dtype=torch.float64, device=self.dev)
-        mxsem_dot(self.h, F64 if a.dtype == torch.float64 else F32, a, b, out)
+        io = F64 if a.dtype == torch.float64 else F32
+        if acc == DOT_DEFAULT:
+            mxsem_dot(self.h, io, a, b, out)
+        else:
+            mxsem_dot_ex(self.h, io, acc, a, b, out)
         return float(out.item())
 
     def precond(self, r, pc=PC_JACOBI):

@@ -192,7 +192,7 @@ def he_normal_weights(seed: int, ch: int = 32, cin: int = 2):
 
 
 # --------------------------------------------------------------------------
-# The five workloads (unit cube, homogeneous Dirichlet on the whole boundary)
+# The workloads (unit cube, homogeneous Dirichlet on the whole boundary)
 # --------------------------------------------------------------------------
 @dataclass(frozen=True)
 class Workload:
@@ -223,6 +223,10 @@ WORKLOADS = {
     "box24_N7_lognormal_helmholtz": Workload("box24_N7_lognormal_helmholtz", 24, 7, None,
                                              1e-10, 10000, rhs="random", rhs_seed=5900,
                                              k_seed=5, helm_h=1.0),
+    # undeformed cube Poisson problem of 8000 elements, N = 7, to 1e-9: the
+    # size and tolerance of the cube Poisson runs of the Neko evaluation
+    # (8192 elements there), for the mixed-precision strategy table
+    "box20_N7": Workload("box20_N7", 20, 7, None, 1e-9, 10000),
 }
 
 
