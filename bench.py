@@ -47,6 +47,8 @@ def main():
                          "box24_N7_lognormal_helmholtz | box20_N7 | batch64")
     ap.add_argument("--mode", default="mixed_ir", choices=["mixed_ir", "mixed_ir_bf16g", "fp64",
                                                            "mixed", "learned", "strategies"])
+    ap.add_argument("--dot", default="fp64", choices=["fp64", "fp32", "dot2"],
+                    help="accumulation of the FP32 loop's dots (mixed / mixed_ir modes)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=200)
     ap.add_argument("--traffic-probe", action="store_true",
@@ -95,6 +97,8 @@ def main():
     b = mesh.mass_rhs(torch.as_tensor(f, device="cuda"))
     x = torch.zeros_like(b)
     opts = dict(mode=mode, tol=wl.tol, max_iter=20000, graph_chunk=16)
+    if args.dot != "fp64":
+        opts["dot"] = {"fp32": mx.DOT_F32, "dot2": mx.DOT_DOT2}[args.dot]
     if args.traffic_probe:
         return traffic_probe(mesh, b, mode)
 
@@ -180,11 +184,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (f64 gather-scatter sums, dots, refinement residuals)"
-        if mode != mx.MODE_FP64 else "f64",
+        "dtype": ("f64" if mode == mx.MODE_FP64 else
+                  "f32 (f64 gather-scatter sums, dots, refinement residuals)" if args.dot == "fp64"
+                  else f"f32 (f64 gather-scatter sums and refinement residuals, {args.dot} dots)"),
         "data": "synthetic",
         "config": {"workload": wl.name, "E": bm.E, "N": wl.N, "nloc": nloc,
-                   "mode": args.mode, "pc": "jacobi", "tol": wl.tol,
+                   "mode": args.mode, "pc": "jacobi", "dot": args.dot, "tol": wl.tol,
                    "iterations_per_step": iters / args.steps},
         "roofline": {"bound": "hbm", "kernel": "ax_kernel (fused p-update + local operator)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -462,7 +467,7 @@ def bench_strategies(args):
     ctx = mx.Context(0)
     xi, _ = mx.mxsem_gll(wl.N)
     bm = W.box_mesh(wl.ne, wl.N, xi, seed=wl.deform_seed)
-    f, _ = W.manufactured(bm)
+    f = W.manufactured(bm)[0] if wl.rhs == "manufactured" else W.random_smooth_rhs(bm, wl.rhs_seed)
     mesh = mx.Mesh(ctx, bm.E, wl.N, bm.xyz, bm.glo, bm.bnd)
     nloc = mesh.nloc
     b = mesh.mass_rhs(torch.as_tensor(f, device="cuda"))

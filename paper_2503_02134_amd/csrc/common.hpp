@@ -244,6 +244,17 @@ __device__ inline void two_prod(float a, float b, float& p, float& e) {
 struct F2 {
   float s, c;  // running sum and its correction
 };
+// An F2 travels through one double slot (partial-sum arrays, LDS) as the
+// bits of a two-float vector: register moves only.
+typedef float f2v_t __attribute__((ext_vector_type(2)));
+__device__ inline double f2_pack(F2 v) {
+  const f2v_t t = {v.s, v.c};
+  return __builtin_bit_cast(double, t);
+}
+__device__ inline F2 f2_unpack(double d) {
+  const f2v_t t = __builtin_bit_cast(f2v_t, d);
+  return F2{t.x, t.y};
+}
 __device__ inline F2 f2_combine(F2 a, F2 b) {
 #pragma clang fp contract(off)
   F2 r;
@@ -303,32 +314,50 @@ struct DotAcc<DOT_DOT2> {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int nw = (blockDim.x + 63) >> 6;
     __syncthreads();
-    if (lane == 0) sred[wid] = __builtin_bit_cast(double, x);
+    if (lane == 0) sred[wid] = f2_pack(x);
     __syncthreads();
     F2 t = {0.f, 0.f};
     if (threadIdx.x == 0)
-      for (int q = 0; q < nw; ++q) t = f2_combine(t, __builtin_bit_cast(F2, sred[q]));
-    return __builtin_bit_cast(double, t);
+      for (int q = 0; q < nw; ++q) t = f2_combine(t, f2_unpack(sred[q]));
+    return f2_pack(t);
   }
 };
 
-// Sum of n workgroup partials of mode dm by one workgroup of NT threads in a
-// fixed order (thread t takes parts t, t + NT, ...; then the block); the
-// FP32 modes return an FP32 value.
+// Sum of n workgroup partials of mode dm (DOT_F32 or DOT_DOT2) by one
+// workgroup of NT threads in a fixed order: thread t combines parts
+// t + k NT into accumulator k % 8 (eight independent chains keep eight loads
+// in flight), then the eight accumulators pairwise, then the block.  The
+// result is an FP32 value.
 template <int NT>
 __device__ inline double dot_finish(int dm, const gptr<const double> __restrict__ parts, int n,
                                     double* sred) {
+  int q = threadIdx.x;
   if (dm == DOT_F32) {
-    float a = 0.f;
-    for (int q = threadIdx.x; q < n; q += NT) a += (float)parts[q];
-    return (double)block_sum(a, (float*)sred);
+    float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (; q + 7 * NT < n; q += 8 * NT) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) a[k] += (float)parts[q + k * NT];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (q + k * NT < n) a[k] += (float)parts[q + k * NT];
+    const float s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    return (double)block_sum(s, (float*)sred);
   }
-  // DOT_DOT2
-  F2 a = {0.f, 0.f};
-  for (int q = threadIdx.x; q < n; q += NT) a = f2_combine(a, __builtin_bit_cast(F2, parts[q]));
+  F2 a[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) a[k] = F2{0.f, 0.f};
+  for (; q + 7 * NT < n; q += 8 * NT) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = f2_combine(a[k], f2_unpack(parts[q + k * NT]));
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (q + k * NT < n) a[k] = f2_combine(a[k], f2_unpack(parts[q + k * NT]));
   DotAcc<DOT_DOT2> acc;
-  acc.v = a;
-  const F2 t = __builtin_bit_cast(F2, acc.block(sred));
+  acc.v = f2_combine(f2_combine(f2_combine(a[0], a[1]), f2_combine(a[2], a[3])),
+                     f2_combine(f2_combine(a[4], a[5]), f2_combine(a[6], a[7])));
+  const F2 t = f2_unpack(acc.block(sred));
   return (double)(t.s + t.c);
 }
 

@@ -225,8 +225,9 @@ WORKLOADS = {
                                              k_seed=5, helm_h=1.0),
     # undeformed cube Poisson problem of 8000 elements, N = 7, to 1e-9: the
     # size and tolerance of the cube Poisson runs of the Neko evaluation
-    # (8192 elements there), for the mixed-precision strategy table
-    "box20_N7": Workload("box20_N7", 20, 7, None, 1e-9, 10000),
+    # (8192 elements there), for the mixed-precision strategy table; a
+    # random smooth source, so that CG has many modes to resolve in FP64 too
+    "box20_N7": Workload("box20_N7", 20, 7, None, 1e-9, 10000, rhs="random", rhs_seed=20),
 }
 
 
