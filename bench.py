@@ -7,7 +7,8 @@ refinement loop).  value = local dofs x (inner + outer iterations) per
 second over the timed steps.  Inputs are resident in HBM before timing.
 
 Beside it: the FP64 solve on the same GPU, the same refinement with BF16
-geometric factors, time-to-1e-8, the roofline of the dominant kernel (the
+geometric factors, time-to-1e-8, energy-to-solution (the GPU package's energy
+counter around repeated FP64 and mixed solves), the roofline of the dominant kernel (the
 fused operator kernel of the inner loop: the first operator launch of every
 graph chunk records its own start and end events on the solve's stream),
 a measured copy-kernel ceiling, and the FP64 CPU oracle timed on a bounded
@@ -165,13 +166,35 @@ def main():
             "ax_us": round(sb.ax_ms * 1e3, 2),
             "ax_gbs": round(nloc * bb / (sb.ax_ms * 1e-3) / 1e9, 1) if sb.ax_ms > 0 else None}
     tt = {}
-    for name, md in (("fp64", mx.MODE_FP64), (args.mode, mode)):
+    opts64 = dict(mode=mx.MODE_FP64, tol=wl.tol, max_iter=20000, graph_chunk=16)
+    for name, kw in (("fp64", opts64), (args.mode, opts)):
         xt = torch.zeros_like(b)
-        _, st8 = mesh.solve(b, xt, mode=md, tol=1e-8, max_iter=20000, graph_chunk=16)
+        _, st8 = mesh.solve(b, xt, **dict(kw, tol=1e-8))
         tt[name] = {"ms": round(st8.ms, 3), "iterations": st8.iterations, "outer": st8.outer,
                     "rel_res": st8.rel_res}
     extra["time_to_1e-8"] = tt
     log(f"fp64: {extra['fp64']}; tt1e-8: {tt}")
+
+    # energy to solution: the GPU package's energy counter around repeated solves
+    read, why = energy_counter()
+    if read is None:
+        extra["energy_to_solution"] = {"unavailable": why}
+    else:
+        en = {}
+        for name, kw, reps in (("fp64", opts64, 3), (args.mode, opts, 6)):
+            torch.cuda.synchronize()
+            j0, t0e = read()
+            for _ in range(reps):
+                x.zero_()
+                mesh.solve(b, x, **kw)
+            torch.cuda.synchronize()
+            j1, t1e = read()
+            en[name] = {"joules_per_solve": round((j1 - j0) / reps, 2),
+                        "avg_watts": round((j1 - j0) / (t1e - t0e), 1), "solves": reps}
+        en["gain"] = round(en["fp64"]["joules_per_solve"] / en[args.mode]["joules_per_solve"], 3)
+        en["counter"] = "amdsmi package energy accumulator (whole GPU, idle power included)"
+        extra["energy_to_solution"] = en
+        log(f"energy: {en}")
 
     out = {
         "metric": "GDOF*iter/s (local dofs x iterations / s) of the SEM PCG solve",
@@ -208,6 +231,37 @@ def main():
     print(json.dumps(out), flush=True)
     mesh.close()
     ctx.close()
+
+
+def energy_counter():
+    """The package energy counter of the GPU that torch calls device 0, read
+    through amdsmi (matched by PCI bus).  Returns (read, None), read() ->
+    (joules, seconds), or (None, reason) when the counter cannot be read."""
+    try:
+        import amdsmi
+        import torch
+        amdsmi.amdsmi_init()
+        bus = getattr(torch.cuda.get_device_properties(0), "pci_bus_id", None)
+        handles = amdsmi.amdsmi_get_processor_handles()
+        h = None
+        for hh in handles:
+            bdf = amdsmi.amdsmi_get_gpu_device_bdf(hh)
+            if bus is not None and int(bdf.split(":")[1], 16) == int(bus):
+                h = hh
+        if h is None and len(handles) == 1:
+            h = handles[0]
+        if h is None:
+            return None, f"no amdsmi device on PCI bus {bus} among {len(handles)}"
+
+        def read():
+            d = amdsmi.amdsmi_get_energy_count(h)
+            return d["energy_accumulator"] * d["counter_resolution"] * 1e-6, time.perf_counter()
+
+        d = amdsmi.amdsmi_get_energy_count(h)
+        log(f"energy counter: {d}")
+        return read, None
+    except Exception as e:  # no amdsmi, no permission, no counter
+        return None, f"{type(e).__name__}: {e}"
 
 
 def copy_ceiling(nbytes):
