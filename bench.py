@@ -180,17 +180,34 @@ def main():
     if read is None:
         extra["energy_to_solution"] = {"unavailable": why}
     else:
+        # The accumulator and its timestamp advance in steps (about one
+        # second apart on this GPU): solves run back to back from one step
+        # of the counter to a later one at least 4 s on, so the window holds
+        # busy time only; the energy of a solve is the window's average power
+        # times the solve's own time.
         en = {}
-        for name, kw, reps in (("fp64", opts64, 3), (args.mode, opts, 6)):
-            torch.cuda.synchronize()
-            j0, t0e = read()
-            for _ in range(reps):
+        for name, kw in (("fp64", opts64), (args.mode, opts)):
+            def solve_once():
                 x.zero_()
-                mesh.solve(b, x, **kw)
-            torch.cuda.synchronize()
-            j1, t1e = read()
-            en[name] = {"joules_per_solve": round((j1 - j0) / reps, 2),
-                        "avg_watts": round((j1 - j0) / (t1e - t0e), 1), "solves": reps}
+                _, st_ = mesh.solve(b, x, **kw)
+                return st_.ms
+
+            _, ts, _ = read()
+            for _ in range(20):  # until the counter steps during a solve
+                solve_once()
+                ja, tsa, _ = read()
+                if tsa != ts:
+                    break
+            times = []
+            jb, tsb = ja, tsa
+            while tsb - tsa < 4.0 and len(times) < 200:
+                times.append(solve_once())
+                jb, tsb, _ = read()
+            watts = (jb - ja) / (tsb - tsa) if tsb > tsa else float("nan")
+            per_ms = sum(times) / len(times)
+            en[name] = {"joules_per_solve": round(watts * per_ms * 1e-3, 2),
+                        "avg_watts": round(watts, 1), "solve_ms": round(per_ms, 2),
+                        "solves": len(times), "counter_window_s": round(tsb - tsa, 3)}
         en["gain"] = round(en["fp64"]["joules_per_solve"] / en[args.mode]["joules_per_solve"], 3)
         en["counter"] = "amdsmi package energy accumulator (whole GPU, idle power included)"
         extra["energy_to_solution"] = en
@@ -236,7 +253,8 @@ def main():
 def energy_counter():
     """The package energy counter of the GPU that torch calls device 0, read
     through amdsmi (matched by PCI bus).  Returns (read, None), read() ->
-    (joules, seconds), or (None, reason) when the counter cannot be read."""
+    (joules, counter timestamp in s, host time in s), or (None, reason) when
+    the counter cannot be read."""
     try:
         import amdsmi
         import torch
@@ -255,7 +273,8 @@ def energy_counter():
 
         def read():
             d = amdsmi.amdsmi_get_energy_count(h)
-            return d["energy_accumulator"] * d["counter_resolution"] * 1e-6, time.perf_counter()
+            return (d["energy_accumulator"] * d["counter_resolution"] * 1e-6,
+                    d["timestamp"] * 1e-9, time.perf_counter())
 
         d = amdsmi.amdsmi_get_energy_count(h)
         log(f"energy counter: {d}")
