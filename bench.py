@@ -527,10 +527,11 @@ def bench_strategies(args):
     """The mixed-precision strategies of Sec. 4.2.1-4.2.2 on one GPU: the
     FP32 CG loop with the gather-scatter sums in FP32 or FP64, the dots in
     FP32, FP64 or compensated FP32 (Dot2), and the gather-scatter in one
-    order per node or in each copy's own order (the summation order of a
-    pairwise exchange between ranks, one copy per rank), with the identity
-    and the Jacobi preconditioner, to the workload's recursive tolerance;
-    FP64 CG beside.  value: local dofs x iterations / s over every solve of
+    order per node or in the summation order of a pairwise exchange between
+    ranks (every element a rank of its own), with the identity and the
+    Jacobi preconditioner, to the workload's recursive tolerance; FP64 CG
+    beside.  Then the rank-count study: the pairwise order with the elements
+    cut into 1 to 64 blocks of ranks, FP32 or FP64 gather-scatter sums.  value: local dofs x iterations / s over every solve of
     the table (the solves differ in cost only by their reductions)."""
     import torch
 
@@ -564,7 +565,8 @@ def bench_strategies(args):
         el += s6.ms
         for gname, mode in (("fp64", mx.MODE_MIXED), ("fp32", mx.MODE_FP32_ALL)):
             for dname, dot in (("fp64", mx.DOT_F64), ("fp32", mx.DOT_F32), ("dot2", mx.DOT_DOT2)):
-                for oname, order in (("one", mx.GS_ORDER_ONE), ("per_copy", mx.GS_ORDER_PER_COPY)):
+                for oname, order in (("one", mx.GS_ORDER_ONE),
+                                     ("pairwise_every_element", mx.GS_ORDER_PAIRWISE)):
                     x = torch.zeros_like(b)
                     _, st = mesh.solve(b, x, mode=mode, pc=pc, tol=wl.tol, max_iter=wl.maxit,
                                        dot=dot, gs_order=order)
@@ -579,19 +581,41 @@ def bench_strategies(args):
                                  "ms": round(st.ms, 2)})
                     its += st.iterations
                     el += st.ms
+    # rank-count study: the pairwise order with the elements cut into
+    # px x py x pz blocks of ranks (Jacobi CG, FP64 dots)
+    ranks_rows = []
+    for layout in ((1, 1, 1), (1, 1, 2), (1, 2, 2), (2, 2, 2), (3, 3, 3), (4, 4, 4), None):
+        mesh.set_ranks(None if layout is None else W.block_ranks(wl.ne, *layout))
+        nr = bm.E if layout is None else layout[0] * layout[1] * layout[2]
+        for gname, mode in (("fp32", mx.MODE_FP32_ALL), ("fp64", mx.MODE_MIXED)):
+            x = torch.zeros_like(b)
+            _, st = mesh.solve(b, x, mode=mode, pc=mx.PC_JACOBI, tol=wl.tol, max_iter=wl.maxit,
+                               dot=mx.DOT_F64, gs_order=mx.GS_ORDER_PAIRWISE)
+            log(f"  pairwise ranks {nr:5d} {str(layout):10s} gs {gname}: it={st.iterations:5d} "
+                f"reason={st.reason} rec={st.rel_res_recursive:.2e} true={st.rel_res:.2e}")
+            ranks_rows.append({"ranks": nr, "layout": "every element" if layout is None else
+                               "x".join(str(c) for c in layout), "gs_sums": gname,
+                               "reason": st.reason, "iterations": st.iterations,
+                               "rec_res": st.rel_res_recursive, "true_res": st.rel_res,
+                               "ms": round(st.ms, 2)})
+            its += st.iterations
+            el += st.ms
+    mesh.set_ranks(None)
     reasons = {mx.CONVERGED: "converged", mx.MAX_ITER: "max_iter", mx.STAGNATED: "stagnated",
                mx.BREAKDOWN: "breakdown"}
-    for r in rows:
+    for r in rows + ranks_rows:
         r["reason"] = reasons.get(r["reason"], str(r["reason"]))
     out = {
         "metric": "GDOF*iter/s (local dofs x iterations / s) of the SEM PCG solve",
         "value": round(nloc * its / (el / 1e3) / 1e9, 4), "unit": "GDOF*iter/s", "n_gpus": 1,
-        "steps": len(rows), "warmup": 1, "ms_per_step": round(el / len(rows), 3),
+        "steps": len(rows) + len(ranks_rows), "warmup": 1,
+        "ms_per_step": round(el / (len(rows) + len(ranks_rows)), 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 loop; gather-scatter sums and dots per row", "data": "synthetic",
         "config": {"workload": wl.name, "E": bm.E, "N": wl.N, "nloc": nloc,
                    "mode": "strategy table", "tol": wl.tol},
         "strategies": rows,
+        "pairwise_ranks": ranks_rows,
     }
     print(json.dumps(out), flush=True)
     mesh.close()

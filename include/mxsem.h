@@ -102,13 +102,17 @@ typedef enum {
 /* ---- summation order of the gather-scatter in the solve ------------------ */
 typedef enum {
   MXSEM_GS_ORDER_ONE = 0,      /* one sum per node (ascending local index),
-                                  written to every copy: the copies stay equal */
-  MXSEM_GS_ORDER_PER_COPY = 1  /* each copy sums the node's copies in an order
-                                  of its own (itself first, then the others
-                                  cyclically): the order of a pairwise
-                                  exchange between ranks, each copy standing
-                                  for a rank (Sec. 4.2.1).  FP32 vectors,
-                                  at most 16 copies per node                 */
+                                  written to every copy: the copies stay equal
+                                  (what an allreduce-based exchange gives)    */
+  MXSEM_GS_ORDER_PAIRWISE = 1  /* the order of a pairwise exchange between
+                                  ranks (Sec. 4.2.1), on one GPU: elements are
+                                  assigned to ranks (mxsem_mesh_set_ranks; by
+                                  default every element is a rank of its own);
+                                  each rank sums its own copies of a node in
+                                  ascending local index, then adds the other
+                                  ranks' partial sums in ascending rank order,
+                                  and its copies receive that value.  FP32
+                                  vectors, at most 16 copies per node        */
 } mxsem_gs_order;
 
 /* termination reasons */
@@ -120,7 +124,7 @@ typedef enum {
 /* apply / gather-scatter flags */
 #define MXSEM_LOCAL_ONLY 1u /* apply: w = A_L u only (no QQ^T, no mask)      */
 #define MXSEM_MASK 2u       /* gather_scatter: also zero Dirichlet entries   */
-#define MXSEM_GS_PER_COPY 4u /* gather_scatter: MXSEM_GS_ORDER_PER_COPY sums  */
+#define MXSEM_GS_PAIRWISE 4u /* gather_scatter: MXSEM_GS_ORDER_PAIRWISE sums  */
 
 /* mesh views (bitmask): which operator copies to keep on the device */
 #define MXSEM_VIEW_F64 1u
@@ -190,11 +194,11 @@ int mxsem_apply(mxsem_mesh *mesh, mxsem_prec io, const void *u, void *w, unsigne
 /* In place v <- QQ^T v: each shared node's copies are summed in ascending
  * local-index order in acc precision (MXSEM_F64 or MXSEM_F32), rounded once
  * to io and written to every copy.  MXSEM_MASK also zeroes Dirichlet
- * entries.  io: MXSEM_F64 or MXSEM_F32.  MXSEM_GS_PER_COPY (io MXSEM_F32,
- * at most 16 copies per node, else MXSEM_ENOTSUP): copy k of a node with
- * copies v_0..v_{m-1} (ascending local index) receives
- * (..((v_k + v_{k+1}) + v_{k+2}) + ..) + v_{k-1}, indices mod m, summed in
- * acc and rounded once to FP32. */
+ * entries.  io: MXSEM_F64 or MXSEM_F32.  MXSEM_GS_PAIRWISE (io MXSEM_F32,
+ * at most 16 copies per node, else MXSEM_ENOTSUP): a copy in rank R of a
+ * node held by ranks R_1 < R_2 < ... receives S_R + S_{R_a} + S_{R_b} + ...
+ * (left to right, the other ranks ascending), S_X the sum of rank X's
+ * copies in ascending local index; sums in acc, rounded once to FP32. */
 int mxsem_gather_scatter(mxsem_mesh *mesh, mxsem_prec io, mxsem_prec acc, void *v,
                          unsigned flags);
 
@@ -213,6 +217,14 @@ int mxsem_dot_ex(mxsem_mesh *mesh, mxsem_prec io, int acc, const void *a, const 
 /* z = M^-1 r for pc = identity or Jacobi (io MXSEM_F64 / MXSEM_F32), or the
  * learned map (MXSEM_F32, network attached). */
 int mxsem_precond(mxsem_mesh *mesh, mxsem_pc pc, mxsem_prec io, const void *r, void *z);
+
+/* Ranks of the pairwise gather-scatter order (Sec. 4.2.1 compares the
+ * exchange modes across rank counts; one GPU emulates their summation
+ * order): rank_host is a host array [E] of ranks >= 0, or NULL for every
+ * element a rank of its own (the default).  Used by MXSEM_GS_PAIRWISE and
+ * by solves with gs_order MXSEM_GS_ORDER_PAIRWISE.  Allocates a device
+ * array [E] on first use; synchronises the context stream. */
+int mxsem_mesh_set_ranks(mxsem_mesh *mesh, const int32_t *rank_host);
 
 /* b = M QQ^T (B f) for a nodal source f (device FP64 vectors). */
 int mxsem_mass_rhs(mxsem_mesh *mesh, const double *f, double *b);

@@ -58,7 +58,7 @@ def _load():
     lib.orc_dot_f32.restype = C.c_float
     lib.orc_dot_c_f32.argtypes = [vp, C.c_int, vp, vp]
     lib.orc_dot_c_f32.restype = C.c_float
-    lib.orc_gs_f32.argtypes = [vp, vp, C.c_int, C.c_int]
+    lib.orc_gs_f32.argtypes = [vp, vp, C.c_int, C.c_int, vp]
     lib.orc_gs_f32.restype = C.c_int
     lib.orc_max_threads.argtypes = []
     lib.orc_max_threads.restype = C.c_int
@@ -273,11 +273,14 @@ class Mesh:
         a, b = _f32(a), _f32(b)
         return np.float32(_lib.orc_dot_c_f32(self._h, 1 if dot2 else 0, _p(a), _p(b)))
 
-    def gs_f32(self, v, acc64: bool, per_copy: bool) -> np.ndarray:
+    def gs_f32(self, v, acc64: bool, pairwise: bool, erank=None) -> np.ndarray:
         """QQ^T on an FP32 vector: FP64 or FP32 sums, one order per group or
-        each copy's own cyclic order (see orc_gs_f32)."""
+        the pairwise order between ranks (erank [E] or None: every element
+        a rank of its own); see orc_gs_f32."""
         v = _f32(v).copy()
-        rc = _lib.orc_gs_f32(self._h, _p(v), 1 if acc64 else 0, 1 if per_copy else 0)
+        er = None if erank is None else np.ascontiguousarray(erank, dtype=np.int32)
+        rc = _lib.orc_gs_f32(self._h, _p(v), 1 if acc64 else 0, 1 if pairwise else 0,
+                             None if er is None else _p(er))
         if rc != 0:
             raise ValueError(f"orc_gs_f32 failed: {rc}")
         return v

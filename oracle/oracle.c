@@ -436,13 +436,14 @@ float orc_dot_c_f32(const orc_mesh *m, int dot2, const float *a, const float *b)
 }
 
 /* QQ^T on an FP32 vector.  acc64: sums in FP64 (else FP32), rounded once to
- * FP32.  per_copy = 0: one sum per group in ascending local index order,
- * written to every copy.  per_copy = 1: copy k (k-th in ascending local
- * index order) receives v_k + v_{k+1} + ... + v_{m-1} + v_0 + ... + v_{k-1},
- * added left to right: the order in which a rank adds its neighbours'
- * contributions to its own in a pairwise exchange, each copy standing for a
- * rank.  Groups of up to 64 copies. */
-int orc_gs_f32(const orc_mesh *m, float *v, int acc64, int per_copy) {
+ * FP32.  pairwise = 0: one sum per group in ascending local index order,
+ * written to every copy.  pairwise = 1: the order of a pairwise exchange
+ * between ranks (Sec. 4.2.1): element e belongs to rank erank[e] (erank
+ * NULL: rank e); a rank's partial is the sum of its copies in ascending
+ * local index; a copy in rank R receives R's partial plus the other ranks'
+ * partials in ascending rank order, added left to right.  Groups of up to
+ * 64 copies. */
+int orc_gs_f32(const orc_mesh *m, float *v, int acc64, int pairwise, const int *erank) {
   for (int64_t q = 0; q < m->ngroups; ++q)
     if (m->goff[q + 1] - m->goff[q] > 64) return ORC_EINVAL;
 #pragma omp parallel for schedule(static)
@@ -450,25 +451,50 @@ int orc_gs_f32(const orc_mesh *m, float *v, int acc64, int per_copy) {
     const int64_t o = m->goff[q];
     const int cnt = (int)(m->goff[q + 1] - o);
     float val[64], out[64];
-    for (int k = 0; k < cnt; ++k) val[k] = v[m->gidx[o + k]];
+    int rank[64];
     for (int k = 0; k < cnt; ++k) {
-      const int k0 = per_copy ? k : 0;
-      if (!per_copy && k > 0) {
-        out[k] = out[0];
-        continue;
+      const int64_t i = m->gidx[o + k];
+      const int64_t e = i / m->n3;
+      val[k] = v[i];
+      rank[k] = pairwise ? (erank ? erank[e] : (int)e) : 0;
+    }
+    /* distinct ranks in ascending order and their partial sums */
+    int rl[64], nr = 0;
+    double pd[64];
+    float pf[64];
+    for (int k = 0; k < cnt; ++k) {
+      int seen = 0;
+      for (int t = 0; t < nr; ++t) seen |= rl[t] == rank[k];
+      if (!seen) rl[nr++] = rank[k];
+    }
+    for (int a = 1; a < nr; ++a) /* insertion sort, ascending */
+      for (int b = a; b > 0 && rl[b - 1] > rl[b]; --b) {
+        const int t = rl[b];
+        rl[b] = rl[b - 1];
+        rl[b - 1] = t;
       }
-      double sd = 0.0;
-      float sf = 0.f;
-      for (int j = 0; j < cnt; ++j) {
-        const float a = val[(k0 + j) % cnt];
-        if (j == 0) {
-          sd = (double)a;
-          sf = a;
-        } else {
-          sd = sd + (double)a;
-          sf = sf + a;
+    for (int t = 0; t < nr; ++t) {
+      int first = 1;
+      pd[t] = 0.0;
+      pf[t] = 0.f;
+      for (int k = 0; k < cnt; ++k)
+        if (rank[k] == rl[t]) {
+          pd[t] = first ? (double)val[k] : pd[t] + (double)val[k];
+          pf[t] = first ? val[k] : pf[t] + val[k];
+          first = 0;
         }
-      }
+    }
+    for (int k = 0; k < cnt; ++k) {
+      int own = 0;
+      for (int t = 0; t < nr; ++t)
+        if (rl[t] == rank[k]) own = t;
+      double sd = pd[own];
+      float sf = pf[own];
+      for (int t = 0; t < nr; ++t)
+        if (t != own) {
+          sd = sd + pd[t];
+          sf = sf + pf[t];
+        }
       out[k] = acc64 ? (float)sd : sf;
     }
     for (int k = 0; k < cnt; ++k) v[m->gidx[o + k]] = out[k];

@@ -136,10 +136,13 @@ struct GsBucket {
 };
 struct GsPlan {
   const int* idx;
+  const int* erank;  // [E] rank of each element for the pairwise order, or null
+                     // (then every element is a rank of its own)
   GsBucket bk[MAX_BUCKETS];
   int nfree;    // buckets [0, nfree): free groups
   int nall;     // buckets [nfree, nall): Dirichlet groups; bk[nall]: mask list
-  int pad0, pad1;
+  int n3;       // entries per element (locates a copy's element)
+  int pad;
 };
 
 // Device view of one problem for the iteration kernels.  Vector and
@@ -174,7 +177,7 @@ struct ProbDev {
 constexpr int GS_THREADS = 256;  // gather-scatter workgroup
 constexpr int GS_PER_THREAD = 2;
 constexpr int GS_CHUNK = GS_THREADS * GS_PER_THREAD;  // items per workgroup
-constexpr int GS_PERCOPY_MAXM = 16;  // largest group of the per-copy summation order
+constexpr int GS_PAIRWISE_MAXM = 16;  // largest group of the pairwise summation order
 constexpr int UPD_THREADS = 256; // threads per vector-update workgroup
 constexpr int UPD_PER_THREAD = 8;  // entries per thread (two 4-wide vectors)
 constexpr int UPD_CHUNK = UPD_THREADS * UPD_PER_THREAD;

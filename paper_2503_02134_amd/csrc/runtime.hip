@@ -426,6 +426,8 @@ int mxsem_mesh_create(mxsem_ctx* ctx, const mxsem_mesh_desc* d, mxsem_mesh** out
     MX_MHIP(hipMemcpyAsync(m->gs_idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice, s));
   MX_MHIP(hipMemcpyAsync(m->mult, mult.data(), nloc, hipMemcpyHostToDevice, s));
   plan.idx = m->gs_idx;
+  plan.n3 = m->n3;
+  plan.erank = nullptr;
   m->plan = plan;
 
   // scratch
@@ -548,16 +550,16 @@ int mxsem_gather_scatter(mxsem_mesh* m, mxsem_prec io, mxsem_prec acc, void* v, 
   MX_CHECK(m && v, MXSEM_EINVAL, "gather_scatter: null argument");
   MX_CHECK(io == MXSEM_F64 || io == MXSEM_F32, MXSEM_EINVAL, "gather_scatter: io must be F64/F32");
   MX_CHECK(acc == MXSEM_F64 || acc == MXSEM_F32, MXSEM_EINVAL, "gather_scatter: acc must be F64/F32");
-  const bool percopy = (flags & MXSEM_GS_PER_COPY) != 0;
-  if (percopy) {
-    MX_CHECK(io == MXSEM_F32, MXSEM_ENOTSUP, "gather_scatter: per-copy order takes FP32 vectors");
-    MX_CHECK(max_copies(m) <= GS_PERCOPY_MAXM, MXSEM_ENOTSUP,
-             "gather_scatter: per-copy order takes at most 16 copies per node");
+  const bool pairwise = (flags & MXSEM_GS_PAIRWISE) != 0;
+  if (pairwise) {
+    MX_CHECK(io == MXSEM_F32, MXSEM_ENOTSUP, "gather_scatter: pairwise order takes FP32 vectors");
+    MX_CHECK(max_copies(m) <= GS_PAIRWISE_MAXM, MXSEM_ENOTSUP,
+             "gather_scatter: pairwise order takes at most 16 copies per node");
   }
   MX_HIP(hipSetDevice(m->ctx->device));
   (void)hipGetLastError();
   MX_HIP(launch_gs_apply(io, acc, v, m->plan, (flags & MXSEM_MASK) != 0, m->ctx->stream,
-                         percopy));
+                         pairwise));
   return MXSEM_OK;
 }
 
@@ -582,6 +584,24 @@ int mxsem_dot_ex(mxsem_mesh* m, mxsem_prec io, int acc, const void* a, const voi
   MX_HIP(hipSetDevice(m->ctx->device));
   (void)hipGetLastError();
   MX_HIP(launch_dot(io, a, b, m->mult, m->nloc, m->part, out_dev, m->ctx->stream, dm));
+  return MXSEM_OK;
+}
+
+int mxsem_mesh_set_ranks(mxsem_mesh* m, const int32_t* rank_host) {
+  MX_CHECK(m, MXSEM_EINVAL, "set_ranks: null mesh");
+  MX_HIP(hipSetDevice(m->ctx->device));
+  (void)hipGetLastError();
+  if (!rank_host) {
+    m->plan.erank = nullptr;
+    return MXSEM_OK;
+  }
+  for (int e = 0; e < m->E; ++e)
+    MX_CHECK(rank_host[e] >= 0, MXSEM_EINVAL, "set_ranks: ranks must be >= 0");
+  if (!m->erank) MX_TRY(mesh_alloc(m, (void**)&m->erank, sizeof(int) * (size_t)m->E));
+  hipStream_t s = m->ctx->stream;
+  MX_HIP(hipStreamSynchronize(s));  // no queued work may still read the old ranks
+  MX_HIP(hipMemcpy(m->erank, rank_host, sizeof(int) * (size_t)m->E, hipMemcpyHostToDevice));
+  m->plan.erank = m->erank;
   return MXSEM_OK;
 }
 

@@ -24,9 +24,10 @@ hipError_t launch_ax_solver(int prec, int dm, int N, const Tile* tiles, int ntil
                             hipEvent_t ev1 = nullptr);
 int max_epb(int N);
 int ax_wave_elements(int N);
-// percopy: every copy sums in its own order (FP32 vectors; see gs_kernel)
+// pairwise: the summation order of a pairwise exchange between the mesh's
+// ranks (FP32 vectors; see gs_kernel)
 hipError_t launch_gs_apply(int prec_io, int prec_acc, void* v, const GsPlan& plan, bool mask,
-                           hipStream_t s, bool percopy = false);
+                           hipStream_t s, bool pairwise = false);
 // sigma_probs > 0: the launch also finishes sigma and alpha of problems
 // 0..sigma_probs-1 (alpha = rho / sigma, breakdown test) in workgroups of its own.
 // ztiles (with on_z): vector-pass tiles of workgroups that set z = dinv r
@@ -34,7 +35,7 @@ hipError_t launch_gs_apply(int prec_io, int prec_acc, void* v, const GsPlan& pla
 // tiles of such a problem do nothing.
 hipError_t launch_gs_solver(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs,
                             hipStream_t s, bool on_z = false, int sigma_probs = 0,
-                            const Tile* ztiles = nullptr, int nz = 0, bool percopy = false);
+                            const Tile* ztiles = nullptr, int nz = 0, bool pairwise = false);
 hipError_t launch_zpc(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs, int pc,
                       hipStream_t s);
 hipError_t launch_fcg_dots(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs,
@@ -143,8 +144,8 @@ struct Plan {
   int graph_k = 0, graph_pc = -1, graph_gprec = -1, graph_method = -1;
   // dot accumulation (DotMode) and gather-scatter order of the captured
   // iteration, set per solve
-  int dm = 0, percopy = 0;
-  int graph_dm = -1, graph_percopy = -1;
+  int dm = 0, pairwise = 0;
+  int graph_dm = -1, graph_pairwise = -1;
   hipEvent_t evA = nullptr, evB = nullptr;
   double ax_ms_sum = 0.0;
   int ax_samples = 0;
@@ -177,7 +178,8 @@ struct mxsem_mesh {
   float* dinv32 = nullptr;
   uint8_t* mult = nullptr;
   int* gs_idx = nullptr;
-  mx::GsPlan plan{};          // device index array + bucket table
+  mx::GsPlan plan{};          // device index array + bucket table (+ element ranks)
+  int* erank = nullptr;       // device [E] ranks of the pairwise order, or null
   // host copy, per bucket: the first (smallest) local index of each group
   // in bucket order (mask list: its entries); places solver tiles
   std::vector<std::vector<int32_t>> gs_first;

@@ -268,7 +268,7 @@ int enqueue_ax(Plan* pl, int gprec, hipStream_t s, bool skip_first) {
 
 static int enqueue_tail(Plan* pl, int pc, hipStream_t s) {
   MX_HIP(launch_gs_solver(pl->vprec, pl->tiles_gs, pl->nt_gs, pl->probs, s, false, pl->P, nullptr,
-                          0, pl->percopy != 0));
+                          0, pl->pairwise != 0));
   MX_HIP(launch_update(pl->vprec, pc, pl->tiles_upd, pl->nt_upd, pl->probs, s, pl->dm));
   MX_HIP(launch_fin_rho(pl->probs, pl->P, 0, s));
   return MXSEM_OK;
@@ -278,7 +278,7 @@ static int enqueue_tail(Plan* pl, int pc, hipStream_t s) {
 static int get_graph(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K) {
   if (pl->graph && pl->graph_k == K && pl->graph_pc == pc && pl->graph_gprec == gprec &&
       pl->graph_method == MXSEM_METHOD_PCG && pl->graph_dm == pl->dm &&
-      pl->graph_percopy == pl->percopy)
+      pl->graph_pairwise == pl->pairwise)
     return MXSEM_OK;
   if (pl->graph) {
     MX_HIP(hipGraphExecDestroy(pl->graph));
@@ -313,7 +313,7 @@ static int get_graph(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K) {
   pl->graph_gprec = gprec;
   pl->graph_method = MXSEM_METHOD_PCG;
   pl->graph_dm = pl->dm;
-  pl->graph_percopy = pl->percopy;
+  pl->graph_pairwise = pl->pairwise;
   return MXSEM_OK;
 }
 
@@ -327,7 +327,7 @@ struct Inner {
   std::vector<char> active;
   double* history = nullptr;  // single-problem plans only
   int dm = DOT_F64;            // DotMode of the dots (PCG)
-  int percopy = 0;             // per-copy gather-scatter order (PCG)
+  int pairwise = 0;             // pairwise gather-scatter order (PCG)
   // results
   std::vector<int> iterations, reason, fallback;
   std::vector<double> res;
@@ -338,7 +338,7 @@ static int run_inner(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K, Inner& 
   const int P = pl->P;
   int max_launch = 0;
   pl->dm = in.dm;
-  pl->percopy = in.percopy;
+  pl->pairwise = in.pairwise;
   for (int p = 0; p < P; ++p) {
     State& st = pl->hstate[p];
     memset(&st, 0, sizeof(State));
@@ -355,6 +355,7 @@ static int run_inner(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K, Inner& 
     Q.rhs_scale = in.scale[p];
     Q.G = G_ptr(m, gp);
     Q.hB = hB_ptr(m, gp);
+    Q.gs = m->plan;  // the element ranks of the pairwise order may have changed
     Q.dm = in.dm;
     if (in.active[p]) max_launch = std::max(max_launch, in.maxit[p] / K + 2);
   }
@@ -427,7 +428,7 @@ static int enqueue_fcg_z(Plan* pl, int pc, hipStream_t s, bool init) {
 static int get_graph_fcg(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K) {
   if (pl->graph && pl->graph_k == K && pl->graph_pc == pc && pl->graph_gprec == gprec &&
       pl->graph_method == MXSEM_METHOD_FCG && pl->graph_dm == pl->dm &&
-      pl->graph_percopy == pl->percopy)
+      pl->graph_pairwise == pl->pairwise)
     return MXSEM_OK;
   if (pl->graph) {
     MX_HIP(hipGraphExecDestroy(pl->graph));
@@ -473,7 +474,7 @@ static int get_graph_fcg(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K) {
   pl->graph_gprec = gprec;
   pl->graph_method = MXSEM_METHOD_FCG;
   pl->graph_dm = pl->dm;
-  pl->graph_percopy = pl->percopy;
+  pl->graph_pairwise = pl->pairwise;
   return MXSEM_OK;
 }
 
@@ -482,7 +483,7 @@ static int run_inner_fcg(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K, Inn
   const int P = pl->P;
   int max_launch = 0;
   pl->dm = DOT_F64;  // flexible CG: FP64 partials (the mode's own accumulation inside them)
-  pl->percopy = 0;
+  pl->pairwise = 0;
   for (int p = 0; p < P; ++p) {
     State& st = pl->hstate[p];
     memset(&st, 0, sizeof(State));
@@ -581,9 +582,9 @@ static int solve_many(mxsem_ctx* ctx, const std::vector<mxsem_mesh*>& meshes, Ge
   hipStream_t s = ctx->stream;
   for (int p = 0; p < P; ++p) {
     mxsem_mesh* m = meshes[p];
-    if (o->gs_order == MXSEM_GS_ORDER_PER_COPY)
-      MX_CHECK(max_copies(m) <= GS_PERCOPY_MAXM, MXSEM_ENOTSUP,
-               "solve: per-copy gather-scatter order takes at most 16 copies per node");
+    if (o->gs_order == MXSEM_GS_ORDER_PAIRWISE)
+      MX_CHECK(max_copies(m) <= GS_PAIRWISE_MAXM, MXSEM_ENOTSUP,
+               "solve: pairwise gather-scatter order takes at most 16 copies per node");
     if (vprec != VP_F64)
       MX_CHECK(m->dinv32 && (gprec == 2 || m->G32), MXSEM_ENOTSUP, "solve: mesh has no FP32 view");
     if (gprec == 2) MX_CHECK(m->G16, MXSEM_ENOTSUP, "solve: mesh has no BF16 view");
@@ -613,7 +614,7 @@ static int solve_many(mxsem_ctx* ctx, const std::vector<mxsem_mesh*>& meshes, Ge
   in.history = o->history;
   in.dm = vprec == VP_F64 ? DOT_F64
                           : dot_mode_of(o->dot, mode == MXSEM_MODE_FP32_ALL ? DOT_F32 : DOT_F64);
-  in.percopy = o->gs_order == MXSEM_GS_ORDER_PER_COPY ? 1 : 0;
+  in.pairwise = o->gs_order == MXSEM_GS_ORDER_PAIRWISE ? 1 : 0;
   std::vector<char> fallback(P, 0);
   const bool fcg = o->method == MXSEM_METHOD_FCG || o->pc == MXSEM_PC_LEARNED;
   auto inner = [&](Plan* q, int gp, Inner& io) {
@@ -825,7 +826,7 @@ static int check_opts(const mxsem_solve_opts* o) {
            MXSEM_ENOTSUP, "solve: x0 is supported in the FP64 and refinement modes");
   MX_CHECK(o->dot >= MXSEM_DOT_DEFAULT && o->dot <= MXSEM_DOT_DOT2, MXSEM_EINVAL,
            "solve: unknown dot accumulation");
-  MX_CHECK(o->gs_order == MXSEM_GS_ORDER_ONE || o->gs_order == MXSEM_GS_ORDER_PER_COPY,
+  MX_CHECK(o->gs_order == MXSEM_GS_ORDER_ONE || o->gs_order == MXSEM_GS_ORDER_PAIRWISE,
            MXSEM_EINVAL, "solve: unknown gather-scatter order");
   const bool pcg = o->method == MXSEM_METHOD_PCG && o->pc != MXSEM_PC_LEARNED;
   MX_CHECK(o->dot == MXSEM_DOT_DEFAULT || o->dot == MXSEM_DOT_F64 ||
@@ -837,7 +838,7 @@ static int check_opts(const mxsem_solve_opts* o) {
            "solve: flexible CG keeps the mode's own dots");
   MX_CHECK(o->gs_order == MXSEM_GS_ORDER_ONE ||
                (pcg && (o->mode == MXSEM_MODE_MIXED || o->mode == MXSEM_MODE_FP32_ALL)),
-           MXSEM_ENOTSUP, "solve: the per-copy gather-scatter order is for PCG in MIXED / FP32_ALL");
+           MXSEM_ENOTSUP, "solve: the pairwise gather-scatter order is for PCG in MIXED / FP32_ALL");
   return MXSEM_OK;
 }
 

@@ -42,13 +42,15 @@ __device__ inline void fin_sigma_step(const ProbDev& P, double* sred);
 // One thread per group, GS_PER_THREAD groups per thread issued together:
 // all index loads, then all value loads, then sums (ascending local index,
 // in the accumulation type ACC), then the stores.  m = 0 is the mask list.
-// PERCOPY: every copy takes the sum in an order of its own instead -- its
-// own value first, then the group's other copies cyclically after it.  This
-// is the summation order of a pairwise exchange between ranks (each rank
-// adds the others' contributions to its own), with every copy standing for
-// a rank: the copies of a node shared by three or more may then differ in
-// their last bits when the sum is rounded in FP32 (m <= GS_PERCOPY_MAXM).
-template <typename T, typename ACC, bool SOLVER, bool PERCOPY = false>
+// PAIRWISE: the summation order of a pairwise exchange between ranks
+// (Sec. 4.2.1), with the elements assigned to ranks by plan->erank (null:
+// every element a rank of its own).  Each rank sums its own copies
+// (ascending local index), then adds the other ranks' partial sums in
+// ascending rank order, and every copy receives its rank's result.  Two
+// ranks always agree (a + b = b + a); copies of a node shared by three or
+// more ranks may differ in their last bits when the sums are FP32
+// (m <= GS_PAIRWISE_MAXM).
+template <typename T, typename ACC, bool SOLVER, bool PAIRWISE = false>
 __global__ void __launch_bounds__(GS_THREADS) gs_kernel(const Tile* __restrict__ tiles,
                                                         const ProbDev* __restrict__ probs,
                                                         GsApi api) {
@@ -110,18 +112,49 @@ __global__ void __launch_bounds__(GS_THREADS) gs_kernel(const Tile* __restrict__
 #pragma unroll
     for (int q = 0; q < GS_PER_THREAD; ++q)
       if (ok[q]) v[idx[g[q]]] = T(0);
-  } else if constexpr (PERCOPY) {
-    if (m > GS_PERCOPY_MAXM) return;  // rejected on the host
+  } else if constexpr (PAIRWISE) {
+    if (m > GS_PAIRWISE_MAXM) return;  // rejected on the host
+    const gptr<const int> erank = gcast(plan->erank);
+    const int n3 = plan->n3;
 #pragma unroll
     for (int q = 0; q < GS_PER_THREAD; ++q)
       if (ok[q]) {
         const gptr<const int> gi = idx + (int64_t)g[q] * m;
-        T a[GS_PERCOPY_MAXM];
-        for (int k = 0; k < m; ++k) a[k] = v[gi[k]];
+        T a[GS_PAIRWISE_MAXM];
+        int rk[GS_PAIRWISE_MAXM];
         for (int k = 0; k < m; ++k) {
-          ACC sum = (ACC)a[k];
-          for (int j = k + 1; j < m; ++j) sum += (ACC)a[j];
-          for (int j = 0; j < k; ++j) sum += (ACC)a[j];
+          const int i = gi[k];
+          a[k] = v[i];
+          rk[k] = erank ? erank[i / n3] : i / n3;
+        }
+        // the ranks holding copies, ascending, with their partial sums
+        ACC part[GS_PAIRWISE_MAXM];
+        int rl[GS_PAIRWISE_MAXM];
+        int nr = 0, last = -1;
+        for (int t = 0; t < m; ++t) {
+          int best = 0x7fffffff;
+          for (int j = 0; j < m; ++j)
+            if (rk[j] > last && rk[j] < best) best = rk[j];
+          if (best == 0x7fffffff) break;
+          ACC ps = ACC(0);
+          bool first = true;
+          for (int j = 0; j < m; ++j)
+            if (rk[j] == best) {
+              ps = first ? (ACC)a[j] : ps + (ACC)a[j];
+              first = false;
+            }
+          rl[nr] = best;
+          part[nr] = ps;
+          ++nr;
+          last = best;
+        }
+        for (int k = 0; k < m; ++k) {
+          int own = 0;
+          for (int t = 0; t < nr; ++t)
+            if (rl[t] == rk[k]) own = t;
+          ACC sum = part[own];
+          for (int t = 0; t < nr; ++t)
+            if (t != own) sum += part[t];
           v[gi[k]] = (T)sum;
         }
       }
@@ -684,7 +717,7 @@ static inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1
 // API gather-scatter: free buckets, then either the Dirichlet-group
 // buckets (no mask) or the mask list.  io/acc: MXSEM_F64 / MXSEM_F32.
 hipError_t launch_gs_apply(int prec_io, int prec_acc, void* v, const GsPlan& plan, bool mask,
-                           hipStream_t s, bool percopy) {
+                           hipStream_t s, bool pairwise) {
   const int last = mask ? plan.nfree : plan.nall;
   for (int bkt = 0; bkt <= plan.nall; ++bkt) {
     if (bkt >= last && !(mask && bkt == plan.nall)) continue;
@@ -692,7 +725,7 @@ hipError_t launch_gs_apply(int prec_io, int prec_acc, void* v, const GsPlan& pla
     if (ng == 0) continue;
     GsApi a{v, plan, bkt, 0};
     dim3 g(nblk(ng, GS_CHUNK)), b(GS_THREADS);
-    if (percopy) {
+    if (pairwise) {
       if (prec_io != MXSEM_F32) return hipErrorInvalidValue;
       if (prec_acc == MXSEM_F64)
         hipLaunchKernelGGL((gs_kernel<float, double, false, true>), g, b, 0, s, nullptr, nullptr, a);
@@ -717,7 +750,7 @@ hipError_t launch_gs_apply(int prec_io, int prec_acc, void* v, const GsPlan& pla
 // vector precision: 0 FP64, 1 FP32 (FP64 accumulation), 3 FP32 (FP32 accumulation)
 hipError_t launch_gs_solver(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs,
                             hipStream_t s, bool on_z, int sigma_probs, const Tile* ztiles, int nz,
-                            bool percopy) {
+                            bool pairwise) {
   static_assert(GS_THREADS == UPD_THREADS, "the Jacobi-z workgroups use the vector-pass tiles");
   const int nfin = ((sigma_probs + XCDS - 1) / XCDS) * XCDS;
   if (ntiles + nfin + nz == 0) return hipSuccess;
@@ -728,10 +761,10 @@ hipError_t launch_gs_solver(int vprec, const Tile* tiles, int ntiles, const Prob
   a.nprob = sigma_probs;
   a.ztiles = ztiles;
   a.nz = ztiles ? nz : 0;
-  if (percopy && (vprec == 0 || on_z || nz)) return hipErrorInvalidValue;
-  if (percopy && vprec == 1)
+  if (pairwise && (vprec == 0 || on_z || nz)) return hipErrorInvalidValue;
+  if (pairwise && vprec == 1)
     hipLaunchKernelGGL((gs_kernel<float, double, true, true>), g, b, 0, s, tiles, probs, a);
-  else if (percopy)
+  else if (pairwise)
     hipLaunchKernelGGL((gs_kernel<float, float, true, true>), g, b, 0, s, tiles, probs, a);
   else if (vprec == 0)
     hipLaunchKernelGGL((gs_kernel<double, double, true>), g, b, 0, s, tiles, probs, a);

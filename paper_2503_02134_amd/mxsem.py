@@ -32,10 +32,10 @@ PC_IDENTITY, PC_JACOBI, PC_LEARNED = 0, 1, 2
 MODE_FP64, MODE_MIXED, MODE_MIXED_IR, MODE_MIXED_IR_BF16G, MODE_FP32_ALL = 0, 1, 2, 3, 4
 METHOD_PCG, METHOD_FCG = 0, 1
 CONVERGED, MAX_ITER, STAGNATED, BREAKDOWN = 1, 2, 3, 4
-LOCAL_ONLY, MASK, GS_PER_COPY = 1, 2, 4
+LOCAL_ONLY, MASK, GS_PAIRWISE = 1, 2, 4
 # dot accumulation of the FP32 loop, and gather-scatter order
 DOT_DEFAULT, DOT_F64, DOT_F32, DOT_DOT2 = 0, 1, 2, 3
-GS_ORDER_ONE, GS_ORDER_PER_COPY = 0, 1
+GS_ORDER_ONE, GS_ORDER_PAIRWISE = 0, 1
 VIEW_F64, VIEW_F32, VIEW_BF16 = 1, 2, 4
 
 MODE_NAMES = {MODE_FP64: "fp64", MODE_MIXED: "mixed", MODE_MIXED_IR: "mixed_ir",
@@ -96,6 +96,7 @@ _SIGS = {
     "mxsem_gather_scatter": [vp, C.c_int, C.c_int, vp, C.c_uint],
     "mxsem_dot": [vp, C.c_int, vp, vp, vp],
     "mxsem_dot_ex": [vp, C.c_int, C.c_int, vp, vp, vp],
+    "mxsem_mesh_set_ranks": [vp, vp],
     "mxsem_precond": [vp, C.c_int, C.c_int, vp, vp],
     "mxsem_mass_rhs": [vp, vp, vp],
     "mxsem_solve": [vp, C.POINTER(mxsem_solve_opts), vp, vp, C.POINTER(mxsem_solve_stats)],
@@ -224,6 +225,16 @@ def mxsem_dot(mesh, io, a, b, out_dev):
 
 def mxsem_dot_ex(mesh, io, acc, a, b, out_dev):
     _check("mxsem_dot_ex", lib().mxsem_dot_ex(mesh, io, acc, _ptr(a), _ptr(b), _ptr(out_dev)))
+
+
+def mxsem_mesh_set_ranks(mesh, ranks):
+    """ranks: int32 array [E] (host) or None (every element a rank of its own)."""
+    if ranks is None:
+        _check("mxsem_mesh_set_ranks", lib().mxsem_mesh_set_ranks(mesh, None))
+        return
+    import numpy as np
+    arr = np.ascontiguousarray(ranks, dtype=np.int32)
+    _check("mxsem_mesh_set_ranks", lib().mxsem_mesh_set_ranks(mesh, arr.ctypes.data_as(C.c_void_p)))
 
 
 def mxsem_precond(mesh, pc, io, r, z):
@@ -439,10 +450,10 @@ class Mesh:
         mxsem_apply(self.h, prec, u, w, LOCAL_ONLY if local_only else 0)
         return w
 
-    def gs(self, v, acc=F64, mask=False, per_copy=False):
+    def gs(self, v, acc=F64, mask=False, pairwise=False):
         v = v.clone()
         io = F64 if v.dtype == torch.float64 else F32
-        flags = (MASK if mask else 0) | (GS_PER_COPY if per_copy else 0)
+        flags = (MASK if mask else 0) | (GS_PAIRWISE if pairwise else 0)
         mxsem_gather_scatter(self.h, io, acc, v, flags)
         return v
 
@@ -454,6 +465,9 @@ class Mesh:
         else:
             mxsem_dot_ex(self.h, io, acc, a, b, out)
         return float(out.item())
+
+    def set_ranks(self, ranks):
+        mxsem_mesh_set_ranks(self.h, ranks)
 
     def precond(self, r, pc=PC_JACOBI):
         z = torch.empty_like(r)

@@ -119,6 +119,15 @@ def box_mesh(ne: int, N: int, xi, seed: int | None = None, amp: float = 0.05) ->
     return BoxMesh(ne=ne, N=N, xyz=xyz, glo=glo, bnd=bnd, h=h, gxyz=gxyz, l2g=l2g)
 
 
+def block_ranks(ne: int, px: int, py: int, pz: int) -> np.ndarray:
+    """Rank of every element when the ne^3 box is cut into px x py x pz blocks
+    of elements (integer division), ranks numbered x fastest; element
+    e = ex + ne (ey + ne ez), as in box_mesh."""
+    ez, ey, ex = np.meshgrid(np.arange(ne), np.arange(ne), np.arange(ne), indexing="ij")
+    rx, ry, rz = ex * px // ne, ey * py // ne, ez * pz // ne
+    return (rx + px * (ry + py * rz)).astype(np.int32).reshape(-1)
+
+
 def sin3(pts: np.ndarray, scale: float = 1.0) -> np.ndarray:
     """scale * sin(pi x) sin(pi y) sin(pi z) per point."""
     return scale * (np.sin(np.pi * pts[:, 0]) * np.sin(np.pi * pts[:, 1])

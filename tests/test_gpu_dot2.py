@@ -1,6 +1,6 @@
 """Dot accumulation (FP64, FP32, compensated Dot2; Sec. 4.2.2) and the
-gather-scatter summation order (one sum per node, or each copy its own
-order; Sec. 4.2.1) on the GPU, through the C ABI, against the oracle.
+gather-scatter summation order (one sum per node, or the pairwise exchange
+between ranks; Sec. 4.2.1) on the GPU, through the C ABI, against the oracle.
 
 Bars:
   gather-scatter, both orders, FP32 or FP64 sums   bitwise (same definition)
@@ -81,26 +81,37 @@ def test_dot_ex_rejects_fp64_with_fp32_accumulation(mx, ctx, orc):
 
 
 @pytest.mark.parametrize("acc", ["F32", "F64"])
-@pytest.mark.parametrize("per_copy", [False, True])
-def test_gather_scatter_orders_bitwise(orc, mx, ctx, acc, per_copy):
+@pytest.mark.parametrize("order", ["one", "pairwise", "pairwise_2x2x2", "pairwise_1x3x2"])
+def test_gather_scatter_orders_bitwise(orc, mx, ctx, acc, order):
     """FP32 gather-scatter with FP32 or FP64 sums, in one order per node or
-    each copy's own order, equals the oracle's bit for bit on a deformed
-    3^3-element N = 5 mesh (copy counts 1, 2, 4, 8; several tiles)."""
-    log(f"gs order acc={acc} per_copy={per_copy}")
-    bmg, gm, bmo, om, _, _ = make_pair(orc, mx, ctx, 3, 5, 4)
+    in the pairwise order (every element its own rank, or blocks of
+    elements), equals the oracle's bit for bit on a deformed 4^3-element
+    N = 5 mesh (copy counts 1, 2, 4, 8; several tiles)."""
+    log(f"gs order acc={acc} order={order}")
+    bmg, gm, bmo, om, _, _ = make_pair(orc, mx, ctx, 4, 5, 4)
+    from paper_2503_02134_amd import workloads as W
+    erank = None
+    if order.startswith("pairwise_"):
+        erank = W.block_ranks(4, *(int(c) for c in order.split("_")[1].split("x")))
+    gm.set_ranks(erank)
     rng = np.random.default_rng(21)
     v = (rng.standard_normal(gm.nloc) * 10.0 ** rng.integers(-5, 6, gm.nloc)).astype(np.float32)
-    got = gm.gs(_t(v, torch.float32), acc=getattr(mx, acc), per_copy=per_copy).cpu().numpy()
-    want = om.gs_f32(v, acc64=(acc == "F64"), per_copy=per_copy)
+    pw = order != "one"
+    got = gm.gs(_t(v, torch.float32), acc=getattr(mx, acc), pairwise=pw).cpu().numpy()
+    want = om.gs_f32(v, acc64=(acc == "F64"), pairwise=pw, erank=erank)
     np.testing.assert_array_equal(got, want)
+    gm.set_ranks(None)
 
 
-def test_gather_scatter_per_copy_needs_fp32(orc, mx, ctx):
+def test_gather_scatter_pairwise_needs_fp32(orc, mx, ctx):
     bmg, gm, _, _, _, _ = make_pair(orc, mx, ctx, 2, 3)
     v = torch.ones(gm.nloc, dtype=torch.float64, device="cuda")
     with pytest.raises(mx.MxsemError) as ei:
-        gm.gs(v, acc=mx.F64, per_copy=True)
+        gm.gs(v, acc=mx.F64, pairwise=True)
     assert ei.value.code == mx.ENOTSUP
+    with pytest.raises(mx.MxsemError) as ei:
+        gm.set_ranks(np.full(gm.E, -1, np.int32))
+    assert ei.value.code == mx.EINVAL
 
 
 def test_solve_option_checks(orc, mx, ctx):
@@ -110,8 +121,8 @@ def test_solve_option_checks(orc, mx, ctx):
     bad = [dict(mode=mx.MODE_FP64, dot=mx.DOT_F32),
            dict(mode=mx.MODE_MIXED_IR_BF16G, dot=mx.DOT_DOT2),
            dict(mode=mx.MODE_MIXED, dot=mx.DOT_DOT2, method=mx.METHOD_FCG),
-           dict(mode=mx.MODE_MIXED_IR, gs_order=mx.GS_ORDER_PER_COPY),
-           dict(mode=mx.MODE_FP64, gs_order=mx.GS_ORDER_PER_COPY),
+           dict(mode=mx.MODE_MIXED_IR, gs_order=mx.GS_ORDER_PAIRWISE),
+           dict(mode=mx.MODE_FP64, gs_order=mx.GS_ORDER_PAIRWISE),
            dict(mode=mx.MODE_MIXED, dot=7),
            dict(mode=mx.MODE_MIXED, gs_order=2)]
     for kw in bad:
@@ -126,13 +137,13 @@ def test_mixed_recipe_with_each_dot_and_order(orc, mx, ctx, pc):
     N = 7 mesh: every variant drives the recursive residual to 1e-10 and
     stays as close to the FP64 solution as the FP64-dot recipe does (the
     FP32 operator's floor); Dot2 takes the FP64-dot iteration count within
-    5%.  With FP64 sums the per-copy order changes nothing visible."""
+    5%.  With FP64 sums the pairwise order changes nothing visible."""
     bmg, gm, bmo, om, fg, fo = make_pair(orc, mx, ctx, 6, 7, 2)
     xs, _ = om.pcg(om.rhs(fo), pc=getattr(orc, pc), tol=1e-13, maxit=8000)
     bg = gm.mass_rhs(_t(fg))
     its = {}
     for dot in ("DOT_F64", "DOT_F32", "DOT_DOT2"):
-        for order in ("GS_ORDER_ONE", "GS_ORDER_PER_COPY"):
+        for order in ("GS_ORDER_ONE", "GS_ORDER_PAIRWISE"):
             log(f"mixed {pc} {dot} {order}")
             x, st = gm.solve(bg, mode=mx.MODE_MIXED, pc=getattr(mx, pc), tol=1e-10,
                              max_iter=8000, dot=getattr(mx, dot), gs_order=getattr(mx, order))
@@ -144,20 +155,36 @@ def test_mixed_recipe_with_each_dot_and_order(orc, mx, ctx, pc):
             its[dot, order] = st.iterations
     base = its["DOT_F64", "GS_ORDER_ONE"]
     assert abs(its["DOT_DOT2", "GS_ORDER_ONE"] - base) <= 0.05 * base
-    assert abs(its["DOT_F64", "GS_ORDER_PER_COPY"] - base) <= 0.05 * base
+    assert abs(its["DOT_F64", "GS_ORDER_PAIRWISE"] - base) <= 0.05 * base
 
 
-def test_fp32_sums_with_per_copy_order(orc, mx, ctx):
-    """FP32 gather-scatter sums in each copy's own order (the paper's
-    pairwise exchange) with FP32 and with Dot2 dots: the solve runs to its
-    end without breakdown, and the copies of the iterate differ (what makes
-    the multi-rank FP32 runs of the paper stagnate)."""
+def test_fp32_sums_in_pairwise_order(orc, mx, ctx):
+    """FP32 gather-scatter sums in the pairwise order: with one rank the solve
+    is the one-order solve bit for bit; with two ranks (their partial sums
+    associate differently from the one order, but a + b = b + a) every
+    node's copies stay equal and the solve converges; with every element a
+    rank of its own (FP32 and Dot2 dots) the solve runs to its end without
+    breakdown and the copies of the iterate differ (what makes the
+    multi-rank FP32 runs of the paper stagnate)."""
+    from paper_2503_02134_amd import workloads as W
     bmg, gm, bmo, om, fg, fo = make_pair(orc, mx, ctx, 6, 7, 2)
     bg = gm.mass_rhs(_t(fg))
+    kw = dict(mode=mx.MODE_FP32_ALL, pc=mx.PC_IDENTITY, tol=1e-9, max_iter=3000)
+    x1, s1 = gm.solve(bg, **kw)
+    gm.set_ranks(W.block_ranks(6, 1, 1, 1))
+    x2, s2 = gm.solve(bg, gs_order=mx.GS_ORDER_PAIRWISE, **kw)
+    log(f"fp32_all pairwise, one rank: it={s2.iterations} reason={s2.reason}")
+    assert s2.iterations == s1.iterations and torch.equal(x1, x2)
+    gm.set_ranks(W.block_ranks(6, 1, 1, 2))
+    x2, s2 = gm.solve(bg, gs_order=mx.GS_ORDER_PAIRWISE, **kw)
+    xv = x2.cpu().numpy()
+    spread = np.max(np.abs(xv - om.gs(xv * om.c)))
+    log(f"fp32_all pairwise, two ranks: it={s2.iterations} reason={s2.reason} spread={spread:.1e}")
+    assert s2.reason == mx.CONVERGED and spread == 0.0
+    gm.set_ranks(None)
     for dot in ("DOT_F32", "DOT_DOT2"):
-        log(f"fp32_all per-copy {dot}")
-        x, st = gm.solve(bg, mode=mx.MODE_FP32_ALL, pc=mx.PC_IDENTITY, tol=1e-9, max_iter=3000,
-                         dot=getattr(mx, dot), gs_order=mx.GS_ORDER_PER_COPY)
+        log(f"fp32_all pairwise, every element a rank, {dot}")
+        x, st = gm.solve(bg, dot=getattr(mx, dot), gs_order=mx.GS_ORDER_PAIRWISE, **kw)
         log(f"  it={st.iterations} reason={st.reason} rec={st.rel_res_recursive:.2e} "
             f"true={st.rel_res:.2e}")
         assert st.reason in (mx.CONVERGED, mx.STAGNATED, mx.MAX_ITER)

@@ -122,57 +122,92 @@ def _groups(bm):
     return [g for g in out.values()]
 
 
+def _expected_gs(v, groups, n3, acc64, pairwise, erank):
+    """Gather-scatter of an FP32 vector taken one addition at a time (numpy
+    FP32 scalars, or Python floats for FP64 sums rounded once to FP32)."""
+    out = v.copy()
+
+    def add(vals):
+        if acc64:
+            s = 0.0
+            for a in vals:
+                s = s + float(a)
+            return s
+        s = vals[0]
+        for a in vals[1:]:
+            s = np.float32(s + a)
+        return s
+
+    for g in groups:
+        if not pairwise:
+            val = np.float32(add([v[i] for i in g]))
+            for i in g:
+                out[i] = val
+            continue
+        rank = [int(erank[i // n3]) if erank is not None else i // n3 for i in g]
+        ranks = sorted(set(rank))
+        part = {R: add([v[i] for i, r in zip(g, rank) if r == R]) for R in ranks}
+        for i, R in zip(g, rank):
+            terms = [part[R]] + [part[Q] for Q in ranks if Q != R]
+            if acc64:
+                s = 0.0
+                for t in terms:
+                    s = s + t
+            else:
+                s = terms[0]
+                for t in terms[1:]:
+                    s = np.float32(s + t)
+            out[i] = np.float32(s)
+    return out
+
+
 @pytest.mark.parametrize("acc64", [False, True])
-def test_gs_f32_orders_brute_force(orc, acc64):
-    """FP32 gather-scatter, both orders, against sums taken one addition at
-    a time (numpy FP32 scalars, or Python floats for FP64 sums rounded once
-    to FP32), on a 2^3-element N = 2 box (copy counts 1, 2, 4, 8)."""
-    bm, M = _tiny_mesh(orc)
+@pytest.mark.parametrize("ranks", [None, (1, 1, 1), (1, 1, 2), (2, 2, 1), (2, 2, 2)])
+def test_gs_f32_orders_brute_force(orc, acc64, ranks):
+    """FP32 gather-scatter, one order per node and the pairwise order (every
+    element its own rank, or px x py x pz blocks of elements), against sums
+    taken one addition at a time, on a 4^3-element N = 2 box (copy counts
+    1, 2, 4, 8)."""
+    bm, M = _tiny_mesh(orc, ne=4, N=2)
+    n3 = 27
+    erank = None if ranks is None else W.block_ranks(4, *ranks)
     rng = np.random.default_rng(11)
     v = (rng.standard_normal(M.nloc) * 10.0 ** rng.integers(-3, 4, M.nloc)).astype(np.float32)
-    one = M.gs_f32(v, acc64, per_copy=False)
-    per = M.gs_f32(v, acc64, per_copy=True)
-    counts = set()
-    for g in _groups(bm):
-        counts.add(len(g))
-        vals = [v[i] for i in g]
-        for k, i in enumerate(g):
-            for res, start in ((one, 0), (per, k)):
-                rot = vals[start:] + vals[:start]
-                if acc64:
-                    s = 0.0
-                    for a in rot:
-                        s = s + float(a)
-                    want = np.float32(s)
-                else:
-                    s = rot[0]
-                    for a in rot[1:]:
-                        s = np.float32(s + a)
-                    want = s
-                assert res[i] == want
-    assert counts == {1, 2, 4, 8}
+    groups = _groups(bm)
+    assert {len(g) for g in groups} == {1, 2, 4, 8}
+    one = M.gs_f32(v, acc64, pairwise=False)
+    assert np.array_equal(one, _expected_gs(v, groups, n3, acc64, False, None))
+    pw = M.gs_f32(v, acc64, pairwise=True, erank=erank)
+    assert np.array_equal(pw, _expected_gs(v, groups, n3, acc64, True, erank))
 
 
 def test_gs_f32_order_properties(orc):
     """With one order all copies of a node are equal, and with FP64 sums the
-    result is the FP64 gather-scatter rounded to FP32.  With per-copy FP32
-    sums the two copies of a face node still agree (a + b = b + a), while
-    copies of nodes shared by four or eight elements differ somewhere."""
-    bm, M = _tiny_mesh(orc, ne=3, N=3)
+    result is the FP64 gather-scatter rounded to FP32.  In the pairwise order
+    with FP32 sums, one rank or two ranks keep every node's copies equal
+    (a + b = b + a), while with 2 x 2 x 2 ranks, or every element a rank of
+    its own, copies of nodes shared by four or eight ranks differ somewhere."""
+    bm, M = _tiny_mesh(orc, ne=4, N=3)
     rng = np.random.default_rng(12)
     v = (rng.standard_normal(M.nloc) * 10.0 ** rng.integers(-4, 5, M.nloc)).astype(np.float32)
-    one64 = M.gs_f32(v, True, per_copy=False)
+    one64 = M.gs_f32(v, True, pairwise=False)
     assert np.array_equal(one64, M.gs(v.astype(np.float64)).astype(np.float32))
-    per32 = M.gs_f32(v, False, per_copy=True)
-    differ = 0
-    for g in _groups(bm):
-        vals = per32[g]
-        if len(g) <= 2:
-            assert np.all(vals == vals[0])
-        else:
-            differ += int(np.any(vals != vals[0]))
-        assert np.all(M.gs_f32(v, False, per_copy=False)[g] == M.gs_f32(v, False, per_copy=False)[g][0])
-    assert differ > 0
+    one32 = M.gs_f32(v, False, pairwise=False)
+    groups = _groups(bm)
+
+    def n_split(x):
+        return sum(int(np.any(x[g] != x[g][0])) for g in groups)
+
+    assert n_split(one32) == 0
+    assert n_split(M.gs_f32(v, False, True, W.block_ranks(4, 1, 1, 1))) == 0
+    assert np.array_equal(M.gs_f32(v, False, True, W.block_ranks(4, 1, 1, 1)), one32)
+    assert n_split(M.gs_f32(v, False, True, W.block_ranks(4, 1, 1, 2))) == 0
+    assert n_split(M.gs_f32(v, False, True, W.block_ranks(4, 2, 2, 2))) > 0
+    per_elem = M.gs_f32(v, False, True, None)
+    assert n_split(per_elem) > 0
+    for g in groups:  # two copies (two ranks) always agree
+        if len(g) == 2:
+            assert per_elem[g[0]] == per_elem[g[1]]
 
 
 def test_weighted_fp32_dot_definition(orc):
