@@ -172,6 +172,10 @@ __global__ void __launch_bounds__(NN_THREADS)
 //   layer 1: H[c][p] = relu(sum_k W1[c][k] X[k][p]),  k = (slot, ci), K = 64
 //   layer 2: T[o][p] = sum_c W2[c][o] H[c][p],         27 taps -> 32 rows
 //   y[p]     = sum_o T[o][p + d_o]                     (zero outside)
+//            = sum_g R_g[p + (0, dy_g, dz_g)],  R_g[q] = sum_dx T[(dx,dy_g,dz_g)][q + (dx,0,0)]
+// over the 9 groups g = (dy, dz): a tile spans the element's full width in
+// i, so the three taps of a group are summed in registers, the i-shifts being
+// lane shifts within a row of 8 lanes (DPP), before anything goes to LDS.
 // Operand layout of the instruction (lane l, h = l/32): A row l%32 and
 // B column l%32, with k = 8h + t; result column l%32, rows
 // 8(v/4) + 4h + v%4.  The first layer's result is therefore already the
@@ -187,26 +191,37 @@ __global__ void __launch_bounds__(NN_THREADS)
 //    32 input slots so that each operand's two halves are taps whose
 //    offsets differ by the same constant in both half waves (1 or 40): an
 //    operand is two paired 32-bit loads.
-//  * U[o][p] = T[o][p + d_o]: tap o's result for source q is stored at
-//    p = q - d_o of plane o (27 planes of 512, unpadded).  Stores whose p
-//    falls outside the element, and the padding rows of the second layer,
-//    go to a 32-word trash row on the bank they would have used; slots that
-//    no source reaches (the convolution's zero border) are cleared once per
-//    workgroup and never written.  The sum over taps is then 27 loads of
-//    consecutive words per position.
-// 16 KB + 55.4 KB keeps two workgroups per CU; workgroups are persistent.
-// Same roundings as the vector kernel: BF16 inputs, weights and h; FP32
-// accumulation; y summed in tap order.
+//  * U[g][p] = R_g[p + (0, dy_g, dz_g)]: group g's sum for source q is
+//    stored at p = q - (0, dy_g, dz_g) of plane g (9 planes of 512,
+//    unpadded).  Stores whose p falls outside the element, and a half wave's
+//    unused fifth group, go to a 32-word trash row on the bank they would
+//    have used; slots that no source reaches (the convolution's zero border)
+//    are cleared once per workgroup and never written.  The sum over groups
+//    is then 9 loads of consecutive words per position.
+// Second-layer result rows: row R = 8 q + 4 h + t holds, for t < 3, tap dx =
+// t - 1 of group g = q + 4 h; the t = 3 rows of q = 0, 1, 2 in half 0 hold
+// group 8 (dx = -1, 0, +1); the other rows are padding.  A lane's registers
+// v = 4 s + t (s < 4) are then group s + 4 h, and v = 3, 7, 11 group 8 (half
+// 0) or padding (half 1).
+// 16 KB + 18.1 KB per workgroup, three workgroups per CU; workgroups are
+// persistent.  Same roundings
+// as the vector kernel: BF16 inputs, weights and h; FP32 accumulation (y
+// summed by groups, each group's taps in dx order).
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef short short2_t __attribute__((ext_vector_type(2)));
 typedef float floatx16_t __attribute__((ext_vector_type(16)));
 typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
 
+// Persistent workgroups per CU of the MFMA forward: 34.5 KB of LDS each, and
+// at most 168 VGPRs, so that three waves share a SIMD.
+constexpr int NN_FWD_WG_PER_CU = 3;
+
 namespace nnm {
 constexpr int XR = 40, XPL = 400, XWORDS = 10 * XPL;  // bordered input grid
-constexpr int UOFF = XWORDS;                          // tap planes after X
-constexpr int TRASH = 27 * 512;                       // 32-word trash row
+constexpr int UOFF = XWORDS;                          // group planes after X
+constexpr int NPL = 9;                                // (dy, dz) groups
+constexpr int TRASH = NPL * 512;                      // 32-word trash row
 constexpr int UWORDS = TRASH + 32;
 constexpr int LDS_BYTES = 4 * (XWORDS + UWORDS);
 constexpr int tdx(int o) { return o % 3 - 1; }
@@ -254,9 +269,29 @@ struct InSlots {
 };
 constexpr InSlots IN{};
 constexpr int pair_gap(int ks) { return ks < 3 ? 1 : XR; }
-// second-layer result slot -> tap (slots 26, 27, 29, 30, 31 are padding)
-constexpr int slot_tap(int s) { return s < 26 ? s : (s == 28 ? 26 : -1); }
-static_assert(26 * 512 / 64 <= 255, "tap planes reachable by 64-word load offsets");
+// second-layer result row -> group (-1: padding) and tap
+constexpr int row_group(int R) {
+  const int q = R / 8, h = (R / 4) % 2, t = R % 4;
+  return t < 3 ? q + 4 * h : (h == 0 && q < 3 ? 8 : -1);
+}
+constexpr int row_dx(int R) { return R % 4 < 3 ? R % 4 - 1 : R / 8 - 1; }
+constexpr int row_tap(int R) {
+  return row_group(R) < 0 ? -1
+                          : tap_of(row_dx(R), row_group(R) % 3 - 1, row_group(R) / 3 - 1);
+}
+constexpr int group_dy(int g) { return g % 3 - 1; }
+constexpr int group_dz(int g) { return g / 3 - 1; }
+// every tap in exactly one row
+constexpr bool rows_cover_taps() {
+  for (int o = 0; o < 27; ++o) {
+    int hits = 0;
+    for (int R = 0; R < 32; ++R) hits += row_tap(R) == o;
+    if (hits != 1) return false;
+  }
+  return true;
+}
+static_assert(rows_cover_taps(), "second-layer rows hold each tap once");
+static_assert(NPL * 512 * 4 <= 65535, "group planes reachable by LDS load offsets");
 }  // namespace nnm
 
 // Weight operands in the per-lane A layout, packed once per weight update:
@@ -275,14 +310,14 @@ __global__ void nn_pack_kernel(const float* __restrict__ W1, const float* __rest
       v[t] = (__bf16)(tap >= 0 ? W1[row * 54 + ci * 27 + tap] : 0.f);
     } else {
       const int c = 16 * (ks - 4) + 8 * (t >> 2) + 4 * h + (t & 3);
-      const int tap = nnm::slot_tap(row);
+      const int tap = nnm::row_tap(row);
       v[t] = (__bf16)(tap >= 0 ? W2[c * 27 + tap] : 0.f);
     }
   }
   pk[ks * 64 + lane] = v;
 }
 
-__global__ void __launch_bounds__(NN_THREADS, 2)
+__global__ void __launch_bounds__(NN_THREADS, NN_FWD_WG_PER_CU)
     nn_fwd_mfma_n8_kernel(const float* __restrict__ r, const float* __restrict__ dinv,
                           const uint8_t* __restrict__ mult, const bf16x8_t* __restrict__ pk,
                           float* __restrict__ zc, int E, const State* __restrict__ st,
@@ -313,26 +348,27 @@ __global__ void __launch_bounds__(NN_THREADS, 2)
   // this lane's column in the wave's tiles 4*wave + mt
   const int ci_ = c & 7, cj = c >> 3, ck = 2 * wave;
   const int xq = (ci_ + 1) + XR * (cj + 1) + XPL * (ck + 1);
-  int xb[4][4][2];  // im2col pair address per (tile, k step, pair)
+  // im2col pair address per (k step, pair) for the wave's first tile; tile
+  // mt adds the constant XPL (mt / 2) + 4 XR (mt % 2)
+  int xb[4][2];
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+    for (int m = 0; m < 2; ++m) xb[ks][m] = xq + IN.off[8 * ks + 4 * h + 2 * m];
+  int wa[4][5];  // group-sum store address per (tile, group slot)
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks)
-#pragma unroll
-      for (int m = 0; m < 2; ++m)
-        xb[mt][ks][m] = xq + XPL * (mt >> 1) + 4 * XR * (mt & 1) + IN.off[8 * ks + 4 * h + 2 * m];
-  int wa[4][14];  // second-layer store address per (tile, result register)
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-    for (int v = 0; v < 14; ++v) {
-      const int o = slot_tap(8 * (v >> 2) + 4 * h + (v & 3));
-      const int dx = o >= 0 ? tdx(o) : 0, dy = o >= 0 ? tdy(o) : 0, dz = o >= 0 ? tdz(o) : 0;
-      const int pi = ci_ - dx, pj = cj + 4 * (mt & 1) - dy, pk_ = ck + (mt >> 1) - dz;
-      const int a = 512 * (o >= 0 ? o : 0) + pi + 8 * pj + 64 * pk_;
-      const bool live = o >= 0 && (unsigned)pi < 8u && (unsigned)pj < 8u && (unsigned)pk_ < 8u;
-      wa[mt][v] = live ? a : TRASH + (a & 31);
+    for (int sg = 0; sg < 5; ++sg) {
+      const int g = sg < 4 ? sg + 4 * h : (h == 0 ? 8 : -1);
+      const int dy = g >= 0 ? group_dy(g) : 0, dz = g >= 0 ? group_dz(g) : 0;
+      const int pj = cj + 4 * (mt & 1) - dy, pk_ = ck + (mt >> 1) - dz;
+      const int a = 512 * (g >= 0 ? g : 0) + ci_ + 8 * pj + 64 * pk_;
+      const bool live = g >= 0 && (unsigned)pj < 8u && (unsigned)pk_ < 8u;
+      wa[mt][sg] = live ? a : TRASH + (a & 31);
     }
+  // the lane's neighbours along i inside its row of 8 (outside: zero)
+  const bool has_left = ci_ > 0, has_right = ci_ < 7;
   // positions of the sum over taps: p = tid and tid + 256
   const int pi = tid & 7, pj = (tid >> 3) & 7, pk0 = tid >> 6;
   const int xw = (pi + 1) + XR * (pj + 1) + XPL * (pk0 + 1);
@@ -412,8 +448,9 @@ __global__ void __launch_bounds__(NN_THREADS, 2)
           u32x4_t w;
 #pragma unroll
           for (int m = 0; m < 2; ++m) {
-            w[2 * m] = X[xb[mt][ks][m]];
-            w[2 * m + 1] = X[xb[mt][ks][m] + pair_gap(ks)];
+            const int xa = xb[ks][m] + XPL * (mt >> 1) + 4 * XR * (mt & 1);
+            w[2 * m] = X[xa];
+            w[2 * m + 1] = X[xa + pair_gap(ks)];
           }
           acc[t2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
               a1[ks], __builtin_bit_cast(bf16x8_t, w), acc[t2], 0, 0, 0);
@@ -442,7 +479,23 @@ __global__ void __launch_bounds__(NN_THREADS, 2)
 #pragma unroll
       for (int t2 = 0; t2 < 2; ++t2)
 #pragma unroll
-        for (int v = 0; v < 14; ++v) U[wa[mp + t2][v]] = acc2[t2][v];
+        for (int sg = 0; sg < 5; ++sg) {
+          // taps dx = -1, 0, +1 of the group: R_g[q] = T_-1[q - 1] + T_0[q] + T_+1[q + 1]
+          const int vm = sg < 4 ? 4 * sg : 3, v0 = sg < 4 ? 4 * sg + 1 : 7,
+                    vp = sg < 4 ? 4 * sg + 2 : 11;
+          // DPP row_shr:1: lane n takes lane n - 1; row_shl:1: lane n takes lane n + 1.
+          // The elements are copied out first: a bit cast of a vector element
+          // in place reads element 0 of the vector.
+          const float tm = acc2[t2][vm], tp = acc2[t2][vp];
+          const float fl = __builtin_bit_cast(
+              float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, tm), 0x111, 0xf, 0xf,
+                                                 true));
+          const float fr = __builtin_bit_cast(
+              float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, tp), 0x101, 0xf, 0xf,
+                                                 true));
+          const float sum = ((has_left ? fl : 0.f) + acc2[t2][v0]) + (has_right ? fr : 0.f);
+          U[wa[mp + t2][sg]] = sum;
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -450,7 +503,7 @@ __global__ void __launch_bounds__(NN_THREADS, 2)
       const int p = tid + q * NN_THREADS;
       float y = 0.f;
 #pragma unroll
-      for (int o = 0; o < 27; ++o) y += U[512 * o + p];
+      for (int g = 0; g < NPL; ++g) y += U[512 * g + p];
       const float zl = dv[q] + s * y;
       // the weight applied to z_L also weights the Jacobi candidate's dots
       // (exact for the power-of-two multiplicities of a box mesh)
@@ -729,12 +782,13 @@ hipError_t launch_nn_fwd(int N, const float* r, const float* dinv, const uint8_t
                          const float* W1, const float* W2, float* zc, int E, hipStream_t s,
                          const State* st, const void* packed, NnDots dd, int* nparts) {
   if (N == 7) {
-    // persistent: two workgroups per CU, each walking elements blockIdx.x, +grid, ...
+    // persistent: NN_FWD_WG_PER_CU workgroups per CU, each walking elements
+    // blockIdx.x, +grid, ...
     int dev = 0, ncu = 0;
     hipError_t err = hipGetDevice(&dev);
     if (err == hipSuccess) err = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (err != hipSuccess) return err;
-    const int grid = std::min(E, 2 * std::max(ncu, 1));
+    const int grid = std::min(E, NN_FWD_WG_PER_CU * std::max(ncu, 1));
     if (nparts) *nparts = grid;
     if (grid <= 0) return hipSuccess;
     if (dd.dots && grid > dd.dstride) return hipErrorInvalidConfiguration;
