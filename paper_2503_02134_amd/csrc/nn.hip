@@ -204,9 +204,9 @@ __global__ void __launch_bounds__(NN_THREADS)
 // v = 4 s + t (s < 4) are then group s + 4 h, and v = 3, 7, 11 group 8 (half
 // 0) or padding (half 1).
 // 16 KB + 18.1 KB per workgroup, three workgroups per CU; workgroups are
-// persistent.  Same roundings
-// as the vector kernel: BF16 inputs, weights and h; FP32 accumulation (y
-// summed by groups, each group's taps in dx order).
+// persistent.  The roundings are the vector kernel's (BF16 inputs, weights
+// and h; FP32 accumulation); y is summed by groups here (each group's taps in
+// dx order), in tap order there.
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef short short2_t __attribute__((ext_vector_type(2)));
@@ -939,11 +939,11 @@ int mxsem_nn_create(mxsem_mesh* m, const mxsem_nn_desc* d, mxsem_nn** out) {
 
 int mxsem_nn_destroy(mxsem_nn* nn) {
   if (!nn) return MXSEM_OK;
-  hipSetDevice(nn->mesh->ctx->device);
-  if (nn->mesh->ctx->stream) hipStreamSynchronize(nn->mesh->ctx->stream);
-  else hipDeviceSynchronize();
+  (void)hipSetDevice(nn->mesh->ctx->device);
+  if (nn->mesh->ctx->stream) (void)hipStreamSynchronize(nn->mesh->ctx->stream);
+  else (void)hipDeviceSynchronize();
   if (nn->mesh->nn == nn) nn->mesh->nn = nullptr;
-  for (void* p : nn->allocs) hipFree(p);
+  for (void* p : nn->allocs) (void)hipFree(p);
   if (nn->W) nn->mesh->ctx->live -= 1;
   delete nn;
   return MXSEM_OK;

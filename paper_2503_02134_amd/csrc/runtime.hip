@@ -205,13 +205,13 @@ int mxsem_ctx_create(int hip_device, void* hip_stream, mxsem_ctx** out) {
 int mxsem_ctx_destroy(mxsem_ctx* c) {
   if (!c) return MXSEM_OK;
   MX_CHECK(c->live == 0, MXSEM_EINVAL, "ctx_destroy: meshes or batches of this context are alive");
-  hipSetDevice(c->device);
-  if (c->stream) hipStreamSynchronize(c->stream);
-  else hipDeviceSynchronize();
-  if (c->capture) hipStreamDestroy(c->capture);
-  if (c->ev0) hipEventDestroy(c->ev0);
-  if (c->ev1) hipEventDestroy(c->ev1);
-  if (c->pinned_flags) hipHostFree(c->pinned_flags);
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  if (c->capture) (void)hipStreamDestroy(c->capture);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->pinned_flags) (void)hipHostFree(c->pinned_flags);
   delete c;
   return MXSEM_OK;
 }
@@ -231,12 +231,12 @@ int mxsem_gll(int N, double* xi, double* w) {
 
 int mxsem_mesh_destroy(mxsem_mesh* m) {
   if (!m) return MXSEM_OK;
-  hipSetDevice(m->ctx->device);
-  if (m->ctx->stream) hipStreamSynchronize(m->ctx->stream);
-  else hipDeviceSynchronize();
+  (void)hipSetDevice(m->ctx->device);
+  if (m->ctx->stream) (void)hipStreamSynchronize(m->ctx->stream);
+  else (void)hipDeviceSynchronize();
   mesh_drop_plans(m);
   for (int q = 0; q < 4; ++q) delete m->bufs[q];
-  for (void* p : m->allocs) hipFree(p);
+  for (void* p : m->allocs) (void)hipFree(p);
   if (m->counted) m->ctx->live -= 1;
   delete m;
   return MXSEM_OK;
@@ -477,7 +477,7 @@ int mxsem_mesh_create(mxsem_ctx* ctx, const mxsem_mesh_desc* d, mxsem_mesh** out
   // the coordinates and k are no longer needed on the device
   for (void* p : {(void*)xyz_d, (void*)k_d, (void*)detmin_d}) {
     if (!p) continue;
-    hipFree(p);
+    (void)hipFree(p);
     m->allocs.erase(std::find(m->allocs.begin(), m->allocs.end(), p));
   }
   for (int q = 0; q < 16; ++q) m->epb[q] = 0;

@@ -84,12 +84,12 @@ int ensure_bufs(mxsem_mesh* m, int vprec, SolverBufs** out) {
 
 void plan_destroy(Plan* pl) {
   if (!pl) return;
-  if (pl->graph) hipGraphExecDestroy(pl->graph);
-  if (pl->evA) hipEventDestroy(pl->evA);
-  if (pl->evB) hipEventDestroy(pl->evB);
-  if (pl->hstate) hipHostFree(pl->hstate);
-  if (pl->hnorm) hipHostFree(pl->hnorm);
-  for (void* p : pl->dev_allocs) hipFree(p);
+  if (pl->graph) (void)hipGraphExecDestroy(pl->graph);
+  if (pl->evA) (void)hipEventDestroy(pl->evA);
+  if (pl->evB) (void)hipEventDestroy(pl->evB);
+  if (pl->hstate) (void)hipHostFree(pl->hstate);
+  if (pl->hnorm) (void)hipHostFree(pl->hnorm);
+  for (void* p : pl->dev_allocs) (void)hipFree(p);
   delete pl;
 }
 
@@ -294,7 +294,7 @@ static int get_graph(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K) {
   }
   hipError_t e = hipStreamEndCapture(cs, &g);
   if (rc != MXSEM_OK) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return rc;
   }
   if (e != hipSuccess) {
@@ -302,7 +302,7 @@ static int get_graph(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K) {
     return MXSEM_EHIP;
   }
   e = hipGraphInstantiate(&pl->graph, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (e != hipSuccess) {
     set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     pl->graph = nullptr;
@@ -455,7 +455,7 @@ static int get_graph_fcg(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K) {
   }
   hipError_t e = hipStreamEndCapture(cs, &g);
   if (rc != MXSEM_OK) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return rc;
   }
   if (e != hipSuccess) {
@@ -463,7 +463,7 @@ static int get_graph_fcg(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K) {
     return MXSEM_EHIP;
   }
   e = hipGraphInstantiate(&pl->graph, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (e != hipSuccess) {
     set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     pl->graph = nullptr;
@@ -901,9 +901,9 @@ int mxsem_batch_create(mxsem_ctx* ctx, int P, mxsem_mesh* const* meshes, const c
 
 int mxsem_batch_destroy(mxsem_batch* bt) {
   if (!bt) return MXSEM_OK;
-  hipSetDevice(bt->ctx->device);
-  if (bt->ctx->stream) hipStreamSynchronize(bt->ctx->stream);
-  else hipDeviceSynchronize();
+  (void)hipSetDevice(bt->ctx->device);
+  if (bt->ctx->stream) (void)hipStreamSynchronize(bt->ctx->stream);
+  else (void)hipDeviceSynchronize();
   for (int q = 0; q < 4; ++q) plan_destroy(bt->plans[q]);
   bt->ctx->live -= 1;
   delete bt;

@@ -31,12 +31,12 @@ int autotune_epb(int device, hipStream_t s, int N, int E, int prec, int* best_ep
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc = MXSEM_OK;
   auto cleanup = [&]() {
-    if (u) hipFree(u);
-    if (w) hipFree(w);
-    if (G) hipFree(G);
-    if (D) hipFree(D);
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
+    if (u) (void)hipFree(u);
+    if (w) (void)hipFree(w);
+    if (G) (void)hipFree(G);
+    if (D) (void)hipFree(D);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
   };
   if (hipMalloc(&u, vb * nloc) != hipSuccess || hipMalloc(&w, vb * nloc) != hipSuccess ||
       hipMalloc(&G, gb * 6 * nloc) != hipSuccess || hipMalloc(&D, 8 * n * n) != hipSuccess ||
@@ -65,16 +65,18 @@ int autotune_epb(int device, hipStream_t s, int N, int E, int prec, int* best_ep
       }
     }
     const int reps = 5;
-    hipEventRecord(e0, s);
-    for (int r = 0; r < reps; ++r) launch_ax_apply(prec, N, E, epb, u, w, G, nullptr, D, s);
-    hipEventRecord(e1, s);
-    if (hipEventSynchronize(e1) != hipSuccess) {
+    hipError_t err = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && err == hipSuccess; ++r)
+      err = launch_ax_apply(prec, N, E, epb, u, w, G, nullptr, D, s);
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err != hipSuccess) {
       cleanup();
-      set_error("autotune: event synchronisation failed");
+      set_error(std::string("autotune: timing failed: ") + hipGetErrorString(err));
       return MXSEM_EHIP;
     }
-    float ms = 0.f;
-    hipEventElapsedTime(&ms, e0, e1);
     ms /= reps;
     if (times) times->push_back(ms);
     if (ms < best) {
