@@ -6,13 +6,15 @@ Jacobi-PCG with FP64 gather-scatter sums and dots, FP64 residuals in the
 refinement loop).  value = local dofs x (inner + outer iterations) per
 second over the timed steps.  Inputs are resident in HBM before timing.
 
-Beside it: the FP64 solve on the same GPU, the same refinement with BF16
-geometric factors, time-to-1e-8, energy-to-solution (the GPU package's energy
-counter around repeated FP64 and mixed solves), the roofline of the dominant kernel (the
-fused operator kernel of the inner loop: the first operator launch of every
-graph chunk records its own start and end events on the solve's stream),
-a measured copy-kernel ceiling, and the FP64 CPU oracle timed on a bounded
-sample of the same workload.  Other workloads: --workload batch64 (64
+Beside it: the same rate over unique nodes, the FP64 solve on the same GPU,
+the same refinement with BF16 geometric factors, time-to-1e-8,
+energy-to-solution (the GPU package's energy counter around repeated FP64
+and mixed solves), the roofline of the dominant kernel (the fused operator
+kernel of the inner loop: the first operator launch of every graph chunk
+records its own start and end events on the solve's stream), a measured
+copy-kernel ceiling, and the FP64 CPU oracle timed on a bounded sample of
+the same workload (with the host's core count and CPU model).  --dot fp32 |
+dot2 sets the accumulation of the inner loop's dots.  Other workloads: --workload batch64 (64
 uneven problems), --workload box24_N7_lognormal_helmholtz --mode learned
 (the learned preconditioner against Jacobi PCG and FP64 PCG) and --workload
 box20_N7 --mode strategies (the mixed-precision strategy table: gather-scatter
@@ -240,6 +242,8 @@ def main():
                      "bytes_per_launch": traffic_bytes, "avg_launch_us": round(ax_avg_ms * 1e3, 2),
                      "launches_timed": tot},
         "setup_s": round(t_setup, 3),
+        # the same rate counted over unique nodes instead of local dofs
+        "gdof_iter_s_unique_nodes": round(value * (wl.ne * wl.N + 1) ** 3 / nloc, 4),
         **extra,
     }
 
@@ -641,8 +645,15 @@ def cpu_baseline(wl, iters):
     # the call also does one true-residual apply at exit: count it as an iteration
     value = om.nloc * (st.iterations + 1) / el / 1e9
     log(f"cpu oracle: {st.iterations} iterations in {el:.1f}s")
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")),
+                         "")
+    except OSError:
+        pass
     return {"value": round(value, 5), "unit": "GDOF*iter/s", "cores": oracle.max_threads(),
-            "kind": "oracle",
+            "cpu_model": model, "kind": "oracle",
             "sample": f"{st.iterations} FP64 Jacobi-PCG iterations of {wl.name} "
                       f"(plain C oracle, OpenMP over elements), {el:.1f} s"}
 
