@@ -223,6 +223,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(elapsed * 1e3 / args.steps, 3),
+        "ms_per_step_median": round(sorted(st.ms for st in stats)[len(stats) // 2], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
