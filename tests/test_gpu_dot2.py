@@ -193,3 +193,32 @@ def test_fp32_sums_in_pairwise_order(orc, mx, ctx):
         spread = np.max(np.abs(xv - om.gs(xv * om.c)))  # 0 when all copies agree
         log(f"  largest difference between a copy and its node's mean: {spread:.2e}")
         assert spread > 0.0
+
+
+def test_rank_count_dependent_stagnation(orc, mx, ctx):
+    """The paper's rank-count result (Sec. 4.2.1, evaluation table) on one
+    GPU: FP32 gather-scatter sums in the pairwise exchange's order converge
+    with one and two ranks and stagnate with 2 x 2 x 2 ranks, while FP64 sums
+    converge with 2 x 2 x 2 ranks (Jacobi CG, FP64 dots, recursive 1e-9, the
+    deformed 8^3-element N = 7 mesh)."""
+    from paper_2503_02134_amd import workloads as W
+    bmg, gm, bmo, om, fg, fo = make_pair(orc, mx, ctx, 8, 7, 2, rhs="random", rhs_seed=20)
+    bg = gm.mass_rhs(_t(fg))
+    kw = dict(pc=mx.PC_JACOBI, tol=1e-9, max_iter=5000, dot=mx.DOT_F64,
+              gs_order=mx.GS_ORDER_PAIRWISE)
+    res = {}
+    for layout in ((1, 1, 1), (1, 1, 2), (2, 2, 2)):
+        gm.set_ranks(W.block_ranks(8, *layout))
+        for gname, mode in (("fp32", mx.MODE_FP32_ALL), ("fp64", mx.MODE_MIXED)):
+            _, st = gm.solve(bg, mode=mode, **kw)
+            log(f"ranks {layout} gs {gname}: it={st.iterations} reason={st.reason} "
+                f"rec={st.rel_res_recursive:.2e}")
+            res[layout, gname] = st
+    gm.set_ranks(None)
+    for layout in ((1, 1, 1), (1, 1, 2)):
+        assert res[layout, "fp32"].reason == mx.CONVERGED
+    assert res[(2, 2, 2), "fp32"].reason == mx.STAGNATED
+    assert res[(2, 2, 2), "fp32"].rel_res_recursive > 1e-8
+    for layout in ((1, 1, 1), (1, 1, 2), (2, 2, 2)):
+        assert res[layout, "fp64"].reason == mx.CONVERGED
+        assert res[layout, "fp64"].iterations == res[(1, 1, 1), "fp64"].iterations
