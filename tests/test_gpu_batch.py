@@ -42,26 +42,35 @@ def _problems(mx, ctx):
     return out
 
 
-@pytest.mark.parametrize("mode", ["MODE_FP64", "MODE_MIXED_IR"])
-def test_batch_equals_standalone_bitwise(mx, ctx, mode):
-    log(f"batch vs standalone, {mode}")
+@pytest.mark.parametrize("mode,extra", [("MODE_FP64", ""), ("MODE_MIXED_IR", ""),
+                                        ("MODE_MIXED_IR", "dot2"),
+                                        ("MODE_FP32_ALL", "pairwise")])
+def test_batch_equals_standalone_bitwise(mx, ctx, mode, extra):
+    """Also with Dot2 dots, and with FP32 sums in the pairwise order (every
+    element a rank): the options travel per problem through the shared
+    launches."""
+    log(f"batch vs standalone, {mode} {extra}")
     probs = _problems(mx, ctx)
     md = getattr(mx, mode)
+    kw = {"dot2": dict(dot=mx.DOT_DOT2),
+          "pairwise": dict(gs_order=mx.GS_ORDER_PAIRWISE, pc=mx.PC_IDENTITY)}.get(extra, {})
+    tol = 1e-7 if extra == "pairwise" else 1e-10
     alone = []
     for m, b in probs:
-        x, st = m.solve(b, mode=md, tol=1e-10, max_iter=4000)
+        x, st = m.solve(b, mode=md, tol=tol, max_iter=4000, **kw)
         alone.append((x.clone(), st))
     bt = mx.mxsem_batch_create(ctx.h, [m.h for m, _ in probs])
     try:
         xs = [torch.zeros_like(b) for _, b in probs]
-        sts = mx.mxsem_batch_solve(bt, mx.solve_opts(mode=md, tol=1e-10, max_iter=4000),
+        sts = mx.mxsem_batch_solve(bt, mx.solve_opts(mode=md, tol=tol, max_iter=4000, **kw),
                                    [b for _, b in probs], xs)
     finally:
         mx.mxsem_batch_destroy(bt)
     for (xa, sa), xb, sb in zip(alone, xs, sts):
         log(f"  alone it={sa.iterations} outer={sa.outer} | batch it={sb.iterations} "
             f"outer={sb.outer} res={sb.rel_res:.2e}")
-        assert sb.reason == mx.CONVERGED
+        assert sb.reason == sa.reason
+        assert extra == "pairwise" or sb.reason == mx.CONVERGED
         assert sb.iterations == sa.iterations and sb.outer == sa.outer
         assert torch.equal(xa, xb)
 
