@@ -26,6 +26,9 @@ struct AxApplyArgs {
   const void* hB;
   const void* D;
   int E;
+  // solver variant: -1 reads and writes p in place; 0 / 1 (the step's
+  // parity) reads p_old from p_alt / p and writes p / p_alt
+  int parity;
 };
 
 // The six geometric factors of local node `node` (= e n^3 + p).  FP64: the
@@ -102,7 +105,7 @@ __global__ void __launch_bounds__(256) ax_kernel(const Tile* __restrict__ tiles,
     Dg = gcast((const T*)P->D);
     G = gcast((const TG*)P->G);
     hB = gcast((const TG*)P->hB);
-    U = gcast((const T*)P->p);
+    U = gcast((const T*)(apply.parity == 0 ? P->p_alt : P->p));
     Wout = gcast((T*)P->w);
     Z = gcast((const T*)P->z);
     E = P->E;
@@ -144,7 +147,7 @@ __global__ void __launch_bounds__(256) ax_kernel(const Tile* __restrict__ tiles,
   if (active) {
     if constexpr (SOLVER) {
       const T beta = (T)gcast(P->st)->beta;
-      gptr<T> __restrict__ Pw = gcast((T*)P->p);
+      gptr<T> __restrict__ Pw = gcast((T*)(apply.parity == 1 ? P->p_alt : P->p));
 #pragma unroll
       for (int k = 0; k < n; ++k) {
         T pv = Z[base + k * n2] + beta * U[base + k * n2];
@@ -281,7 +284,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
     Dg = gcast((const T*)P->D);
     G = gcast((const TG*)P->G);
     hB = gcast((const TG*)P->hB);
-    U = gcast((const T*)P->p);
+    U = gcast((const T*)(apply.parity == 0 ? P->p_alt : P->p));
     Wout = gcast((T*)P->w);
     Z = gcast((const T*)P->z);
     E = P->E;
@@ -329,7 +332,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
   if (active) {
     if constexpr (SOLVER) {
       const T beta = (T)gcast(P->st)->beta;
-      gptr<T> __restrict__ Pw = gcast((T*)P->p);
+      gptr<T> __restrict__ Pw = gcast((T*)(apply.parity == 1 ? P->p_alt : P->p));
 #pragma unroll
       for (int k = 0; k < n; ++k) {
         const T p0 = Z[base0 + k * n2] + beta * U[base0 + k * n2];
@@ -504,8 +507,9 @@ hipError_t launch_ax_apply(int prec, int N, int E, int epb, const void* u, void*
 // vectors and BF16 G take DOT_F64)
 hipError_t launch_ax_solver(int prec, int dm, int N, const Tile* tiles, int ntiles,
                             const ProbDev* probs, int epb, hipStream_t s, hipEvent_t ev0,
-                            hipEvent_t ev1) {
+                            hipEvent_t ev1, int parity) {
   AxApplyArgs a{};
+  a.parity = parity;
   if (prec == 1 && dm == DOT_F32)
     return dispatch<float, float, true, DOT_F32>(N, tiles, probs, a, ntiles, epb, s, ev0, ev1);
   if (prec == 1 && dm == DOT_DOT2)

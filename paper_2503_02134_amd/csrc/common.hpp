@@ -99,6 +99,10 @@ struct State {
   int fallback;  // learned-PC steps replaced by Jacobi
   int pc;        // mxsem_pc
   int fb_pending;  // flexible CG: this step's z must be replaced by Jacobi
+  // PCG with two direction buffers: x is updated every second step with
+  // both steps' alpha p; after an even step the update is pending
+  int x_pending;
+  double alpha_prev;  // alpha of the pending step
 };
 
 // A tile: a block of work of one problem (elements, groups or entries);
@@ -158,8 +162,9 @@ struct ProbDev {
   const uint8_t* mult;  // [nloc] multiplicity m
   // gather-scatter plan
   GsPlan gs;
-  // vectors (vector type)
-  void *x, *r, *z, *p, *w;
+  // vectors (vector type); p_alt: the second direction buffer (the
+  // search direction of step k is kept in p for even k, p_alt for odd k)
+  void *x, *r, *z, *p, *w, *p_alt;
   // FP64 right-hand side of the current (inner) solve and its scale
   const double* rhs64;
   double rhs_scale;  // r = rhs64 * rhs_scale

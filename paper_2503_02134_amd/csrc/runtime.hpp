@@ -19,9 +19,11 @@ namespace mx {
 // launchers (defined in the .hip files)
 hipError_t launch_ax_apply(int prec, int N, int E, int epb, const void* u, void* w, const void* G,
                            const void* hB, const void* D, hipStream_t s);
+// parity: -1 updates p in place; 0 / 1 the step's parity with two direction
+// buffers (see ProbDev::p_alt)
 hipError_t launch_ax_solver(int prec, int dm, int N, const Tile* tiles, int ntiles, const ProbDev* probs,
                             int epb, hipStream_t s, hipEvent_t ev0 = nullptr,
-                            hipEvent_t ev1 = nullptr);
+                            hipEvent_t ev1 = nullptr, int parity = -1);
 int max_epb(int N);
 int ax_wave_elements(int N);
 // pairwise: the summation order of a pairwise exchange between the mesh's
@@ -70,8 +72,13 @@ hipError_t launch_nn_fwd(int N, const float* r, const float* dinv, const uint8_t
                          const float* W1, const float* W2, float* zc, int E, hipStream_t s,
                          const State* st, const void* packed, NnDots dd, int* nparts);
 // dm: DotMode of the dots (FP32 vectors; FP64 vectors take DOT_F64)
+// parity: -1 x += alpha p every step; 0 defers x (pending); 1 adds both
+// steps' alpha p
 hipError_t launch_update(int vprec, int pc, const Tile* tiles, int ntiles, const ProbDev* probs,
-                         hipStream_t s, int dm = DOT_F64);
+                         hipStream_t s, int dm = DOT_F64, int parity = -1);
+// x += alpha_prev p for the problems whose last step left x pending
+hipError_t launch_x_pending(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs,
+                            hipStream_t s);
 hipError_t launch_init(int vprec, int pc, const Tile* tiles, int ntiles, const ProbDev* probs,
                        const double* x0, hipStream_t s, int dm = DOT_F64);
 hipError_t launch_fin_rho(const ProbDev* probs, int nprob, int mode, hipStream_t s);
@@ -108,7 +115,7 @@ enum VPrec { VP_F64 = 0, VP_F32 = 1, VP_F32ACC = 3 };
 // precision (shared by every launch plan that contains the problem).
 struct SolverBufs {
   int vprec = 0;
-  void *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *w = nullptr;
+  void *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *w = nullptr, *p_alt = nullptr;
   double *part_ax = nullptr, *part_gs = nullptr, *part_u0 = nullptr, *part_u1 = nullptr,
          *part_u2 = nullptr;
   int nt_upd = 0, nt_gs = 0;

@@ -68,6 +68,7 @@ int ensure_bufs(mxsem_mesh* m, int vprec, SolverBufs** out) {
   A(&b->z, es * nl);
   A(&b->p, es * nl);
   A(&b->w, es * nl);
+  if (vprec == VP_F64) A(&b->p_alt, es * nl);  // second direction buffer (FP64 only)
   A((void**)&b->part_ax, sizeof(double) * (m->E + 1));  // any tile size fits
   A((void**)&b->part_gs, sizeof(double) * (b->nt_gs + 1));
   A((void**)&b->part_u0, sizeof(double) * (b->nt_upd + 1));
@@ -176,6 +177,7 @@ int plan_build(mxsem_mesh* const* meshes, int P, int vprec, Plan** out) {
     Q.z = b->z;
     Q.p = b->p;
     Q.w = b->w;
+    Q.p_alt = b->p_alt;
     Q.part_ax = b->part_ax;
     Q.part_gs = b->part_gs;
     Q.part_u0 = b->part_u0;
@@ -256,23 +258,33 @@ bool plan_stale(const Plan* pl) {
 }
 
 // operator launches of one iteration; skip_first: the first class is
-// launched by the caller (timed)
-int enqueue_ax(Plan* pl, int gprec, hipStream_t s, bool skip_first) {
+// launched by the caller (timed).  par: the step's parity with two direction
+// buffers, -1 with one.
+int enqueue_ax(Plan* pl, int gprec, hipStream_t s, bool skip_first, int par = -1) {
   const int kprec = pl->vprec == VP_F64 ? 0 : gprec;
   for (size_t c = skip_first ? 1 : 0; c < pl->ax.size(); ++c) {
     const AxClass& ac = pl->ax[c];
-    MX_HIP(launch_ax_solver(kprec, pl->dm, ac.N, ac.tiles, ac.ntiles, pl->probs, ac.epb, s));
+    MX_HIP(launch_ax_solver(kprec, pl->dm, ac.N, ac.tiles, ac.ntiles, pl->probs, ac.epb, s,
+                            nullptr, nullptr, par));
   }
   return MXSEM_OK;
 }
 
-static int enqueue_tail(Plan* pl, int pc, hipStream_t s) {
+static int enqueue_tail(Plan* pl, int pc, hipStream_t s, int par) {
   MX_HIP(launch_gs_solver(pl->vprec, pl->tiles_gs, pl->nt_gs, pl->probs, s, false, pl->P, nullptr,
                           0, pl->pairwise != 0));
-  MX_HIP(launch_update(pl->vprec, pc, pl->tiles_upd, pl->nt_upd, pl->probs, s, pl->dm));
+  MX_HIP(launch_update(pl->vprec, pc, pl->tiles_upd, pl->nt_upd, pl->probs, s, pl->dm, par));
   MX_HIP(launch_fin_rho(pl->probs, pl->P, 0, s));
   return MXSEM_OK;
 }
+
+// Two direction buffers (x updated every second step from both steps'
+// alpha p) for FP64 vectors: the vector pass moves 16 B/dof less every two
+// steps.  With FP32 vectors the second 4 B/dof buffer does not fit beside
+// the reused vectors in the 256 MB last-level cache and the gather-scatter
+// loses more than the vector pass gains, so they keep one buffer updated in
+// place.  With an even K every graph launch starts at an even step.
+static bool two_dir(const Plan* pl, int K) { return pl->vprec == VP_F64 && K % 2 == 0; }
 
 // K iterations; the first iteration's operator launches stay outside
 static int get_graph(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K) {
@@ -288,9 +300,11 @@ static int get_graph(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K) {
   hipGraph_t g = nullptr;
   MX_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   int rc = MXSEM_OK;
+  const bool two_p = two_dir(pl, K);
   for (int k = 0; k < K && rc == MXSEM_OK; ++k) {
-    if (k > 0) rc = enqueue_ax(pl, gprec, cs, false);
-    if (rc == MXSEM_OK) rc = enqueue_tail(pl, pc, cs);
+    const int par = two_p ? k % 2 : -1;
+    if (k > 0) rc = enqueue_ax(pl, gprec, cs, false, par);
+    if (rc == MXSEM_OK) rc = enqueue_tail(pl, pc, cs, par);
   }
   hipError_t e = hipStreamEndCapture(cs, &g);
   if (rc != MXSEM_OK) {
@@ -365,12 +379,13 @@ static int run_inner(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K, Inner& 
   MX_HIP(launch_fin_rho(pl->probs, P, 1, s));
   MX_TRY(get_graph(pl, ctx, gprec, pc, K));
   const int kprec = pl->vprec == VP_F64 ? 0 : gprec;
+  const int par0 = two_dir(pl, K) ? 0 : -1;
   for (int l = 0; l < max_launch; ++l) {
     // the chunk's first operator launch of class 0, with its own start/end events
     const AxClass& a0 = pl->ax[0];
     MX_HIP(launch_ax_solver(kprec, pl->dm, a0.N, a0.tiles, a0.ntiles, pl->probs, a0.epb, s,
-                            pl->evA, pl->evB));
-    MX_TRY(enqueue_ax(pl, gprec, s, true));
+                            pl->evA, pl->evB, par0));
+    MX_TRY(enqueue_ax(pl, gprec, s, true, par0));
     MX_HIP(hipGraphLaunch(pl->graph, s));
     MX_HIP(hipMemcpyAsync(pl->hstate, pl->states, sizeof(State) * P, hipMemcpyDeviceToHost, s));
     MX_HIP(hipStreamSynchronize(s));
@@ -382,6 +397,8 @@ static int run_inner(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K, Inner& 
     for (int p = 0; p < P; ++p) all = all && pl->hstate[p].done;
     if (all) break;
   }
+  // a problem that stopped after an even step still owes x its last alpha p
+  if (par0 == 0) MX_HIP(launch_x_pending(pl->vprec, pl->tiles_upd, pl->nt_upd, pl->probs, s));
   in.iterations.assign(P, 0);
   in.reason.assign(P, 0);
   in.res.assign(P, 0.0);

@@ -279,18 +279,32 @@ __device__ inline uchar4 ld_u8x4_nt(const uint8_t* src) {
 // Each thread handles UPD_PER_THREAD entries as 4-wide vectors when the
 // problem's entry count is a multiple of 4, else one by one (decided per
 // problem, so a problem is reduced the same way alone or in a batch).
+// par: -1 x += alpha p (p updated in place by the operator kernel); with two
+// direction buffers, 0 (even step) leaves x for the next step and records
+// alpha as pending, 1 (odd step) adds alpha_prev p (the even step's
+// direction, in p) and then alpha p_alt: the same two roundings, in the same
+// order, as two steps of the first form.
 template <typename T, int DM, int PC>
 __global__ void __launch_bounds__(UPD_THREADS) update_kernel(const Tile* __restrict__ tiles,
-                                                             const ProbDev* __restrict__ probs) {
+                                                             const ProbDev* __restrict__ probs,
+                                                             int par) {
   __shared__ double sred[16];
   const Tile t = tiles[blockIdx.x];
   const ProbDev& P = probs[t.prob];
-  if (gcast(P.st)->done) return;
-  const T alpha = (T)gcast(P.st)->alpha;
+  const gptr<State> stp = gcast(P.st);
+  if (stp->done) return;
+  const T alpha = (T)stp->alpha;
+  const T alpha0 = par == 1 ? (T)stp->alpha_prev : T(0);
+  if (par >= 0 && t.first == 0 && threadIdx.x == 0) {
+    // read only by later launches (the next step's update, the host)
+    if (par == 0) stp->alpha_prev = stp->alpha;
+    stp->x_pending = par == 0 ? 1 : 0;
+  }
   gptr<T> __restrict__ x = gcast((T*)P.x);
   gptr<T> __restrict__ r = gcast((T*)P.r);
   gptr<T> __restrict__ z = gcast((T*)P.z);
   const gptr<const T> __restrict__ p = gcast((const T*)P.p);
+  const gptr<const T> __restrict__ p1 = gcast((const T*)(par == 1 ? P.p_alt : P.p));
   const gptr<const T> __restrict__ w = gcast((const T*)P.w);
   const gptr<const T> __restrict__ dinv = gcast((const T*)P.dinv);
   const gptr<const uint8_t> __restrict__ mult = gcast(P.mult);
@@ -301,12 +315,20 @@ __global__ void __launch_bounds__(UPD_THREADS) update_kernel(const Tile* __restr
     for (int q = 0; q < UPD_PER_THREAD / 4; ++q) {
       const int64_t v = (int64_t)t.first / 4 + q * UPD_THREADS + threadIdx.x;
       if (4 * v < P.nloc) {
-        VT xv = ld4_nt<VT>((const T*)&((const VT*)x)[v]), pv = ((const VT*)p)[v],
-           rv = ld4_nt<VT>((const T*)&((const VT*)r)[v]), wv = ((const VT*)w)[v];
+        VT rv = ld4_nt<VT>((const T*)&((const VT*)r)[v]), wv = ((const VT*)w)[v];
         const uchar4 mv = ld_u8x4_nt((const uint8_t*)&((const uchar4*)mult)[v]);
-        xv.x += alpha * pv.x; xv.y += alpha * pv.y; xv.z += alpha * pv.z; xv.w += alpha * pv.w;
+        if (par != 0) {
+          VT xv = ld4_nt<VT>((const T*)&((const VT*)x)[v]);
+          if (par == 1) {
+            const VT pv = ((const VT*)p)[v];
+            xv.x += alpha0 * pv.x; xv.y += alpha0 * pv.y; xv.z += alpha0 * pv.z;
+            xv.w += alpha0 * pv.w;
+          }
+          const VT pv = ((const VT*)p1)[v];
+          xv.x += alpha * pv.x; xv.y += alpha * pv.y; xv.z += alpha * pv.z; xv.w += alpha * pv.w;
+          st4_nt<VT>((T*)&((VT*)x)[v], xv);
+        }
         rv.x -= alpha * wv.x; rv.y -= alpha * wv.y; rv.z -= alpha * wv.z; rv.w -= alpha * wv.w;
-        st4_nt<VT>((T*)&((VT*)x)[v], xv);
         st4_nt<VT>((T*)&((VT*)r)[v], rv);
         const double c0 = cweight(mv.x), c1 = cweight(mv.y), c2 = cweight(mv.z),
                      c3 = cweight(mv.w);
@@ -333,9 +355,13 @@ __global__ void __launch_bounds__(UPD_THREADS) update_kernel(const Tile* __restr
     for (int q = 0; q < UPD_PER_THREAD; ++q) {
       const int64_t i = (int64_t)t.first + q * UPD_THREADS + threadIdx.x;
       if (i < P.nloc) {
-        const T xv = x[i] + alpha * p[i];
+        if (par != 0) {
+          T xv = x[i];
+          if (par == 1) xv += alpha0 * p[i];
+          xv += alpha * p1[i];
+          x[i] = xv;
+        }
         const T rv = r[i] - alpha * w[i];
-        x[i] = xv;
         r[i] = rv;
         const double c = cweight(mult[i]);
         rr.addw(rv, c, rv);
@@ -380,6 +406,7 @@ __global__ void init_kernel(const Tile* __restrict__ tiles, const ProbDev* __res
       r[i] = rv;
       x[i] = x0 ? (T)x0[i] : T(0);
       p[i] = T(0);
+      if (P.p_alt) gcast((T*)P.p_alt)[i] = T(0);
       const double c = cweight(gcast(P.mult)[i]);
       rr.addw(rv, c, rv);
       if constexpr (PC >= 0) {
@@ -777,25 +804,56 @@ hipError_t launch_gs_solver(int vprec, const Tile* tiles, int ntiles, const Prob
 
 template <typename T, int DM>
 static void upd_dispatch(int pc, dim3 g, dim3 b, hipStream_t s, const Tile* tiles,
-                         const ProbDev* probs) {
+                         const ProbDev* probs, int par) {
   if (pc == MXSEM_PC_JACOBI)
-    hipLaunchKernelGGL((update_kernel<T, DM, 1>), g, b, 0, s, tiles, probs);
+    hipLaunchKernelGGL((update_kernel<T, DM, 1>), g, b, 0, s, tiles, probs, par);
   else if (pc == MXSEM_PC_IDENTITY)
-    hipLaunchKernelGGL((update_kernel<T, DM, 0>), g, b, 0, s, tiles, probs);
+    hipLaunchKernelGGL((update_kernel<T, DM, 0>), g, b, 0, s, tiles, probs, par);
   else
-    hipLaunchKernelGGL((update_kernel<T, DM, -1>), g, b, 0, s, tiles, probs);
+    hipLaunchKernelGGL((update_kernel<T, DM, -1>), g, b, 0, s, tiles, probs, par);
 }
 
 // dm: DotMode of the dots (FP64 vectors: DOT_F64 only)
 hipError_t launch_update(int vprec, int pc, const Tile* tiles, int ntiles, const ProbDev* probs,
-                         hipStream_t s, int dm) {
+                         hipStream_t s, int dm, int par) {
   dim3 g(ntiles), b(UPD_THREADS);
   if (vprec == 0 && dm != DOT_F64) return hipErrorInvalidValue;
-  if (vprec == 0) upd_dispatch<double, DOT_F64>(pc, g, b, s, tiles, probs);
-  else if (dm == DOT_F64) upd_dispatch<float, DOT_F64>(pc, g, b, s, tiles, probs);
-  else if (dm == DOT_F32) upd_dispatch<float, DOT_F32>(pc, g, b, s, tiles, probs);
-  else if (dm == DOT_DOT2) upd_dispatch<float, DOT_DOT2>(pc, g, b, s, tiles, probs);
+  if (par < -1 || par > 1) return hipErrorInvalidValue;
+  if (vprec == 0) upd_dispatch<double, DOT_F64>(pc, g, b, s, tiles, probs, par);
+  else if (dm == DOT_F64) upd_dispatch<float, DOT_F64>(pc, g, b, s, tiles, probs, par);
+  else if (dm == DOT_F32) upd_dispatch<float, DOT_F32>(pc, g, b, s, tiles, probs, par);
+  else if (dm == DOT_DOT2) upd_dispatch<float, DOT_DOT2>(pc, g, b, s, tiles, probs, par);
   else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// x += alpha_prev p where the problem's last step left x pending
+template <typename T>
+__global__ void __launch_bounds__(UPD_THREADS) x_pending_kernel(const Tile* __restrict__ tiles,
+                                                                const ProbDev* __restrict__ probs) {
+  const Tile t = tiles[blockIdx.x];
+  const ProbDev& P = probs[t.prob];
+  const gptr<const State> st = gcast((const State*)P.st);
+  if (!st->x_pending) return;
+  const T a = (T)st->alpha_prev;
+  gptr<T> __restrict__ x = gcast((T*)P.x);
+  const gptr<const T> __restrict__ p = gcast((const T*)P.p);
+#pragma unroll
+  for (int q = 0; q < UPD_PER_THREAD; ++q) {
+    const int64_t i = (int64_t)t.first + q * UPD_THREADS + threadIdx.x;
+    if (i < P.nloc) x[i] += a * p[i];
+  }
+}
+
+hipError_t launch_x_pending(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs,
+                            hipStream_t s) {
+  if (ntiles == 0) return hipSuccess;
+  if (vprec == 0)
+    hipLaunchKernelGGL((x_pending_kernel<double>), dim3(ntiles), dim3(UPD_THREADS), 0, s, tiles,
+                       probs);
+  else
+    hipLaunchKernelGGL((x_pending_kernel<float>), dim3(ntiles), dim3(UPD_THREADS), 0, s, tiles,
+                       probs);
   return hipGetLastError();
 }
 
