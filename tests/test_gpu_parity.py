@@ -186,15 +186,19 @@ def test_fp64_pcg_box4_N7(orc, mx, ctx):
     assert rel_l2(xg.cpu().numpy(), xo, om.c) <= 1e-11
 
 
-def test_fp64_same_iterates(orc, mx, ctx):
-    """After exactly k iterations the FP64 iterates agree to rounding."""
-    log("FP64 iterates, 30 iterations, deformed ne=3 N=9")
+@pytest.mark.parametrize("maxit,chunk", [(30, 7), (30, 16), (31, 16), (33, 8)])
+def test_fp64_same_iterates(orc, mx, ctx, maxit, chunk):
+    """After exactly k iterations the FP64 iterates agree to rounding: with
+    one direction buffer (odd graph chunk) and with two (even chunk), the
+    latter stopping after an odd step and after an even one (whose pending
+    x update is applied after the solve)."""
+    log(f"FP64 iterates, {maxit} iterations, graph chunk {chunk}, deformed ne=3 N=9")
     bmg, gm, bmo, om, fg, fo = make_pair(orc, mx, ctx, 3, 9, 12, rhs="random", rhs_seed=3)
     bo = om.rhs(fo)
-    xo, so = om.pcg(bo, tol=0.0, maxit=30)
-    xg, sg = gm.solve(gm.mass_rhs(_t(fg)), mode=mx.MODE_FP64, tol=0.0, max_iter=30,
-                      graph_chunk=7)
-    assert sg.iterations == 30 and sg.reason == mx.MAX_ITER
+    xo, so = om.pcg(bo, tol=0.0, maxit=maxit)
+    xg, sg = gm.solve(gm.mass_rhs(_t(fg)), mode=mx.MODE_FP64, tol=0.0, max_iter=maxit,
+                      graph_chunk=chunk)
+    assert sg.iterations == maxit and sg.reason == mx.MAX_ITER
     assert rel_l2(xg.cpu().numpy(), xo) <= 1e-12
 
 
