@@ -9,8 +9,8 @@
  * problem: set up a mesh of E hexahedral elements of order N (Sec. 4,
  * Nekbone solves a Poisson problem on high-order elements; Sec. 5, Neko on
  * hexahedra), apply the matrix-free operator A (Sec. 4.1, CG-loop profiling
- * table, the "ax" line), gather-scatter / direct stiffness summation QQ^T
- * (Sec. 4.2.1), the weighted dot glsc3 (same table, lines 3, 6, 9), the
+ * table, its "ax" row), gather-scatter / direct stiffness summation QQ^T
+ * (Sec. 4.2.1), the weighted dot glsc3 (same table, its glsc3 rows), the
  * Jacobi preconditioner 1/diag(A) (Sec. 5.2) and the (P)CG solve with a
  * stopping tolerance (Sec. 6).  The mixed modes keep the gather-scatter sums
  * and the dot products in FP64 while the loop body runs in FP32 (Sec. 4.2.1

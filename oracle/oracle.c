@@ -11,12 +11,12 @@
  * operator steps below are the textbook spectral-element method):
  *   - GLL nodes/weights and the nodal derivative matrix (the tensor-product
  *     basis behind local_grad3 / local_grad3_t, Sec. 4.1, CG-loop profiling
- *     table, line "ax" and its footnote on mxm and accumulations);
+ *     table, its "ax" row and that row's footnote on mxm and accumulations);
  *   - isoparametric geometric factors G and mass B (initialisation, kept in
  *     FP64 per Sec. 5.2);
  *   - the local operator w_L = sum_ab D_a^T diag(G_ab) D_b u_L + h B u_L;
  *   - direct stiffness summation QQ^T (Sec. 4.2.1) and the Dirichlet mask;
- *   - the c-weighted dot glsc3 (CG-loop profiling table, lines 3/6/9);
+ *   - the c-weighted dot glsc3 (CG-loop profiling table, its glsc3 rows);
  *   - the Jacobi diagonal 1/diag(A) (Sec. 5.2, Jacobi paragraph);
  *   - PCG in the order of the CG-loop profiling table (textbook form),
  *     FP64 iterative refinement around an inner PCG, and flexible CG(1).

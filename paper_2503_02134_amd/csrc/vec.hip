@@ -1,7 +1,7 @@
 // Gather-scatter (direct stiffness summation QQ^T, Sec. 4.2.1), the
-// Dirichlet mask, the c-weighted dots (glsc3, Sec. 4.1 CG-loop profiling
-// table lines 3/6/9), the fused CG vector pass (add2s2 x2 + Jacobi
-// z = dinv r + two dots, lines 7-9 and the preconditioner line), the
+// Dirichlet mask, the c-weighted dots (the glsc3 rows of the CG-loop
+// profiling table, Sec. 4.1), the fused CG vector pass (the two add2s2
+// rows, the preconditioner and the following dots of that table), the
 // device-side scalar updates of (P)CG, and the small casts of iterative
 // refinement.
 //
