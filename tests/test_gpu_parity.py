@@ -289,3 +289,62 @@ def test_full_size_local_operator_sampled(orc, mx, ctx):
     assert np.max(np.abs(got64 - ref)) <= 1e-12 * sc
     ref32 = om.ax_local(us.astype(np.float32).astype(np.float64))
     assert np.max(np.abs(got32 - ref32)) <= 2e-5 * sc
+
+
+@pytest.mark.slow
+def test_full_size_solve_sampled_residual(orc, mx, ctx):
+    """The benchmark solve itself (32^3 deformed elements, N = 7, mixed
+    FP32/FP64 refinement to 1e-10, graph chunks of 16): on sampled elements
+    the oracle recomputes b and b - A x from the returned x.  Each sampled
+    element is taken with every element that shares a node with it, so the
+    oracle's assembled sums are complete on the sample.  The HIP path's FP64
+    residual must agree there entry by entry, the reported relative residual
+    must be the c-weighted norm of that residual, and the sample's share of
+    the residual norm cannot exceed the whole."""
+    from paper_2503_02134_amd import workloads as W
+    wl = W.WORKLOADS["box32_N7_deformed"]
+    log("full-size 32^3 N7 mixed solve, sampled residual")
+    xg, _ = mx.mxsem_gll(wl.N)
+    bmg = W.box_mesh(wl.ne, wl.N, xg, seed=wl.deform_seed)
+    gm = mx.Mesh(ctx, bmg.E, wl.N, bmg.xyz, bmg.glo, bmg.bnd)
+    b = gm.mass_rhs(_t(W.manufactured(bmg)[0]))
+    x, st = gm.solve(b, mode=mx.MODE_MIXED_IR, tol=wl.tol, max_iter=20000, graph_chunk=16)
+    assert st.reason == mx.CONVERGED and st.rel_res <= wl.tol
+    r = (b - gm.apply(x, mx.F64)).cpu().numpy()
+    bh = b.cpu().numpy()
+    xh = x.cpu().numpy()
+    E, n3 = bmg.E, (wl.N + 1) ** 3
+    glo = np.asarray(bmg.glo, dtype=np.int64).reshape(E, n3)
+    c = 1.0 / np.bincount(glo.reshape(-1))[glo.reshape(-1)]
+    assert abs(np.sqrt(np.sum(c * r * r) / np.sum(c * bh * bh)) - st.rel_res) <= 1e-6 * st.rel_res
+    del bmg, gm, x, b
+
+    xo, _ = orc.gll(wl.N)
+    bmo = W.box_mesh(wl.ne, wl.N, xo, seed=wl.deform_seed)
+    fo = W.manufactured(bmo)[0].reshape(E, n3)
+    rng = np.random.default_rng(31)
+    sample = np.unique(np.concatenate([[0, E // 2 + wl.ne // 2, E - 1],
+                                       rng.choice(E, 21, replace=False)]))
+    near = np.isin(glo, np.unique(glo[sample])).any(axis=1)
+    near[sample] = True
+    closure = np.nonzero(near)[0]
+    _, sub = np.unique(glo[closure], return_inverse=True)
+    om = orc.Mesh(len(closure), wl.N, np.asarray(bmo.xyz).reshape(E, -1)[closure],
+                  sub.reshape(len(closure), n3),
+                  np.asarray(bmo.bnd, dtype=np.uint8).reshape(E, n3)[closure])
+    bo = om.rhs(fo[closure].reshape(-1)).reshape(-1, n3)
+    ro = bo - om.apply(xh.reshape(E, n3)[closure].reshape(-1)).reshape(-1, n3)
+    pos = np.searchsorted(closure, sample)
+    bo_s, ro_s = bo[pos], ro[pos]
+    sc = np.max(np.abs(bo_s))
+    assert np.max(np.abs(bh.reshape(E, n3)[sample] - bo_s)) <= 1e-13 * sc
+    # b - A x cancels down to about 1e-12 of b, so its rounding error scales
+    # with the terms of A x: bounded here by max|A s| (s a continuous random
+    # sign vector, an estimate of the operator's infinity norm) times max|x|
+    sg = np.random.default_rng(32).choice([-1.0, 1.0], size=sub.max() + 1)
+    anorm = np.max(np.abs(om.apply(om.mask_apply(sg[sub]))))
+    xs = xh.reshape(E, n3)[closure]
+    assert np.max(np.abs(r.reshape(E, n3)[sample] - ro_s)) <= 1e-12 * anorm * np.max(np.abs(xs))
+    cs = c.reshape(E, n3)[sample]
+    share = np.sqrt(np.sum(cs * ro_s * ro_s))
+    assert share <= 1.001 * st.rel_res * np.sqrt(np.sum(c * bh * bh)) + 1e-12 * sc
