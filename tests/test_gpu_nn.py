@@ -210,3 +210,59 @@ def test_trained_network_gains_over_jacobi(orc, mx, ctx):
         assert nl <= 0.85 * nj
     net.close()
     gm.close()
+
+
+@pytest.mark.slow
+def test_full_size_forward_sampled(orc, mx, ctx):
+    """The network forward on the learned benchmark's mesh (24^3 elements,
+    N = 7, log-normal k, Helmholtz h = 1: the persistent grid's workgroups
+    take about 18 elements each, where the small meshes above give each
+    workgroup at most one).  On sampled elements the oracle assembles z from
+    every element within two node-sharing layers of the sample: the first
+    layer holds every element whose output reaches a sampled node, the
+    second completes the first layer's Jacobi diagonal, which scales the
+    network's inputs.  Same tolerances as the small-mesh forward."""
+    from paper_2503_02134_amd.learned import Network
+    wl = W.WORKLOADS["box24_N7_lognormal_helmholtz"]
+    log("full-size 24^3 N7 nn forward, sampled")
+    xg, _ = mx.mxsem_gll(wl.N)
+    bmg = W.box_mesh(wl.ne, wl.N, xg, seed=wl.deform_seed)
+    gm = mx.Mesh(ctx, bmg.E, wl.N, bmg.xyz, bmg.glo, bmg.bnd,
+                 kcoef=W.lognormal_k(bmg, wl.k_seed), helm_h=wl.helm_h)
+    E, n3 = bmg.E, (wl.N + 1) ** 3
+    glo = np.asarray(bmg.glo, dtype=np.int64).reshape(E, n3)
+    bnd = np.asarray(bmg.bnd, dtype=np.uint8).reshape(E, n3)
+    g = np.random.default_rng(41).standard_normal(glo.max() + 1)
+    r = np.where(bnd != 0, 0.0, g[glo])  # continuous, zero on Dirichlet nodes
+    W1, W2 = W.he_normal_weights(11)
+    net = Network(gm, W1, W2)
+    z = net.forward(torch.as_tensor(r.reshape(-1), dtype=torch.float32,
+                                    device="cuda")).cpu().numpy().reshape(E, n3)
+    net.close()
+    del gm, bmg
+
+    xo, _ = orc.gll(wl.N)
+    bmo = W.box_mesh(wl.ne, wl.N, xo, seed=wl.deform_seed)
+    ko = np.asarray(W.lognormal_k(bmo, wl.k_seed)).reshape(E, n3)
+    rng = np.random.default_rng(42)
+    sample = np.unique(np.concatenate([[0, E // 2 + wl.ne // 2, E - 1],
+                                       rng.choice(E, 21, replace=False)]))
+    l1 = np.isin(glo, np.unique(glo[sample])).any(axis=1)
+    l1[sample] = True
+    l2 = np.isin(glo, np.unique(glo[l1])).any(axis=1)
+    l2[l1] = True
+    closure = np.nonzero(l2)[0]
+    _, sub = np.unique(glo[closure], return_inverse=True)
+    om = orc.Mesh(len(closure), wl.N, np.asarray(bmo.xyz).reshape(E, -1)[closure],
+                  sub.reshape(len(closure), n3), bnd[closure], kcoef=ko[closure],
+                  helm_h=wl.helm_h)
+    onn = orc.NN(W1, W2)
+    pos = np.searchsorted(closure, sample)
+    zo = onn.apply(om, r[closure].reshape(-1)).reshape(-1, n3)[pos].reshape(-1)
+    jac = (om.dinv.reshape(-1, n3)[pos] * r[sample]).reshape(-1)
+    zs = z[sample].reshape(-1)
+    cg, co = zs - jac, zo - jac
+    log(f"  {len(sample)} sampled elements, closure {len(closure)}: rel L2 z "
+        f"{rel_l2(zs, zo):.2e}; correction cos {_cos(cg, co):.6f} rel {rel_l2(cg, co):.2e}")
+    assert rel_l2(zs, zo) <= 1e-2
+    assert _cos(cg, co) >= 0.999 and rel_l2(cg, co) <= 3e-2
