@@ -260,6 +260,51 @@ def test_zero_rhs(orc, mx, ctx):
     assert st.reason == mx.CONVERGED and float(x.abs().max()) == 0.0
 
 
+
+def test_rejects_empty_mesh_and_bad_order(mx, ctx):
+    """E = 0, orders outside 1..15 and a negative or non-finite Helmholtz
+    coefficient are refused before any device work."""
+    for E, N, hh, code in [(0, 3, 0.0, mx.EINVAL), (1, 0, 0.0, mx.ENOTSUP),
+                           (1, 16, 0.0, mx.ENOTSUP), (1, 2, -1.0, mx.EINVAL),
+                           (1, 2, float("nan"), mx.EINVAL)]:
+        n3 = (N + 1) ** 3
+        with pytest.raises(mx.MxsemError) as ei:
+            mx.mxsem_mesh_create(ctx.h, E, N, np.zeros(3 * E * n3), np.zeros(E * n3, np.int64),
+                                 np.zeros(E * n3, np.uint8), None, hh)
+        assert ei.value.code == code, (E, N, hh)
+
+
+@pytest.mark.parametrize("ne,N", [(1, 1), (1, 2), (2, 1)])
+def test_no_or_one_unknown(orc, mx, ctx, ne, N):
+    """Degenerate meshes: one element of order 1 has every node on the
+    Dirichlet boundary (no unknown: x = 0 at once); one element of order 2
+    has one unknown with one copy, 2^3 elements of order 1 one unknown with
+    eight copies.  With one unknown Jacobi PCG is exact after one step,
+    x = b / diag(A) there, as in the oracle's solve."""
+    log(f"degenerate mesh ne={ne} N={N}")
+    bmg, gm, bmo, om, fg, fo = make_pair(orc, mx, ctx, ne, N, None)
+    nloc, ngroups, nmasked, _ = gm.info()
+    free = ~om.mask
+    assert nmasked == int(np.count_nonzero(om.mask))
+    bo = om.rhs(fo)
+    bg = gm.mass_rhs(_t(fg))
+    for mode in ("MODE_FP64", "MODE_MIXED_IR"):
+        x, st = gm.solve(bg, mode=getattr(mx, mode), tol=1e-10, max_iter=50)
+        x = x.cpu().numpy()
+        assert st.reason == mx.CONVERGED, mode
+        assert np.all(x[~free] == 0.0)
+        if not free.any():
+            assert nmasked == nloc and np.all(x == 0.0) and st.iterations == 0
+            continue
+        xo, so = om.pcg(bo, tol=1e-10, maxit=50)
+        exact = om.dinv * bo
+        assert so.iterations == 1
+        assert np.max(np.abs(xo - exact)) <= 1e-14 * np.max(np.abs(exact))
+        assert np.max(np.abs(x - exact)) <= 1e-13 * np.max(np.abs(exact)), mode
+        if mode == "MODE_FP64":
+            assert st.iterations == 1
+
+
 # ------------------------------------------------------------------ full size
 @pytest.mark.slow
 def test_full_size_local_operator_sampled(orc, mx, ctx):
