@@ -75,3 +75,23 @@ def test_product_path_has_no_oracle_dependency():
                 txt = open(os.path.join(dp, f)).read()
                 assert "import oracle" not in txt and "liboracle" not in txt, f
                 assert "from oracle" not in txt, f
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without the built library every call fails at once (no CPU path):
+    a fresh interpreter whose library path points at a missing file."""
+    import subprocess
+    import sys
+    code = (
+        "from paper_2503_02134_amd import mxsem\n"
+        f"mxsem.LIB_PATH = {str(tmp_path / 'libmxsem.so')!r}\n"
+        "try:\n"
+        "    mxsem.mxsem_gll(3)\n"
+        "except RuntimeError as e:\n"
+        "    print('raised:', e)\n"
+        "else:\n"
+        "    print('no error')\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         timeout=120)
+    assert out.returncode == 0, out.stderr
+    assert "raised:" in out.stdout and "is not built" in out.stdout
