@@ -7,7 +7,9 @@ refinement loop).  value = local dofs x (inner + outer iterations) per
 second over the timed steps.  Inputs are resident in HBM before timing.
 
 Beside it: the same rate over unique nodes, the FP64 solve on the same GPU,
-the same refinement with BF16 geometric factors, time-to-1e-8,
+the same refinement with BF16 geometric factors and with the inner
+direction rounded to BF16 every step (an ablation of BF16 operator
+inputs), time-to-1e-8,
 energy-to-solution (the GPU package's energy counter around repeated FP64
 and mixed solves), the roofline of the dominant kernel (the fused operator
 kernel of the inner loop: the first operator launch of every graph chunk
@@ -48,8 +50,9 @@ def main():
     ap.add_argument("--workload", default="box32_N7_deformed",
                     help="box4_N7 | box16_N9_deformed | box32_N7_deformed | "
                          "box24_N7_lognormal_helmholtz | box20_N7 | batch64")
-    ap.add_argument("--mode", default="mixed_ir", choices=["mixed_ir", "mixed_ir_bf16g", "fp64",
-                                                           "mixed", "learned", "strategies"])
+    ap.add_argument("--mode", default="mixed_ir", choices=["mixed_ir", "mixed_ir_bf16g",
+                                                           "mixed_ir_bf16p", "fp64", "mixed",
+                                                           "learned", "strategies"])
     ap.add_argument("--dot", default="fp64", choices=["fp64", "fp32", "dot2"],
                     help="accumulation of the FP32 loop's dots (mixed / mixed_ir modes)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -79,7 +82,8 @@ def main():
         return bench_strategies(args)
     wl = W.WORKLOADS[args.workload]
     modes = {"mixed_ir": mx.MODE_MIXED_IR, "mixed_ir_bf16g": mx.MODE_MIXED_IR_BF16G,
-             "fp64": mx.MODE_FP64, "mixed": mx.MODE_MIXED}
+             "mixed_ir_bf16p": mx.MODE_MIXED_IR_BF16P, "fp64": mx.MODE_FP64,
+             "mixed": mx.MODE_MIXED}
     mode = modes[args.mode]
     ctx = mx.Context(0)
     t0 = time.perf_counter()
@@ -167,6 +171,17 @@ def main():
                                                / torch.linalg.vector_norm(x64)),
             "ax_us": round(sb.ax_ms * 1e3, 2),
             "ax_gbs": round(nloc * bb / (sb.ax_ms * 1e-3) / 1e9, 1) if sb.ax_ms > 0 else None}
+        # ablation of BF16 operator inputs: the inner direction p rounded to
+        # BF16 every step (numerics only; the vectors stay FP32 in memory)
+        xp = torch.zeros_like(b)
+        _, sp = mesh.solve(b, xp, mode=mx.MODE_MIXED_IR_BF16P, tol=wl.tol, max_iter=20000,
+                           graph_chunk=16)
+        extra["mixed_ir_bf16p"] = {
+            "ms": round(sp.ms, 3), "iterations": sp.iterations, "outer": sp.outer,
+            "reason": sp.reason, "fallback_used": sp.fallback_used, "rel_res": sp.rel_res,
+            "gain_vs_fp64": round(s64.ms / sp.ms, 3),
+            "rel_diff_vs_fp64_solution": float(torch.linalg.vector_norm((xp - x64).double())
+                                               / torch.linalg.vector_norm(x64))}
     tt = {}
     opts64 = dict(mode=mx.MODE_FP64, tol=wl.tol, max_iter=20000, graph_chunk=16)
     for name, kw in (("fp64", opts64), (args.mode, opts)):

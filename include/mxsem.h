@@ -80,9 +80,14 @@ typedef enum {
   MXSEM_MODE_MIXED_IR = 2,       /* MIXED inner PCG inside FP64 iterative
                                     refinement with FP64 residuals           */
   MXSEM_MODE_MIXED_IR_BF16G = 3, /* as MIXED_IR, inner operator reads BF16 G */
-  MXSEM_MODE_FP32_ALL = 4        /* ablation: FP32 gather-scatter sums and FP32
+  MXSEM_MODE_FP32_ALL = 4,       /* ablation: FP32 gather-scatter sums and FP32
                                     dot accumulation (the configuration the
                                     paper finds to stagnate)                 */
+  MXSEM_MODE_MIXED_IR_BF16P = 5  /* ablation of BF16 operator inputs: as
+                                    MIXED_IR, with the inner PCG's direction
+                                    p rounded to BF16 (nearest even) each
+                                    step, so the operator, sigma and the x
+                                    update all see the BF16 value; PCG only */
 } mxsem_mode;
 
 typedef enum { MXSEM_METHOD_PCG = 0, MXSEM_METHOD_FCG = 1 } mxsem_method;

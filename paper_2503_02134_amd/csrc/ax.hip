@@ -79,8 +79,10 @@ __device__ inline void elem_sync() {
 
 // Solver variant: p = z + beta p_old (beta from the device state, p
 // written back), w = A_L p, and the workgroup's partial sum of p.w,
-// accumulated as DotMode DM says.
-template <int N, typename T, typename TG, bool SOLVER, int DM>
+// accumulated as DotMode DM says.  PB (an ablation of the solver variant):
+// p is rounded to the nearest BF16 value before it is stored and used, so
+// the whole step works with a direction held in BF16.
+template <int N, typename T, typename TG, bool SOLVER, int DM, bool PB = false>
 __global__ void __launch_bounds__(256) ax_kernel(const Tile* __restrict__ tiles, const ProbDev* __restrict__ probs,
                           AxApplyArgs apply, int epb) {
   constexpr int n = N + 1, n2 = n * n, n3 = n2 * n;
@@ -151,6 +153,7 @@ __global__ void __launch_bounds__(256) ax_kernel(const Tile* __restrict__ tiles,
 #pragma unroll
       for (int k = 0; k < n; ++k) {
         T pv = Z[base + k * n2] + beta * U[base + k * n2];
+        if constexpr (PB) pv = bf16_round(pv);
         Pw[base + k * n2] = pv;
         u[k] = pv;
       }
@@ -258,7 +261,7 @@ constexpr int ax2_epw() {  // elements per wave
   return 64 / ((N + 1) * ((N + 1) / 2));
 }
 
-template <int N, typename T, typename TG, bool SOLVER, int DM>
+template <int N, typename T, typename TG, bool SOLVER, int DM, bool PB = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) ax2_kernel(const Tile* __restrict__ tiles, const ProbDev* __restrict__ probs,
                            AxApplyArgs apply, int epb) {
   constexpr int n = N + 1, n2 = n * n, n3 = n2 * n, hn = n / 2, TPE = n * hn, EPW = 64 / TPE;
@@ -335,8 +338,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
       gptr<T> __restrict__ Pw = gcast((T*)(apply.parity == 1 ? P->p_alt : P->p));
 #pragma unroll
       for (int k = 0; k < n; ++k) {
-        const T p0 = Z[base0 + k * n2] + beta * U[base0 + k * n2];
-        const T p1 = Z[base1 + k * n2] + beta * U[base1 + k * n2];
+        T p0 = Z[base0 + k * n2] + beta * U[base0 + k * n2];
+        T p1 = Z[base1 + k * n2] + beta * U[base1 + k * n2];
+        if constexpr (PB) {
+          p0 = bf16_round(p0);
+          p1 = bf16_round(p1);
+        }
         Pw[base0 + k * n2] = p0;
         Pw[base1 + k * n2] = p1;
         u0[k] = p0;
@@ -445,7 +452,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
 
 // With ev0/ev1 the launch records its own start and end (hipExtLaunchKernel),
 // so the elapsed time between them is the kernel's execution time.
-template <int N, typename T, typename TG, bool SOLVER, int DM>
+template <int N, typename T, typename TG, bool SOLVER, int DM, bool PB>
 static hipError_t launch_one(const Tile* tiles, const ProbDev* probs, const AxApplyArgs& a,
                              int ntiles, int epb, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   constexpr int n = N + 1, n2 = n * n;
@@ -455,10 +462,10 @@ static hipError_t launch_one(const Tile* tiles, const ProbDev* probs, const AxAp
     if (epb < 1 || waves > 4) return hipErrorInvalidConfiguration;
     const size_t shm = sizeof(T) * (n2 + (size_t)waves * EPW * 3 * n2);
     if (ev0)
-      hipExtLaunchKernelGGL((ax2_kernel<N, T, TG, SOLVER, DM>), dim3(ntiles), dim3(64 * waves),
+      hipExtLaunchKernelGGL((ax2_kernel<N, T, TG, SOLVER, DM, PB>), dim3(ntiles), dim3(64 * waves),
                             (uint32_t)shm, s, ev0, ev1, 0, tiles, probs, a, epb);
     else
-      hipLaunchKernelGGL((ax2_kernel<N, T, TG, SOLVER, DM>), dim3(ntiles), dim3(64 * waves), shm, s,
+      hipLaunchKernelGGL((ax2_kernel<N, T, TG, SOLVER, DM, PB>), dim3(ntiles), dim3(64 * waves), shm, s,
                          tiles, probs, a, epb);
     return hipGetLastError();
   }
@@ -466,22 +473,22 @@ static hipError_t launch_one(const Tile* tiles, const ProbDev* probs, const AxAp
   if (epb < 1 || threads > 256) return hipErrorInvalidConfiguration;
   size_t shm = sizeof(T) * (n2 + (size_t)epb * 3 * n2);
   if (ev0)
-    hipExtLaunchKernelGGL((ax_kernel<N, T, TG, SOLVER, DM>), dim3(ntiles), dim3(threads), (uint32_t)shm,
+    hipExtLaunchKernelGGL((ax_kernel<N, T, TG, SOLVER, DM, PB>), dim3(ntiles), dim3(threads), (uint32_t)shm,
                           s, ev0, ev1, 0, tiles, probs, a, epb);
   else
-    hipLaunchKernelGGL((ax_kernel<N, T, TG, SOLVER, DM>), dim3(ntiles), dim3(threads), shm, s, tiles,
+    hipLaunchKernelGGL((ax_kernel<N, T, TG, SOLVER, DM, PB>), dim3(ntiles), dim3(threads), shm, s, tiles,
                        probs, a, epb);
   return hipGetLastError();
 }
 
-template <typename T, typename TG, bool SOLVER, int DM = DOT_F64>
+template <typename T, typename TG, bool SOLVER, int DM = DOT_F64, bool PB = false>
 static hipError_t dispatch(int N, const Tile* tiles, const ProbDev* probs, const AxApplyArgs& a,
                            int ntiles, int epb, hipStream_t s, hipEvent_t ev0 = nullptr,
                            hipEvent_t ev1 = nullptr) {
   switch (N) {
 #define MX_CASE(NN) \
   case NN:          \
-    return launch_one<NN, T, TG, SOLVER, DM>(tiles, probs, a, ntiles, epb, s, ev0, ev1);
+    return launch_one<NN, T, TG, SOLVER, DM, PB>(tiles, probs, a, ntiles, epb, s, ev0, ev1);
     MX_CASE(1) MX_CASE(2) MX_CASE(3) MX_CASE(4) MX_CASE(5) MX_CASE(6) MX_CASE(7) MX_CASE(8)
     MX_CASE(9) MX_CASE(10) MX_CASE(11) MX_CASE(12) MX_CASE(13) MX_CASE(14) MX_CASE(15)
 #undef MX_CASE
@@ -519,6 +526,9 @@ hipError_t launch_ax_solver(int prec, int dm, int N, const Tile* tiles, int ntil
     case 0: return dispatch<double, double, true>(N, tiles, probs, a, ntiles, epb, s, ev0, ev1);
     case 1: return dispatch<float, float, true>(N, tiles, probs, a, ntiles, epb, s, ev0, ev1);
     case 2: return dispatch<float, bf16_t, true>(N, tiles, probs, a, ntiles, epb, s, ev0, ev1);
+    case 3:
+      return dispatch<float, float, true, DOT_F64, true>(N, tiles, probs, a, ntiles, epb, s, ev0,
+                                                         ev1);
     default: return hipErrorInvalidValue;
   }
 }

@@ -62,6 +62,9 @@ __host__ __device__ inline bf16_t float_to_bf16(float f) {
   return (bf16_t)(v.u >> 16);
 }
 
+// the nearest BF16 value, as an FP32 (round to nearest even, finite inputs)
+__device__ inline float bf16_round(float f) { return bf16_to_float(float_to_bf16(f)); }
+
 template <typename T>
 __device__ inline T load_as(const T* p) {
   return *p;

@@ -120,12 +120,13 @@ int default_epb(int N) {
   return best;
 }
 
+// gprec: 0 FP64, 1 FP32, 2 BF16, 3 FP32 (the BF16-direction ablation)
 const void* G_ptr(const mxsem_mesh* m, int gprec) {
-  return gprec == 0 ? (const void*)m->G64 : gprec == 1 ? (const void*)m->G32 : (const void*)m->G16;
+  return gprec == 0 ? (const void*)m->G64 : gprec == 2 ? (const void*)m->G16 : (const void*)m->G32;
 }
 const void* hB_ptr(const mxsem_mesh* m, int gprec) {
   if (m->helm_h == 0.0) return nullptr;
-  return gprec == 0 ? (const void*)m->hB64 : gprec == 1 ? (const void*)m->hB32 : (const void*)m->hB16;
+  return gprec == 0 ? (const void*)m->hB64 : gprec == 2 ? (const void*)m->hB16 : (const void*)m->hB32;
 }
 
 int ensure_tmp(mxsem_mesh* m) {

@@ -38,6 +38,7 @@ int gprec_of_mode(int mode) {
   switch (mode) {
     case MXSEM_MODE_FP64: return 0;
     case MXSEM_MODE_MIXED_IR_BF16G: return 2;
+    case MXSEM_MODE_MIXED_IR_BF16P: return 3;
     default: return 1;
   }
 }
@@ -620,7 +621,8 @@ static int solve_many(mxsem_ctx* ctx, const std::vector<mxsem_mesh*>& meshes, Ge
                       pl->dnorm + p, s));
   MX_TRY(norms_of(pl, ctx, bnorm));
   for (double& v : bnorm) v = sqrt(v);
-  const bool ir = mode == MXSEM_MODE_MIXED_IR || mode == MXSEM_MODE_MIXED_IR_BF16G;
+  const bool ir = mode == MXSEM_MODE_MIXED_IR || mode == MXSEM_MODE_MIXED_IR_BF16G ||
+                  mode == MXSEM_MODE_MIXED_IR_BF16P;
   const int xv = vprec == VP_F64 ? 0 : 1;
   Inner in;
   in.rhs.assign(P, nullptr);
@@ -832,20 +834,22 @@ int mxsem_precond(mxsem_mesh* m, mxsem_pc pc, mxsem_prec io, const void* r, void
 static int check_opts(const mxsem_solve_opts* o) {
   MX_CHECK(o->tol >= 0.0 && o->max_iter >= 1 && o->graph_chunk >= 1 && o->graph_chunk <= 256,
            MXSEM_EINVAL, "solve: bad tol / max_iter / graph_chunk");
-  MX_CHECK(o->mode >= MXSEM_MODE_FP64 && o->mode <= MXSEM_MODE_FP32_ALL, MXSEM_EINVAL,
+  MX_CHECK(o->mode >= MXSEM_MODE_FP64 && o->mode <= MXSEM_MODE_MIXED_IR_BF16P, MXSEM_EINVAL,
            "solve: unknown mode");
   MX_CHECK(o->pc == MXSEM_PC_IDENTITY || o->pc == MXSEM_PC_JACOBI || o->pc == MXSEM_PC_LEARNED,
            MXSEM_EINVAL, "solve: unknown preconditioner");
   MX_CHECK(o->max_outer >= 0 && o->inner_tol > 0.0 && o->inner_tol < 1.0, MXSEM_EINVAL,
            "solve: bad refinement options");
   MX_CHECK(!o->x0_given || o->mode == MXSEM_MODE_FP64 || o->mode == MXSEM_MODE_MIXED_IR ||
-               o->mode == MXSEM_MODE_MIXED_IR_BF16G,
+               o->mode == MXSEM_MODE_MIXED_IR_BF16G || o->mode == MXSEM_MODE_MIXED_IR_BF16P,
            MXSEM_ENOTSUP, "solve: x0 is supported in the FP64 and refinement modes");
   MX_CHECK(o->dot >= MXSEM_DOT_DEFAULT && o->dot <= MXSEM_DOT_DOT2, MXSEM_EINVAL,
            "solve: unknown dot accumulation");
   MX_CHECK(o->gs_order == MXSEM_GS_ORDER_ONE || o->gs_order == MXSEM_GS_ORDER_PAIRWISE,
            MXSEM_EINVAL, "solve: unknown gather-scatter order");
   const bool pcg = o->method == MXSEM_METHOD_PCG && o->pc != MXSEM_PC_LEARNED;
+  MX_CHECK(o->mode != MXSEM_MODE_MIXED_IR_BF16P || pcg, MXSEM_ENOTSUP,
+           "solve: the BF16-direction ablation is for PCG");
   MX_CHECK(o->dot == MXSEM_DOT_DEFAULT || o->dot == MXSEM_DOT_F64 ||
                (pcg && (o->mode == MXSEM_MODE_MIXED || o->mode == MXSEM_MODE_MIXED_IR ||
                         o->mode == MXSEM_MODE_FP32_ALL)),

@@ -30,6 +30,7 @@ F64, F32, BF16G_F32 = 0, 1, 2
 PC_IDENTITY, PC_JACOBI, PC_LEARNED = 0, 1, 2
 # modes
 MODE_FP64, MODE_MIXED, MODE_MIXED_IR, MODE_MIXED_IR_BF16G, MODE_FP32_ALL = 0, 1, 2, 3, 4
+MODE_MIXED_IR_BF16P = 5
 METHOD_PCG, METHOD_FCG = 0, 1
 CONVERGED, MAX_ITER, STAGNATED, BREAKDOWN = 1, 2, 3, 4
 LOCAL_ONLY, MASK, GS_PAIRWISE = 1, 2, 4
@@ -39,7 +40,8 @@ GS_ORDER_ONE, GS_ORDER_PAIRWISE = 0, 1
 VIEW_F64, VIEW_F32, VIEW_BF16 = 1, 2, 4
 
 MODE_NAMES = {MODE_FP64: "fp64", MODE_MIXED: "mixed", MODE_MIXED_IR: "mixed_ir",
-              MODE_MIXED_IR_BF16G: "mixed_ir_bf16g", MODE_FP32_ALL: "fp32_all"}
+              MODE_MIXED_IR_BF16G: "mixed_ir_bf16g", MODE_FP32_ALL: "fp32_all",
+              MODE_MIXED_IR_BF16P: "mixed_ir_bf16p"}
 
 
 class MxsemError(RuntimeError):

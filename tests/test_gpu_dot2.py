@@ -124,7 +124,10 @@ def test_solve_option_checks(orc, mx, ctx):
            dict(mode=mx.MODE_MIXED_IR, gs_order=mx.GS_ORDER_PAIRWISE),
            dict(mode=mx.MODE_FP64, gs_order=mx.GS_ORDER_PAIRWISE),
            dict(mode=mx.MODE_MIXED, dot=7),
-           dict(mode=mx.MODE_MIXED, gs_order=2)]
+           dict(mode=mx.MODE_MIXED, gs_order=2),
+           dict(mode=mx.MODE_MIXED_IR_BF16P, dot=mx.DOT_DOT2),
+           dict(mode=mx.MODE_MIXED_IR_BF16P, method=mx.METHOD_FCG),
+           dict(mode=6)]
     for kw in bad:
         with pytest.raises(mx.MxsemError):
             gm.solve(b, tol=1e-8, max_iter=50, **kw)
