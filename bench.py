@@ -6,7 +6,9 @@ Jacobi-PCG with FP64 gather-scatter sums and dots, FP64 residuals in the
 refinement loop).  value = local dofs x (inner + outer iterations) per
 second over the timed steps.  Inputs are resident in HBM before timing.
 
-Beside it: the same rate over unique nodes, the FP64 solve on the same GPU,
+Beside it: the same rate over unique nodes, the FP64 solve on the same GPU
+(like the time-to-1e-8 solves, the median of as many solves as timed steps,
+at most five, after a warm-up),
 the same refinement with BF16 geometric factors and with the inner
 direction rounded to BF16 every step (an ablation of BF16 operator
 inputs), time-to-1e-8,
@@ -144,16 +146,33 @@ def main():
     traffic_bytes = nloc * bytes_per_dof
     achieved = traffic_bytes / (ax_avg_ms * 1e-3) / 1e9 if ax_avg_ms > 0 else 0.0
 
-    # FP64 solve and time-to-1e-8
+    # FP64 solve and time-to-1e-8: one warm-up solve, then the median of
+    # reps solves from x = 0 (reps = the timed steps, at most 5)
+    reps = max(1, min(5, args.steps))
+
+    def median_solve(xv, kw, warm=True):
+        if warm:
+            xv.zero_()
+            mesh.solve(b, xv, **kw)
+        runs = []
+        for _ in range(reps):
+            xv.zero_()
+            _, st_ = mesh.solve(b, xv, **kw)
+            runs.append(st_)
+        return sorted(runs, key=lambda r: r.ms)[len(runs) // 2]
+
     extra = {}
     x64 = torch.zeros_like(b)
-    _, s64 = mesh.solve(b, x64, mode=mx.MODE_FP64, tol=wl.tol, max_iter=20000, graph_chunk=16)
+    opts64 = dict(mode=mx.MODE_FP64, tol=wl.tol, max_iter=20000, graph_chunk=16)
+    s64 = median_solve(x64, opts64)
     extra["fp64"] = {"iterations": s64.iterations, "ms": round(s64.ms, 3),
                      "gdof_iter_s": round(nloc * s64.iterations / (s64.ms * 1e-3) / 1e9, 3),
-                     "rel_res": s64.rel_res, "ax_us": round(s64.ax_ms * 1e3, 2)}
-    mstep = stats[-1]
+                     "rel_res": s64.rel_res, "ax_us": round(s64.ax_ms * 1e3, 2),
+                     "median_of": reps}
+    mstep = sorted(stats, key=lambda r: r.ms)[len(stats) // 2]
     extra["time_to_solution_ms"] = {"fp64": round(s64.ms, 3), args.mode: round(mstep.ms, 3),
-                                    "gain": round(s64.ms / mstep.ms, 3)}
+                                    "gain": round(s64.ms / mstep.ms, 3),
+                                    "median_of": {"fp64": reps, args.mode: len(stats)}}
     d = (x_mixed - x64).double()
     extra["rel_diff_vs_fp64_solution"] = float(torch.linalg.vector_norm(d)
                                                / torch.linalg.vector_norm(x64))
@@ -183,12 +202,11 @@ def main():
             "rel_diff_vs_fp64_solution": float(torch.linalg.vector_norm((xp - x64).double())
                                                / torch.linalg.vector_norm(x64))}
     tt = {}
-    opts64 = dict(mode=mx.MODE_FP64, tol=wl.tol, max_iter=20000, graph_chunk=16)
     for name, kw in (("fp64", opts64), (args.mode, opts)):
         xt = torch.zeros_like(b)
-        _, st8 = mesh.solve(b, xt, **dict(kw, tol=1e-8))
+        st8 = median_solve(xt, dict(kw, tol=1e-8), warm=False)
         tt[name] = {"ms": round(st8.ms, 3), "iterations": st8.iterations, "outer": st8.outer,
-                    "rel_res": st8.rel_res}
+                    "rel_res": st8.rel_res, "median_of": reps}
     extra["time_to_1e-8"] = tt
     log(f"fp64: {extra['fp64']}; tt1e-8: {tt}")
 
