@@ -437,6 +437,10 @@ __global__ void __launch_bounds__(NN_THREADS, NN_FWD_WG_PER_CU)
       xo[q] = xsrc[base + tid + q * NN_THREADS];
       po[q] = psrc[base + tid + q * NN_THREADS];
     }
+    // raised wave priority for the matrix-core phase: a wave that has begun
+    // its MFMA sequence keeps the SIMD's issue slots ahead of waves in their
+    // load and store phases (300 learned steps: 60.2 -> 58.9 ms)
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int mp = 0; mp < 4; mp += 2) {
       floatx16_t acc[2] = {{0}, {0}};
@@ -497,6 +501,7 @@ __global__ void __launch_bounds__(NN_THREADS, NN_FWD_WG_PER_CU)
           U[wa[mp + t2][sg]] = sum;
         }
     }
+    __builtin_amdgcn_s_setprio(0);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
