@@ -1,6 +1,6 @@
 """HIP path vs the FP64 oracle, element by element, through the C ABI.
 
-Tolerances (derived in DESIGN.md, "Parity tolerances"):
+Tolerances (each derived from the arithmetic of the kernel it bounds):
   FP64 kernels            max|diff| <= 1e-12 * max|ref|  (FMA and order only)
   FP32 operator           max|diff| <= 2e-5 * max|ref|   (~(4n+15) roundings of 2^-24)
   BF16-G operator         max|diff| <= 2e-2 * max|ref|   (G rounded to 2^-9 relative)
