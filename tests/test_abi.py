@@ -95,3 +95,21 @@ def test_missing_library_fails_loudly(tmp_path):
                          timeout=120)
     assert out.returncode == 0, out.stderr
     assert "raised:" in out.stdout and "is not built" in out.stdout
+
+
+def test_binding_constants_match_header():
+    """Every enum value and integer #define of include/mxsem.h has the same
+    value under the binding's name (the header name without MXSEM_)."""
+    from paper_2503_02134_amd import mxsem
+    src = open(os.path.join(ROOT, "include", "mxsem.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    vals = {}
+    for name, v in re.findall(r"\bMXSEM_([A-Z0-9_]+)\s*=\s*(-?\d+)", src):
+        vals[name] = int(v)
+    for name, v in re.findall(r"#define\s+MXSEM_([A-Z0-9_]+)\s+\(?(-?\d+)u?\)?", src):
+        vals[name] = int(v)
+    assert len(vals) >= 35
+    missing = [n for n in vals if not hasattr(mxsem, n)]
+    assert missing == [], missing
+    for n, v in vals.items():
+        assert getattr(mxsem, n) == v, n
