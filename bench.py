@@ -562,7 +562,7 @@ def bench_learned(args):
 
 
 def bench_strategies(args):
-    """The mixed-precision strategies of Sec. 4.2.1-4.2.2 on one GPU: the
+    """The mixed-precision strategies of Sec. 4.2.1 and Sec. 5.2.1 on one GPU: the
     FP32 CG loop with the gather-scatter sums in FP32 or FP64, the dots in
     FP32, FP64 or compensated FP32 (Dot2), and the gather-scatter in one
     order per node or in the summation order of a pairwise exchange between

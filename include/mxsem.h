@@ -92,7 +92,7 @@ typedef enum {
 
 typedef enum { MXSEM_METHOD_PCG = 0, MXSEM_METHOD_FCG = 1 } mxsem_method;
 
-/* ---- accumulation of the dot products of the FP32 loop (Sec. 4.2.2) ------ */
+/* ---- accumulation of the dot products of the FP32 loop (Sec. 5.2.1) ------ */
 typedef enum {
   MXSEM_DOT_DEFAULT = 0, /* the mode's own: FP32 in MXSEM_MODE_FP32_ALL, else FP64 */
   MXSEM_DOT_F64 = 1,     /* FP32 inputs, products and sums in FP64           */

@@ -380,7 +380,7 @@ double orc_dot(const orc_mesh *m, const double *a, const double *b) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* FP32 reductions of the extended-precision study (Sec. 4.2.2, and the     */
+/* FP32 reductions of the extended-precision study (Sec. 5.2.1, and the     */
 /* gather-scatter modes of Sec. 4.2.1).  The only FP32 routines here: they  */
 /* define what the working-precision variants of the dot products and of    */
 /* the gather-scatter compute.  Compiled with contraction off, so every     */
@@ -765,7 +765,12 @@ int orc_pcg(const orc_mesh *m, int pc, const orc_nn *nn, const double *b,
 /* O14: flexible CG with one-step truncation (Notay's FCG(1)):
  *   same as PCG except that the new direction is A-orthogonalised against
  *   the previous one, beta = -(z_k, A p_{k-1})_c / (p_{k-1}, A p_{k-1})_c,
- *   so the preconditioner may be any map r -> z. */
+ *   so the preconditioner may be any map r -> z.
+ * Fallback (the Jacobi fallback of the learned preconditioner, read for the
+ * FP32 loop's preconditioner of Sec. 5.2): a z whose (r,z)_c is not
+ * positive or not finite, or whose (z, A p)_c is not finite, is replaced by
+ * the Jacobi z for that step, the first z included; st->fallback counts the
+ * replaced steps. */
 int orc_fcg(const orc_mesh *m, int pc, const orc_nn *nn, const double *b,
             double *x, double tol, int maxit, double *history, orc_stats *st) {
   int64_t nl = m->nloc;
@@ -790,8 +795,14 @@ int orc_fcg(const orc_mesh *m, int pc, const orc_nn *nn, const double *b,
     st->reason = ORC_CONVERGED;
   } else {
     precond(m, pc, nn, r, z);
-    memcpy(p, z, sizeof(double) * nl);
     double rho = orc_dot(m, r, z);
+    if (!(rho > 0.0) || !isfinite(rho)) {
+      /* the first z is held to the same descent test as every later one */
+      precond(m, ORC_PC_JACOBI, NULL, r, z);
+      rho = orc_dot(m, r, z);
+      st->fallback += 1;
+    }
+    memcpy(p, z, sizeof(double) * nl);
     stag_t sg = {res, 0};
     for (int it = 1; it <= maxit; ++it) {
       orc_apply(m, p, w);

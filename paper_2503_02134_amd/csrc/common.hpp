@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <new>
 #include <string>
 
 #include "../../include/mxsem.h"
@@ -13,6 +14,32 @@ namespace mx {
 // ---------------------------------------------------------------- errors
 void set_error(const std::string& msg);
 const char* get_error();
+
+// Status of an entry point whose body threw: no C++ exception crosses the C
+// boundary (std::bad_alloc becomes MXSEM_ENOMEM, anything else
+// MXSEM_EINTERNAL).
+inline int api_fail(const char* fn, int code) noexcept {
+  try {
+    set_error(std::string(fn) + (code == MXSEM_ENOMEM ? ": host allocation failed"
+                                                      : ": internal error (C++ exception)"));
+  } catch (...) {
+  }
+  return code;
+}
+}  // namespace mx
+
+// Every int-returning extern "C" function wraps its body in these two.
+#define MX_API_BEGIN try {
+#define MX_API_END(fn)                                   \
+  }                                                      \
+  catch (const std::bad_alloc&) {                        \
+    return ::mx::api_fail(fn, MXSEM_ENOMEM);             \
+  }                                                      \
+  catch (...) {                                          \
+    return ::mx::api_fail(fn, MXSEM_EINTERNAL);          \
+  }
+
+namespace mx {
 
 #define MX_HIP(call)                                                          \
   do {                                                                        \
@@ -222,7 +249,7 @@ __device__ inline A block_sum(A v, A* sred) {
 
 // ---------------------------------------------------------------- dot accumulation
 // Accumulation of the dots of an FP32 iteration (the extended-precision
-// study of Sec. 4.2.2):
+// study of Sec. 5.2.1):
 //   DOT_F64   products and sums in FP64 (the mixed recipe);
 //   DOT_F32   products and sums in FP32, the working precision;
 //   DOT_DOT2  compensated FP32, the Dot2 algorithm of Ogita, Rump and Oishi

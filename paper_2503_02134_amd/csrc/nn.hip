@@ -801,6 +801,7 @@ hipError_t launch_nn_fwd(int N, const float* r, const float* dinv, const uint8_t
                        dinv, mult, (const bf16x8_t*)packed, zc, E, st, dd);
     return hipGetLastError();
   }
+  // N = 3 and 5: one workgroup per element (N = 7 takes the matrix-core kernel above)
   if (nparts) *nparts = E;
   if (dd.dots && E > dd.dstride) return hipErrorInvalidConfiguration;
   switch (N) {
@@ -809,7 +810,7 @@ hipError_t launch_nn_fwd(int N, const float* r, const float* dinv, const uint8_t
     hipLaunchKernelGGL((nn_fwd_kernel<NN_>), dim3(E), dim3(NN_THREADS), fwd_lds<NN_>(), s, r, \
                        dinv, mult, W1, W2, zc, E, st, dd);                                  \
     break;
-    MX_NN(3) MX_NN(5) MX_NN(7)
+    MX_NN(3) MX_NN(5)
 #undef MX_NN
     default:
       return hipErrorInvalidValue;
@@ -896,6 +897,7 @@ int nn_forward_into(mxsem_nn* nn, const float* r, float* out, hipStream_t s) {
 extern "C" {
 
 int mxsem_nn_create(mxsem_mesh* m, const mxsem_nn_desc* d, mxsem_nn** out) {
+  MX_API_BEGIN
   MX_CHECK(m && d && out, MXSEM_EINVAL, "nn_create: null argument");
   MX_CHECK(d->cin == NN_CIN && d->ch == NN_CH, MXSEM_ENOTSUP,
            "nn_create: the network has 2 input and 32 hidden channels");
@@ -940,9 +942,11 @@ int mxsem_nn_create(mxsem_mesh* m, const mxsem_nn_desc* d, mxsem_nn** out) {
   m->ctx->live += 1;
   *out = nn;
   return MXSEM_OK;
+  MX_API_END("mxsem_nn_create")
 }
 
 int mxsem_nn_destroy(mxsem_nn* nn) {
+  MX_API_BEGIN
   if (!nn) return MXSEM_OK;
   (void)hipSetDevice(nn->mesh->ctx->device);
   if (nn->mesh->ctx->stream) (void)hipStreamSynchronize(nn->mesh->ctx->stream);
@@ -952,9 +956,11 @@ int mxsem_nn_destroy(mxsem_nn* nn) {
   if (nn->W) nn->mesh->ctx->live -= 1;
   delete nn;
   return MXSEM_OK;
+  MX_API_END("mxsem_nn_destroy")
 }
 
 int mxsem_nn_set_params(mxsem_nn* nn, const float* W1, const float* W2) {
+  MX_API_BEGIN
   MX_CHECK(nn && W1 && W2, MXSEM_EINVAL, "nn_set_params: null argument");
   MX_HIP(hipSetDevice(nn->mesh->ctx->device));
   hipStream_t s = nn->mesh->ctx->stream;
@@ -968,9 +974,11 @@ int mxsem_nn_set_params(mxsem_nn* nn, const float* W1, const float* W2) {
   MX_HIP(hipGetLastError());
   MX_HIP(hipStreamSynchronize(s));
   return MXSEM_OK;
+  MX_API_END("mxsem_nn_set_params")
 }
 
 int mxsem_nn_get_params(mxsem_nn* nn, float* W1, float* W2) {
+  MX_API_BEGIN
   MX_CHECK(nn && W1 && W2, MXSEM_EINVAL, "nn_get_params: null argument");
   MX_HIP(hipSetDevice(nn->mesh->ctx->device));
   hipStream_t s = nn->mesh->ctx->stream;
@@ -978,17 +986,21 @@ int mxsem_nn_get_params(mxsem_nn* nn, float* W1, float* W2) {
   MX_HIP(hipMemcpyAsync(W2, nn->W + NN_W1, sizeof(float) * NN_W2, hipMemcpyDeviceToHost, s));
   MX_HIP(hipStreamSynchronize(s));
   return MXSEM_OK;
+  MX_API_END("mxsem_nn_get_params")
 }
 
 int mxsem_nn_forward(mxsem_nn* nn, const float* r, float* z) {
+  MX_API_BEGIN
   MX_CHECK(nn && r && z, MXSEM_EINVAL, "nn_forward: null argument");
   MX_HIP(hipSetDevice(nn->mesh->ctx->device));
   (void)hipGetLastError();
   return nn_forward_into(nn, r, z, nn->mesh->ctx->stream);
+  MX_API_END("mxsem_nn_forward")
 }
 
 int mxsem_nn_loss_grad(mxsem_nn* nn, const float* r, const float* e, int nsamp, double* loss_dev,
                        float* grad_dev) {
+  MX_API_BEGIN
   MX_CHECK(nn && r && e && nsamp >= 1 && loss_dev, MXSEM_EINVAL, "nn_loss_grad: bad argument");
   mxsem_mesh* m = nn->mesh;
   MX_HIP(hipSetDevice(m->ctx->device));
@@ -1022,9 +1034,11 @@ int mxsem_nn_loss_grad(mxsem_nn* nn, const float* r, const float* e, int nsamp, 
   if (grad_dev)
     MX_HIP(hipMemcpyAsync(grad_dev, nn->grad, sizeof(float) * NN_NP, hipMemcpyDeviceToDevice, s));
   return MXSEM_OK;
+  MX_API_END("mxsem_nn_loss_grad")
 }
 
 int mxsem_nn_adam_step(mxsem_nn* nn, const mxsem_adam* o) {
+  MX_API_BEGIN
   MX_CHECK(nn && o && o->step >= 1, MXSEM_EINVAL, "nn_adam_step: bad argument");
   MX_HIP(hipSetDevice(nn->mesh->ctx->device));
   (void)hipGetLastError();
@@ -1037,10 +1051,12 @@ int mxsem_nn_adam_step(mxsem_nn* nn, const mxsem_adam* o) {
                      nn->Wq + NN_W1, (bf16x8_t*)nn->packed);
   MX_HIP(hipGetLastError());
   return MXSEM_OK;
+  MX_API_END("mxsem_nn_adam_step")
 }
 
 int mxsem_nn_make_pair(mxsem_mesh* m, const double* b, const double* x, const double* xstar,
                        float* r_out, float* e_out) {
+  MX_API_BEGIN
   MX_CHECK(m && b && x && xstar && r_out && e_out, MXSEM_EINVAL, "nn_make_pair: null argument");
   MX_HIP(hipSetDevice(m->ctx->device));
   (void)hipGetLastError();
@@ -1052,13 +1068,16 @@ int mxsem_nn_make_pair(mxsem_mesh* m, const double* b, const double* x, const do
                      m->scal + 2, r_out, e_out, m->nloc);
   MX_HIP(hipGetLastError());
   return MXSEM_OK;
+  MX_API_END("mxsem_nn_make_pair")
 }
 
 int mxsem_mesh_attach_nn(mxsem_mesh* m, mxsem_nn* nn) {
+  MX_API_BEGIN
   MX_CHECK(m, MXSEM_EINVAL, "mesh_attach_nn: null mesh");
   MX_CHECK(!nn || nn->mesh == m, MXSEM_EINVAL, "mesh_attach_nn: network built for another mesh");
   m->nn = nn;
   return MXSEM_OK;
+  MX_API_END("mxsem_mesh_attach_nn")
 }
 
 }  // extern "C"

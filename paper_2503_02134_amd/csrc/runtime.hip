@@ -180,6 +180,7 @@ const char* mxsem_status_str(int st) {
 }
 
 int mxsem_ctx_create(int hip_device, void* hip_stream, mxsem_ctx** out) {
+  MX_API_BEGIN
   MX_CHECK(out, MXSEM_EINVAL, "ctx_create: out is null");
   *out = nullptr;
   int ndev = 0;
@@ -201,9 +202,11 @@ int mxsem_ctx_create(int hip_device, void* hip_stream, mxsem_ctx** out) {
   }
   *out = c;
   return MXSEM_OK;
+  MX_API_END("mxsem_ctx_create")
 }
 
 int mxsem_ctx_destroy(mxsem_ctx* c) {
+  MX_API_BEGIN
   if (!c) return MXSEM_OK;
   MX_CHECK(c->live == 0, MXSEM_EINVAL, "ctx_destroy: meshes or batches of this context are alive");
   (void)hipSetDevice(c->device);
@@ -215,22 +218,28 @@ int mxsem_ctx_destroy(mxsem_ctx* c) {
   if (c->pinned_flags) (void)hipHostFree(c->pinned_flags);
   delete c;
   return MXSEM_OK;
+  MX_API_END("mxsem_ctx_destroy")
 }
 
 int mxsem_ctx_set_stream(mxsem_ctx* c, void* hip_stream) {
+  MX_API_BEGIN
   MX_CHECK(c, MXSEM_EINVAL, "ctx_set_stream: null ctx");
   c->stream = (hipStream_t)hip_stream;
   return MXSEM_OK;
+  MX_API_END("mxsem_ctx_set_stream")
 }
 
 int mxsem_gll(int N, double* xi, double* w) {
+  MX_API_BEGIN
   MX_CHECK(N >= 1 && N <= MAX_N, MXSEM_ENOTSUP, "gll: N must be in 1..15");
   MX_CHECK(xi && w, MXSEM_EINVAL, "gll: null output");
   gll_rule(N, xi, w);
   return MXSEM_OK;
+  MX_API_END("mxsem_gll")
 }
 
 int mxsem_mesh_destroy(mxsem_mesh* m) {
+  MX_API_BEGIN
   if (!m) return MXSEM_OK;
   (void)hipSetDevice(m->ctx->device);
   if (m->ctx->stream) (void)hipStreamSynchronize(m->ctx->stream);
@@ -241,6 +250,7 @@ int mxsem_mesh_destroy(mxsem_mesh* m) {
   if (m->counted) m->ctx->live -= 1;
   delete m;
   return MXSEM_OK;
+  MX_API_END("mxsem_mesh_destroy")
 }
 
 static int mesh_fail(mxsem_mesh* m, int rc) {
@@ -270,6 +280,7 @@ static int mesh_fail(mxsem_mesh* m, int rc) {
   } while (0)
 
 int mxsem_mesh_create(mxsem_ctx* ctx, const mxsem_mesh_desc* d, mxsem_mesh** out) {
+  MX_API_BEGIN
   MX_CHECK(ctx && d && out, MXSEM_EINVAL, "mesh_create: null argument");
   *out = nullptr;
   MX_CHECK(d->N >= 1 && d->N <= MAX_N, MXSEM_ENOTSUP, "mesh_create: N must be in 1..15");
@@ -486,19 +497,23 @@ int mxsem_mesh_create(mxsem_ctx* ctx, const mxsem_mesh_desc* d, mxsem_mesh** out
   m->counted = true;
   *out = m;
   return MXSEM_OK;
+  MX_API_END("mxsem_mesh_create")
 }
 
 int mxsem_mesh_info(const mxsem_mesh* m, int64_t* nloc, int64_t* ngroups, int64_t* nmasked,
                     double* min_detj) {
+  MX_API_BEGIN
   MX_CHECK(m, MXSEM_EINVAL, "mesh_info: null mesh");
   if (nloc) *nloc = m->nloc;
   if (ngroups) *ngroups = m->ngroups;
   if (nmasked) *nmasked = m->nmask_entries;
   if (min_detj) *min_detj = m->min_det;
   return MXSEM_OK;
+  MX_API_END("mxsem_mesh_info")
 }
 
 int mxsem_mesh_get(const mxsem_mesh* m, int what, double* out) {
+  MX_API_BEGIN
   MX_CHECK(m && out, MXSEM_EINVAL, "mesh_get: null argument");
   hipStream_t s = m->ctx->stream;
   MX_HIP(hipSetDevice(m->ctx->device));
@@ -529,6 +544,7 @@ int mxsem_mesh_get(const mxsem_mesh* m, int what, double* out) {
   }
   MX_HIP(hipStreamSynchronize(s));
   return MXSEM_OK;
+  MX_API_END("mxsem_mesh_get")
 }
 
 static int check_prec_view(const mxsem_mesh* m, int prec) {
@@ -539,15 +555,18 @@ static int check_prec_view(const mxsem_mesh* m, int prec) {
 }
 
 int mxsem_apply(mxsem_mesh* m, mxsem_prec io, const void* u, void* w, unsigned flags) {
+  MX_API_BEGIN
   MX_CHECK(m && u && w, MXSEM_EINVAL, "apply: null argument");
   MX_CHECK(u != w, MXSEM_EINVAL, "apply: u and w must not alias");
   MX_TRY(check_prec_view(m, io));
   MX_HIP(hipSetDevice(m->ctx->device));
   (void)hipGetLastError();
   return apply_impl(m, io, u, w, flags, m->ctx->stream);
+  MX_API_END("mxsem_apply")
 }
 
 int mxsem_gather_scatter(mxsem_mesh* m, mxsem_prec io, mxsem_prec acc, void* v, unsigned flags) {
+  MX_API_BEGIN
   MX_CHECK(m && v, MXSEM_EINVAL, "gather_scatter: null argument");
   MX_CHECK(io == MXSEM_F64 || io == MXSEM_F32, MXSEM_EINVAL, "gather_scatter: io must be F64/F32");
   MX_CHECK(acc == MXSEM_F64 || acc == MXSEM_F32, MXSEM_EINVAL, "gather_scatter: acc must be F64/F32");
@@ -562,19 +581,23 @@ int mxsem_gather_scatter(mxsem_mesh* m, mxsem_prec io, mxsem_prec acc, void* v, 
   MX_HIP(launch_gs_apply(io, acc, v, m->plan, (flags & MXSEM_MASK) != 0, m->ctx->stream,
                          pairwise));
   return MXSEM_OK;
+  MX_API_END("mxsem_gather_scatter")
 }
 
 int mxsem_dot(mxsem_mesh* m, mxsem_prec io, const void* a, const void* b, double* out_dev) {
+  MX_API_BEGIN
   MX_CHECK(m && a && b && out_dev, MXSEM_EINVAL, "dot: null argument");
   MX_CHECK(io == MXSEM_F64 || io == MXSEM_F32, MXSEM_EINVAL, "dot: io must be F64/F32");
   MX_HIP(hipSetDevice(m->ctx->device));
   (void)hipGetLastError();
   MX_HIP(launch_dot(io, a, b, m->mult, m->nloc, m->part, out_dev, m->ctx->stream));
   return MXSEM_OK;
+  MX_API_END("mxsem_dot")
 }
 
 int mxsem_dot_ex(mxsem_mesh* m, mxsem_prec io, int acc, const void* a, const void* b,
                  double* out_dev) {
+  MX_API_BEGIN
   MX_CHECK(m && a && b && out_dev, MXSEM_EINVAL, "dot_ex: null argument");
   MX_CHECK(io == MXSEM_F64 || io == MXSEM_F32, MXSEM_EINVAL, "dot_ex: io must be F64/F32");
   MX_CHECK(acc >= MXSEM_DOT_DEFAULT && acc <= MXSEM_DOT_DOT2, MXSEM_EINVAL,
@@ -586,9 +609,11 @@ int mxsem_dot_ex(mxsem_mesh* m, mxsem_prec io, int acc, const void* a, const voi
   (void)hipGetLastError();
   MX_HIP(launch_dot(io, a, b, m->mult, m->nloc, m->part, out_dev, m->ctx->stream, dm));
   return MXSEM_OK;
+  MX_API_END("mxsem_dot_ex")
 }
 
 int mxsem_mesh_set_ranks(mxsem_mesh* m, const int32_t* rank_host) {
+  MX_API_BEGIN
   MX_CHECK(m, MXSEM_EINVAL, "set_ranks: null mesh");
   MX_HIP(hipSetDevice(m->ctx->device));
   (void)hipGetLastError();
@@ -604,9 +629,11 @@ int mxsem_mesh_set_ranks(mxsem_mesh* m, const int32_t* rank_host) {
   MX_HIP(hipMemcpy(m->erank, rank_host, sizeof(int) * (size_t)m->E, hipMemcpyHostToDevice));
   m->plan.erank = m->erank;
   return MXSEM_OK;
+  MX_API_END("mxsem_mesh_set_ranks")
 }
 
 int mxsem_mass_rhs(mxsem_mesh* m, const double* f, double* b) {
+  MX_API_BEGIN
   MX_CHECK(m && f && b, MXSEM_EINVAL, "mass_rhs: null argument");
   MX_HIP(hipSetDevice(m->ctx->device));
   (void)hipGetLastError();
@@ -614,6 +641,7 @@ int mxsem_mass_rhs(mxsem_mesh* m, const double* f, double* b) {
   MX_HIP(launch_mass(m->B64, f, b, m->nloc, s));
   MX_HIP(launch_gs_apply(MXSEM_F64, MXSEM_F64, b, m->plan, true, s));
   return MXSEM_OK;
+  MX_API_END("mxsem_mass_rhs")
 }
 
 }  // extern "C"

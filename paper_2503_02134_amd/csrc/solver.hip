@@ -815,6 +815,7 @@ void mxsem_solve_opts_default(mxsem_solve_opts* o) {
 }
 
 int mxsem_precond(mxsem_mesh* m, mxsem_pc pc, mxsem_prec io, const void* r, void* z) {
+  MX_API_BEGIN
   MX_CHECK(m && r && z, MXSEM_EINVAL, "precond: null argument");
   MX_HIP(hipSetDevice(m->ctx->device));
   (void)hipGetLastError();
@@ -829,6 +830,7 @@ int mxsem_precond(mxsem_mesh* m, mxsem_pc pc, mxsem_prec io, const void* r, void
   const void* dinv = io == MXSEM_F64 ? (const void*)m->dinv64 : (const void*)m->dinv32;
   MX_HIP(launch_precond(io, pc, r, z, dinv, m->nloc, m->ctx->stream));
   return MXSEM_OK;
+  MX_API_END("mxsem_precond")
 }
 
 static int check_opts(const mxsem_solve_opts* o) {
@@ -865,6 +867,7 @@ static int check_opts(const mxsem_solve_opts* o) {
 
 int mxsem_solve(mxsem_mesh* m, const mxsem_solve_opts* o, const double* b, double* x,
                 mxsem_solve_stats* st) {
+  MX_API_BEGIN
   MX_CHECK(m && o && b && x && st, MXSEM_EINVAL, "solve: null argument");
   MX_TRY(check_opts(o));
   MX_HIP(hipSetDevice(m->ctx->device));
@@ -880,6 +883,7 @@ int mxsem_solve(mxsem_mesh* m, const mxsem_solve_opts* o, const double* b, doubl
   std::vector<mxsem_mesh*> ms{m};
   auto get = [m](int vp, Plan** out) { return get_self_plan(m, vp, out); };
   return solve_many(m->ctx, ms, get, o, &b, &x, st);
+  MX_API_END("mxsem_solve")
 }
 
 // ------------------------------------------------------------------ batch
@@ -887,6 +891,7 @@ int mxsem_autotune_cached(mxsem_ctx* ctx, int N, int E, int prec, const char* pa
 
 int mxsem_batch_create(mxsem_ctx* ctx, int P, mxsem_mesh* const* meshes, const char* tune_cache,
                        mxsem_batch** out) {
+  MX_API_BEGIN
   MX_CHECK(ctx && meshes && out && P >= 1, MXSEM_EINVAL, "batch_create: bad argument");
   *out = nullptr;
   for (int p = 0; p < P; ++p) {
@@ -918,9 +923,11 @@ int mxsem_batch_create(mxsem_ctx* ctx, int P, mxsem_mesh* const* meshes, const c
   ctx->live += 1;
   *out = bt;
   return MXSEM_OK;
+  MX_API_END("mxsem_batch_create")
 }
 
 int mxsem_batch_destroy(mxsem_batch* bt) {
+  MX_API_BEGIN
   if (!bt) return MXSEM_OK;
   (void)hipSetDevice(bt->ctx->device);
   if (bt->ctx->stream) (void)hipStreamSynchronize(bt->ctx->stream);
@@ -929,10 +936,12 @@ int mxsem_batch_destroy(mxsem_batch* bt) {
   bt->ctx->live -= 1;
   delete bt;
   return MXSEM_OK;
+  MX_API_END("mxsem_batch_destroy")
 }
 
 int mxsem_batch_solve(mxsem_batch* bt, const mxsem_solve_opts* o, const double* const* b,
                       double* const* x, mxsem_solve_stats* st) {
+  MX_API_BEGIN
   MX_CHECK(bt && o && b && x && st, MXSEM_EINVAL, "batch_solve: null argument");
   MX_TRY(check_opts(o));
   MX_CHECK(o->pc != MXSEM_PC_LEARNED, MXSEM_ENOTSUP,
@@ -955,6 +964,7 @@ int mxsem_batch_solve(mxsem_batch* bt, const mxsem_solve_opts* o, const double* 
     return MXSEM_OK;
   };
   return solve_many(bt->ctx, bt->meshes, get, o, b, x, st);
+  MX_API_END("mxsem_batch_solve")
 }
 
 }  // extern "C"

@@ -133,6 +133,7 @@ using namespace mx;
 extern "C" {
 
 int mxsem_autotune(mxsem_ctx* ctx, int N, int E, mxsem_prec prec, mxsem_tuning* out) {
+  MX_API_BEGIN
   MX_CHECK(ctx && out, MXSEM_EINVAL, "autotune: null argument");
   MX_CHECK(N >= 1 && N <= MAX_N, MXSEM_ENOTSUP, "autotune: N must be in 1..15");
   MX_CHECK(E >= 1, MXSEM_EINVAL, "autotune: E must be >= 1");
@@ -144,11 +145,13 @@ int mxsem_autotune(mxsem_ctx* ctx, int N, int E, mxsem_prec prec, mxsem_tuning* 
   for (int q = 0; q < 16; ++q) out->epb[q] = 0;
   out->epb[N] = best;
   return MXSEM_OK;
+  MX_API_END("mxsem_autotune")
 }
 
 // Tuned tile for (N, E, prec) from the cache file, autotuned and added to
 // the file when missing.
 int mxsem_autotune_cached(mxsem_ctx* ctx, int N, int E, int prec, const char* path, int* epb) {
+  MX_API_BEGIN
   char key[96];
   snprintf(key, sizeof(key), "gfx950:N%d:E%d:p%d", N, E, prec);
   std::map<std::string, int> kv = read_cache(path);
@@ -163,9 +166,11 @@ int mxsem_autotune_cached(mxsem_ctx* ctx, int N, int E, int prec, const char* pa
   kv[key] = *epb;
   write_cache(path, kv);
   return MXSEM_OK;
+  MX_API_END("mxsem_autotune_cached")
 }
 
 int mxsem_mesh_set_tuning(mxsem_mesh* m, const mxsem_tuning* t) {
+  MX_API_BEGIN
   MX_CHECK(m && t, MXSEM_EINVAL, "mesh_set_tuning: null argument");
   const int e = t->epb[m->N];
   MX_CHECK(e >= 0 && e <= max_epb(m->N), MXSEM_EINVAL,
@@ -174,6 +179,7 @@ int mxsem_mesh_set_tuning(mxsem_mesh* m, const mxsem_tuning* t) {
   m->epb[m->N] = e;
   mesh_drop_plans(m);  // plans are rebuilt with the new tiles on next use
   return MXSEM_OK;
+  MX_API_END("mxsem_mesh_set_tuning")
 }
 
 }  // extern "C"

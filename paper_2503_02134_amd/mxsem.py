@@ -150,15 +150,69 @@ def _check(fn: str, rc: int):
 
 
 def _ptr(t) -> int | None:
+    """Address of a host buffer (numpy array or integer address)."""
     if t is None:
         return None
     if isinstance(t, torch.Tensor):
-        assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA/HIP tensors"
-        return t.data_ptr()
+        raise TypeError("host buffers are numpy arrays; device vectors go through _vec")
     if isinstance(t, np.ndarray):
-        assert t.flags.c_contiguous
+        if not t.flags.c_contiguous:
+            raise ValueError("host arrays must be C-contiguous")
         return t.ctypes.data
     return int(t)
+
+
+# What the binding knows of each live handle, so that every device vector is
+# checked before a call could make a kernel read or write past its end:
+# meshes -> (local entries, device), networks -> mesh, batches -> meshes.
+@dataclass
+class _MeshShape:
+    nloc: int
+    device: int
+
+
+_ctx_device: dict = {}
+_mesh_shape: dict = {}
+_nn_mesh: dict = {}
+_batch_meshes: dict = {}
+NN_PARAMS = 32 * 2 * 27 + 32 * 27
+
+
+def _key(h) -> int:
+    return h.value if isinstance(h, C.c_void_p) else int(h or 0)
+
+
+def _shape(mesh) -> _MeshShape:
+    sh = _mesh_shape.get(_key(mesh))
+    if sh is None:
+        raise ValueError("unknown mesh handle (not created through this binding, or destroyed)")
+    return sh
+
+
+def _io_dtype(io: int):
+    if io == F64:
+        return torch.float64
+    if io in (F32, BF16G_F32):
+        return torch.float32
+    raise ValueError(f"unknown precision {io}")
+
+
+def _vec(t, dtype, n: int, device: int, what: str, at_least: bool = False) -> int:
+    """Data pointer of a device vector after checking, in this order, that it
+    is a torch tensor of the given dtype, contiguous, with n entries (at
+    least n with at_least), on the given device; raises otherwise, before
+    anything is launched."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what}: expected a torch tensor, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise TypeError(f"{what}: dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: tensor must be contiguous")
+    if (t.numel() < n) if at_least else (t.numel() != n):
+        raise ValueError(f"{what}: {t.numel()} entries, expected {'at least ' if at_least else ''}{n}")
+    if t.device.type != "cuda" or (t.device.index or 0) != device:
+        raise ValueError(f"{what}: tensor on {t.device}, expected cuda:{device}")
+    return t.data_ptr()
 
 
 # ---------------------------------------------------------------- C ABI, one to one
@@ -166,11 +220,13 @@ def mxsem_ctx_create(device: int = 0, stream=None):
     h = vp()
     s = torch.cuda.current_stream(device).cuda_stream if stream is None else stream
     _check("mxsem_ctx_create", lib().mxsem_ctx_create(device, s, C.byref(h)))
+    _ctx_device[_key(h)] = int(device)
     return h
 
 
 def mxsem_ctx_destroy(ctx):
     _check("mxsem_ctx_destroy", lib().mxsem_ctx_destroy(ctx))
+    _ctx_device.pop(_key(ctx), None)
 
 
 def mxsem_gll(N: int):
@@ -192,11 +248,13 @@ def mxsem_mesh_create(ctx, E, N, xyz, glo, bnd, kcoef=None, helm_h=0.0,
                         None if kk is None else kk.ctypes.data, float(helm_h), views)
     h = vp()
     _check("mxsem_mesh_create", lib().mxsem_mesh_create(ctx, C.byref(d), C.byref(h)))
+    _mesh_shape[_key(h)] = _MeshShape(E * n3, _ctx_device.get(_key(ctx), 0))
     return h
 
 
 def mxsem_mesh_destroy(mesh):
     _check("mxsem_mesh_destroy", lib().mxsem_mesh_destroy(mesh))
+    _mesh_shape.pop(_key(mesh), None)
 
 
 def mxsem_mesh_info(mesh):
@@ -213,20 +271,35 @@ def mxsem_mesh_get(mesh, what: int, size: int) -> np.ndarray:
     return out
 
 
+def _local(mesh, io, t, what):
+    sh = _shape(mesh)
+    return _vec(t, _io_dtype(io), sh.nloc, sh.device, what)
+
+
+def _scalar64(mesh, t, what):
+    return _vec(t, torch.float64, 1, _shape(mesh).device, what, at_least=True)
+
+
 def mxsem_apply(mesh, prec, u, w, flags=0):
-    _check("mxsem_apply", lib().mxsem_apply(mesh, prec, _ptr(u), _ptr(w), flags))
+    pu, pw = _local(mesh, prec, u, "apply: u"), _local(mesh, prec, w, "apply: w")
+    _check("mxsem_apply", lib().mxsem_apply(mesh, prec, pu, pw, flags))
 
 
 def mxsem_gather_scatter(mesh, io, acc, v, flags=0):
-    _check("mxsem_gather_scatter", lib().mxsem_gather_scatter(mesh, io, acc, _ptr(v), flags))
+    pv = _local(mesh, io, v, "gather_scatter: v")
+    _check("mxsem_gather_scatter", lib().mxsem_gather_scatter(mesh, io, acc, pv, flags))
 
 
 def mxsem_dot(mesh, io, a, b, out_dev):
-    _check("mxsem_dot", lib().mxsem_dot(mesh, io, _ptr(a), _ptr(b), _ptr(out_dev)))
+    pa, pb = _local(mesh, io, a, "dot: a"), _local(mesh, io, b, "dot: b")
+    po = _scalar64(mesh, out_dev, "dot: out")
+    _check("mxsem_dot", lib().mxsem_dot(mesh, io, pa, pb, po))
 
 
 def mxsem_dot_ex(mesh, io, acc, a, b, out_dev):
-    _check("mxsem_dot_ex", lib().mxsem_dot_ex(mesh, io, acc, _ptr(a), _ptr(b), _ptr(out_dev)))
+    pa, pb = _local(mesh, io, a, "dot_ex: a"), _local(mesh, io, b, "dot_ex: b")
+    po = _scalar64(mesh, out_dev, "dot_ex: out")
+    _check("mxsem_dot_ex", lib().mxsem_dot_ex(mesh, io, acc, pa, pb, po))
 
 
 def mxsem_mesh_set_ranks(mesh, ranks):
@@ -240,26 +313,42 @@ def mxsem_mesh_set_ranks(mesh, ranks):
 
 
 def mxsem_precond(mesh, pc, io, r, z):
-    _check("mxsem_precond", lib().mxsem_precond(mesh, pc, io, _ptr(r), _ptr(z)))
+    pr, pz = _local(mesh, io, r, "precond: r"), _local(mesh, io, z, "precond: z")
+    _check("mxsem_precond", lib().mxsem_precond(mesh, pc, io, pr, pz))
 
 
 def mxsem_mass_rhs(mesh, f, b):
-    _check("mxsem_mass_rhs", lib().mxsem_mass_rhs(mesh, _ptr(f), _ptr(b)))
+    pf, pb = _local(mesh, F64, f, "mass_rhs: f"), _local(mesh, F64, b, "mass_rhs: b")
+    _check("mxsem_mass_rhs", lib().mxsem_mass_rhs(mesh, pf, pb))
 
 
 def solve_opts(**kw) -> mxsem_solve_opts:
+    """Options with the library's defaults; history is a device FP64 tensor
+    (checked against the mesh and max_iter when the solve is called)."""
     o = mxsem_solve_opts()
     lib().mxsem_solve_opts_default(C.byref(o))
+    hist = kw.pop("history", None)
     for k, v in kw.items():
-        if k == "history":
-            v = _ptr(v)
         setattr(o, k, v)
+    o._history = hist
+    o.history = None if hist is None else hist.data_ptr()
     return o
 
 
+def _check_history(mesh, opts):
+    hist = getattr(opts, "_history", None)
+    if hist is not None:
+        _vec(hist, torch.float64, opts.max_iter + 1, _shape(mesh).device, "solve: history",
+             at_least=True)
+    elif opts.history:
+        raise ValueError("solve: pass the history as a tensor through solve_opts")
+
+
 def mxsem_solve(mesh, opts: mxsem_solve_opts, b, x) -> mxsem_solve_stats:
+    pb, px = _local(mesh, F64, b, "solve: b"), _local(mesh, F64, x, "solve: x")
+    _check_history(mesh, opts)
     st = mxsem_solve_stats()
-    rc = lib().mxsem_solve(mesh, C.byref(opts), _ptr(b), _ptr(x), C.byref(st))
+    rc = lib().mxsem_solve(mesh, C.byref(opts), pb, px, C.byref(st))
     if rc == EBREAKDOWN:
         return st
     _check("mxsem_solve", rc)
@@ -272,17 +361,26 @@ def mxsem_batch_create(ctx, meshes, tune_cache: str | None = None):
     _check("mxsem_batch_create", lib().mxsem_batch_create(
         ctx, len(meshes), C.cast(arr, vp), None if tune_cache is None else tune_cache.encode(),
         C.byref(h)))
+    _batch_meshes[_key(h)] = [_key(m) for m in meshes]
     return h
 
 
 def mxsem_batch_destroy(batch):
     _check("mxsem_batch_destroy", lib().mxsem_batch_destroy(batch))
+    _batch_meshes.pop(_key(batch), None)
 
 
 def mxsem_batch_solve(batch, opts, bs, xs):
-    P = len(bs)
-    barr = (vp * P)(*[_ptr(b) for b in bs])
-    xarr = (vp * P)(*[_ptr(x) for x in xs])
+    ms = _batch_meshes.get(_key(batch))
+    if ms is None:
+        raise ValueError("unknown batch handle")
+    P = len(ms)
+    if len(bs) != P or len(xs) != P:
+        raise ValueError(f"batch_solve: {P} problems, got {len(bs)} b and {len(xs)} x")
+    if opts.history or getattr(opts, "_history", None) is not None:
+        raise ValueError("batch_solve: no residual history for batches")
+    barr = (vp * P)(*[_local(m, F64, b, f"batch_solve: b[{p}]") for p, (m, b) in enumerate(zip(ms, bs))])
+    xarr = (vp * P)(*[_local(m, F64, x, f"batch_solve: x[{p}]") for p, (m, x) in enumerate(zip(ms, xs))])
     st = (mxsem_solve_stats * P)()
     rc = lib().mxsem_batch_solve(batch, C.byref(opts), C.cast(barr, vp), C.cast(xarr, vp),
                                  C.cast(st, vp))
@@ -308,11 +406,20 @@ def mxsem_nn_create(mesh, ch=32, cin=2):
     d = mxsem_nn_desc(cin, ch)
     h = vp()
     _check("mxsem_nn_create", lib().mxsem_nn_create(mesh, C.byref(d), C.byref(h)))
+    _nn_mesh[_key(h)] = _key(mesh)
     return h
 
 
 def mxsem_nn_destroy(nn):
     _check("mxsem_nn_destroy", lib().mxsem_nn_destroy(nn))
+    _nn_mesh.pop(_key(nn), None)
+
+
+def _nn_shape(nn) -> _MeshShape:
+    m = _nn_mesh.get(_key(nn))
+    if m is None:
+        raise ValueError("unknown network handle")
+    return _shape(m)
 
 
 def mxsem_nn_set_params(nn, W1, W2):
@@ -329,12 +436,22 @@ def mxsem_nn_get_params(nn, ch=32, cin=2):
 
 
 def mxsem_nn_forward(nn, r, z):
-    _check("mxsem_nn_forward", lib().mxsem_nn_forward(nn, _ptr(r), _ptr(z)))
+    sh = _nn_shape(nn)
+    pr = _vec(r, torch.float32, sh.nloc, sh.device, "nn_forward: r")
+    pz = _vec(z, torch.float32, sh.nloc, sh.device, "nn_forward: z")
+    _check("mxsem_nn_forward", lib().mxsem_nn_forward(nn, pr, pz))
 
 
 def mxsem_nn_loss_grad(nn, r, e, nsamp, loss_dev, grad_dev):
-    _check("mxsem_nn_loss_grad", lib().mxsem_nn_loss_grad(nn, _ptr(r), _ptr(e), nsamp,
-                                                           _ptr(loss_dev), _ptr(grad_dev)))
+    sh = _nn_shape(nn)
+    if nsamp < 1:
+        raise ValueError("nn_loss_grad: nsamp must be >= 1")
+    pr = _vec(r, torch.float32, nsamp * sh.nloc, sh.device, "nn_loss_grad: r")
+    pe = _vec(e, torch.float32, nsamp * sh.nloc, sh.device, "nn_loss_grad: e")
+    pl = _vec(loss_dev, torch.float64, 1, sh.device, "nn_loss_grad: loss", at_least=True)
+    pg = (None if grad_dev is None else
+          _vec(grad_dev, torch.float32, NN_PARAMS, sh.device, "nn_loss_grad: grad", at_least=True))
+    _check("mxsem_nn_loss_grad", lib().mxsem_nn_loss_grad(nn, pr, pe, nsamp, pl, pg))
 
 
 def mxsem_nn_adam_step(nn, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, step=1):
@@ -347,8 +464,10 @@ def mxsem_mesh_attach_nn(mesh, nn):
 
 
 def mxsem_nn_make_pair(mesh, b, x, xstar, r_out, e_out):
-    _check("mxsem_nn_make_pair", lib().mxsem_nn_make_pair(mesh, _ptr(b), _ptr(x), _ptr(xstar),
-                                                           _ptr(r_out), _ptr(e_out)))
+    ps = [_local(mesh, F64, t, f"nn_make_pair: {nm}") for t, nm in ((b, "b"), (x, "x"), (xstar, "xstar"))]
+    pr = _local(mesh, F32, r_out, "nn_make_pair: r_out")
+    pe = _local(mesh, F32, e_out, "nn_make_pair: e_out")
+    _check("mxsem_nn_make_pair", lib().mxsem_nn_make_pair(mesh, *ps, pr, pe))
 
 
 # ---------------------------------------------------------------- convenience

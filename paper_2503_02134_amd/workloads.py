@@ -144,6 +144,20 @@ def manufactured(mesh: BoxMesh):
     return mesh.to_local(f), mesh.to_local(u)
 
 
+def neumann_cosine_rhs(mesh: BoxMesh, offset: float = 1e-6) -> np.ndarray:
+    """f = cos(pi x) cos(pi y) cos(pi z) + offset (local layout).
+
+    The cosine product has zero mean on the unit cube, so with no Dirichlet
+    node (pure Neumann Poisson, whose operator annihilates constants) the
+    offset is the part of the source outside the operator's range: the
+    problem has no solution and the CG residual cannot fall below that
+    part.  Used to exercise the stagnation rule."""
+    pts = mesh.gxyz
+    f = (np.cos(np.pi * pts[:, 0]) * np.cos(np.pi * pts[:, 1]) * np.cos(np.pi * pts[:, 2])
+         + offset)
+    return mesh.to_local(f)
+
+
 def random_smooth_rhs(mesh: BoxMesh, seed: int, kmax: int = 4) -> np.ndarray:
     """f = sum_{k in [1,kmax]^3} a_k sin(k1 pi x) sin(k2 pi y) sin(k3 pi z),
     a_k ~ N(0,1)/|k|^2 (seeded), sampled at the nodes (local layout)."""

@@ -113,3 +113,78 @@ def test_binding_constants_match_header():
     assert missing == [], missing
     for n, v in vals.items():
         assert getattr(mxsem, n) == v, n
+
+
+def test_binding_checks_vectors_before_any_launch(mx, monkeypatch):
+    """Every device vector is checked (torch tensor, dtype of the call's
+    precision, contiguous, number of entries, device) before the library is
+    called, so a wrong vector raises instead of letting a kernel run past
+    its end.  A mesh the binding knows of is faked here (no GPU): each bad
+    vector raises, and a vector that passes every other check still raises
+    because it is not on the device."""
+    import torch
+    fake = 0x1234
+    monkeypatch.setitem(mx._mesh_shape, fake, mx._MeshShape(nloc=8, device=0))
+
+    def boom(*a, **k):
+        raise AssertionError("the library was called")
+
+    class _NoLib:
+        def __getattr__(self, name):
+            return boom
+
+    monkeypatch.setattr(mx, "lib", lambda: _NoLib())
+    f64 = torch.zeros(8, dtype=torch.float64)
+    f32 = torch.zeros(8, dtype=torch.float32)
+    cases = [
+        (TypeError, lambda: mx.mxsem_apply(fake, mx.F64, f64.numpy(), f64)),      # not a tensor
+        (TypeError, lambda: mx.mxsem_apply(fake, mx.F64, f32, f64)),              # dtype vs io
+        (TypeError, lambda: mx.mxsem_apply(fake, mx.F32, f64, f32)),
+        (TypeError, lambda: mx.mxsem_apply(fake, mx.BF16G_F32, f64, f64)),
+        (ValueError, lambda: mx.mxsem_apply(fake, mx.F64, torch.zeros(7, dtype=torch.float64), f64)),
+        (ValueError, lambda: mx.mxsem_apply(fake, mx.F64, torch.zeros(16, dtype=torch.float64)[::2], f64)),
+        (ValueError, lambda: mx.mxsem_apply(fake, mx.F64, f64, f64)),             # CPU tensors
+        (TypeError, lambda: mx.mxsem_gather_scatter(fake, mx.F32, mx.F64, f64)),
+        (ValueError, lambda: mx.mxsem_gather_scatter(fake, mx.F64, mx.F64, torch.zeros(9, dtype=torch.float64))),
+        (TypeError, lambda: mx.mxsem_dot(fake, mx.F32, f64, f32, torch.zeros(1, dtype=torch.float64))),
+        (TypeError, lambda: mx._scalar64(fake, torch.zeros(1, dtype=torch.float32), "out")),
+        (ValueError, lambda: mx._scalar64(fake, torch.zeros(0, dtype=torch.float64), "out")),
+        (TypeError, lambda: mx.mxsem_precond(fake, mx.PC_JACOBI, mx.F64, f32, f32)),
+        (TypeError, lambda: mx.mxsem_mass_rhs(fake, f32, f64)),
+        (TypeError, lambda: mx.mxsem_solve(fake, _opts(mx), f32, f64)),
+        (ValueError, lambda: mx.mxsem_solve(fake, _opts(mx), torch.zeros(4, dtype=torch.float64), f64)),
+        (ValueError, lambda: mx.mxsem_nn_make_pair(fake, f64, f64, f64, torch.zeros(3, dtype=torch.float32), f32)),
+        (ValueError, lambda: mx._shape(0x999)),                                   # unknown mesh
+    ]
+    for exc, call in cases:
+        with pytest.raises(exc):
+            call()
+    # a history shorter than max_iter + 1 is refused
+    o = _opts(mx)
+    o.max_iter = 10
+    o._history = torch.zeros(10, dtype=torch.float64)
+    with pytest.raises(ValueError, match="history"):
+        mx._check_history(fake, o)
+    o._history = torch.zeros(11, dtype=torch.float32)
+    with pytest.raises(TypeError, match="history"):
+        mx._check_history(fake, o)
+    # networks: r and e hold nsamp vectors, the gradient every parameter
+    monkeypatch.setitem(mx._nn_mesh, 0x77, fake)
+    loss = torch.zeros(1, dtype=torch.float64)
+    with pytest.raises(ValueError):
+        mx.mxsem_nn_loss_grad(0x77, torch.zeros(8, dtype=torch.float32), f32, 2, loss, None)
+    with pytest.raises(ValueError):
+        mx.mxsem_nn_loss_grad(0x77, torch.zeros(16, dtype=torch.float32),
+                              torch.zeros(16, dtype=torch.float32), 2, loss,
+                              torch.zeros(mx.NN_PARAMS - 1, dtype=torch.float32))
+    with pytest.raises(TypeError):
+        mx.mxsem_nn_forward(0x77, f64, f32)
+
+
+def _opts(mx):
+    """Solve options built without the library (the fake above has none)."""
+    o = mx.mxsem_solve_opts()
+    o.max_iter = 100
+    o._history = None
+    o.history = None
+    return o

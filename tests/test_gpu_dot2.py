@@ -1,4 +1,4 @@
-"""Dot accumulation (FP64, FP32, compensated Dot2; Sec. 4.2.2) and the
+"""Dot accumulation (FP64, FP32, compensated Dot2; Sec. 5.2.1) and the
 gather-scatter summation order (one sum per node, or the pairwise exchange
 between ranks; Sec. 4.2.1) on the GPU, through the C ABI, against the oracle.
 

@@ -1,9 +1,21 @@
 """Learned flexible-CG preconditioner through the C ABI vs the FP64 oracle:
 forward, loss and gradients, Adam, flexible CG, fallback and training.
 
-Tolerances: the network runs with BF16-rounded inputs, weights and hidden
-activations and FP32 accumulation, so its correction carries relative
-errors of a few 2^-9 against the FP64 oracle; the Jacobi part is FP32."""
+Forward tolerance, node by node.  The network rounds its inputs x0, its
+weights and its hidden activations h to BF16 (nearest even, unit roundoff
+u = 2^-8) and accumulates in FP32.  With S1 = sum |W1| |x0| over a hidden
+value's 54 terms and Y1 = sum |W2| S1 over an output's 864 terms:
+  - a product of two BF16-rounded factors is off by at most (2u + u^2)
+    of its magnitude, so a hidden pre-activation is off by (2u + u^2) S1
+    plus the FP32 sum's gamma_54 S1;
+  - ReLU is 1-Lipschitz and h's own rounding adds u |h| <= u S1;
+  - the second layer adds W2's rounding, u |W2| |h|, and gamma_864;
+so |y_gpu - y| <= (4u + 12u^2 + 1e-4) Y1 = 0.0164 Y1.  s_e's own rounding
+cancels (the network is positively homogeneous), the Jacobi part and the
+scaling add FP32 roundings (1e-6 of |dinv r| + s_e Y1), and the assembly
+z = M QQ^T(c zL) adds the copies' bounds with the weights c.  The oracle
+evaluates Y1 itself: its forward with |W1|, |W2| on |r| (dinv >= 0) gives
+s_e Y1 + dinv |r|."""
 import numpy as np
 import pytest
 import torch
@@ -49,16 +61,41 @@ def _cos(a, b):
     return float(np.dot(a, b) / np.linalg.norm(a) / np.linalg.norm(b))
 
 
-def test_forward_matches_oracle(orc, mx, ctx):
+U_BF16 = 2.0 ** -8
+FWD_C = 4 * U_BF16 + 12 * U_BF16 ** 2 + 1e-4
+
+
+def forward_bound(orc, om, W1, W2, r):
+    """Per-node bound on |z_gpu - z_oracle| (module docstring)."""
+    onn = orc.NN(np.abs(W1), np.abs(W2))
+    ra = np.abs(r)
+    zl_abs, _ = onn.local(om, ra)
+    jac_abs = om.dinv * ra
+    sY1 = np.maximum(zl_abs - jac_abs, 0.0)
+    bl = FWD_C * sY1 + 1e-6 * (jac_abs + sY1)
+    return om.mask_apply(om.gs(om.c * bl)) + 1e-30
+
+
+def check_forward_elementwise(z, zo, bound, what):
+    err = np.abs(z - zo)
+    ratio = float(np.max(err / bound))
+    log(f"  {what}: max |z - z_oracle| / bound = {ratio:.3f} "
+        f"(max err {err.max():.2e}, max bound {bound.max():.2e})")
+    assert ratio <= 1.0, f"{what}: node {int(np.argmax(err / bound))} beyond its bound"
+
+
+@pytest.mark.parametrize("N", [3, 5, 7])
+def test_forward_matches_oracle(orc, mx, ctx, N):
     from paper_2503_02134_amd.learned import Network
-    log("nn forward vs oracle")
-    bmg, gm, bmo, om = _pair(orc, mx, ctx)
+    log(f"nn forward vs oracle, N = {N}, node by node")
+    bmg, gm, bmo, om = _pair(orc, mx, ctx, N=N)
     W1, W2 = W.he_normal_weights(11)
     net = Network(gm, W1, W2)
     onn = orc.NN(W1, W2)
     r = _cont(bmo, om, 1)
     z = net.forward(torch.as_tensor(r, dtype=torch.float32, device="cuda")).cpu().numpy()
     zo = onn.apply(om, r)
+    check_forward_elementwise(z, zo, forward_bound(orc, om, W1, W2, r), "He-normal weights")
     jac = om.dinv * r
     cg, co = z - jac, zo - jac
     log(f"  rel L2 z {rel_l2(z, zo):.2e}; correction cos {_cos(cg, co):.6f} "
@@ -72,11 +109,58 @@ def test_forward_matches_oracle(orc, mx, ctx):
     net.close()
 
 
-def test_loss_and_gradient_match_oracle(orc, mx, ctx):
+@pytest.mark.parametrize("N", [3, 7])
+def test_forward_single_taps(orc, mx, ctx, N):
+    """One non-zero weight per layer, swept over every offset of each
+    layer, for hidden channels at both ends of the range and both input
+    channels: the output is then one shifted, rectified input, so a tap
+    read at the wrong offset, channel or element border is off by O(1) at
+    the nodes it touches, far beyond the node-by-node bound."""
     from paper_2503_02134_amd.learned import Network
-    log("nn loss/gradient vs oracle")
-    bmg, gm, bmo, om = _pair(orc, mx, ctx, ne=2)
+    log(f"nn forward single taps, N = {N}")
+    bmg, gm, bmo, om = _pair(orc, mx, ctx, ne=2, N=N)
+    r = _cont(bmo, om, 3)
+    rt = torch.as_tensor(r, dtype=torch.float32, device="cuda")
+    net = Network(gm, np.zeros((32, 2, 27)), np.zeros((32, 27)))
+    onn = orc.NN(np.zeros((32, 2, 27)), np.zeros((32, 27)))
+    worst = 0.0
+    for c, ci in ((0, 0), (31, 1), (17, 0)):
+        for layer in (1, 2):
+            for o in range(27):
+                W1 = np.zeros((32, 2, 27))
+                W2 = np.zeros((32, 27))
+                W1[c, ci, o if layer == 1 else 13] = 1.0
+                W2[c, o if layer == 2 else 13] = -1.0 if (o % 2) else 1.0
+                net.set(W1, W2)
+                onn.set(W1, W2)
+                z = net.forward(rt).cpu().numpy()
+                zo = onn.apply(om, r)
+                bound = forward_bound(orc, om, W1, W2, r)
+                ratio = float(np.max(np.abs(z - zo) / bound))
+                worst = max(worst, ratio)
+                assert ratio <= 1.0, (c, ci, layer, o, ratio)
+    log(f"  162 tap settings, worst |z - z_oracle| / bound = {worst:.3f}")
+    net.close()
+
+
+def _bf16_exact(a):
+    """The nearest BF16 values (so the network's own weight rounding is exact)."""
+    return torch.as_tensor(np.asarray(a, np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+@pytest.mark.parametrize("N", [3, 5, 7])
+def test_loss_and_gradient_match_oracle(orc, mx, ctx, N):
+    """Loss and gradient over two pairs against the oracle's FP64 analytic
+    gradient (itself pinned to central differences).  The weights are BF16
+    values, so what remains between the two is the BF16 rounding of the
+    network's inputs and hidden activations and the FP32 sums; the smaller
+    orders get 3^3 elements so that each gradient entry sums over about as
+    many positions as at N = 7."""
+    from paper_2503_02134_amd.learned import Network
+    log(f"nn loss/gradient vs oracle, N = {N}")
+    bmg, gm, bmo, om = _pair(orc, mx, ctx, ne=2 if N == 7 else 3, N=N)
     W1, W2 = W.he_normal_weights(12)
+    W1, W2 = _bf16_exact(W1), _bf16_exact(W2)
     net = Network(gm, W1, W2)
     onn = orc.NN(W1, W2)
     R = np.stack([_cont(bmo, om, 20 + s) for s in range(2)])
@@ -86,8 +170,10 @@ def test_loss_and_gradient_match_oracle(orc, mx, ctx):
                                torch.as_tensor(E, dtype=torch.float32, device="cuda"))
     go = np.concatenate([g1.reshape(-1), g2.reshape(-1)])
     gg = grad.cpu().numpy().astype(np.float64)
+    n1 = g1.size
     log(f"  loss gpu {float(loss.item()):.6f} oracle {lo:.6f}; grad cos {_cos(gg, go):.6f} "
-        f"rel {rel_l2(gg, go):.2e}")
+        f"rel {rel_l2(gg, go):.2e} (W1 part {rel_l2(gg[:n1], go[:n1]):.2e}, "
+        f"W2 part {rel_l2(gg[n1:], go[n1:]):.2e})")
     assert abs(float(loss.item()) - lo) <= 1e-2 * lo
     assert _cos(gg, go) >= 0.999 and rel_l2(gg, go) <= 2e-2
     # one Adam step equals the oracle's on the same gradient
@@ -132,19 +218,40 @@ def test_learned_fcg_with_zero_weights_is_jacobi(orc, mx, ctx):
     net.close()
 
 
-def test_fallback_on_non_finite_network(orc, mx, ctx):
-    """Weights set to NaN from the host: every learned step falls back to
-    Jacobi and the solve still converges."""
+def test_fallback_matches_oracle(orc, mx, ctx):
+    """Weights set to NaN from the host: the network's z is NaN at every
+    step, the first one included, so every step takes the Jacobi z.  The
+    oracle's flexible CG with the same NaN network does the same: one
+    fallback per preconditioner application, i.e. as many as iterations.
+    The FP32 flexible CG (no refinement) to a 1e-6 residual takes the
+    oracle's FP64 count of iterations within 2; inside FP64 refinement the
+    solve reaches the oracle's 1e-13 solution to 1e-8."""
     from paper_2503_02134_amd.learned import Network
-    log("fallback with NaN weights")
+    log("fallback with NaN weights vs the oracle")
     bmg, gm, bmo, om = _pair(orc, mx, ctx, ne=2)
-    net = Network(gm, np.full((32, 2, 27), np.nan), np.full((32, 27), np.nan))
+    Wn1, Wn2 = np.full((32, 2, 27), np.nan), np.full((32, 27), np.nan)
+    net = Network(gm, Wn1, Wn2)
     net.attach()
+    onn = orc.NN(Wn1, Wn2)
     b = gm.mass_rhs(torch.as_tensor(W.random_smooth_rhs(bmg, 5903), device="cuda"))
+    bo = om.rhs(W.random_smooth_rhs(bmo, 5903))
+    _, so = om.fcg(bo, nn=onn, tol=1e-6, maxit=5000)
+    _, st1 = gm.solve(b, mode=mx.MODE_MIXED, pc=mx.PC_LEARNED, method=mx.METHOD_FCG,
+                      tol=1e-6, max_iter=5000)
+    log(f"  to 1e-6: gpu it={st1.iterations} fallback={st1.fallback_used}; "
+        f"oracle it={so.iterations} fallback={so.fallback}")
+    assert so.reason == orc.CONVERGED and so.fallback == so.iterations
+    assert st1.reason == mx.CONVERGED and st1.fallback_used == st1.iterations
+    assert abs(st1.iterations - so.iterations) <= 2
+    xs, _ = om.pcg(bo, tol=1e-13, maxit=5000)
     x, st = gm.solve(b, mode=mx.MODE_MIXED_IR, pc=mx.PC_LEARNED, method=mx.METHOD_FCG,
                      tol=1e-10, max_iter=5000)
-    log(f"  it={st.iterations} fallback={st.fallback_used} res={st.rel_res:.2e}")
-    assert st.reason == mx.CONVERGED and st.fallback_used > 0 and st.rel_res <= 1e-10
+    err = rel_l2(x.cpu().numpy(), xs, om.c)
+    log(f"  refinement to 1e-10: it={st.iterations} outer={st.outer} "
+        f"fallback={st.fallback_used} res={st.rel_res:.2e} err={err:.2e}")
+    assert st.reason == mx.CONVERGED and st.rel_res <= 1e-10
+    assert st.fallback_used == st.iterations
+    assert err <= 1e-8
     net.close()
 
 
@@ -221,7 +328,8 @@ def test_full_size_forward_sampled(orc, mx, ctx):
     every element within two node-sharing layers of the sample: the first
     layer holds every element whose output reaches a sampled node, the
     second completes the first layer's Jacobi diagonal, which scales the
-    network's inputs.  Same tolerances as the small-mesh forward."""
+    network's inputs.  Same node-by-node bound as the small-mesh forward,
+    with the norm checks beside it."""
     from paper_2503_02134_amd.learned import Network
     wl = W.WORKLOADS["box24_N7_lognormal_helmholtz"]
     log("full-size 24^3 N7 nn forward, sampled")
@@ -261,6 +369,8 @@ def test_full_size_forward_sampled(orc, mx, ctx):
     zo = onn.apply(om, r[closure].reshape(-1)).reshape(-1, n3)[pos].reshape(-1)
     jac = (om.dinv.reshape(-1, n3)[pos] * r[sample]).reshape(-1)
     zs = z[sample].reshape(-1)
+    bound = forward_bound(orc, om, W1, W2, r[closure].reshape(-1)).reshape(-1, n3)[pos]
+    check_forward_elementwise(zs, zo, bound.reshape(-1), "sampled elements")
     cg, co = zs - jac, zo - jac
     log(f"  {len(sample)} sampled elements, closure {len(closure)}: rel L2 z "
         f"{rel_l2(zs, zo):.2e}; correction cos {_cos(cg, co):.6f} rel {rel_l2(cg, co):.2e}")

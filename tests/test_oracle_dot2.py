@@ -1,5 +1,5 @@
 """Pins of the oracle's FP32 reductions (the extended-precision study of
-Sec. 4.2.2 and the gather-scatter summation orders of Sec. 4.2.1), no GPU.
+Sec. 5.2.1 and the gather-scatter summation orders of Sec. 4.2.1), no GPU.
 
 Expected values come from exact rational arithmetic (fractions.Fraction),
 from the published error bound of Dot2 (Ogita, Rump and Oishi 2005: the
