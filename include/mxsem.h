@@ -24,8 +24,14 @@
  *    the context stream has finished.  FP64 vectors must be 8-byte aligned,
  *    FP32 vectors 4-byte aligned; 256-byte alignment is best.
  *  - "host" pointers are read or written only during the call.
- *  - Handles own the device memory the library allocates for them (operator
- *    data, gather-scatter plan, solver work vectors); destroy frees it and
+ *  - The library allocates no device memory.  Everything it keeps on the
+ *    device for a mesh, a network, a batch or an autotuning run (operator
+ *    data, gather-scatter plan, solver work vectors, launch tables, partial
+ *    sums) lives in a workspace the caller allocates (for example a torch
+ *    uint8 tensor) and passes to the create call; its size comes from the
+ *    matching *_workspace_bytes call, it must be 256-byte aligned and must
+ *    outlive the handle.  A workspace smaller than reported is refused with
+ *    MXSEM_EINVAL.  Handles own host metadata only; destroy frees that and
  *    never frees caller memory.
  *  - Every call returns 0 (MXSEM_OK) or a negative status; no C++ exception
  *    crosses this boundary and nothing calls exit.  mxsem_last_error()
@@ -165,17 +171,31 @@ typedef struct {
   const uint8_t *bnd;    /* host [E][n^3], nonzero on Dirichlet nodes       */
   const double *kcoef;   /* host [E][n^3] diffusion coefficient, or NULL = 1 */
   double helm_h;         /* Helmholtz coefficient h >= 0 (0: Poisson)       */
-  unsigned views;        /* MXSEM_VIEW_* bitmask; F64 is always kept        */
+  unsigned views;        /* MXSEM_VIEW_* bitmask; F64 is always kept.  The
+                            views fix which solve precisions the mesh can
+                            run: F32 or BF16 adds the FP32 work vectors     */
 } mxsem_mesh_desc;
+
+/* Bytes of device workspace mxsem_mesh_create needs for this description:
+ * G, B, dinv in FP64 and in the views' precisions, the gather-scatter plan
+ * (so the host sort of glo runs here too), the copy counts, the solver work
+ * vectors and partial sums of every precision the views allow, and the
+ * launch tables of the mesh's own solves.  About 200 bytes per local entry
+ * with all views.  Same errors as mxsem_mesh_create's checks of desc. */
+int mxsem_mesh_workspace_bytes(const mxsem_mesh_desc *desc, size_t *bytes);
 
 /* Builds, in FP64 on the device, the geometric factors G (6 per node,
  * times k), the mass B, the multiplicity weight c = 1/m, the gather-scatter
  * plan (host sort of glo), the Dirichlet list and the Jacobi inverse
  * diagonal dinv (0 on Dirichlet nodes); then the FP32 / BF16 copies asked
- * for in views.  Synchronous.  Rejects (MXSEM_EMESH) a non-positive
- * Jacobian, copies of one node that disagree on bnd, and element-interior
- * nodes that are shared or Dirichlet. */
-int mxsem_mesh_create(mxsem_ctx *ctx, const mxsem_mesh_desc *desc, mxsem_mesh **out);
+ * for in views.  workspace: device memory of at least ws_bytes >=
+ * mxsem_mesh_workspace_bytes(desc) bytes, 256-byte aligned, owned by the
+ * caller and used by the mesh until it is destroyed (MXSEM_EINVAL when null,
+ * misaligned or too small).  Synchronous.  Rejects (MXSEM_EMESH) a
+ * non-positive Jacobian, copies of one node that disagree on bnd, and
+ * element-interior nodes that are shared or Dirichlet. */
+int mxsem_mesh_create(mxsem_ctx *ctx, const mxsem_mesh_desc *desc, void *workspace,
+                      size_t ws_bytes, mxsem_mesh **out);
 int mxsem_mesh_destroy(mxsem_mesh *mesh);
 
 /* Sizes: local entries, gather-scatter groups (shared nodes and free
@@ -219,6 +239,24 @@ int mxsem_dot(mxsem_mesh *mesh, mxsem_prec io, const void *a, const void *b,
 int mxsem_dot_ex(mxsem_mesh *mesh, mxsem_prec io, int acc, const void *a, const void *b,
                  double *out_dev);
 
+/* ---- allocation-free dot ---------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Computes
+ * what mxsem_dot_ex computes, with the same kernels and the same partial
+ * sums, bit for bit, but the per-workgroup partial sums live in a static
+ * device array of the library (MXSEM_NOALLOC_SCRATCH_BYTES per GPU, held
+ * until the process ends) instead of the mesh's buffer.  Allocates nothing;
+ * only enqueues two kernels on the context stream (async).  Meshes with more
+ * than MXSEM_NOALLOC_MAX_ENTRIES local entries (one partial per 2048
+ * entries) are refused with MXSEM_EINVAL.  Every call on one GPU shares that
+ * GPU's array and each call overwrites the partials it reads, so calls on
+ * one stream are ordered and safe, while calls that overlap on one GPU
+ * (other streams, contexts or host threads) race. */
+#define MXSEM_NOALLOC_SCRATCH_BYTES 65536
+#define MXSEM_NOALLOC_MAX_ENTRIES 16777216
+int mxsem_dot_ex_noalloc(mxsem_mesh *mesh, mxsem_prec io, int acc, const void *a,
+                         const void *b, double *out_dev);
+
 /* z = M^-1 r for pc = identity or Jacobi (io MXSEM_F64 / MXSEM_F32), or the
  * learned map (MXSEM_F32, network attached). */
 int mxsem_precond(mxsem_mesh *mesh, mxsem_pc pc, mxsem_prec io, const void *r, void *z);
@@ -227,8 +265,8 @@ int mxsem_precond(mxsem_mesh *mesh, mxsem_pc pc, mxsem_prec io, const void *r, v
  * exchange modes across rank counts; one GPU emulates their summation
  * order): rank_host is a host array [E] of ranks >= 0, or NULL for every
  * element a rank of its own (the default).  Used by MXSEM_GS_PAIRWISE and
- * by solves with gs_order MXSEM_GS_ORDER_PAIRWISE.  Allocates a device
- * array [E] on first use; synchronises the context stream. */
+ * by solves with gs_order MXSEM_GS_ORDER_PAIRWISE.  The ranks are kept in
+ * the mesh's workspace; synchronises the context stream. */
 int mxsem_mesh_set_ranks(mxsem_mesh *mesh, const int32_t *rank_host);
 
 /* b = M QQ^T (B f) for a nodal source f (device FP64 vectors). */
@@ -284,20 +322,34 @@ typedef struct {
                          (0 = library default)                              */
 } mxsem_tuning;
 
+/* Bytes of device workspace mxsem_batch_create needs: the launch tables of
+ * the batch's plans (every problem's tiles), overlapped by the autotuning
+ * scratch when a tune cache is given. */
+int mxsem_batch_workspace_bytes(mxsem_ctx *ctx, int P, mxsem_mesh *const *meshes,
+                                const char *tune_cache, size_t *bytes);
 /* P meshes on one context solved together: every captured graph chunk
  * launches each stage once per order class over a tile table that spans
  * all problems; problems that have converged become no-ops.  tune_cache:
  * JSON file path for autotuned tiles (nullable = defaults, or the
- * MXSEM_TUNE_CACHE environment variable). */
+ * MXSEM_TUNE_CACHE environment variable); a missing entry is tuned in the
+ * workspace and added to the file.  workspace: caller device memory of at
+ * least mxsem_batch_workspace_bytes bytes, 256-byte aligned, kept until the
+ * batch is destroyed; the work vectors are the meshes' own. */
 int mxsem_batch_create(mxsem_ctx *ctx, int P, mxsem_mesh *const *meshes,
-                       const char *tune_cache, mxsem_batch **out);
+                       const char *tune_cache, void *workspace, size_t ws_bytes,
+                       mxsem_batch **out);
 int mxsem_batch_destroy(mxsem_batch *batch);
 /* b[p], x[p]: device FP64 vectors per problem; st: host array of P. */
 int mxsem_batch_solve(mxsem_batch *batch, const mxsem_solve_opts *opts,
                       const double *const *b, double *const *x, mxsem_solve_stats *st);
+/* Bytes of device workspace for mxsem_autotune at (N, E, prec): synthetic
+ * u, w, G and D of that size. */
+int mxsem_autotune_workspace_bytes(int N, int E, mxsem_prec prec, size_t *bytes);
 /* Time the candidate tiles of the operator kernel for one (N, E, prec) on
- * the context's device and return the fastest (epb[N]). */
-int mxsem_autotune(mxsem_ctx *ctx, int N, int E, mxsem_prec prec, mxsem_tuning *out);
+ * the context's device, on synthetic data in the caller's workspace, and
+ * return the fastest (epb[N]).  Synchronous. */
+int mxsem_autotune(mxsem_ctx *ctx, int N, int E, mxsem_prec prec, void *workspace,
+                   size_t ws_bytes, mxsem_tuning *out);
 /* Tiles the library will use for a mesh (after any tuning). */
 int mxsem_mesh_set_tuning(mxsem_mesh *mesh, const mxsem_tuning *t);
 
@@ -305,13 +357,19 @@ int mxsem_mesh_set_tuning(mxsem_mesh *mesh, const mxsem_tuning *t);
 typedef struct {
   int cin;            /* input channels, must be 2: [r, dinv r] / s_e      */
   int ch;             /* hidden channels (32)                              */
+  int max_samples;    /* largest nsamp of mxsem_nn_loss_grad (>= 1)        */
 } mxsem_nn_desc;
 
 /* Network z_L = dinv r + s_e * conv2(relu(conv1([r, dinv r]/s_e))), 3x3x3
  * kernels with zero padding at element borders, no bias, s_e = ||dinv r||
  * per element; weights W1 [ch][cin][27], W2 [ch][27] (offset o = (di+1) +
  * 3(dj+1) + 9(dk+1)); BF16 inputs and weights, FP32 accumulation. */
-int mxsem_nn_create(mxsem_mesh *mesh, const mxsem_nn_desc *desc, mxsem_nn **out);
+/* Bytes of device workspace mxsem_nn_create needs on this mesh. */
+int mxsem_nn_workspace_bytes(const mxsem_mesh *mesh, const mxsem_nn_desc *desc, size_t *bytes);
+/* workspace: caller device memory of at least mxsem_nn_workspace_bytes
+ * bytes, 256-byte aligned, kept until the network is destroyed. */
+int mxsem_nn_create(mxsem_mesh *mesh, const mxsem_nn_desc *desc, void *workspace,
+                    size_t ws_bytes, mxsem_nn **out);
 int mxsem_nn_destroy(mxsem_nn *nn);
 int mxsem_nn_set_params(mxsem_nn *nn, const float *W1_host, const float *W2_host);
 int mxsem_nn_get_params(mxsem_nn *nn, float *W1_host, float *W2_host);
@@ -319,7 +377,8 @@ int mxsem_nn_get_params(mxsem_nn *nn, float *W1_host, float *W2_host);
 int mxsem_nn_forward(mxsem_nn *nn, const float *r, float *z);
 /* Mean over nsamp pairs of ||z(r_s) - e_s||_A^2 / ||e_s||_A^2 and its
  * gradient (device FP32 grad [ch*cin*27 + ch*27], W1 part first); r, e:
- * device FP32 [nsamp][nloc]; loss_dev: device FP64 scalar. Async. */
+ * device FP32 [nsamp][nloc], 1 <= nsamp <= desc.max_samples (else
+ * MXSEM_EINVAL); loss_dev: device FP64 scalar. Async. */
 int mxsem_nn_loss_grad(mxsem_nn *nn, const float *r, const float *e, int nsamp,
                        double *loss_dev, float *grad_dev);
 typedef struct {

@@ -22,6 +22,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <memory>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -849,19 +851,57 @@ struct mxsem_nn {
   double* nd = nullptr;   // [2 * max samples] numerators / denominators
   double* dots = nullptr; // [5][dstride] per-workgroup flexible-CG dot partials of the forward
   int dstride = 0;
-  int nd_cap = 0;
+  int nd_cap = 0;         // max_samples of the descriptor
   int nbwd = 0;
-  std::vector<void*> allocs;
+  bool counted = false;
 };
 
 namespace mx {
-static int nn_alloc(mxsem_nn* nn, void** p, size_t bytes) {
-  hipError_t e = hipMalloc(p, bytes ? bytes : 256);
-  if (e != hipSuccess) {
-    set_error(std::string("nn: hipMalloc: ") + hipGetErrorString(e));
-    return MXSEM_ENOMEM;
+// Blocks of a network's workspace: master and BF16-rounded weights,
+// gradient, Adam moments, per-workgroup gradient partials of the backward,
+// the forward's dot partials, the matrix-core weight operands, four FP32
+// work vectors and the per-sample loss terms.  Returns the total; with ws,
+// points nn's arrays at the blocks.
+static size_t nn_layout(const mxsem_mesh* m, int max_samples, mxsem_nn* nn, char* ws) {
+  Layout L;
+  const int64_t nl = m->nloc;
+  const int nbwd = std::min(NN_BWD_BLOCKS, m->E);
+  const int dstride = std::max(m->E, 4096);  // at least every forward grid's workgroup count
+  auto put = [&](auto** p, size_t bytes) {
+    const size_t o = L.take(bytes);
+    if (ws) *p = reinterpret_cast<std::remove_reference_t<decltype(*p)>>(ws + o);
+  };
+  float* f = nullptr;
+  double* dd = nullptr;
+  void* v = nullptr;
+  put(ws ? &nn->W : &f, sizeof(float) * NN_NP);
+  put(ws ? &nn->Wq : &f, sizeof(float) * NN_NP);
+  put(ws ? &nn->grad : &f, sizeof(float) * NN_NP);
+  put(ws ? &nn->mo : &f, sizeof(float) * NN_NP);
+  put(ws ? &nn->ve : &f, sizeof(float) * NN_NP);
+  put(ws ? &nn->part : &f, sizeof(float) * NN_NP * nbwd);
+  put(ws ? &nn->dots : &dd, sizeof(double) * 5 * dstride);
+  put(ws ? &nn->packed : &v, 16 * 6 * 64);
+  put(ws ? &nn->z : &f, sizeof(float) * nl);
+  put(ws ? &nn->d : &f, sizeof(float) * nl);
+  put(ws ? &nn->Ad : &f, sizeof(float) * nl);
+  put(ws ? &nn->g : &f, sizeof(float) * nl);
+  put(ws ? &nn->nd : &dd, sizeof(double) * 2 * max_samples);
+  if (ws) {
+    nn->nbwd = nbwd;
+    nn->dstride = dstride;
+    nn->nd_cap = max_samples;
   }
-  nn->allocs.push_back(*p);
+  return align256(L.total);
+}
+
+static int check_nn_desc(const mxsem_mesh* m, const mxsem_nn_desc* d) {
+  MX_CHECK(d->cin == NN_CIN && d->ch == NN_CH, MXSEM_ENOTSUP,
+           "nn: the network has 2 input and 32 hidden channels");
+  MX_CHECK(d->max_samples >= 1, MXSEM_EINVAL, "nn: max_samples must be >= 1");
+  MX_CHECK(m->N == 3 || m->N == 5 || m->N == 7, MXSEM_ENOTSUP,
+           "nn: learned preconditioner built for N = 3, 5, 7");
+  MX_CHECK(m->dinv32 && m->G32, MXSEM_ENOTSUP, "nn: mesh needs its FP32 view");
   return MXSEM_OK;
 }
 static inline unsigned nb256(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -896,42 +936,30 @@ int nn_forward_into(mxsem_nn* nn, const float* r, float* out, hipStream_t s) {
 
 extern "C" {
 
-int mxsem_nn_create(mxsem_mesh* m, const mxsem_nn_desc* d, mxsem_nn** out) {
+int mxsem_nn_workspace_bytes(const mxsem_mesh* m, const mxsem_nn_desc* d, size_t* bytes) {
+  MX_API_BEGIN
+  MX_CHECK(m && d && bytes, MXSEM_EINVAL, "nn_workspace_bytes: null argument");
+  MX_TRY(check_nn_desc(m, d));
+  *bytes = nn_layout(m, d->max_samples, nullptr, nullptr);
+  return MXSEM_OK;
+  MX_API_END("mxsem_nn_workspace_bytes")
+}
+
+int mxsem_nn_create(mxsem_mesh* m, const mxsem_nn_desc* d, void* workspace, size_t ws_bytes,
+                    mxsem_nn** out) {
   MX_API_BEGIN
   MX_CHECK(m && d && out, MXSEM_EINVAL, "nn_create: null argument");
-  MX_CHECK(d->cin == NN_CIN && d->ch == NN_CH, MXSEM_ENOTSUP,
-           "nn_create: the network has 2 input and 32 hidden channels");
-  MX_CHECK(m->N == 3 || m->N == 5 || m->N == 7, MXSEM_ENOTSUP,
-           "nn_create: learned preconditioner built for N = 3, 5, 7");
-  MX_CHECK(m->dinv32 && m->G32, MXSEM_ENOTSUP, "nn_create: mesh needs its FP32 view");
+  *out = nullptr;
+  MX_TRY(check_nn_desc(m, d));
+  MX_CHECK(workspace && ((uintptr_t)workspace & 255) == 0, MXSEM_EINVAL,
+           "nn_create: workspace must be a 256-byte aligned device pointer");
+  MX_CHECK(ws_bytes >= nn_layout(m, d->max_samples, nullptr, nullptr), MXSEM_EINVAL,
+           "nn_create: workspace smaller than mxsem_nn_workspace_bytes");
   MX_HIP(hipSetDevice(m->ctx->device));
   (void)hipGetLastError();
-  *out = nullptr;
-  mxsem_nn* nn = new mxsem_nn();
+  std::unique_ptr<mxsem_nn> nn(new mxsem_nn());
   nn->mesh = m;
-  nn->nbwd = std::min(NN_BWD_BLOCKS, m->E);
-  const int64_t nl = m->nloc;
-  int rc = MXSEM_OK;
-  auto A = [&](void** p, size_t b) {
-    if (rc == MXSEM_OK) rc = nn_alloc(nn, p, b);
-  };
-  A((void**)&nn->W, sizeof(float) * NN_NP);
-  A((void**)&nn->Wq, sizeof(float) * NN_NP);
-  A((void**)&nn->grad, sizeof(float) * NN_NP);
-  A((void**)&nn->mo, sizeof(float) * NN_NP);
-  A((void**)&nn->ve, sizeof(float) * NN_NP);
-  A((void**)&nn->part, sizeof(float) * NN_NP * nn->nbwd);
-  nn->dstride = std::max(m->E, 4096);  // at least every forward grid's workgroup count
-  A((void**)&nn->dots, sizeof(double) * 5 * nn->dstride);
-  A((void**)&nn->packed, 16 * 6 * 64);
-  A((void**)&nn->z, sizeof(float) * nl);
-  A((void**)&nn->d, sizeof(float) * nl);
-  A((void**)&nn->Ad, sizeof(float) * nl);
-  A((void**)&nn->g, sizeof(float) * nl);
-  if (rc != MXSEM_OK) {
-    mxsem_nn_destroy(nn);
-    return rc;
-  }
+  nn_layout(m, d->max_samples, nn.get(), (char*)workspace);
   hipStream_t s = m->ctx->stream;
   for (float* p : {nn->W, nn->Wq, nn->grad, nn->mo, nn->ve})
     hipLaunchKernelGGL(nn_fill_kernel, dim3(nb256(NN_NP)), dim3(256), 0, s, p, (int64_t)NN_NP, 0.f);
@@ -940,7 +968,8 @@ int mxsem_nn_create(mxsem_mesh* m, const mxsem_nn_desc* d, mxsem_nn** out) {
   MX_HIP(hipGetLastError());
   MX_HIP(hipStreamSynchronize(s));
   m->ctx->live += 1;
-  *out = nn;
+  nn->counted = true;
+  *out = nn.release();
   return MXSEM_OK;
   MX_API_END("mxsem_nn_create")
 }
@@ -952,9 +981,8 @@ int mxsem_nn_destroy(mxsem_nn* nn) {
   if (nn->mesh->ctx->stream) (void)hipStreamSynchronize(nn->mesh->ctx->stream);
   else (void)hipDeviceSynchronize();
   if (nn->mesh->nn == nn) nn->mesh->nn = nullptr;
-  for (void* p : nn->allocs) (void)hipFree(p);
-  if (nn->W) nn->mesh->ctx->live -= 1;
-  delete nn;
+  if (nn->counted) nn->mesh->ctx->live -= 1;
+  delete nn;  // the workspace is the caller's
   return MXSEM_OK;
   MX_API_END("mxsem_nn_destroy")
 }
@@ -1007,10 +1035,8 @@ int mxsem_nn_loss_grad(mxsem_nn* nn, const float* r, const float* e, int nsamp, 
   (void)hipGetLastError();
   hipStream_t s = m->ctx->stream;
   const int64_t nl = m->nloc;
-  if (nn->nd_cap < nsamp) {
-    MX_TRY(nn_alloc(nn, (void**)&nn->nd, sizeof(double) * 2 * nsamp));
-    nn->nd_cap = nsamp;
-  }
+  MX_CHECK(nsamp <= nn->nd_cap, MXSEM_EINVAL,
+           "nn_loss_grad: more samples than the network's max_samples");
   hipLaunchKernelGGL(nn_fill_kernel, dim3(nb256((int64_t)NN_NP * nn->nbwd)), dim3(256), 0, s,
                      nn->part, (int64_t)NN_NP * nn->nbwd, 0.f);
   for (int q = 0; q < nsamp; ++q) {
@@ -1061,7 +1087,6 @@ int mxsem_nn_make_pair(mxsem_mesh* m, const double* b, const double* x, const do
   MX_HIP(hipSetDevice(m->ctx->device));
   (void)hipGetLastError();
   hipStream_t s = m->ctx->stream;
-  MX_TRY(ensure_tmp(m));
   MX_TRY(apply_impl(m, MXSEM_F64, x, m->tmpb, 0, s));
   MX_HIP(launch_residual(b, m->tmpb, m->tmpa, m->mult, m->nloc, m->part, m->scal + 2, s));
   hipLaunchKernelGGL(nn_pair_kernel, dim3(nb256(m->nloc)), dim3(256), 0, s, m->tmpa, xstar, x,

@@ -6,6 +6,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <memory>
+#include <mutex>
+#include <type_traits>
 #include <new>
 #include <string>
 #include <vector>
@@ -13,6 +16,40 @@
 #include "runtime.hpp"
 
 namespace mx {
+
+// Scratch of mxsem_dot_ex_noalloc: the per-workgroup partial sums of the dot
+// live in this static device array (one copy per GPU, held until the
+// process ends) instead of a buffer the library allocates.  In host code
+// the name is only a stand-in: the device address comes from
+// hipGetSymbolAddress, taken once per device at the entry point's first
+// call on that device, and kernels receive that address.
+constexpr int NOALLOC_PARTS = MXSEM_NOALLOC_SCRATCH_BYTES / (int)sizeof(double);
+static_assert((int64_t)NOALLOC_PARTS * UPD_CHUNK == MXSEM_NOALLOC_MAX_ENTRIES,
+              "the entry limit is one partial per vector-pass workgroup");
+static __device__ __align__(256) double scratch[NOALLOC_PARTS];
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_addr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device (dev), looked up once.
+static int scratch_address(int dev, double** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (dev < 0 || dev >= MAX_DEVICES) {
+    set_error("scratch: device index out of range");
+    return MXSEM_EINVAL;
+  }
+  if (!g_scratch_addr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      return MXSEM_EHIP;
+    }
+    g_scratch_addr[dev] = (double*)ptr;
+  }
+  *out = g_scratch_addr[dev];
+  return MXSEM_OK;
+}
 
 static thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
@@ -87,18 +124,6 @@ void deriv_matrix(int N, const double* xi, double* D) {
 }
 
 // ---------------------------------------------------------------- helpers
-int mesh_alloc(mxsem_mesh* m, void** p, size_t bytes) {
-  *p = nullptr;
-  if (bytes == 0) bytes = 256;
-  hipError_t e = hipMalloc(p, bytes);
-  if (e != hipSuccess) {
-    set_error(std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
-    return MXSEM_ENOMEM;
-  }
-  m->allocs.push_back(*p);
-  return MXSEM_OK;
-}
-
 // Elements per workgroup of the operator kernel (workgroups of at most 256
 // threads, rounded up to whole wave64s): one wave's worth for the
 // two-column mapping, else the smallest count whose idle lanes are under 5%,
@@ -127,14 +152,6 @@ const void* G_ptr(const mxsem_mesh* m, int gprec) {
 const void* hB_ptr(const mxsem_mesh* m, int gprec) {
   if (m->helm_h == 0.0) return nullptr;
   return gprec == 0 ? (const void*)m->hB64 : gprec == 2 ? (const void*)m->hB16 : (const void*)m->hB32;
-}
-
-int ensure_tmp(mxsem_mesh* m) {
-  if (!m->tmpa) {
-    MX_TRY(mesh_alloc(m, (void**)&m->tmpa, sizeof(double) * m->nloc));
-    MX_TRY(mesh_alloc(m, (void**)&m->tmpb, sizeof(double) * m->nloc));
-  }
-  return MXSEM_OK;
 }
 
 int max_copies(const mxsem_mesh* m) {
@@ -197,9 +214,10 @@ int mxsem_ctx_create(int hip_device, void* hip_stream, mxsem_ctx** out) {
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->pinned_flags, 64, hipHostMallocDefault);
   if (e != hipSuccess) {
     set_error(std::string("ctx_create: ") + hipGetErrorString(e));
-    delete c;
+    mxsem_ctx_destroy(c);
     return MXSEM_EHIP;
   }
+
   *out = c;
   return MXSEM_OK;
   MX_API_END("mxsem_ctx_create")
@@ -241,16 +259,247 @@ int mxsem_gll(int N, double* xi, double* w) {
 int mxsem_mesh_destroy(mxsem_mesh* m) {
   MX_API_BEGIN
   if (!m) return MXSEM_OK;
-  (void)hipSetDevice(m->ctx->device);
-  if (m->ctx->stream) (void)hipStreamSynchronize(m->ctx->stream);
-  else (void)hipDeviceSynchronize();
+  if (m->ctx) {
+    (void)hipSetDevice(m->ctx->device);
+    if (m->ctx->stream) (void)hipStreamSynchronize(m->ctx->stream);
+    else (void)hipDeviceSynchronize();
+  }
   mesh_drop_plans(m);
   for (int q = 0; q < 4; ++q) delete m->bufs[q];
-  for (void* p : m->allocs) (void)hipFree(p);
   if (m->counted) m->ctx->live -= 1;
-  delete m;
+  delete m;  // the workspace is the caller's
   return MXSEM_OK;
   MX_API_END("mxsem_mesh_destroy")
+}
+
+}  // extern "C"
+
+namespace mx {
+
+static int check_desc(const mxsem_mesh_desc* d) {
+  MX_CHECK(d->N >= 1 && d->N <= MAX_N, MXSEM_ENOTSUP, "mesh: N must be in 1..15");
+  MX_CHECK(d->E >= 1, MXSEM_EINVAL, "mesh: E must be >= 1");
+  MX_CHECK(d->xyz && d->glo && d->bnd, MXSEM_EINVAL, "mesh: xyz, glo, bnd required");
+  MX_CHECK(d->helm_h >= 0.0 && isfinite(d->helm_h), MXSEM_EINVAL, "mesh: helm_h < 0");
+  const int n = d->N + 1;
+  MX_CHECK((int64_t)d->E * n * n * n < (int64_t)INT32_MAX - UPD_CHUNK, MXSEM_ENOTSUP,
+           "mesh: more than 2^31 local entries");
+  return MXSEM_OK;
+}
+
+static void mesh_basics(mxsem_mesh* m, const mxsem_mesh_desc* d) {
+  m->E = d->E;
+  m->N = d->N;
+  m->n = d->N + 1;
+  m->n3 = m->n * m->n * m->n;
+  m->nloc = (int64_t)d->E * m->n3;
+  m->helm_h = d->helm_h;
+  m->views = d->views | MXSEM_VIEW_F64;
+}
+
+// Gather-scatter plan on the host (a counting sort of the local entries by
+// global id): groups bucketed by copy count (8, 4, 2 first, at 16-byte
+// aligned offsets so that a group's indices are one vector load), free
+// groups before Dirichlet ones, then the Dirichlet list.  Fills m->plan's
+// bucket table, m->gs_first, m->ngroups, m->nmask_entries; the index array
+// and the per-entry copy counts go to idx and mult.
+static int host_plan(const mxsem_mesh_desc* d, mxsem_mesh* m, std::vector<int32_t>& idx,
+                     std::vector<uint8_t>& mult) {
+  const int64_t nloc = m->nloc;
+  const int64_t* glo = d->glo;
+  int64_t gmax = -1;
+  for (int64_t i = 0; i < nloc; ++i) {
+    MX_CHECK(glo[i] >= 0, MXSEM_EINVAL, "mesh: negative global id");
+    gmax = std::max(gmax, glo[i]);
+  }
+  std::vector<int32_t> order(nloc);
+  std::vector<int64_t> gstart;  // group boundaries in `order`
+  if (gmax < 4 * nloc + 1024) {
+    std::vector<int32_t> cnt(gmax + 2, 0);
+    for (int64_t i = 0; i < nloc; ++i) cnt[glo[i] + 1]++;
+    for (int64_t g = 0; g <= gmax; ++g) cnt[g + 1] += cnt[g];
+    std::vector<int32_t> pos(cnt.begin(), cnt.end() - 1);
+    for (int64_t i = 0; i < nloc; ++i) order[pos[glo[i]]++] = (int32_t)i;
+    for (int64_t g = 0; g <= gmax; ++g)
+      if (cnt[g + 1] > cnt[g]) gstart.push_back(cnt[g]);
+  } else {
+    for (int64_t i = 0; i < nloc; ++i) order[i] = (int32_t)i;
+    std::stable_sort(order.begin(), order.end(),
+                     [glo](int32_t a, int32_t b) { return glo[a] < glo[b]; });
+    for (int64_t t = 0; t < nloc; ++t)
+      if (t == 0 || glo[order[t]] != glo[order[t - 1]]) gstart.push_back(t);
+  }
+  gstart.push_back(nloc);
+  const int64_t ng = (int64_t)gstart.size() - 1;
+  mult.assign(nloc, 0);
+  struct Grp {
+    int32_t m, first;  // size, position in `order`
+  };
+  std::vector<std::vector<Grp>> freeb(256), maskb(256);
+  std::vector<int32_t> masklist;
+  const uint8_t* bnd = d->bnd;
+  int64_t ngroups = 0;
+  for (int64_t q = 0; q < ng; ++q) {
+    const int64_t a = gstart[q], b = gstart[q + 1];
+    const int32_t sz = (int32_t)(b - a);
+    MX_CHECK(sz <= 255, MXSEM_ENOTSUP, "mesh: a node shared by more than 255 elements");
+    const bool msk = bnd[order[a]] != 0;
+    for (int64_t t = a; t < b; ++t) {
+      const int32_t li = order[t];
+      MX_CHECK((bnd[li] != 0) == msk, MXSEM_EMESH,
+               "mesh: copies of a global node disagree on the Dirichlet flag");
+      mult[li] = (uint8_t)sz;
+      if (msk) masklist.push_back(li);
+    }
+    if (sz >= 2) {
+      (msk ? maskb : freeb)[sz].push_back(Grp{sz, (int32_t)a});
+      ++ngroups;
+    }
+  }
+  std::sort(masklist.begin(), masklist.end());
+  std::vector<int> morder = {8, 4, 2};
+  for (int mm = 255; mm >= 2; --mm)
+    if (mm != 8 && mm != 4 && mm != 2) morder.push_back(mm);
+  idx.clear();
+  GsPlan plan{};
+  int nb = 0;
+  m->gs_first.assign(MAX_BUCKETS, {});
+  auto emit = [&](std::vector<std::vector<Grp>>& bks) -> bool {
+    for (int mm : morder) {
+      auto& gv = bks[mm];
+      if (gv.empty()) continue;
+      if (nb >= MAX_BUCKETS - 1) return false;
+      std::sort(gv.begin(), gv.end(),
+                [&order](const Grp& x, const Grp& y) { return order[x.first] < order[y.first]; });
+      while (idx.size() % 4) idx.push_back(0);  // 16-byte aligned bucket start
+      plan.bk[nb] = GsBucket{mm, (int)gv.size(), (int)idx.size(), 0};
+      std::vector<int32_t>& gf = m->gs_first[nb];
+      gf.reserve(gv.size());
+      for (const Grp& gr : gv) {
+        gf.push_back(order[gr.first]);
+        for (int t = 0; t < gr.m; ++t) idx.push_back(order[gr.first + t]);
+      }
+      ++nb;
+    }
+    return true;
+  };
+  MX_CHECK(emit(freeb), MXSEM_ENOTSUP, "mesh: too many distinct node multiplicities");
+  plan.nfree = nb;
+  MX_CHECK(emit(maskb), MXSEM_ENOTSUP, "mesh: too many distinct node multiplicities");
+  plan.nall = nb;
+  while (idx.size() % 4) idx.push_back(0);
+  plan.bk[nb] = GsBucket{0, (int)masklist.size(), (int)idx.size(), 0};
+  idx.insert(idx.end(), masklist.begin(), masklist.end());
+  m->gs_first[nb] = masklist;
+  m->ngroups = ngroups;
+  m->nmask_entries = (int)masklist.size();
+  plan.n3 = m->n3;
+  plan.erank = nullptr;
+  m->plan = plan;
+  return MXSEM_OK;
+}
+
+// Device arrays used only while a mesh is built (inside the blocks of the
+// FP64 work vectors, which no solve has touched yet).
+struct SetupTemps {
+  double *wq = nullptr, *xyz = nullptr, *k = nullptr, *detmin = nullptr;
+  size_t begin = 0, end = 0;  // byte range of the workspace they occupy
+};
+
+// Every block of a mesh's workspace in one order: mxsem_mesh_workspace_bytes
+// reports the total, mxsem_mesh_create (ws != nullptr) points the mesh's
+// arrays at the blocks.  Returns the total in bytes.
+static size_t mesh_layout(mxsem_mesh* m, size_t nidx, bool has_k, char* ws, SetupTemps* tmp) {
+  Layout L;
+  const int64_t nl = m->nloc;
+  const int n = m->n;
+  const bool h = m->helm_h != 0.0;
+  const bool f32 = (m->views & MXSEM_VIEW_F32) != 0, b16 = (m->views & MXSEM_VIEW_BF16) != 0;
+  auto put = [&](auto** p, size_t bytes) {
+    const size_t o = L.take(bytes);
+    if (ws) *p = reinterpret_cast<std::remove_reference_t<decltype(*p)>>(ws + o);
+  };
+  put(&m->D64, sizeof(double) * n * n);
+  put(&m->D32, sizeof(float) * n * n);
+  put(&m->G64, sizeof(double) * 6 * nl);
+  put(&m->B64, sizeof(double) * nl);
+  if (h) put(&m->hB64, sizeof(double) * nl);
+  put(&m->dinv64, sizeof(double) * nl);
+  put(&m->mult, (size_t)nl);
+  put(&m->gs_idx, sizeof(int) * std::max<size_t>(nidx, 4));
+  put(&m->part, sizeof(double) * ((nl + UPD_CHUNK - 1) / UPD_CHUNK + 64));
+  put(&m->scal, sizeof(double) * 8);
+  put(&m->tmpa, sizeof(double) * nl);
+  put(&m->tmpb, sizeof(double) * nl);
+  put(&m->erank, sizeof(int) * (size_t)m->E);
+  if (f32 || b16) put(&m->dinv32, sizeof(float) * nl);
+  if (f32) {
+    put(&m->G32, sizeof(float) * 6 * nl);
+    if (h) put(&m->hB32, sizeof(float) * nl);
+  }
+  if (b16) {
+    put(&m->G16, sizeof(bf16_t) * 6 * nl);
+    if (h) put(&m->hB16, sizeof(bf16_t) * nl);
+  }
+  const size_t work = align256(L.total);
+  carve_solver_bufs(m, VP_F64, ws, L);
+  if (f32 || b16) {
+    carve_solver_bufs(m, VP_F32, ws, L);
+    if (ws) {  // the FP32-sums ablation runs on the same vectors
+      m->bufs[VP_F32ACC] = new SolverBufs(*m->bufs[VP_F32]);
+      m->bufs[VP_F32ACC]->vprec = VP_F32ACC;
+    }
+  }
+  {
+    Layout T;
+    T.total = work;
+    const size_t owq = T.take(sizeof(double) * n), oxyz = T.take(sizeof(double) * 3 * nl);
+    const size_t ok = has_k ? T.take(sizeof(double) * nl) : 0;
+    const size_t odet = T.take(sizeof(double) * ((nl + 255) / 256));
+    if (ws && tmp) {
+      tmp->begin = work;
+      tmp->end = T.total;
+      tmp->wq = (double*)(ws + owq);
+      tmp->xyz = (double*)(ws + oxyz);
+      tmp->k = has_k ? (double*)(ws + ok) : nullptr;
+      tmp->detmin = (double*)(ws + odet);
+    }
+    L.total = std::max(L.total, T.total);
+  }
+  const size_t tb = plan_table_bytes(&m, 1);
+  const int vps[3] = {VP_F64, VP_F32, VP_F32ACC};
+  for (int q = 0; q < ((f32 || b16) ? 3 : 1); ++q) {
+    const size_t o = L.take(tb);
+    if (ws) {
+      m->plan_tables[vps[q]].base = ws + o;
+      m->plan_tables[vps[q]].size = tb;
+    }
+  }
+  return align256(L.total);
+}
+
+__global__ void ws_zero_kernel(uint4* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+}  // namespace mx
+
+extern "C" {
+
+int mxsem_mesh_workspace_bytes(const mxsem_mesh_desc* d, size_t* bytes) {
+  MX_API_BEGIN
+  MX_CHECK(d && bytes, MXSEM_EINVAL, "mesh_workspace_bytes: null argument");
+  MX_TRY(check_desc(d));
+  mxsem_mesh tmp;
+  mesh_basics(&tmp, d);
+  std::vector<int32_t> idx;
+  std::vector<uint8_t> mult;
+  MX_TRY(host_plan(d, &tmp, idx, mult));
+  *bytes = mesh_layout(&tmp, idx.size(), d->kcoef != nullptr, nullptr, nullptr);
+  return MXSEM_OK;
+  MX_API_END("mxsem_mesh_workspace_bytes")
 }
 
 static int mesh_fail(mxsem_mesh* m, int rc) {
@@ -279,31 +528,42 @@ static int mesh_fail(mxsem_mesh* m, int rc) {
     }                              \
   } while (0)
 
-int mxsem_mesh_create(mxsem_ctx* ctx, const mxsem_mesh_desc* d, mxsem_mesh** out) {
+int mxsem_mesh_create(mxsem_ctx* ctx, const mxsem_mesh_desc* d, void* workspace, size_t ws_bytes,
+                      mxsem_mesh** out) {
   MX_API_BEGIN
-  MX_CHECK(ctx && d && out, MXSEM_EINVAL, "mesh_create: null argument");
+  // every argument is checked before the device is touched
+  MX_CHECK(d && out, MXSEM_EINVAL, "mesh_create: null argument");
   *out = nullptr;
-  MX_CHECK(d->N >= 1 && d->N <= MAX_N, MXSEM_ENOTSUP, "mesh_create: N must be in 1..15");
-  MX_CHECK(d->E >= 1, MXSEM_EINVAL, "mesh_create: E must be >= 1");
-  MX_CHECK(d->xyz && d->glo && d->bnd, MXSEM_EINVAL, "mesh_create: xyz, glo, bnd required");
-  MX_CHECK(d->helm_h >= 0.0 && isfinite(d->helm_h), MXSEM_EINVAL, "mesh_create: helm_h < 0");
-  const int n = d->N + 1, n3 = n * n * n;
-  const int64_t nloc = (int64_t)d->E * n3;
-  MX_CHECK(nloc < (int64_t)INT32_MAX - UPD_CHUNK, MXSEM_ENOTSUP,
-           "mesh_create: more than 2^31 local entries");
+  MX_TRY(check_desc(d));
+  MX_CHECK(workspace && ((uintptr_t)workspace & 255) == 0, MXSEM_EINVAL,
+           "mesh_create: workspace must be a 256-byte aligned device pointer");
+  std::unique_ptr<mxsem_mesh> mh(new mxsem_mesh());
+  mesh_basics(mh.get(), d);
+  // gather-scatter plan (host) and the workspace layout it implies
+  std::vector<int32_t> idx;
+  std::vector<uint8_t> mult;
+  MX_TRY(host_plan(d, mh.get(), idx, mult));
+  const size_t need = mesh_layout(mh.get(), idx.size(), d->kcoef != nullptr, nullptr, nullptr);
+  MX_CHECK(ws_bytes >= need, MXSEM_EINVAL,
+           "mesh_create: workspace smaller than mxsem_mesh_workspace_bytes");
+  MX_CHECK(ctx, MXSEM_EINVAL, "mesh_create: null context");
   MX_HIP(hipSetDevice(ctx->device));
   (void)hipGetLastError();
-  mxsem_mesh* m = new (std::nothrow) mxsem_mesh();
-  MX_CHECK(m, MXSEM_ENOMEM, "mesh_create: host allocation failed");
+  mxsem_mesh* m = mh.release();
   m->ctx = ctx;
-  m->E = d->E;
-  m->N = d->N;
-  m->n = n;
-  m->n3 = n3;
-  m->nloc = nloc;
-  m->helm_h = d->helm_h;
-  m->views = d->views | MXSEM_VIEW_F64;
+  const int n = m->n;
+  const int64_t nloc = m->nloc;
   hipStream_t s = ctx->stream;
+  SetupTemps tmp;
+  m->ws = (char*)workspace;
+  m->ws_bytes = ws_bytes;
+  mesh_layout(m, idx.size(), d->kcoef != nullptr, m->ws, &tmp);
+  {
+    const int64_t n16 = (int64_t)(need / 16);
+    hipLaunchKernelGGL(ws_zero_kernel, dim3((unsigned)std::min<int64_t>((n16 + 255) / 256, 65536)),
+                       dim3(256), 0, s, (uint4*)m->ws, n16);
+    MX_MHIP(hipGetLastError());
+  }
 
   // reference element
   std::vector<double> xi(n), wq(n), D(n * n);
@@ -311,150 +571,34 @@ int mxsem_mesh_create(mxsem_ctx* ctx, const mxsem_mesh_desc* d, mxsem_mesh** out
   deriv_matrix(d->N, xi.data(), D.data());
   std::vector<float> D32h(n * n);
   for (int q = 0; q < n * n; ++q) D32h[q] = (float)D[q];
-  double* wq_d;
-  MX_MTRY(mesh_alloc(m, (void**)&m->D64, sizeof(double) * n * n));
-  MX_MTRY(mesh_alloc(m, (void**)&m->D32, sizeof(float) * n * n));
-  MX_MTRY(mesh_alloc(m, (void**)&wq_d, sizeof(double) * n));
   MX_MHIP(hipMemcpyAsync(m->D64, D.data(), sizeof(double) * n * n, hipMemcpyHostToDevice, s));
   MX_MHIP(hipMemcpyAsync(m->D32, D32h.data(), sizeof(float) * n * n, hipMemcpyHostToDevice, s));
-  MX_MHIP(hipMemcpyAsync(wq_d, wq.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+  MX_MHIP(hipMemcpyAsync(tmp.wq, wq.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
 
   // geometry (FP64, on the device)
-  double *xyz_d = nullptr, *k_d = nullptr, *detmin_d = nullptr;
-  MX_MTRY(mesh_alloc(m, (void**)&xyz_d, sizeof(double) * 3 * nloc));
-  MX_MHIP(hipMemcpyAsync(xyz_d, d->xyz, sizeof(double) * 3 * nloc, hipMemcpyHostToDevice, s));
-  if (d->kcoef) {
-    MX_MTRY(mesh_alloc(m, (void**)&k_d, sizeof(double) * nloc));
-    MX_MHIP(hipMemcpyAsync(k_d, d->kcoef, sizeof(double) * nloc, hipMemcpyHostToDevice, s));
-  }
-  MX_MTRY(mesh_alloc(m, (void**)&m->G64, sizeof(double) * 6 * nloc));
-  MX_MTRY(mesh_alloc(m, (void**)&m->B64, sizeof(double) * nloc));
-  const int nb_geom = (int)((nloc + 255) / 256);
-  MX_MTRY(mesh_alloc(m, (void**)&detmin_d, sizeof(double) * nb_geom));
+  MX_MHIP(hipMemcpyAsync(tmp.xyz, d->xyz, sizeof(double) * 3 * nloc, hipMemcpyHostToDevice, s));
+  if (d->kcoef)
+    MX_MHIP(hipMemcpyAsync(tmp.k, d->kcoef, sizeof(double) * nloc, hipMemcpyHostToDevice, s));
   int nbg = 0;
-  MX_MHIP(launch_geom(m->E, n, xyz_d, m->D64, wq_d, k_d, m->G64, m->B64, detmin_d, &nbg, s));
+  MX_MHIP(launch_geom(m->E, n, tmp.xyz, m->D64, tmp.wq, tmp.k, m->G64, m->B64, tmp.detmin, &nbg, s));
   std::vector<double> detmin(nbg);
-  MX_MHIP(hipMemcpyAsync(detmin.data(), detmin_d, sizeof(double) * nbg, hipMemcpyDeviceToHost, s));
+  MX_MHIP(hipMemcpyAsync(detmin.data(), tmp.detmin, sizeof(double) * nbg, hipMemcpyDeviceToHost, s));
   MX_MHIP(hipStreamSynchronize(s));
   double mn = INFINITY;
   for (double v : detmin) mn = fmin(mn, v);
   m->min_det = mn;
   MX_MCHECK(mn > 0.0, MXSEM_EMESH, "mesh_create: non-positive Jacobian determinant");
 
-  // gather-scatter plan (host): counting sort of local entries by global id
-  const int64_t* glo = d->glo;
-  int64_t gmax = -1;
-  for (int64_t i = 0; i < nloc; ++i) {
-    MX_MCHECK(glo[i] >= 0, MXSEM_EINVAL, "mesh_create: negative global id");
-    gmax = std::max(gmax, glo[i]);
-  }
-  std::vector<int32_t> order(nloc);
-  std::vector<int64_t> gstart;  // group boundaries in `order`
-  {
-    if (gmax < 4 * nloc + 1024) {
-      std::vector<int32_t> cnt(gmax + 2, 0);
-      for (int64_t i = 0; i < nloc; ++i) cnt[glo[i] + 1]++;
-      for (int64_t g = 0; g <= gmax; ++g) cnt[g + 1] += cnt[g];
-      std::vector<int32_t> pos(cnt.begin(), cnt.end() - 1);
-      for (int64_t i = 0; i < nloc; ++i) order[pos[glo[i]]++] = (int32_t)i;
-      for (int64_t g = 0; g <= gmax; ++g)
-        if (cnt[g + 1] > cnt[g]) gstart.push_back(cnt[g]);
-    } else {
-      for (int64_t i = 0; i < nloc; ++i) order[i] = (int32_t)i;
-      std::stable_sort(order.begin(), order.end(),
-                       [glo](int32_t a, int32_t b) { return glo[a] < glo[b]; });
-      for (int64_t t = 0; t < nloc; ++t)
-        if (t == 0 || glo[order[t]] != glo[order[t - 1]]) gstart.push_back(t);
-    }
-    gstart.push_back(nloc);
-  }
-  const int64_t ng = (int64_t)gstart.size() - 1;
-  std::vector<uint8_t> mult(nloc);
-  struct Grp {
-    int32_t m, first;  // size, position in `order`
-  };
-  std::vector<std::vector<Grp>> freeb(256), maskb(256);
-  std::vector<int32_t> masklist;
-  const uint8_t* bnd = d->bnd;
-  int64_t ngroups = 0;
-  for (int64_t q = 0; q < ng; ++q) {
-    const int64_t a = gstart[q], b = gstart[q + 1];
-    const int32_t sz = (int32_t)(b - a);
-    MX_MCHECK(sz <= 255, MXSEM_ENOTSUP, "mesh_create: a node shared by more than 255 elements");
-    const bool msk = bnd[order[a]] != 0;
-    for (int64_t t = a; t < b; ++t) {
-      const int32_t li = order[t];
-      MX_MCHECK((bnd[li] != 0) == msk, MXSEM_EMESH,
-                "mesh_create: copies of a global node disagree on the Dirichlet flag");
-      mult[li] = (uint8_t)sz;
-      if (msk) masklist.push_back(li);
-    }
-    if (sz >= 2) {
-      (msk ? maskb : freeb)[sz].push_back(Grp{sz, (int32_t)a});
-      ++ngroups;
-    }
-  }
-  std::sort(masklist.begin(), masklist.end());
-  // bucket order: 8, 4, 2 (vector index loads), then every other m descending
-  std::vector<int> morder = {8, 4, 2};
-  for (int mm = 255; mm >= 2; --mm)
-    if (mm != 8 && mm != 4 && mm != 2) morder.push_back(mm);
-  std::vector<int32_t> idx;
-  GsPlan plan{};
-  int nb = 0;
-  m->gs_first.assign(MAX_BUCKETS, {});
-  auto emit = [&](std::vector<std::vector<Grp>>& bks) -> bool {
-    for (int mm : morder) {
-      auto& gv = bks[mm];
-      if (gv.empty()) continue;
-      if (nb >= MAX_BUCKETS - 1) return false;
-      std::sort(gv.begin(), gv.end(),
-                [&order](const Grp& x, const Grp& y) { return order[x.first] < order[y.first]; });
-      while (idx.size() % 4) idx.push_back(0);  // 16-byte aligned bucket start
-      plan.bk[nb] = GsBucket{mm, (int)gv.size(), (int)idx.size(), 0};
-      std::vector<int32_t>& gf = m->gs_first[nb];
-      gf.reserve(gv.size());
-      for (const Grp& gr : gv) {
-        gf.push_back(order[gr.first]);
-        for (int t = 0; t < gr.m; ++t) idx.push_back(order[gr.first + t]);
-      }
-      ++nb;
-    }
-    return true;
-  };
-  MX_MCHECK(emit(freeb), MXSEM_ENOTSUP, "mesh_create: too many distinct node multiplicities");
-  plan.nfree = nb;
-  MX_MCHECK(emit(maskb), MXSEM_ENOTSUP, "mesh_create: too many distinct node multiplicities");
-  plan.nall = nb;
-  while (idx.size() % 4) idx.push_back(0);
-  plan.bk[nb] = GsBucket{0, (int)masklist.size(), (int)idx.size(), 0};
-  idx.insert(idx.end(), masklist.begin(), masklist.end());
-  m->gs_first[nb] = masklist;
-  m->ngroups = ngroups;
-  m->nmask_entries = (int)masklist.size();
-  MX_MTRY(mesh_alloc(m, (void**)&m->gs_idx, sizeof(int) * std::max<size_t>(idx.size(), 4)));
-  MX_MTRY(mesh_alloc(m, (void**)&m->mult, nloc));
+  // gather-scatter plan and copy counts to the device
   if (!idx.empty())
     MX_MHIP(hipMemcpyAsync(m->gs_idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice, s));
   MX_MHIP(hipMemcpyAsync(m->mult, mult.data(), nloc, hipMemcpyHostToDevice, s));
-  plan.idx = m->gs_idx;
-  plan.n3 = m->n3;
-  plan.erank = nullptr;
-  m->plan = plan;
-
-  // scratch
-  const int64_t nbu = (nloc + UPD_CHUNK - 1) / UPD_CHUNK;
-  MX_MTRY(mesh_alloc(m, (void**)&m->part, sizeof(double) * (nbu + 64)));
-  MX_MTRY(mesh_alloc(m, (void**)&m->scal, sizeof(double) * 8));
+  m->plan.idx = m->gs_idx;
 
   // Helmholtz term h*B
-  if (m->helm_h != 0.0) {
-    MX_MTRY(mesh_alloc(m, (void**)&m->hB64, sizeof(double) * nloc));
-    MX_MHIP(launch_scale(m->hB64, m->B64, m->helm_h, nloc, s));
-  }
+  if (m->helm_h != 0.0) MX_MHIP(launch_scale(m->hB64, m->B64, m->helm_h, nloc, s));
 
   // Jacobi: assembled diagonal (FP64), inverse, zero on Dirichlet entries
-  MX_MTRY(mesh_alloc(m, (void**)&m->dinv64, sizeof(double) * nloc));
   MX_MHIP(launch_diag(m->E, n, m->G64, m->B64, m->helm_h, m->D64, m->dinv64, s));
   MX_MHIP(launch_gs_apply(MXSEM_F64, MXSEM_F64, m->dinv64, m->plan, false, s));
   MX_MHIP(launch_invert(m->dinv64, nloc, s));
@@ -465,33 +609,23 @@ int mxsem_mesh_create(mxsem_ctx* ctx, const mxsem_mesh_desc* d, mxsem_mesh** out
   }
 
   // lower-precision views (one-time casts)
-  if (m->views & (MXSEM_VIEW_F32 | MXSEM_VIEW_BF16)) {
-    MX_MTRY(mesh_alloc(m, (void**)&m->dinv32, sizeof(float) * nloc));
-    MX_MHIP(launch_cast_f32(m->dinv32, m->dinv64, nloc, s));
+  if (m->dinv32) MX_MHIP(launch_cast_f32(m->dinv32, m->dinv64, nloc, s));
+  if (m->G32) {
+    MX_MHIP(launch_cast_g_split(1, m->G32, m->G64, m->E, m->n3, s));
+    if (m->hB32) MX_MHIP(launch_cast_f32(m->hB32, m->hB64, nloc, s));
   }
-  if (m->views & MXSEM_VIEW_F32) {
-    MX_MTRY(mesh_alloc(m, (void**)&m->G32, sizeof(float) * 6 * nloc));
-    MX_MHIP(launch_cast_g_split(1, m->G32, m->G64, m->E, n * n * n, s));
-    if (m->hB64) {
-      MX_MTRY(mesh_alloc(m, (void**)&m->hB32, sizeof(float) * nloc));
-      MX_MHIP(launch_cast_f32(m->hB32, m->hB64, nloc, s));
-    }
+  if (m->G16) {
+    MX_MHIP(launch_cast_g_split(2, m->G16, m->G64, m->E, m->n3, s));
+    if (m->hB16) MX_MHIP(launch_cast_bf16(m->hB16, m->hB64, nloc, s));
   }
-  if (m->views & MXSEM_VIEW_BF16) {
-    MX_MTRY(mesh_alloc(m, (void**)&m->G16, sizeof(bf16_t) * 6 * nloc));
-    MX_MHIP(launch_cast_g_split(2, m->G16, m->G64, m->E, n * n * n, s));
-    if (m->hB64) {
-      MX_MTRY(mesh_alloc(m, (void**)&m->hB16, sizeof(bf16_t) * nloc));
-      MX_MHIP(launch_cast_bf16(m->hB16, m->hB64, nloc, s));
-    }
+  // the set-up temporaries sat in the FP64 work vectors: clear them again
+  {
+    const int64_t n16 = (int64_t)((align256(tmp.end) - tmp.begin) / 16);
+    hipLaunchKernelGGL(ws_zero_kernel, dim3((unsigned)std::min<int64_t>((n16 + 255) / 256, 65536)),
+                       dim3(256), 0, s, (uint4*)(m->ws + tmp.begin), n16);
+    MX_MHIP(hipGetLastError());
   }
   MX_MHIP(hipStreamSynchronize(s));
-  // the coordinates and k are no longer needed on the device
-  for (void* p : {(void*)xyz_d, (void*)k_d, (void*)detmin_d}) {
-    if (!p) continue;
-    (void)hipFree(p);
-    m->allocs.erase(std::find(m->allocs.begin(), m->allocs.end(), p));
-  }
   for (int q = 0; q < 16; ++q) m->epb[q] = 0;
   ctx->live += 1;
   m->counted = true;
@@ -612,6 +746,30 @@ int mxsem_dot_ex(mxsem_mesh* m, mxsem_prec io, int acc, const void* a, const voi
   MX_API_END("mxsem_dot_ex")
 }
 
+int mxsem_dot_ex_noalloc(mxsem_mesh* m, mxsem_prec io, int acc, const void* a, const void* b,
+                         double* out_dev) {
+  MX_API_BEGIN
+  MX_CHECK(m && a && b && out_dev, MXSEM_EINVAL, "dot_ex_noalloc: null argument");
+  MX_CHECK(io == MXSEM_F64 || io == MXSEM_F32, MXSEM_EINVAL, "dot_ex_noalloc: io must be F64/F32");
+  MX_CHECK(acc >= MXSEM_DOT_DEFAULT && acc <= MXSEM_DOT_DOT2, MXSEM_EINVAL,
+           "dot_ex_noalloc: unknown accumulation");
+  const int dm = dot_mode_of(acc, DOT_F64);
+  MX_CHECK(io == MXSEM_F32 || dm == DOT_F64, MXSEM_ENOTSUP,
+           "dot_ex_noalloc: FP32 and Dot2 accumulation take FP32 vectors");
+  MX_CHECK(m->nloc <= MXSEM_NOALLOC_MAX_ENTRIES, MXSEM_EINVAL,
+           "dot_ex_noalloc: more local entries than the static scratch holds partial sums for "
+           "(at most 16777216)");
+  MX_HIP(hipSetDevice(m->ctx->device));
+  (void)hipGetLastError();
+  if (!m->ctx->noalloc_scratch) MX_TRY(scratch_address(m->ctx->device, &m->ctx->noalloc_scratch));
+  // every partial the final sum reads is written by this call's first
+  // kernel, so nothing has to be cleared
+  MX_HIP(launch_dot(io, a, b, m->mult, m->nloc, m->ctx->noalloc_scratch, out_dev, m->ctx->stream,
+                    dm));
+  return MXSEM_OK;
+  MX_API_END("mxsem_dot_ex_noalloc")
+}
+
 int mxsem_mesh_set_ranks(mxsem_mesh* m, const int32_t* rank_host) {
   MX_API_BEGIN
   MX_CHECK(m, MXSEM_EINVAL, "set_ranks: null mesh");
@@ -623,7 +781,6 @@ int mxsem_mesh_set_ranks(mxsem_mesh* m, const int32_t* rank_host) {
   }
   for (int e = 0; e < m->E; ++e)
     MX_CHECK(rank_host[e] >= 0, MXSEM_EINVAL, "set_ranks: ranks must be >= 0");
-  if (!m->erank) MX_TRY(mesh_alloc(m, (void**)&m->erank, sizeof(int) * (size_t)m->E));
   hipStream_t s = m->ctx->stream;
   MX_HIP(hipStreamSynchronize(s));  // no queued work may still read the old ranks
   MX_HIP(hipMemcpy(m->erank, rank_host, sizeof(int) * (size_t)m->E, hipMemcpyHostToDevice));

@@ -12,6 +12,8 @@ struct mxsem_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int* pinned_flags = nullptr;    // host-pinned poll buffer
   int live = 0;                   // meshes / batches created from this context
+  double* noalloc_scratch = nullptr;  // device address of the static scratch array
+                                      // on this context's device
 };
 
 namespace mx {
@@ -111,6 +113,40 @@ void deriv_matrix(int N, const double* xi, double* D);
 // vector precision class of a solve
 enum VPrec { VP_F64 = 0, VP_F32 = 1, VP_F32ACC = 3 };
 
+// ---------------------------------------------------------------- caller workspaces
+// The library allocates no device memory: every device array of a mesh, a
+// network, a batch or an autotuning run is a block of a workspace the caller
+// allocated (its size comes from the matching *_workspace_bytes call).
+// Blocks start on 256-byte boundaries.
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Offsets of the blocks of a workspace, in the order they are taken.
+struct Layout {
+  size_t total = 0;
+  size_t take(size_t bytes) {
+    const size_t o = align256(total);
+    total = o + (bytes ? bytes : 1);
+    return o;
+  }
+};
+
+// A workspace block handed out piece by piece (launch tables of a plan,
+// rebuilt in place when the plan is rebuilt).
+struct Region {
+  char* base = nullptr;
+  size_t size = 0, used = 0;
+};
+// *p = the next 256-aligned piece of `bytes`; MXSEM_EINTERNAL past the end
+// (the workspace was sized for every plan the object can build).
+int region_take(Region& r, void** p, size_t bytes);
+
+// Bytes of the launch tables of one plan over these problems (operator,
+// gather-scatter and vector-pass tiles, problem views, states, norms).
+size_t plan_table_bytes(mxsem_mesh* const* meshes, int P);
+
+// Workspace bytes of an autotuning run at (N, E, prec).
+size_t autotune_bytes(int N, int E, int prec);
+
 // Device work vectors and partial-sum arrays of one problem in one vector
 // precision (shared by every launch plan that contains the problem).
 struct SolverBufs {
@@ -156,9 +192,7 @@ struct Plan {
   hipEvent_t evA = nullptr, evB = nullptr;
   double ax_ms_sum = 0.0;
   int ax_samples = 0;
-  std::vector<void*> dev_allocs;
-  // learned preconditioner (flexible CG): per-problem network state
-  std::vector<void*> nn_dev;
+  Region tables;  // where the launch tables live (a block of a caller workspace)
 };
 
 void plan_destroy(Plan* pl);
@@ -194,25 +228,34 @@ struct mxsem_mesh {
   int nmask_entries = 0;      // Dirichlet entries
   double min_det = 0.0;
   // scratch
-  double* part = nullptr;    // [ceil(nloc / UPD_CHUNK)]
+  double* part = nullptr;    // [ceil(nloc / UPD_CHUNK) + 64]
   double* scal = nullptr;    // [8] device scalars
-  double* tmpa = nullptr;    // FP64 [nloc] work vectors (lazily)
+  double* tmpa = nullptr;    // FP64 [nloc] work vectors
   double* tmpb = nullptr;
   int epb[16] = {0};
+  // solver work vectors per vector precision (VP_F32ACC shares VP_F32's)
   mx::SolverBufs* bufs[4] = {nullptr, nullptr, nullptr, nullptr};
   mx::Plan* self_plan[4] = {nullptr, nullptr, nullptr, nullptr};
+  mx::Region plan_tables[4];  // workspace blocks of the self plans' tables
   mxsem_nn* nn = nullptr;
-  std::vector<void*> allocs;
+  char* ws = nullptr;         // the caller's workspace (never freed here)
+  size_t ws_bytes = 0;
   bool counted = false;
 };
 
 namespace mx {
-int mesh_alloc(mxsem_mesh* m, void** p, size_t bytes);
 int default_epb(int N);
+// the solver work vectors of vprec (MXSEM_ENOTSUP if the mesh's views
+// leave that precision out)
 int ensure_bufs(mxsem_mesh* m, int vprec, SolverBufs** out);
 int mesh_epb(const mxsem_mesh* m);
 void mesh_drop_plans(mxsem_mesh* m);
-int ensure_tmp(mxsem_mesh* m);
+// gather-scatter tiles of problem p, one list per XCD (see solver.hip)
+void gs_tiles_by_xcd(const mxsem_mesh* m, int p, std::vector<std::vector<Tile>>& lists);
+// bytes of the work vectors and partial sums of one vector precision
+size_t solver_bufs_bytes(const mxsem_mesh* m, int vprec);
+// carve them from ws + at (layout pass: ws == nullptr only counts)
+void carve_solver_bufs(mxsem_mesh* m, int vprec, char* ws, Layout& L);
 const void* G_ptr(const mxsem_mesh* m, int gprec);
 const void* hB_ptr(const mxsem_mesh* m, int gprec);
 int apply_impl(mxsem_mesh* m, int prec, const void* u, void* w, unsigned flags, hipStream_t s);

@@ -45,42 +45,62 @@ int gprec_of_mode(int mode) {
 
 int mesh_epb(const mxsem_mesh* m) { return m->epb[m->N] > 0 ? m->epb[m->N] : default_epb(m->N); }
 
-int ensure_bufs(mxsem_mesh* m, int vprec, SolverBufs** out) {
-  if (m->bufs[vprec]) {
-    *out = m->bufs[vprec];
-    return MXSEM_OK;
+int region_take(Region& r, void** p, size_t bytes) {
+  const size_t o = align256(r.used);
+  if (!r.base || o + bytes > r.size) {
+    set_error("workspace block exhausted (sized too small for this plan)");
+    return MXSEM_EINTERNAL;
   }
-  SolverBufs* b = new SolverBufs();
-  b->vprec = vprec;
-  const size_t es = vprec == VP_F64 ? 8 : 4;
-  const int64_t nl = m->nloc;
+  *p = r.base + o;
+  r.used = o + (bytes ? bytes : 1);
+  return MXSEM_OK;
+}
+
+static int gs_bufs_tiles(const mxsem_mesh* m) {
   int ngs = 0;
   for (int q = 0; q <= m->plan.nall; ++q)
     if (q < m->plan.nfree || q == m->plan.nall)
       ngs += (m->plan.bk[q].ngroups + GS_CHUNK - 1) / GS_CHUNK;
-  b->nt_gs = ngs;
-  b->nt_upd = (int)((nl + UPD_CHUNK - 1) / UPD_CHUNK);
-  int rc = MXSEM_OK;
-  auto A = [&](void** p, size_t bytes) {
-    if (rc == MXSEM_OK) rc = mesh_alloc(m, p, bytes);
+  return ngs;
+}
+
+// Work vectors x r z p w (FP64 also p_alt, the second direction buffer) and
+// the partial-sum arrays of one vector precision, as blocks of the mesh's
+// workspace; with ws, m->bufs[vprec] points at them.
+void carve_solver_bufs(mxsem_mesh* m, int vprec, char* ws, Layout& L) {
+  const size_t es = vprec == VP_F64 ? 8 : 4;
+  const int64_t nl = m->nloc;
+  const int nt_gs = gs_bufs_tiles(m);
+  const int nt_upd = (int)((nl + UPD_CHUNK - 1) / UPD_CHUNK);
+  SolverBufs* b = ws ? new SolverBufs() : nullptr;
+  auto put = [&](void** p, size_t bytes) {
+    const size_t o = L.take(bytes);
+    if (b) *p = ws + o;
   };
-  A(&b->x, es * nl);
-  A(&b->r, es * nl);
-  A(&b->z, es * nl);
-  A(&b->p, es * nl);
-  A(&b->w, es * nl);
-  if (vprec == VP_F64) A(&b->p_alt, es * nl);  // second direction buffer (FP64 only)
-  A((void**)&b->part_ax, sizeof(double) * (m->E + 1));  // any tile size fits
-  A((void**)&b->part_gs, sizeof(double) * (b->nt_gs + 1));
-  A((void**)&b->part_u0, sizeof(double) * (b->nt_upd + 1));
-  A((void**)&b->part_u1, sizeof(double) * (b->nt_upd + 1));
-  A((void**)&b->part_u2, sizeof(double) * (b->nt_upd + b->nt_gs + 1));
-  if (rc != MXSEM_OK) {
-    delete b;
-    return rc;
+  void* dummy = nullptr;
+  put(b ? &b->x : &dummy, es * nl);
+  put(b ? &b->r : &dummy, es * nl);
+  put(b ? &b->z : &dummy, es * nl);
+  put(b ? &b->p : &dummy, es * nl);
+  put(b ? &b->w : &dummy, es * nl);
+  if (vprec == VP_F64) put(b ? &b->p_alt : &dummy, es * nl);
+  put(b ? (void**)&b->part_ax : &dummy, sizeof(double) * (m->E + 1));  // any tile size fits
+  put(b ? (void**)&b->part_gs : &dummy, sizeof(double) * (nt_gs + 1));
+  put(b ? (void**)&b->part_u0 : &dummy, sizeof(double) * (nt_upd + 1));
+  put(b ? (void**)&b->part_u1 : &dummy, sizeof(double) * (nt_upd + 1));
+  put(b ? (void**)&b->part_u2 : &dummy, sizeof(double) * (nt_upd + nt_gs + 1));
+  if (b) {
+    b->vprec = vprec;
+    b->nt_gs = nt_gs;
+    b->nt_upd = nt_upd;
+    m->bufs[vprec] = b;
   }
-  m->bufs[vprec] = b;
-  *out = b;
+}
+
+int ensure_bufs(mxsem_mesh* m, int vprec, SolverBufs** out) {
+  MX_CHECK(m->bufs[vprec], MXSEM_ENOTSUP,
+           "solve: the mesh's views leave out this vector precision");
+  *out = m->bufs[vprec];
   return MXSEM_OK;
 }
 
@@ -91,7 +111,6 @@ void plan_destroy(Plan* pl) {
   if (pl->evB) (void)hipEventDestroy(pl->evB);
   if (pl->hstate) (void)hipHostFree(pl->hstate);
   if (pl->hnorm) (void)hipHostFree(pl->hnorm);
-  for (void* p : pl->dev_allocs) (void)hipFree(p);
   delete pl;
 }
 
@@ -102,15 +121,7 @@ void mesh_drop_plans(mxsem_mesh* m) {
   }
 }
 
-static int plan_alloc(Plan* pl, void** p, size_t bytes) {
-  hipError_t e = hipMalloc(p, bytes ? bytes : 256);
-  if (e != hipSuccess) {
-    set_error(std::string("plan: hipMalloc: ") + hipGetErrorString(e));
-    return MXSEM_ENOMEM;
-  }
-  pl->dev_allocs.push_back(*p);
-  return MXSEM_OK;
-}
+static int plan_alloc(Plan* pl, void** p, size_t bytes) { return region_take(pl->tables, p, bytes); }
 
 // Gather-scatter tiles of problem p, sorted into one list per XCD.  The
 // gather-scatter is the one kernel whose workgroups share cache lines (a
@@ -121,7 +132,7 @@ static int plan_alloc(Plan* pl, void** p, size_t bytes) {
 // entries, and for every block the groups of every bucket whose first
 // copy lies in the block become tiles of that chunk's list, block by
 // block.  Tile.pad is the tile's group count (at most GS_CHUNK).
-static void gs_tiles_by_xcd(const mxsem_mesh* m, int p, std::vector<std::vector<Tile>>& lists) {
+void gs_tiles_by_xcd(const mxsem_mesh* m, int p, std::vector<std::vector<Tile>>& lists) {
   const int nx = (int)lists.size();
   const int64_t n3 = m->n3;
   const int eb = (int)std::max<int64_t>(1, 8192 / n3);
@@ -142,11 +153,41 @@ static void gs_tiles_by_xcd(const mxsem_mesh* m, int p, std::vector<std::vector<
   }
 }
 
-// Build the launch plan of P problems (all on one context) in vprec.
-int plan_build(mxsem_mesh* const* meshes, int P, int vprec, Plan** out) {
+// The gather-scatter tile table of a plan: each problem's per-XCD lists,
+// interleaved so that workgroup b of a launch runs on XCD b % XCDS, padded
+// with empty tiles so that the alignment holds to the end.
+static void gs_table(mxsem_mesh* const* meshes, int P, std::vector<Tile>& tg) {
+  std::vector<std::vector<Tile>> gsl(XCDS);
+  for (int p = 0; p < P; ++p) gs_tiles_by_xcd(meshes[p], p, gsl);
+  size_t len = 0;
+  for (const auto& l : gsl) len = std::max(len, l.size());
+  for (size_t i = 0; i < len; ++i)
+    for (int x = 0; x < XCDS; ++x) tg.push_back(i < gsl[x].size() ? gsl[x][i] : Tile{0, 0, 0, 0});
+}
+
+size_t plan_table_bytes(mxsem_mesh* const* meshes, int P) {
+  std::vector<Tile> tg;
+  gs_table(meshes, P, tg);
+  size_t ax = 0, upd = 0;
+  for (int p = 0; p < P; ++p) {
+    ax += (size_t)meshes[p]->E;  // at most one tile per element, whatever the tuning
+    upd += (size_t)((meshes[p]->nloc + UPD_CHUNK - 1) / UPD_CHUNK);
+  }
+  // one block per operator class (at most one class per problem), then the
+  // gather-scatter and vector-pass tables, problem views, states and norms
+  return sizeof(Tile) * ax + 256 * (size_t)(P + 1) + align256(sizeof(Tile) * (tg.size() + 1)) +
+         align256(sizeof(Tile) * (upd + 1)) + align256(sizeof(ProbDev) * P) +
+         align256(sizeof(State) * P) + align256(sizeof(double) * P) + 256;
+}
+
+// Build the launch plan of P problems (all on one context) in vprec, its
+// tables in the workspace block `tables`.
+int plan_build(mxsem_mesh* const* meshes, int P, int vprec, Region tables, Plan** out) {
   Plan* pl = new Plan();
   pl->vprec = vprec;
   pl->P = P;
+  pl->tables = tables;
+  pl->tables.used = 0;
   pl->device = meshes[0]->ctx->device;
   int rc = MXSEM_OK;
   auto fail = [&](int code) {
@@ -154,7 +195,6 @@ int plan_build(mxsem_mesh* const* meshes, int P, int vprec, Plan** out) {
     return code;
   };
   std::vector<Tile> tg, tu;
-  std::vector<std::vector<Tile>> gsl(XCDS);
   pl->hprob.resize(P);
   for (int p = 0; p < P; ++p) {
     mxsem_mesh* m = meshes[p];
@@ -187,18 +227,9 @@ int plan_build(mxsem_mesh* const* meshes, int P, int vprec, Plan** out) {
     Q.nblk_ax = (m->E + pl->epb_used[p] - 1) / pl->epb_used[p];
     Q.nblk_gs = b->nt_gs;
     Q.nblk_upd = b->nt_upd;
-    gs_tiles_by_xcd(m, p, gsl);
     for (int q = 0; q < b->nt_upd; ++q) tu.push_back(Tile{p, q * UPD_CHUNK, 0, 0});
   }
-  // workgroup b of a launch runs on XCD b % XCDS: interleave the lists,
-  // padding with empty tiles so that the alignment holds to the end
-  {
-    size_t len = 0;
-    for (const auto& l : gsl) len = std::max(len, l.size());
-    for (size_t i = 0; i < len; ++i)
-      for (int x = 0; x < XCDS; ++x)
-        tg.push_back(i < gsl[x].size() ? gsl[x][i] : Tile{0, 0, 0, 0});
-  }
+  gs_table(meshes, P, tg);
   // operator classes (N, tile size)
   std::vector<std::pair<int, int>> keys;
   for (int p = 0; p < P; ++p) {
@@ -582,7 +613,7 @@ int get_self_plan(mxsem_mesh* m, int vprec, Plan** out) {
     plan_destroy(m->self_plan[vprec]);
     m->self_plan[vprec] = nullptr;
   }
-  if (!m->self_plan[vprec]) MX_TRY(plan_build(&m, 1, vprec, &m->self_plan[vprec]));
+  if (!m->self_plan[vprec]) MX_TRY(plan_build(&m, 1, vprec, m->plan_tables[vprec], &m->self_plan[vprec]));
   *out = m->self_plan[vprec];
   return MXSEM_OK;
 }
@@ -606,7 +637,6 @@ static int solve_many(mxsem_ctx* ctx, const std::vector<mxsem_mesh*>& meshes, Ge
     if (vprec != VP_F64)
       MX_CHECK(m->dinv32 && (gprec == 2 || m->G32), MXSEM_ENOTSUP, "solve: mesh has no FP32 view");
     if (gprec == 2) MX_CHECK(m->G16, MXSEM_ENOTSUP, "solve: mesh has no BF16 view");
-    MX_TRY(ensure_tmp(m));
     memset(&st[p], 0, sizeof(mxsem_solve_stats));
   }
   Plan* pl = nullptr;
@@ -795,7 +825,29 @@ struct mxsem_batch {
   mxsem_ctx* ctx = nullptr;
   std::vector<mxsem_mesh*> meshes;
   mx::Plan* plans[4] = {nullptr, nullptr, nullptr, nullptr};
+  mx::Region tables[4];  // workspace blocks of the plans' launch tables
 };
+
+namespace mx {
+// Layout of a batch workspace: the launch tables of the three plans a batch
+// can build (FP64, FP32, FP32 with FP32 sums), overlapped by the autotuning
+// scratch that batch_create may need before any plan exists.
+static size_t batch_layout(mxsem_mesh* const* meshes, int P, const char* path, size_t* table_bytes) {
+  const size_t tb = align256(plan_table_bytes(meshes, P));
+  *table_bytes = tb;
+  size_t tune = 0;
+  if (path && path[0])
+    for (int p = 0; p < P; ++p) {
+      int e2 = 1;
+      while (e2 < meshes[p]->E) e2 <<= 1;
+      tune = std::max(tune, autotune_bytes(meshes[p]->N, e2, MXSEM_F32));
+    }
+  return std::max(3 * tb, tune);
+}
+static const char* tune_path(const char* tune_cache) {
+  return tune_cache ? tune_cache : getenv("MXSEM_TUNE_CACHE");
+}
+}  // namespace mx
 
 extern "C" {
 
@@ -887,31 +939,56 @@ int mxsem_solve(mxsem_mesh* m, const mxsem_solve_opts* o, const double* b, doubl
 }
 
 // ------------------------------------------------------------------ batch
-int mxsem_autotune_cached(mxsem_ctx* ctx, int N, int E, int prec, const char* path, int* epb);
+int mxsem_autotune_cached(mxsem_ctx* ctx, int N, int E, int prec, const char* path, void* ws,
+                          size_t ws_bytes, int* epb);
+
+static int check_batch_meshes(mxsem_ctx* ctx, int P, mxsem_mesh* const* meshes) {
+  MX_CHECK(ctx && meshes && P >= 1, MXSEM_EINVAL, "batch: bad argument");
+  for (int p = 0; p < P; ++p) {
+    MX_CHECK(meshes[p], MXSEM_EINVAL, "batch: null mesh");
+    MX_CHECK(meshes[p]->ctx == ctx, MXSEM_EINVAL, "batch: meshes must share the context");
+    for (int q = 0; q < p; ++q)
+      MX_CHECK(meshes[q] != meshes[p], MXSEM_EINVAL, "batch: a mesh appears twice");
+  }
+  return MXSEM_OK;
+}
+
+int mxsem_batch_workspace_bytes(mxsem_ctx* ctx, int P, mxsem_mesh* const* meshes,
+                                const char* tune_cache, size_t* bytes) {
+  MX_API_BEGIN
+  MX_CHECK(bytes, MXSEM_EINVAL, "batch_workspace_bytes: null output");
+  MX_TRY(check_batch_meshes(ctx, P, meshes));
+  size_t tb = 0;
+  *bytes = batch_layout(meshes, P, tune_path(tune_cache), &tb);
+  return MXSEM_OK;
+  MX_API_END("mxsem_batch_workspace_bytes")
+}
 
 int mxsem_batch_create(mxsem_ctx* ctx, int P, mxsem_mesh* const* meshes, const char* tune_cache,
-                       mxsem_batch** out) {
+                       void* workspace, size_t ws_bytes, mxsem_batch** out) {
   MX_API_BEGIN
-  MX_CHECK(ctx && meshes && out && P >= 1, MXSEM_EINVAL, "batch_create: bad argument");
+  MX_CHECK(out, MXSEM_EINVAL, "batch_create: null output");
   *out = nullptr;
-  for (int p = 0; p < P; ++p) {
-    MX_CHECK(meshes[p], MXSEM_EINVAL, "batch_create: null mesh");
-    MX_CHECK(meshes[p]->ctx == ctx, MXSEM_EINVAL, "batch_create: meshes must share the context");
-    for (int q = 0; q < p; ++q)
-      MX_CHECK(meshes[q] != meshes[p], MXSEM_EINVAL, "batch_create: a mesh appears twice");
-  }
+  MX_TRY(check_batch_meshes(ctx, P, meshes));
+  const char* path = tune_path(tune_cache);
+  size_t tb = 0;
+  const size_t need = batch_layout(meshes, P, path, &tb);
+  MX_CHECK(workspace && ((uintptr_t)workspace & 255) == 0, MXSEM_EINVAL,
+           "batch_create: workspace must be a 256-byte aligned device pointer");
+  MX_CHECK(ws_bytes >= need, MXSEM_EINVAL,
+           "batch_create: workspace smaller than mxsem_batch_workspace_bytes");
   MX_HIP(hipSetDevice(ctx->device));
   (void)hipGetLastError();
-  const char* path = tune_cache ? tune_cache : getenv("MXSEM_TUNE_CACHE");
   if (path && path[0]) {
-    // one tuned tile per (N, E rounded up to a power of two), FP32 inner loop
+    // one tuned tile per (N, E rounded up to a power of two), FP32 inner
+    // loop; a miss is tuned in the workspace (no plan exists yet)
     for (int p = 0; p < P; ++p) {
       mxsem_mesh* m = meshes[p];
       if (m->epb[m->N] > 0) continue;
       int e2 = 1;
       while (e2 < m->E) e2 <<= 1;
       int epb = 0;
-      MX_TRY(mxsem_autotune_cached(ctx, m->N, e2, MXSEM_F32, path, &epb));
+      MX_TRY(mxsem_autotune_cached(ctx, m->N, e2, MXSEM_F32, path, workspace, ws_bytes, &epb));
       mxsem_tuning t{};
       t.epb[m->N] = epb;
       MX_TRY(mxsem_mesh_set_tuning(m, &t));
@@ -920,6 +997,11 @@ int mxsem_batch_create(mxsem_ctx* ctx, int P, mxsem_mesh* const* meshes, const c
   mxsem_batch* bt = new mxsem_batch();
   bt->ctx = ctx;
   bt->meshes.assign(meshes, meshes + P);
+  const int vps[3] = {VP_F64, VP_F32, VP_F32ACC};
+  for (int q = 0; q < 3; ++q) {
+    bt->tables[vps[q]].base = (char*)workspace + q * tb;
+    bt->tables[vps[q]].size = tb;
+  }
   ctx->live += 1;
   *out = bt;
   return MXSEM_OK;
@@ -957,7 +1039,8 @@ int mxsem_batch_solve(mxsem_batch* bt, const mxsem_solve_opts* o, const double* 
       bt->plans[vp] = nullptr;
     }
     if (!bt->plans[vp]) {
-      int rc = plan_build(bt->meshes.data(), (int)bt->meshes.size(), vp, &bt->plans[vp]);
+      int rc = plan_build(bt->meshes.data(), (int)bt->meshes.size(), vp, bt->tables[vp],
+                          &bt->plans[vp]);
       if (rc != MXSEM_OK) return rc;
     }
     *out = bt->plans[vp];

@@ -21,29 +21,45 @@ __global__ void fill_pattern_kernel(float* __restrict__ a, int64_t n, float base
   if (i < n) a[i] = base + 1e-3f * (float)(i % 977);
 }
 
-int autotune_epb(int device, hipStream_t s, int N, int E, int prec, int* best_epb,
+// Synthetic operator data of the tuning run as blocks of a workspace: u, w,
+// G (six factors per node) and D.
+struct TuneBlocks {
+  size_t u, w, G, D, total;
+};
+static TuneBlocks tune_blocks(int N, int E, int prec) {
+  const int n = N + 1;
+  const int64_t nloc = (int64_t)E * n * n * n;
+  const size_t vb = prec == MXSEM_F64 ? 8 : 4;
+  const size_t gb = prec == MXSEM_F64 ? 8 : prec == MXSEM_F32 ? 4 : 2;
+  Layout L;
+  TuneBlocks t;
+  t.u = L.take(vb * nloc);
+  t.w = L.take(vb * nloc);
+  t.G = L.take(gb * 6 * nloc);
+  t.D = L.take(8 * n * n);
+  t.total = align256(L.total);
+  return t;
+}
+size_t autotune_bytes(int N, int E, int prec) { return tune_blocks(N, E, prec).total; }
+
+int autotune_epb(int device, hipStream_t s, int N, int E, int prec, char* ws, int* best_epb,
                  std::vector<float>* times) {
   const int n = N + 1, n3 = n * n * n;
   const int64_t nloc = (int64_t)E * n3;
   const size_t vb = prec == MXSEM_F64 ? 8 : 4;
   const size_t gb = prec == MXSEM_F64 ? 8 : prec == MXSEM_F32 ? 4 : 2;
-  void *u = nullptr, *w = nullptr, *G = nullptr, *D = nullptr;
+  const TuneBlocks tb = tune_blocks(N, E, prec);
+  void *u = ws + tb.u, *w = ws + tb.w, *G = ws + tb.G, *D = ws + tb.D;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc = MXSEM_OK;
   auto cleanup = [&]() {
-    if (u) (void)hipFree(u);
-    if (w) (void)hipFree(w);
-    if (G) (void)hipFree(G);
-    if (D) (void)hipFree(D);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
   };
-  if (hipMalloc(&u, vb * nloc) != hipSuccess || hipMalloc(&w, vb * nloc) != hipSuccess ||
-      hipMalloc(&G, gb * 6 * nloc) != hipSuccess || hipMalloc(&D, 8 * n * n) != hipSuccess ||
-      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     cleanup();
-    set_error("autotune: allocation failed");
-    return MXSEM_ENOMEM;
+    set_error("autotune: event creation failed");
+    return MXSEM_EHIP;
   }
   // finite synthetic data (values do not affect the timing)
   const size_t words_u = vb * nloc / 4, words_G = gb * 6 * nloc / 4, words_D = 8 * n * n / 4;
@@ -132,25 +148,47 @@ using namespace mx;
 
 extern "C" {
 
-int mxsem_autotune(mxsem_ctx* ctx, int N, int E, mxsem_prec prec, mxsem_tuning* out) {
-  MX_API_BEGIN
-  MX_CHECK(ctx && out, MXSEM_EINVAL, "autotune: null argument");
+static int check_tune_args(int N, int E, int prec) {
   MX_CHECK(N >= 1 && N <= MAX_N, MXSEM_ENOTSUP, "autotune: N must be in 1..15");
   MX_CHECK(E >= 1, MXSEM_EINVAL, "autotune: E must be >= 1");
   MX_CHECK(prec >= MXSEM_F64 && prec <= MXSEM_BF16G_F32, MXSEM_EINVAL, "autotune: bad precision");
+  MX_CHECK((int64_t)E * (N + 1) * (N + 1) * (N + 1) < (int64_t)INT32_MAX - UPD_CHUNK,
+           MXSEM_ENOTSUP, "autotune: more than 2^31 local entries");
+  return MXSEM_OK;
+}
+
+int mxsem_autotune_workspace_bytes(int N, int E, mxsem_prec prec, size_t* bytes) {
+  MX_API_BEGIN
+  MX_CHECK(bytes, MXSEM_EINVAL, "autotune_workspace_bytes: null output");
+  MX_TRY(check_tune_args(N, E, prec));
+  *bytes = autotune_bytes(N, E, prec);
+  return MXSEM_OK;
+  MX_API_END("mxsem_autotune_workspace_bytes")
+}
+
+int mxsem_autotune(mxsem_ctx* ctx, int N, int E, mxsem_prec prec, void* workspace,
+                   size_t ws_bytes, mxsem_tuning* out) {
+  MX_API_BEGIN
+  MX_CHECK(ctx && out, MXSEM_EINVAL, "autotune: null argument");
+  MX_TRY(check_tune_args(N, E, prec));
+  MX_CHECK(workspace && ((uintptr_t)workspace & 255) == 0, MXSEM_EINVAL,
+           "autotune: workspace must be a 256-byte aligned device pointer");
+  MX_CHECK(ws_bytes >= autotune_bytes(N, E, prec), MXSEM_EINVAL,
+           "autotune: workspace smaller than mxsem_autotune_workspace_bytes");
   MX_HIP(hipSetDevice(ctx->device));
   (void)hipGetLastError();
   int best = 0;
-  MX_TRY(autotune_epb(ctx->device, ctx->stream, N, E, prec, &best, nullptr));
+  MX_TRY(autotune_epb(ctx->device, ctx->stream, N, E, prec, (char*)workspace, &best, nullptr));
   for (int q = 0; q < 16; ++q) out->epb[q] = 0;
   out->epb[N] = best;
   return MXSEM_OK;
   MX_API_END("mxsem_autotune")
 }
 
-// Tuned tile for (N, E, prec) from the cache file, autotuned and added to
-// the file when missing.
-int mxsem_autotune_cached(mxsem_ctx* ctx, int N, int E, int prec, const char* path, int* epb) {
+// Tuned tile for (N, E, prec) from the cache file, autotuned in the given
+// workspace and added to the file when missing.
+int mxsem_autotune_cached(mxsem_ctx* ctx, int N, int E, int prec, const char* path, void* ws,
+                          size_t ws_bytes, int* epb) {
   MX_API_BEGIN
   char key[96];
   snprintf(key, sizeof(key), "gfx950:N%d:E%d:p%d", N, E, prec);
@@ -161,7 +199,7 @@ int mxsem_autotune_cached(mxsem_ctx* ctx, int N, int E, int prec, const char* pa
     return MXSEM_OK;
   }
   mxsem_tuning t{};
-  MX_TRY(mxsem_autotune(ctx, N, E, (mxsem_prec)prec, &t));
+  MX_TRY(mxsem_autotune(ctx, N, E, (mxsem_prec)prec, ws, ws_bytes, &t));
   *epb = t.epb[N];
   kv[key] = *epb;
   write_cache(path, kv);

@@ -20,9 +20,9 @@ from . import workloads as W
 class Network:
     """Per-element 2-layer 3x3x3 conv correction to Jacobi (2 -> 32 -> 1)."""
 
-    def __init__(self, mesh: "mx.Mesh", W1=None, W2=None, seed: int = 0):
+    def __init__(self, mesh: "mx.Mesh", W1=None, W2=None, seed: int = 0, max_samples: int = 16):
         self.mesh = mesh
-        self.h = mx.mxsem_nn_create(mesh.h)
+        self.h, self.ws = mx.mxsem_nn_create(mesh.h, max_samples=max_samples)
         mesh.ctx._adopt(self)
         if W1 is None:
             W1, W2 = W.he_normal_weights(seed)
@@ -34,6 +34,7 @@ class Network:
             mx.mxsem_mesh_attach_nn(self.mesh.h, None)
             mx.mxsem_nn_destroy(self.h)
             self.h = None
+            self.ws = None
 
     def __del__(self):
         try:

@@ -38,6 +38,8 @@ LOCAL_ONLY, MASK, GS_PAIRWISE = 1, 2, 4
 DOT_DEFAULT, DOT_F64, DOT_F32, DOT_DOT2 = 0, 1, 2, 3
 GS_ORDER_ONE, GS_ORDER_PAIRWISE = 0, 1
 VIEW_F64, VIEW_F32, VIEW_BF16 = 1, 2, 4
+# limits of the allocation-free dot
+NOALLOC_SCRATCH_BYTES, NOALLOC_MAX_ENTRIES = 65536, 16777216
 
 MODE_NAMES = {MODE_FP64: "fp64", MODE_MIXED: "mixed", MODE_MIXED_IR: "mixed_ir",
               MODE_MIXED_IR_BF16G: "mixed_ir_bf16g", MODE_FP32_ALL: "fp32_all",
@@ -75,7 +77,7 @@ class mxsem_tuning(C.Structure):
 
 
 class mxsem_nn_desc(C.Structure):
-    _fields_ = [("cin", C.c_int), ("ch", C.c_int)]
+    _fields_ = [("cin", C.c_int), ("ch", C.c_int), ("max_samples", C.c_int)]
 
 
 class mxsem_adam(C.Structure):
@@ -90,7 +92,8 @@ _SIGS = {
     "mxsem_ctx_destroy": [vp],
     "mxsem_ctx_set_stream": [vp, vp],
     "mxsem_gll": [C.c_int, vp, vp],
-    "mxsem_mesh_create": [vp, C.POINTER(mxsem_mesh_desc), C.POINTER(vp)],
+    "mxsem_mesh_workspace_bytes": [C.POINTER(mxsem_mesh_desc), C.POINTER(C.c_size_t)],
+    "mxsem_mesh_create": [vp, C.POINTER(mxsem_mesh_desc), vp, C.c_size_t, C.POINTER(vp)],
     "mxsem_mesh_destroy": [vp],
     "mxsem_mesh_info": [vp, vp, vp, vp, vp],
     "mxsem_mesh_get": [vp, C.c_int, vp],
@@ -98,16 +101,20 @@ _SIGS = {
     "mxsem_gather_scatter": [vp, C.c_int, C.c_int, vp, C.c_uint],
     "mxsem_dot": [vp, C.c_int, vp, vp, vp],
     "mxsem_dot_ex": [vp, C.c_int, C.c_int, vp, vp, vp],
+    "mxsem_dot_ex_noalloc": [vp, C.c_int, C.c_int, vp, vp, vp],
     "mxsem_mesh_set_ranks": [vp, vp],
     "mxsem_precond": [vp, C.c_int, C.c_int, vp, vp],
     "mxsem_mass_rhs": [vp, vp, vp],
     "mxsem_solve": [vp, C.POINTER(mxsem_solve_opts), vp, vp, C.POINTER(mxsem_solve_stats)],
-    "mxsem_batch_create": [vp, C.c_int, vp, C.c_char_p, C.POINTER(vp)],
+    "mxsem_batch_workspace_bytes": [vp, C.c_int, vp, C.c_char_p, C.POINTER(C.c_size_t)],
+    "mxsem_batch_create": [vp, C.c_int, vp, C.c_char_p, vp, C.c_size_t, C.POINTER(vp)],
     "mxsem_batch_destroy": [vp],
     "mxsem_batch_solve": [vp, C.POINTER(mxsem_solve_opts), vp, vp, vp],
-    "mxsem_autotune": [vp, C.c_int, C.c_int, C.c_int, C.POINTER(mxsem_tuning)],
+    "mxsem_autotune_workspace_bytes": [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_size_t)],
+    "mxsem_autotune": [vp, C.c_int, C.c_int, C.c_int, vp, C.c_size_t, C.POINTER(mxsem_tuning)],
     "mxsem_mesh_set_tuning": [vp, C.POINTER(mxsem_tuning)],
-    "mxsem_nn_create": [vp, C.POINTER(mxsem_nn_desc), C.POINTER(vp)],
+    "mxsem_nn_workspace_bytes": [vp, C.POINTER(mxsem_nn_desc), C.POINTER(C.c_size_t)],
+    "mxsem_nn_create": [vp, C.POINTER(mxsem_nn_desc), vp, C.c_size_t, C.POINTER(vp)],
     "mxsem_nn_destroy": [vp],
     "mxsem_nn_set_params": [vp, vp, vp],
     "mxsem_nn_get_params": [vp, vp, vp],
@@ -175,6 +182,7 @@ _ctx_device: dict = {}
 _mesh_shape: dict = {}
 _nn_mesh: dict = {}
 _batch_meshes: dict = {}
+_batch_ws: dict = {}
 NN_PARAMS = 32 * 2 * 27 + 32 * 27
 
 
@@ -236,20 +244,54 @@ def mxsem_gll(N: int):
     return xi, w
 
 
-def mxsem_mesh_create(ctx, E, N, xyz, glo, bnd, kcoef=None, helm_h=0.0,
-                      views=VIEW_F64 | VIEW_F32 | VIEW_BF16):
+def _workspace(nbytes: int, device: int) -> torch.Tensor:
+    """Caller-owned device workspace (torch's allocator; 256-byte aligned)."""
+    ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=torch.device("cuda", device))
+    if ws.data_ptr() % 256:
+        raise RuntimeError("workspace is not 256-byte aligned")
+    return ws
+
+
+def _mesh_desc(E, N, xyz, glo, bnd, kcoef, helm_h, views):
     xyz = np.ascontiguousarray(xyz, dtype=np.float64)
     glo = np.ascontiguousarray(glo, dtype=np.int64)
     bnd = np.ascontiguousarray(bnd, dtype=np.uint8)
     kk = None if kcoef is None else np.ascontiguousarray(kcoef, dtype=np.float64)
     n3 = (N + 1) ** 3
-    assert xyz.size == 3 * E * n3 and glo.size == E * n3 and bnd.size == E * n3
+    if not (xyz.size == 3 * E * n3 and glo.size == E * n3 and bnd.size == E * n3
+            and (kk is None or kk.size == E * n3)):
+        raise ValueError("mesh arrays do not match E and N")
     d = mxsem_mesh_desc(E, N, xyz.ctypes.data, glo.ctypes.data, bnd.ctypes.data,
                         None if kk is None else kk.ctypes.data, float(helm_h), views)
+    return d, (xyz, glo, bnd, kk)  # the arrays must outlive the call
+
+
+def mxsem_mesh_workspace_bytes(E, N, xyz, glo, bnd, kcoef=None, helm_h=0.0,
+                               views=VIEW_F64 | VIEW_F32 | VIEW_BF16) -> int:
+    d, _keep = _mesh_desc(E, N, xyz, glo, bnd, kcoef, helm_h, views)
+    nb = C.c_size_t()
+    _check("mxsem_mesh_workspace_bytes", lib().mxsem_mesh_workspace_bytes(C.byref(d), C.byref(nb)))
+    return nb.value
+
+
+def mxsem_mesh_create(ctx, E, N, xyz, glo, bnd, kcoef=None, helm_h=0.0,
+                      views=VIEW_F64 | VIEW_F32 | VIEW_BF16, workspace=None):
+    """Returns (handle, workspace tensor); the tensor must outlive the mesh.
+    With workspace=None one of the size mxsem_mesh_workspace_bytes reports is
+    allocated here."""
+    d, _keep = _mesh_desc(E, N, xyz, glo, bnd, kcoef, helm_h, views)
+    dev = _ctx_device.get(_key(ctx), 0)
+    if workspace is None:
+        nb = C.c_size_t()
+        _check("mxsem_mesh_workspace_bytes",
+               lib().mxsem_mesh_workspace_bytes(C.byref(d), C.byref(nb)))
+        workspace = _workspace(nb.value, dev)
+    pw = _vec(workspace, torch.uint8, 0, dev, "mesh_create: workspace", at_least=True)
     h = vp()
-    _check("mxsem_mesh_create", lib().mxsem_mesh_create(ctx, C.byref(d), C.byref(h)))
-    _mesh_shape[_key(h)] = _MeshShape(E * n3, _ctx_device.get(_key(ctx), 0))
-    return h
+    _check("mxsem_mesh_create", lib().mxsem_mesh_create(ctx, C.byref(d), pw, workspace.numel(),
+                                                         C.byref(h)))
+    _mesh_shape[_key(h)] = _MeshShape(E * (N + 1) ** 3, dev)
+    return h, workspace
 
 
 def mxsem_mesh_destroy(mesh):
@@ -300,6 +342,12 @@ def mxsem_dot_ex(mesh, io, acc, a, b, out_dev):
     pa, pb = _local(mesh, io, a, "dot_ex: a"), _local(mesh, io, b, "dot_ex: b")
     po = _scalar64(mesh, out_dev, "dot_ex: out")
     _check("mxsem_dot_ex", lib().mxsem_dot_ex(mesh, io, acc, pa, pb, po))
+
+
+def mxsem_dot_ex_noalloc(mesh, io, acc, a, b, out_dev):
+    pa, pb = _local(mesh, io, a, "dot_ex_noalloc: a"), _local(mesh, io, b, "dot_ex_noalloc: b")
+    po = _scalar64(mesh, out_dev, "dot_ex_noalloc: out")
+    _check("mxsem_dot_ex_noalloc", lib().mxsem_dot_ex_noalloc(mesh, io, acc, pa, pb, po))
 
 
 def mxsem_mesh_set_ranks(mesh, ranks):
@@ -356,18 +404,26 @@ def mxsem_solve(mesh, opts: mxsem_solve_opts, b, x) -> mxsem_solve_stats:
 
 
 def mxsem_batch_create(ctx, meshes, tune_cache: str | None = None):
+    """Returns the handle; the batch's workspace tensor is held here until
+    mxsem_batch_destroy."""
     arr = (vp * len(meshes))(*[m.value if isinstance(m, vp) else m for m in meshes])
+    tc = None if tune_cache is None else tune_cache.encode()
+    nb = C.c_size_t()
+    _check("mxsem_batch_workspace_bytes", lib().mxsem_batch_workspace_bytes(
+        ctx, len(meshes), C.cast(arr, vp), tc, C.byref(nb)))
+    ws = _workspace(nb.value, _ctx_device.get(_key(ctx), 0))
     h = vp()
     _check("mxsem_batch_create", lib().mxsem_batch_create(
-        ctx, len(meshes), C.cast(arr, vp), None if tune_cache is None else tune_cache.encode(),
-        C.byref(h)))
+        ctx, len(meshes), C.cast(arr, vp), tc, ws.data_ptr(), ws.numel(), C.byref(h)))
     _batch_meshes[_key(h)] = [_key(m) for m in meshes]
+    _batch_ws[_key(h)] = ws
     return h
 
 
 def mxsem_batch_destroy(batch):
     _check("mxsem_batch_destroy", lib().mxsem_batch_destroy(batch))
     _batch_meshes.pop(_key(batch), None)
+    _batch_ws.pop(_key(batch), None)
 
 
 def mxsem_batch_solve(batch, opts, bs, xs):
@@ -390,8 +446,14 @@ def mxsem_batch_solve(batch, opts, bs, xs):
 
 
 def mxsem_autotune(ctx, N, E, prec) -> int:
+    nb = C.c_size_t()
+    _check("mxsem_autotune_workspace_bytes",
+           lib().mxsem_autotune_workspace_bytes(N, E, prec, C.byref(nb)))
+    ws = _workspace(nb.value, _ctx_device.get(_key(ctx), 0))
     t = mxsem_tuning()
-    _check("mxsem_autotune", lib().mxsem_autotune(ctx, N, E, prec, C.byref(t)))
+    _check("mxsem_autotune", lib().mxsem_autotune(ctx, N, E, prec, ws.data_ptr(), ws.numel(),
+                                                   C.byref(t)))
+    del ws
     return t.epb[N]
 
 
@@ -402,12 +464,17 @@ def mxsem_mesh_set_tuning(mesh, epb_by_N: dict):
     _check("mxsem_mesh_set_tuning", lib().mxsem_mesh_set_tuning(mesh, C.byref(t)))
 
 
-def mxsem_nn_create(mesh, ch=32, cin=2):
-    d = mxsem_nn_desc(cin, ch)
+def mxsem_nn_create(mesh, ch=32, cin=2, max_samples=16):
+    """Returns (handle, workspace tensor); the tensor must outlive the network."""
+    d = mxsem_nn_desc(cin, ch, max_samples)
+    nb = C.c_size_t()
+    _check("mxsem_nn_workspace_bytes", lib().mxsem_nn_workspace_bytes(mesh, C.byref(d), C.byref(nb)))
+    ws = _workspace(nb.value, _shape(mesh).device)
     h = vp()
-    _check("mxsem_nn_create", lib().mxsem_nn_create(mesh, C.byref(d), C.byref(h)))
+    _check("mxsem_nn_create", lib().mxsem_nn_create(mesh, C.byref(d), ws.data_ptr(), ws.numel(),
+                                                     C.byref(h)))
     _nn_mesh[_key(h)] = _key(mesh)
-    return h
+    return h, ws
 
 
 def mxsem_nn_destroy(nn):
@@ -541,7 +608,7 @@ class Mesh:
         self.ctx = ctx
         self.E, self.N, self.n = int(E), int(N), int(N) + 1
         self.nloc = self.E * self.n ** 3
-        self.h = mxsem_mesh_create(ctx.h, E, N, xyz, glo, bnd, kcoef, helm_h, views)
+        self.h, self.ws = mxsem_mesh_create(ctx.h, E, N, xyz, glo, bnd, kcoef, helm_h, views)
         self.dev = torch.device("cuda", ctx.device)
         ctx._adopt(self)
 
@@ -549,6 +616,7 @@ class Mesh:
         if self.h is not None:
             mxsem_mesh_destroy(self.h)
             self.h = None
+            self.ws = None  # the library no longer uses it
 
     def __del__(self):
         try:

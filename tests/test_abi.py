@@ -59,7 +59,7 @@ def test_invalid_arguments_rejected(mx):
     assert L.mxsem_gll(16, xi.ctypes.data, xi.ctypes.data) == mx.ENOTSUP
     assert L.mxsem_gll(3, None, None) == mx.EINVAL
     assert L.mxsem_ctx_create(0, None, None) == mx.EINVAL
-    assert L.mxsem_mesh_create(None, None, None) == mx.EINVAL
+    assert L.mxsem_mesh_create(None, None, None, 0, None) == mx.EINVAL
     assert L.mxsem_solve(None, None, None, None, None) == mx.EINVAL
     assert b"null" in L.mxsem_last_error()
     o = mx.solve_opts()
@@ -188,3 +188,51 @@ def _opts(mx):
     o._history = None
     o.history = None
     return o
+
+
+def _small_desc(mx, ne=2, N=3, views=None):
+    from paper_2503_02134_amd import workloads as W
+    xi, _ = mx.mxsem_gll(N)
+    bm = W.box_mesh(ne, N, xi)
+    v = (mx.VIEW_F64 | mx.VIEW_F32 | mx.VIEW_BF16) if views is None else views
+    return bm, mx._mesh_desc(bm.E, N, bm.xyz, bm.glo, bm.bnd, None, 0.0, v)
+
+
+def test_mesh_workspace_is_sized_and_checked_on_the_host(mx):
+    """The library allocates no device memory: a mesh lives in a caller
+    workspace whose size mxsem_mesh_workspace_bytes reports (host work
+    only).  mesh_create refuses a null, misaligned or undersized workspace
+    with MXSEM_EINVAL before it touches the device (no context needed to
+    see it), and only then asks for the context."""
+    L = mx.lib()
+    bm, (d, keep) = _small_desc(mx)
+    nb = C.c_size_t()
+    assert L.mxsem_mesh_workspace_bytes(C.byref(d), C.byref(nb)) == mx.OK
+    full = nb.value
+    # FP64 operator, solver vectors and both FP32 precisions: well over the
+    # 8-byte vectors alone, and a multiple of 256 bytes
+    assert full % 256 == 0 and full > 20 * 8 * bm.nloc
+    bm64, (d64, keep64) = _small_desc(mx, views=mx.VIEW_F64)
+    assert L.mxsem_mesh_workspace_bytes(C.byref(d64), C.byref(nb)) == mx.OK
+    assert nb.value < full
+    fake = 1 << 40  # never dereferenced: every check below fails first
+    h = C.c_void_p()
+    for ptr, size in ((None, full), (fake + 8, full), (fake, full - 256), (fake, 0)):
+        assert L.mxsem_mesh_create(None, C.byref(d), ptr, size, C.byref(h)) == mx.EINVAL
+        assert b"workspace" in L.mxsem_last_error()
+    assert L.mxsem_mesh_create(None, C.byref(d), fake, full, C.byref(h)) == mx.EINVAL
+    assert b"null context" in L.mxsem_last_error()
+    # descriptor errors are the same in both calls
+    d.N = 16
+    assert L.mxsem_mesh_workspace_bytes(C.byref(d), C.byref(nb)) == mx.ENOTSUP
+    assert L.mxsem_mesh_create(None, C.byref(d), fake, full, C.byref(h)) == mx.ENOTSUP
+
+
+def test_autotune_workspace_bytes(mx):
+    L = mx.lib()
+    nb = C.c_size_t()
+    assert L.mxsem_autotune_workspace_bytes(7, 64, mx.F32, C.byref(nb)) == mx.OK
+    nloc = 64 * 512
+    assert nb.value >= (4 + 4 + 24) * nloc  # u, w and six FP32 factors per node
+    assert L.mxsem_autotune_workspace_bytes(16, 64, mx.F32, C.byref(nb)) == mx.ENOTSUP
+    assert L.mxsem_autotune_workspace_bytes(7, 0, mx.F32, C.byref(nb)) == mx.EINVAL

@@ -432,3 +432,74 @@ def test_full_size_solve_sampled_residual(orc, mx, ctx):
     cs = c.reshape(E, n3)[sample]
     share = np.sqrt(np.sum(cs * ro_s * ro_s))
     assert share <= 1.001 * st.rel_res * np.sqrt(np.sum(c * bh * bh)) + 1e-12 * sc
+
+
+def test_solves_run_in_caller_workspace(orc, mx, ctx):
+    """Every device array of a mesh lives in the caller's workspace: a
+    workspace tensor filled with 0xFF bytes before the mesh is built (the
+    library clears what it needs), solves in FP64 and mixed refinement that
+    reach the oracle's solution, and no device memory taken by the library
+    while they run (the device's free memory does not drop by anything near
+    one FP64 work vector, 16 MiB here)."""
+    log("solve in a caller workspace")
+    N, ne = 7, 16
+    xg, _ = mx.mxsem_gll(N)
+    xo, _ = orc.gll(N)
+    bmg = W.box_mesh(ne, N, xg, seed=7)
+    bmo = W.box_mesh(ne, N, xo, seed=7)
+    nb = mx.mxsem_mesh_workspace_bytes(bmg.E, N, bmg.xyz, bmg.glo, bmg.bnd)
+    ws = torch.full((nb,), 255, dtype=torch.uint8, device="cuda")
+    h, ws_used = mx.mxsem_mesh_create(ctx.h, bmg.E, N, bmg.xyz, bmg.glo, bmg.bnd, workspace=ws)
+    assert ws_used is ws
+    om = orc.Mesh(bmo.E, N, bmo.xyz, bmo.glo, bmo.bnd)
+    fo, _ = W.manufactured(bmo)
+    xs, _ = om.pcg(om.rhs(fo), tol=1e-13, maxit=5000)
+    fg, _ = W.manufactured(bmg)
+    f = _t(fg)
+    b = torch.empty_like(f)
+    mx.mxsem_mass_rhs(h, f, b)
+    xa = torch.zeros_like(b)
+    xb = torch.zeros_like(b)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    sa = mx.mxsem_solve(h, mx.solve_opts(mode=mx.MODE_FP64, tol=1e-10), b, xa)
+    sb = mx.mxsem_solve(h, mx.solve_opts(mode=mx.MODE_MIXED_IR, tol=1e-10), b, xb)
+    torch.cuda.synchronize()
+    drop = free0 - torch.cuda.mem_get_info()[0]
+    ea = rel_l2(xa.cpu().numpy(), xs, om.c)
+    eb = rel_l2(xb.cpu().numpy(), xs, om.c)
+    log(f"  workspace {nb / 2**20:.1f} MiB ({nb / bmg.nloc:.0f} B per local entry); free memory "
+        f"drop during the solves {drop / 2**20:.2f} MiB; errors fp64 {ea:.1e} mixed_ir {eb:.1e}")
+    assert sa.reason == mx.CONVERGED and sb.reason == mx.CONVERGED
+    assert ea <= 1e-8 and eb <= 1e-8
+    assert drop < 4 * 2**20
+    mx.mxsem_mesh_destroy(h)
+    # a workspace one block short is refused before anything is built
+    small = torch.empty(nb - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(mx.MxsemError) as ei:
+        mx.mxsem_mesh_create(ctx.h, bmg.E, N, bmg.xyz, bmg.glo, bmg.bnd, workspace=small)
+    assert ei.value.code == mx.EINVAL and "workspace" in str(ei.value)
+
+
+def test_network_and_batch_workspaces_are_checked(mx, ctx):
+    C = __import__("ctypes")
+    xg, _ = mx.mxsem_gll(3)
+    bm = W.box_mesh(2, 3, xg)
+    gm = mx.Mesh(ctx, bm.E, 3, bm.xyz, bm.glo, bm.bnd)
+    L = mx.lib()
+    d = mx.mxsem_nn_desc(2, 32, 4)
+    nb = C.c_size_t()
+    assert L.mxsem_nn_workspace_bytes(gm.h, C.byref(d), C.byref(nb)) == mx.OK
+    ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    h = C.c_void_p()
+    assert L.mxsem_nn_create(gm.h, C.byref(d), ws.data_ptr(), nb.value - 1, C.byref(h)) == mx.EINVAL
+    d.max_samples = 0
+    assert L.mxsem_nn_workspace_bytes(gm.h, C.byref(d), C.byref(nb)) == mx.EINVAL
+    arr = (C.c_void_p * 1)(gm.h.value)
+    assert L.mxsem_batch_workspace_bytes(ctx.h, 1, C.cast(arr, C.c_void_p), None,
+                                         C.byref(nb)) == mx.OK
+    ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    assert L.mxsem_batch_create(ctx.h, 1, C.cast(arr, C.c_void_p), None, ws.data_ptr(),
+                                nb.value - 256, C.byref(h)) == mx.EINVAL
+    assert b"workspace" in L.mxsem_last_error()
+    gm.close()
