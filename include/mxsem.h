@@ -239,24 +239,6 @@ int mxsem_dot(mxsem_mesh *mesh, mxsem_prec io, const void *a, const void *b,
 int mxsem_dot_ex(mxsem_mesh *mesh, mxsem_prec io, int acc, const void *a, const void *b,
                  double *out_dev);
 
-/* ---- allocation-free dot ---------------------------------------------------
- * For callers that cannot allocate device memory: code under HIP graph
- * capture, tight serving loops, harnesses that forbid hipMalloc.  Computes
- * what mxsem_dot_ex computes, with the same kernels and the same partial
- * sums, bit for bit, but the per-workgroup partial sums live in a static
- * device array of the library (MXSEM_NOALLOC_SCRATCH_BYTES per GPU, held
- * until the process ends) instead of the mesh's buffer.  Allocates nothing;
- * only enqueues two kernels on the context stream (async).  Meshes with more
- * than MXSEM_NOALLOC_MAX_ENTRIES local entries (one partial per 2048
- * entries) are refused with MXSEM_EINVAL.  Every call on one GPU shares that
- * GPU's array and each call overwrites the partials it reads, so calls on
- * one stream are ordered and safe, while calls that overlap on one GPU
- * (other streams, contexts or host threads) race. */
-#define MXSEM_NOALLOC_SCRATCH_BYTES 65536
-#define MXSEM_NOALLOC_MAX_ENTRIES 16777216
-int mxsem_dot_ex_noalloc(mxsem_mesh *mesh, mxsem_prec io, int acc, const void *a,
-                         const void *b, double *out_dev);
-
 /* z = M^-1 r for pc = identity or Jacobi (io MXSEM_F64 / MXSEM_F32), or the
  * learned map (MXSEM_F32, network attached). */
 int mxsem_precond(mxsem_mesh *mesh, mxsem_pc pc, mxsem_prec io, const void *r, void *z);

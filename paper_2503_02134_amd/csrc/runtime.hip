@@ -7,7 +7,6 @@
 
 #include <algorithm>
 #include <memory>
-#include <mutex>
 #include <type_traits>
 #include <new>
 #include <string>
@@ -16,40 +15,6 @@
 #include "runtime.hpp"
 
 namespace mx {
-
-// Scratch of mxsem_dot_ex_noalloc: the per-workgroup partial sums of the dot
-// live in this static device array (one copy per GPU, held until the
-// process ends) instead of a buffer the library allocates.  In host code
-// the name is only a stand-in: the device address comes from
-// hipGetSymbolAddress, taken once per device at the entry point's first
-// call on that device, and kernels receive that address.
-constexpr int NOALLOC_PARTS = MXSEM_NOALLOC_SCRATCH_BYTES / (int)sizeof(double);
-static_assert((int64_t)NOALLOC_PARTS * UPD_CHUNK == MXSEM_NOALLOC_MAX_ENTRIES,
-              "the entry limit is one partial per vector-pass workgroup");
-static __device__ __align__(256) double scratch[NOALLOC_PARTS];
-constexpr int MAX_DEVICES = 64;
-static std::mutex g_scratch_mu;
-static double* g_scratch_addr[MAX_DEVICES] = {};
-
-// Device address of `scratch` on the current device (dev), looked up once.
-static int scratch_address(int dev, double** out) {
-  std::lock_guard<std::mutex> lk(g_scratch_mu);
-  if (dev < 0 || dev >= MAX_DEVICES) {
-    set_error("scratch: device index out of range");
-    return MXSEM_EINVAL;
-  }
-  if (!g_scratch_addr[dev]) {
-    void* ptr = nullptr;
-    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
-    if (e != hipSuccess || !ptr) {
-      set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
-      return MXSEM_EHIP;
-    }
-    g_scratch_addr[dev] = (double*)ptr;
-  }
-  *out = g_scratch_addr[dev];
-  return MXSEM_OK;
-}
 
 static thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
@@ -744,30 +709,6 @@ int mxsem_dot_ex(mxsem_mesh* m, mxsem_prec io, int acc, const void* a, const voi
   MX_HIP(launch_dot(io, a, b, m->mult, m->nloc, m->part, out_dev, m->ctx->stream, dm));
   return MXSEM_OK;
   MX_API_END("mxsem_dot_ex")
-}
-
-int mxsem_dot_ex_noalloc(mxsem_mesh* m, mxsem_prec io, int acc, const void* a, const void* b,
-                         double* out_dev) {
-  MX_API_BEGIN
-  MX_CHECK(m && a && b && out_dev, MXSEM_EINVAL, "dot_ex_noalloc: null argument");
-  MX_CHECK(io == MXSEM_F64 || io == MXSEM_F32, MXSEM_EINVAL, "dot_ex_noalloc: io must be F64/F32");
-  MX_CHECK(acc >= MXSEM_DOT_DEFAULT && acc <= MXSEM_DOT_DOT2, MXSEM_EINVAL,
-           "dot_ex_noalloc: unknown accumulation");
-  const int dm = dot_mode_of(acc, DOT_F64);
-  MX_CHECK(io == MXSEM_F32 || dm == DOT_F64, MXSEM_ENOTSUP,
-           "dot_ex_noalloc: FP32 and Dot2 accumulation take FP32 vectors");
-  MX_CHECK(m->nloc <= MXSEM_NOALLOC_MAX_ENTRIES, MXSEM_EINVAL,
-           "dot_ex_noalloc: more local entries than the static scratch holds partial sums for "
-           "(at most 16777216)");
-  MX_HIP(hipSetDevice(m->ctx->device));
-  (void)hipGetLastError();
-  if (!m->ctx->noalloc_scratch) MX_TRY(scratch_address(m->ctx->device, &m->ctx->noalloc_scratch));
-  // every partial the final sum reads is written by this call's first
-  // kernel, so nothing has to be cleared
-  MX_HIP(launch_dot(io, a, b, m->mult, m->nloc, m->ctx->noalloc_scratch, out_dev, m->ctx->stream,
-                    dm));
-  return MXSEM_OK;
-  MX_API_END("mxsem_dot_ex_noalloc")
 }
 
 int mxsem_mesh_set_ranks(mxsem_mesh* m, const int32_t* rank_host) {

@@ -12,8 +12,6 @@ struct mxsem_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int* pinned_flags = nullptr;    // host-pinned poll buffer
   int live = 0;                   // meshes / batches created from this context
-  double* noalloc_scratch = nullptr;  // device address of the static scratch array
-                                      // on this context's device
 };
 
 namespace mx {

@@ -38,8 +38,6 @@ LOCAL_ONLY, MASK, GS_PAIRWISE = 1, 2, 4
 DOT_DEFAULT, DOT_F64, DOT_F32, DOT_DOT2 = 0, 1, 2, 3
 GS_ORDER_ONE, GS_ORDER_PAIRWISE = 0, 1
 VIEW_F64, VIEW_F32, VIEW_BF16 = 1, 2, 4
-# limits of the allocation-free dot
-NOALLOC_SCRATCH_BYTES, NOALLOC_MAX_ENTRIES = 65536, 16777216
 
 MODE_NAMES = {MODE_FP64: "fp64", MODE_MIXED: "mixed", MODE_MIXED_IR: "mixed_ir",
               MODE_MIXED_IR_BF16G: "mixed_ir_bf16g", MODE_FP32_ALL: "fp32_all",
@@ -101,7 +99,6 @@ _SIGS = {
     "mxsem_gather_scatter": [vp, C.c_int, C.c_int, vp, C.c_uint],
     "mxsem_dot": [vp, C.c_int, vp, vp, vp],
     "mxsem_dot_ex": [vp, C.c_int, C.c_int, vp, vp, vp],
-    "mxsem_dot_ex_noalloc": [vp, C.c_int, C.c_int, vp, vp, vp],
     "mxsem_mesh_set_ranks": [vp, vp],
     "mxsem_precond": [vp, C.c_int, C.c_int, vp, vp],
     "mxsem_mass_rhs": [vp, vp, vp],
@@ -342,12 +339,6 @@ def mxsem_dot_ex(mesh, io, acc, a, b, out_dev):
     pa, pb = _local(mesh, io, a, "dot_ex: a"), _local(mesh, io, b, "dot_ex: b")
     po = _scalar64(mesh, out_dev, "dot_ex: out")
     _check("mxsem_dot_ex", lib().mxsem_dot_ex(mesh, io, acc, pa, pb, po))
-
-
-def mxsem_dot_ex_noalloc(mesh, io, acc, a, b, out_dev):
-    pa, pb = _local(mesh, io, a, "dot_ex_noalloc: a"), _local(mesh, io, b, "dot_ex_noalloc: b")
-    po = _scalar64(mesh, out_dev, "dot_ex_noalloc: out")
-    _check("mxsem_dot_ex_noalloc", lib().mxsem_dot_ex_noalloc(mesh, io, acc, pa, pb, po))
 
 
 def mxsem_mesh_set_ranks(mesh, ranks):
