@@ -6,23 +6,33 @@ Jacobi-PCG with FP64 gather-scatter sums and dots, FP64 residuals in the
 refinement loop).  value = local dofs x (inner + outer iterations) per
 second over the timed steps.  Inputs are resident in HBM before timing.
 
-Beside it: the same rate over unique nodes, the FP64 solve on the same GPU
-(like the time-to-1e-8 solves, the median of as many solves as timed steps,
-at most five, after a warm-up),
-the same refinement with BF16 geometric factors and with the inner
-direction rounded to BF16 every step (an ablation of BF16 operator
-inputs), time-to-1e-8,
-energy-to-solution (the GPU package's energy counter around repeated FP64
-and mixed solves), the roofline of the dominant kernel (the fused operator
-kernel of the inner loop: the first operator launch of every graph chunk
-records its own start and end events on the solve's stream), a measured
-copy-kernel ceiling, and the FP64 CPU oracle timed on a bounded sample of
-the same workload (with the host's core count and CPU model).  --dot fp32 |
-dot2 sets the accumulation of the inner loop's dots.  Other workloads: --workload batch64 (64
-uneven problems), --workload box24_N7_lognormal_helmholtz --mode learned
-(the learned preconditioner against Jacobi PCG and FP64 PCG) and --workload
-box20_N7 --mode strategies (the mixed-precision strategy table: gather-scatter
-sums, dot accumulation and gather-scatter order).
+The default run (box32_N7_deformed, mixed_ir) reports beside it:
+  - the same rate over unique nodes; the FP64 solve on the same GPU, the
+    refinement with BF16 geometric factors and with the inner direction
+    rounded to BF16 every step (an ablation of BF16 operator inputs), and
+    the solves to a relative residual of 1e-8 (medians of as many solves as
+    timed steps, at most five, after a warm-up);
+  - energy-to-solution (the GPU package's energy counter around repeated
+    FP64 and mixed solves);
+  - the roofline of the dominant kernel (the fused operator kernel of the
+    inner loop: the first operator launch of every graph chunk records its
+    own start and end events on the solve's stream) beside the library's
+    streaming copy at the same traffic;
+  - the learned-preconditioner leg on box24_N7_lognormal_helmholtz: pairs
+    from the FP64 solver, training, scale calibration, then learned flexible
+    CG, Jacobi PCG (both inside FP64 refinement) and FP64 Jacobi PCG on a
+    held-out right-hand side, to residuals 1e-10 and 1e-8, medians of five;
+  - the CPU oracle (plain C, FP64, OpenMP over elements) on the host cores:
+    its Jacobi-PCG solve of the benchmark workload from x = 0 to 1e-10 is
+    timed (cpu_baseline), continued to 1e-13 for the reference solution x*,
+    and every GPU solution of both legs is reported with its relative
+    c-norm error against the oracle's x* (error_vs_oracle).
+--no-learned and --no-cpu drop those legs; --dot fp32 | dot2 sets the
+accumulation of the inner loop's dots.  Other workloads: --workload batch64
+(64 uneven problems), --workload box24_N7_lognormal_helmholtz --mode learned
+(the learned leg alone, four held-out right-hand sides) and --workload
+box20_N7 --mode strategies (the mixed-precision strategy table:
+gather-scatter sums, dot accumulation and gather-scatter order).
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -57,8 +67,10 @@ def main():
                                                            "learned", "strategies"])
     ap.add_argument("--dot", default="fp64", choices=["fp64", "fp32", "dot2"],
                     help="accumulation of the FP32 loop's dots (mixed / mixed_ir modes)")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-iters", type=int, default=200)
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the CPU oracle (baseline timing and reference solutions)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-preconditioner leg of the default run")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="short run for hardware-counter collection: a 1 GiB device copy "
                          "(calibration), then 20 inner iterations of the solve; no JSON line")
@@ -133,8 +145,8 @@ def main():
         log(f"step {i}: it={st.iterations} outer={st.outer} reason={st.reason} "
             f"res={st.rel_res:.2e} {st.ms:.1f} ms ax={st.ax_ms * 1e3:.1f} us")
     value = nloc * iters / elapsed / 1e9
-    x_mixed = x.clone()
-    copy_gbs = copy_ceiling(nloc * 20)
+    sols = {args.mode: x.double().cpu().numpy()}  # GPU solutions, checked against the oracle
+    copy_gbs = copy_ceiling(ctx, nloc * 20)
 
     # dominant kernel: fused operator kernel of the inner loop
     tot = sum(s for _, s in ax_ms)
@@ -173,9 +185,7 @@ def main():
     extra["time_to_solution_ms"] = {"fp64": round(s64.ms, 3), args.mode: round(mstep.ms, 3),
                                     "gain": round(s64.ms / mstep.ms, 3),
                                     "median_of": {"fp64": reps, args.mode: len(stats)}}
-    d = (x_mixed - x64).double()
-    extra["rel_diff_vs_fp64_solution"] = float(torch.linalg.vector_norm(d)
-                                               / torch.linalg.vector_norm(x64))
+    sols["fp64"] = x64.cpu().numpy()
     if mode == mx.MODE_MIXED_IR:
         # the same refinement with BF16 geometric factors (FP32 vectors,
         # FP32 accumulation in the operator)
@@ -186,10 +196,9 @@ def main():
         extra["mixed_ir_bf16g"] = {
             "ms": round(sb.ms, 3), "iterations": sb.iterations, "outer": sb.outer,
             "rel_res": sb.rel_res, "gain_vs_fp64": round(s64.ms / sb.ms, 3),
-            "rel_diff_vs_fp64_solution": float(torch.linalg.vector_norm((xb - x64).double())
-                                               / torch.linalg.vector_norm(x64)),
             "ax_us": round(sb.ax_ms * 1e3, 2),
             "ax_gbs": round(nloc * bb / (sb.ax_ms * 1e-3) / 1e9, 1) if sb.ax_ms > 0 else None}
+        sols["mixed_ir_bf16g"] = xb.cpu().numpy()
         # ablation of BF16 operator inputs: the inner direction p rounded to
         # BF16 every step (numerics only; the vectors stay FP32 in memory)
         xp = torch.zeros_like(b)
@@ -198,16 +207,16 @@ def main():
         extra["mixed_ir_bf16p"] = {
             "ms": round(sp.ms, 3), "iterations": sp.iterations, "outer": sp.outer,
             "reason": sp.reason, "fallback_used": sp.fallback_used, "rel_res": sp.rel_res,
-            "gain_vs_fp64": round(s64.ms / sp.ms, 3),
-            "rel_diff_vs_fp64_solution": float(torch.linalg.vector_norm((xp - x64).double())
-                                               / torch.linalg.vector_norm(x64))}
+            "gain_vs_fp64": round(s64.ms / sp.ms, 3)}
+        sols["mixed_ir_bf16p"] = xp.cpu().numpy()
     tt = {}
     for name, kw in (("fp64", opts64), (args.mode, opts)):
         xt = torch.zeros_like(b)
         st8 = median_solve(xt, dict(kw, tol=1e-8), warm=False)
         tt[name] = {"ms": round(st8.ms, 3), "iterations": st8.iterations, "outer": st8.outer,
                     "rel_res": st8.rel_res, "median_of": reps}
-    extra["time_to_1e-8"] = tt
+        sols[f"residual_1e-8/{name}"] = xt.cpu().numpy()
+    extra["time_to_residual_1e-8"] = tt
     log(f"fp64: {extra['fp64']}; tt1e-8: {tt}")
 
     # energy to solution: the GPU package's energy counter around repeated solves
@@ -281,11 +290,19 @@ def main():
         **extra,
     }
 
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_iters)
-    print(json.dumps(out), flush=True)
     mesh.close()
+    learned_sols = None
+    if not args.no_learned and args.workload == "box32_N7_deformed":
+        out["learned"], learned_sols = learned_leg(ctx, reps, log)
     ctx.close()
+    if not args.no_cpu:
+        out["cpu_baseline"], errs = oracle_leg(wl, sols)
+        out["error_vs_oracle"] = errs
+        if learned_sols is not None:
+            errs5 = oracle_reference_errors(W.WORKLOADS["box24_N7_lognormal_helmholtz"],
+                                            learned_sols["rhs_seed"], learned_sols["x"])
+            out["learned"]["error_vs_oracle"] = errs5
+    print(json.dumps(out), flush=True)
 
 
 def energy_counter():
@@ -321,26 +338,32 @@ def energy_counter():
         return None, f"{type(e).__name__}: {e}"
 
 
-def copy_ceiling(nbytes):
-    """Read + write bandwidth of a plain device-to-device copy of nbytes
-    (torch's copy kernel), the same 2 x nbytes of traffic as one operator
-    launch when nbytes = 20 B per local dof: a measured ceiling to set beside
-    the operator kernel's achieved bandwidth."""
+def copy_ceiling(ctx, nbytes):
+    """Read + write bandwidth of the library's streaming copy (one pass,
+    non-temporal loads and stores) of nbytes: with nbytes = 20 B per local
+    dof it moves the same 40 B per dof as one operator launch, so it is the
+    measured ceiling set beside the operator kernel's bandwidth.  Median of
+    20 launches, each timed by its own events on the context's stream."""
     import torch
+
+    from paper_2503_02134_amd import mxsem as mx
+    nbytes = (nbytes // 16) * 16
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(3):
-        dst.copy_(src)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 20
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    sec = e0.elapsed_time(e1) * 1e-3 / reps
+        mx.mxsem_stream_copy(ctx.h, src, dst)
+    assert torch.equal(src, dst)
+    stream = torch.cuda.current_stream()
+    times = []
+    for _ in range(20):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        mx.mxsem_stream_copy(ctx.h, src, dst)
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
     del src, dst
+    sec = sorted(times)[len(times) // 2]
     return round(2 * nbytes / sec / 1e9, 1)
 
 
@@ -660,36 +683,166 @@ def bench_strategies(args):
     ctx.close()
 
 
-def cpu_baseline(wl, iters):
-    """FP64 oracle Jacobi-PCG on the same workload, a bounded number of
-    iterations (tol 0), GDOF*iter/s of the iteration loop only."""
+def learned_leg(ctx, reps, log):
+    """The learned preconditioner on box24_N7_lognormal_helmholtz (24^3
+    elements, N = 7, log-normal k, h = 1): 128 training pairs from the FP64
+    solver on 16 right-hand sides, 300 Adam steps, the correction's scale
+    calibrated on a training right-hand side; then, on the held-out
+    right-hand side of seed 5900, learned flexible CG and Jacobi PCG (both
+    inside FP64 refinement) and FP64 Jacobi PCG, each to relative residuals
+    1e-10 and 1e-8, the median of reps solves after a warm-up.  Returns the
+    record and the solutions (for the oracle's errors)."""
     import numpy as np
+    import torch
 
+    from paper_2503_02134_amd import mxsem as mx
+    from paper_2503_02134_amd import workloads as W
+    from paper_2503_02134_amd.learned import (Network, calibrate_scale, make_pairs, rhs_batch,
+                                              train)
+    wl = W.WORKLOADS["box24_N7_lognormal_helmholtz"]
+    xi, _ = mx.mxsem_gll(wl.N)
+    bm = W.box_mesh(wl.ne, wl.N, xi)
+    kf = W.lognormal_k(bm, wl.k_seed)
+    mesh = mx.Mesh(ctx, bm.E, wl.N, bm.xyz, bm.glo, bm.bnd, kcoef=kf, helm_h=wl.helm_h)
+    nloc = mesh.nloc
+    log(f"learned leg: {wl.name} nloc={nloc}")
+    t0 = time.perf_counter()
+    train_rhs = rhs_batch(bm, mesh, range(5100, 5116))
+    R, E = make_pairs(mesh, train_rhs, samples=8, mesh_np=bm, seed=11)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    net = Network(mesh, seed=3)
+    t0 = time.perf_counter()
+    losses = train(net, R, E, steps=300, batch=4, lr=2e-3, seed=1, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del R, E
+    lam, cal = calibrate_scale(net, mesh, train_rhs[0], log=log)
+    net.attach()
+    seed = 5900
+    b = rhs_batch(bm, mesh, [seed])[0]
+    methods = (("learned", dict(mode=mx.MODE_MIXED_IR, pc=mx.PC_LEARNED, method=mx.METHOD_FCG)),
+               ("jacobi_mixed_ir", dict(mode=mx.MODE_MIXED_IR)),
+               ("fp64_jacobi", dict(mode=mx.MODE_FP64)))
+    rec = {}
+    xs = {}
+    for tol in (wl.tol, 1e-8):
+        for name, kw in methods:
+            x = torch.zeros_like(b)
+            mesh.solve(b, x, tol=tol, max_iter=50000, **kw)  # warm-up
+            runs = []
+            for _ in range(reps):
+                x.zero_()
+                _, st = mesh.solve(b, x, tol=tol, max_iter=50000, **kw)
+                runs.append(st)
+            st = sorted(runs, key=lambda r: r.ms)[len(runs) // 2]
+            it = st.iterations + st.outer
+            key = f"residual_{tol:.0e}"
+            rec.setdefault(key, {})[name] = {
+                "ms": round(st.ms, 3), "iterations": it, "rel_res": st.rel_res,
+                "gdof_iter_s": round(nloc * it / (st.ms * 1e-3) / 1e9, 3),
+                "fallback_steps": st.fallback_used, "median_of": reps}
+            xs[f"{key}/{name}"] = x.cpu().numpy()
+            log(f"  {key} {name}: {it} it, {st.ms:.1f} ms, res {st.rel_res:.2e}")
+    for key in list(rec):
+        r = rec[key]
+        r["learned_vs_jacobi_time"] = round(r["jacobi_mixed_ir"]["ms"] / r["learned"]["ms"], 3)
+        r["learned_vs_fp64_time"] = round(r["fp64_jacobi"]["ms"] / r["learned"]["ms"], 3)
+    out = {"workload": wl.name, "E": bm.E, "N": wl.N, "nloc": nloc, "held_out_rhs_seed": seed,
+           **rec,
+           "training": {"pairs": 128, "rhs_seeds": "5100-5115", "adam_steps": 300,
+                        "loss_first": losses[0], "loss_last20": float(np.mean(losses[-20:])),
+                        "scale": lam,
+                        "calibration_iterations": {str(k): v for k, v in cal.items()},
+                        "pairs_s": round(t_data, 2), "train_s": round(t_train, 2)}}
+    net.close()
+    mesh.close()
+    return out, {"rhs_seed": seed, "x": xs}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            return next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        return ""
+
+
+def _oracle_problem(wl, rhs_seed=None):
     import oracle
     from paper_2503_02134_amd import workloads as W
     xo, _ = oracle.gll(wl.N)
     bm = W.box_mesh(wl.ne, wl.N, xo, seed=wl.deform_seed)
     kf = W.lognormal_k(bm, wl.k_seed) if wl.k_seed is not None else None
-    f = W.manufactured(bm)[0] if wl.rhs == "manufactured" else W.random_smooth_rhs(bm, wl.rhs_seed)
+    if rhs_seed is None:
+        f = W.manufactured(bm)[0] if wl.rhs == "manufactured" else W.random_smooth_rhs(bm, wl.rhs_seed)
+    else:
+        f = W.random_smooth_rhs(bm, rhs_seed)
     om = oracle.Mesh(bm.E, wl.N, bm.xyz, bm.glo, bm.bnd, kcoef=kf, helm_h=wl.helm_h)
-    b = om.rhs(f)
+    return om, om.rhs(f)
+
+
+def _c_err(om, x, xs):
+    import numpy as np
+    c = om.c
+    return float(np.sqrt(np.sum(c * (x - xs) ** 2) / np.sum(c * xs * xs)))
+
+
+def oracle_leg(wl, sols):
+    """The oracle on the host cores: its FP64 Jacobi-PCG solve of the
+    workload from x = 0 to relative residual 1e-10 is timed (the CPU
+    baseline), then continued from that solution to 1e-13, which gives the
+    reference solution x*; every GPU solution in sols gets its relative
+    c-norm error against x*."""
+    import oracle
     t0 = time.perf_counter()
-    _, st = om.pcg(b, tol=0.0, maxit=iters)
+    om, b = _oracle_problem(wl)
+    log(f"oracle: {wl.name} set up in {time.perf_counter() - t0:.1f}s; solving to 1e-10")
+    t0 = time.perf_counter()
+    x10, st10 = om.pcg(b, tol=1e-10, maxit=20000)
     el = time.perf_counter() - t0
-    # the call also does one true-residual apply at exit: count it as an iteration
-    value = om.nloc * (st.iterations + 1) / el / 1e9
-    log(f"cpu oracle: {st.iterations} iterations in {el:.1f}s")
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as fh:
-            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")),
-                         "")
-    except OSError:
-        pass
-    return {"value": round(value, 5), "unit": "GDOF*iter/s", "cores": oracle.max_threads(),
-            "cpu_model": model, "kind": "oracle",
-            "sample": f"{st.iterations} FP64 Jacobi-PCG iterations of {wl.name} "
-                      f"(plain C oracle, OpenMP over elements), {el:.1f} s"}
+    log(f"oracle: {st10.iterations} iterations to 1e-10 in {el:.1f}s; continuing to 1e-13")
+    t1 = time.perf_counter()
+    xs, st13 = om.pcg(b, tol=1e-13, maxit=20000, x0=x10)
+    el13 = time.perf_counter() - t1
+    log(f"oracle: x* after {st13.iterations} more iterations ({el13:.1f}s), "
+        f"true residual {st13.rel_res_true:.2e}")
+    # the solve ends with one true-residual operator application: counted
+    # as an iteration's worth of work
+    value = om.nloc * (st10.iterations + 1) / el / 1e9
+    base = {"value": round(value, 5), "unit": "GDOF*iter/s", "cores": oracle.max_threads(),
+            "cpu_model": _cpu_model(), "kind": "oracle",
+            "sample": (f"the whole FP64 Jacobi-PCG solve of {wl.name} from x = 0 to relative "
+                       f"residual 1e-10 (plain C oracle, OpenMP over elements): "
+                       f"{st10.iterations} iterations, {el:.1f} s"),
+            "iterations": st10.iterations, "time_to_solution_s": round(el, 2),
+            "rel_res_true": st10.rel_res_true}
+    errs = {"reference": (f"oracle FP64 Jacobi-PCG to relative residual 1e-13 "
+                          f"({st10.iterations} + {st13.iterations} iterations, true residual "
+                          f"{st13.rel_res_true:.1e})"),
+            "norm": "relative c-weighted L2 (c = 1/multiplicity)",
+            "cpu_solution_1e-10": _c_err(om, x10, xs)}
+    for name, x in sols.items():
+        errs[name] = _c_err(om, x, xs)
+    log(f"errors vs oracle: {errs}")
+    return base, errs
+
+
+def oracle_reference_errors(wl, rhs_seed, xs_gpu):
+    """x* of one right-hand side from the oracle's FP64 Jacobi-PCG to 1e-13,
+    and the relative c-norm errors of the given GPU solutions against it."""
+    t0 = time.perf_counter()
+    om, b = _oracle_problem(wl, rhs_seed)
+    xs, st = om.pcg(b, tol=1e-13, maxit=50000)
+    log(f"oracle: {wl.name} rhs {rhs_seed}: x* in {st.iterations} iterations "
+        f"({time.perf_counter() - t0:.1f}s)")
+    errs = {"reference": (f"oracle FP64 Jacobi-PCG of right-hand side {rhs_seed} to relative "
+                          f"residual 1e-13 ({st.iterations} iterations)"),
+            "norm": "relative c-weighted L2 (c = 1/multiplicity)"}
+    for name, x in xs_gpu.items():
+        errs[name] = _c_err(om, x, xs)
+    log(f"errors vs oracle: {errs}")
+    return errs
 
 
 if __name__ == "__main__":

@@ -379,6 +379,13 @@ int mxsem_mesh_attach_nn(mxsem_mesh *mesh, mxsem_nn *nn);
 int mxsem_nn_make_pair(mxsem_mesh *mesh, const double *b, const double *x, const double *xstar,
                        float *r_out, float *e_out);
 
+/* ---- bandwidth reference ---------------------------------------------------- */
+/* dst = src for `bytes` bytes of device memory (a multiple of 16, both
+ * pointers 16-byte aligned, no overlap): a one-pass streaming copy with
+ * non-temporal loads and stores, the measured HBM ceiling that the operator
+ * kernel's bandwidth is set beside.  Async on the context stream. */
+int mxsem_stream_copy(mxsem_ctx *ctx, const void *src, void *dst, size_t bytes);
+
 /* ---- diagnostics ------------------------------------------------------------ */
 const char *mxsem_status_str(int status);
 const char *mxsem_last_error(void);

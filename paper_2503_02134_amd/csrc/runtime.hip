@@ -711,6 +711,20 @@ int mxsem_dot_ex(mxsem_mesh* m, mxsem_prec io, int acc, const void* a, const voi
   MX_API_END("mxsem_dot_ex")
 }
 
+int mxsem_stream_copy(mxsem_ctx* ctx, const void* src, void* dst, size_t bytes) {
+  MX_API_BEGIN
+  MX_CHECK(ctx && src && dst, MXSEM_EINVAL, "stream_copy: null argument");
+  MX_CHECK(bytes % 16 == 0 && ((uintptr_t)src & 15) == 0 && ((uintptr_t)dst & 15) == 0,
+           MXSEM_EINVAL, "stream_copy: pointers and size must be multiples of 16 bytes");
+  MX_CHECK((const char*)src + bytes <= (const char*)dst || (const char*)dst + bytes <= (const char*)src,
+           MXSEM_EINVAL, "stream_copy: buffers overlap");
+  MX_HIP(hipSetDevice(ctx->device));
+  (void)hipGetLastError();
+  if (bytes) MX_HIP(launch_stream_copy(src, dst, (int64_t)(bytes / 16), ctx->stream));
+  return MXSEM_OK;
+  MX_API_END("mxsem_stream_copy")
+}
+
 int mxsem_mesh_set_ranks(mxsem_mesh* m, const int32_t* rank_host) {
   MX_API_BEGIN
   MX_CHECK(m, MXSEM_EINVAL, "set_ranks: null mesh");

@@ -974,6 +974,30 @@ hipError_t launch_axpy_cast(int vprec, double* x64, const void* xT, double sc, d
   return hipGetLastError();
 }
 
+// Streaming copy, the bandwidth reference of the roofline: a workgroup of
+// 256 threads moves 16 KB, four 16-byte vectors per thread, each load and
+// store instruction of a wave covering 1 KB of consecutive bytes; all four
+// loads are issued before the stores, non-temporal in both directions like
+// the operator kernel's streams.
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) stream_copy_kernel(const u32x4_t* __restrict__ src,
+                                                          u32x4_t* __restrict__ dst, int64_t n16) {
+  const int64_t i0 = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  u32x4_t v[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (i0 + q * 256 < n16) v[q] = __builtin_nontemporal_load(&src[i0 + q * 256]);
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (i0 + q * 256 < n16) __builtin_nontemporal_store(v[q], &dst[i0 + q * 256]);
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t n16, hipStream_t s) {
+  hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)((n16 + 1023) / 1024)), dim3(256), 0, s,
+                     (const u32x4_t*)src, (u32x4_t*)dst, n16);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(double* x, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(zero_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, x, n);
   return hipGetLastError();

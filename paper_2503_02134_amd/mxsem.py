@@ -120,6 +120,7 @@ _SIGS = {
     "mxsem_nn_adam_step": [vp, C.POINTER(mxsem_adam)],
     "mxsem_mesh_attach_nn": [vp, vp],
     "mxsem_nn_make_pair": [vp, vp, vp, vp, vp, vp],
+    "mxsem_stream_copy": [vp, vp, vp, C.c_size_t],
     "mxsem_version": [],
 }
 
@@ -526,6 +527,15 @@ def mxsem_nn_make_pair(mesh, b, x, xstar, r_out, e_out):
     pr = _local(mesh, F32, r_out, "nn_make_pair: r_out")
     pe = _local(mesh, F32, e_out, "nn_make_pair: e_out")
     _check("mxsem_nn_make_pair", lib().mxsem_nn_make_pair(mesh, *ps, pr, pe))
+
+
+def mxsem_stream_copy(ctx, src, dst):
+    """dst = src (device tensors of equal byte size, a multiple of 16)."""
+    dev = _ctx_device.get(_key(ctx), 0)
+    n = src.numel() * src.element_size()
+    ps = _vec(src, src.dtype, src.numel(), dev, "stream_copy: src")
+    pd = _vec(dst, src.dtype, src.numel(), dev, "stream_copy: dst")
+    _check("mxsem_stream_copy", lib().mxsem_stream_copy(ctx, ps, pd, n))
 
 
 # ---------------------------------------------------------------- convenience

@@ -23,3 +23,24 @@ def test_energy_counter_unavailable_without_gpu():
         return  # the GPU tests exercise the counter through the benchmark itself
     read, why = bench.energy_counter()
     assert read is None and isinstance(why, str) and why
+
+
+def test_oracle_leg_on_a_small_workload():
+    """The oracle leg of the default run on the 4^3, N = 7 workload: the
+    timed solve to 1e-10, its continuation to the 1e-13 reference x*, and
+    the error of a given solution against x* (its own 1e-10 solution is
+    close to x*, a perturbed copy is not)."""
+    sys.path.insert(0, ROOT)
+    import numpy as np
+
+    import bench
+    from paper_2503_02134_amd import workloads as W
+    wl = W.WORKLOADS["box4_N7"]
+    om, b = bench._oracle_problem(wl)
+    x10, _ = om.pcg(b, tol=1e-10, maxit=2000)
+    base, errs = bench.oracle_leg(wl, {"same": x10, "perturbed": x10 * (1 + 1e-6)})
+    assert base["kind"] == "oracle" and base["iterations"] > 0 and "1e-10" in base["sample"]
+    assert base["value"] > 0 and base["cores"] >= 1
+    assert errs["cpu_solution_1e-10"] < 1e-8 and errs["same"] == errs["cpu_solution_1e-10"]
+    assert abs(errs["perturbed"] - 1e-6) < 1e-7
+    assert "1e-13" in errs["reference"]

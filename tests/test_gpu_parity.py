@@ -503,3 +503,17 @@ def test_network_and_batch_workspaces_are_checked(mx, ctx):
                                 nb.value - 256, C.byref(h)) == mx.EINVAL
     assert b"workspace" in L.mxsem_last_error()
     gm.close()
+
+
+def test_stream_copy(mx, ctx):
+    """The bandwidth reference copies bit for bit, including a tail shorter
+    than one thread's 64 bytes, and refuses unaligned sizes."""
+    for n in (4, 20, 1 << 20, (1 << 20) + 12):
+        src = torch.randn(n, dtype=torch.float32, device="cuda")
+        dst = torch.zeros_like(src)
+        mx.mxsem_stream_copy(ctx.h, src, dst)
+        torch.cuda.synchronize()
+        assert torch.equal(src, dst), n
+    src = torch.zeros(3, dtype=torch.float32, device="cuda")
+    with pytest.raises(mx.MxsemError):
+        mx.mxsem_stream_copy(ctx.h, src, torch.zeros_like(src))
