@@ -21,7 +21,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 CONVERGED, MAXITER, STAGNATED, BREAKDOWN = 1, 2, 3, 4
-PC_IDENTITY, PC_JACOBI, PC_NN = 0, 1, 2
+PC_IDENTITY, PC_JACOBI, PC_NN, PC_MG = 0, 1, 2, 3
 
 _lib = None
 
@@ -86,6 +86,17 @@ def _load():
     lib.orc_nn_loss_grad.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp, vp]
     lib.orc_adam.argtypes = [C.c_int, vp, vp, vp, vp, C.c_int, C.c_double, C.c_double,
                              C.c_double, C.c_double]
+    lib.orc_mg_create.argtypes = [vp, C.c_int, vp, vp, C.c_int, C.POINTER(vp)]
+    lib.orc_mg_destroy.argtypes = [vp]
+    for f in ("orc_mg_apply", "orc_mg_schwarz_local", "orc_mg_restrict", "orc_mg_prolong_add"):
+        getattr(lib, f).argtypes = [vp, vp, vp, vp]
+    lib.orc_mg_nlev.argtypes = [vp]
+    lib.orc_mg_level_nu.argtypes = [vp, C.c_int]
+    lib.orc_mg_level_omega.argtypes = [vp, C.c_int]
+    lib.orc_mg_level_omega.restype = C.c_double
+    lib.orc_mg_level_dense.argtypes = [vp, C.c_int, vp]
+    lib.orc_mg_vcycle.argtypes = [vp, vp, vp]
+    lib.orc_mg_eig.argtypes = [vp, C.c_int, C.c_int, vp, vp]
     _lib = lib
     return lib
 
@@ -286,12 +297,17 @@ class Mesh:
         return v
 
     # --- solvers -----------------------------------------------------------
-    def pcg(self, b, pc=PC_JACOBI, tol=1e-10, maxit=1000, x0=None, history=False, nn=None):
+    def pcg(self, b, pc=PC_JACOBI, tol=1e-10, maxit=1000, x0=None, history=False, nn=None,
+            mg=None):
         b = _f64(b).reshape(-1)
         x = np.zeros(self.nloc) if x0 is None else _f64(x0).reshape(-1).copy()
         hist = np.zeros(maxit + 1) if history else None
         st = _Stats()
-        rc = _lib.orc_pcg(self._h, pc, None if nn is None else nn._h, _p(b), _p(x),
+        if mg is not None:
+            pc, obj = PC_MG, mg._h
+        else:
+            obj = None if nn is None else nn._h
+        rc = _lib.orc_pcg(self._h, pc, obj, _p(b), _p(x),
                           0 if x0 is None else 1, tol, maxit,
                           None if hist is None else _p(hist), C.byref(st))
         if rc != 0:
@@ -328,6 +344,83 @@ class Mesh:
             raise RuntimeError(rc)
         s = _stats(st)
         return x, s, outer[: s.outer + 1]
+
+
+class MG:
+    """Oracle copy of the two-level Schwarz / multigrid preconditioner of a
+    Dirichlet box mesh of ne^3 elements (lexicographic)."""
+
+    def __init__(self, mesh: Mesh, ne: int, xyz, kcoef=None, coarsest_max: int = 512):
+        _load()
+        self.mesh = mesh
+        self._xyz = _f64(xyz).reshape(-1)
+        self._k = None if kcoef is None else _f64(kcoef).reshape(-1)
+        h = C.c_void_p()
+        rc = _lib.orc_mg_create(mesh._h, ne, _p(self._xyz),
+                                None if self._k is None else _p(self._k), coarsest_max,
+                                C.byref(h))
+        if rc != 0:
+            raise ValueError(f"orc_mg_create failed: {rc}")
+        self._h = h
+        self.ne = ne
+        self.nlev = _lib.orc_mg_nlev(h)
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                _lib.orc_mg_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    def _local_op(self, fn, r):
+        r = _f64(r).reshape(-1)
+        z = np.zeros(self.mesh.nloc)
+        getattr(_lib, fn)(self.mesh._h, self._h, _p(r), _p(z))
+        return z
+
+    def apply(self, r):
+        return self._local_op("orc_mg_apply", r)
+
+    def schwarz_local(self, r):
+        return self._local_op("orc_mg_schwarz_local", r)
+
+    def level_nu(self, l: int) -> int:
+        return _lib.orc_mg_level_nu(self._h, l)
+
+    def level_omega(self, l: int) -> float:
+        return _lib.orc_mg_level_omega(self._h, l)
+
+    def level_dense(self, l: int) -> np.ndarray:
+        nn = self.level_nu(l) ** 3
+        A = np.zeros((nn, nn))
+        _lib.orc_mg_level_dense(self._h, l, _p(A))
+        return A
+
+    def restrict(self, r):
+        r = _f64(r).reshape(-1)
+        rc = np.zeros(self.level_nu(0) ** 3)
+        _lib.orc_mg_restrict(self.mesh._h, self._h, _p(r), _p(rc))
+        return rc
+
+    def prolong_add(self, zc, z):
+        zc = _f64(zc).reshape(-1)
+        z = _f64(z).reshape(-1).copy()
+        _lib.orc_mg_prolong_add(self.mesh._h, self._h, _p(zc), _p(z))
+        return z
+
+    def vcycle(self, b):
+        b = _f64(b).reshape(-1)
+        x = np.zeros_like(b)
+        _lib.orc_mg_vcycle(self._h, _p(b), _p(x))
+        return x
+
+    def eig(self, e: int, d: int):
+        n = self.mesh.n
+        S = np.zeros((n, n))
+        lam = np.zeros(n)
+        _lib.orc_mg_eig(self._h, e, d, _p(S), _p(lam))
+        return S, lam
 
 
 def _stats(st: _Stats) -> SolveStats:

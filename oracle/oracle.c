@@ -50,6 +50,7 @@
 #define ORC_PC_IDENTITY 0
 #define ORC_PC_JACOBI 1
 #define ORC_PC_NN 2
+#define ORC_PC_MG 3
 
 /* ------------------------------------------------------------------------ */
 /* O1: Legendre polynomial L_N and the Gauss-Lobatto-Legendre rule.          */
@@ -637,15 +638,21 @@ void orc_mesh_get(const orc_mesh *m, int what, double *out) {
 /* Preconditioners (O9 Jacobi, identity) and an optional learned one.        */
 /* ------------------------------------------------------------------------ */
 typedef struct orc_nn orc_nn;
+typedef struct orc_mg orc_mg;
 int orc_nn_apply(const orc_mesh *m, const orc_nn *nn, const double *r, double *z);
+void orc_mg_apply(const orc_mesh *m, const orc_mg *mg, const double *r, double *z);
 
-static void precond(const orc_mesh *m, int pc, const orc_nn *nn, const double *r,
+/* z = M^-1 r; pcobj is the network (ORC_PC_NN) or the multigrid
+ * preconditioner (ORC_PC_MG) */
+static void precond(const orc_mesh *m, int pc, const void *pcobj, const double *r,
                     double *z) {
   if (pc == ORC_PC_JACOBI) {
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < m->nloc; ++i) z[i] = m->dinv[i] * r[i];
-  } else if (pc == ORC_PC_NN && nn) {
-    orc_nn_apply(m, nn, r, z);
+  } else if (pc == ORC_PC_NN && pcobj) {
+    orc_nn_apply(m, (const orc_nn *)pcobj, r, z);
+  } else if (pc == ORC_PC_MG && pcobj) {
+    orc_mg_apply(m, (const orc_mg *)pcobj, r, z);
   } else {
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < m->nloc; ++i) z[i] = m->mask[i] ? 0.0 : r[i];
@@ -691,7 +698,7 @@ static double true_rel_res(const orc_mesh *m, const double *b, const double *x,
  *         z = M^-1 r; rho' = (r,z)_c; beta = rho'/rho; p = z + beta p.
  * history (nullable, maxit+1 entries) receives ||r||_c/||b||_c per
  * iteration (entry 0 = initial). */
-int orc_pcg(const orc_mesh *m, int pc, const orc_nn *nn, const double *b,
+int orc_pcg(const orc_mesh *m, int pc, const void *nn, const double *b,
             double *x, int x0_given, double tol, int maxit, double *history,
             orc_stats *st) {
   int64_t nl = m->nloc;
@@ -771,7 +778,7 @@ int orc_pcg(const orc_mesh *m, int pc, const orc_nn *nn, const double *b,
  * positive or not finite, or whose (z, A p)_c is not finite, is replaced by
  * the Jacobi z for that step, the first z included; st->fallback counts the
  * replaced steps. */
-int orc_fcg(const orc_mesh *m, int pc, const orc_nn *nn, const double *b,
+int orc_fcg(const orc_mesh *m, int pc, const void *nn, const double *b,
             double *x, double tol, int maxit, double *history, orc_stats *st) {
   int64_t nl = m->nloc;
   double *r = (double *)malloc(sizeof(double) * nl);
@@ -1159,4 +1166,622 @@ void orc_adam(int np, double *theta, const double *g, double *mo, double *ve, in
     double mh = mo[i] / c1, vh = ve[i] / c2;
     theta[i] -= lr * mh / (sqrt(vh) + eps);
   }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Two-level Schwarz / multigrid preconditioner for box meshes.              */
+/*                                                                           */
+/* The paper's multigrid preconditioner (solveM in the CG-loop profiling     */
+/* table, 70% of the time with it; Sec. 4.2, inspection of the              */
+/* preconditioned CG: the Schwarz weights are square roots, and single-      */
+/* precision square roots made the mixed solve stagnate) is Nekbone's; the   */
+/* paper gives none of its algorithm.  The reading taken is the textbook     */
+/* two-level additive Schwarz method (Dryja and Widlund) with the spectral-  */
+/* element local solves of hybrid Schwarz/multigrid (Lottes and Fischer):    */
+/*                                                                           */
+/*   z = M QQ^T( ws * FDM_e( ws * r_L ) )  +  P V( P^T r )                   */
+/*                                                                           */
+/*  - ws = sqrt(c), c = 1/m: the counting weights of the overlapping        */
+/*    subdomains, split symmetrically (square root taken in FP64);           */
+/*  - FDM_e: the exact inverse, by fast diagonalisation, of a separable      */
+/*    operator on element e extended by one GLL interval into each           */
+/*    neighbour with zero Dirichlet values at the extended ends.  Per        */
+/*    direction, the 1-D stiffness and mass of the element (mean length l,   */
+/*    mean coefficient k) gain at each shared face the face-node diagonal    */
+/*    entry of the neighbour's 1-D matrices; at a Dirichlet face the face    */
+/*    node is decoupled.  A = k (Bz Bx By Ax + ...) + h Bz By Bx is inverted  */
+/*    through the generalised eigenpairs A_d s = lambda B_d s, S^T B S = I;  */
+/*  - P: trilinear interpolation from the element-vertex lattice (order 1)  */
+/*    to the element's GLL nodes; the coarse operator is Galerkin, P^T A P,  */
+/*    assembled from the 8x8 element matrices as a 27-point lattice stencil; */
+/*  - V: one V-cycle of geometric multigrid on the lattice: two damped       */
+/*    Jacobi sweeps before and after the coarse correction (damping 1 over  */
+/*    the row-sum bound of D^-1 A), full-weighting restriction (transpose of */
+/*    trilinear interpolation), Galerkin coarse stencils, coarsening by two  */
+/*    while the intervals are even and the level has more unknowns than the  */
+/*    coarsest limit, and a dense Cholesky solve on the coarsest level.      */
+/* The box structure (E = ne^3 elements in lexicographic order, global ids  */
+/* on the lattice of GLL nodes, Dirichlet on the whole boundary) gives the  */
+/* neighbours and the lattice.                                               */
+/* ------------------------------------------------------------------------ */
+#define ORC_MG_MAXLEV 12
+
+typedef struct {
+  int nI;       /* lattice intervals per direction */
+  int nu;       /* unknowns per direction (interior lattice nodes) */
+  double *st;   /* [nu^3][27] stencil, offset s = (dx+1) + 3(dy+1) + 9(dz+1) */
+  double omega; /* Jacobi damping */
+} orc_lvl;
+
+struct orc_mg {
+  int ne, n, E;
+  double *S;    /* [E][3][n][n]: S[e][d][node][mode] */
+  double *lam;  /* [E][3][n] */
+  double *kbar; /* [E] */
+  double ws[256];
+  int nlev;
+  orc_lvl lv[ORC_MG_MAXLEV];
+  int nc;       /* unknowns of the coarsest level */
+  double *L;    /* its dense Cholesky factor, lower triangle [nc][nc] */
+};
+
+static int lat_idx(int nu, int I, int J, int K) { return (I - 1) + nu * ((J - 1) + nu * (K - 1)); }
+
+/* eigenvalues and eigenvectors of a symmetric matrix by cyclic Jacobi
+ * rotations: A (n x n, destroyed) = Q diag(w) Q^T, Q[i][j] column j */
+static void jacobi_eigen(int n, double *A, double *w, double *Q) {
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) Q[i * n + j] = i == j ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        tot += A[i * n + j] * A[i * n + j];
+        if (i != j) off += A[i * n + j] * A[i * n + j];
+      }
+    if (off <= 1e-30 * tot) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double apq = A[p * n + q];
+        if (apq == 0.0) continue;
+        double theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+        double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) { /* A <- A J (columns p, q) */
+          double akp = A[k * n + p], akq = A[k * n + q];
+          A[k * n + p] = c * akp - s * akq;
+          A[k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) { /* A <- J^T A (rows p, q) */
+          double apk = A[p * n + k], aqk = A[q * n + k];
+          A[p * n + k] = c * apk - s * aqk;
+          A[q * n + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) { /* Q <- Q J */
+          double qkp = Q[k * n + p], qkq = Q[k * n + q];
+          Q[k * n + p] = c * qkp - s * qkq;
+          Q[k * n + q] = s * qkp + c * qkq;
+        }
+      }
+  }
+  for (int i = 0; i < n; ++i) w[i] = A[i * n + i];
+}
+
+/* mean length of element e along direction d: distance between the two end
+ * nodes of each of its n^2 lines along d, averaged */
+static double elem_length(const orc_mesh *m, const double *xyz, int e, int d) {
+  int n = m->n, N = m->N;
+  const double *X = xyz + (int64_t)e * 3 * m->n3;
+  double sum = 0.0;
+  for (int b = 0; b < n; ++b)
+    for (int a = 0; a < n; ++a) {
+      int p0, p1;
+      if (d == 0) { p0 = 0 + n * (a + n * b); p1 = N + n * (a + n * b); }
+      else if (d == 1) { p0 = a + n * (0 + n * b); p1 = a + n * (N + n * b); }
+      else { p0 = a + n * (b + n * 0); p1 = a + n * (b + n * N); }
+      double dx = X[p1] - X[p0], dy = X[m->n3 + p1] - X[m->n3 + p0];
+      double dz = X[2 * m->n3 + p1] - X[2 * m->n3 + p0];
+      sum += sqrt(dx * dx + dy * dy + dz * dz);
+    }
+  return sum / (n * n);
+}
+
+/* the 1-D extended operator of one element and direction, and its
+ * generalised eigenpairs (S = B^-1/2 Q, so S^T B S = I, S^T A S = diag) */
+static void fdm_1d(int n, const double *Ar, const double *rho, double l, double llo, double lhi,
+                   int dlo, int dhi, double *S, double *lam) {
+  int N = n - 1;
+  double A[32 * 32], B[32], C[32 * 32], Q[32 * 32];
+  for (int i = 0; i < n; ++i) {
+    B[i] = 0.5 * l * rho[i];
+    for (int j = 0; j < n; ++j) A[i * n + j] = (2.0 / l) * Ar[i * n + j];
+  }
+  if (llo > 0.0) {
+    A[0] += (2.0 / llo) * Ar[N * n + N];
+    B[0] += 0.5 * llo * rho[N];
+  }
+  if (lhi > 0.0) {
+    A[N * n + N] += (2.0 / lhi) * Ar[0];
+    B[N] += 0.5 * lhi * rho[0];
+  }
+  int ends[2] = {dlo ? 0 : -1, dhi ? N : -1};
+  for (int t = 0; t < 2; ++t) {
+    int q = ends[t];
+    if (q < 0) continue;
+    for (int j = 0; j < n; ++j) A[q * n + j] = A[j * n + q] = 0.0;
+    A[q * n + q] = 1.0;
+    B[q] = 1.0;
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) C[i * n + j] = A[i * n + j] / sqrt(B[i] * B[j]);
+  jacobi_eigen(n, C, lam, Q);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) S[i * n + j] = Q[i * n + j] / sqrt(B[i]);
+}
+
+static void lvl_apply(const orc_lvl *L, const double *x, double *y) {
+  int nu = L->nu;
+#pragma omp parallel for schedule(static)
+  for (int K = 1; K <= nu; ++K)
+    for (int J = 1; J <= nu; ++J)
+      for (int I = 1; I <= nu; ++I) {
+        const double *a = L->st + 27 * (int64_t)lat_idx(nu, I, J, K);
+        double s = 0.0;
+        for (int t = 0; t < 27; ++t) {
+          int i2 = I + t % 3 - 1, j2 = J + (t / 3) % 3 - 1, k2 = K + t / 9 - 1;
+          if (i2 < 1 || j2 < 1 || k2 < 1 || i2 > nu || j2 > nu || k2 > nu) continue;
+          s += a[t] * x[lat_idx(nu, i2, j2, k2)];
+        }
+        y[lat_idx(nu, I, J, K)] = s;
+      }
+}
+
+/* trilinear interpolation weight of coarse node c at fine lattice node f
+ * (per direction: 1 at f = 2c, 1/2 at f = 2c +- 1) */
+static double pw1(int f, int c) {
+  int d = f - 2 * c;
+  return d == 0 ? 1.0 : (d == 1 || d == -1) ? 0.5 : 0.0;
+}
+
+/* Galerkin coarse stencil P^T A_f P of a lattice level (coarse nodes c,
+ * fine nodes f = 2c + delta, and every fine stencil neighbour's coarse
+ * parents) */
+static void lvl_rap(const orc_lvl *F, orc_lvl *Cl) {
+  int nuf = F->nu, nuc = Cl->nu;
+  memset(Cl->st, 0, sizeof(double) * 27 * (size_t)nuc * nuc * nuc);
+  for (int K = 1; K <= nuc; ++K)
+    for (int J = 1; J <= nuc; ++J)
+      for (int I = 1; I <= nuc; ++I) {
+        double *ac = Cl->st + 27 * (int64_t)lat_idx(nuc, I, J, K);
+        for (int dz = -1; dz <= 1; ++dz)
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+              int fi = 2 * I + dx, fj = 2 * J + dy, fk = 2 * K + dz;
+              double w = pw1(fi, I) * pw1(fj, J) * pw1(fk, K);
+              const double *af = F->st + 27 * (int64_t)lat_idx(nuf, fi, fj, fk);
+              for (int t = 0; t < 27; ++t) {
+                int gi = fi + t % 3 - 1, gj = fj + (t / 3) % 3 - 1, gk = fk + t / 9 - 1;
+                if (gi < 1 || gj < 1 || gk < 1 || gi > nuf || gj > nuf || gk > nuf) continue;
+                double wa = w * af[t];
+                for (int ck = gk / 2; ck <= (gk + 1) / 2; ++ck)
+                  for (int cj = gj / 2; cj <= (gj + 1) / 2; ++cj)
+                    for (int ci = gi / 2; ci <= (gi + 1) / 2; ++ci) {
+                      if (ci < 1 || cj < 1 || ck < 1 || ci > nuc || cj > nuc || ck > nuc) continue;
+                      double p2 = pw1(gi, ci) * pw1(gj, cj) * pw1(gk, ck);
+                      if (p2 == 0.0) continue;
+                      int s = (ci - I + 1) + 3 * (cj - J + 1) + 9 * (ck - K + 1);
+                      ac[s] += wa * p2;
+                    }
+              }
+            }
+      }
+}
+
+static double lvl_omega(const orc_lvl *L) {
+  int nu = L->nu;
+  double mx = 0.0;
+  for (int K = 1; K <= nu; ++K)
+    for (int J = 1; J <= nu; ++J)
+      for (int I = 1; I <= nu; ++I) {
+        const double *a = L->st + 27 * (int64_t)lat_idx(nu, I, J, K);
+        double s = 0.0;
+        for (int t = 0; t < 27; ++t) {
+          int i2 = I + t % 3 - 1, j2 = J + (t / 3) % 3 - 1, k2 = K + t / 9 - 1;
+          if (i2 < 1 || j2 < 1 || k2 < 1 || i2 > nu || j2 > nu || k2 > nu) continue;
+          s += fabs(a[t]);
+        }
+        if (s / a[13] > mx) mx = s / a[13];
+      }
+  return 1.0 / mx;
+}
+
+void orc_mg_destroy(orc_mg *mg) {
+  if (!mg) return;
+  free(mg->S);
+  free(mg->lam);
+  free(mg->kbar);
+  for (int l = 0; l < mg->nlev; ++l) free(mg->lv[l].st);
+  free(mg->L);
+  free(mg);
+}
+
+/* J[i][a]: the order-1 basis at GLL node i ((1 - xi)/2, (1 + xi)/2) */
+static void lin_basis(const orc_mesh *m, double *J) {
+  for (int i = 0; i < m->n; ++i) {
+    J[2 * i] = 0.5 * (1.0 - m->xi[i]);
+    J[2 * i + 1] = 0.5 * (1.0 + m->xi[i]);
+  }
+}
+
+/* Builds the preconditioner.  ne: elements per direction (E = ne^3); xyz and
+ * kcoef (nullable) as given to orc_mesh_create; coarsest_max: largest
+ * number of unknowns solved directly.  Returns ORC_EINVAL when the mesh is
+ * not a Dirichlet box of lexicographic elements, or when the coarsest level
+ * would exceed 4096 unknowns. */
+int orc_mg_create(const orc_mesh *m, int ne, const double *xyz, const double *kcoef,
+                  int coarsest_max, orc_mg **out) {
+  int n = m->n, N = m->N, n3 = m->n3, E = m->E;
+  if (ne < 2 || (int64_t)ne * ne * ne != E || !xyz || !out) return ORC_EINVAL;
+  /* every node of the domain boundary is Dirichlet: the box faces of the
+   * boundary elements */
+  for (int e = 0; e < E; ++e) {
+    int ex = e % ne, ey = (e / ne) % ne, ez = e / (ne * ne);
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          int onb = (ex == 0 && i == 0) || (ex == ne - 1 && i == N) || (ey == 0 && j == 0) ||
+                    (ey == ne - 1 && j == N) || (ez == 0 && k == 0) || (ez == ne - 1 && k == N);
+          if (onb != m->mask[(int64_t)e * n3 + i + n * (j + n * k)]) return ORC_EINVAL;
+        }
+  }
+  orc_mg *mg = (orc_mg *)calloc(1, sizeof(orc_mg));
+  if (!mg) return ORC_ENOMEM;
+  mg->ne = ne;
+  mg->n = n;
+  mg->E = E;
+  for (int q = 1; q < 256; ++q) mg->ws[q] = sqrt(1.0 / q);
+  mg->S = (double *)malloc(sizeof(double) * (size_t)E * 3 * n * n);
+  mg->lam = (double *)malloc(sizeof(double) * (size_t)E * 3 * n);
+  mg->kbar = (double *)malloc(sizeof(double) * E);
+  double *len = (double *)malloc(sizeof(double) * (size_t)E * 3);
+  double *Ar = (double *)malloc(sizeof(double) * n * n);
+  if (!mg->S || !mg->lam || !mg->kbar || !len || !Ar) {
+    free(len); free(Ar);
+    orc_mg_destroy(mg);
+    return ORC_ENOMEM;
+  }
+  /* reference 1-D stiffness D^T diag(rho) D */
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double s = 0.0;
+      for (int l = 0; l < n; ++l) s += m->D[l * n + i] * m->rho[l] * m->D[l * n + j];
+      Ar[i * n + j] = s;
+    }
+  for (int e = 0; e < E; ++e) {
+    for (int d = 0; d < 3; ++d) len[3 * e + d] = elem_length(m, xyz, e, d);
+    double kb = 0.0;
+    for (int p = 0; p < n3; ++p) kb += kcoef ? kcoef[(int64_t)e * n3 + p] : 1.0;
+    mg->kbar[e] = kb / n3;
+  }
+  for (int e = 0; e < E; ++e) {
+    int ec[3] = {e % ne, (e / ne) % ne, e / (ne * ne)};
+    int stride[3] = {1, ne, ne * ne};
+    for (int d = 0; d < 3; ++d) {
+      double llo = ec[d] > 0 ? len[3 * (e - stride[d]) + d] : 0.0;
+      double lhi = ec[d] < ne - 1 ? len[3 * (e + stride[d]) + d] : 0.0;
+      fdm_1d(n, Ar, m->rho, len[3 * e + d], llo, lhi, ec[d] == 0, ec[d] == ne - 1,
+             mg->S + ((size_t)e * 3 + d) * n * n, mg->lam + ((size_t)e * 3 + d) * n);
+    }
+  }
+  free(len);
+  free(Ar);
+  /* coarse level 0: element-vertex lattice, Galerkin element matrices */
+  int nI = ne, nlev = 0;
+  for (;;) {
+    orc_lvl *L = &mg->lv[nlev];
+    L->nI = nI;
+    L->nu = nI - 1;
+    L->st = (double *)calloc(27 * (size_t)L->nu * L->nu * L->nu, sizeof(double));
+    if (!L->st) { mg->nlev = nlev + 1; orc_mg_destroy(mg); return ORC_ENOMEM; }
+    ++nlev;
+    int nunk = L->nu * L->nu * L->nu;
+    if (nunk <= coarsest_max || nI % 2 || nI < 4 || nlev == ORC_MG_MAXLEV) break;
+    nI /= 2;
+  }
+  mg->nlev = nlev;
+  {
+    double J[64];
+    lin_basis(m, J);
+    double *u = (double *)malloc(sizeof(double) * m->nloc);
+    double *w = (double *)malloc(sizeof(double) * m->nloc);
+    double *K = (double *)malloc(sizeof(double) * (size_t)E * 64);
+    if (!u || !w || !K) { free(u); free(w); free(K); orc_mg_destroy(mg); return ORC_ENOMEM; }
+    for (int a = 0; a < 8; ++a) {
+      for (int e = 0; e < E; ++e)
+        for (int k = 0; k < n; ++k)
+          for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i)
+              u[(int64_t)e * n3 + i + n * (j + n * k)] =
+                  J[2 * i + (a & 1)] * J[2 * j + ((a >> 1) & 1)] * J[2 * k + (a >> 2)];
+      orc_ax_local(m, u, w);
+      for (int e = 0; e < E; ++e)
+        for (int b = 0; b < 8; ++b) {
+          double s = 0.0;
+          for (int k = 0; k < n; ++k)
+            for (int j = 0; j < n; ++j)
+              for (int i = 0; i < n; ++i)
+                s += J[2 * i + (b & 1)] * J[2 * j + ((b >> 1) & 1)] * J[2 * k + (b >> 2)] *
+                     w[(int64_t)e * n3 + i + n * (j + n * k)];
+          K[(size_t)e * 64 + b * 8 + a] = s;
+        }
+    }
+    orc_lvl *L0 = &mg->lv[0];
+    int nu = L0->nu;
+    for (int e = 0; e < E; ++e) {
+      int ex = e % ne, ey = (e / ne) % ne, ez = e / (ne * ne);
+      for (int b = 0; b < 8; ++b) {
+        int I = ex + (b & 1), Jn = ey + ((b >> 1) & 1), Kn = ez + (b >> 2);
+        if (I < 1 || Jn < 1 || Kn < 1 || I > nu || Jn > nu || Kn > nu) continue;
+        for (int a = 0; a < 8; ++a) {
+          int I2 = ex + (a & 1), J2 = ey + ((a >> 1) & 1), K2 = ez + (a >> 2);
+          if (I2 < 1 || J2 < 1 || K2 < 1 || I2 > nu || J2 > nu || K2 > nu) continue;
+          int s = (I2 - I + 1) + 3 * (J2 - Jn + 1) + 9 * (K2 - Kn + 1);
+          L0->st[27 * (int64_t)lat_idx(nu, I, Jn, Kn) + s] += K[(size_t)e * 64 + b * 8 + a];
+        }
+      }
+    }
+    free(u); free(w); free(K);
+  }
+  for (int l = 1; l < nlev; ++l) lvl_rap(&mg->lv[l - 1], &mg->lv[l]);
+  for (int l = 0; l < nlev; ++l) mg->lv[l].omega = lvl_omega(&mg->lv[l]);
+  /* coarsest: dense Cholesky */
+  orc_lvl *Lc = &mg->lv[nlev - 1];
+  int nc = Lc->nu * Lc->nu * Lc->nu;
+  if (nc > 4096) { orc_mg_destroy(mg); return ORC_EINVAL; }
+  mg->nc = nc;
+  mg->L = (double *)calloc((size_t)nc * nc, sizeof(double));
+  if (!mg->L) { orc_mg_destroy(mg); return ORC_ENOMEM; }
+  {
+    int nu = Lc->nu;
+    double *Ad = mg->L;
+    for (int K = 1; K <= nu; ++K)
+      for (int J = 1; J <= nu; ++J)
+        for (int I = 1; I <= nu; ++I) {
+          int r = lat_idx(nu, I, J, K);
+          for (int t = 0; t < 27; ++t) {
+            int i2 = I + t % 3 - 1, j2 = J + (t / 3) % 3 - 1, k2 = K + t / 9 - 1;
+            if (i2 < 1 || j2 < 1 || k2 < 1 || i2 > nu || j2 > nu || k2 > nu) continue;
+            Ad[(size_t)r * nc + lat_idx(nu, i2, j2, k2)] = Lc->st[27 * (int64_t)r + t];
+          }
+        }
+    for (int j = 0; j < nc; ++j) { /* in-place Cholesky, lower triangle */
+      double d = Ad[(size_t)j * nc + j];
+      for (int k = 0; k < j; ++k) d -= Ad[(size_t)j * nc + k] * Ad[(size_t)j * nc + k];
+      if (!(d > 0.0)) { orc_mg_destroy(mg); return ORC_EINVAL; }
+      d = sqrt(d);
+      Ad[(size_t)j * nc + j] = d;
+      for (int i = j + 1; i < nc; ++i) {
+        double s = Ad[(size_t)i * nc + j];
+        for (int k = 0; k < j; ++k) s -= Ad[(size_t)i * nc + k] * Ad[(size_t)j * nc + k];
+        Ad[(size_t)i * nc + j] = s / d;
+      }
+    }
+  }
+  *out = mg;
+  return ORC_OK;
+}
+
+/* one V-cycle on lattice level l for right-hand side b; x receives the result */
+static void vcycle(const orc_mg *mg, int l, const double *b, double *x) {
+  const orc_lvl *L = &mg->lv[l];
+  int nu = L->nu, nn = nu * nu * nu;
+  if (l == mg->nlev - 1) {
+    const double *Lf = mg->L;
+    int nc = mg->nc;
+    for (int i = 0; i < nc; ++i) { /* L y = b */
+      double s = b[i];
+      for (int k = 0; k < i; ++k) s -= Lf[(size_t)i * nc + k] * x[k];
+      x[i] = s / Lf[(size_t)i * nc + i];
+    }
+    for (int i = nc - 1; i >= 0; --i) { /* L^T x = y */
+      double s = x[i];
+      for (int k = i + 1; k < nc; ++k) s -= Lf[(size_t)k * nc + i] * x[k];
+      x[i] = s / Lf[(size_t)i * nc + i];
+    }
+    return;
+  }
+  double *r = (double *)malloc(sizeof(double) * nn);
+  const orc_lvl *C = &mg->lv[l + 1];
+  int nuc = C->nu, nnc = nuc * nuc * nuc;
+  double *bc = (double *)malloc(sizeof(double) * nnc);
+  double *xc = (double *)malloc(sizeof(double) * nnc);
+  memset(x, 0, sizeof(double) * nn);
+  for (int sweep = 0; sweep < 4; ++sweep) {
+    if (sweep == 2) {
+      /* coarse correction: r = b - A x, bc = P^T r, x += P V(bc) */
+      lvl_apply(L, x, r);
+      for (int i = 0; i < nn; ++i) r[i] = b[i] - r[i];
+      for (int K = 1; K <= nuc; ++K)
+        for (int J = 1; J <= nuc; ++J)
+          for (int I = 1; I <= nuc; ++I) {
+            double s = 0.0;
+            for (int dz = -1; dz <= 1; ++dz)
+              for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx)
+                  s += pw1(2 * I + dx, I) * pw1(2 * J + dy, J) * pw1(2 * K + dz, K) *
+                       r[lat_idx(nu, 2 * I + dx, 2 * J + dy, 2 * K + dz)];
+            bc[lat_idx(nuc, I, J, K)] = s;
+          }
+      vcycle(mg, l + 1, bc, xc);
+      for (int K = 1; K <= nu; ++K)
+        for (int J = 1; J <= nu; ++J)
+          for (int I = 1; I <= nu; ++I) {
+            double s = 0.0;
+            for (int ck = K / 2; ck <= (K + 1) / 2; ++ck)
+              for (int cj = J / 2; cj <= (J + 1) / 2; ++cj)
+                for (int ci = I / 2; ci <= (I + 1) / 2; ++ci) {
+                  if (ci < 1 || cj < 1 || ck < 1 || ci > nuc || cj > nuc || ck > nuc) continue;
+                  s += pw1(I, ci) * pw1(J, cj) * pw1(K, ck) * xc[lat_idx(nuc, ci, cj, ck)];
+                }
+            x[lat_idx(nu, I, J, K)] += s;
+          }
+    }
+    /* damped Jacobi: x += omega D^-1 (b - A x) */
+    lvl_apply(L, x, r);
+    for (int K = 1; K <= nu; ++K)
+      for (int J = 1; J <= nu; ++J)
+        for (int I = 1; I <= nu; ++I) {
+          int q = lat_idx(nu, I, J, K);
+          x[q] += L->omega * (b[q] - r[q]) / L->st[27 * (int64_t)q + 13];
+        }
+  }
+  free(r); free(bc); free(xc);
+}
+
+/* the Schwarz part before assembly: zL = ws * FDM_e(ws * r) per element */
+void orc_mg_schwarz_local(const orc_mesh *m, const orc_mg *mg, const double *r, double *zL) {
+  int n = m->n, n3 = m->n3;
+#pragma omp parallel for schedule(static)
+  for (int e = 0; e < m->E; ++e) {
+    double v[4096], u[4096];
+    const double *Sx = mg->S + ((size_t)e * 3 + 0) * n * n, *Sy = Sx + n * n, *Sz = Sy + n * n;
+    const double *lx = mg->lam + (size_t)e * 3 * n, *ly = lx + n, *lz = ly + n;
+    int64_t o = (int64_t)e * n3;
+    for (int p = 0; p < n3; ++p) v[p] = mg->ws[(int)m->mult[o + p]] * r[o + p];
+    /* u = (Sz x Sy x Sx)^T v, one direction at a time */
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          double s = 0.0;
+          for (int q = 0; q < n; ++q) s += Sx[q * n + i] * v[q + n * (j + n * k)];
+          u[i + n * (j + n * k)] = s;
+        }
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          double s = 0.0;
+          for (int q = 0; q < n; ++q) s += Sy[q * n + j] * u[i + n * (q + n * k)];
+          v[i + n * (j + n * k)] = s;
+        }
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          double s = 0.0;
+          for (int q = 0; q < n; ++q) s += Sz[q * n + k] * v[i + n * (j + n * q)];
+          u[i + n * (j + n * k)] = s / (mg->kbar[e] * (lx[i] + ly[j] + lz[k]) + m->helm_h);
+        }
+    /* back: v = (Sz x Sy x Sx) u */
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          double s = 0.0;
+          for (int q = 0; q < n; ++q) s += Sz[k * n + q] * u[i + n * (j + n * q)];
+          v[i + n * (j + n * k)] = s;
+        }
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          double s = 0.0;
+          for (int q = 0; q < n; ++q) s += Sy[j * n + q] * v[i + n * (q + n * k)];
+          u[i + n * (j + n * k)] = s;
+        }
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          double s = 0.0;
+          for (int q = 0; q < n; ++q) s += Sx[i * n + q] * u[q + n * (j + n * k)];
+          zL[o + i + n * (j + n * k)] = mg->ws[(int)m->mult[o + i + n * (j + n * k)]] * s;
+        }
+  }
+}
+
+/* restriction to the coarse lattice: rc = P^T r (r continuous, c-weighted
+ * over the local copies) */
+void orc_mg_restrict(const orc_mesh *m, const orc_mg *mg, const double *r, double *rc) {
+  int n = m->n, n3 = m->n3, ne = mg->ne, nu = mg->lv[0].nu;
+  double J[64];
+  lin_basis(m, J);
+  memset(rc, 0, sizeof(double) * nu * nu * nu);
+  for (int e = 0; e < m->E; ++e) {
+    int ex = e % ne, ey = (e / ne) % ne, ez = e / (ne * ne);
+    for (int b = 0; b < 8; ++b) {
+      int I = ex + (b & 1), Jn = ey + ((b >> 1) & 1), Kn = ez + (b >> 2);
+      if (I < 1 || Jn < 1 || Kn < 1 || I > nu || Jn > nu || Kn > nu) continue;
+      double s = 0.0;
+      for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+          for (int i = 0; i < n; ++i) {
+            int64_t q = (int64_t)e * n3 + i + n * (j + n * k);
+            s += J[2 * i + (b & 1)] * J[2 * j + ((b >> 1) & 1)] * J[2 * k + (b >> 2)] * m->c[q] * r[q];
+          }
+      rc[lat_idx(nu, I, Jn, Kn)] += s;
+    }
+  }
+}
+
+/* z += P zc (trilinear interpolation of the coarse lattice values) */
+void orc_mg_prolong_add(const orc_mesh *m, const orc_mg *mg, const double *zc, double *z) {
+  int n = m->n, n3 = m->n3, ne = mg->ne, nu = mg->lv[0].nu;
+  double J[64];
+  lin_basis(m, J);
+#pragma omp parallel for schedule(static)
+  for (int e = 0; e < m->E; ++e) {
+    int ex = e % ne, ey = (e / ne) % ne, ez = e / (ne * ne);
+    double cv[8];
+    for (int b = 0; b < 8; ++b) {
+      int I = ex + (b & 1), Jn = ey + ((b >> 1) & 1), Kn = ez + (b >> 2);
+      cv[b] = (I < 1 || Jn < 1 || Kn < 1 || I > nu || Jn > nu || Kn > nu)
+                  ? 0.0 : zc[lat_idx(nu, I, Jn, Kn)];
+    }
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          double s = 0.0;
+          for (int b = 0; b < 8; ++b)
+            s += J[2 * i + (b & 1)] * J[2 * j + ((b >> 1) & 1)] * J[2 * k + (b >> 2)] * cv[b];
+          z[(int64_t)e * n3 + i + n * (j + n * k)] += s;
+        }
+  }
+}
+
+/* z = M QQ^T(ws FDM(ws r)) + P V(P^T r) */
+void orc_mg_apply(const orc_mesh *m, const orc_mg *mg, const double *r, double *z) {
+  int nu = mg->lv[0].nu, nn = nu * nu * nu;
+  double *rc = (double *)malloc(sizeof(double) * nn);
+  double *zc = (double *)malloc(sizeof(double) * nn);
+  orc_mg_schwarz_local(m, mg, r, z);
+  orc_gs(m, z);
+  orc_mask(m, z);
+  orc_mg_restrict(m, mg, r, rc);
+  vcycle(mg, 0, rc, zc);
+  orc_mg_prolong_add(m, mg, zc, z);
+  free(rc);
+  free(zc);
+}
+
+/* accessors for the pins: levels, their stencils as dense matrices, the
+ * coarse correction alone, the per-element 1-D eigenpairs */
+int orc_mg_nlev(const orc_mg *mg) { return mg->nlev; }
+int orc_mg_level_nu(const orc_mg *mg, int l) { return mg->lv[l].nu; }
+double orc_mg_level_omega(const orc_mg *mg, int l) { return mg->lv[l].omega; }
+void orc_mg_level_dense(const orc_mg *mg, int l, double *A) {
+  const orc_lvl *L = &mg->lv[l];
+  int nu = L->nu, nn = nu * nu * nu;
+  memset(A, 0, sizeof(double) * (size_t)nn * nn);
+  for (int K = 1; K <= nu; ++K)
+    for (int J = 1; J <= nu; ++J)
+      for (int I = 1; I <= nu; ++I) {
+        int r = lat_idx(nu, I, J, K);
+        for (int t = 0; t < 27; ++t) {
+          int i2 = I + t % 3 - 1, j2 = J + (t / 3) % 3 - 1, k2 = K + t / 9 - 1;
+          if (i2 < 1 || j2 < 1 || k2 < 1 || i2 > nu || j2 > nu || k2 > nu) continue;
+          A[(size_t)r * nn + lat_idx(nu, i2, j2, k2)] = L->st[27 * (int64_t)r + t];
+        }
+      }
+}
+void orc_mg_vcycle(const orc_mg *mg, const double *b, double *x) { vcycle(mg, 0, b, x); }
+void orc_mg_eig(const orc_mg *mg, int e, int d, double *S, double *lam) {
+  int n = mg->n;
+  memcpy(S, mg->S + ((size_t)e * 3 + d) * n * n, sizeof(double) * n * n);
+  memcpy(lam, mg->lam + ((size_t)e * 3 + d) * n, sizeof(double) * n);
 }
