@@ -14,6 +14,8 @@ The default run (box32_N7_deformed, mixed_ir) reports beside it:
     timed steps, at most five, after a warm-up);
   - energy-to-solution (the GPU package's energy counter around repeated
     FP64 and mixed solves);
+  - the two-level Schwarz / multigrid preconditioner (flexible CG, FP64
+    and mixed refinement, medians of five);
   - the roofline of the dominant kernel (the fused operator kernel of the
     inner loop: the first operator launch of every graph chunk records its
     own start and end events on the solve's stream) beside the library's
@@ -110,7 +112,11 @@ def main():
         f = W.random_smooth_rhs(bm, wl.rhs_seed)
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
-    mesh = mx.Mesh(ctx, bm.E, wl.N, bm.xyz, bm.glo, bm.bnd, kcoef=kf, helm_h=wl.helm_h)
+    views = mx.VIEW_F64 | mx.VIEW_F32 | mx.VIEW_BF16
+    if wl.name == "box32_N7_deformed" and not args.traffic_probe:
+        views |= mx.VIEW_MG  # the multigrid leg below
+    mesh = mx.Mesh(ctx, bm.E, wl.N, bm.xyz, bm.glo, bm.bnd, kcoef=kf, helm_h=wl.helm_h,
+                   views=views)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     nloc = mesh.nloc
@@ -209,6 +215,23 @@ def main():
             "reason": sp.reason, "fallback_used": sp.fallback_used, "rel_res": sp.rel_res,
             "gain_vs_fp64": round(s64.ms / sp.ms, 3)}
         sols["mixed_ir_bf16p"] = xp.cpu().numpy()
+    if views & mx.VIEW_MG:
+        # the two-level Schwarz / multigrid preconditioner (the paper's
+        # solveM): FP64 and mixed refinement, medians like the FP64 solve
+        mgr = {}
+        for name, kw in (("fp64", dict(opts64, pc=mx.PC_MG)), (args.mode, dict(opts, pc=mx.PC_MG))):
+            xm = torch.zeros_like(b)
+            sm = median_solve(xm, kw)
+            it = sm.iterations + sm.outer
+            mgr[name] = {"ms": round(sm.ms, 3), "iterations": sm.iterations, "outer": sm.outer,
+                         "rel_res": sm.rel_res, "median_of": reps,
+                         "gdof_iter_s": round(nloc * it / (sm.ms * 1e-3) / 1e9, 3)}
+            sols[f"multigrid/{name}"] = xm.cpu().numpy()
+            log(f"multigrid {name}: {it} it, {sm.ms:.1f} ms, res {sm.rel_res:.2e}")
+        mgr["gain_mixed_over_fp64"] = round(mgr["fp64"]["ms"] / mgr[args.mode]["ms"], 3)
+        mgr["gain_over_jacobi"] = {"fp64": round(s64.ms / mgr["fp64"]["ms"], 3),
+                                   args.mode: round(mstep.ms / mgr[args.mode]["ms"], 3)}
+        extra["multigrid"] = mgr
     tt = {}
     for name, kw in (("fp64", opts64), (args.mode, opts)):
         xt = torch.zeros_like(b)

@@ -73,8 +73,19 @@ typedef enum {
 typedef enum {
   MXSEM_PC_IDENTITY = 0, /* z = r (Sec. 5, identity-preconditioned CG)      */
   MXSEM_PC_JACOBI = 1,   /* z = dinv * r, dinv = 1/diag(A) built in FP64 (Sec. 5.2) */
-  MXSEM_PC_LEARNED = 2   /* z = M QQ^T(c*(dinv*r + s_e NN(r))), needs an
+  MXSEM_PC_LEARNED = 2,  /* z = M QQ^T(c*(dinv*r + s_e NN(r))), needs an
                             attached network and method FCG                */
+  MXSEM_PC_MG = 3        /* two-level Schwarz / multigrid (the solveM step of
+                            Sec. 4.1's CG-loop table; Sec. 4.2 on its Schwarz
+                            weights): z = M QQ^T(ws FDM_e(ws r)) + P V(P^T r),
+                            ws = sqrt(1/m) taken in FP64, FDM_e the fast-
+                            diagonalisation solve on element e extended by
+                            one GLL interval into its neighbours, P trilinear
+                            interpolation from the element-vertex lattice, V
+                            one geometric V-cycle (damped Jacobi, Galerkin
+                            stencils, dense coarsest solve) in FP64.  Needs a
+                            mesh built with MXSEM_VIEW_MG; solves run it in
+                            flexible CG (one extra dot), single meshes only */
 } mxsem_pc;
 
 /* ---- solve modes -------------------------------------------------------- */
@@ -141,6 +152,12 @@ typedef enum {
 #define MXSEM_VIEW_F64 1u
 #define MXSEM_VIEW_F32 2u
 #define MXSEM_VIEW_BF16 4u
+#define MXSEM_VIEW_MG 8u   /* also build the multigrid preconditioner: needs a
+                              box of ne^3 elements (ne >= 2) in lexicographic
+                              order, global ids on the lattice of GLL nodes
+                              (id = gx + G1 (gy + G1 gz), G1 = ne N + 1) and
+                              Dirichlet conditions on the whole box boundary
+                              (else MXSEM_ENOTSUP); about 30 B per local entry */
 
 typedef struct mxsem_ctx mxsem_ctx;
 typedef struct mxsem_mesh mxsem_mesh;

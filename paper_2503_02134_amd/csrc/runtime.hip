@@ -231,6 +231,7 @@ int mxsem_mesh_destroy(mxsem_mesh* m) {
   }
   mesh_drop_plans(m);
   for (int q = 0; q < 4; ++q) delete m->bufs[q];
+  delete m->mg;
   if (m->counted) m->ctx->live -= 1;
   delete m;  // the workspace is the caller's
   return MXSEM_OK;
@@ -249,6 +250,9 @@ static int check_desc(const mxsem_mesh_desc* d) {
   const int n = d->N + 1;
   MX_CHECK((int64_t)d->E * n * n * n < (int64_t)INT32_MAX - UPD_CHUNK, MXSEM_ENOTSUP,
            "mesh: more than 2^31 local entries");
+  MX_CHECK((d->views & ~(MXSEM_VIEW_F64 | MXSEM_VIEW_F32 | MXSEM_VIEW_BF16 | MXSEM_VIEW_MG)) == 0,
+           MXSEM_EINVAL, "mesh: unknown view bits");
+  if (d->views & MXSEM_VIEW_MG) MX_TRY(mg_check_box(d));
   return MXSEM_OK;
 }
 
@@ -431,6 +435,10 @@ static size_t mesh_layout(mxsem_mesh* m, size_t nidx, bool has_k, char* ws, Setu
     }
     L.total = std::max(L.total, T.total);
   }
+  if (m->views & MXSEM_VIEW_MG) {
+    if (ws && !m->mg) m->mg = new MgData();
+    mg_layout(m, ws, L);
+  }
   const size_t tb = plan_table_bytes(&m, 1);
   const int vps[3] = {VP_F64, VP_F32, VP_F32ACC};
   for (int q = 0; q < ((f32 || b16) ? 3 : 1); ++q) {
@@ -583,9 +591,11 @@ int mxsem_mesh_create(mxsem_ctx* ctx, const mxsem_mesh_desc* d, void* workspace,
     MX_MHIP(launch_cast_g_split(2, m->G16, m->G64, m->E, m->n3, s));
     if (m->hB16) MX_MHIP(launch_cast_bf16(m->hB16, m->hB64, nloc, s));
   }
+  if (m->mg) MX_MTRY(mg_setup(m, d, s));
   // the set-up temporaries sat in the FP64 work vectors: clear them again
   {
-    const int64_t n16 = (int64_t)((align256(tmp.end) - tmp.begin) / 16);
+    const size_t end = std::max(tmp.end, (size_t)((char*)m->bufs[VP_F64]->part_ax - m->ws));
+    const int64_t n16 = (int64_t)((align256(end) - tmp.begin) / 16);
     hipLaunchKernelGGL(ws_zero_kernel, dim3((unsigned)std::min<int64_t>((n16 + 255) / 256, 65536)),
                        dim3(256), 0, s, (uint4*)(m->ws + tmp.begin), n16);
     MX_MHIP(hipGetLastError());

@@ -139,6 +139,50 @@ struct Region {
 // (the workspace was sized for every plan the object can build).
 int region_take(Region& r, void** p, size_t bytes);
 
+// ---------------------------------------------------------------- multigrid
+// Two-level Schwarz / multigrid preconditioner of a box mesh (mg.hip).
+constexpr int MG_MAXLEV = 12;
+constexpr int MG_COARSEST_MAX = 512;  // unknowns of the directly solved level
+struct MgLevel {
+  int nu = 0;              // interior lattice nodes per direction
+  double omega = 0.0;      // Jacobi damping
+  double* st = nullptr;    // [nu^3][27] stencil
+  double *b = nullptr, *x = nullptr, *x2 = nullptr, *r = nullptr;  // [nu^3]
+};
+struct MgData {
+  int ne = 0, nlev = 0, nc = 0;
+  double *S64 = nullptr, *lam64 = nullptr;  // [E][3][n][n], [E][3][n]
+  float *S32 = nullptr, *lam32 = nullptr;
+  double* kbar = nullptr;                   // [E] mean coefficient
+  double* ws64 = nullptr;                   // [256] sqrt(1/m) (FP64 square roots)
+  float* ws32 = nullptr;                    // the same, rounded once to FP32
+  double* J = nullptr;                      // [n][2] order-1 basis at the GLL nodes
+  double* corner = nullptr;                 // [E][8] restricted residual per element vertex
+  int* ecorner = nullptr;                   // [E][8] lattice index of each corner, -1 on the boundary
+  double* K = nullptr;                      // [E][64] Galerkin element matrices (set-up)
+  double* cinv = nullptr;                   // [nc][nc] inverse of the coarsest operator
+  MgLevel lv[MG_MAXLEV];
+};
+// elements per direction of a box mesh of E elements (0 if E is no cube)
+int mg_cube_root(int E);
+// the levels' interior node counts per direction for ne elements per direction
+int mg_levels(int ne, int* nu);
+// blocks of the preconditioner in the mesh workspace (ws == nullptr: sizes only)
+void mg_layout(mxsem_mesh* m, char* ws, Layout& L);
+// the box structure of a mesh description: MXSEM_OK or MXSEM_ENOTSUP
+int mg_check_box(const mxsem_mesh_desc* d);
+// builds the preconditioner's data (after the operator data exist)
+int mg_setup(mxsem_mesh* m, const mxsem_mesh_desc* d, hipStream_t s);
+// z = M^-1 r (vprec VP_F64 or FP32 vectors); st: the solve's state (the
+// kernels return at once when it is done), or null.  pl: the solve's plan
+// (single problem, z its work vector), or null; with a plan the coarse
+// correction is left to mg_prolong_dots, which adds it while it sums the
+// flexible-CG dots of the step
+struct Plan;
+int mg_apply(mxsem_mesh* m, int vprec, const void* r, void* z, hipStream_t s, const State* st,
+             const Plan* pl = nullptr);
+int mg_prolong_dots(const mxsem_mesh* m, const Plan* pl, hipStream_t s);
+
 // Bytes of the launch tables of one plan over these problems (operator,
 // gather-scatter and vector-pass tiles, problem views, states, norms).
 size_t plan_table_bytes(mxsem_mesh* const* meshes, int P);
@@ -237,6 +281,7 @@ struct mxsem_mesh {
   mx::Plan* self_plan[4] = {nullptr, nullptr, nullptr, nullptr};
   mx::Region plan_tables[4];  // workspace blocks of the self plans' tables
   mxsem_nn* nn = nullptr;
+  mx::MgData* mg = nullptr;   // multigrid preconditioner (MXSEM_VIEW_MG)
   char* ws = nullptr;         // the caller's workspace (never freed here)
   size_t ws_bytes = 0;
   bool counted = false;

@@ -466,6 +466,12 @@ static int enqueue_fcg_z(Plan* pl, int pc, hipStream_t s, bool init) {
     MX_HIP(launch_fin_beta(pl->probs, pl->P, init ? 1 : 0, s, dots, nparts, dstride));
     MX_HIP(launch_gs_solver(pl->vprec, pl->tiles_gs, pl->nt_gs, pl->probs, s, true, 0,
                             pl->tiles_upd, pl->nt_upd));
+  } else if (pc == MXSEM_PC_MG) {
+    // two-level Schwarz / multigrid z (single-problem plans)
+    MX_TRY(mg_apply(pl->meshes[0], pl->vprec, pl->bufs[0]->r, pl->bufs[0]->z, s, pl->hprob[0].st,
+                    pl));
+    MX_TRY(mg_prolong_dots(pl->meshes[0], pl, s));
+    MX_HIP(launch_fin_beta(pl->probs, pl->P, init ? 1 : 0, s));
   } else {
     MX_HIP(launch_zpc(pl->vprec, pl->tiles_upd, pl->nt_upd, pl->probs, pc, s));
     MX_HIP(launch_fcg_dots(pl->vprec, pl->tiles_upd, pl->nt_upd, pl->probs, s));
@@ -665,7 +671,10 @@ static int solve_many(mxsem_ctx* ctx, const std::vector<mxsem_mesh*>& meshes, Ge
                           : dot_mode_of(o->dot, mode == MXSEM_MODE_FP32_ALL ? DOT_F32 : DOT_F64);
   in.pairwise = o->gs_order == MXSEM_GS_ORDER_PAIRWISE ? 1 : 0;
   std::vector<char> fallback(P, 0);
-  const bool fcg = o->method == MXSEM_METHOD_FCG || o->pc == MXSEM_PC_LEARNED;
+  // the learned and the multigrid preconditioners run in flexible CG (the
+  // multigrid one is linear and symmetric, so this is PCG with one more dot)
+  const bool fcg = o->method == MXSEM_METHOD_FCG || o->pc == MXSEM_PC_LEARNED ||
+                   o->pc == MXSEM_PC_MG;
   auto inner = [&](Plan* q, int gp, Inner& io) {
     return fcg ? run_inner_fcg(q, ctx, gp, o->pc, o->graph_chunk, io)
                : run_inner(q, ctx, gp, o->pc, o->graph_chunk, io);
@@ -780,8 +789,11 @@ static int solve_many(mxsem_ctx* ctx, const std::vector<mxsem_mesh*>& meshes, Ge
         f.tol[p] = r > 0 ? o->tol * bnorm[p] / r : o->tol;
         f.maxit[p] = std::max(1, o->max_iter - st[p].iterations);
       }
-      MX_TRY(run_inner(p64, ctx, 0, o->pc == MXSEM_PC_LEARNED ? MXSEM_PC_JACOBI : o->pc,
-                       o->graph_chunk, f));
+      if (o->pc == MXSEM_PC_MG)
+        MX_TRY(run_inner_fcg(p64, ctx, 0, MXSEM_PC_MG, o->graph_chunk, f));
+      else
+        MX_TRY(run_inner(p64, ctx, 0, o->pc == MXSEM_PC_LEARNED ? MXSEM_PC_JACOBI : o->pc,
+                         o->graph_chunk, f));
       for (int p = 0; p < P; ++p) {
         if (!fallback[p]) continue;
         MX_HIP(launch_axpy_cast(0, x[p], p64->bufs[p]->x, 1.0, 1.0, meshes[p]->nloc, s));
@@ -876,6 +888,11 @@ int mxsem_precond(mxsem_mesh* m, mxsem_pc pc, mxsem_prec io, const void* r, void
     MX_CHECK(io == MXSEM_F32, MXSEM_ENOTSUP, "precond: the learned map takes FP32 vectors");
     return mxsem_nn_forward(m->nn, (const float*)r, (float*)z);
   }
+  if (pc == MXSEM_PC_MG) {
+    MX_CHECK(io == MXSEM_F64 || io == MXSEM_F32, MXSEM_EINVAL, "precond: io must be F64/F32");
+    MX_CHECK(r != z, MXSEM_EINVAL, "precond: r and z must not alias for the multigrid map");
+    return mg_apply(m, io == MXSEM_F64 ? VP_F64 : VP_F32, r, z, m->ctx->stream, nullptr);
+  }
   MX_CHECK(pc == MXSEM_PC_IDENTITY || pc == MXSEM_PC_JACOBI, MXSEM_EINVAL, "precond: unknown pc");
   MX_CHECK(io == MXSEM_F64 || io == MXSEM_F32, MXSEM_EINVAL, "precond: io must be F64/F32");
   if (io == MXSEM_F32) MX_CHECK(m->dinv32, MXSEM_ENOTSUP, "precond: mesh has no FP32 view");
@@ -890,7 +907,8 @@ static int check_opts(const mxsem_solve_opts* o) {
            MXSEM_EINVAL, "solve: bad tol / max_iter / graph_chunk");
   MX_CHECK(o->mode >= MXSEM_MODE_FP64 && o->mode <= MXSEM_MODE_MIXED_IR_BF16P, MXSEM_EINVAL,
            "solve: unknown mode");
-  MX_CHECK(o->pc == MXSEM_PC_IDENTITY || o->pc == MXSEM_PC_JACOBI || o->pc == MXSEM_PC_LEARNED,
+  MX_CHECK(o->pc == MXSEM_PC_IDENTITY || o->pc == MXSEM_PC_JACOBI || o->pc == MXSEM_PC_LEARNED ||
+               o->pc == MXSEM_PC_MG,
            MXSEM_EINVAL, "solve: unknown preconditioner");
   MX_CHECK(o->max_outer >= 0 && o->inner_tol > 0.0 && o->inner_tol < 1.0, MXSEM_EINVAL,
            "solve: bad refinement options");
@@ -901,7 +919,8 @@ static int check_opts(const mxsem_solve_opts* o) {
            "solve: unknown dot accumulation");
   MX_CHECK(o->gs_order == MXSEM_GS_ORDER_ONE || o->gs_order == MXSEM_GS_ORDER_PAIRWISE,
            MXSEM_EINVAL, "solve: unknown gather-scatter order");
-  const bool pcg = o->method == MXSEM_METHOD_PCG && o->pc != MXSEM_PC_LEARNED;
+  const bool pcg = o->method == MXSEM_METHOD_PCG && o->pc != MXSEM_PC_LEARNED &&
+                   o->pc != MXSEM_PC_MG;
   MX_CHECK(o->mode != MXSEM_MODE_MIXED_IR_BF16P || pcg, MXSEM_ENOTSUP,
            "solve: the BF16-direction ablation is for PCG");
   MX_CHECK(o->dot == MXSEM_DOT_DEFAULT || o->dot == MXSEM_DOT_F64 ||
@@ -932,6 +951,8 @@ int mxsem_solve(mxsem_mesh* m, const mxsem_solve_opts* o, const double* b, doubl
   }
   MX_CHECK(o->method == MXSEM_METHOD_PCG || o->method == MXSEM_METHOD_FCG, MXSEM_EINVAL,
            "solve: unknown method");
+  if (o->pc == MXSEM_PC_MG)
+    MX_CHECK(m->mg, MXSEM_EINVAL, "solve: the mesh was built without MXSEM_VIEW_MG");
   std::vector<mxsem_mesh*> ms{m};
   auto get = [m](int vp, Plan** out) { return get_self_plan(m, vp, out); };
   return solve_many(m->ctx, ms, get, o, &b, &x, st);
@@ -1026,7 +1047,7 @@ int mxsem_batch_solve(mxsem_batch* bt, const mxsem_solve_opts* o, const double* 
   MX_API_BEGIN
   MX_CHECK(bt && o && b && x && st, MXSEM_EINVAL, "batch_solve: null argument");
   MX_TRY(check_opts(o));
-  MX_CHECK(o->pc != MXSEM_PC_LEARNED, MXSEM_ENOTSUP,
+  MX_CHECK(o->pc != MXSEM_PC_LEARNED && o->pc != MXSEM_PC_MG, MXSEM_ENOTSUP,
            "batch_solve: batches run (flexible) CG with Jacobi or identity");
   MX_CHECK(!o->history, MXSEM_ENOTSUP, "batch_solve: no residual history for batches");
   const int P = (int)bt->meshes.size();

@@ -27,7 +27,7 @@ OK, EINVAL, ENOTSUP, EHIP, EBREAKDOWN, EINTERNAL, ENOMEM, EMESH = 0, -1, -2, -3,
 # precisions
 F64, F32, BF16G_F32 = 0, 1, 2
 # preconditioners
-PC_IDENTITY, PC_JACOBI, PC_LEARNED = 0, 1, 2
+PC_IDENTITY, PC_JACOBI, PC_LEARNED, PC_MG = 0, 1, 2, 3
 # modes
 MODE_FP64, MODE_MIXED, MODE_MIXED_IR, MODE_MIXED_IR_BF16G, MODE_FP32_ALL = 0, 1, 2, 3, 4
 MODE_MIXED_IR_BF16P = 5
@@ -37,7 +37,7 @@ LOCAL_ONLY, MASK, GS_PAIRWISE = 1, 2, 4
 # dot accumulation of the FP32 loop, and gather-scatter order
 DOT_DEFAULT, DOT_F64, DOT_F32, DOT_DOT2 = 0, 1, 2, 3
 GS_ORDER_ONE, GS_ORDER_PAIRWISE = 0, 1
-VIEW_F64, VIEW_F32, VIEW_BF16 = 1, 2, 4
+VIEW_F64, VIEW_F32, VIEW_BF16, VIEW_MG = 1, 2, 4, 8
 
 MODE_NAMES = {MODE_FP64: "fp64", MODE_MIXED: "mixed", MODE_MIXED_IR: "mixed_ir",
               MODE_MIXED_IR_BF16G: "mixed_ir_bf16g", MODE_FP32_ALL: "fp32_all",

@@ -236,3 +236,25 @@ def test_autotune_workspace_bytes(mx):
     assert nb.value >= (4 + 4 + 24) * nloc  # u, w and six FP32 factors per node
     assert L.mxsem_autotune_workspace_bytes(16, 64, mx.F32, C.byref(nb)) == mx.ENOTSUP
     assert L.mxsem_autotune_workspace_bytes(7, 0, mx.F32, C.byref(nb)) == mx.EINVAL
+
+
+def test_multigrid_view_is_sized_and_checked_on_the_host(mx):
+    """MXSEM_VIEW_MG adds the multigrid blocks to the mesh workspace, and a
+    mesh that is not a Dirichlet box of lexicographic elements is refused
+    with MXSEM_ENOTSUP by the sizing call already."""
+    L = mx.lib()
+    bm, (d, keep) = _small_desc(mx, ne=4, N=3)
+    nb0, nb1 = C.c_size_t(), C.c_size_t()
+    assert L.mxsem_mesh_workspace_bytes(C.byref(d), C.byref(nb0)) == mx.OK
+    d.views |= mx.VIEW_MG
+    assert L.mxsem_mesh_workspace_bytes(C.byref(d), C.byref(nb1)) == mx.OK
+    # eigenvector matrices (3 n^2 per element, FP64 and FP32), lattice stencils
+    assert nb1.value - nb0.value >= bm.E * 3 * 16 * 12
+    glo = np.ascontiguousarray(bm.glo.reshape(bm.E, -1)[::-1])
+    bm2, (d2, keep2) = _small_desc(mx, ne=4, N=3)
+    d2.glo = glo.ctypes.data
+    d2.views |= mx.VIEW_MG
+    assert L.mxsem_mesh_workspace_bytes(C.byref(d2), C.byref(nb1)) == mx.ENOTSUP
+    assert b"lattice" in L.mxsem_last_error()
+    d2.views = 16
+    assert L.mxsem_mesh_workspace_bytes(C.byref(d2), C.byref(nb1)) == mx.EINVAL
