@@ -376,9 +376,11 @@ def test_full_size_local_operator_sampled(orc, mx, ctx):
 
 
 @pytest.mark.slow
-def test_full_size_solve_sampled_residual(orc, mx, ctx):
+@pytest.mark.parametrize("pc", ["jacobi", "multigrid"])
+def test_full_size_solve_sampled_residual(orc, mx, ctx, pc):
     """The benchmark solve itself (32^3 deformed elements, N = 7, mixed
-    FP32/FP64 refinement to 1e-10, graph chunks of 16): on sampled elements
+    FP32/FP64 refinement to 1e-10, graph chunks of 16), with the Jacobi and
+    with the multigrid preconditioner: on sampled elements
     the oracle recomputes b and b - A x from the returned x.  Each sampled
     element is taken with every element that shares a node with it, so the
     oracle's assembled sums are complete on the sample.  The HIP path's FP64
@@ -387,12 +389,15 @@ def test_full_size_solve_sampled_residual(orc, mx, ctx):
     the residual norm cannot exceed the whole."""
     from paper_2503_02134_amd import workloads as W
     wl = W.WORKLOADS["box32_N7_deformed"]
-    log("full-size 32^3 N7 mixed solve, sampled residual")
+    log(f"full-size 32^3 N7 mixed solve ({pc}), sampled residual")
     xg, _ = mx.mxsem_gll(wl.N)
     bmg = W.box_mesh(wl.ne, wl.N, xg, seed=wl.deform_seed)
-    gm = mx.Mesh(ctx, bmg.E, wl.N, bmg.xyz, bmg.glo, bmg.bnd)
+    views = mx.VIEW_F64 | mx.VIEW_F32 | mx.VIEW_BF16 | (mx.VIEW_MG if pc == "multigrid" else 0)
+    gm = mx.Mesh(ctx, bmg.E, wl.N, bmg.xyz, bmg.glo, bmg.bnd, views=views)
     b = gm.mass_rhs(_t(W.manufactured(bmg)[0]))
-    x, st = gm.solve(b, mode=mx.MODE_MIXED_IR, tol=wl.tol, max_iter=20000, graph_chunk=16)
+    x, st = gm.solve(b, mode=mx.MODE_MIXED_IR, tol=wl.tol, max_iter=20000, graph_chunk=16,
+                     pc=mx.PC_MG if pc == "multigrid" else mx.PC_JACOBI)
+    log(f"  {st.iterations} + {st.outer} iterations, relative residual {st.rel_res:.2e}")
     assert st.reason == mx.CONVERGED and st.rel_res <= wl.tol
     r = (b - gm.apply(x, mx.F64)).cpu().numpy()
     bh = b.cpu().numpy()
