@@ -24,12 +24,15 @@ The default run (box32_N7_deformed, mixed_ir) reports beside it:
     from the FP64 solver, training, scale calibration, then learned flexible
     CG, Jacobi PCG (both inside FP64 refinement) and FP64 Jacobi PCG on a
     held-out right-hand side, to residuals 1e-10 and 1e-8, medians of five;
+  - the 64-problem batch (shared graph launches, mixed refinement, median of
+    three) against the 64 FP64 solves one after another;
   - the CPU oracle (plain C, FP64, OpenMP over elements) on the host cores:
     its Jacobi-PCG solve of the benchmark workload from x = 0 to 1e-10 is
     timed (cpu_baseline), continued to 1e-13 for the reference solution x*,
     and every GPU solution of both legs is reported with its relative
-    c-norm error against the oracle's x* (error_vs_oracle).
---no-learned and --no-cpu drop those legs; --dot fp32 | dot2 sets the
+    c-norm error against the oracle's x* (error_vs_oracle), as are three of
+    the batch's problems.
+--no-learned, --no-batch and --no-cpu drop those legs; --dot fp32 | dot2 sets the
 accumulation of the inner loop's dots.  Other workloads: --workload batch64
 (64 uneven problems), --workload box24_N7_lognormal_helmholtz --mode learned
 (the learned leg alone, four held-out right-hand sides) and --workload
@@ -73,6 +76,8 @@ def main():
                     help="skip the CPU oracle (baseline timing and reference solutions)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-preconditioner leg of the default run")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-problem batch leg of the default run")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="short run for hardware-counter collection: a 1 GiB device copy "
                          "(calibration), then 20 inner iterations of the solve; no JSON line")
@@ -317,6 +322,10 @@ def main():
     learned_sols = None
     if not args.no_learned and args.workload == "box32_N7_deformed":
         out["learned"], learned_sols = learned_leg(ctx, reps, log)
+    batch_sols = None
+    if not args.no_batch and args.workload == "box32_N7_deformed":
+        out["batch"], batch_sols = batch_leg(ctx, 3, 1, keep=batch_oracle_problems())
+        log(f"batch: {out['batch']}")
     ctx.close()
     if not args.no_cpu:
         out["cpu_baseline"], errs = oracle_leg(wl, sols)
@@ -325,6 +334,8 @@ def main():
             errs5 = oracle_reference_errors(W.WORKLOADS["box24_N7_lognormal_helmholtz"],
                                             learned_sols["rhs_seed"], learned_sols["x"])
             out["learned"]["error_vs_oracle"] = errs5
+        if batch_sols is not None:
+            out["batch"]["error_vs_oracle"] = batch_oracle_errors(batch_sols)
     print(json.dumps(out), flush=True)
 
 
@@ -433,19 +444,20 @@ def ax_traffic_from_profile(mode):
     return int(m_b.group(1))
 
 
-def bench_batch(args):
+def batch_leg(ctx, steps, warmup, keep=()):
     """64 uneven Poisson problems (E in {8^3,12^3,16^3,24^3}, N in {5,7,9},
     seeded smooth RHS) solved together in shared graph launches (mixed
-    refinement), against 64 sequential FP64 solves on the same GPU."""
+    refinement, medians over `steps` batch solves), against the 64 FP64
+    solves one after another on the same GPU.  Returns the result record and
+    the solutions of the problems listed in `keep` (for the oracle's errors)."""
     import torch
 
     from paper_2503_02134_amd import mxsem as mx
     from paper_2503_02134_amd import workloads as W
-    ctx = mx.Context(0)
     draws = W.batch_draws()
     meshes, bs = [], []
     t0 = time.perf_counter()
-    for ne, N, seed in draws:
+    for q, (ne, N, seed) in enumerate(draws):
         xi, _ = mx.mxsem_gll(N)
         bm = W.box_mesh(ne, N, xi)
         m = mx.Mesh(ctx, bm.E, N, bm.xyz, bm.glo, bm.bnd)
@@ -453,6 +465,8 @@ def bench_batch(args):
         bs.append(m.mass_rhs(torch.as_tensor(f, device="cuda")))
         meshes.append(m)
         del bm
+        if q % 16 == 15:
+            log(f"batch64: {q + 1} problems set up ({time.perf_counter() - t0:.1f}s)")
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     nloc = [m.nloc for m in meshes]
@@ -463,23 +477,27 @@ def bench_batch(args):
     t_tune = time.perf_counter() - t0
     xs = [torch.zeros_like(b) for b in bs]
     opts = mx.solve_opts(mode=mx.MODE_MIXED_IR, tol=1e-10, max_iter=20000, graph_chunk=16)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         for x in xs:
             x.zero_()
         mx.mxsem_batch_solve(bt, opts, bs, xs)
     torch.cuda.synchronize()
-    its = 0
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
+    times, its = [], 0
+    for _ in range(steps):
         for x in xs:
             x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         sts = mx.mxsem_batch_solve(bt, opts, bs, xs)
-        its += sum(n * (s.iterations + s.outer) for n, s in zip(nloc, sts))
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        its = sum(n * (s.iterations + s.outer) for n, s in zip(nloc, sts))
+    el = sorted(times)[len(times) // 2]
     conv = sum(s.reason == mx.CONVERGED for s in sts)
     worst = max(s.rel_res for s in sts)
+    kept = {p: xs[p].cpu().numpy() for p in keep}
     # the same problems one after another in FP64
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     its64 = 0
     for m, b in zip(meshes, bs):
@@ -487,26 +505,41 @@ def bench_batch(args):
         its64 += m.nloc * s.iterations
     torch.cuda.synchronize()
     el64 = time.perf_counter() - t0
-    out = {
-        "metric": "GDOF*iter/s (local dofs x iterations / s) of the SEM PCG solve",
-        "value": round(its / el / 1e9, 4), "unit": "GDOF*iter/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(el * 1e3 / args.steps, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 (f64 gather-scatter sums, dots, refinement residuals)",
-        "data": "synthetic",
-        "config": {"workload": "batch64", "problems": len(meshes), "nloc_total": sum(nloc),
-                   "mode": "mixed_ir (batched)", "tol": 1e-10},
+    rec = {
+        "problems": len(meshes), "nloc_total": sum(nloc), "mode": "mixed_ir (batched)",
+        "tol": 1e-10, "ms": round(el * 1e3, 3), "median_of": steps,
+        "gdof_iter_s": round(its / el / 1e9, 4),
         "converged": conv, "worst_rel_res": worst,
         "sequential_fp64": {"ms": round(el64 * 1e3, 3),
                             "gdof_iter_s": round(its64 / el64 / 1e9, 4)},
-        "batch_vs_sequential_fp64_time": round(el64 / (el / args.steps), 3),
+        "batch_vs_sequential_fp64_time": round(el64 / el, 3),
         "setup_s": round(t_setup, 2), "tune_s": round(t_tune, 2),
     }
-    print(json.dumps(out), flush=True)
     mx.mxsem_batch_destroy(bt)
     for m in meshes:
         m.close()
+    return rec, kept
+
+
+def bench_batch(args):
+    """The batch leg on its own, as the bench line (value: the batched solve's
+    GDOF*iter/s)."""
+    from paper_2503_02134_amd import mxsem as mx
+    ctx = mx.Context(0)
+    rec, _ = batch_leg(ctx, max(args.steps, 1), args.warmup)
+    out = {
+        "metric": "GDOF*iter/s (local dofs x iterations / s) of the SEM PCG solve",
+        "value": rec["gdof_iter_s"], "unit": "GDOF*iter/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": rec["ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (f64 gather-scatter sums, dots, refinement residuals)",
+        "data": "synthetic",
+        "config": {"workload": "batch64", "problems": rec["problems"],
+                   "nloc_total": rec["nloc_total"], "mode": rec["mode"], "tol": rec["tol"]},
+        **{k: v for k, v in rec.items() if k not in ("problems", "nloc_total", "mode", "tol")},
+    }
+    print(json.dumps(out), flush=True)
     ctx.close()
 
 
@@ -849,6 +882,37 @@ def oracle_leg(wl, sols):
         errs[name] = _c_err(om, x, xs)
     log(f"errors vs oracle: {errs}")
     return base, errs
+
+
+def batch_oracle_problems():
+    """The batch problems whose solutions the oracle checks: the first one of
+    each order on 8^3 elements (the oracle solves each in a few seconds)."""
+    from paper_2503_02134_amd import workloads as W
+    picked, seen = [], set()
+    for p, (ne, N, _) in enumerate(W.batch_draws()):
+        if ne == 8 and N not in seen:
+            picked.append(p)
+            seen.add(N)
+    return tuple(picked)
+
+
+def batch_oracle_errors(sols):
+    """Relative c-norm errors of batch solutions (problem -> x) against the
+    oracle's FP64 Jacobi-PCG solution of the same problem to 1e-13."""
+    import oracle
+    from paper_2503_02134_amd import workloads as W
+    draws = W.batch_draws()
+    errs = {"reference": "oracle FP64 Jacobi-PCG of each listed problem to relative residual 1e-13",
+            "norm": "relative c-weighted L2 (c = 1/multiplicity)"}
+    for p, x in sols.items():
+        ne, N, seed = draws[p]
+        xo, _ = oracle.gll(N)
+        bm = W.box_mesh(ne, N, xo)
+        om = oracle.Mesh(bm.E, N, bm.xyz, bm.glo, bm.bnd)
+        xs, st = om.pcg(om.rhs(W.random_smooth_rhs(bm, seed)), tol=1e-13, maxit=50000)
+        errs[f"problem_{p}_ne{ne}_N{N}"] = _c_err(om, x, xs)
+    log(f"batch errors vs oracle: {errs}")
+    return errs
 
 
 def oracle_reference_errors(wl, rhs_seed, xs_gpu):

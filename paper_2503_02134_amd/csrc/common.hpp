@@ -206,6 +206,11 @@ struct ProbDev {
   double* part_u2;   // per tile: (z,w)_c (flexible CG)
   int nblk_ax, nblk_gs, nblk_upd;
   int dm;            // DotMode of the partial sums (PCG)
+  // box lattice (ne^3 lexicographic elements, lattice global ids, Dirichlet
+  // on the whole boundary, n = 8 or 16): elements per direction (else 0),
+  // log2 n, 1/ne and 1/ne^2; the PCG vector pass then forms QQ^T w itself
+  int box_ne, box_ln;
+  float box_rne, box_rne2;
   State* st;
 };
 

@@ -60,15 +60,12 @@ int mg_levels(int ne, int* nu) {
   return l;
 }
 
-int mg_check_box(const mxsem_mesh_desc* d) {
+// ne when the mesh is a box lattice: E = ne^3 elements in lexicographic
+// order (x fastest), global ids gx + G1 (gy + G1 gz) with gx = ex N + i and
+// G1 = ne N + 1, and Dirichlet conditions exactly on the box boundary; else 0
+int box_lattice_ne(const mxsem_mesh_desc* d) {
   const int ne = mg_cube_root(d->E);
-  MX_CHECK(ne >= 2, MXSEM_ENOTSUP, "multigrid: needs a box of ne^3 elements, ne >= 2");
-  {
-    int nu[MG_MAXLEV];
-    const int nl = mg_levels(ne, nu);
-    MX_CHECK((int64_t)nu[nl - 1] * nu[nl - 1] * nu[nl - 1] <= 4096, MXSEM_ENOTSUP,
-             "multigrid: the lattice cannot be coarsened to 4096 unknowns (odd element count)");
-  }
+  if (ne < 1) return 0;
   const int N = d->N, n = N + 1, n3 = n * n * n;
   const int64_t G1 = (int64_t)ne * N + 1;
   for (int e = 0; e < d->E; ++e) {
@@ -78,14 +75,24 @@ int mg_check_box(const mxsem_mesh_desc* d) {
         for (int i = 0; i < n; ++i) {
           const int64_t q = (int64_t)e * n3 + i + n * (j + n * k);
           const int64_t gx = (int64_t)ex * N + i, gy = (int64_t)ey * N + j, gz = (int64_t)ez * N + k;
-          MX_CHECK(d->glo[q] == gx + G1 * (gy + G1 * gz), MXSEM_ENOTSUP,
-                   "multigrid: global ids are not the box lattice of lexicographic elements");
+          if (d->glo[q] != gx + G1 * (gy + G1 * gz)) return 0;
           const bool onb = gx == 0 || gy == 0 || gz == 0 || gx == G1 - 1 || gy == G1 - 1 ||
                            gz == G1 - 1;
-          MX_CHECK((d->bnd[q] != 0) == onb, MXSEM_ENOTSUP,
-                   "multigrid: needs Dirichlet conditions on the whole box boundary");
+          if ((d->bnd[q] != 0) != onb) return 0;
         }
   }
+  return ne;
+}
+
+int mg_check_box(const mxsem_mesh_desc* d) {
+  const int ne = box_lattice_ne(d);
+  MX_CHECK(ne >= 2, MXSEM_ENOTSUP,
+           "multigrid: needs a box of ne^3 >= 8 elements in lexicographic order with lattice "
+           "global ids and Dirichlet conditions on the whole boundary");
+  int nu[MG_MAXLEV];
+  const int nl = mg_levels(ne, nu);
+  MX_CHECK((int64_t)nu[nl - 1] * nu[nl - 1] * nu[nl - 1] <= 4096, MXSEM_ENOTSUP,
+           "multigrid: the lattice cannot be coarsened to 4096 unknowns (odd element count)");
   return MXSEM_OK;
 }
 

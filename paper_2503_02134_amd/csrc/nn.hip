@@ -15,9 +15,11 @@
 // of 864).  Weights are uniform across the wave and are read through the
 // scalar cache.
 // Backward, a fixed set of workgroups each walking a fixed list of
-// elements: forward recomputed in LDS, then every thread accumulates the
-// gradient entries it owns over all positions and elements; one partial per
-// workgroup, summed in a fixed order afterwards (deterministic, no atomics).
+// elements, the forward recomputed: for N = 7 on the matrix cores (four
+// small GEMMs per 32-position tile, see nn_bwd_mfma_n8_kernel), for N = 3
+// and 5 in vector FP32 with every thread accumulating the gradient entries
+// it owns.  One partial per workgroup, summed in a fixed order afterwards
+// (deterministic, no atomics).
 #include <math.h>
 #include <string.h>
 
@@ -296,18 +298,27 @@ static_assert(rows_cover_taps(), "second-layer rows hold each tap once");
 static_assert(NPL * 512 * 4 <= 65535, "group planes reachable by LDS load offsets");
 }  // namespace nnm
 
-// Weight operands in the per-lane A layout, packed once per weight update:
-// pk[ks * 64 + lane] for the 4 first-layer and then 2 second-layer k steps.
-// First layer: row = channel, k = 16 ks + 8h + 2u + ci <-> input slot
-// 8 ks + 4h + u.  Second layer: row = result slot, k = 16 ks + 8h + t <->
-// channel 16 ks + 8(t/4) + 4h + t%4 (the first layer's result rows there).
+// Weight operands in the per-lane operand layout, packed once per weight
+// update: pk[ks * 64 + lane].  Forward (A operands, ks 0..5): the 4
+// first-layer and then 2 second-layer k steps.  First layer: row = channel,
+// k = 16 ks + 8h + 2u + ci <-> input slot 8 ks + 4h + u.  Second layer: row =
+// result slot, k = 16 ks + 8h + t <-> channel 16 ks + 8(t/4) + 4h + t%4 (the
+// first layer's result rows there).  Backward (B operands, column =
+// channel, ks 6..11): W1^T over the slots s = 16 (ks - 6) + 8h + t = 32 ci +
+// tap, then W2^T over the taps 16 (ks - 10) + 8h + t; taps 27..31 are zero.
 __global__ void nn_pack_kernel(const float* __restrict__ W1, const float* __restrict__ W2,
                                bf16x8_t* __restrict__ pk) {
-  const int lane = threadIdx.x & 63, ks = threadIdx.x >> 6;  // 6 x 64 threads
+  const int lane = threadIdx.x & 63, ks = threadIdx.x >> 6;  // 12 x 64 threads
   const int row = lane & 31, h = lane >> 5;
   bf16x8_t v;
   for (int t = 0; t < 8; ++t) {
-    if (ks < 4) {
+    if (ks >= 10) {
+      const int tap = 16 * (ks - 10) + 8 * h + t;
+      v[t] = (__bf16)(tap < 27 ? W2[row * 27 + tap] : 0.f);
+    } else if (ks >= 6) {
+      const int sl = 16 * (ks - 6) + 8 * h + t, ci = sl >> 5, tap = sl & 31;
+      v[t] = (__bf16)(tap < 27 ? W1[row * 54 + ci * 27 + tap] : 0.f);
+    } else if (ks < 4) {
       const int tap = nnm::IN.tap[8 * ks + 4 * h + (t >> 1)], ci = t & 1;
       v[t] = (__bf16)(tap >= 0 ? W1[row * 54 + ci * 27 + tap] : 0.f);
     } else {
@@ -703,6 +714,174 @@ __global__ void __launch_bounds__(NN_THREADS)
   }
 }
 
+// Backward for N = 7 on the matrix cores (v_mfma_f32_32x32x16_bf16).  For
+// one element, with positions p, hidden channels c, taps o (offsets d_o) and
+// input slots s = (ci, o):
+//   (1) H^T[p][c]   = relu(sum_s X_s[p] W1[c][s])            forward, recomputed
+//   (3) Ga^T[p][c]  = [H[c][p] > 0] sum_o gy[p - d_o] W2[c][o]  gradient at h
+//   (2) gW2^T[o][c] += sum_p gy[p - d_o] H[c][p]
+//   (4) gW1^T[s][c] += sum_p x_ci[p + d_o] Ga[c][p]
+// with X_s[p] = x_ci[p + d_o] and zero values outside the element.  (1) and
+// (3) are computed transposed, positions along the result rows: a lane then
+// holds one channel's results at 16 positions, which is the B operand that
+// (2) and (4) need in the same lane, the 16 positions taken as two K steps in
+// the lane's result-row order (a permutation of the summation index that the
+// A operand, gathered from LDS, follows).  x, H, gy and Ga enter the matrix
+// cores rounded to BF16; products are summed in FP32.
+// Tiles of 32 positions (8 along i, 4 along j, one k layer), 16 per element,
+// four per wave; workgroups are persistent over elements, each keeps its
+// gradient in the accumulators of its four waves and adds them (in wave
+// order) to its partial row at the end.
+namespace nnb {
+constexpr int GR = 10, GP = 100, GW = 1000;  // zero-bordered 10^3 grid of u16
+constexpr int XOFF = 0, GOFF = 2 * GW;       // x0, x1 grids, then gy
+constexpr int GRID_U16 = 3 * GW;
+constexpr int tdx(int o) { return o % 3 - 1; }
+constexpr int tdy(int o) { return (o / 3) % 3 - 1; }
+constexpr int tdz(int o) { return o / 9 - 1; }
+constexpr int toff(int o) { return o < 27 ? tdx(o) + GR * tdy(o) + GP * tdz(o) : 0; }
+}  // namespace nnb
+
+__global__ void __launch_bounds__(NN_THREADS)
+    nn_bwd_mfma_n8_kernel(const float* __restrict__ r, const float* __restrict__ dinv,
+                          const float* __restrict__ gzl, const bf16x8_t* __restrict__ pkb,
+                          float* __restrict__ part, int E) {
+  using namespace nnb;
+  constexpr int n3 = 512;
+  __shared__ unsigned short grid[GRID_U16];
+  __shared__ float red[48 * 64];
+  __shared__ float sred[8];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int h = lane >> 5, rl = lane & 31;
+  for (int q = tid; q < GRID_U16; q += NN_THREADS) grid[q] = 0;
+  // weight operands: W1^T (4 K steps) and W2^T (2), column = channel
+  bf16x8_t b1[4], b2[2];
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) b1[ks] = pkb[ks * 64 + lane];
+#pragma unroll
+  for (int ks = 0; ks < 2; ++ks) b2[ks] = pkb[(4 + ks) * 64 + lane];
+  floatx16_t g2 = {0}, g1a = {0}, g1b = {0};
+  for (int e = blockIdx.x; e < E; e += gridDim.x) {
+    const int64_t base = (int64_t)e * n3;
+    float rv[2], dv[2], ss = 0.f;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int p = tid + q * NN_THREADS;
+      rv[q] = r[base + p];
+      dv[q] = dinv[base + p] * rv[q];
+      ss += dv[q] * dv[q];
+    }
+    const float s = sqrtf(block_sum_bcast(ss, sred));  // barriers: the last element is done
+    const float inv = s > 0.f ? 1.f / s : 0.f;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int p = tid + q * NN_THREADS;
+      const int i = p & 7, j = (p >> 3) & 7, k = p >> 6;
+      const int gq = (k + 1) * GP + (j + 1) * GR + (i + 1);
+      grid[XOFF + gq] = float_to_bf16(rv[q] * inv);
+      grid[XOFF + GW + gq] = float_to_bf16(dv[q] * inv);
+      grid[GOFF + gq] = float_to_bf16(s * gzl[base + p]);
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int tq = 0; tq < 4; ++tq) {
+      const int t = wave + 4 * tq;
+      const int kk = t >> 1, j0 = 4 * (t & 1);
+      // (1) and (3): this lane's row is position (rl % 8, j0 + rl / 8, kk)
+      const int pc = (kk + 1) * GP + (j0 + (rl >> 3) + 1) * GR + (rl & 7) + 1;
+      floatx16_t a1 = {0}, a3 = {0};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        u32x4_t w;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          // slots 16 ks + 8 h + 2u, +1: channel ks / 2, taps (16 ks + 8 h + 2u) % 32, +1
+          const int o0 = (16 * ks + 2 * u) & 31, o1 = (16 * ks + 8 + 2 * u) & 31;
+          const int ci = ks >> 1;
+          const int fa = h ? toff(o1) : toff(o0), fb = h ? toff(o1 + 1) : toff(o0 + 1);
+          const unsigned lo = grid[XOFF + ci * GW + pc + fa];
+          const unsigned hi = grid[XOFF + ci * GW + pc + fb];
+          w[u] = lo | (hi << 16);
+        }
+        a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, w), b1[ks], a1,
+                                                      0, 0, 0);
+      }
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        u32x4_t w;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int o0 = 16 * ks + 2 * u, o1 = 16 * ks + 8 + 2 * u;
+          const int fa = h ? toff(o1) : toff(o0), fb = h ? toff(o1 + 1) : toff(o0 + 1);
+          const unsigned lo = grid[GOFF + pc - fa];
+          const unsigned hi = grid[GOFF + pc - fb];
+          w[u] = lo | (hi << 16);
+        }
+        a3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, w), b2[ks], a3,
+                                                      0, 0, 0);
+      }
+      // H = relu (BF16) and Ga = [H > 0] a3 (BF16), as B operands (K steps v < 8, v >= 8)
+      u32x4_t hb[2], gb[2];
+#pragma unroll
+      for (int v = 0; v < 16; v += 2) {
+        const unsigned h0 = a1[v] > 0.f ? float_to_bf16(a1[v]) : 0u;
+        const unsigned h1 = a1[v + 1] > 0.f ? float_to_bf16(a1[v + 1]) : 0u;
+        const unsigned q0 = h0 ? float_to_bf16(a3[v]) : 0u;
+        const unsigned q1 = h1 ? float_to_bf16(a3[v + 1]) : 0u;
+        hb[v >> 3][(v & 7) >> 1] = h0 | (h1 << 16);
+        gb[v >> 3][(v & 7) >> 1] = q0 | (q1 << 16);
+      }
+      // (2) and (4): this lane's row is tap rl (rows 27..31 are discarded);
+      // K index 8 h + u of step q <-> result row 8 (2q + u / 4) + 4 h + u % 4,
+      // i.e. position (4 h + u % 4, j0 + 2 q + u / 4, kk)
+      const int ob = toff(rl < 27 ? rl : 13);
+      const int pr = (kk + 1) * GP + (j0 + 1) * GR + 4 * h + 1;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        u32x4_t wg, wx0, wx1;
+#pragma unroll
+        for (int u = 0; u < 8; u += 2) {
+          const int c0 = pr + (2 * q + (u >> 2)) * GR + (u & 3);
+          const unsigned g0 = grid[GOFF + c0 - ob], g1 = grid[GOFF + c0 + 1 - ob];
+          const unsigned x00 = grid[XOFF + c0 + ob], x01 = grid[XOFF + c0 + 1 + ob];
+          const unsigned x10 = grid[XOFF + GW + c0 + ob], x11 = grid[XOFF + GW + c0 + 1 + ob];
+          wg[u >> 1] = g0 | (g1 << 16);
+          wx0[u >> 1] = x00 | (x01 << 16);
+          wx1[u >> 1] = x10 | (x11 << 16);
+        }
+        g2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, wg),
+                                                      __builtin_bit_cast(bf16x8_t, hb[q]), g2, 0, 0, 0);
+        g1a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, wx0),
+                                                       __builtin_bit_cast(bf16x8_t, gb[q]), g1a, 0, 0, 0);
+        g1b = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, wx1),
+                                                       __builtin_bit_cast(bf16x8_t, gb[q]), g1b, 0, 0, 0);
+      }
+    }
+  }
+  // the four waves' gradients, added in wave order
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        float* rr = red + v * 64 + lane;
+        rr[0] = (w ? rr[0] : 0.f) + g2[v];
+        rr[16 * 64] = (w ? rr[16 * 64] : 0.f) + g1a[v];
+        rr[32 * 64] = (w ? rr[32 * 64] : 0.f) + g1b[v];
+      }
+    }
+    __syncthreads();
+  }
+  float* pb = part + (int64_t)blockIdx.x * NN_NP;
+  for (int q = tid; q < 48 * 64; q += NN_THREADS) {
+    const int blk = q >> 10, v = (q >> 6) & 15, l = q & 63;
+    const int c = l & 31, o = 8 * (v >> 2) + 4 * (l >> 5) + (v & 3);
+    if (o >= 27) continue;
+    const float val = red[q];
+    if (blk == 0) pb[NN_W1 + c * 27 + o] += val;
+    else pb[c * 54 + (blk - 1) * 27 + o] += val;
+  }
+}
+
 // grad[i] = scale * sum_b part[b][i] (fixed order, FP64 accumulation)
 __global__ void nn_grad_reduce_kernel(const float* __restrict__ part, int nb, float scale,
                                       float* __restrict__ grad) {
@@ -821,15 +1000,21 @@ hipError_t launch_nn_fwd(int N, const float* r, const float* dinv, const uint8_t
 }
 
 hipError_t launch_nn_bwd(int N, const float* r, const float* dinv, const float* gzl,
-                         const float* W1, const float* W2, float* part, int nblocks, int E,
-                         hipStream_t s) {
+                         const float* W1, const float* W2, const void* packed, float* part,
+                         int nblocks, int E, hipStream_t s) {
+  if (N == 7) {
+    hipLaunchKernelGGL(nn_bwd_mfma_n8_kernel, dim3(nblocks), dim3(NN_THREADS), 0, s, r, dinv, gzl,
+                       (const bf16x8_t*)packed + 6 * 64, part, E);
+    return hipGetLastError();
+  }
+  // N = 3 and 5 (N = 7 takes the matrix-core kernel above)
   switch (N) {
 #define MX_NN(NN_)                                                                           \
   case NN_:                                                                                  \
     hipLaunchKernelGGL((nn_bwd_kernel<NN_>), dim3(nblocks), dim3(NN_THREADS), bwd_lds<NN_>(), \
                        s, r, dinv, gzl, W1, W2, part, E);                                    \
     break;
-    MX_NN(3) MX_NN(5) MX_NN(7)
+    MX_NN(3) MX_NN(5)
 #undef MX_NN
     default:
       return hipErrorInvalidValue;
@@ -846,7 +1031,7 @@ struct mxsem_nn {
   int cin = NN_CIN, ch = NN_CH;
   float *W = nullptr, *Wq = nullptr, *grad = nullptr, *mo = nullptr, *ve = nullptr;
   float* part = nullptr;  // [NN_BWD_BLOCKS][NN_NP]
-  void* packed = nullptr; // [6][64] BF16x8 weight operands of the matrix-core forward
+  void* packed = nullptr; // [12][64] BF16x8 weight operands of the matrix-core kernels
   float *z = nullptr, *d = nullptr, *Ad = nullptr, *g = nullptr;
   double* nd = nullptr;   // [2 * max samples] numerators / denominators
   double* dots = nullptr; // [5][dstride] per-workgroup flexible-CG dot partials of the forward
@@ -881,7 +1066,7 @@ static size_t nn_layout(const mxsem_mesh* m, int max_samples, mxsem_nn* nn, char
   put(ws ? &nn->ve : &f, sizeof(float) * NN_NP);
   put(ws ? &nn->part : &f, sizeof(float) * NN_NP * nbwd);
   put(ws ? &nn->dots : &dd, sizeof(double) * 5 * dstride);
-  put(ws ? &nn->packed : &v, 16 * 6 * 64);
+  put(ws ? &nn->packed : &v, 16 * 12 * 64);
   put(ws ? &nn->z : &f, sizeof(float) * nl);
   put(ws ? &nn->d : &f, sizeof(float) * nl);
   put(ws ? &nn->Ad : &f, sizeof(float) * nl);
@@ -963,7 +1148,7 @@ int mxsem_nn_create(mxsem_mesh* m, const mxsem_nn_desc* d, void* workspace, size
   hipStream_t s = m->ctx->stream;
   for (float* p : {nn->W, nn->Wq, nn->grad, nn->mo, nn->ve})
     hipLaunchKernelGGL(nn_fill_kernel, dim3(nb256(NN_NP)), dim3(256), 0, s, p, (int64_t)NN_NP, 0.f);
-  hipLaunchKernelGGL(nn_pack_kernel, dim3(1), dim3(6 * 64), 0, s, nn->Wq, nn->Wq + NN_W1,
+  hipLaunchKernelGGL(nn_pack_kernel, dim3(1), dim3(12 * 64), 0, s, nn->Wq, nn->Wq + NN_W1,
                      (bf16x8_t*)nn->packed);
   MX_HIP(hipGetLastError());
   MX_HIP(hipStreamSynchronize(s));
@@ -995,7 +1180,7 @@ int mxsem_nn_set_params(mxsem_nn* nn, const float* W1, const float* W2) {
   MX_HIP(hipMemcpyAsync(nn->W, W1, sizeof(float) * NN_W1, hipMemcpyHostToDevice, s));
   MX_HIP(hipMemcpyAsync(nn->W + NN_W1, W2, sizeof(float) * NN_W2, hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(nn_round_kernel, dim3(nb256(NN_NP)), dim3(256), 0, s, nn->W, nn->Wq);
-  hipLaunchKernelGGL(nn_pack_kernel, dim3(1), dim3(6 * 64), 0, s, nn->Wq, nn->Wq + NN_W1,
+  hipLaunchKernelGGL(nn_pack_kernel, dim3(1), dim3(12 * 64), 0, s, nn->Wq, nn->Wq + NN_W1,
                      (bf16x8_t*)nn->packed);
   for (float* p : {nn->mo, nn->ve})
     hipLaunchKernelGGL(nn_fill_kernel, dim3(nb256(NN_NP)), dim3(256), 0, s, p, (int64_t)NN_NP, 0.f);
@@ -1050,7 +1235,7 @@ int mxsem_nn_loss_grad(mxsem_nn* nn, const float* r, const float* e, int nsamp, 
     MX_HIP(launch_dot(MXSEM_F32, eq, nn->g, m->mult, nl, m->part, nn->nd + 2 * q + 1, s));
     hipLaunchKernelGGL(nn_gout_kernel, dim3(nb256(nl)), dim3(256), 0, s, nn->Ad, m->mult,
                        nn->nd + 2 * q + 1, nn->g, nl);
-    MX_HIP(launch_nn_bwd(m->N, rq, m->dinv32, nn->g, nn->Wq, nn->Wq + NN_W1, nn->part, nn->nbwd,
+    MX_HIP(launch_nn_bwd(m->N, rq, m->dinv32, nn->g, nn->Wq, nn->Wq + NN_W1, nn->packed, nn->part, nn->nbwd,
                          m->E, s));
   }
   hipLaunchKernelGGL(nn_grad_reduce_kernel, dim3(nb256(NN_NP)), dim3(256), 0, s, nn->part,
@@ -1073,7 +1258,7 @@ int mxsem_nn_adam_step(mxsem_nn* nn, const mxsem_adam* o) {
   hipLaunchKernelGGL(nn_adam_kernel, dim3(nb256(NN_NP)), dim3(256), 0, nn->mesh->ctx->stream,
                      nn->W, nn->Wq, nn->grad, nn->mo, nn->ve, (float)o->lr, (float)o->beta1,
                      (float)o->beta2, (float)o->eps, c1, c2);
-  hipLaunchKernelGGL(nn_pack_kernel, dim3(1), dim3(6 * 64), 0, nn->mesh->ctx->stream, nn->Wq,
+  hipLaunchKernelGGL(nn_pack_kernel, dim3(1), dim3(12 * 64), 0, nn->mesh->ctx->stream, nn->Wq,
                      nn->Wq + NN_W1, (bf16x8_t*)nn->packed);
   MX_HIP(hipGetLastError());
   return MXSEM_OK;

@@ -264,6 +264,11 @@ static void mesh_basics(mxsem_mesh* m, const mxsem_mesh_desc* d) {
   m->nloc = (int64_t)d->E * m->n3;
   m->helm_h = d->helm_h;
   m->views = d->views | MXSEM_VIEW_F64;
+  // the vector pass's box assembly indexes with shifts (n a power of two)
+  // and float quotients (E < 2^24), and a thread's four entries hold at most
+  // one x-face entry (n >= 8)
+  const bool pow2 = m->n == 8 || m->n == 16;
+  m->box_ne = (pow2 && d->E < (1 << 24)) ? box_lattice_ne(d) : 0;
 }
 
 // Gather-scatter plan on the host (a counting sort of the local entries by

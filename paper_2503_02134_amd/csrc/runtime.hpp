@@ -73,9 +73,11 @@ hipError_t launch_nn_fwd(int N, const float* r, const float* dinv, const uint8_t
                          const State* st, const void* packed, NnDots dd, int* nparts);
 // dm: DotMode of the dots (FP32 vectors; FP64 vectors take DOT_F64)
 // parity: -1 x += alpha p every step; 0 defers x (pending); 1 adds both
-// steps' alpha p
+// steps' alpha p.  asm_w: box-lattice problems (box_ne > 0) form QQ^T w and
+// the mask in this pass (their gather-scatter of w is left out of the step);
+// vprec VP_F64 or VP_F32 (FP64 sums).
 hipError_t launch_update(int vprec, int pc, const Tile* tiles, int ntiles, const ProbDev* probs,
-                         hipStream_t s, int dm = DOT_F64, int parity = -1);
+                         hipStream_t s, int dm = DOT_F64, int parity = -1, bool asm_w = false);
 // x += alpha_prev p for the problems whose last step left x pending
 hipError_t launch_x_pending(int vprec, const Tile* tiles, int ntiles, const ProbDev* probs,
                             hipStream_t s);
@@ -171,6 +173,8 @@ int mg_levels(int ne, int* nu);
 void mg_layout(mxsem_mesh* m, char* ws, Layout& L);
 // the box structure of a mesh description: MXSEM_OK or MXSEM_ENOTSUP
 int mg_check_box(const mxsem_mesh_desc* d);
+// ne of a box-lattice mesh (see mg.hip), else 0
+int box_lattice_ne(const mxsem_mesh_desc* d);
 // builds the preconditioner's data (after the operator data exist)
 int mg_setup(mxsem_mesh* m, const mxsem_mesh_desc* d, hipStream_t s);
 // z = M^-1 r (vprec VP_F64 or FP32 vectors); st: the solve's state (the
@@ -222,8 +226,10 @@ struct Plan {
   double* dnorm = nullptr;         // device [P] per-problem scalars
   double* hnorm = nullptr;         // pinned host [P]
   std::vector<AxClass> ax;
-  Tile* tiles_gs = nullptr;
+  Tile* tiles_gs = nullptr;   // every problem (z in flexible CG, the pairwise order)
   int nt_gs = 0;
+  Tile* tiles_gsw = nullptr;  // problems whose PCG step assembles w in the vector pass left out
+  int nt_gsw = 0;
   Tile* tiles_upd = nullptr;
   int nt_upd = 0;
   hipGraphExec_t graph = nullptr;
@@ -246,6 +252,9 @@ struct mxsem_mesh {
   mxsem_ctx* ctx = nullptr;
   int E = 0, N = 0, n = 0, n3 = 0;
   int64_t nloc = 0;
+  // box lattice with n = 8 or 16: elements per direction (the PCG step
+  // forms QQ^T w in the vector pass), else 0
+  int box_ne = 0;
   double helm_h = 0.0;
   unsigned views = 0;
   // device operator data

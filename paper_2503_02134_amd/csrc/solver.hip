@@ -155,10 +155,13 @@ void gs_tiles_by_xcd(const mxsem_mesh* m, int p, std::vector<std::vector<Tile>>&
 
 // The gather-scatter tile table of a plan: each problem's per-XCD lists,
 // interleaved so that workgroup b of a launch runs on XCD b % XCDS, padded
-// with empty tiles so that the alignment holds to the end.
-static void gs_table(mxsem_mesh* const* meshes, int P, std::vector<Tile>& tg) {
+// with empty tiles so that the alignment holds to the end.  w_only: the
+// table of the PCG step's gather-scatter of w, which leaves out box-lattice
+// problems (their vector pass assembles w).
+static void gs_table(mxsem_mesh* const* meshes, int P, std::vector<Tile>& tg, bool w_only = false) {
   std::vector<std::vector<Tile>> gsl(XCDS);
-  for (int p = 0; p < P; ++p) gs_tiles_by_xcd(meshes[p], p, gsl);
+  for (int p = 0; p < P; ++p)
+    if (!(w_only && meshes[p]->box_ne > 0)) gs_tiles_by_xcd(meshes[p], p, gsl);
   size_t len = 0;
   for (const auto& l : gsl) len = std::max(len, l.size());
   for (size_t i = 0; i < len; ++i)
@@ -166,8 +169,9 @@ static void gs_table(mxsem_mesh* const* meshes, int P, std::vector<Tile>& tg) {
 }
 
 size_t plan_table_bytes(mxsem_mesh* const* meshes, int P) {
-  std::vector<Tile> tg;
+  std::vector<Tile> tg, tgw;
   gs_table(meshes, P, tg);
+  gs_table(meshes, P, tgw, true);
   size_t ax = 0, upd = 0;
   for (int p = 0; p < P; ++p) {
     ax += (size_t)meshes[p]->E;  // at most one tile per element, whatever the tuning
@@ -176,6 +180,7 @@ size_t plan_table_bytes(mxsem_mesh* const* meshes, int P) {
   // one block per operator class (at most one class per problem), then the
   // gather-scatter and vector-pass tables, problem views, states and norms
   return sizeof(Tile) * ax + 256 * (size_t)(P + 1) + align256(sizeof(Tile) * (tg.size() + 1)) +
+         align256(sizeof(Tile) * (tgw.size() + 1)) +
          align256(sizeof(Tile) * (upd + 1)) + align256(sizeof(ProbDev) * P) +
          align256(sizeof(State) * P) + align256(sizeof(double) * P) + 256;
 }
@@ -194,7 +199,7 @@ int plan_build(mxsem_mesh* const* meshes, int P, int vprec, Region tables, Plan*
     plan_destroy(pl);
     return code;
   };
-  std::vector<Tile> tg, tu;
+  std::vector<Tile> tg, tgw, tu;
   pl->hprob.resize(P);
   for (int p = 0; p < P; ++p) {
     mxsem_mesh* m = meshes[p];
@@ -227,9 +232,14 @@ int plan_build(mxsem_mesh* const* meshes, int P, int vprec, Region tables, Plan*
     Q.nblk_ax = (m->E + pl->epb_used[p] - 1) / pl->epb_used[p];
     Q.nblk_gs = b->nt_gs;
     Q.nblk_upd = b->nt_upd;
+    Q.box_ne = m->box_ne;
+    Q.box_ln = m->n == 8 ? 3 : 4;
+    Q.box_rne = m->box_ne ? 1.0f / (float)m->box_ne : 0.f;
+    Q.box_rne2 = m->box_ne ? 1.0f / ((float)m->box_ne * (float)m->box_ne) : 0.f;
     for (int q = 0; q < b->nt_upd; ++q) tu.push_back(Tile{p, q * UPD_CHUNK, 0, 0});
   }
   gs_table(meshes, P, tg);
+  gs_table(meshes, P, tgw, true);
   // operator classes (N, tile size)
   std::vector<std::pair<int, int>> keys;
   for (int p = 0; p < P; ++p) {
@@ -260,8 +270,10 @@ int plan_build(mxsem_mesh* const* meshes, int P, int vprec, Region tables, Plan*
     pl->ax.push_back(ac);
   }
   pl->nt_gs = (int)tg.size();
+  pl->nt_gsw = (int)tgw.size();
   pl->nt_upd = (int)tu.size();
   if ((rc = plan_alloc(pl, (void**)&pl->tiles_gs, sizeof(Tile) * (tg.size() + 1))) != MXSEM_OK ||
+      (rc = plan_alloc(pl, (void**)&pl->tiles_gsw, sizeof(Tile) * (tgw.size() + 1))) != MXSEM_OK ||
       (rc = plan_alloc(pl, (void**)&pl->tiles_upd, sizeof(Tile) * (tu.size() + 1))) != MXSEM_OK ||
       (rc = plan_alloc(pl, (void**)&pl->probs, sizeof(ProbDev) * P)) != MXSEM_OK ||
       (rc = plan_alloc(pl, (void**)&pl->states, sizeof(State) * P)) != MXSEM_OK ||
@@ -270,6 +282,9 @@ int plan_build(mxsem_mesh* const* meshes, int P, int vprec, Region tables, Plan*
   for (int p = 0; p < P; ++p) pl->hprob[p].st = pl->states + p;
   if ((!tg.empty() &&
        hipMemcpy(pl->tiles_gs, tg.data(), sizeof(Tile) * tg.size(), hipMemcpyHostToDevice) !=
+           hipSuccess) ||
+      (!tgw.empty() &&
+       hipMemcpy(pl->tiles_gsw, tgw.data(), sizeof(Tile) * tgw.size(), hipMemcpyHostToDevice) !=
            hipSuccess) ||
       hipMemcpy(pl->tiles_upd, tu.data(), sizeof(Tile) * tu.size(), hipMemcpyHostToDevice) !=
           hipSuccess ||
@@ -302,10 +317,21 @@ int enqueue_ax(Plan* pl, int gprec, hipStream_t s, bool skip_first, int par = -1
   return MXSEM_OK;
 }
 
+// The rest of a PCG step after the operator: gather-scatter of w (with
+// sigma and alpha finished in the same launch), vector pass, rho/beta and
+// the convergence tests.  With FP64 vectors, box-lattice problems skip the
+// gather-scatter: their vector pass sums the copies itself, in the same
+// order, so the launch only finishes sigma for them (and sums the other
+// problems' copies).  On the 32^3, N = 7 mesh this took an FP64 step from
+// 101 + 174 us (gather-scatter + vector pass) to 12 + 227 us.  FP32 vectors
+// keep the separate gather-scatter: there the neighbour reads cost the
+// vector pass 25 us (80 -> 105 us) against 24 us saved (33.5 -> 9.1 us).
 static int enqueue_tail(Plan* pl, int pc, hipStream_t s, int par) {
-  MX_HIP(launch_gs_solver(pl->vprec, pl->tiles_gs, pl->nt_gs, pl->probs, s, false, pl->P, nullptr,
-                          0, pl->pairwise != 0));
-  MX_HIP(launch_update(pl->vprec, pc, pl->tiles_upd, pl->nt_upd, pl->probs, s, pl->dm, par));
+  const bool asm_w = !pl->pairwise && pl->vprec == VP_F64;
+  MX_HIP(launch_gs_solver(pl->vprec, asm_w ? pl->tiles_gsw : pl->tiles_gs,
+                          asm_w ? pl->nt_gsw : pl->nt_gs, pl->probs, s, false, pl->P, nullptr, 0,
+                          pl->pairwise != 0));
+  MX_HIP(launch_update(pl->vprec, pc, pl->tiles_upd, pl->nt_upd, pl->probs, s, pl->dm, par, asm_w));
   MX_HIP(launch_fin_rho(pl->probs, pl->P, 0, s));
   return MXSEM_OK;
 }

@@ -274,6 +274,156 @@ __device__ inline uchar4 ld_u8x4_nt(const uint8_t* src) {
   return m;
 }
 
+// Assembled w in the vector pass (box lattices, ProbDev::box_ne > 0).  The
+// PCG step of such a problem has no gather-scatter launch for w: the vector
+// pass forms QQ^T w and the Dirichlet mask from the operator's local w.  The
+// copies of a node are the entries of the elements that share it: along
+// each direction in which the node lies on an element face, the neighbour
+// across that face, at the opposite face coordinate.  They are summed in
+// FP64 in ascending local index, i.e. ascending element, which is the
+// lexicographic order of the element offsets (dz, dy, dx) -- the order in
+// which the gather-scatter kernel sums the node's group -- and rounded once,
+// so every copy gets the same value and the iterates are bitwise those of
+// the separate gather-scatter.  A thread's four entries i0..i0+3 lie in one
+// row of one element (n = 8 or 16): the row's copies across y and z faces
+// are whole rows (one 4-wide load each), and an x face adds one entry per
+// such row at the row's first or last slot (never both: n >= 8).
+//
+// The index work, the loads and the sums of the assembly are split so that
+// the vector pass can issue every load of a thread (its own streams and the
+// neighbours') before it waits for any: BoxRows holds the clamped addresses
+// (a copy that is not needed reads the thread's own row, which is valid) and
+// the options, box_load issues the loads, box_sum forms the sums.
+struct BoxRows {
+  int64_t rs, ry, rz, ryz;  // entry a = 0 of the row in this element, across y, z, both
+  int xoff;                 // offset of the x-face copy from a row's entry a = 0
+  int a0;
+  bool dir_row, xlo, xhi, xlo_dir, xhi_dir;
+  bool hy, hz, ylo, zlo;    // copies across y / z faces; the neighbour is the lower one
+};
+template <typename VT, typename T>
+struct BoxVals {
+  typedef T E4 __attribute__((ext_vector_type(4)));
+  E4 ry, rz, ryz;
+  T xs, xy, xz, xyz;
+};
+// box == false (a problem that is not a box lattice, in a launch that
+// assembles the others): every address is the thread's own entries, and
+// box_sum returns the thread's own values
+__device__ inline BoxRows box_rows(uint32_t i0, const ProbDev& P, bool box) {
+  BoxRows R;
+  const int ln = P.box_ln, n = 1 << ln, N = n - 1, ne = P.box_ne;
+  const uint32_t e = i0 >> (3 * ln);
+  const int node = (int)(i0 & ((1u << (3 * ln)) - 1u));
+  const int a0 = node & N, row = node >> ln;
+  const int b = row & N, c = row >> ln;
+  // (ex, ey, ez) of e: quotients by a float reciprocal, corrected by one
+  // step (e < 2^24, so the product is off by less than one)
+  const int ne2 = ne * ne;
+  int ez = (int)((float)e * P.box_rne2);
+  ez -= ez * ne2 > (int)e;
+  ez += (ez + 1) * ne2 <= (int)e;
+  const int rem = (int)e - ez * ne2;
+  int ey = (int)((float)rem * P.box_rne);
+  ey -= ey * ne > rem;
+  ey += (ey + 1) * ne <= rem;
+  const int ex = rem - ey * ne;
+  const int GL = ne * N;  // lattice index of the far boundary
+  const int gy = ey * N + b, gz = ez * N + c, gx0 = ex * N + a0;
+  R.a0 = a0;
+  R.dir_row = gy == 0 || gy == GL || gz == 0 || gz == GL;
+  R.xlo = a0 == 0;
+  R.xhi = a0 + 3 == N;
+  R.xlo_dir = R.xlo && gx0 == 0;
+  R.xhi_dir = R.xhi && gx0 + 3 == GL;
+  R.ylo = b == 0;
+  R.zlo = c == 0;
+  R.hy = !R.dir_row && (b == 0 || b == N);
+  R.hz = !R.dir_row && (c == 0 || c == N);
+  const int dy = R.ylo ? -1 : 1, cy = R.ylo ? N : 0;
+  const int dz = R.zlo ? -1 : 1, cz = R.zlo ? N : 0;
+  const int64_t n3 = (int64_t)1 << (3 * ln);
+  R.rs = (int64_t)i0 - a0;
+  const int64_t ey_e = (int64_t)e + dy * ne, ez_e = (int64_t)e + (int64_t)dz * ne2;
+  const int64_t eyz_e = ez_e + dy * ne;
+  R.ry = R.hy ? (ey_e << (3 * ln)) + ((int64_t)(cy + (c << ln)) << ln) : R.rs;
+  R.rz = R.hz ? (ez_e << (3 * ln)) + ((int64_t)(b + (cz << ln)) << ln) : R.rs;
+  R.ryz = (R.hy && R.hz) ? (eyz_e << (3 * ln)) + ((int64_t)(cy + (cz << ln)) << ln) : R.rs;
+  const bool xl = R.xlo && !R.xlo_dir, xh = R.xhi && !R.xhi_dir;
+  R.xoff = xl ? (int)(N - n3) : xh ? (int)n3 : a0;
+  if (!box) {  // box_sum then returns the thread's own values
+    R.rs = R.ry = R.rz = R.ryz = i0;
+    R.a0 = 0;
+    R.xoff = 0;
+    R.dir_row = R.xlo = R.xhi = R.xlo_dir = R.xhi_dir = R.hy = R.hz = false;
+  }
+  return R;
+}
+template <typename T, typename VT>
+__device__ inline void box_load(const gptr<const T> __restrict__ w, const BoxRows& R,
+                                BoxVals<VT, T>& V) {
+  typedef typename BoxVals<VT, T>::E4 E4;
+  V.ry = *((const E4*)&w[R.ry + R.a0]);
+  V.rz = *((const E4*)&w[R.rz + R.a0]);
+  V.ryz = *((const E4*)&w[R.ryz + R.a0]);
+  V.xs = w[R.rs + R.xoff];
+  V.xy = w[R.ry + R.xoff];
+  V.xz = w[R.rz + R.xoff];
+  V.xyz = w[R.ryz + R.xoff];
+}
+// One copy's row in the running sums: its entries at the four slots and its
+// x-face entry (added before slot 0 or after slot 3); first: the node's
+// first copy (the sums start from it).
+template <typename T>
+__device__ inline void box_add(bool on, bool first, bool xl, bool xh, T r0, T r1, T r2, T r3,
+                               T xv, double& s0, double& s1, double& s2, double& s3) {
+  double t0 = (double)r0;
+  if (xl) t0 = (first ? (double)xv : s0 + (double)xv) + t0;
+  else t0 = first ? t0 : s0 + t0;
+  const double t1 = first ? (double)r1 : s1 + (double)r1;
+  const double t2 = first ? (double)r2 : s2 + (double)r2;
+  double t3 = first ? (double)r3 : s3 + (double)r3;
+  if (xh) t3 += (double)xv;
+  s0 = on ? t0 : s0;
+  s1 = on ? t1 : s1;
+  s2 = on ? t2 : s2;
+  s3 = on ? t3 : s3;
+}
+// wv: the thread's own four local values on entry, the assembled ones on return
+template <typename T, typename VT>
+__device__ inline void box_sum(const BoxRows& R, const BoxVals<VT, T>& V, VT& wv) {
+  if (R.dir_row) {
+    wv.x = T(0), wv.y = T(0), wv.z = T(0), wv.w = T(0);
+    return;
+  }
+  const T w0 = wv.x, w1 = wv.y, w2 = wv.z, w3 = wv.w;
+  const bool xl = R.xlo && !R.xlo_dir, xh = R.xhi && !R.xhi_dir;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  // rows in ascending element order, (dz, dy) lexicographic: the lower
+  // neighbour before this element, the upper one after; at each position one
+  // of the four rows (this element's, across y, across z, across both)
+#pragma unroll
+  for (int qz = 0; qz < 2; ++qz)
+#pragma unroll
+    for (int qy = 0; qy < 2; ++qy) {
+      const bool zn = R.hz && (R.zlo ? qz == 0 : qz == 1);
+      const bool yn = R.hy && (R.ylo ? qy == 0 : qy == 1);
+      const bool take = (qz == 0 || R.hz) && (qy == 0 || R.hy);
+      const bool first = qz == 0 && qy == 0;
+      box_add<T>(take && !zn && !yn, first, xl, xh, w0, w1, w2, w3, V.xs, s0, s1, s2, s3);
+      box_add<T>(take && !zn && yn, first, xl, xh, V.ry.x, V.ry.y, V.ry.z, V.ry.w, V.xy, s0, s1,
+                 s2, s3);
+      box_add<T>(take && zn && !yn, first, xl, xh, V.rz.x, V.rz.y, V.rz.z, V.rz.w, V.xz, s0, s1,
+                 s2, s3);
+      box_add<T>(take && zn && yn, first, xl, xh, V.ryz.x, V.ryz.y, V.ryz.z, V.ryz.w, V.xyz, s0,
+                 s1, s2, s3);
+    }
+  wv.x = R.xlo_dir ? T(0) : (T)s0;
+  wv.y = (T)s1;
+  wv.z = (T)s2;
+  wv.w = R.xhi_dir ? T(0) : (T)s3;
+}
+
 // PC: 0 identity, 1 Jacobi, -1 none (z left alone; flexible CG computes it)
 // x += alpha p; r -= alpha w; z = M^-1 r; partials (r,z)_c and (r,r)_c.
 // Each thread handles UPD_PER_THREAD entries as 4-wide vectors when the
@@ -284,7 +434,9 @@ __device__ inline uchar4 ld_u8x4_nt(const uint8_t* src) {
 // alpha as pending, 1 (odd step) adds alpha_prev p (the even step's
 // direction, in p) and then alpha p_alt: the same two roundings, in the same
 // order, as two steps of the first form.
-template <typename T, int DM, int PC>
+// ASM: box-lattice problems assemble w here (box_rows / box_load /
+// box_sum); the others read the w their gather-scatter launch assembled.
+template <typename T, int DM, int PC, bool ASM>
 __global__ void __launch_bounds__(UPD_THREADS) update_kernel(const Tile* __restrict__ tiles,
                                                              const ProbDev* __restrict__ probs,
                                                              int par) {
@@ -309,11 +461,21 @@ __global__ void __launch_bounds__(UPD_THREADS) update_kernel(const Tile* __restr
   const gptr<const T> __restrict__ dinv = gcast((const T*)P.dinv);
   const gptr<const uint8_t> __restrict__ mult = gcast(P.mult);
   DotAcc<DM> rz, rr;
+  const bool asm_box = ASM && P.box_ne > 0;
   if ((P.nloc & 3) == 0) {
     typedef typename V4<T>::type VT;
 #pragma unroll
     for (int q = 0; q < UPD_PER_THREAD / 4; ++q) {
       const int64_t v = (int64_t)t.first / 4 + q * UPD_THREADS + threadIdx.x;
+      // box assembly: the neighbour loads issued beside the thread's own,
+      // with no branch around them (a copy that is not needed, or an entry
+      // past the end, reads a valid address of the thread's own)
+      BoxRows br;
+      BoxVals<VT, T> bv;
+      if constexpr (ASM) {
+        br = box_rows((uint32_t)(4 * (4 * v < P.nloc ? v : 0)), P, asm_box);
+        box_load<T, VT>(w, br, bv);
+      }
       if (4 * v < P.nloc) {
         VT rv = ld4_nt<VT>((const T*)&((const VT*)r)[v]), wv = ((const VT*)w)[v];
         const uchar4 mv = ld_u8x4_nt((const uint8_t*)&((const uchar4*)mult)[v]);
@@ -328,6 +490,8 @@ __global__ void __launch_bounds__(UPD_THREADS) update_kernel(const Tile* __restr
           xv.x += alpha * pv.x; xv.y += alpha * pv.y; xv.z += alpha * pv.z; xv.w += alpha * pv.w;
           st4_nt<VT>((T*)&((VT*)x)[v], xv);
         }
+        // (the identity for a problem that is not a box lattice)
+        if constexpr (ASM) box_sum<T, VT>(br, bv, wv);
         rv.x -= alpha * wv.x; rv.y -= alpha * wv.y; rv.z -= alpha * wv.z; rv.w -= alpha * wv.w;
         st4_nt<VT>((T*)&((VT*)r)[v], rv);
         const double c0 = cweight(mv.x), c1 = cweight(mv.y), c2 = cweight(mv.z),
@@ -802,27 +966,37 @@ hipError_t launch_gs_solver(int vprec, const Tile* tiles, int ntiles, const Prob
   return hipGetLastError();
 }
 
+template <typename T, int DM, bool ASM>
+static void upd_dispatch2(int pc, dim3 g, dim3 b, hipStream_t s, const Tile* tiles,
+                          const ProbDev* probs, int par) {
+  if (pc == MXSEM_PC_JACOBI)
+    hipLaunchKernelGGL((update_kernel<T, DM, 1, ASM>), g, b, 0, s, tiles, probs, par);
+  else if (pc == MXSEM_PC_IDENTITY)
+    hipLaunchKernelGGL((update_kernel<T, DM, 0, ASM>), g, b, 0, s, tiles, probs, par);
+  else
+    hipLaunchKernelGGL((update_kernel<T, DM, -1, ASM>), g, b, 0, s, tiles, probs, par);
+}
 template <typename T, int DM>
 static void upd_dispatch(int pc, dim3 g, dim3 b, hipStream_t s, const Tile* tiles,
-                         const ProbDev* probs, int par) {
-  if (pc == MXSEM_PC_JACOBI)
-    hipLaunchKernelGGL((update_kernel<T, DM, 1>), g, b, 0, s, tiles, probs, par);
-  else if (pc == MXSEM_PC_IDENTITY)
-    hipLaunchKernelGGL((update_kernel<T, DM, 0>), g, b, 0, s, tiles, probs, par);
+                         const ProbDev* probs, int par, int asm_w) {
+  if (asm_w)
+    upd_dispatch2<T, DM, true>(pc, g, b, s, tiles, probs, par);
   else
-    hipLaunchKernelGGL((update_kernel<T, DM, -1>), g, b, 0, s, tiles, probs, par);
+    upd_dispatch2<T, DM, false>(pc, g, b, s, tiles, probs, par);
 }
 
 // dm: DotMode of the dots (FP64 vectors: DOT_F64 only)
 hipError_t launch_update(int vprec, int pc, const Tile* tiles, int ntiles, const ProbDev* probs,
-                         hipStream_t s, int dm, int par) {
+                         hipStream_t s, int dm, int par, bool asm_w) {
   dim3 g(ntiles), b(UPD_THREADS);
   if (vprec == 0 && dm != DOT_F64) return hipErrorInvalidValue;
   if (par < -1 || par > 1) return hipErrorInvalidValue;
-  if (vprec == 0) upd_dispatch<double, DOT_F64>(pc, g, b, s, tiles, probs, par);
-  else if (dm == DOT_F64) upd_dispatch<float, DOT_F64>(pc, g, b, s, tiles, probs, par);
-  else if (dm == DOT_F32) upd_dispatch<float, DOT_F32>(pc, g, b, s, tiles, probs, par);
-  else if (dm == DOT_DOT2) upd_dispatch<float, DOT_DOT2>(pc, g, b, s, tiles, probs, par);
+  if (asm_w && vprec != 0 && vprec != 1) return hipErrorInvalidValue;  // FP64 sums only
+  const int aw = asm_w ? 1 : 0;
+  if (vprec == 0) upd_dispatch<double, DOT_F64>(pc, g, b, s, tiles, probs, par, aw);
+  else if (dm == DOT_F64) upd_dispatch<float, DOT_F64>(pc, g, b, s, tiles, probs, par, aw);
+  else if (dm == DOT_F32) upd_dispatch<float, DOT_F32>(pc, g, b, s, tiles, probs, par, aw);
+  else if (dm == DOT_DOT2) upd_dispatch<float, DOT_DOT2>(pc, g, b, s, tiles, probs, par, aw);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

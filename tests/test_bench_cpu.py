@@ -44,3 +44,27 @@ def test_oracle_leg_on_a_small_workload():
     assert errs["cpu_solution_1e-10"] < 1e-8 and errs["same"] == errs["cpu_solution_1e-10"]
     assert abs(errs["perturbed"] - 1e-6) < 1e-7
     assert "1e-13" in errs["reference"]
+
+
+def test_batch_oracle_errors():
+    """The batch leg's oracle check: one problem of each order on 8^3
+    elements, each solution's error against the oracle's 1e-13 solution of
+    that problem (the oracle's own 1e-10 solution is close, a perturbed one
+    is off by the perturbation)."""
+    sys.path.insert(0, ROOT)
+    import oracle
+
+    import bench
+    from paper_2503_02134_amd import workloads as W
+    picked = bench.batch_oracle_problems()
+    draws = W.batch_draws()
+    assert sorted(draws[p][1] for p in picked) == [5, 7, 9]
+    assert all(draws[p][0] == 8 for p in picked)
+    p = picked[1]
+    ne, N, seed = draws[p]
+    xo, _ = oracle.gll(N)
+    bm = W.box_mesh(ne, N, xo)
+    om = oracle.Mesh(bm.E, N, bm.xyz, bm.glo, bm.bnd)
+    x10, _ = om.pcg(om.rhs(W.random_smooth_rhs(bm, seed)), tol=1e-10, maxit=5000)
+    errs = bench.batch_oracle_errors({p: x10 * (1 + 1e-6)})
+    assert abs(errs[f"problem_{p}_ne{ne}_N{N}"] - 1e-6) < 1e-7

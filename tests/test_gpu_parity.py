@@ -203,6 +203,41 @@ def test_fp64_same_iterates(orc, mx, ctx, maxit, chunk):
     assert rel_l2(xg.cpu().numpy(), xo) <= 1e-12
 
 
+@pytest.mark.parametrize("mode", ["MODE_FP64", "MODE_MIXED"])
+@pytest.mark.parametrize("N,ne,chunk,helm", [(7, 4, 8, 0.0), (7, 3, 5, 1.0), (3, 5, 4, 0.0),
+                                              (15, 2, 6, 0.0)])
+def test_box_assembly_equals_gather_scatter(orc, mx, ctx, N, ne, chunk, helm, mode):
+    """Box lattices of order N = 7 or 15 form QQ^T w in the vector pass of
+    the PCG step (FP64 vectors, and FP32 vectors with FP64 sums) instead of a
+    gather-scatter launch.  The same mesh with its
+    global ids relabelled by a random bijection (the same copies, no longer a
+    lattice) takes the gather-scatter; both sum a node's copies in FP64 in
+    ascending local index, so the iterates are bitwise equal (one and two
+    direction buffers: odd and even graph chunks).  N = 3 (n = 4) is not
+    assembled in the vector pass and checks the two gather-scatter routes
+    alike.  The oracle's iterates after the same number of steps agree to
+    rounding."""
+    maxit = 37
+    log(f"{mode} box assembly vs gather-scatter, ne={ne} N={N} chunk={chunk} h={helm}")
+    bmg, gm, bmo, om, fg, fo = make_pair(orc, mx, ctx, ne, N, seed=4, helm_h=helm, rhs="random",
+                                         rhs_seed=8)
+    g = np.asarray(bmg.glo).reshape(-1)
+    relabel = np.random.default_rng(1).permutation(int(g.max()) + 1)
+    glo2 = relabel[g].reshape(np.asarray(bmg.glo).shape)
+    gm2 = mx.Mesh(ctx, bmg.E, N, bmg.xyz, glo2, bmg.bnd, helm_h=helm)
+    b = gm.mass_rhs(_t(fg))
+    md = getattr(mx, mode)
+    xa, sa = gm.solve(b, mode=md, tol=0.0, max_iter=maxit, graph_chunk=chunk)
+    xb, sb = gm2.solve(b, mode=md, tol=0.0, max_iter=maxit, graph_chunk=chunk)
+    assert sa.iterations == sb.iterations == maxit
+    assert torch.equal(xa, xb)
+    xo, _ = om.pcg(om.rhs(fo), tol=0.0, maxit=maxit)
+    # FP32 loop: the iterates of the FP32-rounded operator
+    assert rel_l2(xa.cpu().numpy(), xo) <= (1e-12 if mode == "MODE_FP64" else 1e-4)
+    gm2.close()
+    gm.close()
+
+
 @pytest.mark.parametrize("mode,bound", [("MODE_MIXED_IR", 1e-8), ("MODE_MIXED_IR_BF16G", 1e-8),
                                         ("MODE_MIXED_IR_BF16P", 1e-8), ("MODE_FP64", 1e-8)])
 def test_mixed_modes_reach_oracle_solution(orc, mx, ctx, mode, bound):
