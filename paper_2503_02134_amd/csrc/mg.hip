@@ -468,9 +468,30 @@ int mg_setup(mxsem_mesh* m, const mxsem_mesh_desc* d, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ apply kernels
+// Synchronisation of the element's threads around the LDS exchanges: when
+// the element's n^2 threads are one wave (n^2 divides 64), LDS operations of
+// the wave complete in order and a compiler-level wave barrier suffices;
+// otherwise a workgroup barrier.
+template <int n2>
+__device__ inline void mg_sync() {
+  if constexpr (64 % n2 == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // Schwarz part and restriction.  One element per workgroup (n^2 column
 // threads, rounded up to whole waves); z_e = ws * S diag(1/Lambda) S^T
-// (ws * r_e), corner[e][a] = sum_node J3[node][a] c r (FP64).
+// (ws * r_e), corner[e][a] = sum_node J3[node][a] c r (FP64).  The column's
+// r and copy counts are loaded first; the element's Sx and Sy are staged in
+// LDS (each thread reads the rows and columns it needs there), while Sz and
+// the restriction weights J are the same for every lane and are read from
+// global memory as scalars (they stay out of the vector registers, which
+// keeps several waves per SIMD).  The z direction is register-only, the x and
+// y contractions exchange the element's values through LDS.
 template <typename T, int N>
 __global__ void __launch_bounds__(256)
     mg_schwarz_kernel(const T* __restrict__ r, T* __restrict__ z, const uint8_t* __restrict__ mult,
@@ -480,35 +501,38 @@ __global__ void __launch_bounds__(256)
                       const State* __restrict__ st) {
   constexpr int n = N + 1, n2 = n * n, n3 = n2 * n;
   __shared__ T buf[n3];
-  __shared__ T sS[3 * n2];
+  __shared__ T sS[2 * n2];
   __shared__ T sl[3 * n];
-  __shared__ double sJ[2 * n];
   const int e = blockIdx.x;
   if (e >= E || (st && gcast(st)->done)) return;
   const int tid = threadIdx.x;
-  for (int q = tid; q < 3 * n2; q += blockDim.x) sS[q] = S[(int64_t)e * 3 * n2 + q];
-  for (int q = tid; q < 3 * n; q += blockDim.x) sl[q] = lam[(int64_t)e * 3 * n + q];
-  for (int q = tid; q < 2 * n; q += blockDim.x) sJ[q] = J[q];
   const bool act = tid < n2;
   const int i = act ? tid % n : 0, j = act ? tid / n : 0;
   const int64_t base = (int64_t)e * n3 + i + n * j;
-  T v[n];
-  double c0 = 0.0, c1 = 0.0;  // sum_k J_k0 c r, sum_k J_k1 c r along this column
+  const T* __restrict__ Se = S + (int64_t)e * 3 * n2;
+  const T* __restrict__ Sz = Se + 2 * n2;  // uniform: scalar loads
+  T rv[n];
   uint8_t mk[n];
-  __syncthreads();
 #pragma unroll
   for (int k = 0; k < n; ++k) {
     mk[k] = act ? mult[base + k * n2] : (uint8_t)1;
-    const T rv = act ? r[base + k * n2] : T(0);
-    v[k] = ws[mk[k]] * rv;
-    const double cr = (double)rv * cweight(mk[k]);
-    c0 += sJ[2 * k] * cr;
-    c1 += sJ[2 * k + 1] * cr;
+    rv[k] = act ? r[base + k * n2] : T(0);
   }
-  // forward transform: contract k (registers), then j and i (LDS)
+  for (int q = tid; q < 2 * n2; q += blockDim.x) sS[q] = Se[q];
+  for (int q = tid; q < 3 * n; q += blockDim.x) sl[q] = lam[(int64_t)e * 3 * n + q];
+  __syncthreads();
   const T* Sx = sS;
   const T* Sy = sS + n2;
-  const T* Sz = sS + 2 * n2;
+  T v[n];
+  double c0 = 0.0, c1 = 0.0;  // sum_k J_k0 c r, sum_k J_k1 c r along this column
+#pragma unroll
+  for (int k = 0; k < n; ++k) {
+    v[k] = ws[mk[k]] * rv[k];
+    const double cr = (double)rv[k] * cweight(mk[k]);
+    c0 += J[2 * k] * cr;
+    c1 += J[2 * k + 1] * cr;
+  }
+  // forward transform: contract k (registers), then j and i (LDS)
   T u[n];
 #pragma unroll
   for (int kk = 0; kk < n; ++kk) {
@@ -520,7 +544,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
   for (int k = 0; k < n; ++k)
     if (act) buf[k * n2 + j * n + i] = u[k];
-  __syncthreads();
+  mg_sync<n2>();
 #pragma unroll
   for (int k = 0; k < n; ++k) {
     T a = T(0);
@@ -528,11 +552,11 @@ __global__ void __launch_bounds__(256)
     for (int q = 0; q < n; ++q) a += Sy[q * n + j] * buf[k * n2 + q * n + i];
     v[k] = a;
   }
-  __syncthreads();
+  mg_sync<n2>();
 #pragma unroll
   for (int k = 0; k < n; ++k)
     if (act) buf[k * n2 + j * n + i] = v[k];
-  __syncthreads();
+  mg_sync<n2>();
   const double kb = kbar[e];
 #pragma unroll
   for (int k = 0; k < n; ++k) {
@@ -542,12 +566,12 @@ __global__ void __launch_bounds__(256)
     const T den = (T)(kb * (double)(sl[i] + sl[n + j] + sl[2 * n + k]) + h);
     u[k] = a / den;
   }
-  __syncthreads();
+  mg_sync<n2>();
   // back transform: i and j (LDS), then k (registers)
 #pragma unroll
   for (int k = 0; k < n; ++k)
     if (act) buf[k * n2 + j * n + i] = u[k];
-  __syncthreads();
+  mg_sync<n2>();
 #pragma unroll
   for (int k = 0; k < n; ++k) {
     T a = T(0);
@@ -555,11 +579,11 @@ __global__ void __launch_bounds__(256)
     for (int q = 0; q < n; ++q) a += Sx[i * n + q] * buf[k * n2 + j * n + q];
     v[k] = a;
   }
-  __syncthreads();
+  mg_sync<n2>();
 #pragma unroll
   for (int k = 0; k < n; ++k)
     if (act) buf[k * n2 + j * n + i] = v[k];
-  __syncthreads();
+  mg_sync<n2>();
 #pragma unroll
   for (int k = 0; k < n; ++k) {
     T a = T(0);
@@ -579,7 +603,7 @@ __global__ void __launch_bounds__(256)
   double cc[8];
 #pragma unroll
   for (int a = 0; a < 8; ++a)
-    cc[a] = act ? sJ[2 * i + (a & 1)] * sJ[2 * j + ((a >> 1) & 1)] * ((a >> 2) ? c1 : c0) : 0.0;
+    cc[a] = act ? J[2 * i + (a & 1)] * J[2 * j + ((a >> 1) & 1)] * ((a >> 2) ? c1 : c0) : 0.0;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
