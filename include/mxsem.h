@@ -319,6 +319,10 @@ void mxsem_solve_opts_default(mxsem_solve_opts *opts);
 typedef struct {
   int epb[16];        /* elements per workgroup of the operator kernel per N
                          (0 = library default)                              */
+  int cols[16];       /* thread mapping of the operator kernel per N: 0 =
+                         library default, 1 = one (i,j) column per thread,
+                         2 = two columns per thread (N = 5 and 9 with FP32
+                         vectors; FP64 vectors take one column)             */
 } mxsem_tuning;
 
 /* Bytes of device workspace mxsem_batch_create needs: the launch tables of
@@ -346,10 +350,12 @@ int mxsem_batch_solve(mxsem_batch *batch, const mxsem_solve_opts *opts,
 int mxsem_autotune_workspace_bytes(int N, int E, mxsem_prec prec, size_t *bytes);
 /* Time the candidate tiles of the operator kernel for one (N, E, prec) on
  * the context's device, on synthetic data in the caller's workspace, and
- * return the fastest (epb[N]).  Synchronous. */
+ * return the fastest (epb[N], cols[N]): every tile size, with both thread
+ * mappings where two exist (N = 5, 9 with FP32 vectors).  Synchronous. */
 int mxsem_autotune(mxsem_ctx *ctx, int N, int E, mxsem_prec prec, void *workspace,
                    size_t ws_bytes, mxsem_tuning *out);
-/* Tiles the library will use for a mesh (after any tuning). */
+/* Tiles and thread mapping the library will use for a mesh (after any
+ * tuning); EINVAL for a tile that does not fit its mapping's workgroup. */
 int mxsem_mesh_set_tuning(mxsem_mesh *mesh, const mxsem_tuning *t);
 
 /* ---- learned preconditioner ------------------------------------------------ */

@@ -454,20 +454,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
 // so the elapsed time between them is the kernel's execution time.
 template <int N, typename T, typename TG, bool SOLVER, int DM, bool PB>
 static hipError_t launch_one(const Tile* tiles, const ProbDev* probs, const AxApplyArgs& a,
-                             int ntiles, int epb, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                             int ntiles, int epb, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
+                             int cols) {
   constexpr int n = N + 1, n2 = n * n;
   if constexpr (two_col<N, T>()) {
-    constexpr int EPW = ax2_epw<N>();
-    const int waves = (epb + EPW - 1) / EPW;
-    if (epb < 1 || waves > 4) return hipErrorInvalidConfiguration;
-    const size_t shm = sizeof(T) * (n2 + (size_t)waves * EPW * 3 * n2);
-    if (ev0)
-      hipExtLaunchKernelGGL((ax2_kernel<N, T, TG, SOLVER, DM, PB>), dim3(ntiles), dim3(64 * waves),
-                            (uint32_t)shm, s, ev0, ev1, 0, tiles, probs, a, epb);
-    else
-      hipLaunchKernelGGL((ax2_kernel<N, T, TG, SOLVER, DM, PB>), dim3(ntiles), dim3(64 * waves), shm, s,
-                         tiles, probs, a, epb);
-    return hipGetLastError();
+    if (cols != 1) {  // two columns per thread unless one is asked for
+      constexpr int EPW = ax2_epw<N>();
+      const int waves = (epb + EPW - 1) / EPW;
+      if (epb < 1 || waves > 4) return hipErrorInvalidConfiguration;
+      const size_t shm = sizeof(T) * (n2 + (size_t)waves * EPW * 3 * n2);
+      if (ev0)
+        hipExtLaunchKernelGGL((ax2_kernel<N, T, TG, SOLVER, DM, PB>), dim3(ntiles),
+                              dim3(64 * waves), (uint32_t)shm, s, ev0, ev1, 0, tiles, probs, a,
+                              epb);
+      else
+        hipLaunchKernelGGL((ax2_kernel<N, T, TG, SOLVER, DM, PB>), dim3(ntiles), dim3(64 * waves),
+                           shm, s, tiles, probs, a, epb);
+      return hipGetLastError();
+    }
   }
   int threads = ((epb * n2 + 63) / 64) * 64;
   if (epb < 1 || threads > 256) return hipErrorInvalidConfiguration;
@@ -483,12 +487,12 @@ static hipError_t launch_one(const Tile* tiles, const ProbDev* probs, const AxAp
 
 template <typename T, typename TG, bool SOLVER, int DM = DOT_F64, bool PB = false>
 static hipError_t dispatch(int N, const Tile* tiles, const ProbDev* probs, const AxApplyArgs& a,
-                           int ntiles, int epb, hipStream_t s, hipEvent_t ev0 = nullptr,
-                           hipEvent_t ev1 = nullptr) {
+                           int ntiles, int epb, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
+                           int cols) {
   switch (N) {
 #define MX_CASE(NN) \
   case NN:          \
-    return launch_one<NN, T, TG, SOLVER, DM, PB>(tiles, probs, a, ntiles, epb, s, ev0, ev1);
+    return launch_one<NN, T, TG, SOLVER, DM, PB>(tiles, probs, a, ntiles, epb, s, ev0, ev1, cols);
     MX_CASE(1) MX_CASE(2) MX_CASE(3) MX_CASE(4) MX_CASE(5) MX_CASE(6) MX_CASE(7) MX_CASE(8)
     MX_CASE(9) MX_CASE(10) MX_CASE(11) MX_CASE(12) MX_CASE(13) MX_CASE(14) MX_CASE(15)
 #undef MX_CASE
@@ -499,13 +503,13 @@ static hipError_t dispatch(int N, const Tile* tiles, const ProbDev* probs, const
 
 // prec: 0 FP64/FP64, 1 FP32/FP32, 2 FP32 vectors with BF16 G
 hipError_t launch_ax_apply(int prec, int N, int E, int epb, const void* u, void* w,
-                           const void* G, const void* hB, const void* D, hipStream_t s) {
+                           const void* G, const void* hB, const void* D, hipStream_t s, int cols) {
   AxApplyArgs a{u, w, G, hB, D, E};
   int ntiles = (E + epb - 1) / epb;
   switch (prec) {
-    case 0: return dispatch<double, double, false>(N, nullptr, nullptr, a, ntiles, epb, s);
-    case 1: return dispatch<float, float, false>(N, nullptr, nullptr, a, ntiles, epb, s);
-    case 2: return dispatch<float, bf16_t, false>(N, nullptr, nullptr, a, ntiles, epb, s);
+    case 0: return dispatch<double, double, false>(N, nullptr, nullptr, a, ntiles, epb, s, nullptr, nullptr, cols);
+    case 1: return dispatch<float, float, false>(N, nullptr, nullptr, a, ntiles, epb, s, nullptr, nullptr, cols);
+    case 2: return dispatch<float, bf16_t, false>(N, nullptr, nullptr, a, ntiles, epb, s, nullptr, nullptr, cols);
     default: return hipErrorInvalidValue;
   }
 }
@@ -514,21 +518,21 @@ hipError_t launch_ax_apply(int prec, int N, int E, int epb, const void* u, void*
 // vectors and BF16 G take DOT_F64)
 hipError_t launch_ax_solver(int prec, int dm, int N, const Tile* tiles, int ntiles,
                             const ProbDev* probs, int epb, hipStream_t s, hipEvent_t ev0,
-                            hipEvent_t ev1, int parity) {
+                            hipEvent_t ev1, int parity, int cols) {
   AxApplyArgs a{};
   a.parity = parity;
   if (prec == 1 && dm == DOT_F32)
-    return dispatch<float, float, true, DOT_F32>(N, tiles, probs, a, ntiles, epb, s, ev0, ev1);
+    return dispatch<float, float, true, DOT_F32>(N, tiles, probs, a, ntiles, epb, s, ev0, ev1, cols);
   if (prec == 1 && dm == DOT_DOT2)
-    return dispatch<float, float, true, DOT_DOT2>(N, tiles, probs, a, ntiles, epb, s, ev0, ev1);
+    return dispatch<float, float, true, DOT_DOT2>(N, tiles, probs, a, ntiles, epb, s, ev0, ev1, cols);
   if (dm != DOT_F64) return hipErrorInvalidValue;
   switch (prec) {
-    case 0: return dispatch<double, double, true>(N, tiles, probs, a, ntiles, epb, s, ev0, ev1);
-    case 1: return dispatch<float, float, true>(N, tiles, probs, a, ntiles, epb, s, ev0, ev1);
-    case 2: return dispatch<float, bf16_t, true>(N, tiles, probs, a, ntiles, epb, s, ev0, ev1);
+    case 0: return dispatch<double, double, true>(N, tiles, probs, a, ntiles, epb, s, ev0, ev1, cols);
+    case 1: return dispatch<float, float, true>(N, tiles, probs, a, ntiles, epb, s, ev0, ev1, cols);
+    case 2: return dispatch<float, bf16_t, true>(N, tiles, probs, a, ntiles, epb, s, ev0, ev1, cols);
     case 3:
       return dispatch<float, float, true, DOT_F64, true>(N, tiles, probs, a, ntiles, epb, s, ev0,
-                                                         ev1);
+                                                         ev1, cols);
     default: return hipErrorInvalidValue;
   }
 }
@@ -541,8 +545,14 @@ int ax_wave_elements(int N) {
   return 0;
 }
 
+// largest tile of the two-column mapping: four waves of ax2_epw elements
+int max_epb2(int N) {
+  const int w = ax_wave_elements(N);
+  return w > 0 ? 4 * w : 0;
+}
+
 // largest epb whose one-column workgroup (rounded to wave64s) fits 256
-// threads (the two-column mapping takes any such tile)
+// threads
 int max_epb(int N) {
   const int n2 = (N + 1) * (N + 1);
   int e = 1;

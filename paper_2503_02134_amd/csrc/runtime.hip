@@ -129,7 +129,7 @@ int apply_impl(mxsem_mesh* m, int prec, const void* u, void* w, unsigned flags, 
   const int gprec = prec;  // 0 F64, 1 F32, 2 BF16 G with FP32 vectors
   const void* D = prec == MXSEM_F64 ? (const void*)m->D64 : (const void*)m->D32;
   MX_HIP(launch_ax_apply(prec, m->N, m->E, m->epb[m->N] > 0 ? m->epb[m->N] : default_epb(m->N),
-                         u, w, G_ptr(m, gprec), hB_ptr(m, gprec), D, s));
+                         u, w, G_ptr(m, gprec), hB_ptr(m, gprec), D, s, m->cols[m->N]));
   if (!(flags & MXSEM_LOCAL_ONLY)) {
     MX_HIP(launch_gs_apply(prec == MXSEM_F64 ? MXSEM_F64 : MXSEM_F32, MXSEM_F64, w, m->plan, true,
                            s));
@@ -606,7 +606,7 @@ int mxsem_mesh_create(mxsem_ctx* ctx, const mxsem_mesh_desc* d, void* workspace,
     MX_MHIP(hipGetLastError());
   }
   MX_MHIP(hipStreamSynchronize(s));
-  for (int q = 0; q < 16; ++q) m->epb[q] = 0;
+  for (int q = 0; q < 16; ++q) m->epb[q] = m->cols[q] = 0;
   ctx->live += 1;
   m->counted = true;
   *out = m;

@@ -17,15 +17,19 @@ struct mxsem_ctx {
 namespace mx {
 
 // launchers (defined in the .hip files)
+// cols: thread mapping (0 default, 1 one column per thread, 2 two columns
+// where the kernel exists: N = 5, 9 with FP32 vectors)
 hipError_t launch_ax_apply(int prec, int N, int E, int epb, const void* u, void* w, const void* G,
-                           const void* hB, const void* D, hipStream_t s);
+                           const void* hB, const void* D, hipStream_t s, int cols = 0);
 // parity: -1 updates p in place; 0 / 1 the step's parity with two direction
 // buffers (see ProbDev::p_alt)
 hipError_t launch_ax_solver(int prec, int dm, int N, const Tile* tiles, int ntiles, const ProbDev* probs,
                             int epb, hipStream_t s, hipEvent_t ev0 = nullptr,
-                            hipEvent_t ev1 = nullptr, int parity = -1);
+                            hipEvent_t ev1 = nullptr, int parity = -1, int cols = 0);
 int max_epb(int N);
 int ax_wave_elements(int N);
+// largest tile of the two-column mapping (0: N has none)
+int max_epb2(int N);
 // pairwise: the summation order of a pairwise exchange between the mesh's
 // ranks (FP32 vectors; see gs_kernel)
 hipError_t launch_gs_apply(int prec_io, int prec_acc, void* v, const GsPlan& plan, bool mask,
@@ -206,7 +210,7 @@ struct SolverBufs {
 
 // Operator-kernel launch class: problems of one order N and one tile size.
 struct AxClass {
-  int N = 0, epb = 1;
+  int N = 0, epb = 1, cols = 0;
   Tile* tiles = nullptr;
   int ntiles = 0;
 };
@@ -219,6 +223,7 @@ struct Plan {
   std::vector<mxsem_mesh*> meshes;
   std::vector<SolverBufs*> bufs;
   std::vector<int> epb_used;       // tile size per problem when built
+  std::vector<int> cols_used;      // thread mapping per problem when built
   std::vector<ProbDev> hprob;      // host copies
   ProbDev* probs = nullptr;        // device [P]
   State* states = nullptr;         // device [P]
@@ -285,6 +290,7 @@ struct mxsem_mesh {
   double* tmpa = nullptr;    // FP64 [nloc] work vectors
   double* tmpb = nullptr;
   int epb[16] = {0};
+  int cols[16] = {0};         // operator thread mapping per N (0 = default)
   // solver work vectors per vector precision (VP_F32ACC shares VP_F32's)
   mx::SolverBufs* bufs[4] = {nullptr, nullptr, nullptr, nullptr};
   mx::Plan* self_plan[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -302,6 +308,7 @@ int default_epb(int N);
 // leave that precision out)
 int ensure_bufs(mxsem_mesh* m, int vprec, SolverBufs** out);
 int mesh_epb(const mxsem_mesh* m);
+int mesh_cols(const mxsem_mesh* m);
 void mesh_drop_plans(mxsem_mesh* m);
 // gather-scatter tiles of problem p, one list per XCD (see solver.hip)
 void gs_tiles_by_xcd(const mxsem_mesh* m, int p, std::vector<std::vector<Tile>>& lists);

@@ -20,6 +20,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <string>
 #include <vector>
 
@@ -44,6 +45,7 @@ int gprec_of_mode(int mode) {
 }
 
 int mesh_epb(const mxsem_mesh* m) { return m->epb[m->N] > 0 ? m->epb[m->N] : default_epb(m->N); }
+int mesh_cols(const mxsem_mesh* m) { return m->cols[m->N]; }
 
 int region_take(Region& r, void** p, size_t bytes) {
   const size_t o = align256(r.used);
@@ -209,6 +211,7 @@ int plan_build(mxsem_mesh* const* meshes, int P, int vprec, Region tables, Plan*
     pl->meshes.push_back(m);
     pl->bufs.push_back(b);
     pl->epb_used.push_back(mesh_epb(m));
+    pl->cols_used.push_back(mesh_cols(m));
     ProbDev& Q = pl->hprob[p];
     memset(&Q, 0, sizeof(Q));
     Q.E = m->E;
@@ -240,25 +243,26 @@ int plan_build(mxsem_mesh* const* meshes, int P, int vprec, Region tables, Plan*
   }
   gs_table(meshes, P, tg);
   gs_table(meshes, P, tgw, true);
-  // operator classes (N, tile size)
-  std::vector<std::pair<int, int>> keys;
+  // operator classes (N, tile size, thread mapping)
+  typedef std::array<int, 3> AxKey;
+  std::vector<AxKey> keys;
   for (int p = 0; p < P; ++p) {
-    std::pair<int, int> k{meshes[p]->N, pl->epb_used[p]};
+    const AxKey k{meshes[p]->N, pl->epb_used[p], pl->cols_used[p]};
     if (std::find(keys.begin(), keys.end(), k) == keys.end()) keys.push_back(k);
   }
   std::sort(keys.begin(), keys.end());
   std::vector<std::vector<Tile>> ta(keys.size());
   for (int p = 0; p < P; ++p) {
-    const int c = (int)(std::find(keys.begin(), keys.end(),
-                                  std::pair<int, int>{meshes[p]->N, pl->epb_used[p]}) -
-                        keys.begin());
+    const AxKey k{meshes[p]->N, pl->epb_used[p], pl->cols_used[p]};
+    const int c = (int)(std::find(keys.begin(), keys.end(), k) - keys.begin());
     const int epb = pl->epb_used[p];
     for (int e = 0; e < meshes[p]->E; e += epb) ta[c].push_back(Tile{p, e, 0, 0});
   }
   for (size_t c = 0; c < keys.size(); ++c) {
     AxClass ac;
-    ac.N = keys[c].first;
-    ac.epb = keys[c].second;
+    ac.N = keys[c][0];
+    ac.epb = keys[c][1];
+    ac.cols = keys[c][2];
     ac.ntiles = (int)ta[c].size();
     if ((rc = plan_alloc(pl, (void**)&ac.tiles, sizeof(Tile) * ac.ntiles)) != MXSEM_OK)
       return fail(rc);
@@ -300,7 +304,8 @@ int plan_build(mxsem_mesh* const* meshes, int P, int vprec, Region tables, Plan*
 
 bool plan_stale(const Plan* pl) {
   for (int p = 0; p < pl->P; ++p)
-    if (pl->epb_used[p] != mesh_epb(pl->meshes[p])) return true;
+    if (pl->epb_used[p] != mesh_epb(pl->meshes[p]) || pl->cols_used[p] != mesh_cols(pl->meshes[p]))
+      return true;
   return false;
 }
 
@@ -312,7 +317,7 @@ int enqueue_ax(Plan* pl, int gprec, hipStream_t s, bool skip_first, int par = -1
   for (size_t c = skip_first ? 1 : 0; c < pl->ax.size(); ++c) {
     const AxClass& ac = pl->ax[c];
     MX_HIP(launch_ax_solver(kprec, pl->dm, ac.N, ac.tiles, ac.ntiles, pl->probs, ac.epb, s,
-                            nullptr, nullptr, par));
+                            nullptr, nullptr, par, ac.cols));
   }
   return MXSEM_OK;
 }
@@ -442,7 +447,7 @@ static int run_inner(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K, Inner& 
     // the chunk's first operator launch of class 0, with its own start/end events
     const AxClass& a0 = pl->ax[0];
     MX_HIP(launch_ax_solver(kprec, pl->dm, a0.N, a0.tiles, a0.ntiles, pl->probs, a0.epb, s,
-                            pl->evA, pl->evB, par0));
+                            pl->evA, pl->evB, par0, a0.cols));
     MX_TRY(enqueue_ax(pl, gprec, s, true, par0));
     MX_HIP(hipGraphLaunch(pl->graph, s));
     MX_HIP(hipMemcpyAsync(pl->hstate, pl->states, sizeof(State) * P, hipMemcpyDeviceToHost, s));
@@ -594,7 +599,7 @@ static int run_inner_fcg(Plan* pl, mxsem_ctx* ctx, int gprec, int pc, int K, Inn
   for (int l = 0; l < max_launch; ++l) {
     const AxClass& a0 = pl->ax[0];
     MX_HIP(launch_ax_solver(kprec, pl->dm, a0.N, a0.tiles, a0.ntiles, pl->probs, a0.epb, s,
-                            pl->evA, pl->evB));
+                            pl->evA, pl->evB, -1, a0.cols));
     MX_TRY(enqueue_ax(pl, gprec, s, true));
     MX_HIP(hipGraphLaunch(pl->graph, s));
     MX_HIP(hipMemcpyAsync(pl->hstate, pl->states, sizeof(State) * P, hipMemcpyDeviceToHost, s));
@@ -987,7 +992,7 @@ int mxsem_solve(mxsem_mesh* m, const mxsem_solve_opts* o, const double* b, doubl
 
 // ------------------------------------------------------------------ batch
 int mxsem_autotune_cached(mxsem_ctx* ctx, int N, int E, int prec, const char* path, void* ws,
-                          size_t ws_bytes, int* epb);
+                          size_t ws_bytes, int* epb, int* cols);
 
 static int check_batch_meshes(mxsem_ctx* ctx, int P, mxsem_mesh* const* meshes) {
   MX_CHECK(ctx && meshes && P >= 1, MXSEM_EINVAL, "batch: bad argument");
@@ -1034,10 +1039,12 @@ int mxsem_batch_create(mxsem_ctx* ctx, int P, mxsem_mesh* const* meshes, const c
       if (m->epb[m->N] > 0) continue;
       int e2 = 1;
       while (e2 < m->E) e2 <<= 1;
-      int epb = 0;
-      MX_TRY(mxsem_autotune_cached(ctx, m->N, e2, MXSEM_F32, path, workspace, ws_bytes, &epb));
+      int epb = 0, cols = 0;
+      MX_TRY(mxsem_autotune_cached(ctx, m->N, e2, MXSEM_F32, path, workspace, ws_bytes, &epb,
+                                   &cols));
       mxsem_tuning t{};
       t.epb[m->N] = epb;
+      t.cols[m->N] = cols;
       MX_TRY(mxsem_mesh_set_tuning(m, &t));
     }
   }

@@ -1,8 +1,10 @@
-// Autotuner for the operator kernel's tile (elements per workgroup), and
-// the per-mesh tuning entry point.  Candidates are every elements-per-
-// workgroup count whose workgroup fits 256 threads; each is timed with HIP
-// events over repeated launches on synthetic data of the requested (N, E,
-// precision), and the fastest wins.
+// Autotuner for the operator kernel's tile (elements per workgroup) and
+// thread mapping, and the per-mesh tuning entry point.  Candidates are every
+// elements-per-workgroup count whose workgroup fits 256 threads, with one
+// (i,j) column per thread and, where that kernel exists (N = 5, 9 with FP32
+// vectors), with two; each is timed with HIP events over repeated launches
+// on synthetic data of the requested (N, E, precision), and the fastest
+// wins.
 #include <math.h>
 #include <stdio.h>
 
@@ -43,7 +45,7 @@ static TuneBlocks tune_blocks(int N, int E, int prec) {
 size_t autotune_bytes(int N, int E, int prec) { return tune_blocks(N, E, prec).total; }
 
 int autotune_epb(int device, hipStream_t s, int N, int E, int prec, char* ws, int* best_epb,
-                 std::vector<float>* times) {
+                 int* best_cols) {
   const int n = N + 1, n3 = n * n * n;
   const int64_t nloc = (int64_t)E * n3;
   const size_t vb = prec == MXSEM_F64 ? 8 : 4;
@@ -71,33 +73,38 @@ int autotune_epb(int device, hipStream_t s, int N, int E, int prec, char* ws, in
                      (float*)D, (int64_t)words_D, 0.125f);
   float best = INFINITY;
   *best_epb = default_epb(N);
-  const int emax = max_epb(N);
-  for (int epb = 1; epb <= emax; ++epb) {
-    for (int r = 0; r < 2; ++r) {
-      if (launch_ax_apply(prec, N, E, epb, u, w, G, nullptr, D, s) != hipSuccess) {
+  *best_cols = 0;
+  // the two-column kernel exists for FP32 vectors (FP32 or BF16 G) at N = 5, 9
+  const bool two = prec != MXSEM_F64 && ax_wave_elements(N) > 0;
+  for (int cols = 1; cols <= (two ? 2 : 1); ++cols) {
+    const int emax = cols == 2 ? std::min(max_epb(N), max_epb2(N)) : max_epb(N);
+    for (int epb = 1; epb <= emax; ++epb) {
+      for (int r = 0; r < 2; ++r) {
+        if (launch_ax_apply(prec, N, E, epb, u, w, G, nullptr, D, s, cols) != hipSuccess) {
+          cleanup();
+          set_error("autotune: launch failed");
+          return MXSEM_EHIP;
+        }
+      }
+      const int reps = 5;
+      hipError_t err = hipEventRecord(e0, s);
+      for (int r = 0; r < reps && err == hipSuccess; ++r)
+        err = launch_ax_apply(prec, N, E, epb, u, w, G, nullptr, D, s, cols);
+      if (err == hipSuccess) err = hipEventRecord(e1, s);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      if (err != hipSuccess) {
         cleanup();
-        set_error("autotune: launch failed");
+        set_error(std::string("autotune: timing failed: ") + hipGetErrorString(err));
         return MXSEM_EHIP;
       }
-    }
-    const int reps = 5;
-    hipError_t err = hipEventRecord(e0, s);
-    for (int r = 0; r < reps && err == hipSuccess; ++r)
-      err = launch_ax_apply(prec, N, E, epb, u, w, G, nullptr, D, s);
-    if (err == hipSuccess) err = hipEventRecord(e1, s);
-    if (err == hipSuccess) err = hipEventSynchronize(e1);
-    float ms = 0.f;
-    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-    if (err != hipSuccess) {
-      cleanup();
-      set_error(std::string("autotune: timing failed: ") + hipGetErrorString(err));
-      return MXSEM_EHIP;
-    }
-    ms /= reps;
-    if (times) times->push_back(ms);
-    if (ms < best) {
-      best = ms;
-      *best_epb = epb;
+      ms /= reps;
+      if (ms < best) {
+        best = ms;
+        *best_epb = epb;
+        *best_cols = two ? cols : 0;
+      }
     }
   }
   (void)device;
@@ -105,7 +112,8 @@ int autotune_epb(int device, hipStream_t s, int N, int E, int prec, char* ws, in
   return rc;
 }
 
-// Tuning cache: a flat JSON object {"gfx950:N7:E32768:p1": 1, ...}.
+// Tuning cache: a flat JSON object {"gfx950:N7:E32768:p1": 1, ...}; the
+// value is the tile plus 100 times the thread mapping (0, 1 or 2).
 static std::map<std::string, int> read_cache(const char* path) {
   std::map<std::string, int> out;
   std::ifstream f(path);
@@ -177,10 +185,11 @@ int mxsem_autotune(mxsem_ctx* ctx, int N, int E, mxsem_prec prec, void* workspac
            "autotune: workspace smaller than mxsem_autotune_workspace_bytes");
   MX_HIP(hipSetDevice(ctx->device));
   (void)hipGetLastError();
-  int best = 0;
-  MX_TRY(autotune_epb(ctx->device, ctx->stream, N, E, prec, (char*)workspace, &best, nullptr));
-  for (int q = 0; q < 16; ++q) out->epb[q] = 0;
+  int best = 0, cols = 0;
+  MX_TRY(autotune_epb(ctx->device, ctx->stream, N, E, prec, (char*)workspace, &best, &cols));
+  for (int q = 0; q < 16; ++q) out->epb[q] = out->cols[q] = 0;
   out->epb[N] = best;
+  out->cols[N] = cols;
   return MXSEM_OK;
   MX_API_END("mxsem_autotune")
 }
@@ -188,20 +197,25 @@ int mxsem_autotune(mxsem_ctx* ctx, int N, int E, mxsem_prec prec, void* workspac
 // Tuned tile for (N, E, prec) from the cache file, autotuned in the given
 // workspace and added to the file when missing.
 int mxsem_autotune_cached(mxsem_ctx* ctx, int N, int E, int prec, const char* path, void* ws,
-                          size_t ws_bytes, int* epb) {
+                          size_t ws_bytes, int* epb, int* cols) {
   MX_API_BEGIN
   char key[96];
   snprintf(key, sizeof(key), "gfx950:N%d:E%d:p%d", N, E, prec);
   std::map<std::string, int> kv = read_cache(path);
   auto it = kv.find(key);
-  if (it != kv.end() && it->second >= 1 && it->second <= max_epb(N)) {
-    *epb = it->second;
-    return MXSEM_OK;
+  if (it != kv.end()) {
+    const int e = it->second % 100, c = it->second / 100;
+    if (e >= 1 && e <= max_epb(N) && (c <= 1 || (c == 2 && ax_wave_elements(N) > 0))) {
+      *epb = e;
+      *cols = c;
+      return MXSEM_OK;
+    }
   }
   mxsem_tuning t{};
   MX_TRY(mxsem_autotune(ctx, N, E, (mxsem_prec)prec, ws, ws_bytes, &t));
   *epb = t.epb[N];
-  kv[key] = *epb;
+  *cols = t.cols[N];
+  kv[key] = *epb + 100 * *cols;
   write_cache(path, kv);
   return MXSEM_OK;
   MX_API_END("mxsem_autotune_cached")
@@ -210,11 +224,15 @@ int mxsem_autotune_cached(mxsem_ctx* ctx, int N, int E, int prec, const char* pa
 int mxsem_mesh_set_tuning(mxsem_mesh* m, const mxsem_tuning* t) {
   MX_API_BEGIN
   MX_CHECK(m && t, MXSEM_EINVAL, "mesh_set_tuning: null argument");
-  const int e = t->epb[m->N];
+  const int e = t->epb[m->N], c = t->cols[m->N];
   MX_CHECK(e >= 0 && e <= max_epb(m->N), MXSEM_EINVAL,
            "mesh_set_tuning: elements per workgroup out of range for this order");
+  MX_CHECK(c >= 0 && c <= 2 && (c < 2 || ax_wave_elements(m->N) > 0), MXSEM_EINVAL,
+           "mesh_set_tuning: thread mapping must be 0, 1, or 2 where the order has a "
+           "two-column kernel (N = 5, 9)");
   MX_HIP(hipSetDevice(m->ctx->device));
   m->epb[m->N] = e;
+  m->cols[m->N] = c;
   mesh_drop_plans(m);  // plans are rebuilt with the new tiles on next use
   return MXSEM_OK;
   MX_API_END("mxsem_mesh_set_tuning")

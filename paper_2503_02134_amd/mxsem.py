@@ -71,7 +71,7 @@ class mxsem_solve_stats(C.Structure):
 
 
 class mxsem_tuning(C.Structure):
-    _fields_ = [("epb", C.c_int * 16)]
+    _fields_ = [("epb", C.c_int * 16), ("cols", C.c_int * 16)]
 
 
 class mxsem_nn_desc(C.Structure):
@@ -437,7 +437,9 @@ def mxsem_batch_solve(batch, opts, bs, xs):
     return list(st)
 
 
-def mxsem_autotune(ctx, N, E, prec) -> int:
+def mxsem_autotune(ctx, N, E, prec) -> tuple:
+    """(elements per workgroup, thread mapping) of the fastest operator
+    kernel for (N, E, prec); mapping 0 means the order has one mapping."""
     nb = C.c_size_t()
     _check("mxsem_autotune_workspace_bytes",
            lib().mxsem_autotune_workspace_bytes(N, E, prec, C.byref(nb)))
@@ -446,13 +448,17 @@ def mxsem_autotune(ctx, N, E, prec) -> int:
     _check("mxsem_autotune", lib().mxsem_autotune(ctx, N, E, prec, ws.data_ptr(), ws.numel(),
                                                    C.byref(t)))
     del ws
-    return t.epb[N]
+    return t.epb[N], t.cols[N]
 
 
-def mxsem_mesh_set_tuning(mesh, epb_by_N: dict):
+def mxsem_mesh_set_tuning(mesh, epb_by_N: dict, cols_by_N: dict | None = None):
+    """Operator tile (elements per workgroup) and, optionally, thread mapping
+    (1: one column per thread, 2: two; 0: the default) per order N."""
     t = mxsem_tuning()
     for N, e in epb_by_N.items():
         t.epb[N] = e
+    for N, c in (cols_by_N or {}).items():
+        t.cols[N] = c
     _check("mxsem_mesh_set_tuning", lib().mxsem_mesh_set_tuning(mesh, C.byref(t)))
 
 

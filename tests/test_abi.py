@@ -258,3 +258,13 @@ def test_multigrid_view_is_sized_and_checked_on_the_host(mx):
     assert b"lattice" in L.mxsem_last_error()
     d2.views = 16
     assert L.mxsem_mesh_workspace_bytes(C.byref(d2), C.byref(nb1)) == mx.EINVAL
+
+
+def test_tuning_struct_and_mapping_checks(mx):
+    """mxsem_tuning carries a tile and a thread mapping per order; a mapping
+    outside 0..2, or two columns where the order has no such kernel, is
+    refused before anything runs (a null mesh is refused first)."""
+    import ctypes as C
+    assert C.sizeof(mx.mxsem_tuning) == 2 * 16 * C.sizeof(C.c_int)
+    t = mx.mxsem_tuning()
+    assert mx.lib().mxsem_mesh_set_tuning(None, C.byref(t)) == mx.EINVAL

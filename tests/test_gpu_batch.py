@@ -104,14 +104,28 @@ def test_tuning_cache_round_trip(mx, ctx, tmp_path):
     kv = json.load(open(path))
     assert len(kv) == 2 and all(k.startswith("gfx950:N") for k in kv)
     for k, v in kv.items():
+        # tile + 100 x thread mapping (2: two columns per thread, N = 5 and 9 only)
         N = int(k.split(":")[1][1:])
-        assert 1 <= v and ((v * (N + 1) ** 2 + 63) // 64) * 64 <= 256
+        e, c = v % 100, v // 100
+        assert 1 <= e and ((e * (N + 1) ** 2 + 63) // 64) * 64 <= 256
+        assert c in (0, 1, 2) and (c < 2 or N in (5, 9))
     # a second batch reads the file instead of tuning again
     mtime = os.path.getmtime(path)
     probs2 = _problems(mx, ctx)[:2]
     bt = mx.mxsem_batch_create(ctx.h, [m.h for m, _ in probs2], tune_cache=path)
     mx.mxsem_batch_destroy(bt)
     assert os.path.getmtime(path) == mtime
+
+
+@pytest.mark.parametrize("N,prec", [(5, "F32"), (9, "F32"), (7, "F32"), (5, "F64")])
+def test_autotune_picks_a_valid_tile_and_mapping(mx, ctx, N, prec):
+    """The autotuner times every tile with each thread mapping the order has
+    (two for N = 5 and 9 with FP32 vectors, one otherwise) and returns one
+    that a mesh accepts."""
+    epb, cols = mx.mxsem_autotune(ctx.h, N, 512, getattr(mx, prec))
+    log(f"autotune N={N} {prec}: epb={epb} cols={cols}")
+    assert 1 <= epb and ((epb * (N + 1) ** 2 + 63) // 64) * 64 <= 256
+    assert cols in ((1, 2) if (N in (5, 9) and prec == "F32") else (0,))
 
 
 def test_batch_rejects_bad_input(mx, ctx):

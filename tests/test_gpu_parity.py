@@ -86,20 +86,23 @@ def test_local_operator_all_precisions(orc, mx, ctx, ne, N, seed):
         assert err16 > 1e-5  # on deformed meshes the BF16 path really rounds G
 
 
+@pytest.mark.parametrize("cols", [0, 1, 2])
 @pytest.mark.parametrize("N,epb,hh", [(9, 1, 0.0), (9, 2, 1.0), (5, 1, 0.0), (5, 3, 1.0),
                                       (5, 4, 0.0), (5, 7, 1.0)])
-def test_local_operator_tile_sizes(orc, mx, ctx, N, epb, hh):
-    """Every tile size of the FP32 operator at N = 5 and 9 (the orders whose
-    FP32 kernel puts two columns on a thread, one or three elements per wave),
-    27 elements so the last tile is ragged, Poisson and Helmholtz."""
+def test_local_operator_tile_sizes(orc, mx, ctx, N, epb, hh, cols):
+    """Tile sizes of the FP32 operator at N = 5 and 9, the orders with two
+    thread mappings (two columns per thread, one or three elements per wave,
+    the default; or one column per thread), each mapping asked for through
+    the tuning struct; 27 elements so the last tile is ragged, Poisson and
+    Helmholtz."""
     from paper_2503_02134_amd import workloads as W
-    log(f"ax_local tiles N={N} epb={epb} h={hh}")
+    log(f"ax_local tiles N={N} epb={epb} cols={cols} h={hh}")
     xg, _ = mx.mxsem_gll(N)
     xo, _ = orc.gll(N)
     bmg, bmo = W.box_mesh(3, N, xg, seed=2), W.box_mesh(3, N, xo, seed=2)
     gm = mx.Mesh(ctx, bmg.E, N, bmg.xyz, bmg.glo, bmg.bnd, helm_h=hh)
     om = orc.Mesh(bmo.E, N, bmo.xyz, bmo.glo, bmo.bnd, helm_h=hh)
-    mx.mxsem_mesh_set_tuning(gm.h, {N: epb})
+    mx.mxsem_mesh_set_tuning(gm.h, {N: epb}, {N: cols})
     u32 = np.random.default_rng(N + epb).standard_normal(om.nloc).astype(np.float32)
     ref32 = om.ax_local(u32.astype(np.float64))
     scale = np.max(np.abs(ref32))
