@@ -50,6 +50,148 @@ __device__ inline void fin_sigma_step(const ProbDev& P, double* sred);
 // ranks always agree (a + b = b + a); copies of a node shared by three or
 // more ranks may differ in their last bits when the sums are FP32
 // (m <= GS_PAIRWISE_MAXM).
+// The pairwise order for one group of m copies (local indices ids, ascending).
+template <typename T, typename ACC>
+__device__ inline void gs_pairwise_group(gptr<T> v, const int* ids, int m,
+                                         const gptr<const int> erank, int n3) {
+  T a[GS_PAIRWISE_MAXM];
+  int rk[GS_PAIRWISE_MAXM];
+  for (int k = 0; k < m; ++k) {
+    const int i = ids[k];
+    a[k] = v[i];
+    rk[k] = erank ? erank[i / n3] : i / n3;
+  }
+  // the ranks holding copies, ascending, with their partial sums
+  ACC part[GS_PAIRWISE_MAXM];
+  int rl[GS_PAIRWISE_MAXM];
+  int nr = 0, last = -1;
+  for (int t = 0; t < m; ++t) {
+    int best = 0x7fffffff;
+    for (int j = 0; j < m; ++j)
+      if (rk[j] > last && rk[j] < best) best = rk[j];
+    if (best == 0x7fffffff) break;
+    ACC ps = ACC(0);
+    bool first = true;
+    for (int j = 0; j < m; ++j)
+      if (rk[j] == best) {
+        ps = first ? (ACC)a[j] : ps + (ACC)a[j];
+        first = false;
+      }
+    rl[nr] = best;
+    part[nr] = ps;
+    ++nr;
+    last = best;
+  }
+  for (int k = 0; k < m; ++k) {
+    int own = 0;
+    for (int t = 0; t < nr; ++t)
+      if (rl[t] == rk[k]) own = t;
+    ACC sum = part[own];
+    for (int t = 0; t < nr; ++t)
+      if (t != own) sum += part[t];
+    v[ids[k]] = (T)sum;
+  }
+}
+
+// Box lattices (ProbDev::box_ne > 0) have tiles of whole elements whose
+// groups are found by index arithmetic instead of the index array
+// (Tile::aux < 0, Tile::first the first element, Tile::pad the element
+// count: four elements at N = 7, one at N = 15).  Element e owns the nodes
+// it shares with the elements above it and with none below: the interiors of
+// its x+, y+ and z+ faces (2 copies), its three upper edges (4) and its upper
+// corner (8); a node on the box boundary is left to the mask list.  A tile lists its
+// elements' face groups, then their edge groups, then their corners, so a
+// wave mostly does groups of one size.  The copies are the node's entries
+// in the elements e + dz ne^2 + dy ne + dx (dx, dy, dz in {0, 1}, 1 across
+// an upper face), summed in that lexicographic order, which is ascending
+// local index: the order of the index-array groups, so the results are
+// bitwise theirs.
+// One box tile, one group per thread per pass (56 registers, eight waves
+// per SIMD: two groups per thread with all their loads issued together took
+// 104 registers and was slower, 38 against 31 us on 32^3 elements, N = 7).
+template <typename T, typename ACC, bool PAIRWISE, int N>
+__device__ inline void gs_box_tile(gptr<T> v, const ProbDev& P, int e0, int nel) {
+  constexpr int n = N + 1, M = N - 1, F = 3 * M * M, ED = 3 * M;
+  constexpr int ln = n == 8 ? 3 : 4;
+  const int ne = P.box_ne, ne2 = ne * ne;
+  // coordinates of the tile's first element (float quotients, corrected)
+  int ez = (int)((float)e0 * P.box_rne2);
+  ez -= ez * ne2 > e0;
+  ez += (ez + 1) * ne2 <= e0;
+  const int rem = e0 - ez * ne2;
+  int ey = (int)((float)rem * P.box_rne);
+  ey -= ey * ne > rem;
+  ey += (ey + 1) * ne <= rem;
+  const int ex0 = rem - ey * ne, ey0 = ey, ez0 = ez;
+  const int nF = nel * F, nE = nel * ED, ntot = nF + nE + nel;
+  for (int s = (int)threadIdx.x; s < ntot; s += GS_THREADS) {
+    int el, a, b, c, m;
+    if (s < nF) {
+      el = s / F;
+      const int r = s - el * F, f = r / (M * M), uv = r - f * M * M;
+      const int u = 1 + uv % M, w = 1 + uv / M;
+      a = f == 0 ? N : u;
+      b = f == 0 ? u : f == 1 ? N : w;
+      c = f == 2 ? N : w;
+      m = 2;
+    } else if (s < nF + nE) {
+      const int s2 = s - nF;
+      el = s2 / ED;
+      const int r = s2 - el * ED, k = r / M, u = 1 + r % M;
+      a = k == 2 ? u : N;
+      b = k == 1 ? u : N;
+      c = k == 0 ? u : N;
+      m = 4;
+    } else {
+      el = s - nF - nE;
+      a = b = c = N;
+      m = 8;
+    }
+    const bool ux = a == N, uy = b == N, uz = c == N;
+    // the element's coordinates: the first element's, moved on by el
+    int ex = ex0 + el, eyy = ey0, ezz = ez0;
+    while (ex >= ne) ex -= ne, ++eyy;
+    while (eyy >= ne) eyy -= ne, ++ezz;
+    if ((ux && ex == ne - 1) || (uy && eyy == ne - 1) || (uz && ezz == ne - 1)) continue;
+    const int e = e0 + el;
+    int ids[8];
+    int q = 0;
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+          if ((dz && !uz) || (dy && !uy) || (dx && !ux)) continue;
+          const int eo = e + dz * ne2 + dy * ne + dx;
+          ids[q++] = (eo << (3 * ln)) + (dx ? 0 : a) + ((dy ? 0 : b) << ln) +
+                     ((dz ? 0 : c) << (2 * ln));
+        }
+    if constexpr (PAIRWISE) {
+      gs_pairwise_group<T, ACC>(v, ids, m, gcast(P.gs.erank), P.gs.n3);
+    } else if (m == 2) {
+      const T val = (T)((ACC)v[ids[0]] + (ACC)v[ids[1]]);
+      v[ids[0]] = val;
+      v[ids[1]] = val;
+    } else if (m == 4) {
+      const T a0 = v[ids[0]], a1 = v[ids[1]], a2 = v[ids[2]], a3 = v[ids[3]];
+      const T val = (T)((((ACC)a0 + (ACC)a1) + (ACC)a2) + (ACC)a3);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[ids[k]] = val;
+    } else {
+      T av[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) av[k] = v[ids[k]];
+      ACC sum = (ACC)av[0];
+#pragma unroll
+      for (int k = 1; k < 8; ++k) sum += (ACC)av[k];
+      const T val = (T)sum;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[ids[k]] = val;
+    }
+  }
+}
+
 template <typename T, typename ACC, bool SOLVER, bool PAIRWISE = false>
 __global__ void __launch_bounds__(GS_THREADS) gs_kernel(const Tile* __restrict__ tiles,
                                                         const ProbDev* __restrict__ probs,
@@ -92,6 +234,13 @@ __global__ void __launch_bounds__(GS_THREADS) gs_kernel(const Tile* __restrict__
     bucket = t.aux;
     first = t.first;
     count = t.pad;
+    if (bucket < 0) {  // box lattice: groups by index arithmetic
+      if (P.box_ln == 3)
+        gs_box_tile<T, ACC, PAIRWISE, 7>(v, P, first, count);
+      else
+        gs_box_tile<T, ACC, PAIRWISE, 15>(v, P, first, count);
+      return;
+    }
   } else {
     plan = &api.plan;
     v = gcast((T*)api.v);
@@ -114,49 +263,13 @@ __global__ void __launch_bounds__(GS_THREADS) gs_kernel(const Tile* __restrict__
       if (ok[q]) v[idx[g[q]]] = T(0);
   } else if constexpr (PAIRWISE) {
     if (m > GS_PAIRWISE_MAXM) return;  // rejected on the host
-    const gptr<const int> erank = gcast(plan->erank);
-    const int n3 = plan->n3;
 #pragma unroll
     for (int q = 0; q < GS_PER_THREAD; ++q)
       if (ok[q]) {
         const gptr<const int> gi = idx + (int64_t)g[q] * m;
-        T a[GS_PAIRWISE_MAXM];
-        int rk[GS_PAIRWISE_MAXM];
-        for (int k = 0; k < m; ++k) {
-          const int i = gi[k];
-          a[k] = v[i];
-          rk[k] = erank ? erank[i / n3] : i / n3;
-        }
-        // the ranks holding copies, ascending, with their partial sums
-        ACC part[GS_PAIRWISE_MAXM];
-        int rl[GS_PAIRWISE_MAXM];
-        int nr = 0, last = -1;
-        for (int t = 0; t < m; ++t) {
-          int best = 0x7fffffff;
-          for (int j = 0; j < m; ++j)
-            if (rk[j] > last && rk[j] < best) best = rk[j];
-          if (best == 0x7fffffff) break;
-          ACC ps = ACC(0);
-          bool first = true;
-          for (int j = 0; j < m; ++j)
-            if (rk[j] == best) {
-              ps = first ? (ACC)a[j] : ps + (ACC)a[j];
-              first = false;
-            }
-          rl[nr] = best;
-          part[nr] = ps;
-          ++nr;
-          last = best;
-        }
-        for (int k = 0; k < m; ++k) {
-          int own = 0;
-          for (int t = 0; t < nr; ++t)
-            if (rl[t] == rk[k]) own = t;
-          ACC sum = part[own];
-          for (int t = 0; t < nr; ++t)
-            if (t != own) sum += part[t];
-          v[gi[k]] = (T)sum;
-        }
+        int ids[GS_PAIRWISE_MAXM];
+        for (int k = 0; k < m; ++k) ids[k] = gi[k];
+        gs_pairwise_group<T, ACC>(v, ids, m, gcast(plan->erank), plan->n3);
       }
   } else if (m == 2) {
     gi2_t ix[GS_PER_THREAD];
