@@ -627,9 +627,12 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// level-0 right-hand side: each interior vertex sums the corners of its elements
+// level-0 right-hand side: each interior vertex sums the corners of its
+// elements; with A, also the first Jacobi sweep from x = 0 (x1 = omega b /
+// a_diag, the point's own values only)
 __global__ void mg_gather_kernel(const double* __restrict__ corner, double* __restrict__ b, int ne,
-                                 const State* __restrict__ st) {
+                                 const State* __restrict__ st, const double* __restrict__ A,
+                                 double* __restrict__ x1, double omega) {
   const int nu = ne - 1;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nu * nu * nu || (st && gcast(st)->done)) return;
@@ -643,6 +646,7 @@ __global__ void mg_gather_kernel(const double* __restrict__ corner, double* __re
     s += corner[((int64_t)ex + ne * ((int64_t)ey + ne * ez)) * 8 + c];
   }
   b[q] = s;
+  if (A) x1[q] = omega * s / A[(int64_t)q * 27 + 13];
 }
 
 __device__ inline double stencil_apply(const double* __restrict__ a, const double* __restrict__ x,
@@ -681,9 +685,12 @@ __global__ void lat_residual_kernel(const double* __restrict__ A, const double* 
   r[q] = b[q] - stencil_apply(A + (int64_t)q * 27, x, nu, I, J, K);
 }
 
-// bc = P^T r (full weighting)
+// bc = P^T r (full weighting); with Ac, also the coarse level's first Jacobi
+// sweep from x = 0 (xc1 = omega_c bc / ac_diag, the point's own values only)
 __global__ void lat_restrict_kernel(const double* __restrict__ r, double* __restrict__ bc, int nuf,
-                                    int nuc, const State* __restrict__ st) {
+                                    int nuc, const State* __restrict__ st,
+                                    const double* __restrict__ Ac, double* __restrict__ xc1,
+                                    double omegac) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nuc * nuc * nuc || (st && gcast(st)->done)) return;
   const int I = q % nuc + 1, J = (q / nuc) % nuc + 1, K = q / (nuc * nuc) + 1;
@@ -695,6 +702,7 @@ __global__ void lat_restrict_kernel(const double* __restrict__ r, double* __rest
     s += w * r[(2 * I + dx - 1) + nuf * ((2 * J + dy - 1) + nuf * (2 * K + dz - 1))];
   }
   bc[q] = s;
+  if (Ac) xc1[q] = omegac * s / Ac[(int64_t)q * 27 + 13];
 }
 
 // x += P xc (trilinear interpolation from the coarser level)
@@ -877,26 +885,34 @@ int mg_apply(mxsem_mesh* m, int vprec, const void* r, void* z, hipStream_t s, co
     MX_HIP(launch_gs_solver(pl->vprec, pl->tiles_gs, pl->nt_gs, pl->probs, s, true, 0, nullptr, 0));
   else
     MX_HIP(launch_gs_apply(f64 ? MXSEM_F64 : MXSEM_F32, MXSEM_F64, z, m->plan, true, s));
-  // coarse correction: one V-cycle on the vertex lattice
+  // coarse correction: one V-cycle on the vertex lattice.  The first sweep
+  // of each smoothed level starts from x = 0 and needs only the point's own
+  // right-hand side, so it is formed where that right-hand side is (the
+  // corner gather, the restriction); the other steps couple neighbours and
+  // keep launches of their own (fusing the residual into the restriction, or
+  // the prolongation into the next sweep, recomputes neighbours' values on
+  // grids of a few thousand points and was slower: 137 and 38 us against 6
+  // and 10 us on the 32^3 mesh).
   const int L = g->nlev;
   {
-    const int nu = g->lv[0].nu;
+    MgLevel& v = g->lv[0];
+    const int nu = v.nu;
     hipLaunchKernelGGL(mg_gather_kernel, dim3(lat_blocks(nu * nu * nu)), dim3(256), 0, s, g->corner,
-                       g->lv[0].b, g->ne, st);
+                       v.b, g->ne, st, L > 1 ? (const double*)v.st : nullptr, v.x2, v.omega);
     MX_HIP(hipGetLastError());
   }
   for (int l = 0; l + 1 < L; ++l) {
     MgLevel& v = g->lv[l];
     const int nn = v.nu * v.nu * v.nu;
     hipLaunchKernelGGL(lat_jacobi_kernel, dim3(lat_blocks(nn)), dim3(256), 0, s, v.st, v.b,
-                       (const double*)nullptr, v.x2, v.nu, v.omega, st);
-    hipLaunchKernelGGL(lat_jacobi_kernel, dim3(lat_blocks(nn)), dim3(256), 0, s, v.st, v.b,
                        (const double*)v.x2, v.x, v.nu, v.omega, st);
     hipLaunchKernelGGL(lat_residual_kernel, dim3(lat_blocks(nn)), dim3(256), 0, s, v.st, v.b,
                        (const double*)v.x, v.r, v.nu, st);
     MgLevel& c = g->lv[l + 1];
+    const bool csmooth = l + 2 < L;  // the coarser level is smoothed, not solved
     hipLaunchKernelGGL(lat_restrict_kernel, dim3(lat_blocks(c.nu * c.nu * c.nu)), dim3(256), 0, s,
-                       (const double*)v.r, c.b, v.nu, c.nu, st);
+                       (const double*)v.r, c.b, v.nu, c.nu, st,
+                       csmooth ? (const double*)c.st : nullptr, c.x2, c.omega);
     MX_HIP(hipGetLastError());
   }
   {
