@@ -723,6 +723,50 @@ __device__ inline double fixed_sum(const gptr<const double> __restrict__ parts, 
   return block_sum(s, sred);
 }
 
+// fixed_sum of two arrays of n partials at once (the same order for each,
+// so the results are bitwise those of two fixed_sum calls, in one pass of
+// loads and one block reduction); sred holds 32 doubles; thread 0 gets both
+template <int NT>
+__device__ inline void fixed_sum2(const gptr<const double> __restrict__ p0,
+                                  const gptr<const double> __restrict__ p1, int n, double* sred,
+                                  double& s0, double& s1) {
+  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0}, b[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int q = threadIdx.x;
+  for (; q + 7 * NT < n; q += 8 * NT) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      a[k] += p0[q + k * NT];
+      b[k] += p1[q + k * NT];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (q + k * NT < n) {
+      a[k] += p0[q + k * NT];
+      b[k] += p1[q + k * NT];
+    }
+  double sa = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  double sb = ((b[0] + b[1]) + (b[2] + b[3])) + ((b[4] + b[5]) + (b[6] + b[7]));
+  for (int off = 32; off > 0; off >>= 1) {
+    sa += __shfl_down(sa, off, 64);
+    sb += __shfl_down(sb, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    sred[wid] = sa;
+    sred[16 + wid] = sb;
+  }
+  __syncthreads();
+  s0 = s1 = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < nw; ++w) {
+      s0 += sred[w];
+      s1 += sred[16 + w];
+    }
+}
+
 // sigma = (p, A p)_c; alpha = rho / sigma; breakdown if sigma <= 0 or not
 // finite.  Run by a workgroup of the gather-scatter launch of the same step.
 __device__ inline void fin_sigma_step(const ProbDev& P, double* sred) {
@@ -778,7 +822,7 @@ __device__ inline bool step_test(const gptr<State> st, double rr) {
 }
 
 __global__ void fin_rho_kernel(const ProbDev* __restrict__ probs, int mode) {
-  __shared__ double sred[16];
+  __shared__ double sred[32];
   const ProbDev& P = probs[blockIdx.x];
   const gptr<State> st = gcast(P.st);
   if (st->done) return;
@@ -786,8 +830,7 @@ __global__ void fin_rho_kernel(const ProbDev* __restrict__ probs, int mode) {
   const gptr<const double> p1 = gcast((const double*)P.part_u1);
   double rz, rr;
   if (P.dm == DOT_F64) {
-    rz = fixed_sum<FIN_THREADS>(p0, P.nblk_upd, sred);
-    rr = fixed_sum<FIN_THREADS>(p1, P.nblk_upd, sred);
+    fixed_sum2<FIN_THREADS>(p0, p1, P.nblk_upd, sred, rz, rr);
   } else {
     rz = dot_finish<FIN_THREADS>(P.dm, p0, P.nblk_upd, sred);
     rr = dot_finish<FIN_THREADS>(P.dm, p1, P.nblk_upd, sred);
