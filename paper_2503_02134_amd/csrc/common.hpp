@@ -218,6 +218,7 @@ constexpr int GS_THREADS = 256;  // gather-scatter workgroup
 constexpr int GS_PER_THREAD = 2;
 constexpr int GS_CHUNK = GS_THREADS * GS_PER_THREAD;  // items per workgroup
 constexpr int GS_PAIRWISE_MAXM = 16;  // largest group of the pairwise summation order
+constexpr int GS_ROW_EL = 4;  // elements per row tile of a box lattice (N = 7)
 constexpr int UPD_THREADS = 256; // threads per vector-update workgroup
 constexpr int UPD_PER_THREAD = 8;  // entries per thread (two 4-wide vectors)
 constexpr int UPD_CHUNK = UPD_THREADS * UPD_PER_THREAD;

@@ -134,26 +134,38 @@ static int plan_alloc(Plan* pl, void** p, size_t bytes) { return region_take(pl-
 // entries, and for every block the groups of every bucket whose first
 // copy lies in the block become tiles of that chunk's list, block by
 // block.  Tile.pad is the tile's group count (at most GS_CHUNK).  On a box
-// lattice the free groups of a block are instead the groups its elements
-// own, found by index arithmetic: tiles of 4 elements at N = 7 and of one
-// at N = 15 (Tile.aux = -1, Tile.first the first element, Tile.pad the
-// count); the mask list keeps its index tiles.
+// lattice the free groups of a block are instead found by index
+// arithmetic.  At N = 7 the tiles are runs of at most GS_ROW_EL elements
+// along one x line of the lattice, each owning whole rows of the vector
+// (Tile.aux = -2, Tile.first the first element, Tile.pad the count); they
+// also zero the box boundary, so the mask list is left out.  At N = 15 the
+// tiles hold the groups one element owns (Tile.aux = -1) and the mask list
+// keeps its index tiles.
 void gs_tiles_by_xcd(const mxsem_mesh* m, int p, std::vector<std::vector<Tile>>& lists) {
   const int nx = (int)lists.size();
   const int64_t n3 = m->n3;
   const int eb = (int)std::max<int64_t>(1, 8192 / n3);
-  const bool box = m->box_ne > 0;
+  const bool box = m->box_ne > 0, rows = box && m->n == 8;
+  const int ne = m->box_ne;
   const int ept = (3 * m->N * m->N - 3 * m->N + 1) <= GS_CHUNK / 4 ? 4 : 1;  // elements per tile
   std::vector<size_t> cur(MAX_BUCKETS, 0);
   for (int e0 = 0; e0 < m->E; e0 += eb) {
     const int e1 = std::min(m->E, e0 + eb);
     const int x = (int)((int64_t)e0 * nx / m->E);
     const int64_t lim = (int64_t)e1 * n3;
-    if (box)
+    if (rows) {
+      for (int e = e0; e < e1;) {
+        const int len = std::min({GS_ROW_EL, e1 - e, (e / ne + 1) * ne - e});
+        lists[x].push_back(Tile{p, e, -2, len});
+        e += len;
+      }
+    } else if (box) {
       for (int e = e0; e < e1; e += ept) lists[x].push_back(Tile{p, e, -1, std::min(ept, e1 - e)});
+    }
     for (int q = 0; q <= m->plan.nall; ++q) {
       if (q >= m->plan.nfree && q < m->plan.nall) continue;  // Dirichlet groups: masked instead
       if (box && q < m->plan.nfree) continue;                  // box tiles above
+      if (rows && q == m->plan.nall) continue;                 // the row tiles zero the boundary
       const std::vector<int32_t>& gf = m->gs_first[q];
       size_t g1 = cur[q];
       while (g1 < gf.size() && gf[g1] < lim) ++g1;

@@ -192,6 +192,185 @@ __device__ inline void gs_box_tile(gptr<T> v, const ProbDev& P, int e0, int nel)
   }
 }
 
+// Lattice coordinates of element e of a box problem (float quotients,
+// corrected by one either way).
+__device__ inline void box_coords(int e, const ProbDev& P, int& ex, int& ey, int& ez) {
+  const int ne = P.box_ne, ne2 = ne * ne;
+  int z = (int)((float)e * P.box_rne2);
+  z -= z * ne2 > e;
+  z += (z + 1) * ne2 <= e;
+  const int rem = e - z * ne2;
+  int y = (int)((float)rem * P.box_rne);
+  y -= y * ne > rem;
+  y += (y + 1) * ne <= rem;
+  ex = rem - y * ne, ey = y, ez = z;
+}
+
+// Row tiles of a box lattice at N = 7 (Tile::aux = -2, Tile::first the
+// first element, Tile::pad the count).  A row is the n = 8 entries of one
+// element at fixed (j, k).  Its owner is the element itself, moved one down
+// in y when j = 0 and one down in z when k = 0 (where the box continues
+// below).  An owner's rows sit in row slots s = 0..n in each direction: its
+// own rows j = s for s = 1..N (and s = 0 on the lower box face) and row
+// j = 0 of the element above (s = n, the second copy of line s = N, where
+// the box continues above); likewise in z.  A tile is a run of at most
+// GS_ROW_EL consecutive elements of one x line of the lattice.  It owns
+// their rows and the nodes of their x+ faces: it reads the rows whole into
+// LDS, with column i = 0 of the element after the run, forms each shared
+// node's sum of copies in ACC (lexicographic (dz, dy, dx) order, which is
+// ascending local index, so the sums are the index groups' bitwise) or zero
+// on the box boundary, and writes the rows whole, except column i = 0 of the
+// run's first element when an element precedes it: the run to the left
+// writes that column.  Every entry has one writer, no workgroup reads an
+// entry that another one writes, and the mask list is not needed.
+constexpr int GS_ROW_N = 8;  // row tiles: n = N + 1
+__device__ inline bool row_held(int s, bool lo, bool hi) {
+  return s == 0 ? lo : (s == GS_ROW_N ? hi : true);
+}
+template <typename T, typename ACC>
+__device__ inline void gs_row_tile(gptr<T> v, const ProbDev& P, int e0, int nel) {
+  constexpr int n = GS_ROW_N, N = n - 1, VW = 16 / (int)sizeof(T), PR = n / VW;
+  static_assert(GS_ROW_EL * n * n == GS_THREADS, "one thread per line of the run");
+  typedef T VT __attribute__((ext_vector_type(VW)));
+  // the end entries of every copy of every line, for the neighbouring elements
+  __shared__ T col0[GS_ROW_EL][n * n][4], colN[GS_ROW_EL][n * n][4];
+  const int ne = P.box_ne, ne2 = ne * ne;
+  int ex0, oy, oz;
+  box_coords(e0, P, ex0, oy, oz);
+  const bool ylo = oy == 0, yhi = oy + 1 < ne, zlo = oz == 0, zhi = oz + 1 < ne;
+  // one thread per (element, z line, y line); lines t = 0..N, line 0 only
+  // on the lower box face; line N has a second copy (slot n) where the box
+  // continues above
+  const int el = (int)threadIdx.x / (n * n), ln = (int)threadIdx.x % (n * n);
+  const int ty = ln % n, tz = ln / n;
+  const int ex = ex0 + el;
+  const bool live = el < nel && (ty > 0 || ylo) && (tz > 0 || zlo);
+  const int cy = (ty == N && yhi) ? 2 : 1, cz = (tz == N && zhi) ? 2 : 1, nc = cy * cz;
+  const bool xh = ex + 1 < ne;  // a copy of entry N in the element after
+  const bool bnd = ty == 0 || tz == 0 || (ty == N && !yhi) || (tz == N && !zhi);
+  auto row_at = [&](int e, int c) -> int64_t {  // copy c = 2 dz + dy (dy < cy, dz < cz)
+    const int dy = cy == 2 ? (c & 1) : 0, dz = cy == 2 ? (c >> 1) : c;
+    const int64_t ee = (int64_t)e0 + e + dy * ne + dz * ne2;
+    return ee * (n * n * n) + (dy ? 0 : ty) * n + (dz ? 0 : tz) * (n * n);
+  };
+  // before the barrier: the rows, the interior sums (entries 1..N-1, no
+  // neighbour needed) and the end entries published for the neighbours
+  T o[n], a0[4], aN[4], nxt[4];
+  if (live) {
+    T a[4][n];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (c < nc) {
+#pragma unroll
+        for (int h = 0; h < PR; ++h) {
+          const VT q = *(const VT*)&v[row_at(el, c) + h * VW];
+#pragma unroll
+          for (int u = 0; u < VW; ++u) a[c][h * VW + u] = q[u];
+        }
+        // entry 0 of the element after the run: only this run reads or writes it
+        if (el == nel - 1 && xh) nxt[c] = v[row_at(nel, c)];
+      }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (c < nc) {
+        a0[c] = a[c][0];
+        aN[c] = a[c][N];
+        col0[el][ln][c] = a0[c];
+        colN[el][ln][c] = aN[c];
+      }
+    // the sums in lexicographic (dz, dy, dx) order: ascending local index
+#pragma unroll
+    for (int i = 1; i < N; ++i) {
+      ACC s = (ACC)a[0][i];
+#pragma unroll
+      for (int c = 1; c < 4; ++c)
+        if (c < nc) s += (ACC)a[c][i];
+      o[i] = bnd ? T(0) : (T)s;
+    }
+  }
+  __syncthreads();
+  if (!live) return;
+  T pv[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    if (c < nc) {
+      pv[c] = el > 0 ? colN[el - 1][ln][c] : T(0);
+      if (el + 1 < nel) nxt[c] = col0[el + 1][ln][c];
+    }
+  if (bnd || ex == 0) {
+    o[0] = T(0);
+  } else {  // with the element before (formed there too, in the same order)
+    ACC s = (ACC)pv[0];
+    s += (ACC)a0[0];
+#pragma unroll
+    for (int c = 1; c < 4; ++c)
+      if (c < nc) {
+        s += (ACC)pv[c];
+        s += (ACC)a0[c];
+      }
+    o[0] = (T)s;
+  }
+  if (bnd || !xh) {
+    o[N] = T(0);
+  } else {
+    ACC s = (ACC)aN[0];
+    s += (ACC)nxt[0];
+#pragma unroll
+    for (int c = 1; c < 4; ++c)
+      if (c < nc) {
+        s += (ACC)aN[c];
+        s += (ACC)nxt[c];
+      }
+    o[N] = (T)s;
+  }
+  // the rows whole, except entry 0 of the run's first element when an
+  // element precedes it (the run to the left writes it); entry N's copies
+  // in the element after the run
+  const bool skip0 = el == 0 && ex > 0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    if (c < nc) {
+      const int64_t r = row_at(el, c);
+#pragma unroll
+      for (int h = 0; h < PR; ++h) {
+        if (h == 0 && skip0) {
+#pragma unroll
+          for (int u = 1; u < VW; ++u) v[r + u] = o[u];
+        } else {
+          VT q;
+#pragma unroll
+          for (int u = 0; u < VW; ++u) q[u] = o[h * VW + u];
+          *(VT*)&v[r + h * VW] = q;
+        }
+      }
+      if (el == nel - 1 && xh) v[row_at(nel, c)] = o[N];
+    }
+}
+
+// The pairwise order on a row tile: the run's elements' groups as box tiles
+// form them (no group holds a box-boundary node), then zero the
+// box-boundary entries of the rows the run owns.
+template <typename T, typename ACC>
+__device__ inline void gs_row_pairwise(gptr<T> v, const ProbDev& P, int e0, int nel) {
+  constexpr int n = GS_ROW_N, N = n - 1, S = n + 1;
+  gs_box_tile<T, ACC, true, N>(v, P, e0, nel);
+  const int ne = P.box_ne, ne2 = ne * ne;
+  int ex0, oy, oz;
+  box_coords(e0, P, ex0, oy, oz);
+  const bool ylo = oy == 0, yhi = oy + 1 < ne, zlo = oz == 0, zhi = oz + 1 < ne;
+  for (int f = (int)threadIdx.x; f < nel * S * S * n; f += GS_THREADS) {
+    const int i = f % n, r = f / n, sy = r % S, sz = (r / S) % S, el = r / (S * S);
+    if (!row_held(sy, ylo, yhi) || !row_held(sz, zlo, zhi)) continue;
+    const int ex = ex0 + el;
+    const bool bnd = sy == 0 || sz == 0 || (sy == N && !yhi) || (sz == N && !zhi) ||
+                     (i == 0 && ex == 0) || (i == N && ex + 1 == ne);
+    if (bnd) {
+      const int64_t ee = (int64_t)e0 + el + (sy == n ? ne : 0) + (sz == n ? ne2 : 0);
+      v[ee * (n * n * n) + (sy & (n - 1)) * n + (sz & (n - 1)) * (n * n) + i] = T(0);
+    }
+  }
+}
+
 template <typename T, typename ACC, bool SOLVER, bool PAIRWISE = false>
 __global__ void __launch_bounds__(GS_THREADS) gs_kernel(const Tile* __restrict__ tiles,
                                                         const ProbDev* __restrict__ probs,
@@ -234,6 +413,13 @@ __global__ void __launch_bounds__(GS_THREADS) gs_kernel(const Tile* __restrict__
     bucket = t.aux;
     first = t.first;
     count = t.pad;
+    if (bucket == -2) {  // box lattice at N = 7: row tiles
+      if constexpr (PAIRWISE)
+        gs_row_pairwise<T, ACC>(v, P, first, count);
+      else
+        gs_row_tile<T, ACC>(v, P, first, count);
+      return;
+    }
     if (bucket < 0) {  // box lattice: groups by index arithmetic
       if (P.box_ln == 3)
         gs_box_tile<T, ACC, PAIRWISE, 7>(v, P, first, count);

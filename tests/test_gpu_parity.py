@@ -206,22 +206,28 @@ def test_fp64_same_iterates(orc, mx, ctx, maxit, chunk):
     assert rel_l2(xg.cpu().numpy(), xo) <= 1e-12
 
 
-@pytest.mark.parametrize("mode", ["MODE_FP64", "MODE_MIXED"])
-@pytest.mark.parametrize("N,ne,chunk,helm", [(7, 4, 8, 0.0), (7, 3, 5, 1.0), (3, 5, 4, 0.0),
-                                              (15, 2, 6, 0.0)])
+@pytest.mark.parametrize("mode", ["MODE_FP64", "MODE_MIXED", "MODE_MIXED/pairwise"])
+@pytest.mark.parametrize("N,ne,chunk,helm", [(7, 4, 8, 0.0), (7, 3, 5, 1.0), (7, 6, 8, 0.0),
+                                              (7, 9, 7, 0.0), (3, 5, 4, 0.0), (15, 2, 6, 0.0)])
 def test_box_assembly_equals_gather_scatter(orc, mx, ctx, N, ne, chunk, helm, mode):
-    """Box lattices of order N = 7 or 15 form QQ^T w in the vector pass of
-    the PCG step (FP64 vectors, and FP32 vectors with FP64 sums) instead of a
-    gather-scatter launch.  The same mesh with its
-    global ids relabelled by a random bijection (the same copies, no longer a
-    lattice) takes the gather-scatter; both sum a node's copies in FP64 in
-    ascending local index, so the iterates are bitwise equal (one and two
-    direction buffers: odd and even graph chunks).  N = 3 (n = 4) is not
-    assembled in the vector pass and checks the two gather-scatter routes
-    alike.  The oracle's iterates after the same number of steps agree to
-    rounding."""
+    """Box lattices find a node's copies by index arithmetic: with FP64
+    vectors (N = 7, 15) the vector pass of the PCG step forms QQ^T w itself;
+    with FP32 vectors the gather-scatter launch does, at N = 7 in row tiles
+    (runs of up to four elements along an x line of the lattice, cut inside
+    the line for ne = 6 and 9, that also zero the box boundary) and at N = 15
+    in per-element tiles.  The same mesh with its global ids relabelled by a
+    random bijection (the same copies, no longer a lattice) takes the index
+    gather-scatter; both sum a node's copies in FP64 in ascending local index
+    (or, with the pairwise order, per element rank), so the iterates are
+    bitwise equal (one and two direction buffers: odd and even graph
+    chunks).  N = 3 (n = 4) checks the two index routes alike.  The oracle's
+    iterates after the same number of steps agree to rounding."""
     maxit = 37
-    log(f"{mode} box assembly vs gather-scatter, ne={ne} N={N} chunk={chunk} h={helm}")
+    mode, _, order = mode.partition("/")
+    if order and N != 7:
+        pytest.skip("the pairwise order is checked on the row tiles (N = 7)")
+    kw = dict(gs_order=mx.GS_ORDER_PAIRWISE) if order else {}
+    log(f"{mode} {order} box assembly vs gather-scatter, ne={ne} N={N} chunk={chunk} h={helm}")
     bmg, gm, bmo, om, fg, fo = make_pair(orc, mx, ctx, ne, N, seed=4, helm_h=helm, rhs="random",
                                          rhs_seed=8)
     g = np.asarray(bmg.glo).reshape(-1)
@@ -230,8 +236,8 @@ def test_box_assembly_equals_gather_scatter(orc, mx, ctx, N, ne, chunk, helm, mo
     gm2 = mx.Mesh(ctx, bmg.E, N, bmg.xyz, glo2, bmg.bnd, helm_h=helm)
     b = gm.mass_rhs(_t(fg))
     md = getattr(mx, mode)
-    xa, sa = gm.solve(b, mode=md, tol=0.0, max_iter=maxit, graph_chunk=chunk)
-    xb, sb = gm2.solve(b, mode=md, tol=0.0, max_iter=maxit, graph_chunk=chunk)
+    xa, sa = gm.solve(b, mode=md, tol=0.0, max_iter=maxit, graph_chunk=chunk, **kw)
+    xb, sb = gm2.solve(b, mode=md, tol=0.0, max_iter=maxit, graph_chunk=chunk, **kw)
     assert sa.iterations == sb.iterations == maxit
     assert torch.equal(xa, xb)
     xo, _ = om.pcg(om.rhs(fo), tol=0.0, maxit=maxit)
