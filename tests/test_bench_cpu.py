@@ -50,7 +50,8 @@ def test_batch_oracle_errors():
     """The batch leg's oracle check: one problem of each order on 8^3
     elements, each solution's error against the oracle's 1e-13 solution of
     that problem (the oracle's own 1e-10 solution is close, a perturbed one
-    is off by the perturbation)."""
+    is off by the perturbation), and the oracle's timed 1e-10 solves of them
+    as the batch's CPU sample."""
     sys.path.insert(0, ROOT)
     import oracle
 
@@ -65,6 +66,29 @@ def test_batch_oracle_errors():
     xo, _ = oracle.gll(N)
     bm = W.box_mesh(ne, N, xo)
     om = oracle.Mesh(bm.E, N, bm.xyz, bm.glo, bm.bnd)
-    x10, _ = om.pcg(om.rhs(W.random_smooth_rhs(bm, seed)), tol=1e-10, maxit=5000)
-    errs = bench.batch_oracle_errors({p: x10 * (1 + 1e-6)})
+    x10, st = om.pcg(om.rhs(W.random_smooth_rhs(bm, seed)), tol=1e-10, maxit=5000)
+    errs, cpu = bench.batch_oracle_errors({p: x10 * (1 + 1e-6)})
     assert abs(errs[f"problem_{p}_ne{ne}_N{N}"] - 1e-6) < 1e-7
+    one = cpu["problems"][f"problem_{p}_ne{ne}_N{N}"]
+    assert abs(one["iterations"] - st.iterations) <= 2 and one["s"] > 0
+    assert cpu["kind"] == "oracle" and cpu["value"] > 0 and cpu["cores"] >= 1
+
+
+def test_learned_oracle_reference_and_timing():
+    """The learned leg's oracle check on a small log-normal Helmholtz problem
+    (4^3 elements, N = 7): the timed 1e-10 solve is the CPU sample, x* its
+    continuation to 1e-13; a perturbed copy of the oracle's own solution is
+    off by the perturbation."""
+    sys.path.insert(0, ROOT)
+    import dataclasses
+
+    import bench
+    from paper_2503_02134_amd import workloads as W
+    wl = dataclasses.replace(W.WORKLOADS["box24_N7_lognormal_helmholtz"], name="box4_lognormal",
+                             ne=4)
+    om, b = bench._oracle_problem(wl, 5900)
+    x10, st = om.pcg(b, tol=1e-10, maxit=5000)
+    errs, cpu = bench.oracle_reference_errors(wl, 5900, {"perturbed": x10 * (1 + 1e-6)})
+    assert abs(errs["perturbed"] - 1e-6) < 1e-7
+    assert cpu["iterations"] == st.iterations and cpu["value"] > 0
+    assert "1e-10" in cpu["sample"] and "1e-13" in errs["reference"]
