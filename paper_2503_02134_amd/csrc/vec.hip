@@ -214,15 +214,19 @@ __device__ inline void box_coords(int e, const ProbDev& P, int& ex, int& ey, int
 // own rows j = s for s = 1..N (and s = 0 on the lower box face) and row
 // j = 0 of the element above (s = n, the second copy of line s = N, where
 // the box continues above); likewise in z.  A tile is a run of at most
-// GS_ROW_EL consecutive elements of one x line of the lattice.  It owns
-// their rows and the nodes of their x+ faces: it reads the rows whole into
-// LDS, with column i = 0 of the element after the run, forms each shared
-// node's sum of copies in ACC (lexicographic (dz, dy, dx) order, which is
-// ascending local index, so the sums are the index groups' bitwise) or zero
-// on the box boundary, and writes the rows whole, except column i = 0 of the
-// run's first element when an element precedes it: the run to the left
-// writes that column.  Every entry has one writer, no workgroup reads an
-// entry that another one writes, and the mask list is not needed.
+// GS_ROW_EL consecutive elements of one x line of the lattice, one thread
+// per (element, row line).  A thread reads its line's copies as whole rows
+// (16-byte loads) into registers, and, for the last element of the run,
+// entry 0 of the element after it; the rows' end entries pass between the
+// run's elements through LDS (one barrier).  It forms each node's sum of
+// copies in ACC (lexicographic (dz, dy, dx) order, which is ascending local
+// index, so the sums are the index groups' bitwise) or zero on the box
+// boundary; an x-face node is formed by the threads on both sides, in the
+// same order.  It writes its rows whole, except entry 0 of the run's first
+// element when an element precedes it: the run to the left writes that
+// column, with its own copies of those nodes.  Every entry has one writer,
+// no workgroup uses an entry that another one writes, and the mask list is
+// not needed.
 constexpr int GS_ROW_N = 8;  // row tiles: n = N + 1
 __device__ inline bool row_held(int s, bool lo, bool hi) {
   return s == 0 ? lo : (s == GS_ROW_N ? hi : true);
