@@ -208,13 +208,15 @@ def test_fp64_same_iterates(orc, mx, ctx, maxit, chunk):
 
 @pytest.mark.parametrize("mode", ["MODE_FP64", "MODE_MIXED", "MODE_MIXED/pairwise"])
 @pytest.mark.parametrize("N,ne,chunk,helm", [(7, 4, 8, 0.0), (7, 3, 5, 1.0), (7, 6, 8, 0.0),
-                                              (7, 9, 7, 0.0), (3, 5, 4, 0.0), (15, 2, 6, 0.0)])
+                                              (7, 9, 7, 0.0), (7, 2, 4, 0.0), (7, 5, 16, 1.0),
+                                              (3, 5, 4, 0.0), (15, 2, 6, 0.0)])
 def test_box_assembly_equals_gather_scatter(orc, mx, ctx, N, ne, chunk, helm, mode):
     """Box lattices find a node's copies by index arithmetic: with FP64
     vectors (N = 7, 15) the vector pass of the PCG step forms QQ^T w itself;
     with FP32 vectors the gather-scatter launch does, at N = 7 in row tiles
     (runs of up to four elements along an x line of the lattice, cut inside
-    the line for ne = 6 and 9, that also zero the box boundary) and at N = 15
+    the line for ne = 5, 6 and 9 and at the planner's 16-element chunk
+    boundaries for ne = 3, 5, 6 and 9, that also zero the box boundary) and at N = 15
     in per-element tiles.  The same mesh with its global ids relabelled by a
     random bijection (the same copies, no longer a lattice) takes the index
     gather-scatter; both sum a node's copies in FP64 in ascending local index
