@@ -163,6 +163,9 @@ def main():
     tot = sum(s for _, s in ax_ms)
     ax_avg_ms = sum(a * s for a, s in ax_ms) / max(tot, 1)
     vec_bytes = 8 if mode == mx.MODE_FP64 else 4
+    # a plain stream of the operator's own split: z, p_old and G read (four
+    # times what is written), p and w written
+    mix_gbs = mix_ceiling(ctx, 4 * 2 * vec_bytes * nloc, 2 * vec_bytes * nloc)
     g_bytes = 6 * (8 if mode == mx.MODE_FP64 else 2 if mode == mx.MODE_MIXED_IR_BF16G else 4)
     hb = 0 if wl.helm_h == 0 else g_bytes // 6
     bytes_per_dof = 4 * vec_bytes + g_bytes + hb  # z, p_old in; p, w out; G (and h*B) in
@@ -308,6 +311,7 @@ def main():
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "copy_ceiling_gbs": copy_gbs,
+                     "stream_4to1_ceiling_gbs": mix_gbs,
                      "traffic": ax_traffic_from_profile(mode) if wl.name == "box32_N7_deformed"
                      else None,
                      "bytes_per_launch": traffic_bytes, "avg_launch_us": round(ax_avg_ms * 1e3, 2),
@@ -401,6 +405,36 @@ def copy_ceiling(ctx, nbytes):
     del src, dst
     sec = sorted(times)[len(times) // 2]
     return round(2 * nbytes / sec / 1e9, 1)
+
+
+def mix_ceiling(ctx, read_bytes, write_bytes):
+    """Bandwidth of the library's streaming mix (mxsem_stream_mix: one pass,
+    non-temporal, read_bytes read for write_bytes written) at the operator
+    kernel's own split, 32 bytes read and 8 written per local dof: the
+    measured ceiling of a plain stream with the operator's bytes.  Median of
+    20 launches, each timed by its own events on the context's stream."""
+    import torch
+
+    from paper_2503_02134_amd import mxsem as mx
+    write_bytes = (write_bytes // 16) * 16
+    k = read_bytes // write_bytes
+    src = torch.ones(k * write_bytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty(write_bytes // 4, dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        mx.mxsem_stream_mix(ctx.h, src, dst)
+    assert bool((dst == float(k)).all())
+    stream = torch.cuda.current_stream()
+    times = []
+    for _ in range(20):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        mx.mxsem_stream_mix(ctx.h, src, dst)
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
+    del src, dst
+    sec = sorted(times)[len(times) // 2]
+    return round((k + 1) * write_bytes / sec / 1e9, 1)
 
 
 def traffic_probe(mesh, b, mode):

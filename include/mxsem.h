@@ -408,6 +408,16 @@ int mxsem_nn_make_pair(mxsem_mesh *mesh, const double *b, const double *x, const
  * non-temporal loads and stores, the measured HBM ceiling that the operator
  * kernel's bandwidth is set beside.  Async on the context stream. */
 int mxsem_stream_copy(mxsem_ctx *ctx, const void *src, void *dst, size_t bytes);
+/* The same reference at a kernel's own read:write split: with n =
+ * write_bytes / 16 and k = read_bytes / write_bytes (1, 2, 4 or 8), dst
+ * holds n 16-byte words of four FP32 and dst[i] = src[i] + src[n + i] + ...
+ * + src[(k-1) n + i], summed left to right in FP32.  Device pointers,
+ * 16-byte aligned, write_bytes a positive multiple of 16, read_bytes a
+ * multiple of it, no overlap (MXSEM_EINVAL otherwise).  k = 4 is the
+ * operator kernel's split (32 bytes read, 8 written per local dof).  Async
+ * on the context stream. */
+int mxsem_stream_mix(mxsem_ctx *ctx, const void *src, size_t read_bytes, void *dst,
+                     size_t write_bytes);
 
 /* ---- diagnostics ------------------------------------------------------------ */
 const char *mxsem_status_str(int status);

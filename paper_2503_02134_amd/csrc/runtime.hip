@@ -740,6 +740,28 @@ int mxsem_stream_copy(mxsem_ctx* ctx, const void* src, void* dst, size_t bytes) 
   MX_API_END("mxsem_stream_copy")
 }
 
+int mxsem_stream_mix(mxsem_ctx* ctx, const void* src, size_t read_bytes, void* dst,
+                     size_t write_bytes) {
+  MX_API_BEGIN
+  MX_CHECK(ctx && src && dst, MXSEM_EINVAL, "stream_mix: null argument");
+  MX_CHECK(write_bytes > 0 && write_bytes % 16 == 0 && read_bytes % write_bytes == 0 &&
+               ((uintptr_t)src & 15) == 0 && ((uintptr_t)dst & 15) == 0,
+           MXSEM_EINVAL,
+           "stream_mix: 16-byte aligned pointers, write_bytes a positive multiple of 16 and "
+           "read_bytes a multiple of write_bytes");
+  const size_t k = read_bytes / write_bytes;
+  MX_CHECK(k == 1 || k == 2 || k == 4 || k == 8, MXSEM_EINVAL,
+           "stream_mix: read_bytes / write_bytes must be 1, 2, 4 or 8");
+  MX_CHECK((const char*)src + read_bytes <= (const char*)dst ||
+               (const char*)dst + write_bytes <= (const char*)src,
+           MXSEM_EINVAL, "stream_mix: buffers overlap");
+  MX_HIP(hipSetDevice(ctx->device));
+  (void)hipGetLastError();
+  MX_HIP(launch_stream_mix(src, dst, (int64_t)(write_bytes / 16), (int)k, ctx->stream));
+  return MXSEM_OK;
+  MX_API_END("mxsem_stream_mix")
+}
+
 int mxsem_mesh_set_ranks(mxsem_mesh* m, const int32_t* rank_host) {
   MX_API_BEGIN
   MX_CHECK(m, MXSEM_EINVAL, "set_ranks: null mesh");

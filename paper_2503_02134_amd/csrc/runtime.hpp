@@ -98,6 +98,7 @@ hipError_t launch_axpy_cast(int vprec, double* x64, const void* xT, double sc, d
                             int64_t n, hipStream_t s);
 hipError_t launch_zero(double* x, int64_t n, hipStream_t s);
 hipError_t launch_stream_copy(const void* src, void* dst, int64_t n16, hipStream_t s);
+hipError_t launch_stream_mix(const void* src, void* dst, int64_t n16, int k, hipStream_t s);
 hipError_t launch_mass(const double* B, const double* f, double* b, int64_t n, hipStream_t s);
 hipError_t launch_cast_f32(float* d, const double* src, int64_t n, hipStream_t s);
 hipError_t launch_cast_bf16(bf16_t* d, const double* src, int64_t n, hipStream_t s);

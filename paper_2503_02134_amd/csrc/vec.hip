@@ -1518,6 +1518,46 @@ hipError_t launch_stream_copy(const void* src, void* dst, int64_t n16, hipStream
   return hipGetLastError();
 }
 
+// Streaming mix, the bandwidth reference at a kernel's own read:write
+// split: dst[i] = src[i] + src[n + i] + ... + src[(K-1) n + i] (16-byte
+// words of four FP32, summed left to right), so K bytes are read for every
+// byte written.  Same shape as the copy: four output words per thread, every
+// load of the thread issued before its adds, non-temporal both ways.
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+template <int K>
+__global__ void __launch_bounds__(256) stream_mix_kernel(const f32x4_t* __restrict__ src,
+                                                         f32x4_t* __restrict__ dst, int64_t n16) {
+  const int64_t i0 = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  f32x4_t v[4][K];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (i0 + q * 256 < n16)
+#pragma unroll
+      for (int j = 0; j < K; ++j) v[q][j] = __builtin_nontemporal_load(&src[j * n16 + i0 + q * 256]);
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (i0 + q * 256 < n16) {
+      f32x4_t t = v[q][0];
+#pragma unroll
+      for (int j = 1; j < K; ++j) t += v[q][j];
+      __builtin_nontemporal_store(t, &dst[i0 + q * 256]);
+    }
+}
+
+hipError_t launch_stream_mix(const void* src, void* dst, int64_t n16, int k, hipStream_t s) {
+  const dim3 g((unsigned)((n16 + 1023) / 1024)), b(256);
+  const f32x4_t* a = (const f32x4_t*)src;
+  f32x4_t* d = (f32x4_t*)dst;
+  switch (k) {
+    case 1: hipLaunchKernelGGL(stream_mix_kernel<1>, g, b, 0, s, a, d, n16); break;
+    case 2: hipLaunchKernelGGL(stream_mix_kernel<2>, g, b, 0, s, a, d, n16); break;
+    case 4: hipLaunchKernelGGL(stream_mix_kernel<4>, g, b, 0, s, a, d, n16); break;
+    case 8: hipLaunchKernelGGL(stream_mix_kernel<8>, g, b, 0, s, a, d, n16); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(double* x, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(zero_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, x, n);
   return hipGetLastError();

@@ -121,6 +121,7 @@ _SIGS = {
     "mxsem_mesh_attach_nn": [vp, vp],
     "mxsem_nn_make_pair": [vp, vp, vp, vp, vp, vp],
     "mxsem_stream_copy": [vp, vp, vp, C.c_size_t],
+    "mxsem_stream_mix": [vp, vp, C.c_size_t, vp, C.c_size_t],
     "mxsem_version": [],
 }
 
@@ -542,6 +543,15 @@ def mxsem_stream_copy(ctx, src, dst):
     ps = _vec(src, src.dtype, src.numel(), dev, "stream_copy: src")
     pd = _vec(dst, src.dtype, src.numel(), dev, "stream_copy: dst")
     _check("mxsem_stream_copy", lib().mxsem_stream_copy(ctx, ps, pd, n))
+
+
+def mxsem_stream_mix(ctx, src, dst):
+    """dst = src[0:n] + src[n:2n] + ... (FP32 device tensors, dst of n
+    entries, src of k n with k = 1, 2, 4 or 8, n a multiple of 4)."""
+    dev = _ctx_device.get(_key(ctx), 0)
+    ps = _vec(src, torch.float32, src.numel(), dev, "stream_mix: src")
+    pd = _vec(dst, torch.float32, dst.numel(), dev, "stream_mix: dst")
+    _check("mxsem_stream_mix", lib().mxsem_stream_mix(ctx, ps, src.numel() * 4, pd, dst.numel() * 4))
 
 
 # ---------------------------------------------------------------- convenience

@@ -61,6 +61,8 @@ def test_invalid_arguments_rejected(mx):
     assert L.mxsem_ctx_create(0, None, None) == mx.EINVAL
     assert L.mxsem_mesh_create(None, None, None, 0, None) == mx.EINVAL
     assert L.mxsem_solve(None, None, None, None, None) == mx.EINVAL
+    assert L.mxsem_stream_copy(None, None, None, 16) == mx.EINVAL
+    assert L.mxsem_stream_mix(None, None, 64, None, 16) == mx.EINVAL
     assert b"null" in L.mxsem_last_error()
     o = mx.solve_opts()
     assert o.tol == 1e-10 and o.graph_chunk >= 1 and o.inner_tol == 1e-4

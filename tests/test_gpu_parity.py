@@ -568,3 +568,25 @@ def test_stream_copy(mx, ctx):
     src = torch.zeros(3, dtype=torch.float32, device="cuda")
     with pytest.raises(mx.MxsemError):
         mx.mxsem_stream_copy(ctx.h, src, torch.zeros_like(src))
+
+
+def test_stream_mix(mx, ctx):
+    """The mixed-stream reference sums its k slabs left to right in FP32
+    (bit for bit against torch's elementwise adds in the same order),
+    including a tail shorter than one thread's four words, and refuses
+    ratios other than 1, 2, 4, 8 and unaligned sizes."""
+    for k in (1, 2, 4, 8):
+        for n in (4, 20, 1 << 18, (1 << 18) + 12):
+            src = torch.randn(k * n, dtype=torch.float32, device="cuda")
+            dst = torch.zeros(n, dtype=torch.float32, device="cuda")
+            mx.mxsem_stream_mix(ctx.h, src, dst)
+            ref = src[0:n].clone()
+            for j in range(1, k):
+                ref = ref + src[j * n:(j + 1) * n]
+            torch.cuda.synchronize()
+            assert torch.equal(dst, ref), (k, n)
+    with pytest.raises(mx.MxsemError):
+        mx.mxsem_stream_mix(ctx.h, torch.zeros(12, device="cuda"), torch.zeros(4, device="cuda"))
+    with pytest.raises(mx.MxsemError):
+        mx.mxsem_stream_mix(ctx.h, torch.zeros(6, device="cuda"), torch.zeros(2, device="cuda"))
+
