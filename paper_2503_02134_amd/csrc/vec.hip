@@ -424,11 +424,8 @@ __global__ void __launch_bounds__(GS_THREADS) gs_kernel(const Tile* __restrict__
         gs_row_tile<T, ACC>(v, P, first, count);
       return;
     }
-    if (bucket < 0) {  // box lattice: groups by index arithmetic
-      if (P.box_ln == 3)
-        gs_box_tile<T, ACC, PAIRWISE, 7>(v, P, first, count);
-      else
-        gs_box_tile<T, ACC, PAIRWISE, 15>(v, P, first, count);
+    if (bucket < 0) {  // box lattice at N = 15: each element's groups by index arithmetic
+      gs_box_tile<T, ACC, PAIRWISE, 15>(v, P, first, count);
       return;
     }
   } else {
