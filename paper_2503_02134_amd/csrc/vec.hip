@@ -1240,11 +1240,6 @@ __global__ void cast_g_split_kernel(TG* __restrict__ d, const double* __restrict
   }
 }
 
-__global__ void fill_state_kernel(State* __restrict__ st, int nprob, const State* __restrict__ tmpl) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nprob) st[i] = tmpl[i];
-}
-
 // ------------------------------------------------------------ host launchers
 static inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
