@@ -394,7 +394,10 @@ def test_no_or_one_unknown(orc, mx, ctx, ne, N):
 @pytest.mark.slow
 def test_full_size_local_operator_sampled(orc, mx, ctx):
     """32^3 deformed elements, N = 7 (the benchmark's operator launch):
-    sampled elements agree with the oracle run on those elements alone."""
+    sampled elements agree with the oracle run on those elements alone, in
+    FP64, FP32 and with BF16 geometric factors (each factor rounded once to
+    BF16, a relative 2^-8 per entry: within 2e-2 of the largest entry, and
+    measurably rounded on this deformed mesh)."""
     from paper_2503_02134_amd import workloads as W
     log("full-size 32^3 N7 ax sampled")
     xg, _ = mx.mxsem_gll(7)
@@ -404,6 +407,7 @@ def test_full_size_local_operator_sampled(orc, mx, ctx):
     u = rng.standard_normal(gm.nloc)
     w64 = gm.apply(_t(u), mx.F64, local_only=True).cpu().numpy()
     w32 = gm.apply(_t(u, torch.float32), mx.F32, local_only=True).cpu().numpy()
+    w16 = gm.apply(_t(u, torch.float32), mx.BF16G_F32, local_only=True).cpu().numpy()
     xo, _ = orc.gll(7)
     bmo = W.box_mesh(32, 7, xo, seed=3)
     sample = np.sort(rng.choice(bmg.E, 64, replace=False))
@@ -419,6 +423,9 @@ def test_full_size_local_operator_sampled(orc, mx, ctx):
     assert np.max(np.abs(got64 - ref)) <= 1e-12 * sc
     ref32 = om.ax_local(us.astype(np.float32).astype(np.float64))
     assert np.max(np.abs(got32 - ref32)) <= 2e-5 * sc
+    got16 = w16.reshape(bmg.E, n3)[sample].reshape(-1)
+    err16 = np.max(np.abs(got16 - ref32)) / sc
+    assert 1e-5 < err16 <= 2e-2, err16
 
 
 @pytest.mark.slow
